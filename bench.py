@@ -1,0 +1,204 @@
+#!/usr/bin/env python3
+"""Throughput of the per-step FAS solve of the second-order CHHS scheme on one GPU.
+
+One "step" is one time step of (2.4)-(2.7): setup, FAS V(2,2) cycles to the
+residual tolerance, energy/mass reductions and the state rotation, all through
+the C ABI of libchhs.  The default workload is the 2D spinodal quench on
+(0,1)^2 at 2048^2 (eps 0.01, gamma 1, s 1e-4, phi0 = 0.05 (2U - 1), FP64).
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "FAS cell-updates/s + HBM roofline %; batched FP32+refine vs plain FP64 at tol"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def smooth_bytes_per_cell(dim):
+    """Algorithmic bytes of one finest-level smoothing launch (one color), per cell.
+
+    A full smoothing step on the finest level must read phi, mu, p, phi_*,
+    phi^m and f_mu once and write phi, mu, p once: 9 FP64 values per cell.  One
+    launch updates one color, i.e. half of that per cell of the grid.
+    """
+    return 9 * 8 / 2.0
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def oracle_sample(phi_prev, phi_cur, mu, p, w, cycles_per_step):
+    """Time the oracle on a bounded sample of the same step: setup, one V-cycle
+    and one residual evaluation; return (cell-updates/s estimate, description)."""
+    import numpy as np
+    from oracle import fas, scheme
+    n = phi_cur.shape[-1]
+    prm = scheme.Params(eps=w["eps"], gamma=w["gamma"], s=w["s"], h=1.0 / n)
+    t0 = time.perf_counter()
+    phi_star, f = scheme.step_rhs(phi_prev, phi_cur, prm)
+    levels = fas.build_levels(phi_star, phi_cur.copy(), f, prm.h)
+    u = [phi_cur.copy(), mu.copy(), p - np.mean(p)]
+    us = [None] * len(levels)
+    us[0] = u
+    t1 = time.perf_counter()
+    scheme.residual_norm(scheme.residual(u, f, levels[0], prm), prm.h)
+    t2 = time.perf_counter()
+    fas.vcycle(levels, us, 0, prm, fas.Opts())
+    t3 = time.perf_counter()
+    t_step = (t1 - t0) + (t2 - t1) * (cycles_per_step + 1) + (t3 - t2) * cycles_per_step
+    desc = (f"oracle on the first timed step's input at {n}^2: setup {t1 - t0:.2f}s, one "
+            f"residual {t2 - t1:.2f}s, one V(2,2) cycle {t3 - t2:.2f}s, timed once each; "
+            f"step time = setup + {cycles_per_step:.2f} x (cycle + residual) + residual, "
+            f"with the GPU's mean V-cycles per step")
+    return phi_cur.size / t_step, desc, t3 - t0
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="2d-2048-fp64")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-parity", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build runs one GPU only (--gpus {args.gpus} requested); "
+              "the batched and single-grid paths are measured on one MI355X", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1611_02967_amd import build as _build
+    if not os.path.exists(_build.LIB):
+        log("libchhs.so missing: building")
+        _build.build()
+    from paper_1611_02967_amd import chhs
+    from workloads import WORKLOADS, uniform_field
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    w = WORKLOADS[args.workload]
+    n, dim = w["n"], w["dim"]
+    shape = (n,) * dim
+    cells = n ** dim
+    log(f"workload {args.workload}: {shape}, eps {w['eps']}, gamma {w['gamma']}, s {w['s']}")
+
+    phi0 = uniform_field(shape, w["seed"], mean=w["mean"], amp=0.05)
+    prob = chhs.make_problem(shape, 1.0 / n, w["eps"], w["gamma"], w["s"])
+    opts = chhs.chhs_default_opts(tol=1e-10, timing=1)
+    sv = chhs.Solver(prob, opts)
+    tp = torch.from_numpy(phi0).cuda()
+    tc = tp.clone()
+    tm = torch.zeros_like(tp)
+    tpp = torch.zeros_like(tp)
+
+    for k in range(args.warmup):
+        _, st = sv.step(tp, tc, tm, tpp, 1)
+        log(f"warmup step {k + 1}/{args.warmup}: {st[0]['vcycles']} V-cycles, res {st[0]['res_norm']:.2e}")
+    torch.cuda.synchronize()
+    start_state = [t.cpu().numpy() for t in (tp, tc, tm, tpp)]
+    sv.timing(reset=True)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, st = sv.step(tp, tc, tm, tpp, args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    tim = sv.timing()
+    s0 = st[0]
+    vcyc = s0["total_vcycles"]
+    log(f"timed {args.steps} steps in {elapsed:.3f}s, {vcyc} V-cycles, last res {s0['res_norm']:.2e}")
+
+    ms_smooth, n_smooth = tim["smooth0"]
+    avg_launch_s = ms_smooth / 1e3 / max(1, n_smooth)
+    bytes_launch = smooth_bytes_per_cell(dim) * cells
+    achieved = bytes_launch / avg_launch_s / 1e9 if n_smooth else 0.0
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "finest-level smoothing launch (one color)",
+                "avg_launch_us": round(avg_launch_s * 1e6, 2), "launches": n_smooth,
+                "algorithmic_bytes_per_launch": bytes_launch}
+    kernel_ms = {k: round(v[0], 3) for k, v in tim.items() if v[1]}
+
+    out = {
+        "metric": METRIC,
+        "value": cells * args.steps / elapsed,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "grid": list(shape), "eps": w["eps"],
+                   "gamma": w["gamma"], "s": w["s"], "tol": 1e-10, "cycle": "V(2,2)",
+                   "precision": "fp64"},
+        "vcycles_per_s": vcyc / elapsed,
+        "steps_per_s": args.steps / elapsed,
+        "vcycles_per_step": vcyc / args.steps,
+        "res_norm_last": s0["res_norm"],
+        "kernel_ms": kernel_ms,
+        "roofline": roofline,
+    }
+
+    if not args.no_parity:
+        # parity of the same workload at a size the oracle solves in seconds
+        from oracle import fas, scheme
+        m = 128
+        sm = (m,) * dim
+        prm = scheme.Params(eps=w["eps"], gamma=w["gamma"], s=w["s"], h=1.0 / m)
+        ph0 = uniform_field(sm, w["seed"], mean=w["mean"], amp=0.05)
+        z = np.zeros(sm)
+        ref = fas.solve_step(ph0, ph0, z, z, prm, fas.Opts(tol=1e-10))
+        sv2 = chhs.Solver(chhs.make_problem(sm, prm.h, prm.eps, prm.gamma, prm.s),
+                          chhs.chhs_default_opts(tol=1e-10))
+        a = torch.from_numpy(ph0).cuda()
+        b = a.clone()
+        zm, zp = torch.zeros_like(a), torch.zeros_like(a)
+        sv2.step(a, b, zm, zp, 1)
+        err = float(np.max(np.abs(b.cpu().numpy() - ref.phi)))
+        out["parity"] = {"grid": list(sm), "steps": 1, "max_abs_err_phi_vs_oracle": err}
+        log(f"parity at {m}^{dim}: max|phi - oracle| = {err:.2e}")
+
+    if not args.no_cpu_baseline:
+        log("timing the oracle on a bounded sample (single-threaded NumPy)")
+        rate, desc, wall = oracle_sample(*start_state, w, vcyc / args.steps)
+        out["cpu_baseline"] = {"value": rate, "unit": "cell-updates/s", "cores": 1,
+                               "kind": "oracle", "sample": desc,
+                               "host": {"cpu": cpu_model(), "os_cpu_count": os.cpu_count(),
+                                        "omp_threads": os.environ.get("OMP_NUM_THREADS")},
+                               "wall_s": round(wall, 2)}
+        log(f"oracle: {rate:.3e} cell-updates/s ({wall:.1f}s of CPU work)")
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

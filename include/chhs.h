@@ -1,0 +1,194 @@
+/*
+ * chhs.h -- C ABI of the MI355X (gfx950) solver for one time step of the
+ * second-order convex-splitting scheme for Cahn-Hilliard-Hele-Shaw
+ * (Chen, Feng, Liu, Wang, Wise, arXiv 1611.02967).
+ *
+ * Problem (Section 2, scheme (2.4)-(2.7)): on a cell-centred grid of one
+ * spacing h over a box, given (phi^{m-1}, phi^m) find (phi^{m+1}, mu^{m+1/2},
+ * p^{m+1/2}) with homogeneous Neumann data (App. A.1, eqn:nbc1-3) such that
+ *
+ *   phi - s div(M(a) grad mu) - s div(a grad p) = phi^m                        (2.5)
+ *   mu - chi(phi, phi^m) + 3/4 eps^2 Lap phi    = -phi_* - 1/4 eps^2 Lap phi^{m-1}   (2.6)
+ *   s Lap p + s gamma div(a grad mu)            = 0        (2.7, times s)
+ *
+ * with phi_* = 3/2 phi^m - 1/2 phi^{m-1}, a = A_h phi_*, M(a) = 1 + gamma a^2,
+ * chi(x, y) = (x^2 + y^2)(x + y)/4 (2.4), the operators of App. A.2.  p is
+ * fixed to mean zero.  The system is solved by nonlinear multigrid (full
+ * approximation scheme, Section 5) with V(nu1, nu2) cycles down to a 2^d
+ * coarsest grid until the residual norm is <= tol.
+ *
+ * Residual norm: ||R|| = (||R_phi||^2 + ||R_mu||^2 + ||R_p||^2)^(1/2) with the
+ * discrete l2 norm of App. A.2 (weights h^d), R = f - N(u) for the three rows
+ * above (the pressure row as written, i.e. multiplied by s).
+ *
+ * Layout: every cell-centred field is a dense FP64 array of nx*ny*nz values,
+ * x fastest (index (k*ny + j)*nx + i), interior cells only (no ghost layer).
+ * Batches of independent instances are packed one after another in instance
+ * order.  All field pointers below are DEVICE pointers owned by the caller.
+ *
+ * Streams: all device work is enqueued on the stream given to chhs_init.
+ * Calls that return host results synchronise that stream before returning.
+ *
+ * Errors: every int-returning call returns CHHS_OK (0) or a negative code;
+ * no call aborts or throws.  chhs_strerror gives a static message.
+ *
+ * Thread safety: a context may be used by one host thread at a time.
+ */
+#ifndef CHHS_H
+#define CHHS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    CHHS_OK = 0,
+    CHHS_E_INVAL = -1,     /* bad sizes or parameters                          */
+    CHHS_E_NOMEM = -2,     /* workspace smaller than chhs_workspace_bytes      */
+    CHHS_E_HIP = -3,       /* a HIP runtime call failed                        */
+    CHHS_E_NOCONV = -4,    /* max_vcycles reached above tol; state not advanced */
+    CHHS_E_NONFINITE = -5, /* residual norm became NaN or Inf; state not advanced */
+    CHHS_E_STATE = -6      /* call order violated (e.g. a V-cycle before setup) */
+};
+
+/* One instance: dim = 2 or 3 (nz = 1 for 2D); h = L/N in every direction
+ * (Section 2: one spacing for all directions); eps, gamma > 0 of (1.2)-(1.4)
+ * (gamma = 0 allowed: no flow); dt = the time step s.  Extents must halve
+ * together: nx = cx 2^k, ny = cy 2^k (, nz = cz 2^k) with the same k >= 1. */
+typedef struct chhs_problem {
+    int32_t dim, nx, ny, nz;
+    double h, eps, gamma, dt;
+} chhs_problem;
+
+/* Solver options.  Defaults (chhs_default_opts): nu1 = nu2 = 2, tol = 1e-10,
+ * max_vcycles = 100, coarse_sweeps = 50 (smoothing steps on the coarsest grid),
+ * precision 0 = FP64 throughout, 1 = FP32 smoothing/transfer inside FP64
+ * residual + correction (iterative refinement), use_graph = 1 replays each
+ * V-cycle as a captured HIP graph, timing = 1 brackets every launch of the
+ * timed kernel classes with HIP events (see chhs_get_timing). */
+typedef struct chhs_opts {
+    int32_t nu1, nu2, max_vcycles, coarse_sweeps;
+    double tol;
+    int32_t precision;
+    int32_t use_graph;
+    int32_t timing;
+    int32_t reserved[5];
+} chhs_opts;
+
+/* Kernel classes of chhs_timing. */
+enum {
+    CHHS_K_SMOOTH0 = 0,    /* smoothing launches on the finest level            */
+    CHHS_K_RESTRICT0 = 1,  /* residual + restriction from the finest level      */
+    CHHS_K_PROLONG0 = 2,   /* prolongation + correction into the finest level   */
+    CHHS_K_COARSE = 3,     /* every launch on coarser levels                    */
+    CHHS_K_NORM = 4,       /* residual-norm reduction on the finest level       */
+    CHHS_K_SETUP = 5,      /* per-step setup and energy reductions              */
+    CHHS_K_COUNT = 8
+};
+
+/* Device time per kernel class accumulated while opts.timing = 1. */
+typedef struct chhs_timing {
+    double ms[CHHS_K_COUNT];
+    int64_t launches[CHHS_K_COUNT];
+} chhs_timing;
+
+/* Per-instance statistics of the last step (or of the current system). */
+typedef struct chhs_stats {
+    int32_t vcycles;       /* V-cycles taken by the last step                 */
+    int32_t status;        /* CHHS_OK / CHHS_E_NOCONV / CHHS_E_NONFINITE      */
+    int32_t total_vcycles; /* V-cycles summed over the steps of the call      */
+    int32_t steps_done;    /* steps applied by the call                       */
+    double res[3];         /* ||R_phi||, ||R_mu||, ||R_p|| at exit            */
+    double res_norm;       /* combined residual norm at exit                  */
+    double res0;           /* combined residual norm of the initial guess     */
+    double mass;           /* (phi^{m+1}, 1)                                  */
+    double E_h;            /* E_h(phi^{m+1}), (2.8)                           */
+    double F_h;            /* F_h(phi^{m+1}, phi^m), (2.9)                    */
+    double diss_mu;        /* s ||grad_h mu||^2                               */
+    double diss_u;         /* (s/gamma) ||u||^2, u = -grad p - gamma a grad mu */
+    double max_abs_phi;    /* max |phi^{m+1}|                                 */
+} chhs_stats;
+
+typedef struct chhs_ctx chhs_ctx;
+
+/* Fills *o with the defaults listed above. */
+void chhs_default_opts(chhs_opts* o);
+
+/* Bytes of device workspace chhs_init needs for n_inst instances p[0..n_inst-1]
+ * under options o; 0 if the arguments are invalid. */
+size_t chhs_workspace_bytes(const chhs_problem* p, int32_t n_inst, const chhs_opts* o);
+
+/* Creates a context.  workspace_dev: caller-owned device memory of ws_bytes
+ * >= chhs_workspace_bytes(...), 256-byte aligned, kept alive until
+ * chhs_destroy.  hip_stream: a hipStream_t (NULL = the null stream).  The
+ * context itself (host memory, pinned staging, captured graphs) is owned by
+ * the library.  Returns CHHS_E_INVAL, CHHS_E_NOMEM or CHHS_E_HIP on failure,
+ * with *out = NULL. */
+int chhs_init(const chhs_problem* p, int32_t n_inst, const chhs_opts* o,
+              void* workspace_dev, size_t ws_bytes, void* hip_stream, chhs_ctx** out);
+
+/* Advances nsteps time steps of (2.4)-(2.7).  phi_prev, phi_cur (device,
+ * in/out): (phi^{m-1}, phi^m) on entry, (phi^{m+n-1}, phi^{m+n}) on success;
+ * pass identical contents for the first step (phi^{-1} := phi^0, Remark 2.2).
+ * mu, p (device, in/out): initial guess in, mu^{m+n-1/2}, p^{m+n-1/2} (mean
+ * zero) out.  stats_host: n_inst records of the last step, or NULL.  On
+ * CHHS_E_NOCONV / CHHS_E_NONFINITE the failing step is not applied: the four
+ * arrays hold the state before that step. */
+int chhs_step(chhs_ctx* c, double* phi_prev, double* phi_cur, double* mu, double* p,
+              int32_t nsteps, chhs_stats* stats_host);
+
+/* Loads the system of one step (setup of (2.4)-(2.7): phi_*, right-hand side,
+ * cell averages on all levels) from (phi_prev, phi_cur) and the initial guess
+ * (phi_cur, mu, p), without solving.  Device pointers, read only. */
+int chhs_setup_step(chhs_ctx* c, const double* phi_prev, const double* phi_cur,
+                    const double* mu, const double* p);
+
+/* One FAS V(nu1, nu2) cycle on the loaded system (p normalised to mean zero
+ * afterwards); writes the residual norm after the cycle to res_norm_host
+ * [n_inst] (host memory). */
+int chhs_fas_vcycle(chhs_ctx* c, double* res_norm_host);
+
+/* Residual norms of the current iterate of the loaded system:
+ * out_host[n_inst][4] = ||R_phi||, ||R_mu||, ||R_p||, combined. */
+int chhs_residual_norms(chhs_ctx* c, double* out_host);
+
+/* Copies the current iterate (phi, mu, p) of the loaded system into caller
+ * device arrays (any may be NULL). */
+int chhs_get_solution(chhs_ctx* c, double* phi, double* mu, double* p);
+
+/* Discrete mass, E_h(phi) (2.8) and F_h(phi, phi_prev) (2.9) of caller device
+ * arrays: out_host[n_inst][3] = mass, E_h, F_h.  eps and h of each instance
+ * are those given to chhs_init. */
+int chhs_energy_mass(chhs_ctx* c, const double* phi, const double* phi_prev, double* out_host);
+
+/* Level-by-level access for kernel-level tests.  field: 0 phi, 1 mu, 2 p,
+ * 3 f_phi, 4 f_mu, 5 f_p, 6 phi_*, 7 phi^m (psi).  dir 0: level -> dev,
+ * dir 1: dev -> level.  Single-instance contexts only. */
+int chhs_level_count(chhs_ctx* c, int32_t* levels);
+int chhs_level_shape(chhs_ctx* c, int32_t level, int32_t* nxyz3);
+int chhs_copy_field(chhs_ctx* c, int32_t level, int32_t field, double* dev, int32_t dir);
+
+/* One smoothing step (red then black collective cell update) on one level,
+ * and the restriction + FAS coarse right-hand side from level to level+1.
+ * Single-instance contexts only; for kernel-level tests. */
+int chhs_smooth(chhs_ctx* c, int32_t level, int32_t nsweeps);
+int chhs_restrict(chhs_ctx* c, int32_t level);
+
+/* Copies the accumulated kernel timing into *out (host); reset != 0 zeroes it.
+ * Synchronises the stream.  All zero unless opts.timing = 1. */
+int chhs_get_timing(chhs_ctx* c, chhs_timing* out, int32_t reset);
+
+/* Releases the context (not the caller's workspace).  NULL is ignored. */
+void chhs_destroy(chhs_ctx* c);
+
+/* Static text for a return code. */
+const char* chhs_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CHHS_H */

@@ -1,0 +1,141 @@
+"""The C ABI library loads on the host and exports what include/chhs.h declares.
+
+No device work: only calls that validate arguments on the host before any
+HIP call are made here.
+"""
+import ctypes
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "chhs.h")
+
+
+def _ensure_built():
+    from paper_1611_02967_amd import build
+    if not os.path.exists(build.LIB):
+        build.build()
+    return build.LIB
+
+
+@pytest.fixture(scope="module")
+def binding():
+    _ensure_built()
+    from paper_1611_02967_amd import chhs
+    return chhs
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(chhs_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_four_entry_points():
+    names = declared_functions()
+    for required in ("chhs_init", "chhs_step", "chhs_fas_vcycle", "chhs_energy_mass"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(_ensure_built())
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_declares_every_symbol(binding):
+    assert set(declared_functions()) <= set(binding._SIGS)
+
+
+def test_struct_layouts_match_the_c_compiler(binding):
+    """sizeof/offsetof as gcc sees the header equal the ctypes mirrors."""
+    prog = r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "chhs.h"
+int main(void) {
+  printf("%zu %zu %zu\n", sizeof(chhs_problem), sizeof(chhs_opts), sizeof(chhs_stats));
+  printf("%zu %zu %zu\n", offsetof(chhs_problem, h), offsetof(chhs_opts, tol), offsetof(chhs_opts, reserved));
+  printf("%zu %zu %zu\n", offsetof(chhs_stats, res), offsetof(chhs_stats, max_abs_phi), offsetof(chhs_stats, res0));
+  return 0;
+}
+"""
+    with tempfile.TemporaryDirectory() as tmp:
+        src = os.path.join(tmp, "layout.c")
+        exe = os.path.join(tmp, "layout")
+        open(src, "w").write(prog)
+        subprocess.run(["gcc", "-I", os.path.dirname(HEADER), src, "-o", exe], check=True)
+        out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()
+    got = [int(x) for x in out]
+    want = [ctypes.sizeof(binding.chhs_problem), ctypes.sizeof(binding.chhs_opts),
+            ctypes.sizeof(binding.chhs_stats),
+            binding.chhs_problem.h.offset, binding.chhs_opts.tol.offset,
+            binding.chhs_opts.reserved.offset,
+            binding.chhs_stats.res.offset, binding.chhs_stats.max_abs_phi.offset,
+            binding.chhs_stats.res0.offset]
+    assert got == want
+
+
+def test_workspace_bytes_rejects_invalid_problems(binding):
+    o = binding.chhs_default_opts()
+    good = binding.make_problem((64, 64), 1 / 64, 0.05, 1.0, 1e-3)
+    assert binding.chhs_workspace_bytes([good], o) > 0
+    bad = [
+        binding.make_problem((64, 64), 1 / 64, 0.05, 1.0, 0.0),     # dt = 0
+        binding.make_problem((64, 64), 1 / 64, 0.0, 1.0, 1e-3),     # eps = 0
+        binding.make_problem((64, 64), 1 / 64, 0.05, -1.0, 1e-3),   # gamma < 0
+        binding.make_problem((64, 64), 0.0, 0.05, 1.0, 1e-3),       # h = 0
+        binding.make_problem((34, 34), 1 / 34, 0.05, 1.0, 1e-3),    # coarsest 17 > 8
+        binding.make_problem((3, 3), 1 / 3, 0.05, 1.0, 1e-3),       # a single level
+        binding.make_problem((64, 4), 1 / 64, 0.05, 1.0, 1e-3),     # coarsest 32 x 2
+    ]
+    for p in bad:
+        assert binding.chhs_workspace_bytes([p], o) == 0
+    assert binding.chhs_workspace_bytes([good], binding.chhs_default_opts(tol=0.0)) == 0
+    assert binding.chhs_workspace_bytes([good], binding.chhs_default_opts(nu1=0, nu2=0)) == 0
+
+
+def test_workspace_accounts_for_every_level(binding):
+    """11 arrays per coarse level and 8 on the finest, 256-byte aligned."""
+    o = binding.chhs_default_opts()
+    p = binding.make_problem((64, 64), 1 / 64, 0.05, 1.0, 1e-3)
+    n = binding.chhs_workspace_bytes([p], o)
+    cells = [64 * 64 // 4 ** l for l in range(6)]
+    arrays = 8 * ((cells[0] * 8 + 255) // 256 * 256)
+    arrays += sum(11 * ((c * 8 + 255) // 256 * 256) for c in cells[1:])
+    assert n >= arrays
+
+
+def test_init_rejects_bad_arguments_on_the_host(binding):
+    o = binding.chhs_default_opts()
+    p = binding.make_problem((64, 64), 1 / 64, 0.05, 1.0, 1e-3)
+    arr = (binding.chhs_problem * 1)(p)
+    handle = ctypes.c_void_p()
+    # NULL workspace
+    rc = binding._lib.chhs_init(arr, 1, ctypes.byref(o), None, 1 << 20, None, ctypes.byref(handle))
+    assert rc == binding.CHHS_E_INVAL and not handle.value
+    # workspace too small (pointer never dereferenced: size is checked first)
+    rc = binding._lib.chhs_init(arr, 1, ctypes.byref(o), ctypes.c_void_p(1 << 20), 16, None,
+                                ctypes.byref(handle))
+    assert rc == binding.CHHS_E_NOMEM and not handle.value
+    # misaligned workspace
+    rc = binding._lib.chhs_init(arr, 1, ctypes.byref(o), ctypes.c_void_p((1 << 20) + 8), 1 << 30,
+                                None, ctypes.byref(handle))
+    assert rc == binding.CHHS_E_INVAL
+
+
+def test_strerror_covers_every_code(binding):
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert binding.chhs_strerror(code) != "unknown error code"
+    assert binding.chhs_strerror(-99) == "unknown error code"
+
+
+def test_entry_points_reject_null_context(binding):
+    assert binding._lib.chhs_fas_vcycle(None, None) == binding.CHHS_E_INVAL
+    assert binding._lib.chhs_step(None, None, None, None, None, 1, None) == binding.CHHS_E_INVAL
+    assert binding._lib.chhs_energy_mass(None, None, None, None) == binding.CHHS_E_INVAL
+    binding._lib.chhs_destroy(None)

@@ -1,0 +1,250 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Kernel level (one smoothing step, one restriction with the FAS coarse
+right-hand side, one V-cycle) the HIP path runs the same algorithm as the
+oracle's FAS, so iterates agree to rounding (<= 1e-12).  Step level both solve
+(2.4)-(2.7) to the same tolerance: the per-step protocol starts both from the
+oracle's (phi^{m-1}, phi^m) and requires max |phi_gpu - phi_oracle| <= 1e-10.
+"""
+import numpy as np
+import pytest
+
+from oracle import fas, grid, newton, scheme
+from workloads import WORKLOADS, uniform_field
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(64, 64), (48, 40), (16, 16, 16), (12, 8, 16)]
+
+
+@pytest.fixture(scope="module")
+def chhs():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_1611_02967_amd import chhs as binding
+    return binding
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def _inputs(shape, seed):
+    prev = uniform_field(shape, seed, amp=0.6)
+    cur = prev + uniform_field(shape, seed + 1, amp=0.1)
+    mu0 = uniform_field(shape, seed + 2, amp=0.3)
+    p0 = uniform_field(shape, seed + 3, amp=0.01)
+    return prev, cur, mu0, p0
+
+
+def _prm(shape, eps=0.05, gamma=2.0, s=1e-3):
+    return scheme.Params(eps=eps, gamma=gamma, s=s, h=1.0 / shape[-1])
+
+
+def _solver(chhs, shape, prm, **opts):
+    prob = chhs.make_problem(shape, prm.h, prm.eps, prm.gamma, prm.s)
+    return chhs.Solver(prob, chhs.chhs_default_opts(**opts))
+
+
+def _oracle_level0(prev, cur, mu0, p0, prm):
+    phi_star, f = scheme.step_rhs(prev, cur, prm)
+    lvl = scheme.Level(h=prm.h, phi_star=phi_star, psi=cur.copy(), f=f)
+    u = [cur.copy(), mu0.copy(), p0 - p0.mean()]
+    return lvl, u
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_setup_matches_oracle(chhs, shape):
+    prm = _prm(shape)
+    prev, cur, mu0, p0 = _inputs(shape, 100)
+    sv = _solver(chhs, shape, prm)
+    sv.setup_step(dev(prev), dev(cur), dev(mu0), dev(p0))
+    lvl, u = _oracle_level0(prev, cur, mu0, p0, prm)
+    np.testing.assert_allclose(host(sv.read_field(0, "phi_star")), lvl.phi_star, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(host(sv.read_field(0, "f_mu")), lvl.f[1], rtol=1e-13, atol=1e-13)
+    np.testing.assert_allclose(host(sv.read_field(0, "p")), u[2], rtol=0, atol=1e-15)
+    levels = fas.build_levels(lvl.phi_star, lvl.psi, lvl.f, prm.h)
+    assert len(levels) == len(sv.levels())
+    for l, ol in enumerate(levels):
+        np.testing.assert_allclose(host(sv.read_field(l, "phi_star")), ol.phi_star, rtol=0, atol=1e-14)
+        np.testing.assert_allclose(host(sv.read_field(l, "psi")), ol.psi, rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_one_smoothing_step_matches_oracle(chhs, shape):
+    prm = _prm(shape)
+    prev, cur, mu0, p0 = _inputs(shape, 200)
+    sv = _solver(chhs, shape, prm)
+    sv.setup_step(dev(prev), dev(cur), dev(mu0), dev(p0))
+    sv.smooth(0, 1)
+    lvl, u = _oracle_level0(prev, cur, mu0, p0, prm)
+    fas.sweep(u, lvl, prm)
+    for name, want in zip(("phi", "mu", "p"), u):
+        got = host(sv.read_field(0, name))
+        scale = max(1.0, np.max(np.abs(want)))
+        assert np.max(np.abs(got - want)) <= 1e-12 * scale, name
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_restriction_and_coarse_rhs_match_oracle(chhs, shape):
+    prm = _prm(shape)
+    prev, cur, mu0, p0 = _inputs(shape, 300)
+    sv = _solver(chhs, shape, prm)
+    sv.setup_step(dev(prev), dev(cur), dev(mu0), dev(p0))
+    sv.smooth(0, 1)
+    sv.restrict(0)
+    lvl, u = _oracle_level0(prev, cur, mu0, p0, prm)
+    fas.sweep(u, lvl, prm)
+    levels = fas.build_levels(lvl.phi_star, lvl.psi, lvl.f, prm.h)
+    r = scheme.residual(u, lvl.f, levels[0], prm)
+    uc = [fas.restrict(x) for x in u]
+    nc = scheme.apply_N(uc, levels[1], prm)
+    fc = [fas.restrict(r[k]) + nc[k] for k in range(3)]
+    for name, want in zip(("phi", "mu", "p", "f_phi", "f_mu", "f_p"), uc + fc):
+        got = host(sv.read_field(1, name))
+        scale = max(1.0, np.max(np.abs(want)))
+        assert np.max(np.abs(got - want)) <= 1e-11 * scale, name
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_one_vcycle_matches_oracle(chhs, shape):
+    prm = _prm(shape)
+    prev, cur, mu0, p0 = _inputs(shape, 400)
+    sv = _solver(chhs, shape, prm)
+    sv.setup_step(dev(prev), dev(cur), dev(mu0), dev(p0))
+    res_gpu = sv.fas_vcycle()[0]
+    lvl, u = _oracle_level0(prev, cur, mu0, p0, prm)
+    levels = fas.build_levels(lvl.phi_star, lvl.psi, lvl.f, prm.h)
+    us = [None] * len(levels)
+    us[0] = u
+    fas.vcycle(levels, us, 0, prm, fas.Opts())
+    u[2] -= u[2].mean()
+    res_or = scheme.residual_norm(scheme.residual(u, lvl.f, levels[0], prm), prm.h)
+    for name, want in zip(("phi", "mu", "p"), u):
+        got = host(sv.read_field(0, name))
+        assert np.max(np.abs(got - want)) <= 1e-11 * max(1.0, np.max(np.abs(want))), name
+    assert abs(res_gpu - res_or) <= 1e-9 * res_or + 1e-14
+
+
+def _per_step(chhs, phi0, prm, nsteps, tol):
+    """Per-step protocol: both paths start every step from the oracle's state."""
+    sv = _solver(chhs, phi0.shape, prm, tol=tol)
+    prev, cur = phi0.copy(), phi0.copy()
+    mu = np.zeros_like(phi0)
+    p = np.zeros_like(phi0)
+    worst = 0.0
+    for m in range(nsteps):
+        r = fas.solve_step(prev, cur, mu, p, prm, fas.Opts(tol=tol))
+        tp, tc, tm, tpp = dev(prev), dev(cur), dev(mu), dev(p)
+        rc, st = sv.step(tp, tc, tm, tpp, 1)
+        assert st[0]["res_norm"] <= tol
+        assert st[0]["vcycles"] == r.vcycles, (m, st[0]["vcycles"], r.vcycles)
+        err = np.max(np.abs(host(tc) - r.phi))
+        worst = max(worst, err)
+        assert np.max(np.abs(host(tp) - cur)) == 0.0      # rotation: phi_prev <- phi^m
+        assert np.max(np.abs(host(tm) - r.mu)) <= 1e-9
+        prev, cur, mu, p = cur, r.phi, r.mu, r.p
+    return worst
+
+
+def test_2d_64_workload_per_step_parity(chhs):
+    """20 steps of the 2D 64^2 workload (eps 0.05, gamma 1, s 1e-3, V(2,2), tol 1e-10)."""
+    w = WORKLOADS["2d-64-fp64"]
+    n = w["n"]
+    prm = scheme.Params(eps=w["eps"], gamma=w["gamma"], s=w["s"], h=1.0 / n)
+    phi0 = uniform_field((n, n), w["seed"], mean=w["mean"], amp=0.05)
+    worst = _per_step(chhs, phi0, prm, w["steps"], tol=1e-10)
+    assert worst <= 1e-10, worst
+
+
+def test_3d_per_step_parity_tight_tol(chhs):
+    n = 16
+    prm = scheme.Params(eps=0.1, gamma=2.0, s=5e-4, h=1.0 / n)
+    phi0 = uniform_field((n, n, n), 2969, mean=0.1, amp=0.05)
+    worst = _per_step(chhs, phi0, prm, 3, tol=1e-12)
+    assert worst <= 1e-11, worst
+
+
+@pytest.mark.parametrize("shape", [(8, 8), (4, 4, 4)])
+def test_gpu_matches_newton_on_tiny_grids(chhs, shape):
+    prev, cur, mu0, p0 = _inputs(shape, 500)
+    prm = _prm(shape, eps=0.1, gamma=2.0, s=0.5)
+    phi_n, mu_n, p_n, _ = newton.solve(prev, cur, prm.eps, prm.gamma, prm.s, prm.h)
+    sv = _solver(chhs, shape, prm, tol=1e-13, max_vcycles=200)
+    tp, tc, tm, tpp = dev(prev), dev(cur), dev(np.zeros(shape)), dev(np.zeros(shape))
+    sv.step(tp, tc, tm, tpp, 1)
+    assert np.max(np.abs(host(tc) - phi_n)) <= 1e-12
+    assert np.max(np.abs(host(tm) - mu_n)) <= 1e-12
+    assert np.max(np.abs(host(tpp) - p_n)) <= 1e-10
+
+
+def test_energy_mass_and_step_stats_match_oracle(chhs):
+    shape = (32, 32)
+    prm = _prm(shape, eps=0.05, gamma=2.0, s=1e-3)
+    prev, cur, _, _ = _inputs(shape, 600)
+    sv = _solver(chhs, shape, prm)
+    mass, e_h, f_h = sv.energy_mass(dev(cur), dev(prev))[0]
+    assert abs(mass - grid.mass(cur, prm.h)) <= 1e-13
+    assert abs(e_h - scheme.energy_E(cur, prm)) <= 1e-12 * max(1, abs(e_h))
+    assert abs(f_h - scheme.energy_F(cur, prev, prm)) <= 1e-12 * max(1, abs(f_h))
+    z = np.zeros(shape)
+    tp, tc, tm, tpp = dev(prev), dev(cur), dev(z), dev(z)
+    _, st = sv.step(tp, tc, tm, tpp, 1)
+    phi, mu, p = host(tc), host(tm), host(tpp)
+    d_mu, d_u = scheme.dissipation(mu, p, 1.5 * cur - 0.5 * prev, prm)
+    s0 = st[0]
+    assert abs(s0["mass"] - grid.mass(phi, prm.h)) <= 1e-13
+    assert abs(s0["E_h"] - scheme.energy_E(phi, prm)) <= 1e-12
+    assert abs(s0["F_h"] - scheme.energy_F(phi, cur, prm)) <= 1e-12
+    assert abs(s0["diss_mu"] - d_mu) <= 1e-12 * max(1, d_mu)
+    assert abs(s0["diss_u"] - d_u) <= 1e-12 * max(1, d_u)
+    assert s0["max_abs_phi"] == np.max(np.abs(phi))
+    # the exact energy balance behind Theorem 2.1 on the GPU's own outputs
+    lhs, rhs = scheme.energy_identity_terms(phi, cur, prev, mu, p, prm)
+    assert abs(lhs - rhs) <= 1e-9
+
+
+def test_repeat_runs_are_bitwise_identical(chhs):
+    shape = (64, 64)
+    prm = _prm(shape)
+    prev, cur, mu0, p0 = _inputs(shape, 700)
+    outs = []
+    for _ in range(2):
+        sv = _solver(chhs, shape, prm)
+        tp, tc, tm, tpp = dev(prev), dev(cur), dev(mu0), dev(p0)
+        sv.step(tp, tc, tm, tpp, 2)
+        outs.append((host(tc), host(tm), host(tpp)))
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+
+
+def test_nonfinite_input_is_reported_and_state_kept(chhs):
+    shape = (32, 32)
+    prm = _prm(shape)
+    prev, cur, mu0, p0 = _inputs(shape, 800)
+    cur[5, 7] = np.nan
+    sv = _solver(chhs, shape, prm)
+    tp, tc, tm, tpp = dev(prev), dev(cur), dev(mu0), dev(p0)
+    rc, st = sv.step(tp, tc, tm, tpp, 1, check=False)
+    assert rc == chhs.CHHS_E_NONFINITE
+    assert st[0]["steps_done"] == 0
+    np.testing.assert_array_equal(host(tp), prev)
+
+
+def test_no_convergence_is_reported_and_state_kept(chhs):
+    shape = (32, 32)
+    prm = _prm(shape)
+    prev, cur, mu0, p0 = _inputs(shape, 900)
+    sv = _solver(chhs, shape, prm, tol=1e-30, max_vcycles=3)
+    tp, tc, tm, tpp = dev(prev), dev(cur), dev(mu0), dev(p0)
+    rc, st = sv.step(tp, tc, tm, tpp, 1, check=False)
+    assert rc == chhs.CHHS_E_NOCONV
+    assert st[0]["vcycles"] == 3 and st[0]["steps_done"] == 0
+    assert 0 < st[0]["res_norm"] < st[0]["res0"]
+    np.testing.assert_array_equal(host(tc), cur)
+    np.testing.assert_array_equal(host(tm), mu0)
