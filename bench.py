@@ -27,14 +27,23 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def smooth_bytes_per_cell(dim):
-    """Algorithmic bytes of one finest-level smoothing launch (one color), per cell.
+def launch_bytes_per_cell(dim, cls, nu):
+    """Algorithmic bytes per fine cell of one finest-level launch of a kernel class.
 
-    A full smoothing step on the finest level must read phi, mu, p, phi_*,
-    phi^m and f_mu once and write phi, mu, p once: 9 FP64 values per cell.  One
-    launch updates one color, i.e. half of that per cell of the grid.
+    FP64 (8 B per value).  On the finest level f_phi = phi^m and f_p = 0, so a
+    smoothing step must read phi, mu, p, phi_*, phi^m, f_mu and write phi, mu, p.
+    2D (one tiled launch per pre- and per post-smoothing group of nu steps):
+      pre0  : 6 reads + 3 writes, plus the restricted u_c, ub_c and R(r) on
+              the coarse grid (9 values per 4 fine cells)            = 90 B
+      post0 : 6 reads + 3 writes, plus the coarse u_c and ub_c read
+              for the prolonged correction (6 values per 4 cells)     = 84 B
+    3D (per-cell kernels, one launch per color): half of a smoothing step,
+      (6 reads + 3 writes) / 2                                        = 36 B
     """
-    return 9 * 8 / 2.0
+    w = 8
+    if dim == 2:
+        return {"pre0": (9 + 9 / 4) * w, "post0": (9 + 6 / 4) * w}[cls]
+    return 9 * w / 2.0
 
 
 def cpu_model():
@@ -133,15 +142,27 @@ def main():
     vcyc = s0["total_vcycles"]
     log(f"timed {args.steps} steps in {elapsed:.3f}s, {vcyc} V-cycles, last res {s0['res_norm']:.2e}")
 
-    ms_smooth, n_smooth = tim["smooth0"]
-    avg_launch_s = ms_smooth / 1e3 / max(1, n_smooth)
-    bytes_launch = smooth_bytes_per_cell(dim) * cells
-    achieved = bytes_launch / avg_launch_s / 1e9 if n_smooth else 0.0
+    # dominant finest-level kernel class by device time
+    cls = max(("pre0", "post0"), key=lambda k: tim[k][0])
+    ms_k, n_k = tim[cls]
+    avg_launch_s = ms_k / 1e3 / max(1, n_k)
+    bytes_launch = launch_bytes_per_cell(dim, cls, 2) * cells
+    achieved = bytes_launch / avg_launch_s / 1e9 if n_k else 0.0
+    names = {"pre0": "finest-level pre-smoothing launch" + (
+                 " (2 fused red-black steps + residual + restriction)" if dim == 2 else " (one color)"),
+             "post0": "finest-level post-smoothing launch" + (
+                 " (prolongation + 2 fused red-black steps + residual norm)" if dim == 2 else " (one color)")}
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "finest-level smoothing launch (one color)",
-                "avg_launch_us": round(avg_launch_s * 1e6, 2), "launches": n_smooth,
-                "algorithmic_bytes_per_launch": bytes_launch}
+                "kernel": names[cls], "avg_launch_us": round(avg_launch_s * 1e6, 2),
+                "launches": n_k, "algorithmic_bytes_per_launch": bytes_launch}
+    other = "post0" if cls == "pre0" else "pre0"
+    if tim[other][1]:
+        avg_o = tim[other][0] / 1e3 / tim[other][1]
+        b_o = launch_bytes_per_cell(dim, other, 2) * cells
+        roofline["other_kernel"] = {"kernel": names[other], "avg_launch_us": round(avg_o * 1e6, 2),
+                                    "achieved": round(b_o / avg_o / 1e9, 1),
+                                    "algorithmic_bytes_per_launch": b_o}
     kernel_ms = {k: round(v[0], 3) for k, v in tim.items() if v[1]}
 
     out = {

@@ -64,7 +64,7 @@ typedef struct chhs_problem {
 } chhs_problem;
 
 /* Solver options.  Defaults (chhs_default_opts): nu1 = nu2 = 2, tol = 1e-10,
- * max_vcycles = 100, coarse_sweeps = 50 (smoothing steps on the coarsest grid),
+ * max_vcycles = 100, coarse_sweeps = 4 (smoothing steps on the coarsest grid),
  * precision 0 = FP64 throughout, 1 = FP32 smoothing/transfer inside FP64
  * residual + correction (iterative refinement), use_graph = 1 replays each
  * V-cycle as a captured HIP graph, timing = 1 brackets every launch of the
@@ -80,11 +80,13 @@ typedef struct chhs_opts {
 
 /* Kernel classes of chhs_timing. */
 enum {
-    CHHS_K_SMOOTH0 = 0,    /* smoothing launches on the finest level            */
-    CHHS_K_RESTRICT0 = 1,  /* residual + restriction from the finest level      */
-    CHHS_K_PROLONG0 = 2,   /* prolongation + correction into the finest level   */
-    CHHS_K_COARSE = 3,     /* every launch on coarser levels                    */
-    CHHS_K_NORM = 4,       /* residual-norm reduction on the finest level       */
+    CHHS_K_PRE0 = 0,       /* finest-level pre-smoothing launches (2D: nu1 steps
+                              fused with residual + restriction)                */
+    CHHS_K_POST0 = 1,      /* finest-level post-smoothing launches (2D: fused
+                              with prolongation and the residual norm)          */
+    CHHS_K_TRANSFER0 = 2,  /* standalone transfer kernels at the finest level   */
+    CHHS_K_COARSE = 3,     /* every launch on coarser levels (incl. the tail)   */
+    CHHS_K_NORM = 4,       /* standalone residual-norm reductions and p shift   */
     CHHS_K_SETUP = 5,      /* per-step setup and energy reductions              */
     CHHS_K_COUNT = 8
 };

@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libchhs.so")
 ARCH = "gfx950"
 
-SOURCES = ["chhs_api.hip", "chhs_kernels.hip"]
+SOURCES = ["chhs_api.hip", "chhs_kernels.hip", "chhs_tile2d.hip", "chhs_tail.hip"]
 
 # -packed-fp32-ops: keep the compiler from forming packed FP32 instructions
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

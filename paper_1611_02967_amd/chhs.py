@@ -38,7 +38,7 @@ class chhs_opts(ctypes.Structure):
                 ("reserved", ctypes.c_int32 * 5)]
 
 
-K_CLASSES = ["smooth0", "restrict0", "prolong0", "coarse", "norm", "setup", "k6", "k7"]
+K_CLASSES = ["pre0", "post0", "transfer0", "coarse", "norm", "setup", "k6", "k7"]
 
 
 class chhs_timing(ctypes.Structure):

@@ -5,6 +5,7 @@
 // and the time-step loop with its state rotation.
 #include <cmath>
 #include <cstring>
+#include <utility>
 #include <vector>
 
 #include "chhs.h"
@@ -18,7 +19,9 @@ struct chhs_ctx {
     int n_inst = 1;
     hipStream_t stream = nullptr;
     std::vector<Level<double>> lv;     // level 0 = finest
-    double* partial = nullptr;         // kMaxPartials x kPartialStride doubles
+    double* partial = nullptr;         // partial_cap x kPartialStride doubles
+    int tail = 0;                      // first level handled by the one-workgroup tail
+    size_t tail_lds = 0;               // its LDS bytes
     double* dres = nullptr;            // small device result area (64 doubles)
     double* hres = nullptr;            // pinned host mirror of dres
     bool loaded = false;               // a step system is set up
@@ -84,6 +87,34 @@ bool level_extents(const chhs_problem* p, std::vector<int>& ext) {
     return nx <= 8 && ny <= 8 && nz <= 8;
 }
 
+// Blocks whose partial sums the reduction buffer must hold.
+int partial_capacity(const chhs_problem* p) {
+    int cap = chhs::kMaxPartials;
+    if (p->dim == 2) {
+        const int t = chhs::tile2d_blocks(p->nx, p->ny);
+        if (t > cap) cap = t;
+    }
+    return cap;
+}
+
+// First level of the single-workgroup tail: the finest level whose own and
+// coarser levels' 11 fields fit the LDS budget.
+int pick_tail(const std::vector<Level<double>>& lv, size_t* bytes) {
+    const int nlev = int(lv.size());
+    std::vector<int> cells(nlev);
+    for (int l = 0; l < nlev; ++l) cells[l] = lv[l].n;
+    for (int l = 0; l < nlev; ++l) {
+        if (nlev - l > chhs::kMaxTailLevels) continue;
+        const size_t b = chhs::tail_lds_bytes(&cells[l], nlev - l, sizeof(double));
+        if (b <= chhs::kTailLdsBudget) {
+            *bytes = b;
+            return l;
+        }
+    }
+    *bytes = chhs::tail_lds_bytes(&cells[nlev - 1], 1, sizeof(double));
+    return nlev - 1;
+}
+
 // Walks the workspace layout; assigns pointers when base != nullptr.
 size_t plan(const chhs_problem* p, char* base, std::vector<Level<double>>* out,
             double** partial, double** dres) {
@@ -117,6 +148,11 @@ size_t plan(const chhs_problem* p, char* base, std::vector<Level<double>>* out,
         L.f2 = take(n);
         L.pstar = take(n);
         L.psi = take(n);
+        if (p->dim == 2) {
+            L.phi_alt = take(n);
+            L.mu_alt = take(n);
+            L.p_alt = take(n);
+        }
         L.h = h;
         L.lam = p->dt / (h * h);
         L.kap = 0.75 * p->eps * p->eps / (h * h);
@@ -124,7 +160,7 @@ size_t plan(const chhs_problem* p, char* base, std::vector<Level<double>>* out,
         if (out) out->push_back(L);
         h *= 2.0;
     }
-    double* part = take(size_t(chhs::kMaxPartials) * chhs::kPartialStride);
+    double* part = take(size_t(partial_capacity(p)) * chhs::kPartialStride);
     double* res = take(64);
     if (partial) *partial = part;
     if (dres) *dres = res;
@@ -186,41 +222,127 @@ void resolve_timing(chhs_ctx* c) {
     c->pending.clear();
 }
 
-void smooth(chhs_ctx* c, int l) {
+// After an out-of-place launch on level l: the written copy becomes current.
+void swap_u(chhs_ctx* c, int l) {
+    Level<double>& L = c->lv[l];
+    std::swap(L.phi, L.phi_alt);
+    std::swap(L.mu, L.mu_alt);
+    std::swap(L.p, L.p_alt);
+}
+
+// Per-cell red-black smoothing (3D levels above the tail, and chhs_smooth on 3D).
+void smooth_cells(chhs_ctx* c, int l, int cls) {
     for (int color = 0; color < 2; ++color) {
-        TimedScope t(c, l == 0 ? CHHS_K_SMOOTH0 : CHHS_K_COARSE);
+        TimedScope t(c, cls);
         chhs::launch_smooth(c->prob.dim, c->lv[l], color, c->stream);
     }
 }
 
-void vcycle(chhs_ctx* c, int l) {
-    const int dim = c->prob.dim;
-    const int last = int(c->lv.size()) - 1;
-    if (l == last) {
-        for (int s = 0; s < c->opts.coarse_sweeps; ++s) smooth(c, l);
+// nsweeps smoothing steps on level l with the production kernels.
+void smooth_steps(chhs_ctx* c, int l, int nsweeps, int cls) {
+    if (c->prob.dim == 2) {
+        const Level<double>& L = c->lv[l];
+        while (nsweeps > 0) {
+            const int k = nsweeps >= 2 ? 2 : 1;
+            nsweeps -= k;
+            {
+                TimedScope t(c, cls);
+                chhs::launch_tile2d<double>(L, L, l == 0, k, 0, false, nullptr, c->stream);
+            }
+            swap_u(c, l);
+        }
         return;
     }
-    for (int s = 0; s < c->opts.nu1; ++s) smooth(c, l);
+    for (int s = 0; s < nsweeps; ++s) smooth_cells(c, l, cls);
+}
+
+// One V-cycle from level l.  Returns the number of residual-norm partials the
+// finest level's last post-smoothing launch produced (0 if none).
+int vcycle(chhs_ctx* c, int l) {
+    const int dim = c->prob.dim;
+    const int nlev = int(c->lv.size());
+    const bool l0 = l == 0;
+    if (l >= c->tail) {
+        TimedScope t(c, l0 ? CHHS_K_PRE0 : CHHS_K_COARSE);
+        chhs::launch_tail<double>(dim, &c->lv[l], nlev - l, c->opts.nu1, c->opts.nu2,
+                                  c->opts.coarse_sweeps, c->tail_lds, c->stream);
+        return 0;
+    }
+    const Level<double>& L = c->lv[l];
+    const Level<double>& C = c->lv[l + 1];
+    const int pre_cls = l0 ? CHHS_K_PRE0 : CHHS_K_COARSE;
+    const int post_cls = l0 ? CHHS_K_POST0 : CHHS_K_COARSE;
+    const int xfer_cls = l0 ? CHHS_K_TRANSFER0 : CHHS_K_COARSE;
+    int nb = 0;
+    if (dim == 2) {
+        int rem = c->opts.nu1;
+        if (rem == 0) {
+            TimedScope t(c, xfer_cls);
+            chhs::launch_restrict_residual(dim, L, C, c->stream);
+        } else {
+            while (rem > 2) {
+                {
+                    TimedScope t(c, pre_cls);
+                    chhs::launch_tile2d<double>(L, C, l0, 2, 0, false, nullptr, c->stream);
+                }
+                swap_u(c, l);
+                rem -= 2;
+            }
+            {
+                TimedScope t(c, pre_cls);
+                chhs::launch_tile2d<double>(L, C, l0, rem, 1, false, nullptr, c->stream);
+            }
+            swap_u(c, l);
+        }
+        {
+            TimedScope t(c, xfer_cls);
+            chhs::launch_coarse_rhs(dim, C, c->stream);
+        }
+        vcycle(c, l + 1);
+        rem = c->opts.nu2;
+        if (rem == 0) {
+            TimedScope t(c, xfer_cls);
+            chhs::launch_prolong(dim, L, C, c->stream);
+        } else {
+            bool first = true;
+            while (rem > 0) {
+                const int k = rem >= 2 ? 2 : 1;
+                rem -= k;
+                const bool norm = l0 && rem == 0;
+                {
+                    TimedScope t(c, post_cls);
+                    nb = chhs::launch_tile2d<double>(L, C, l0, k, norm ? 2 : 0, first,
+                                                     norm ? c->partial : nullptr, c->stream);
+                }
+                swap_u(c, l);
+                first = false;
+            }
+        }
+        return l0 && c->opts.nu2 > 0 ? nb : 0;
+    }
+    for (int s = 0; s < c->opts.nu1; ++s) smooth_cells(c, l, pre_cls);
     {
-        TimedScope t(c, l == 0 ? CHHS_K_RESTRICT0 : CHHS_K_COARSE);
-        chhs::launch_restrict_residual(dim, c->lv[l], c->lv[l + 1], c->stream);
-        chhs::launch_coarse_rhs(dim, c->lv[l + 1], c->stream);
+        TimedScope t(c, xfer_cls);
+        chhs::launch_restrict_residual(dim, L, C, c->stream);
+        chhs::launch_coarse_rhs(dim, C, c->stream);
     }
     vcycle(c, l + 1);
     {
-        TimedScope t(c, l == 0 ? CHHS_K_PROLONG0 : CHHS_K_COARSE);
-        chhs::launch_prolong(dim, c->lv[l], c->lv[l + 1], c->stream);
+        TimedScope t(c, xfer_cls);
+        chhs::launch_prolong(dim, L, C, c->stream);
     }
-    for (int s = 0; s < c->opts.nu2; ++s) smooth(c, l);
+    for (int s = 0; s < c->opts.nu2; ++s) smooth_cells(c, l, post_cls);
+    return 0;
 }
 
 // Residual norms of level 0 into hres[0..3] (||R_phi||, ||R_mu||, ||R_p||, total);
-// p is shifted to mean zero on the way (it does not enter N).
-int residual_and_normalise(chhs_ctx* c) {
+// p is shifted to mean zero on the way (it does not enter N).  nb > 0: the
+// partial sums of the current iterate are already in the partial buffer.
+int residual_and_normalise(chhs_ctx* c, int nb = 0) {
     const Level<double>& L = c->lv[0];
     {
         TimedScope t(c, CHHS_K_NORM);
-        const int nb = chhs::launch_residual_partials(c->prob.dim, L, c->partial, c->stream);
+        if (nb == 0) nb = chhs::launch_residual_partials(c->prob.dim, L, c->partial, c->stream);
         chhs::launch_reduce_final(c->partial, nb, 4, c->dres, c->stream);
         chhs::launch_shift_p(L, c->dres + 3, c->stream);
     }
@@ -290,7 +412,7 @@ void chhs_default_opts(chhs_opts* o) {
     o->nu1 = 2;
     o->nu2 = 2;
     o->max_vcycles = 100;
-    o->coarse_sweeps = 50;
+    o->coarse_sweeps = 4;
     o->tol = 1e-10;
     o->precision = 0;
     o->use_graph = 0;
@@ -318,6 +440,11 @@ int chhs_init(const chhs_problem* p, int32_t n_inst, const chhs_opts* o, void* w
     c->n_inst = n_inst;
     c->stream = static_cast<hipStream_t>(hip_stream);
     plan(p, static_cast<char*>(workspace_dev), &c->lv, &c->partial, &c->dres);
+    c->tail = pick_tail(c->lv, &c->tail_lds);
+    if (chhs::prepare_tail<double>(p->dim, c->tail_lds) != 0) {
+        delete c;
+        return CHHS_E_HIP;
+    }
     if (hipHostMalloc(reinterpret_cast<void**>(&c->hres), 64 * sizeof(double),
                       hipHostMallocDefault) != hipSuccess) {
         delete c;
@@ -340,10 +467,10 @@ int chhs_setup_step(chhs_ctx* c, const double* phi_prev, const double* phi_cur,
 int chhs_fas_vcycle(chhs_ctx* c, double* res_norm_host) {
     if (c == nullptr) return CHHS_E_INVAL;
     if (!c->loaded) return CHHS_E_STATE;
-    vcycle(c, 0);
+    const int nb = vcycle(c, 0);
     int rc = check_launch();
     if (rc) return rc;
-    rc = residual_and_normalise(c);
+    rc = residual_and_normalise(c, nb);
     if (rc) return rc;
     if (res_norm_host) res_norm_host[0] = c->hres[3];
     return std::isfinite(c->hres[3]) ? CHHS_OK : CHHS_E_NONFINITE;
@@ -385,8 +512,8 @@ int chhs_step(chhs_ctx* c, double* phi_prev, double* phi_cur, double* mu, double
         st.res0 = c->hres[3];
         int cycles = 0;
         while (c->hres[3] > c->opts.tol && cycles < c->opts.max_vcycles) {
-            vcycle(c, 0);
-            rc = residual_and_normalise(c);
+            const int nb = vcycle(c, 0);
+            rc = residual_and_normalise(c, nb);
             if (rc) break;
             ++cycles;
             if (!std::isfinite(c->hres[3])) break;
@@ -476,7 +603,7 @@ int chhs_copy_field(chhs_ctx* c, int32_t level, int32_t field, double* dev, int3
 int chhs_smooth(chhs_ctx* c, int32_t level, int32_t nsweeps) {
     if (c == nullptr || level < 0 || level >= int(c->lv.size()) || nsweeps < 0)
         return CHHS_E_INVAL;
-    for (int s = 0; s < nsweeps; ++s) smooth(c, level);
+    smooth_steps(c, level, nsweeps, level == 0 ? CHHS_K_PRE0 : CHHS_K_COARSE);
     int rc = check_launch();
     if (rc) return rc;
     HIP_TRY(hipStreamSynchronize(c->stream));

@@ -14,7 +14,7 @@ from workloads import WORKLOADS, uniform_field
 
 pytestmark = pytest.mark.gpu
 
-SHAPES = [(64, 64), (48, 40), (16, 16, 16), (12, 8, 16)]
+SHAPES = [(64, 64), (48, 40), (256, 192), (16, 16, 16), (12, 8, 16)]
 
 
 @pytest.fixture(scope="module")
@@ -90,6 +90,45 @@ def test_one_smoothing_step_matches_oracle(chhs, shape):
         assert np.max(np.abs(got - want)) <= 1e-12 * scale, name
 
 
+@pytest.mark.parametrize("shape", [(64, 64), (48, 40), (96, 160), (12, 8, 16)])
+def test_two_fused_smoothing_steps_match_oracle(chhs, shape):
+    """Two smoothing steps in one call (one fused launch on 2D levels)."""
+    prm = _prm(shape)
+    prev, cur, mu0, p0 = _inputs(shape, 250)
+    sv = _solver(chhs, shape, prm)
+    sv.setup_step(dev(prev), dev(cur), dev(mu0), dev(p0))
+    sv.smooth(0, 2)
+    lvl, u = _oracle_level0(prev, cur, mu0, p0, prm)
+    fas.sweep(u, lvl, prm)
+    fas.sweep(u, lvl, prm)
+    for name, want in zip(("phi", "mu", "p"), u):
+        got = host(sv.read_field(0, name))
+        assert np.max(np.abs(got - want)) <= 1e-12 * max(1.0, np.max(np.abs(want))), name
+
+
+@pytest.mark.parametrize("shape", [(64, 64), (128, 96), (16, 16, 16)])
+@pytest.mark.parametrize("nsweeps", [1, 2, 3])
+def test_smoothing_on_a_coarse_level_matches_oracle(chhs, shape, nsweeps):
+    """Level 1 carries general f_phi, f_p (not phi^m and 0 as on level 0)."""
+    prm = _prm(shape)
+    prev, cur, mu0, p0 = _inputs(shape, 260)
+    sv = _solver(chhs, shape, prm)
+    sv.setup_step(dev(prev), dev(cur), dev(mu0), dev(p0))
+    cshape = tuple(n // 2 for n in shape)
+    u = [uniform_field(cshape, 270 + k, amp=0.5) for k in range(3)]
+    f = [uniform_field(cshape, 280 + k, amp=0.5) for k in range(3)]
+    for name, val in zip(("phi", "mu", "p", "f_phi", "f_mu", "f_p"), u + f):
+        sv.write_field(1, name, dev(val))
+    sv.smooth(1, nsweeps)
+    lvl = scheme.Level(h=2 * prm.h, phi_star=host(sv.read_field(1, "phi_star")),
+                       psi=host(sv.read_field(1, "psi")), f=f)
+    for _ in range(nsweeps):
+        fas.sweep(u, lvl, prm)
+    for name, want in zip(("phi", "mu", "p"), u):
+        got = host(sv.read_field(1, name))
+        assert np.max(np.abs(got - want)) <= 1e-11 * max(1.0, np.max(np.abs(want))), name
+
+
 @pytest.mark.parametrize("shape", SHAPES)
 def test_restriction_and_coarse_rhs_match_oracle(chhs, shape):
     prm = _prm(shape)
@@ -129,6 +168,60 @@ def test_one_vcycle_matches_oracle(chhs, shape):
         got = host(sv.read_field(0, name))
         assert np.max(np.abs(got - want)) <= 1e-11 * max(1.0, np.max(np.abs(want))), name
     assert abs(res_gpu - res_or) <= 1e-9 * res_or + 1e-14
+
+
+@pytest.mark.parametrize("n", [1024, 2048])
+def test_one_vcycle_at_full_size_matches_oracle(chhs, n):
+    """One V-cycle of the 2D spinodal workload at full size (thousands of tiled
+    blocks in several dispatch waves), iterate by iterate against the oracle."""
+    w = WORKLOADS["2d-2048-fp64"]
+    prm = scheme.Params(eps=w["eps"], gamma=w["gamma"], s=w["s"], h=1.0 / n)
+    prev = uniform_field((n, n), w["seed"], amp=0.05)
+    cur = prev + uniform_field((n, n), w["seed"] + 1, amp=0.01)
+    z = np.zeros((n, n))
+    sv = _solver(chhs, (n, n), prm)
+    sv.setup_step(dev(prev), dev(cur), dev(z), dev(z))
+    res_gpu = sv.fas_vcycle()[0]
+    lvl, u = _oracle_level0(prev, cur, z, z, prm)
+    levels = fas.build_levels(lvl.phi_star, lvl.psi, lvl.f, prm.h)
+    us = [None] * len(levels)
+    us[0] = u
+    fas.vcycle(levels, us, 0, prm, fas.Opts())
+    u[2] -= u[2].mean()
+    for name, want in zip(("phi", "mu", "p"), u):
+        got = host(sv.read_field(0, name))
+        assert np.max(np.abs(got - want)) <= 1e-11 * max(1.0, np.max(np.abs(want))), name
+    res_or = scheme.residual_norm(scheme.residual(u, lvl.f, levels[0], prm), prm.h)
+    assert abs(res_gpu - res_or) <= 1e-8 * res_or + 1e-14
+
+
+def test_full_size_2048_steps_satisfy_the_scheme(chhs):
+    """Bench configuration (2048^2, eps 0.01, gamma 1, s 1e-4, tol 1e-10): the GPU
+    steps satisfy (2.5)-(2.7) to tol (oracle residual of the GPU output), conserve
+    mass and obey the exact energy balance of Theorem 2.1."""
+    w = WORKLOADS["2d-2048-fp64"]
+    n = w["n"]
+    prm = scheme.Params(eps=w["eps"], gamma=w["gamma"], s=w["s"], h=1.0 / n)
+    phi0 = uniform_field((n, n), w["seed"], mean=w["mean"], amp=0.05)
+    sv = _solver(chhs, (n, n), prm, tol=1e-10)
+    tp, tc = dev(phi0), dev(phi0)
+    tm, tpp = dev(np.zeros((n, n))), dev(np.zeros((n, n)))
+    for _ in range(2):
+        prev, cur = host(tp), host(tc)
+        _, st = sv.step(tp, tc, tm, tpp, 1)
+        phi, mu, p = host(tc), host(tm), host(tpp)
+        phi_star, f = scheme.step_rhs(prev, cur, prm)
+        lvl = scheme.Level(h=prm.h, phi_star=phi_star, psi=cur, f=f)
+        r = scheme.residual([phi, mu, p], f, lvl, prm)
+        res = scheme.residual_norm(r, prm.h)
+        assert res <= 1.01e-10 and abs(res - st[0]["res_norm"]) <= 1e-3 * res + 1e-15
+        # mass: (phi^{m+1},1) - (phi^m,1) = -(R_phi,1) exactly, so |dm| <= ||R_phi||
+        dm = grid.mass(phi, prm.h) - grid.mass(cur, prm.h)
+        assert abs(dm + grid.mass(r[0], prm.h)) <= 1e-13
+        assert abs(dm) <= grid.norm2(r[0], prm.h) + 1e-15
+        lhs, rhs = scheme.energy_identity_terms(phi, cur, prev, mu, p, prm)
+        assert abs(lhs - rhs) <= 1e-9
+        assert abs(p.mean()) <= 1e-13
 
 
 def _per_step(chhs, phi0, prm, nsteps, tol):
