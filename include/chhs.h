@@ -66,7 +66,7 @@ typedef struct chhs_problem {
 /* Solver options.  Defaults (chhs_default_opts): nu1 = nu2 = 2, tol = 1e-10,
  * max_vcycles = 100, coarse_sweeps = 4 (smoothing steps on the coarsest grid),
  * precision 0 = FP64 throughout, 1 = FP32 smoothing/transfer inside FP64
- * residual + correction (iterative refinement), use_graph = 1 replays each
+ * residual + correction (iterative refinement), use_graph = 1 (default) replays each
  * V-cycle as a captured HIP graph, timing = 1 brackets every launch of the
  * timed kernel classes with HIP events (see chhs_get_timing). */
 typedef struct chhs_opts {

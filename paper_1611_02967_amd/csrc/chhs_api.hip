@@ -1,43 +1,120 @@
 // Host driver and C ABI of libchhs (declared in include/chhs.h).
 //
-// Owns the multigrid hierarchy carved out of the caller's workspace, the FAS
-// V-cycle schedule, the stopping test (one residual-norm readback per cycle)
-// and the time-step loop with its state rotation.
+// Owns the multigrid hierarchies of a batch of independent instances carved
+// out of the caller's workspace, the task tables that let one launch per level
+// cover every instance, the FAS V-cycle schedule (optionally replayed as a
+// captured HIP graph), the per-instance stopping test (one small readback per
+// cycle), the mixed-precision iterative refinement, and the time-step loop
+// with its state rotation.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 #include <utility>
 #include <vector>
 
 #include "chhs.h"
 #include "chhs_internal.hpp"
 
+using chhs::Batch;
+using chhs::CellTask;
+using chhs::InstInfo;
 using chhs::Level;
+using chhs::LevelDesc;
+using chhs::Range;
+using chhs::TileTask;
+using chhs::kMaxLevels;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// A table of block tasks in device memory.
+template <typename Task>
+struct Table {
+    Task* dev = nullptr;
+    int n = 0;
+};
+
+// Everything the workspace holds, computed from the problems alone.
+struct Layout {
+    size_t bytes = 0;
+    std::vector<LevelDesc<double>> desc;       // [inst * kMaxLevels + l] (device pointers)
+    std::vector<LevelDesc<float>> desc32;      // FP32 correction hierarchy (mixed precision)
+    std::vector<InstInfo> info;
+    std::vector<std::vector<CellTask>> A, B, Bc;
+    std::vector<std::vector<TileTask>> T, Tall;
+    std::vector<int> tail_insts;
+    std::vector<CellTask> A0n;              // finest-level cells of instances without a fused norm
+    std::vector<Range> rngA0, rngT0, rngA0n;
+    int max_nlev = 0, depth = 0;
+    size_t tail_lds = 0, tail_lds32 = 0;
+    // offsets into the workspace
+    size_t off_desc = 0, off_desc32 = 0, off_info = 0, off_tail = 0, off_rngA0 = 0, off_rngT0 = 0,
+           off_rngA0n = 0;
+    size_t off_A0n = 0, off_partial_t = 0;
+    size_t off_partial = 0, off_res = 0, off_eres = 0, off_act_cycle = 0, off_act_next = 0,
+           off_cycles = 0;
+    std::vector<size_t> off_A, off_B, off_Bc, off_T, off_Tall;
+    int partial_cap = 0, partial_t_cap = 0;
+};
+
+}  // namespace
 
 struct chhs_ctx {
-    chhs_problem prob;
+    std::vector<chhs_problem> prob;
     chhs_opts opts;
     int n_inst = 1;
+    int dim = 2;
+    bool mixed = false;
     hipStream_t stream = nullptr;
-    std::vector<Level<double>> lv;     // level 0 = finest
-    double* partial = nullptr;         // partial_cap x kPartialStride doubles
-    int tail = 0;                      // first level handled by the one-workgroup tail
-    size_t tail_lds = 0;               // its LDS bytes
-    double* dres = nullptr;            // small device result area (64 doubles)
-    double* hres = nullptr;            // pinned host mirror of dres
-    bool loaded = false;               // a step system is set up
-    // kernel timing (opts.timing): event pairs awaiting resolution, totals
+    Layout lay;
+    char* base = nullptr;
+    // device views
+    LevelDesc<double>* ddesc = nullptr;
+    LevelDesc<float>* ddesc32 = nullptr;
+    InstInfo* dinfo = nullptr;
+    Table<CellTask> A[kMaxLevels], B[kMaxLevels], Bc[kMaxLevels];
+    Table<TileTask> T[kMaxLevels], Tall[kMaxLevels];
+    Table<CellTask> A0n;
+    int* tail_insts = nullptr;
+    Range* rngA0 = nullptr;
+    Range* rngT0 = nullptr;
+    Range* rngA0n = nullptr;
+    double* partial = nullptr;
+    double* partial_t = nullptr;    // norm partials of the fused finest-level launch
+    double* res = nullptr;          // [n_inst][kResStride]
+    double* eres = nullptr;         // [n_inst][kResStride]
+    int* act_cycle = nullptr;
+    int* act_next = nullptr;
+    int* cycles = nullptr;
+    // pinned host mirror: res | eres | act_next | cycles
+    double* hres = nullptr;
+    double* heres = nullptr;
+    int* hact = nullptr;
+    int* hcyc = nullptr;
+    int cur[kMaxLevels] = {};       // current copy of u per FP64 level
+    int cur32[kMaxLevels] = {};     // current copy of u per FP32 level
+    bool fused_norm = false;
+    bool loaded = false;
+    // graph replay of one cycle; two slots in mixed precision (the FP64 finest
+    // level alternates its copy once per refinement step)
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    bool graph_failed = false;
+    int capturing = -1;             // slot being captured, -1 when none
+    // kernel timing (opts.timing)
     struct Pending { hipEvent_t a, b; int cls; };
     std::vector<hipEvent_t> ev_pool;
-    std::vector<Pending> pending;
+    std::vector<Pending> pending;        // resolved and recycled after each sync
+    std::vector<Pending> graph_pairs[2]; // recorded by every replay of a graph slot
+    int last_slot = -1;                  // slot replayed since the last synchronisation
     double t_ms[CHHS_K_COUNT] = {};
     int64_t t_n[CHHS_K_COUNT] = {};
 };
 
 namespace {
-
-constexpr size_t kAlign = 256;
-
-size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 bool valid_problem(const chhs_problem* p) {
     if (p == nullptr) return false;
@@ -50,7 +127,7 @@ bool valid_problem(const chhs_problem* p) {
         !std::isfinite(p->dt))
         return false;
     const double cells = double(p->nx) * p->ny * p->nz;
-    return cells < 2147483647.0;
+    return cells < 1073741824.0;
 }
 
 bool valid_opts(const chhs_opts* o) {
@@ -58,7 +135,7 @@ bool valid_opts(const chhs_opts* o) {
     if (o->nu1 < 0 || o->nu2 < 0 || o->nu1 + o->nu2 < 1) return false;
     if (o->max_vcycles < 1 || o->coarse_sweeps < 1) return false;
     if (!(o->tol > 0.0) || !std::isfinite(o->tol)) return false;
-    if (o->precision != 0) return false;   // FP64 only in this build of the driver
+    if (o->precision != 0 && o->precision != 1) return false;
     return true;
 }
 
@@ -67,10 +144,7 @@ bool valid_opts(const chhs_opts* o) {
 // two levels.
 bool level_extents(const chhs_problem* p, std::vector<int>& ext) {
     int nx = p->nx, ny = p->ny, nz = p->nz;
-    ext.clear();
-    ext.push_back(nx);
-    ext.push_back(ny);
-    ext.push_back(nz);
+    ext.assign({nx, ny, nz});
     for (;;) {
         const bool even = nx % 2 == 0 && ny % 2 == 0 && (p->dim == 2 || nz % 2 == 0);
         const bool big = nx >= 4 && ny >= 4 && (p->dim == 2 || nz >= 4);
@@ -78,93 +152,194 @@ bool level_extents(const chhs_problem* p, std::vector<int>& ext) {
         nx /= 2;
         ny /= 2;
         if (p->dim == 3) nz /= 2;
-        ext.push_back(nx);
-        ext.push_back(ny);
-        ext.push_back(nz);
+        ext.insert(ext.end(), {nx, ny, nz});
     }
     const int nlev = int(ext.size() / 3);
-    if (nlev < 2) return false;
+    if (nlev < 2 || nlev > kMaxLevels) return false;
     return nx <= 8 && ny <= 8 && nz <= 8;
 }
 
-// Blocks whose partial sums the reduction buffer must hold.
-int partial_capacity(const chhs_problem* p) {
-    int cap = chhs::kMaxPartials;
-    if (p->dim == 2) {
-        const int t = chhs::tile2d_blocks(p->nx, p->ny);
-        if (t > cap) cap = t;
-    }
-    return cap;
-}
-
-// First level of the single-workgroup tail: the finest level whose own and
-// coarser levels' 11 fields fit the LDS budget.
-int pick_tail(const std::vector<Level<double>>& lv, size_t* bytes) {
-    const int nlev = int(lv.size());
-    std::vector<int> cells(nlev);
-    for (int l = 0; l < nlev; ++l) cells[l] = lv[l].n;
+// First level of the one-workgroup tail: the finest level whose own and
+// coarser levels' FP64 fields (and, in mixed precision, the 12 FP32 fields of
+// the correction form) fit the LDS budget.
+int pick_tail(const std::vector<int>& cells, bool mixed, size_t* bytes, size_t* bytes32) {
+    const int nlev = int(cells.size());
     for (int l = 0; l < nlev; ++l) {
         if (nlev - l > chhs::kMaxTailLevels) continue;
-        const size_t b = chhs::tail_lds_bytes(&cells[l], nlev - l, sizeof(double));
-        if (b <= chhs::kTailLdsBudget) {
+        const size_t b = chhs::tail_lds_bytes(&cells[l], nlev - l, sizeof(double), 11);
+        const size_t b32 = chhs::tail_lds_bytes(&cells[l], nlev - l, sizeof(float), 12);
+        if (b <= chhs::kTailLdsBudget && (!mixed || b32 <= chhs::kTailLdsBudget)) {
             *bytes = b;
+            *bytes32 = b32;
             return l;
         }
     }
-    *bytes = chhs::tail_lds_bytes(&cells[nlev - 1], 1, sizeof(double));
+    *bytes = chhs::tail_lds_bytes(&cells[nlev - 1], 1, sizeof(double), 11);
+    *bytes32 = chhs::tail_lds_bytes(&cells[nlev - 1], 1, sizeof(float), 12);
     return nlev - 1;
 }
 
-// Walks the workspace layout; assigns pointers when base != nullptr.
-size_t plan(const chhs_problem* p, char* base, std::vector<Level<double>>* out,
-            double** partial, double** dres) {
-    std::vector<int> ext;
-    if (!level_extents(p, ext)) return 0;
-    size_t off = 0;
-    auto take = [&](size_t count) -> double* {
-        double* ptr = base ? reinterpret_cast<double*>(base + off) : nullptr;
-        off += align_up(count * sizeof(double));
-        return ptr;
-    };
-    const int nlev = int(ext.size() / 3);
-    double h = p->h;
-    for (int l = 0; l < nlev; ++l) {
-        Level<double> L{};
-        L.nx = ext[3 * l];
-        L.ny = ext[3 * l + 1];
-        L.nz = ext[3 * l + 2];
-        L.n = L.nx * L.ny * L.nz;
-        const size_t n = size_t(L.n);
-        L.phi = take(n);
-        L.mu = take(n);
-        L.p = take(n);
-        if (l > 0) {
-            L.ub0 = take(n);
-            L.ub1 = take(n);
-            L.ub2 = take(n);
-        }
-        L.f0 = take(n);
-        L.f1 = take(n);
-        L.f2 = take(n);
-        L.pstar = take(n);
-        L.psi = take(n);
-        if (p->dim == 2) {
-            L.phi_alt = take(n);
-            L.mu_alt = take(n);
-            L.p_alt = take(n);
-        }
-        L.h = h;
-        L.lam = p->dt / (h * h);
-        L.kap = 0.75 * p->eps * p->eps / (h * h);
-        L.gamma = p->gamma;
-        if (out) out->push_back(L);
-        h *= 2.0;
+void cell_tasks(std::vector<CellTask>& out, int inst, int n) {
+    for (int c = 0; c < n; c += chhs::kBlock) out.push_back({inst, c});
+}
+
+void tile_tasks(std::vector<TileTask>& out, int inst, int nx, int ny) {
+    const int tx = (nx + chhs::kTileX - 1) / chhs::kTileX;
+    const int ty = (ny + chhs::kTileY - 1) / chhs::kTileY;
+    for (int by = 0; by < ty; ++by)
+        for (int bx = 0; bx < tx; ++bx) out.push_back({inst, bx, by});
+}
+
+void ranges_of(std::vector<Range>& r, int n_inst, const std::vector<CellTask>& t) {
+    r.assign(n_inst, Range{0, 0});
+    for (int q = 0; q < int(t.size()); ++q) {
+        Range& x = r[t[q].inst];
+        if (x.end == 0) x.begin = q;
+        x.end = q + 1;
     }
-    double* part = take(size_t(partial_capacity(p)) * chhs::kPartialStride);
-    double* res = take(64);
-    if (partial) *partial = part;
-    if (dres) *dres = res;
-    return off;
+}
+
+// Builds the layout; base != nullptr fills the device pointers of the descriptors.
+bool plan(const chhs_problem* p, int n_inst, const chhs_opts* o, char* base, Layout& L) {
+    L = Layout();
+    const int dim = p[0].dim;
+    const bool mixed = o->precision == 1;
+    L.A.resize(kMaxLevels);
+    L.B.resize(kMaxLevels);
+    L.Bc.resize(kMaxLevels);
+    L.T.resize(kMaxLevels);
+    L.Tall.resize(kMaxLevels);
+    L.desc.assign(size_t(n_inst) * kMaxLevels, LevelDesc<double>{});
+    if (mixed) L.desc32.assign(size_t(n_inst) * kMaxLevels, LevelDesc<float>{});
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> size_t {
+        const size_t o2 = off;
+        off += align_up(bytes);
+        return o2;
+    };
+    auto ptr = [&](size_t o2) -> double* {
+        return base ? reinterpret_cast<double*>(base + o2) : nullptr;
+    };
+    auto ptr32 = [&](size_t o2) -> float* {
+        return base ? reinterpret_cast<float*>(base + o2) : nullptr;
+    };
+    int packed = 0;
+    for (int i = 0; i < n_inst; ++i) {
+        if (!valid_problem(&p[i]) || p[i].dim != dim) return false;
+        std::vector<int> ext;
+        if (!level_extents(&p[i], ext)) return false;
+        const int nlev = int(ext.size() / 3);
+        std::vector<int> cells(nlev);
+        for (int l = 0; l < nlev; ++l) cells[l] = ext[3 * l] * ext[3 * l + 1] * ext[3 * l + 2];
+        size_t tb = 0, tb32 = 0;
+        const int tail = pick_tail(cells, mixed, &tb, &tb32);
+        L.tail_lds = std::max(L.tail_lds, tb);
+        L.tail_lds32 = std::max(L.tail_lds32, tb32);
+        InstInfo in{};
+        in.dim = dim;
+        in.nlev = nlev;
+        in.tail = tail;
+        in.off = packed;
+        in.n0 = cells[0];
+        in.fused = (!mixed && dim == 2 && o->nu2 > 0 && tail > 0) ? 1 : 0;
+        in.h = p[i].h;
+        in.eps = p[i].eps;
+        in.gamma = p[i].gamma;
+        in.dt = p[i].dt;
+        L.info.push_back(in);
+        packed += cells[0];
+        L.max_nlev = std::max(L.max_nlev, nlev);
+        L.depth = std::max(L.depth, tail);
+        double h = p[i].h;
+        for (int l = 0; l < nlev; ++l) {
+            const int n = cells[l];
+            LevelDesc<double>& d = L.desc[size_t(i) * kMaxLevels + l];
+            d.nx = ext[3 * l];
+            d.ny = ext[3 * l + 1];
+            d.nz = ext[3 * l + 2];
+            d.n = n;
+            const size_t nb = size_t(n) * sizeof(double);
+            for (int k = 0; k < 3; ++k) d.u[0][k] = ptr(take(nb));
+            // a second copy of u for out-of-place kernels: the tiled smoother
+            // (2D) and the FP64 refinement step (mixed, finest level)
+            const bool two = dim == 2 || (mixed && l == 0);
+            for (int k = 0; k < 3; ++k) d.u[1][k] = two ? ptr(take(nb)) : d.u[0][k];
+            if (l > 0)
+                for (int k = 0; k < 3; ++k) d.ub[k] = ptr(take(nb));
+            for (int k = 0; k < 3; ++k) d.f[k] = ptr(take(nb));
+            d.pstar = ptr(take(nb));
+            d.psi = ptr(take(nb));
+            d.b = nullptr;
+            d.h = h;
+            d.lam = p[i].dt / (h * h);
+            d.kap = 0.75 * p[i].eps * p[i].eps / (h * h);
+            d.gamma = p[i].gamma;
+            if (mixed) {
+                LevelDesc<float>& e = L.desc32[size_t(i) * kMaxLevels + l];
+                e.nx = d.nx;
+                e.ny = d.ny;
+                e.nz = d.nz;
+                e.n = n;
+                const size_t nf = size_t(n) * sizeof(float);
+                for (int k = 0; k < 3; ++k) e.u[0][k] = ptr32(take(nf));
+                for (int k = 0; k < 3; ++k) e.u[1][k] = dim == 2 ? ptr32(take(nf)) : e.u[0][k];
+                if (l > 0)
+                    for (int k = 0; k < 3; ++k) e.ub[k] = ptr32(take(nf));
+                for (int k = 0; k < 3; ++k) e.f[k] = ptr32(take(nf));
+                e.pstar = ptr32(take(nf));
+                e.psi = ptr32(take(nf));
+                e.b = ptr32(take(nf));
+                e.h = float(h);
+                e.lam = float(d.lam);
+                e.kap = float(d.kap);
+                e.gamma = float(d.gamma);
+            }
+            h *= 2.0;
+            cell_tasks(L.A[l], i, n);
+            if (l < tail) cell_tasks(L.B[l], i, n);
+            if (dim == 2) tile_tasks(L.Tall[l], i, d.nx, d.ny);
+            if (dim == 2 && l < tail) tile_tasks(L.T[l], i, d.nx, d.ny);
+        }
+        for (int l = 0; l + 1 < nlev && l < tail; ++l) cell_tasks(L.Bc[l], i, cells[l + 1]);
+        if (!in.fused) cell_tasks(L.A0n, i, cells[0]);
+        L.tail_insts.push_back(i);
+    }
+    // per-instance ranges of the finest-level partial buffers
+    ranges_of(L.rngA0, n_inst, L.A[0]);
+    ranges_of(L.rngA0n, n_inst, L.A0n);
+    L.rngT0.assign(n_inst, Range{0, 0});
+    for (int q = 0; q < int(L.T[0].size()); ++q) {
+        Range& r = L.rngT0[L.T[0][q].inst];
+        if (r.end == 0) r.begin = q;
+        r.end = q + 1;
+    }
+    L.partial_cap = int(L.A[0].size());
+    L.partial_t_cap = int(std::max<size_t>(1, L.T[0].size()));
+    L.off_desc = take(L.desc.size() * sizeof(LevelDesc<double>));
+    L.off_desc32 = take(std::max<size_t>(1, L.desc32.size()) * sizeof(LevelDesc<float>));
+    L.off_info = take(L.info.size() * sizeof(InstInfo));
+    L.off_tail = take(L.tail_insts.size() * sizeof(int));
+    L.off_rngA0 = take(n_inst * sizeof(Range));
+    L.off_rngT0 = take(n_inst * sizeof(Range));
+    L.off_rngA0n = take(n_inst * sizeof(Range));
+    L.off_A0n = take(L.A0n.size() * sizeof(CellTask));
+    for (int l = 0; l < kMaxLevels; ++l) {
+        L.off_A.push_back(take(L.A[l].size() * sizeof(CellTask)));
+        L.off_B.push_back(take(L.B[l].size() * sizeof(CellTask)));
+        L.off_Bc.push_back(take(L.Bc[l].size() * sizeof(CellTask)));
+        L.off_T.push_back(take(L.T[l].size() * sizeof(TileTask)));
+        L.off_Tall.push_back(take(L.Tall[l].size() * sizeof(TileTask)));
+    }
+    L.off_partial = take(size_t(L.partial_cap) * chhs::kPartialStride * sizeof(double));
+    L.off_partial_t = take(size_t(L.partial_t_cap) * chhs::kPartialStride * sizeof(double));
+    // res | act_next | cycles contiguous: one readback per cycle
+    L.off_res = take(size_t(n_inst) * chhs::kResStride * sizeof(double) + 2 * n_inst * sizeof(int));
+    L.off_act_next = L.off_res + size_t(n_inst) * chhs::kResStride * sizeof(double);
+    L.off_cycles = L.off_act_next + n_inst * sizeof(int);
+    L.off_eres = take(size_t(n_inst) * chhs::kResStride * sizeof(double));
+    L.off_act_cycle = take(n_inst * sizeof(int));
+    L.bytes = off;
+    return true;
 }
 
 #define HIP_TRY(expr)                                  \
@@ -173,6 +348,17 @@ size_t plan(const chhs_problem* p, char* base, std::vector<Level<double>>* out,
     } while (0)
 
 int check_launch() { return hipGetLastError() == hipSuccess ? CHHS_OK : CHHS_E_HIP; }
+
+template <typename Task>
+int upload(Table<Task>& t, char* base, size_t off, const std::vector<Task>& v, hipStream_t st) {
+    t.dev = reinterpret_cast<Task*>(base + off);
+    t.n = int(v.size());
+    if (!v.empty())
+        HIP_TRY(hipMemcpyAsync(t.dev, v.data(), v.size() * sizeof(Task), hipMemcpyHostToDevice, st));
+    return CHHS_OK;
+}
+
+// ---- kernel timing ---------------------------------------------------------------------
 
 hipEvent_t pooled_event(chhs_ctx* c) {
     if (c->ev_pool.empty()) {
@@ -186,7 +372,8 @@ hipEvent_t pooled_event(chhs_ctx* c) {
 }
 
 // Brackets the launches issued during its lifetime with a pair of events on
-// the context stream when timing is enabled.
+// the context stream when timing is enabled (captured into the graph when a
+// cycle is being captured).
 class TimedScope {
   public:
     TimedScope(chhs_ctx* c, int cls) : c_(c), cls_(cls) {
@@ -199,7 +386,10 @@ class TimedScope {
         hipEvent_t b = pooled_event(c_);
         if (b == nullptr) return;
         (void)hipEventRecord(b, c_->stream);
-        c_->pending.push_back({a_, b, cls_});
+        if (c_->capturing >= 0)
+            c_->graph_pairs[c_->capturing].push_back({a_, b, cls_});
+        else
+            c_->pending.push_back({a_, b, cls_});
     }
 
   private:
@@ -208,202 +398,366 @@ class TimedScope {
     hipEvent_t a_ = nullptr;
 };
 
-// Accumulates the elapsed times of completed event pairs (stream synchronised).
+void accumulate(chhs_ctx* c, const chhs_ctx::Pending& pe) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, pe.a, pe.b) == hipSuccess) {
+        c->t_ms[pe.cls] += ms;
+        c->t_n[pe.cls] += 1;
+    }
+}
+
+// After a stream synchronisation: accumulate the event pairs of the graph
+// replayed since the last one, and accumulate and recycle the eager pairs.
 void resolve_timing(chhs_ctx* c) {
+    if (c->last_slot >= 0)
+        for (auto& pe : c->graph_pairs[c->last_slot]) accumulate(c, pe);
+    c->last_slot = -1;
     for (auto& pe : c->pending) {
-        float ms = 0.0f;
-        if (hipEventElapsedTime(&ms, pe.a, pe.b) == hipSuccess) {
-            c->t_ms[pe.cls] += ms;
-            c->t_n[pe.cls] += 1;
-        }
+        accumulate(c, pe);
         c->ev_pool.push_back(pe.a);
         c->ev_pool.push_back(pe.b);
     }
     c->pending.clear();
 }
 
-// After an out-of-place launch on level l: the written copy becomes current.
-void swap_u(chhs_ctx* c, int l) {
-    Level<double>& L = c->lv[l];
-    std::swap(L.phi, L.phi_alt);
-    std::swap(L.mu, L.mu_alt);
-    std::swap(L.p, L.p_alt);
+// ---- batched launches ------------------------------------------------------------------
+
+template <typename T>
+Batch<T> make_batch(const LevelDesc<T>* desc, const int* cur, int level, const int* active) {
+    Batch<T> b;
+    b.desc = desc;
+    b.active = active;
+    b.level = level;
+    b.cur = cur[level];
+    b.cur_c = 0;    // a coarser level is always at copy 0 when a transfer touches it
+    return b;
 }
 
-// Per-cell red-black smoothing (3D levels above the tail, and chhs_smooth on 3D).
-void smooth_cells(chhs_ctx* c, int l, int cls) {
-    for (int color = 0; color < 2; ++color) {
+Batch<double> batch(chhs_ctx* c, int level, const int* active) {
+    return make_batch(c->ddesc, c->cur, level, active);
+}
+
+Batch<float> batch32(chhs_ctx* c, int level, const int* active) {
+    return make_batch(c->ddesc32, c->cur32, level, active);
+}
+
+// The hierarchy of one precision: device descriptors, host copies, current
+// copies of u per level, tail LDS bytes.
+template <typename T>
+struct Hier {
+    const LevelDesc<T>* dev;
+    const std::vector<LevelDesc<T>>* host;
+    int* cur;
+    size_t tail_lds;
+};
+
+Hier<double> hier64(chhs_ctx* c) { return {c->ddesc, &c->lay.desc, c->cur, c->lay.tail_lds}; }
+Hier<float> hier32(chhs_ctx* c) { return {c->ddesc32, &c->lay.desc32, c->cur32, c->lay.tail_lds32}; }
+
+// One tiled launch on level l; flips the level's current copy.
+template <typename T>
+void tiled(chhs_ctx* c, const Hier<T>& H, const Table<TileTask>& tt, int l, int ns, int epi,
+           bool pro, const int* active, int cls) {
+    Batch<T> b = make_batch(H.dev, H.cur, l, active);
+    {
         TimedScope t(c, cls);
-        chhs::launch_smooth(c->prob.dim, c->lv[l], color, c->stream);
+        chhs::launch_tile2d<T>(b, tt.dev, tt.n, std::is_same<T, double>::value && l == 0, ns, epi,
+                               pro, epi == 2 ? c->partial_t : nullptr, c->stream);
     }
+    H.cur[l] ^= 1;
 }
 
-// nsweeps smoothing steps on level l with the production kernels.
-void smooth_steps(chhs_ctx* c, int l, int nsweeps, int cls) {
-    if (c->prob.dim == 2) {
-        const Level<double>& L = c->lv[l];
+// An odd number of out-of-place launches on level l left copy 1 current: copy
+// it back so that every level ends each V-cycle on copy 0.
+template <typename T>
+void restore_copy0(chhs_ctx* c, const Hier<T>& H, int l) {
+    for (int i = 0; i < c->n_inst; ++i) {
+        const LevelDesc<T>& d = (*H.host)[size_t(i) * kMaxLevels + l];
+        if (d.u[1][0] == d.u[0][0] || d.n == 0) continue;
+        const size_t nb = size_t(d.n) * sizeof(T);
+        for (int k = 0; k < 3; ++k)
+            (void)hipMemcpyAsync(d.u[0][k], d.u[1][k], nb, hipMemcpyDeviceToDevice, c->stream);
+    }
+    H.cur[l] = 0;
+}
+
+// nsweeps smoothing steps on level l of the FP64 hierarchy (2D: tiled,
+// including levels inside the tail for kernel tests; 3D: per-cell red-black).
+void smooth_steps(chhs_ctx* c, int l, int nsweeps, const int* active, int cls) {
+    if (c->dim == 2) {
         while (nsweeps > 0) {
             const int k = nsweeps >= 2 ? 2 : 1;
             nsweeps -= k;
-            {
-                TimedScope t(c, cls);
-                chhs::launch_tile2d<double>(L, L, l == 0, k, 0, false, nullptr, c->stream);
-            }
-            swap_u(c, l);
+            tiled(c, hier64(c), c->Tall[l], l, k, 0, false, active, cls);
         }
         return;
     }
-    for (int s = 0; s < nsweeps; ++s) smooth_cells(c, l, cls);
+    Batch<double> b = batch(c, l, active);
+    for (int s = 0; s < nsweeps; ++s)
+        for (int color = 0; color < 2; ++color) {
+            TimedScope t(c, cls);
+            chhs::launch_smooth(3, b, c->A[l].dev, c->A[l].n, color, c->stream);
+        }
 }
 
-// One V-cycle from level l.  Returns the number of residual-norm partials the
-// finest level's last post-smoothing launch produced (0 if none).
-int vcycle(chhs_ctx* c, int l) {
-    const int dim = c->prob.dim;
-    const int nlev = int(c->lv.size());
-    const bool l0 = l == 0;
-    if (l >= c->tail) {
-        TimedScope t(c, l0 ? CHHS_K_PRE0 : CHHS_K_COARSE);
-        chhs::launch_tail<double>(dim, &c->lv[l], nlev - l, c->opts.nu1, c->opts.nu2,
-                                  c->opts.coarse_sweeps, c->tail_lds, c->stream);
-        return 0;
-    }
-    const Level<double>& L = c->lv[l];
-    const Level<double>& C = c->lv[l + 1];
-    const int pre_cls = l0 ? CHHS_K_PRE0 : CHHS_K_COARSE;
-    const int post_cls = l0 ? CHHS_K_POST0 : CHHS_K_COARSE;
-    const int xfer_cls = l0 ? CHHS_K_TRANSFER0 : CHHS_K_COARSE;
-    int nb = 0;
-    if (dim == 2) {
-        int rem = c->opts.nu1;
-        if (rem == 0) {
-            TimedScope t(c, xfer_cls);
-            chhs::launch_restrict_residual(dim, L, C, c->stream);
-        } else {
+// Enqueues one FAS V(nu1, nu2) cycle of one hierarchy over the batch for the
+// instances in act_cycle.  FP64: the plain form, whose finest-level post
+// launch also yields the fused norm partials; FP32: the correction form.
+template <typename T>
+void enqueue_vcycle(chhs_ctx* c, const Hier<T>& H) {
+    constexpr bool kPlain = std::is_same<T, double>::value;
+    const int dim = c->dim;
+    const int* act = c->act_cycle;
+    const int depth = c->lay.depth;
+    const chhs_opts& o = c->opts;
+    for (int d = 0; d < depth; ++d) {
+        const int pre_cls = d == 0 ? CHHS_K_PRE0 : CHHS_K_COARSE;
+        const int xfer_cls = d == 0 ? CHHS_K_TRANSFER0 : CHHS_K_COARSE;
+        if (dim == 2 && o.nu1 > 0) {
+            int rem = o.nu1;
             while (rem > 2) {
-                {
-                    TimedScope t(c, pre_cls);
-                    chhs::launch_tile2d<double>(L, C, l0, 2, 0, false, nullptr, c->stream);
-                }
-                swap_u(c, l);
+                tiled(c, H, c->T[d], d, 2, 0, false, act, pre_cls);
                 rem -= 2;
             }
-            {
-                TimedScope t(c, pre_cls);
-                chhs::launch_tile2d<double>(L, C, l0, rem, 1, false, nullptr, c->stream);
-            }
-            swap_u(c, l);
-        }
-        {
-            TimedScope t(c, xfer_cls);
-            chhs::launch_coarse_rhs(dim, C, c->stream);
-        }
-        vcycle(c, l + 1);
-        rem = c->opts.nu2;
-        if (rem == 0) {
-            TimedScope t(c, xfer_cls);
-            chhs::launch_prolong(dim, L, C, c->stream);
+            tiled(c, H, c->T[d], d, rem, 1, false, act, pre_cls);
         } else {
+            if (dim == 3)
+                for (int s = 0; s < o.nu1; ++s)
+                    for (int color = 0; color < 2; ++color) {
+                        TimedScope t(c, pre_cls);
+                        chhs::launch_smooth(3, make_batch(H.dev, H.cur, d, act), c->B[d].dev,
+                                            c->B[d].n, color, c->stream);
+                    }
+            TimedScope t(c, xfer_cls);
+            chhs::launch_restrict_residual(dim, make_batch(H.dev, H.cur, d, act), c->Bc[d].dev,
+                                           c->Bc[d].n, c->stream);
+        }
+        TimedScope t(c, xfer_cls);
+        chhs::launch_coarse_rhs(dim, make_batch(H.dev, H.cur, d, act), c->Bc[d].dev, c->Bc[d].n,
+                                c->stream);
+    }
+    {
+        // an instance's tail level is only ever written by the restriction into
+        // it (copy 0) and by the tail itself: it is always read from copy 0
+        TimedScope t(c, depth == 0 ? CHHS_K_PRE0 : CHHS_K_COARSE);
+        chhs::launch_tail<T, !kPlain>(dim, H.dev, c->dinfo, c->tail_insts, c->n_inst, act, 0u,
+                                      o.nu1, o.nu2, o.coarse_sweeps, H.tail_lds, c->stream);
+    }
+    for (int d = depth - 1; d >= 0; --d) {
+        const int post_cls = d == 0 ? CHHS_K_POST0 : CHHS_K_COARSE;
+        const int xfer_cls = d == 0 ? CHHS_K_TRANSFER0 : CHHS_K_COARSE;
+        if (dim == 2 && o.nu2 > 0) {
+            int rem = o.nu2;
             bool first = true;
             while (rem > 0) {
                 const int k = rem >= 2 ? 2 : 1;
                 rem -= k;
-                const bool norm = l0 && rem == 0;
-                {
-                    TimedScope t(c, post_cls);
-                    nb = chhs::launch_tile2d<double>(L, C, l0, k, norm ? 2 : 0, first,
-                                                     norm ? c->partial : nullptr, c->stream);
-                }
-                swap_u(c, l);
+                const bool norm = kPlain && d == 0 && rem == 0 && c->fused_norm;
+                tiled(c, H, c->T[d], d, k, norm ? 2 : 0, first, act, post_cls);
                 first = false;
             }
+        } else {
+            {
+                TimedScope t(c, xfer_cls);
+                chhs::launch_prolong(dim, make_batch(H.dev, H.cur, d, act), c->B[d].dev, c->B[d].n,
+                                     c->stream);
+            }
+            if (dim == 3)
+                for (int s = 0; s < o.nu2; ++s)
+                    for (int color = 0; color < 2; ++color) {
+                        TimedScope t(c, post_cls);
+                        chhs::launch_smooth(3, make_batch(H.dev, H.cur, d, act), c->B[d].dev,
+                                            c->B[d].n, color, c->stream);
+                    }
         }
-        return l0 && c->opts.nu2 > 0 ? nb : 0;
+        if (H.cur[d] != 0) restore_copy0(c, H, d);
     }
-    for (int s = 0; s < c->opts.nu1; ++s) smooth_cells(c, l, pre_cls);
-    {
-        TimedScope t(c, xfer_cls);
-        chhs::launch_restrict_residual(dim, L, C, c->stream);
-        chhs::launch_coarse_rhs(dim, C, c->stream);
-    }
-    vcycle(c, l + 1);
-    {
-        TimedScope t(c, xfer_cls);
-        chhs::launch_prolong(dim, L, C, c->stream);
-    }
-    for (int s = 0; s < c->opts.nu2; ++s) smooth_cells(c, l, post_cls);
-    return 0;
 }
 
-// Residual norms of level 0 into hres[0..3] (||R_phi||, ||R_mu||, ||R_p||, total);
-// p is shifted to mean zero on the way (it does not enter N).  nb > 0: the
-// partial sums of the current iterate are already in the partial buffer.
-int residual_and_normalise(chhs_ctx* c, int nb = 0) {
-    const Level<double>& L = c->lv[0];
-    {
-        TimedScope t(c, CHHS_K_NORM);
-        if (nb == 0) nb = chhs::launch_residual_partials(c->prob.dim, L, c->partial, c->stream);
-        chhs::launch_reduce_final(c->partial, nb, 4, c->dres, c->stream);
-        chhs::launch_shift_p(L, c->dres + 3, c->stream);
+// Plain FP64: one V-cycle, the residual norms (p normalised to mean zero).
+void enqueue_plain_cycle(chhs_ctx* c, bool count) {
+    const int* act = c->act_cycle;
+    const chhs_opts& o = c->opts;
+    chhs::launch_copy_int(c->act_cycle, c->act_next, c->n_inst, c->stream);
+    enqueue_vcycle(c, hier64(c));
+    TimedScope t(c, CHHS_K_NORM);
+    // instances without a fused finest-level norm: per-cell residual partials
+    chhs::launch_residual_partials(c->dim, batch(c, 0, act), c->A0n.dev, c->A0n.n, c->partial,
+                                   c->stream);
+    chhs::launch_inst_reduce(c->partial, c->rngA0n, c->partial_t, c->rngT0, 1, c->dinfo, act,
+                             c->act_next, c->cycles, c->res, c->n_inst, o.tol,
+                             count ? o.max_vcycles : 1 << 30, count ? 1 : 0, c->stream);
+    chhs::launch_shift_p(batch(c, 0, act), c->A[0].dev, c->A[0].n, c->res, c->stream);
+}
+
+// Mixed precision, one refinement step: zero FP32 correction, one FP32
+// correction-form V-cycle, then in FP64 u += e, the residual of the full
+// system (into the FP32 right-hand side) and its norms.
+void enqueue_refinement(chhs_ctx* c, bool count, bool add) {
+    const int* act = c->act_cycle;
+    const chhs_opts& o = c->opts;
+    chhs::launch_copy_int(c->act_cycle, c->act_next, c->n_inst, c->stream);
+    if (add) {
+        chhs::launch_zero_correction(batch32(c, 0, act), c->A[0].dev, c->A[0].n, c->stream);
+        enqueue_vcycle(c, hier32(c));
     }
-    int rc = check_launch();
-    if (rc) return rc;
-    HIP_TRY(hipMemcpyAsync(c->hres, c->dres, 4 * sizeof(double), hipMemcpyDeviceToHost,
-                           c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    resolve_timing(c);
-    const double hd = std::pow(L.h, c->prob.dim);
-    const double s0 = c->hres[0] * hd, s1 = c->hres[1] * hd, s2 = c->hres[2] * hd;
-    c->hres[0] = std::sqrt(s0);
-    c->hres[1] = std::sqrt(s1);
-    c->hres[2] = std::sqrt(s2);
-    c->hres[3] = std::sqrt(s0 + s1 + s2);
+    TimedScope t(c, CHHS_K_NORM);
+    chhs::launch_mixed_residual(c->dim, batch(c, 0, add ? act : nullptr), batch32(c, 0, act),
+                                c->A[0].dev, c->A[0].n, add ? 1 : 0, c->partial, c->stream);
+    c->cur[0] ^= 1;
+    chhs::launch_inst_reduce(c->partial, c->rngA0, nullptr, nullptr, 0, c->dinfo,
+                             add ? act : nullptr, c->act_next, c->cycles, c->res, c->n_inst,
+                             o.tol, count ? o.max_vcycles : 1 << 30, count ? 1 : 0, c->stream);
+    chhs::launch_shift_p(batch(c, 0, add ? act : nullptr), c->A[0].dev, c->A[0].n, c->res,
+                         c->stream);
+}
+
+void enqueue_cycle(chhs_ctx* c, bool count) {
+    if (c->mixed)
+        enqueue_refinement(c, count, true);
+    else
+        enqueue_plain_cycle(c, count);
+}
+
+// Readback of res | act_next | cycles (contiguous on both sides) into the
+// pinned mirror (enqueued).
+int enqueue_readback(chhs_ctx* c) {
+    const int n = c->n_inst;
+    const size_t bytes = size_t(n) * chhs::kResStride * sizeof(double) + 2 * n * sizeof(int);
+    HIP_TRY(hipMemcpyAsync(c->hres, c->res, bytes, hipMemcpyDeviceToHost, c->stream));
     return CHHS_OK;
 }
 
+int sync_results(chhs_ctx* c) {
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    resolve_timing(c);
+    return CHHS_OK;
+}
+
+void drop_graphs(chhs_ctx* c) {
+    for (int s = 0; s < 2; ++s) {
+        if (c->gexec[s]) (void)hipGraphExecDestroy(c->gexec[s]);
+        if (c->graph[s]) (void)hipGraphDestroy(c->graph[s]);
+        c->gexec[s] = nullptr;
+        c->graph[s] = nullptr;
+        for (auto& pe : c->graph_pairs[s]) {
+            c->ev_pool.push_back(pe.a);
+            c->ev_pool.push_back(pe.b);
+        }
+        c->graph_pairs[s].clear();
+    }
+}
+
+// One counted cycle (plain V-cycle or mixed refinement step) with norms and
+// readback, replayed from a captured graph when enabled; returns after the
+// results are on the host.  The graph slot is the FP64 finest level's current
+// copy, which a mixed refinement step flips.
+int run_cycle(chhs_ctx* c, bool count) {
+    const int slot = c->mixed ? c->cur[0] : 0;
+    if (count && c->opts.use_graph && !c->graph_failed && c->gexec[slot] == nullptr) {
+        c->capturing = slot;
+        const int saved_cur0 = c->cur[0];
+        bool ok = hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed) == hipSuccess;
+        hipGraph_t g = nullptr;
+        if (ok) {
+            enqueue_cycle(c, count);
+            ok = enqueue_readback(c) == CHHS_OK;
+            ok = (hipStreamEndCapture(c->stream, &g) == hipSuccess) && ok && g != nullptr;
+        }
+        c->capturing = -1;
+        if (ok && hipGraphInstantiate(&c->gexec[slot], g, nullptr, nullptr, 0) != hipSuccess) {
+            c->gexec[slot] = nullptr;
+            ok = false;
+        }
+        c->graph[slot] = g;
+        (void)hipGetLastError();
+        c->cur[0] = saved_cur0;   // the capture did not run anything
+        if (!ok) {
+            c->graph_failed = true;
+            drop_graphs(c);
+        }
+    }
+    if (count && c->gexec[slot] != nullptr) {
+        HIP_TRY(hipGraphLaunch(c->gexec[slot], c->stream));
+        c->last_slot = slot;
+        if (c->mixed) c->cur[0] ^= 1;
+    } else {
+        enqueue_cycle(c, count);
+        int rc = check_launch();
+        if (rc) return rc;
+        rc = enqueue_readback(c);
+        if (rc) return rc;
+    }
+    return sync_results(c);
+}
+
+// Setup of every instance's step system, p normalised to mean zero, and the
+// norms of the initial guess on the host.
 int setup(chhs_ctx* c, const double* phi_prev, const double* phi_cur, const double* mu,
           const double* p) {
-    const int dim = c->prob.dim;
-    const double q = 0.25 * c->prob.eps * c->prob.eps / (c->prob.h * c->prob.h);
-    TimedScope t(c, CHHS_K_SETUP);
-    chhs::launch_setup(dim, c->lv[0], phi_prev, phi_cur, mu, p, q, c->stream);
-    for (size_t l = 0; l + 1 < c->lv.size(); ++l)
-        chhs::launch_restrict_frozen(dim, c->lv[l], c->lv[l + 1], c->stream);
-    c->loaded = true;
-    return check_launch();
-}
-
-// Energies of phi against q (and the flow terms when mu != nullptr) into out[0..9]:
-// mass, E_h, F_h, diss_mu, diss_u, max|phi|.
-int energies(chhs_ctx* c, const double* phi, const double* q, const double* mu,
-             const double* p, const double* pstar, double* out) {
-    const chhs_problem& P = c->prob;
+    const int dim = c->dim;
     {
         TimedScope t(c, CHHS_K_SETUP);
-        const int nb = chhs::launch_energy_partials(P.dim, P.nx, P.ny, P.nz, phi, q, mu, p, pstar,
-                                                    P.gamma, c->partial, c->stream);
-        chhs::launch_reduce_energy(c->partial, nb, c->dres + 8, c->stream);
+        chhs::launch_fill_int(c->act_next, c->n_inst, 1, c->stream);
+        chhs::launch_fill_int(c->cycles, c->n_inst, 0, c->stream);
+        chhs::launch_copy_int(c->act_cycle, c->act_next, c->n_inst, c->stream);
+        chhs::launch_setup(dim, batch(c, 0, nullptr), c->A[0].dev, c->A[0].n, c->dinfo, phi_prev,
+                           phi_cur, mu, p, c->stream);
+        if (c->mixed) {
+            chhs::launch_mixed_frozen(batch(c, 0, nullptr), batch32(c, 0, nullptr), c->A[0].dev,
+                                      c->A[0].n, c->stream);
+            for (int l = 0; l + 1 < c->lay.max_nlev; ++l)
+                chhs::launch_restrict_frozen(dim, batch32(c, l, nullptr), c->A[l + 1].dev,
+                                             c->A[l + 1].n, c->stream);
+        } else {
+            for (int l = 0; l + 1 < c->lay.max_nlev; ++l)
+                chhs::launch_restrict_frozen(dim, batch(c, l, nullptr), c->A[l + 1].dev,
+                                             c->A[l + 1].n, c->stream);
+        }
+    }
+    if (c->mixed) {
+        enqueue_refinement(c, false, false);
+    } else {
+        TimedScope t(c, CHHS_K_NORM);
+        chhs::launch_residual_partials(dim, batch(c, 0, nullptr), c->A[0].dev, c->A[0].n,
+                                       c->partial, c->stream);
+        chhs::launch_inst_reduce(c->partial, c->rngA0, nullptr, nullptr, 0, c->dinfo, nullptr,
+                                 c->act_next, c->cycles, c->res, c->n_inst, c->opts.tol,
+                                 c->opts.max_vcycles, 0, c->stream);
+        chhs::launch_shift_p(batch(c, 0, nullptr), c->A[0].dev, c->A[0].n, c->res, c->stream);
     }
     int rc = check_launch();
     if (rc) return rc;
-    HIP_TRY(hipMemcpyAsync(c->hres + 8, c->dres + 8, 9 * sizeof(double),
+    rc = enqueue_readback(c);
+    if (rc) return rc;
+    c->loaded = true;
+    return sync_results(c);
+}
+
+// Energies into heres (per instance): workspace mode or caller arrays.
+int energies(chhs_ctx* c, int ws, const double* phi, const double* q) {
+    {
+        TimedScope t(c, CHHS_K_SETUP);
+        chhs::launch_energy_partials(c->dim, batch(c, 0, nullptr), c->A[0].dev, c->A[0].n,
+                                     c->dinfo, ws, phi, q, c->partial, c->stream);
+        chhs::launch_energy_reduce(c->partial, c->rngA0, c->dinfo, c->eres, c->n_inst, c->stream);
+    }
+    int rc = check_launch();
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(c->heres, c->eres, size_t(c->n_inst) * chhs::kResStride * sizeof(double),
                            hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    resolve_timing(c);
-    const double* v = c->hres + 8;
-    const double h = P.h, hd = std::pow(h, P.dim), e2 = P.eps * P.eps, ih2 = 1.0 / (h * h);
-    const double E = hd * (0.25 * v[2] - 0.5 * v[1] + 0.5 * e2 * v[3] * ih2);
-    out[0] = hd * v[0];
-    out[1] = E;
-    out[2] = E + hd * (0.25 * v[4] + 0.125 * e2 * v[5] * ih2);
-    out[3] = P.dt * hd * v[6] * ih2;
-    out[4] = P.gamma > 0.0 ? P.dt / P.gamma * hd * v[7] * ih2 : 0.0;
-    out[5] = v[8];
-    return CHHS_OK;
+    return sync_results(c);
+}
+
+const double* hres_of(chhs_ctx* c, int i) { return c->hres + size_t(i) * chhs::kResStride; }
+
+bool any_active(chhs_ctx* c) {
+    for (int i = 0; i < c->n_inst; ++i)
+        if (c->hact[i]) return true;
+    return false;
 }
 
 }  // namespace
-
 extern "C" {
 
 void chhs_default_opts(chhs_opts* o) {
@@ -415,41 +769,101 @@ void chhs_default_opts(chhs_opts* o) {
     o->coarse_sweeps = 4;
     o->tol = 1e-10;
     o->precision = 0;
-    o->use_graph = 0;
+    o->use_graph = 1;
     o->timing = 0;
 }
 
 size_t chhs_workspace_bytes(const chhs_problem* p, int32_t n_inst, const chhs_opts* o) {
-    if (n_inst != 1 || !valid_problem(p) || !valid_opts(o)) return 0;
-    return plan(p, nullptr, nullptr, nullptr, nullptr);
+    if (p == nullptr || n_inst < 1 || !valid_opts(o)) return 0;
+    Layout L;
+    if (!plan(p, n_inst, o, nullptr, L)) return 0;
+    return L.bytes;
 }
 
 int chhs_init(const chhs_problem* p, int32_t n_inst, const chhs_opts* o, void* workspace_dev,
               size_t ws_bytes, void* hip_stream, chhs_ctx** out) {
     if (out == nullptr) return CHHS_E_INVAL;
     *out = nullptr;
-    if (n_inst != 1 || !valid_problem(p) || !valid_opts(o) || workspace_dev == nullptr)
+    if (p == nullptr || n_inst < 1 || !valid_opts(o) || workspace_dev == nullptr)
         return CHHS_E_INVAL;
     if (reinterpret_cast<uintptr_t>(workspace_dev) % kAlign != 0) return CHHS_E_INVAL;
-    const size_t need = plan(p, nullptr, nullptr, nullptr, nullptr);
-    if (need == 0) return CHHS_E_INVAL;
-    if (ws_bytes < need) return CHHS_E_NOMEM;
+    Layout probe;
+    if (!plan(p, n_inst, o, nullptr, probe)) return CHHS_E_INVAL;
+    if (ws_bytes < probe.bytes) return CHHS_E_NOMEM;
     chhs_ctx* c = new chhs_ctx();
-    c->prob = *p;
+    c->prob.assign(p, p + n_inst);
     c->opts = *o;
     c->n_inst = n_inst;
+    c->dim = p[0].dim;
+    c->mixed = o->precision == 1;
     c->stream = static_cast<hipStream_t>(hip_stream);
-    plan(p, static_cast<char*>(workspace_dev), &c->lv, &c->partial, &c->dres);
-    c->tail = pick_tail(c->lv, &c->tail_lds);
-    if (chhs::prepare_tail<double>(p->dim, c->tail_lds) != 0) {
+    c->base = static_cast<char*>(workspace_dev);
+    plan(p, n_inst, o, c->base, c->lay);
+    Layout& L = c->lay;
+    char* b = c->base;
+    int rc = CHHS_OK;
+    auto fail = [&](int code) {
+        if (c->hres) (void)hipHostFree(c->hres);
         delete c;
-        return CHHS_E_HIP;
+        return code;
+    };
+    if (chhs::prepare_tail<double, false>(c->dim, L.tail_lds) != 0) return fail(CHHS_E_HIP);
+    if (c->mixed && chhs::prepare_tail<float, true>(c->dim, L.tail_lds32) != 0)
+        return fail(CHHS_E_HIP);
+    c->ddesc = reinterpret_cast<LevelDesc<double>*>(b + L.off_desc);
+    c->ddesc32 = reinterpret_cast<LevelDesc<float>*>(b + L.off_desc32);
+    c->dinfo = reinterpret_cast<InstInfo*>(b + L.off_info);
+    c->tail_insts = reinterpret_cast<int*>(b + L.off_tail);
+    c->rngA0 = reinterpret_cast<Range*>(b + L.off_rngA0);
+    c->rngT0 = reinterpret_cast<Range*>(b + L.off_rngT0);
+    c->rngA0n = reinterpret_cast<Range*>(b + L.off_rngA0n);
+    c->partial_t = reinterpret_cast<double*>(b + L.off_partial_t);
+    c->partial = reinterpret_cast<double*>(b + L.off_partial);
+    c->res = reinterpret_cast<double*>(b + L.off_res);
+    c->eres = reinterpret_cast<double*>(b + L.off_eres);
+    c->act_cycle = reinterpret_cast<int*>(b + L.off_act_cycle);
+    c->act_next = reinterpret_cast<int*>(b + L.off_act_next);
+    c->cycles = reinterpret_cast<int*>(b + L.off_cycles);
+    hipStream_t st = c->stream;
+    if (c->mixed && hipMemcpyAsync(c->ddesc32, L.desc32.data(),
+                                   L.desc32.size() * sizeof(LevelDesc<float>),
+                                   hipMemcpyHostToDevice, st) != hipSuccess)
+        return fail(CHHS_E_HIP);
+    if (hipMemcpyAsync(c->ddesc, L.desc.data(), L.desc.size() * sizeof(LevelDesc<double>),
+                       hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(c->dinfo, L.info.data(), L.info.size() * sizeof(InstInfo),
+                       hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(c->tail_insts, L.tail_insts.data(), L.tail_insts.size() * sizeof(int),
+                       hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(c->rngA0, L.rngA0.data(), n_inst * sizeof(Range), hipMemcpyHostToDevice,
+                       st) != hipSuccess ||
+        hipMemcpyAsync(c->rngT0, L.rngT0.data(), n_inst * sizeof(Range), hipMemcpyHostToDevice,
+                       st) != hipSuccess ||
+        hipMemcpyAsync(c->rngA0n, L.rngA0n.data(), n_inst * sizeof(Range), hipMemcpyHostToDevice,
+                       st) != hipSuccess)
+        return fail(CHHS_E_HIP);
+    for (int l = 0; l < kMaxLevels; ++l) {
+        rc |= upload(c->A[l], b, L.off_A[l], L.A[l], st);
+        rc |= upload(c->B[l], b, L.off_B[l], L.B[l], st);
+        rc |= upload(c->Bc[l], b, L.off_Bc[l], L.Bc[l], st);
+        rc |= upload(c->T[l], b, L.off_T[l], L.T[l], st);
+        rc |= upload(c->Tall[l], b, L.off_Tall[l], L.Tall[l], st);
     }
-    if (hipHostMalloc(reinterpret_cast<void**>(&c->hres), 64 * sizeof(double),
-                      hipHostMallocDefault) != hipSuccess) {
-        delete c;
-        return CHHS_E_HIP;
-    }
+    rc |= upload(c->A0n, b, L.off_A0n, L.A0n, st);
+    if (rc) return fail(CHHS_E_HIP);
+    // pinned mirror, same layout as the device result block: res | act_next |
+    // cycles, then the energies
+    const size_t nres = size_t(n_inst) * chhs::kResStride;
+    const size_t nint = (2 * size_t(n_inst) * sizeof(int) + sizeof(double) - 1) / sizeof(double);
+    const size_t hbytes = (2 * nres + nint) * sizeof(double);
+    if (hipHostMalloc(reinterpret_cast<void**>(&c->hres), hbytes, hipHostMallocDefault) !=
+        hipSuccess)
+        return fail(CHHS_E_HIP);
+    c->hact = reinterpret_cast<int*>(c->hres + nres);
+    c->hcyc = c->hact + n_inst;
+    c->heres = c->hres + nres + nint;
+    c->fused_norm = !c->mixed && c->dim == 2 && o->nu2 > 0;
+    if (hipStreamSynchronize(st) != hipSuccess) return fail(CHHS_E_HIP);
     *out = c;
     return CHHS_OK;
 }
@@ -459,41 +873,48 @@ int chhs_setup_step(chhs_ctx* c, const double* phi_prev, const double* phi_cur,
     if (c == nullptr || phi_prev == nullptr || phi_cur == nullptr || mu == nullptr ||
         p == nullptr)
         return CHHS_E_INVAL;
-    int rc = setup(c, phi_prev, phi_cur, mu, p);
-    if (rc) return rc;
-    return residual_and_normalise(c);
+    return setup(c, phi_prev, phi_cur, mu, p);
 }
 
 int chhs_fas_vcycle(chhs_ctx* c, double* res_norm_host) {
     if (c == nullptr) return CHHS_E_INVAL;
     if (!c->loaded) return CHHS_E_STATE;
-    const int nb = vcycle(c, 0);
-    int rc = check_launch();
+    // every instance takes part, whatever its convergence state
+    chhs::launch_fill_int(c->act_next, c->n_inst, 1, c->stream);
+    int rc = run_cycle(c, false);
     if (rc) return rc;
-    rc = residual_and_normalise(c, nb);
-    if (rc) return rc;
-    if (res_norm_host) res_norm_host[0] = c->hres[3];
-    return std::isfinite(c->hres[3]) ? CHHS_OK : CHHS_E_NONFINITE;
+    bool finite = true;
+    for (int i = 0; i < c->n_inst; ++i) {
+        if (res_norm_host) res_norm_host[i] = hres_of(c, i)[3];
+        finite = finite && std::isfinite(hres_of(c, i)[3]);
+    }
+    return finite ? CHHS_OK : CHHS_E_NONFINITE;
 }
 
 int chhs_residual_norms(chhs_ctx* c, double* out_host) {
     if (c == nullptr || out_host == nullptr) return CHHS_E_INVAL;
     if (!c->loaded) return CHHS_E_STATE;
-    int rc = residual_and_normalise(c);
+    chhs::launch_residual_partials(c->dim, batch(c, 0, nullptr), c->A[0].dev, c->A[0].n,
+                                   c->partial, c->stream);
+    chhs::launch_inst_reduce(c->partial, c->rngA0, nullptr, nullptr, 0, c->dinfo, nullptr,
+                             c->act_next, c->cycles, c->res, c->n_inst, c->opts.tol, 1 << 30, 0,
+                             c->stream);
+    int rc = check_launch();
     if (rc) return rc;
-    std::memcpy(out_host, c->hres, 4 * sizeof(double));
+    rc = enqueue_readback(c);
+    if (rc) return rc;
+    rc = sync_results(c);
+    if (rc) return rc;
+    for (int i = 0; i < c->n_inst; ++i) std::memcpy(out_host + 4 * i, hres_of(c, i), 4 * sizeof(double));
     return CHHS_OK;
 }
 
 int chhs_get_solution(chhs_ctx* c, double* phi, double* mu, double* p) {
     if (c == nullptr) return CHHS_E_INVAL;
     if (!c->loaded) return CHHS_E_STATE;
-    const Level<double>& L = c->lv[0];
-    const size_t bytes = size_t(L.n) * sizeof(double);
-    if (phi) HIP_TRY(hipMemcpyAsync(phi, L.phi, bytes, hipMemcpyDeviceToDevice, c->stream));
-    if (mu) HIP_TRY(hipMemcpyAsync(mu, L.mu, bytes, hipMemcpyDeviceToDevice, c->stream));
-    if (p) HIP_TRY(hipMemcpyAsync(p, L.p, bytes, hipMemcpyDeviceToDevice, c->stream));
-    return CHHS_OK;
+    chhs::launch_get_solution(batch(c, 0, nullptr), c->A[0].dev, c->A[0].n, c->dinfo, phi, mu, p,
+                              c->stream);
+    return check_launch();
 }
 
 int chhs_step(chhs_ctx* c, double* phi_prev, double* phi_cur, double* mu, double* p,
@@ -501,59 +922,55 @@ int chhs_step(chhs_ctx* c, double* phi_prev, double* phi_cur, double* mu, double
     if (c == nullptr || phi_prev == nullptr || phi_cur == nullptr || mu == nullptr ||
         p == nullptr || nsteps < 0)
         return CHHS_E_INVAL;
-    chhs_stats st;
-    std::memset(&st, 0, sizeof(st));
-    const Level<double>& L = c->lv[0];
-    const size_t bytes = size_t(L.n) * sizeof(double);
+    const int n = c->n_inst;
+    std::vector<chhs_stats> st(n);
+    for (auto& s : st) std::memset(&s, 0, sizeof(s));
     int rc = CHHS_OK;
-    for (int m = 0; m < nsteps; ++m) {
-        rc = chhs_setup_step(c, phi_prev, phi_cur, mu, p);
+    for (int m = 0; m < nsteps && rc == CHHS_OK; ++m) {
+        rc = setup(c, phi_prev, phi_cur, mu, p);
         if (rc) break;
-        st.res0 = c->hres[3];
-        int cycles = 0;
-        while (c->hres[3] > c->opts.tol && cycles < c->opts.max_vcycles) {
-            const int nb = vcycle(c, 0);
-            rc = residual_and_normalise(c, nb);
+        for (int i = 0; i < n; ++i) st[i].res0 = hres_of(c, i)[3];
+        while (any_active(c)) {
+            rc = run_cycle(c, true);
             if (rc) break;
-            ++cycles;
-            if (!std::isfinite(c->hres[3])) break;
         }
         if (rc) break;
-        st.vcycles = cycles;
-        st.total_vcycles += cycles;
-        for (int k = 0; k < 3; ++k) st.res[k] = c->hres[k];
-        st.res_norm = c->hres[3];
-        if (!std::isfinite(c->hres[3])) {
-            rc = CHHS_E_NONFINITE;
-            break;
+        for (int i = 0; i < n; ++i) {
+            const double* r = hres_of(c, i);
+            st[i].vcycles = c->hcyc[i];
+            st[i].total_vcycles += c->hcyc[i];
+            for (int k = 0; k < 3; ++k) st[i].res[k] = r[k];
+            st[i].res_norm = r[3];
+            st[i].status = CHHS_OK;
+            if (!std::isfinite(r[3]))
+                st[i].status = CHHS_E_NONFINITE;
+            else if (r[3] > c->opts.tol)
+                st[i].status = CHHS_E_NOCONV;
+            if (st[i].status != CHHS_OK && rc == CHHS_OK) rc = st[i].status;
         }
-        if (c->hres[3] > c->opts.tol) {
-            rc = CHHS_E_NOCONV;
-            break;
-        }
+        if (rc) break;
         if (m == nsteps - 1 && stats_host != nullptr) {
-            double e[6];
-            rc = energies(c, L.phi, phi_cur, L.mu, L.p, L.pstar, e);
+            rc = energies(c, 1, nullptr, nullptr);
             if (rc) break;
-            st.mass = e[0];
-            st.E_h = e[1];
-            st.F_h = e[2];
-            st.diss_mu = e[3];
-            st.diss_u = e[4];
-            st.max_abs_phi = e[5];
+            for (int i = 0; i < n; ++i) {
+                const double* e = c->heres + size_t(i) * chhs::kResStride;
+                st[i].mass = e[0];
+                st[i].E_h = e[1];
+                st[i].F_h = e[2];
+                st[i].diss_mu = e[3];
+                st[i].diss_u = e[4];
+                st[i].max_abs_phi = e[5];
+            }
         }
         // rotate: (phi^{m-1}, phi^m) <- (phi^m, phi^{m+1}); mu, p <- this step's
-        if (hipMemcpyAsync(phi_prev, phi_cur, bytes, hipMemcpyDeviceToDevice, c->stream) ||
-            hipMemcpyAsync(phi_cur, L.phi, bytes, hipMemcpyDeviceToDevice, c->stream) ||
-            hipMemcpyAsync(mu, L.mu, bytes, hipMemcpyDeviceToDevice, c->stream) ||
-            hipMemcpyAsync(p, L.p, bytes, hipMemcpyDeviceToDevice, c->stream)) {
-            rc = CHHS_E_HIP;
-            break;
-        }
-        ++st.steps_done;
+        chhs::launch_copy_out(batch(c, 0, nullptr), c->A[0].dev, c->A[0].n, c->dinfo, phi_prev,
+                              phi_cur, mu, p, c->stream);
+        rc = check_launch();
+        if (rc) break;
+        for (int i = 0; i < n; ++i) ++st[i].steps_done;
     }
-    st.status = rc;
-    if (stats_host) *stats_host = st;
+    if (stats_host != nullptr)
+        for (int i = 0; i < n; ++i) stats_host[i] = st[i];
     if (hipStreamSynchronize(c->stream) != hipSuccess && rc == CHHS_OK) rc = CHHS_E_HIP;
     return rc;
 }
@@ -561,37 +978,42 @@ int chhs_step(chhs_ctx* c, double* phi_prev, double* phi_cur, double* mu, double
 int chhs_energy_mass(chhs_ctx* c, const double* phi, const double* phi_prev, double* out_host) {
     if (c == nullptr || phi == nullptr || phi_prev == nullptr || out_host == nullptr)
         return CHHS_E_INVAL;
-    double e[6];
-    int rc = energies(c, phi, phi_prev, nullptr, nullptr, nullptr, e);
+    int rc = energies(c, 0, phi, phi_prev);
     if (rc) return rc;
-    out_host[0] = e[0];
-    out_host[1] = e[1];
-    out_host[2] = e[2];
+    for (int i = 0; i < c->n_inst; ++i) {
+        const double* e = c->heres + size_t(i) * chhs::kResStride;
+        out_host[3 * i + 0] = e[0];
+        out_host[3 * i + 1] = e[1];
+        out_host[3 * i + 2] = e[2];
+    }
     return CHHS_OK;
 }
 
 int chhs_level_count(chhs_ctx* c, int32_t* levels) {
-    if (c == nullptr || levels == nullptr) return CHHS_E_INVAL;
-    *levels = int32_t(c->lv.size());
+    if (c == nullptr || levels == nullptr || c->n_inst != 1) return CHHS_E_INVAL;
+    *levels = c->lay.info[0].nlev;
     return CHHS_OK;
 }
 
 int chhs_level_shape(chhs_ctx* c, int32_t level, int32_t* nxyz3) {
-    if (c == nullptr || nxyz3 == nullptr || level < 0 || level >= int(c->lv.size()))
+    if (c == nullptr || nxyz3 == nullptr || c->n_inst != 1 || level < 0 ||
+        level >= c->lay.info[0].nlev)
         return CHHS_E_INVAL;
-    nxyz3[0] = c->lv[level].nx;
-    nxyz3[1] = c->lv[level].ny;
-    nxyz3[2] = c->lv[level].nz;
+    const LevelDesc<double>& d = c->lay.desc[level];
+    nxyz3[0] = d.nx;
+    nxyz3[1] = d.ny;
+    nxyz3[2] = d.nz;
     return CHHS_OK;
 }
 
 int chhs_copy_field(chhs_ctx* c, int32_t level, int32_t field, double* dev, int32_t dir) {
-    if (c == nullptr || dev == nullptr || level < 0 || level >= int(c->lv.size()) ||
-        field < 0 || field > 7 || (dir != 0 && dir != 1))
+    if (c == nullptr || dev == nullptr || c->n_inst != 1 || level < 0 ||
+        level >= c->lay.info[0].nlev || field < 0 || field > 7 || (dir != 0 && dir != 1))
         return CHHS_E_INVAL;
-    Level<double>& L = c->lv[level];
-    double* f[8] = {L.phi, L.mu, L.p, L.f0, L.f1, L.f2, L.pstar, L.psi};
-    const size_t bytes = size_t(L.n) * sizeof(double);
+    const LevelDesc<double>& d = c->lay.desc[level];
+    const int cu = c->cur[level];
+    double* f[8] = {d.u[cu][0], d.u[cu][1], d.u[cu][2], d.f[0], d.f[1], d.f[2], d.pstar, d.psi};
+    const size_t bytes = size_t(d.n) * sizeof(double);
     if (dir == 0)
         HIP_TRY(hipMemcpyAsync(dev, f[field], bytes, hipMemcpyDeviceToDevice, c->stream));
     else
@@ -601,9 +1023,18 @@ int chhs_copy_field(chhs_ctx* c, int32_t level, int32_t field, double* dev, int3
 }
 
 int chhs_smooth(chhs_ctx* c, int32_t level, int32_t nsweeps) {
-    if (c == nullptr || level < 0 || level >= int(c->lv.size()) || nsweeps < 0)
+    if (c == nullptr || c->n_inst != 1 || level < 0 || level >= c->lay.info[0].nlev ||
+        nsweeps < 0)
         return CHHS_E_INVAL;
-    smooth_steps(c, level, nsweeps, level == 0 ? CHHS_K_PRE0 : CHHS_K_COARSE);
+    smooth_steps(c, level, nsweeps, nullptr, level == 0 ? CHHS_K_PRE0 : CHHS_K_COARSE);
+    if (c->cur[level] != 0) {
+        // the single instance's level: make the result copy 0 again
+        const LevelDesc<double>& d = c->lay.desc[level];
+        const size_t nb = size_t(d.n) * sizeof(double);
+        for (int k = 0; k < 3; ++k)
+            HIP_TRY(hipMemcpyAsync(d.u[0][k], d.u[1][k], nb, hipMemcpyDeviceToDevice, c->stream));
+        c->cur[level] = 0;
+    }
     int rc = check_launch();
     if (rc) return rc;
     HIP_TRY(hipStreamSynchronize(c->stream));
@@ -611,9 +1042,12 @@ int chhs_smooth(chhs_ctx* c, int32_t level, int32_t nsweeps) {
 }
 
 int chhs_restrict(chhs_ctx* c, int32_t level) {
-    if (c == nullptr || level < 0 || level + 1 >= int(c->lv.size())) return CHHS_E_INVAL;
-    chhs::launch_restrict_residual(c->prob.dim, c->lv[level], c->lv[level + 1], c->stream);
-    chhs::launch_coarse_rhs(c->prob.dim, c->lv[level + 1], c->stream);
+    if (c == nullptr || c->n_inst != 1 || level < 0 || level + 1 >= c->lay.info[0].nlev)
+        return CHHS_E_INVAL;
+    chhs::launch_restrict_residual(c->dim, batch(c, level, nullptr), c->A[level + 1].dev,
+                                   c->A[level + 1].n, c->stream);
+    chhs::launch_coarse_rhs(c->dim, batch(c, level, nullptr), c->A[level + 1].dev,
+                            c->A[level + 1].n, c->stream);
     int rc = check_launch();
     if (rc) return rc;
     HIP_TRY(hipStreamSynchronize(c->stream));
@@ -637,10 +1071,9 @@ int chhs_get_timing(chhs_ctx* c, chhs_timing* out, int32_t reset) {
 
 void chhs_destroy(chhs_ctx* c) {
     if (c == nullptr) return;
-    if (!c->pending.empty()) {
-        (void)hipStreamSynchronize(c->stream);
-        resolve_timing(c);
-    }
+    (void)hipStreamSynchronize(c->stream);
+    resolve_timing(c);
+    drop_graphs(c);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     if (c->hres) (void)hipHostFree(c->hres);
     delete c;

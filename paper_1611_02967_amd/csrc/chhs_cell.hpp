@@ -2,6 +2,14 @@
 // coarse tail: the residual operator N(u) of (2.5)-(2.7) and the collective
 // (phi, mu, p) update at one cell.  Level pointers may address global memory
 // or LDS.
+//
+// CORR selects the correction form used by the mixed-precision inner solve:
+// the unknown is a correction e to a base state b (held in Level::psi's
+// companion b), and chi(phi, psi) is replaced by
+//   g(e) = chi(b + e, psi) - chi(b, psi) = e (3b^2 + 2b psi + psi^2 + (3b + psi) e + e^2) / 4,
+// written in product form so that no two nearly equal cubes are subtracted,
+// with g'(e) = chi'(b + e, psi).  Every other term of N is linear in u and is
+// unchanged.
 #pragma once
 
 #include "chhs_internal.hpp"
@@ -36,12 +44,25 @@ __device__ __forceinline__ void for_each_nb(int i, int j, int k, int nx, int ny,
     }
 }
 
+// The nonlinear term of (2.6) at one cell and its derivative.
+template <typename T, bool CORR>
+__device__ __forceinline__ T nonlin(T x, T psi, T b) {
+    if (CORR)
+        return T(0.25) * x * (T(3) * b * b + T(2) * b * psi + psi * psi + (T(3) * b + psi) * x + x * x);
+    return T(0.25) * (x * x + psi * psi) * (x + psi);
+}
+template <typename T, bool CORR>
+__device__ __forceinline__ T dnonlin(T x, T psi, T b) {
+    const T y = CORR ? b + x : x;
+    return T(0.25) * (T(3) * y * y + T(2) * y * psi + psi * psi);
+}
+
 // N(u) at one cell for the three rows of (2.5)-(2.7), the pressure row times s:
 //   N_phi = phi - lam sum M_f (mu_nb - mu) - lam sum a_f (p_nb - p)
 //   N_mu  = mu - chi(phi, psi) + kap sum (phi_nb - phi)
 //   N_p   = lam sum (p_nb - p) + lam gamma sum a_f (mu_nb - mu)
 // with a_f = (phi_*,c + phi_*,nb)/2 and M_f = 1 + gamma a_f^2.
-template <int DIM, typename T>
+template <int DIM, typename T, bool CORR = false>
 __device__ __forceinline__ void cell_operator(const Level<T>& L, int idx, int i, int j, int k,
                                               T& n0, T& n1, T& n2) {
     const T phic = L.phi[idx], muc = L.mu[idx], pc = L.p[idx], psc = L.pstar[idx];
@@ -58,7 +79,7 @@ __device__ __forceinline__ void cell_operator(const Level<T>& L, int idx, int i,
         samu += a * dmu;
     });
     const T psi = L.psi[idx];
-    const T chi = T(0.25) * (phic * phic + psi * psi) * (phic + psi);
+    const T chi = nonlin<T, CORR>(phic, psi, CORR ? L.b[idx] : T(0));
     n0 = phic - L.lam * smm - L.lam * sap;
     n1 = muc - chi + L.kap * sphi;
     n2 = L.lam * sp + L.lam * L.gamma * samu;
@@ -71,7 +92,7 @@ __device__ __forceinline__ void cell_operator(const Level<T>& L, int idx, int i,
 //   -lam gamma Sa mu - lam nF p       = b3
 // are solved by eliminating p; the reduced 2x2 determinant is
 // 1 + lam (nF + gamma (Sa2 - Sa^2/nF)) (chi' + kap nF) >= 1.
-template <int DIM, typename T>
+template <int DIM, typename T, bool CORR = false>
 __device__ __forceinline__ void cell_solve(const Level<T>& L, int idx, int i, int j, int k,
                                            T& phi_o, T& mu_o, T& p_o) {
     const T psc = L.pstar[idx];
@@ -92,8 +113,9 @@ __device__ __forceinline__ void cell_solve(const Level<T>& L, int idx, int i, in
     });
     const T phit = L.phi[idx];
     const T psi = L.psi[idx];
-    const T dchi = T(0.25) * (T(3) * phit * phit + T(2) * phit * psi + psi * psi);
-    const T chi = T(0.25) * (phit * phit + psi * psi) * (phit + psi);
+    const T base = CORR ? L.b[idx] : T(0);
+    const T dchi = dnonlin<T, CORR>(phit, psi, base);
+    const T chi = nonlin<T, CORR>(phit, psi, base);
     const T b1 = L.f0[idx] + L.lam * smmu + L.lam * sap;
     const T b2 = L.f1[idx] + chi - dchi * phit - L.kap * sphi;
     const T b3 = L.f2[idx] - L.lam * sp - L.lam * L.gamma * samu;

@@ -4,6 +4,11 @@
 // nx x ny (x nz) box of one spacing h, interior cells only, x fastest.
 // Homogeneous Neumann data (eqn:nbc1-3) are applied by leaving boundary faces
 // out of every stencil sum: a missing neighbour contributes no flux.
+//
+// Every launch covers a batch of independent instances: a block finds its
+// instance and cells through a task table (one entry per block) and the level
+// through a table of descriptors in device memory.  A single grid is a batch
+// of one.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -13,15 +18,22 @@
 
 namespace chhs {
 
-// Device view of one multigrid level of one instance.
-//   u      = (phi, mu, p), the current iterate
-//   ub     = u as restricted from the finer level before the coarse solve (FAS)
-//   f      = right-hand side of the three rows of (2.5)-(2.7)
-//   pstar  = phi_* of (2.4) (cell average of the finer level's on coarse levels)
-//   psi    = phi^m, the second argument of chi
-//   phi_alt, mu_alt, p_alt = second copy of u: out-of-place kernels (the tiled
-//          2D smoother) read u and write u_alt, and the host then swaps the
-//          two, so that no block reads a halo another block already updated
+constexpr int kMaxLevels = 16;       // levels per instance
+constexpr int kBlock = 256;          // threads per block of the cell kernels
+constexpr int kMaxTailLevels = 8;    // levels handled by the single-workgroup tail
+constexpr size_t kTailLdsBudget = 150 * 1024;   // LDS bytes the tail may stage
+constexpr int kPartialStride = 16;   // doubles per block in the partial buffer
+constexpr int kResStride = 16;       // doubles per instance in the result area
+
+// Working view of one multigrid level of one instance.
+//   u = (phi, mu, p)      the current iterate; (phi_alt, mu_alt, p_alt) the other
+//                         copy, written by out-of-place kernels
+//   ub                    u as restricted from the finer level (FAS)
+//   f                     right-hand side of the three rows of (2.5)-(2.7)
+//   pstar, psi            phi_* (2.4) and phi^m (second argument of chi), cell
+//                         averages of the finer level's on coarse levels
+//   b                     base state of the correction form (mixed precision
+//                         inner solve); null in the plain form
 // lam = s/h^2, kap = 3/4 eps^2 / h^2, gamma as in (1.3).
 template <typename T>
 struct Level {
@@ -36,6 +48,7 @@ struct Level {
     T* f2;
     T* pstar;
     T* psi;
+    T* b;
     T* phi_alt;
     T* mu_alt;
     T* p_alt;
@@ -43,61 +56,163 @@ struct Level {
     T lam, kap, gamma, h;
 };
 
-constexpr int kBlock = 256;          // threads per block of the cell kernels
-constexpr int kMaxTailLevels = 8;    // levels handled by the single-workgroup tail
-constexpr size_t kTailLdsBudget = 150 * 1024;   // LDS bytes the tail may stage
-constexpr int kMaxPartials = 1024;   // blocks of the two-pass reductions
-constexpr int kPartialStride = 16;   // doubles per block in the partial buffer
+// Descriptor of one level of one instance, written once at init.  u[c] is copy
+// c of (phi, mu, p); levels without a second copy repeat the first.
+template <typename T>
+struct LevelDesc {
+    T* u[2][3];
+    T* ub[3];
+    T* f[3];
+    T* pstar;
+    T* psi;
+    T* b;
+    int nx, ny, nz, n;
+    T lam, kap, gamma, h;
+};
 
-// ---- launchers (chhs_kernels.hip); dim is 2 or 3 ------------------------------
-void launch_setup(int dim, const Level<double>& L, const double* phi_prev,
-                  const double* phi_cur, const double* mu, const double* p,
-                  double quarter_eps2_over_h2, hipStream_t st);
-void launch_restrict_frozen(int dim, const Level<double>& F, const Level<double>& C,
+template <typename T>
+__host__ __device__ inline Level<T> make_view(const LevelDesc<T>& d, int cur) {
+    Level<T> v;
+    v.phi = d.u[cur][0];
+    v.mu = d.u[cur][1];
+    v.p = d.u[cur][2];
+    v.phi_alt = d.u[cur ^ 1][0];
+    v.mu_alt = d.u[cur ^ 1][1];
+    v.p_alt = d.u[cur ^ 1][2];
+    v.ub0 = d.ub[0];
+    v.ub1 = d.ub[1];
+    v.ub2 = d.ub[2];
+    v.f0 = d.f[0];
+    v.f1 = d.f[1];
+    v.f2 = d.f[2];
+    v.pstar = d.pstar;
+    v.psi = d.psi;
+    v.b = d.b;
+    v.nx = d.nx;
+    v.ny = d.ny;
+    v.nz = d.nz;
+    v.n = d.n;
+    v.lam = d.lam;
+    v.kap = d.kap;
+    v.gamma = d.gamma;
+    v.h = d.h;
+    return v;
+}
+
+// Per-instance constants in device memory.
+struct InstInfo {
+    int dim, nlev, tail;   // levels; first level of the one-workgroup tail
+    int off;               // offset of the instance in packed caller arrays
+    int n0;                // cells of the finest level
+    int fused;             // the finest-level post launch yields the norm partials
+    double h, eps, gamma, dt;
+};
+
+struct CellTask { int inst; int cell0; };      // kBlock consecutive cells of one level
+struct TileTask { int inst; int bx; int by; }; // one tile of a 2D level
+struct Range { int begin; int end; };          // an instance's blocks in a partial buffer
+
+// Arguments common to every batched launch.
+template <typename T>
+struct Batch {
+    const LevelDesc<T>* desc;   // [inst * kMaxLevels + level]
+    const int* active;          // instance takes part in this cycle (nullptr: all)
+    int level;                  // level of the launch (the finer one for transfers)
+    int cur;                    // current copy of u on `level`
+    int cur_c;                  // current copy of u on level + 1
+};
+
+// ---- per-cell kernels (chhs_kernels.hip); dim is 2 or 3 ----------------------------
+void launch_setup(int dim, const Batch<double>& b, const CellTask* t, int nt, const InstInfo* info,
+                  const double* phi_prev, const double* phi_cur, const double* mu,
+                  const double* p, hipStream_t st);
+// FP64 overloads act on the plain form, FP32 overloads on the correction form
+// of the mixed-precision inner solve (restriction then also averages b).
+void launch_restrict_frozen(int dim, const Batch<double>& b, const CellTask* t, int nt,
                             hipStream_t st);
-void launch_smooth(int dim, const Level<double>& L, int color, hipStream_t st);
-void launch_restrict_residual(int dim, const Level<double>& F, const Level<double>& C,
+void launch_restrict_frozen(int dim, const Batch<float>& b, const CellTask* t, int nt,
+                            hipStream_t st);
+void launch_smooth(int dim, const Batch<double>& b, const CellTask* t, int nt, int color,
+                   hipStream_t st);
+void launch_smooth(int dim, const Batch<float>& b, const CellTask* t, int nt, int color,
+                   hipStream_t st);
+void launch_restrict_residual(int dim, const Batch<double>& b, const CellTask* t, int nt,
                               hipStream_t st);
-void launch_coarse_rhs(int dim, const Level<double>& C, hipStream_t st);
-void launch_prolong(int dim, const Level<double>& F, const Level<double>& C, hipStream_t st);
+void launch_restrict_residual(int dim, const Batch<float>& b, const CellTask* t, int nt,
+                              hipStream_t st);
+void launch_coarse_rhs(int dim, const Batch<double>& b, const CellTask* t, int nt, hipStream_t st);
+void launch_coarse_rhs(int dim, const Batch<float>& b, const CellTask* t, int nt, hipStream_t st);
+void launch_prolong(int dim, const Batch<double>& b, const CellTask* t, int nt, hipStream_t st);
+void launch_prolong(int dim, const Batch<float>& b, const CellTask* t, int nt, hipStream_t st);
+// Mixed precision (finest level): FP32 copies of phi_*, phi^m; a zero FP32
+// correction; the FP64 outer step u' = u (+ e), R = f - N(u') written as u'
+// (other FP64 copy), R and b = phi' in FP32, and norm partials (as
+// launch_residual_partials).
+void launch_mixed_frozen(const Batch<double>& b64, const Batch<float>& b32, const CellTask* t,
+                         int nt, hipStream_t st);
+void launch_zero_correction(const Batch<float>& b32, const CellTask* t, int nt, hipStream_t st);
+void launch_mixed_residual(int dim, const Batch<double>& b64, const Batch<float>& b32,
+                           const CellTask* t, int nt, int add, double* partial, hipStream_t st);
+// partial[block][0..3] = sum R_phi^2, R_mu^2, R_p^2, p over the block's cells
+void launch_residual_partials(int dim, const Batch<double>& b, const CellTask* t, int nt,
+                              double* partial, hipStream_t st);
+// Per instance i (one block each), if active[i] (or active == nullptr): sums
+// its partials in a fixed order -- partial_t[ranges_t[i]] when use_fused and
+// info[i].fused, else partial[ranges[i]]; res[i*kResStride + 0..3] = ||R_phi||,
+// ||R_mu||, ||R_p||, combined norm; 4 = mean(p); 5 = 1 if the norm is not
+// finite; count != 0: cycles[i] += 1; act_next[i] = norm > tol, finite and
+// cycles[i] < max_cycles.  Inactive instances keep their results.
+void launch_inst_reduce(const double* partial, const Range* ranges, const double* partial_t,
+                        const Range* ranges_t, int use_fused, const InstInfo* info,
+                        const int* active, int* act_next, int* cycles, double* res, int n_inst,
+                        double tol, int max_cycles, int count, hipStream_t st);
+// p -= mean(p) (res slot 4) on the finest level of active instances.
+void launch_shift_p(const Batch<double>& b, const CellTask* t, int nt, const double* res,
+                    hipStream_t st);
+// Energy partials over the finest level: ws != 0 takes phi = u, q = phi^m and
+// the flow terms from mu, p, phi_* of the workspace; else the packed caller
+// arrays phi and q and no flow terms.  partial[block][0..8]: sum phi, phi^2,
+// phi^4, |D phi|^2 h^2, (phi-q)^2, |D(phi-q)|^2 h^2, |D mu|^2 h^2, |u|^2 h^2,
+// max |phi| (interior faces only).
+void launch_energy_partials(int dim, const Batch<double>& b, const CellTask* t, int nt,
+                            const InstInfo* info, int ws, const double* phi, const double* q,
+                            double* partial, hipStream_t st);
+// Per instance: out[i*kResStride + 0..5] = mass, E_h, F_h, s||grad mu||^2,
+// (s/gamma)||u||^2, max |phi|.
+void launch_energy_reduce(const double* partial, const Range* ranges, const InstInfo* info,
+                          double* out, int n_inst, hipStream_t st);
+// State rotation into packed caller arrays: phi_prev <- phi_cur, phi_cur <- phi,
+// mu <- mu, p <- p (finest level, current copy).
+void launch_copy_out(const Batch<double>& b, const CellTask* t, int nt, const InstInfo* info,
+                     double* phi_prev, double* phi_cur, double* mu, double* p, hipStream_t st);
+// Finest-level iterate into packed caller arrays (any may be null).
+void launch_get_solution(const Batch<double>& b, const CellTask* t, int nt, const InstInfo* info,
+                         double* phi, double* mu, double* p, hipStream_t st);
+void launch_fill_int(int* dst, int n, int value, hipStream_t st);
+void launch_copy_int(int* dst, const int* src, int n, hipStream_t st);
 
-// Residual reduction: partial[b][0..3] = sum R_phi^2, R_mu^2, R_p^2, p over the
-// cells of block b; returns the number of blocks used.
-int launch_residual_partials(int dim, const Level<double>& L, double* partial, hipStream_t st);
-// out[c] = sum over blocks of partial[b][c] for c < ncomp (fixed order).
-void launch_reduce_final(const double* partial, int nblocks, int ncomp, double* out,
-                         hipStream_t st);
-// p -= sum_p / n with sum_p read from device memory.
-void launch_shift_p(const Level<double>& L, const double* sum_p, hipStream_t st);
-
-// Energy reduction over (phi, q[, mu, p, pstar]): partial[b][0..8] =
-//   sum phi, phi^2, phi^4, |D phi|^2 h^2, (phi-q)^2, |D(phi-q)|^2 h^2,
-//   |D mu|^2 h^2, |u|^2 h^2, and max |phi| in slot 8.
-// Face sums run over interior faces; mu == nullptr skips the two flow terms.
-int launch_energy_partials(int dim, int nx, int ny, int nz, const double* phi,
-                           const double* q, const double* mu, const double* p,
-                           const double* pstar, double gamma, double* partial,
-                           hipStream_t st);
-void launch_reduce_energy(const double* partial, int nblocks, double* out, hipStream_t st);
-
-// ---- tiled 2D smoothing (chhs_tile2d.hip) ----------------------------------------
-// Blocks of one tiled launch on an nx x ny level.
-int tile2d_blocks(int nx, int ny);
-// ns fused smoothing steps on L; epi 0 none, 1 residual + restriction into C,
-// 2 residual-norm partials (4 per block); pro: prolongation of C's correction
-// first; level0: f_phi = phi^m and f_p = 0 implied.  Returns blocks launched.
+// ---- tiled 2D smoothing (chhs_tile2d.hip) ------------------------------------------
+constexpr int kTileX = 64;
+constexpr int kTileY = 16;
+// ns fused smoothing steps on level b.level of every tasked instance, read from
+// copy b.cur and written to the other copy; epi 0 none, 1 residual + restriction
+// into level + 1 (copy b.cur_c), 2 residual-norm partials (4 per block, in task
+// order); pro: prolongation of level + 1's correction first; level0: f_phi =
+// phi^m and f_p = 0 implied.
 template <typename T>
-int launch_tile2d(const Level<T>& L, const Level<T>& C, bool level0, int ns, int epi, bool pro,
-                  double* partial, hipStream_t st);
+void launch_tile2d(const Batch<T>& b, const TileTask* t, int nt, bool level0, int ns, int epi,
+                   bool pro, double* partial, hipStream_t st);
 
-// ---- single-workgroup coarse tail (chhs_tail.hip) ---------------------------------
-size_t tail_lds_bytes(const int* cells, int nlev, size_t elem);
-template <typename T>
+// ---- single-workgroup coarse tail (chhs_tail.hip) ----------------------------------
+size_t tail_lds_bytes(const int* cells, int nlev, size_t elem, int nfields);
+template <typename T, bool CORR>
 int prepare_tail(int dim, size_t lds_bytes);
-// V(nu1, nu2) cycle over levels[0..nlev-1] (levels[0] = the tail's top level,
-// whose iterate is updated in global memory).
-template <typename T>
-void launch_tail(int dim, const Level<T>* levels, int nlev, int nu1, int nu2, int coarse_sweeps,
-                 size_t lds_bytes, hipStream_t st);
+// One workgroup per listed instance: V(nu1, nu2) cycle over levels info.tail ..
+// info.nlev - 1 of that instance; bit l of cur_mask = current copy of u on
+// level l.
+template <typename T, bool CORR>
+void launch_tail(int dim, const LevelDesc<T>* desc, const InstInfo* info, const int* insts,
+                 int ninst, const int* active, unsigned cur_mask, int nu1, int nu2,
+                 int coarse_sweeps, size_t lds_bytes, hipStream_t st);
 
 }  // namespace chhs

@@ -1,25 +1,45 @@
-// Cell kernels of the FAS solve for one step of the CHHS scheme (2.4)-(2.7).
+// Per-cell kernels of the FAS solve for one step of the CHHS scheme (2.4)-(2.7),
+// batched over independent instances.
 //
-// One thread per cell; neighbours are read straight from global memory.  The
+// A block covers kBlock consecutive cells of one level of one instance, named
+// by its CellTask; neighbours are read straight from global memory.  The
 // stencils are the App. A.2 operators with boundary faces left out (zero flux,
-// App. A.1).  The arithmetic is FP64 throughout.
+// App. A.1).  FP64 throughout.
 #include "chhs_cell.hpp"
 
 namespace chhs {
 namespace {
 
+__device__ __forceinline__ bool inactive(const int* active, int inst) {
+    return active != nullptr && active[inst] == 0;
+}
+
+template <typename T>
+__device__ __forceinline__ Level<T> view_at(const Batch<T>& b, int inst, int level, int cur) {
+    return make_view(b.desc[inst * kMaxLevels + level], cur);
+}
+
 template <int DIM>
-__global__ __launch_bounds__(kBlock) void k_setup(Level<double> L, const double* __restrict__ phi_prev,
-                        const double* __restrict__ phi_cur, const double* __restrict__ mu,
-                        const double* __restrict__ p, double q) {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kBlock) void k_setup(Batch<double> b, const CellTask* __restrict__ t,
+                                                  const InstInfo* __restrict__ info,
+                                                  const double* __restrict__ phi_prev,
+                                                  const double* __restrict__ phi_cur,
+                                                  const double* __restrict__ mu,
+                                                  const double* __restrict__ p) {
+    const CellTask tk = t[blockIdx.x];
+    const Level<double> L = view_at(b, tk.inst, 0, b.cur);
+    const int idx = tk.cell0 + threadIdx.x;
     if (idx >= L.n) return;
+    const InstInfo in = info[tk.inst];
+    const int g = in.off + idx;
     int i, j, k;
     decode<DIM>(idx, L.nx, L.ny, i, j, k);
-    const double pm = phi_prev[idx];
-    const double pc = phi_cur[idx];
+    const double pm = phi_prev[g];
+    const double pc = phi_cur[g];
     double lap = 0.0;
-    for_each_nb<DIM>(i, j, k, L.nx, L.ny, L.nz, idx, [&](int nb) { lap += phi_prev[nb] - pm; });
+    for_each_nb<DIM>(i, j, k, L.nx, L.ny, L.nz, idx,
+                     [&](int nb) { lap += phi_prev[in.off + nb] - pm; });
+    const double q = 0.25 * in.eps * in.eps / (in.h * in.h);
     const double ps = 1.5 * pc - 0.5 * pm;           // phi_*, (2.4)
     L.pstar[idx] = ps;
     L.psi[idx] = pc;
@@ -27,17 +47,22 @@ __global__ __launch_bounds__(kBlock) void k_setup(Level<double> L, const double*
     L.f1[idx] = -ps - q * lap;                        // (2.6): -phi_* - eps^2/4 Lap phi^{m-1}
     L.f2[idx] = 0.0;                                  // (2.7)
     L.phi[idx] = pc;                                  // initial guess phi^m
-    L.mu[idx] = mu[idx];
-    L.p[idx] = p[idx];
+    L.mu[idx] = mu[g];
+    L.p[idx] = p[g];
 }
 
-template <int DIM>
-__global__ __launch_bounds__(kBlock) void k_restrict_frozen(Level<double> F, Level<double> C) {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+// tasks over coarse cells (level b.level + 1)
+template <int DIM, typename T>
+__global__ __launch_bounds__(kBlock) void k_restrict_frozen(Batch<T> b,
+                                                            const CellTask* __restrict__ t) {
+    const CellTask tk = t[blockIdx.x];
+    const Level<T> F = view_at(b, tk.inst, b.level, 0);
+    const Level<T> C = view_at(b, tk.inst, b.level + 1, 0);
+    const int idx = tk.cell0 + threadIdx.x;
     if (idx >= C.n) return;
     int ci, cj, ck;
     decode<DIM>(idx, C.nx, C.ny, ci, cj, ck);
-    double sps = 0.0, sph = 0.0;
+    T sps = 0, sph = 0;
     for (int dz = 0; dz < (DIM == 3 ? 2 : 1); ++dz)
         for (int dy = 0; dy < 2; ++dy)
             for (int dx = 0; dx < 2; ++dx) {
@@ -45,20 +70,24 @@ __global__ __launch_bounds__(kBlock) void k_restrict_frozen(Level<double> F, Lev
                 sps += F.pstar[f];
                 sph += F.psi[f];
             }
-    const double w = DIM == 3 ? 0.125 : 0.25;
+    const T w = DIM == 3 ? T(0.125) : T(0.25);
     C.pstar[idx] = sps * w;
     C.psi[idx] = sph * w;
 }
 
-template <int DIM>
-__global__ __launch_bounds__(kBlock) void k_smooth(Level<double> L, int color) {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+template <int DIM, typename T, bool CORR>
+__global__ __launch_bounds__(kBlock) void k_smooth(Batch<T> b, const CellTask* __restrict__ t,
+                                                   int color) {
+    const CellTask tk = t[blockIdx.x];
+    if (inactive(b.active, tk.inst)) return;
+    const Level<T> L = view_at(b, tk.inst, b.level, b.cur);
+    const int idx = tk.cell0 + threadIdx.x;
     if (idx >= L.n) return;
     int i, j, k;
     decode<DIM>(idx, L.nx, L.ny, i, j, k);
     if (((i + j + k) & 1) != color) return;
-    double phi, mu, p;
-    cell_solve<DIM>(L, idx, i, j, k, phi, mu, p);
+    T phi, mu, p;
+    cell_solve<DIM, T, CORR>(L, idx, i, j, k, phi, mu, p);
     L.phi[idx] = phi;
     L.mu[idx] = mu;
     L.p[idx] = p;
@@ -66,29 +95,36 @@ __global__ __launch_bounds__(kBlock) void k_smooth(Level<double> L, int color) {
 
 // Per coarse cell: u_c = R u, ub_c = u_c, f_c = R(f - N(u)) (the N_c(u_c) part
 // is added by k_coarse_rhs once all of u_c is written).
-template <int DIM>
-__global__ __launch_bounds__(kBlock) void k_restrict_residual(Level<double> F, Level<double> C) {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+template <int DIM, typename T, bool CORR>
+__global__ __launch_bounds__(kBlock) void k_restrict_residual(Batch<T> b,
+                                                              const CellTask* __restrict__ t) {
+    const CellTask tk = t[blockIdx.x];
+    if (inactive(b.active, tk.inst)) return;
+    const Level<T> F = view_at(b, tk.inst, b.level, b.cur);
+    const Level<T> C = view_at(b, tk.inst, b.level + 1, b.cur_c);
+    const int idx = tk.cell0 + threadIdx.x;
     if (idx >= C.n) return;
     int ci, cj, ck;
     decode<DIM>(idx, C.nx, C.ny, ci, cj, ck);
-    double su0 = 0, su1 = 0, su2 = 0, sr0 = 0, sr1 = 0, sr2 = 0;
+    T su0 = 0, su1 = 0, su2 = 0, sr0 = 0, sr1 = 0, sr2 = 0, sb = 0;
 #pragma unroll 1
     for (int dz = 0; dz < (DIM == 3 ? 2 : 1); ++dz)
         for (int dy = 0; dy < 2; ++dy)
             for (int dx = 0; dx < 2; ++dx) {
                 const int fi = 2 * ci + dx, fj = 2 * cj + dy, fk = 2 * ck + dz;
                 const int f = (fk * F.ny + fj) * F.nx + fi;
-                double n0, n1, n2;
-                cell_operator<DIM>(F, f, fi, fj, fk, n0, n1, n2);
+                T n0, n1, n2;
+                cell_operator<DIM, T, CORR>(F, f, fi, fj, fk, n0, n1, n2);
                 sr0 += F.f0[f] - n0;
                 sr1 += F.f1[f] - n1;
                 sr2 += F.f2[f] - n2;
                 su0 += F.phi[f];
                 su1 += F.mu[f];
                 su2 += F.p[f];
+                if (CORR) sb += F.b[f];
             }
-    const double w = DIM == 3 ? 0.125 : 0.25;
+    const T w = DIM == 3 ? T(0.125) : T(0.25);
+    if (CORR) C.b[idx] = sb * w;
     C.phi[idx] = C.ub0[idx] = su0 * w;
     C.mu[idx] = C.ub1[idx] = su1 * w;
     C.p[idx] = C.ub2[idx] = su2 * w;
@@ -97,22 +133,32 @@ __global__ __launch_bounds__(kBlock) void k_restrict_residual(Level<double> F, L
     C.f2[idx] = sr2 * w;
 }
 
-template <int DIM>
-__global__ __launch_bounds__(kBlock) void k_coarse_rhs(Level<double> C) {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+// tasks over coarse cells: f_c += N_c(u_c)
+template <int DIM, typename T, bool CORR>
+__global__ __launch_bounds__(kBlock) void k_coarse_rhs(Batch<T> b,
+                                                       const CellTask* __restrict__ t) {
+    const CellTask tk = t[blockIdx.x];
+    if (inactive(b.active, tk.inst)) return;
+    const Level<T> C = view_at(b, tk.inst, b.level + 1, b.cur_c);
+    const int idx = tk.cell0 + threadIdx.x;
     if (idx >= C.n) return;
     int i, j, k;
     decode<DIM>(idx, C.nx, C.ny, i, j, k);
-    double n0, n1, n2;
-    cell_operator<DIM>(C, idx, i, j, k, n0, n1, n2);
+    T n0, n1, n2;
+    cell_operator<DIM, T, CORR>(C, idx, i, j, k, n0, n1, n2);
     C.f0[idx] += n0;
     C.f1[idx] += n1;
     C.f2[idx] += n2;
 }
 
-template <int DIM>
-__global__ __launch_bounds__(kBlock) void k_prolong(Level<double> F, Level<double> C) {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+// tasks over fine cells: u += P(u_c - ub_c)
+template <int DIM, typename T>
+__global__ __launch_bounds__(kBlock) void k_prolong(Batch<T> b, const CellTask* __restrict__ t) {
+    const CellTask tk = t[blockIdx.x];
+    if (inactive(b.active, tk.inst)) return;
+    const Level<T> F = view_at(b, tk.inst, b.level, b.cur);
+    const Level<T> C = view_at(b, tk.inst, b.level + 1, b.cur_c);
+    const int idx = tk.cell0 + threadIdx.x;
     if (idx >= F.n) return;
     int i, j, k;
     decode<DIM>(idx, F.nx, F.ny, i, j, k);
@@ -122,10 +168,109 @@ __global__ __launch_bounds__(kBlock) void k_prolong(Level<double> F, Level<doubl
     F.p[idx] += C.p[c] - C.ub2[c];
 }
 
-// ---- deterministic reductions --------------------------------------------------
+template <int NC>
+__device__ __forceinline__ void block_sum(double (&v)[NC], double* out);
+
+// ---- mixed precision: FP64 outer work around the FP32 correction solve ---------------
+
+// FP32 copies of the finest level's frozen data (phi_*, phi^m).
+__global__ __launch_bounds__(kBlock) void k_mixed_frozen(Batch<double> b64, Batch<float> b32,
+                                                         const CellTask* __restrict__ t) {
+    const CellTask tk = t[blockIdx.x];
+    const Level<double> L = view_at(b64, tk.inst, 0, 0);
+    const Level<float> E = view_at(b32, tk.inst, 0, 0);
+    const int idx = tk.cell0 + threadIdx.x;
+    if (idx >= L.n) return;
+    E.pstar[idx] = float(L.pstar[idx]);
+    E.psi[idx] = float(L.psi[idx]);
+}
+
+// Zero correction on the FP32 finest level (current copy).
+__global__ __launch_bounds__(kBlock) void k_zero_correction(Batch<float> b32,
+                                                            const CellTask* __restrict__ t) {
+    const CellTask tk = t[blockIdx.x];
+    if (inactive(b32.active, tk.inst)) return;
+    const Level<float> E = view_at(b32, tk.inst, 0, b32.cur);
+    const int idx = tk.cell0 + threadIdx.x;
+    if (idx >= E.n) return;
+    E.phi[idx] = 0.0f;
+    E.mu[idx] = 0.0f;
+    E.p[idx] = 0.0f;
+}
+
+// Outer step of the iterative refinement on the finest level, in FP64:
+//   u' = u + e (add != 0; e the FP32 correction of the last inner cycle),
+//   R  = f - N(u') with the plain (2.5)-(2.7) operator,
+// written as u' into the other FP64 copy, R and b = u'_phi rounded to FP32
+// into the FP32 finest level's right-hand side and base state, and the block
+// partial sums of R^2 and p'.
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_mixed_residual(Batch<double> b64, Batch<float> b32,
+                                                           const CellTask* __restrict__ t,
+                                                           int add, double* partial) {
+    const CellTask tk = t[blockIdx.x];
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    if (!inactive(b64.active, tk.inst)) {
+        const Level<double> L = view_at(b64, tk.inst, 0, b64.cur);
+        const Level<float> E = view_at(b32, tk.inst, 0, b32.cur);
+        const int idx = tk.cell0 + threadIdx.x;
+        if (idx < L.n) {
+            int i, j, k;
+            decode<DIM>(idx, L.nx, L.ny, i, j, k);
+            auto u_at = [&](int q, double& ph, double& m, double& pp) {
+                ph = L.phi[q];
+                m = L.mu[q];
+                pp = L.p[q];
+                if (add) {
+                    ph += double(E.phi[q]);
+                    m += double(E.mu[q]);
+                    pp += double(E.p[q]);
+                }
+            };
+            double phic, muc, pc;
+            u_at(idx, phic, muc, pc);
+            const double psc = L.pstar[idx];
+            double smm = 0, sap = 0, sphi = 0, sp = 0, samu = 0;
+            for_each_nb<DIM>(i, j, k, L.nx, L.ny, L.nz, idx, [&](int nb) {
+                double phn, mun, pn;
+                u_at(nb, phn, mun, pn);
+                const double a = 0.5 * (psc + L.pstar[nb]);
+                const double m = 1.0 + L.gamma * a * a;
+                const double dmu = mun - muc;
+                const double dp = pn - pc;
+                smm += m * dmu;
+                sap += a * dp;
+                sphi += phn - phic;
+                sp += dp;
+                samu += a * dmu;
+            });
+            const double psi = L.psi[idx];
+            const double r0 = psi - (phic - L.lam * smm - L.lam * sap);
+            const double r1 = L.f1[idx] - (muc - nonlin<double, false>(phic, psi, 0.0) + L.kap * sphi);
+            const double r2 = -(L.lam * sp + L.lam * L.gamma * samu);
+            L.phi_alt[idx] = phic;
+            L.mu_alt[idx] = muc;
+            L.p_alt[idx] = pc;
+            E.f0[idx] = float(r0);
+            E.f1[idx] = float(r1);
+            E.f2[idx] = float(r2);
+            E.b[idx] = float(phic);
+            v[0] = r0 * r0;
+            v[1] = r1 * r1;
+            v[2] = r2 * r2;
+            v[3] = pc;
+        }
+    }
+    double out[4];
+    block_sum<4>(v, out);
+    if (threadIdx.x == 0)
+        for (int c = 0; c < 4; ++c) partial[blockIdx.x * kPartialStride + c] = out[c];
+}
+
+// ---- deterministic reductions --------------------------------------------------------
 
 template <int NC>
-__device__ __forceinline__ void block_sum_store(double (&v)[NC], double* out) {
+__device__ __forceinline__ void block_sum(double (&v)[NC], double* out) {
     for (int off = 32; off > 0; off >>= 1)
         for (int c = 0; c < NC; ++c) v[c] += __shfl_xor(v[c], off, 64);
     __shared__ double sh[NC][kBlock / 64];
@@ -139,183 +284,357 @@ __device__ __forceinline__ void block_sum_store(double (&v)[NC], double* out) {
             for (int w = 0; w < kBlock / 64; ++w) s += sh[c][w];
             out[c] = s;
         }
+    __syncthreads();
+}
+
+__device__ __forceinline__ double block_max(double v) {
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    __shared__ double shm[kBlock / 64];
+    if ((threadIdx.x & 63) == 0) shm[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double m = 0.0;
+    for (int w = 0; w < kBlock / 64; ++w) m = fmax(m, shm[w]);
+    __syncthreads();
+    return m;
 }
 
 template <int DIM>
-__global__ __launch_bounds__(kBlock) void k_residual_partials(Level<double> L, double* partial) {
+__global__ __launch_bounds__(kBlock) void k_residual_partials(Batch<double> b,
+                                                              const CellTask* __restrict__ t,
+                                                              double* partial) {
+    const CellTask tk = t[blockIdx.x];
     double v[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < L.n;
-         idx += gridDim.x * blockDim.x) {
-        int i, j, k;
-        decode<DIM>(idx, L.nx, L.ny, i, j, k);
-        double n0, n1, n2;
-        cell_operator<DIM>(L, idx, i, j, k, n0, n1, n2);
-        const double r0 = L.f0[idx] - n0, r1 = L.f1[idx] - n1, r2 = L.f2[idx] - n2;
-        v[0] += r0 * r0;
-        v[1] += r1 * r1;
-        v[2] += r2 * r2;
-        v[3] += L.p[idx];
+    if (!inactive(b.active, tk.inst)) {
+        const Level<double> L = view_at(b, tk.inst, 0, b.cur);
+        const int idx = tk.cell0 + threadIdx.x;
+        if (idx < L.n) {
+            int i, j, k;
+            decode<DIM>(idx, L.nx, L.ny, i, j, k);
+            double n0, n1, n2;
+            cell_operator<DIM>(L, idx, i, j, k, n0, n1, n2);
+            const double r0 = L.f0[idx] - n0, r1 = L.f1[idx] - n1, r2 = L.f2[idx] - n2;
+            v[0] = r0 * r0;
+            v[1] = r1 * r1;
+            v[2] = r2 * r2;
+            v[3] = L.p[idx];
+        }
     }
-    block_sum_store<4>(v, partial + blockIdx.x * kPartialStride);
-}
-
-__global__ __launch_bounds__(kBlock) void k_reduce_final(const double* partial, int nblocks, int ncomp, double* out) {
-    double v[8];
-    for (int c = 0; c < 8; ++c) v[c] = 0.0;
-    for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
-        for (int c = 0; c < 8; ++c)
-            if (c < ncomp) v[c] += partial[b * kPartialStride + c];
-    double res[8];
-    block_sum_store<8>(v, res);
+    double out[4];
+    block_sum<4>(v, out);
     if (threadIdx.x == 0)
-        for (int c = 0; c < ncomp; ++c) out[c] = res[c];
+        for (int c = 0; c < 4; ++c) partial[blockIdx.x * kPartialStride + c] = out[c];
 }
 
-__global__ __launch_bounds__(kBlock) void k_shift_p(double* p, int n, const double* sum_p) {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= n) return;
-    p[idx] -= sum_p[0] / double(n);
+__global__ __launch_bounds__(kBlock) void k_inst_reduce(const double* __restrict__ partial,
+                                                        const Range* __restrict__ ranges,
+                                                        const double* __restrict__ partial_t,
+                                                        const Range* __restrict__ ranges_t,
+                                                        int use_fused,
+                                                        const InstInfo* __restrict__ info,
+                                                        const int* active, int* act_next,
+                                                        int* cycles, double* res, double tol,
+                                                        int max_cycles, int count) {
+    const int i = blockIdx.x;
+    if (inactive(active, i)) return;
+    const InstInfo in = info[i];
+    const bool fused = use_fused && in.fused;
+    const Range rg = fused ? ranges_t[i] : ranges[i];
+    const double* src = fused ? partial_t : partial;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int q = rg.begin + threadIdx.x; q < rg.end; q += kBlock)
+        for (int c = 0; c < 4; ++c) v[c] += src[q * kPartialStride + c];
+    double s[4];
+    block_sum<4>(v, s);
+    if (threadIdx.x != 0) return;
+    double hd = in.h * in.h;
+    if (in.dim == 3) hd *= in.h;
+    const double a = s[0] * hd, bb = s[1] * hd, c = s[2] * hd;
+    const double tot = sqrt(a + bb + c);
+    double* r = res + i * kResStride;
+    r[0] = sqrt(a);
+    r[1] = sqrt(bb);
+    r[2] = sqrt(c);
+    r[3] = tot;
+    r[4] = s[3] / double(in.n0);
+    const bool finite = tot == tot && tot < 1e300;
+    r[5] = finite ? 0.0 : 1.0;
+    int cyc = cycles[i];
+    if (count) cycles[i] = ++cyc;
+    act_next[i] = (finite && tot > tol && cyc < max_cycles) ? 1 : 0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_shift_p(Batch<double> b, const CellTask* __restrict__ t,
+                                                    const double* __restrict__ res) {
+    const CellTask tk = t[blockIdx.x];
+    if (inactive(b.active, tk.inst)) return;
+    const Level<double> L = view_at(b, tk.inst, 0, b.cur);
+    const int idx = tk.cell0 + threadIdx.x;
+    if (idx >= L.n) return;
+    L.p[idx] -= res[tk.inst * kResStride + 4];
 }
 
 template <int DIM>
-__global__ __launch_bounds__(kBlock) void k_energy_partials(int nx, int ny, int nz, const double* __restrict__ phi,
-                                  const double* __restrict__ q, const double* __restrict__ mu,
-                                  const double* __restrict__ p, const double* __restrict__ ps,
-                                  double gamma, double* partial) {
+__global__ __launch_bounds__(kBlock) void k_energy_partials(Batch<double> b,
+                                                            const CellTask* __restrict__ t,
+                                                            const InstInfo* __restrict__ info,
+                                                            int ws, const double* __restrict__ phi_c,
+                                                            const double* __restrict__ q_c,
+                                                            double* partial) {
+    const CellTask tk = t[blockIdx.x];
+    const Level<double> L = view_at(b, tk.inst, 0, b.cur);
+    const int off = info[tk.inst].off;
+    const double gamma = L.gamma;
+    const double* phi = ws ? L.phi : phi_c + off;
+    const double* q = ws ? L.psi : q_c + off;
     double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     double vmax = 0.0;
-    const int n = nx * ny * nz;
-    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n;
-         idx += gridDim.x * blockDim.x) {
+    const int idx = tk.cell0 + threadIdx.x;
+    if (idx < L.n) {
         int i, j, k;
-        decode<DIM>(idx, nx, ny, i, j, k);
+        decode<DIM>(idx, L.nx, L.ny, i, j, k);
         const double f = phi[idx];
         const double d = f - q[idx];
-        v[0] += f;
-        v[1] += f * f;
-        v[2] += f * f * f * f;
-        v[4] += d * d;
-        vmax = fmax(vmax, fabs(f));
+        v[0] = f;
+        v[1] = f * f;
+        v[2] = f * f * f * f;
+        v[4] = d * d;
+        vmax = fabs(f);
         // forward faces only: every interior face counted once
         auto face = [&](int nb) {
             const double df = phi[nb] - f;
             const double dd = (phi[nb] - q[nb]) - d;
             v[3] += df * df;
             v[5] += dd * dd;
-            if (mu != nullptr) {
-                const double dm = mu[nb] - mu[idx];
-                const double a = 0.5 * (ps[idx] + ps[nb]);
-                const double u = -(p[nb] - p[idx]) - gamma * a * dm;
+            if (ws) {
+                const double dm = L.mu[nb] - L.mu[idx];
+                const double a = 0.5 * (L.pstar[idx] + L.pstar[nb]);
+                const double u = -(L.p[nb] - L.p[idx]) - gamma * a * dm;
                 v[6] += dm * dm;
                 v[7] += u * u;
             }
         };
-        if (i < nx - 1) face(idx + 1);
-        if (j < ny - 1) face(idx + nx);
-        if (DIM == 3 && k < nz - 1) face(idx + nx * ny);
+        if (i < L.nx - 1) face(idx + 1);
+        if (j < L.ny - 1) face(idx + L.nx);
+        if (DIM == 3 && k < L.nz - 1) face(idx + L.nx * L.ny);
     }
-    double* out = partial + blockIdx.x * kPartialStride;
-    block_sum_store<8>(v, out);
-    for (int off = 32; off > 0; off >>= 1) vmax = fmax(vmax, __shfl_xor(vmax, off, 64));
-    __shared__ double shm[kBlock / 64];
-    if ((threadIdx.x & 63) == 0) shm[threadIdx.x >> 6] = vmax;
-    __syncthreads();
+    double out[8];
+    block_sum<8>(v, out);
+    const double m = block_max(vmax);
     if (threadIdx.x == 0) {
-        double m = 0.0;
-        for (int w = 0; w < kBlock / 64; ++w) m = fmax(m, shm[w]);
-        out[8] = m;
+        double* pp = partial + blockIdx.x * kPartialStride;
+        for (int c = 0; c < 8; ++c) pp[c] = out[c];
+        pp[8] = m;
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_reduce_energy(const double* partial, int nblocks, double* out) {
+__global__ __launch_bounds__(kBlock) void k_energy_reduce(const double* __restrict__ partial,
+                                                          const Range* __restrict__ ranges,
+                                                          const InstInfo* __restrict__ info,
+                                                          double* out) {
+    const int i = blockIdx.x;
+    const Range rg = ranges[i];
     double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     double vmax = 0.0;
-    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
-        for (int c = 0; c < 8; ++c) v[c] += partial[b * kPartialStride + c];
-        vmax = fmax(vmax, partial[b * kPartialStride + 8]);
+    for (int q = rg.begin + threadIdx.x; q < rg.end; q += kBlock) {
+        for (int c = 0; c < 8; ++c) v[c] += partial[q * kPartialStride + c];
+        vmax = fmax(vmax, partial[q * kPartialStride + 8]);
     }
-    double res[8];
-    block_sum_store<8>(v, res);
-    for (int off = 32; off > 0; off >>= 1) vmax = fmax(vmax, __shfl_xor(vmax, off, 64));
-    __shared__ double shm[kBlock / 64];
-    if ((threadIdx.x & 63) == 0) shm[threadIdx.x >> 6] = vmax;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double m = 0.0;
-        for (int w = 0; w < kBlock / 64; ++w) m = fmax(m, shm[w]);
-        for (int c = 0; c < 8; ++c) out[c] = res[c];
-        out[8] = m;
-    }
+    double s[8];
+    block_sum<8>(v, s);
+    const double m = block_max(vmax);
+    if (threadIdx.x != 0) return;
+    const InstInfo in = info[i];
+    double hd = in.h * in.h;
+    if (in.dim == 3) hd *= in.h;
+    const double e2 = in.eps * in.eps, ih2 = 1.0 / (in.h * in.h);
+    const double E = hd * (0.25 * s[2] - 0.5 * s[1] + 0.5 * e2 * s[3] * ih2);
+    double* o = out + i * kResStride;
+    o[0] = hd * s[0];
+    o[1] = E;
+    o[2] = E + hd * (0.25 * s[4] + 0.125 * e2 * s[5] * ih2);
+    o[3] = in.dt * hd * s[6] * ih2;
+    o[4] = in.gamma > 0.0 ? in.dt / in.gamma * hd * s[7] * ih2 : 0.0;
+    o[5] = m;
+}
+
+__global__ __launch_bounds__(kBlock) void k_copy_out(Batch<double> b, const CellTask* __restrict__ t,
+                                                     const InstInfo* __restrict__ info,
+                                                     double* phi_prev, double* phi_cur, double* mu,
+                                                     double* p) {
+    const CellTask tk = t[blockIdx.x];
+    const Level<double> L = view_at(b, tk.inst, 0, b.cur);
+    const int idx = tk.cell0 + threadIdx.x;
+    if (idx >= L.n) return;
+    const int g = info[tk.inst].off + idx;
+    phi_prev[g] = phi_cur[g];
+    phi_cur[g] = L.phi[idx];
+    mu[g] = L.mu[idx];
+    p[g] = L.p[idx];
+}
+
+__global__ __launch_bounds__(kBlock) void k_get_solution(Batch<double> b,
+                                                         const CellTask* __restrict__ t,
+                                                         const InstInfo* __restrict__ info,
+                                                         double* phi, double* mu, double* p) {
+    const CellTask tk = t[blockIdx.x];
+    const Level<double> L = view_at(b, tk.inst, 0, b.cur);
+    const int idx = tk.cell0 + threadIdx.x;
+    if (idx >= L.n) return;
+    const int g = info[tk.inst].off + idx;
+    if (phi) phi[g] = L.phi[idx];
+    if (mu) mu[g] = L.mu[idx];
+    if (p) p[g] = L.p[idx];
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill_int(int* dst, int n, int value) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = value;
+}
+
+__global__ __launch_bounds__(kBlock) void k_copy_int(int* dst, const int* src, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
 }
 
 inline int blocks_for(int n) { return (n + kBlock - 1) / kBlock; }
-inline int partial_blocks(int n) {
-    const int b = blocks_for(n);
-    return b < kMaxPartials ? b : kMaxPartials;
-}
 
 }  // namespace
 
-#define CHHS_DISPATCH(dim, KERNEL, GRID, ...)                                         \
-    do {                                                                              \
-        if ((dim) == 2)                                                               \
-            hipLaunchKernelGGL(KERNEL<2>, dim3(GRID), dim3(kBlock), 0, st, __VA_ARGS__); \
-        else                                                                          \
-            hipLaunchKernelGGL(KERNEL<3>, dim3(GRID), dim3(kBlock), 0, st, __VA_ARGS__); \
+#define CHHS_DISPATCH(dim, KERNEL, GRID, ...)                                             \
+    do {                                                                                  \
+        if ((GRID) <= 0) break;                                                           \
+        if ((dim) == 2)                                                                   \
+            hipLaunchKernelGGL(KERNEL<2>, dim3(GRID), dim3(kBlock), 0, st, __VA_ARGS__);  \
+        else                                                                              \
+            hipLaunchKernelGGL(KERNEL<3>, dim3(GRID), dim3(kBlock), 0, st, __VA_ARGS__);  \
     } while (0)
 
-void launch_setup(int dim, const Level<double>& L, const double* phi_prev, const double* phi_cur,
-                  const double* mu, const double* p, double q, hipStream_t st) {
-    CHHS_DISPATCH(dim, k_setup, blocks_for(L.n), L, phi_prev, phi_cur, mu, p, q);
+void launch_setup(int dim, const Batch<double>& b, const CellTask* t, int nt, const InstInfo* info,
+                  const double* phi_prev, const double* phi_cur, const double* mu,
+                  const double* p, hipStream_t st) {
+    CHHS_DISPATCH(dim, k_setup, nt, b, t, info, phi_prev, phi_cur, mu, p);
 }
 
-void launch_restrict_frozen(int dim, const Level<double>& F, const Level<double>& C,
+#define CHHS_DISPATCH_T(dim, KERNEL, GRID, ...)                                           \
+    do {                                                                                  \
+        if ((GRID) <= 0) break;                                                           \
+        if ((dim) == 2)                                                                   \
+            hipLaunchKernelGGL((KERNEL<2, CHHS_TARGS>), dim3(GRID), dim3(kBlock), 0, st,     \
+                               __VA_ARGS__);                                              \
+        else                                                                              \
+            hipLaunchKernelGGL((KERNEL<3, CHHS_TARGS>), dim3(GRID), dim3(kBlock), 0, st,     \
+                               __VA_ARGS__);                                              \
+    } while (0)
+
+#define CHHS_TARGS double
+void launch_restrict_frozen(int dim, const Batch<double>& b, const CellTask* t, int nt,
                             hipStream_t st) {
-    CHHS_DISPATCH(dim, k_restrict_frozen, blocks_for(C.n), F, C);
+    CHHS_DISPATCH_T(dim, k_restrict_frozen, nt, b, t);
 }
-
-void launch_smooth(int dim, const Level<double>& L, int color, hipStream_t st) {
-    CHHS_DISPATCH(dim, k_smooth, blocks_for(L.n), L, color);
+void launch_prolong(int dim, const Batch<double>& b, const CellTask* t, int nt, hipStream_t st) {
+    CHHS_DISPATCH_T(dim, k_prolong, nt, b, t);
 }
-
-void launch_restrict_residual(int dim, const Level<double>& F, const Level<double>& C,
+#undef CHHS_TARGS
+#define CHHS_TARGS float
+void launch_restrict_frozen(int dim, const Batch<float>& b, const CellTask* t, int nt,
+                            hipStream_t st) {
+    CHHS_DISPATCH_T(dim, k_restrict_frozen, nt, b, t);
+}
+void launch_prolong(int dim, const Batch<float>& b, const CellTask* t, int nt, hipStream_t st) {
+    CHHS_DISPATCH_T(dim, k_prolong, nt, b, t);
+}
+#undef CHHS_TARGS
+#define CHHS_TARGS double, false
+void launch_smooth(int dim, const Batch<double>& b, const CellTask* t, int nt, int color,
+                   hipStream_t st) {
+    CHHS_DISPATCH_T(dim, k_smooth, nt, b, t, color);
+}
+void launch_restrict_residual(int dim, const Batch<double>& b, const CellTask* t, int nt,
                               hipStream_t st) {
-    CHHS_DISPATCH(dim, k_restrict_residual, blocks_for(C.n), F, C);
+    CHHS_DISPATCH_T(dim, k_restrict_residual, nt, b, t);
+}
+void launch_coarse_rhs(int dim, const Batch<double>& b, const CellTask* t, int nt, hipStream_t st) {
+    CHHS_DISPATCH_T(dim, k_coarse_rhs, nt, b, t);
+}
+#undef CHHS_TARGS
+#define CHHS_TARGS float, true
+void launch_smooth(int dim, const Batch<float>& b, const CellTask* t, int nt, int color,
+                   hipStream_t st) {
+    CHHS_DISPATCH_T(dim, k_smooth, nt, b, t, color);
+}
+void launch_restrict_residual(int dim, const Batch<float>& b, const CellTask* t, int nt,
+                              hipStream_t st) {
+    CHHS_DISPATCH_T(dim, k_restrict_residual, nt, b, t);
+}
+void launch_coarse_rhs(int dim, const Batch<float>& b, const CellTask* t, int nt, hipStream_t st) {
+    CHHS_DISPATCH_T(dim, k_coarse_rhs, nt, b, t);
+}
+#undef CHHS_TARGS
+
+void launch_mixed_frozen(const Batch<double>& b64, const Batch<float>& b32, const CellTask* t,
+                         int nt, hipStream_t st) {
+    if (nt > 0) hipLaunchKernelGGL(k_mixed_frozen, dim3(nt), dim3(kBlock), 0, st, b64, b32, t);
 }
 
-void launch_coarse_rhs(int dim, const Level<double>& C, hipStream_t st) {
-    CHHS_DISPATCH(dim, k_coarse_rhs, blocks_for(C.n), C);
+void launch_zero_correction(const Batch<float>& b32, const CellTask* t, int nt, hipStream_t st) {
+    if (nt > 0) hipLaunchKernelGGL(k_zero_correction, dim3(nt), dim3(kBlock), 0, st, b32, t);
 }
 
-void launch_prolong(int dim, const Level<double>& F, const Level<double>& C, hipStream_t st) {
-    CHHS_DISPATCH(dim, k_prolong, blocks_for(F.n), F, C);
+void launch_mixed_residual(int dim, const Batch<double>& b64, const Batch<float>& b32,
+                           const CellTask* t, int nt, int add, double* partial, hipStream_t st) {
+    CHHS_DISPATCH(dim, k_mixed_residual, nt, b64, b32, t, add, partial);
 }
 
-int launch_residual_partials(int dim, const Level<double>& L, double* partial, hipStream_t st) {
-    const int nb = partial_blocks(L.n);
-    CHHS_DISPATCH(dim, k_residual_partials, nb, L, partial);
-    return nb;
+void launch_residual_partials(int dim, const Batch<double>& b, const CellTask* t, int nt,
+                              double* partial, hipStream_t st) {
+    CHHS_DISPATCH(dim, k_residual_partials, nt, b, t, partial);
 }
 
-void launch_reduce_final(const double* partial, int nblocks, int ncomp, double* out,
-                         hipStream_t st) {
-    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kBlock), 0, st, partial, nblocks, ncomp, out);
+void launch_inst_reduce(const double* partial, const Range* ranges, const double* partial_t,
+                        const Range* ranges_t, int use_fused, const InstInfo* info,
+                        const int* active, int* act_next, int* cycles, double* res, int n_inst,
+                        double tol, int max_cycles, int count, hipStream_t st) {
+    hipLaunchKernelGGL(k_inst_reduce, dim3(n_inst), dim3(kBlock), 0, st, partial, ranges,
+                       partial_t, ranges_t, use_fused, info, active, act_next, cycles, res, tol,
+                       max_cycles, count);
 }
 
-void launch_shift_p(const Level<double>& L, const double* sum_p, hipStream_t st) {
-    hipLaunchKernelGGL(k_shift_p, dim3(blocks_for(L.n)), dim3(kBlock), 0, st, L.p, L.n, sum_p);
+void launch_shift_p(const Batch<double>& b, const CellTask* t, int nt, const double* res,
+                    hipStream_t st) {
+    if (nt > 0) hipLaunchKernelGGL(k_shift_p, dim3(nt), dim3(kBlock), 0, st, b, t, res);
 }
 
-int launch_energy_partials(int dim, int nx, int ny, int nz, const double* phi, const double* q,
-                           const double* mu, const double* p, const double* pstar, double gamma,
-                           double* partial, hipStream_t st) {
-    const int nb = partial_blocks(nx * ny * nz);
-    CHHS_DISPATCH(dim, k_energy_partials, nb, nx, ny, nz, phi, q, mu, p, pstar, gamma, partial);
-    return nb;
+void launch_energy_partials(int dim, const Batch<double>& b, const CellTask* t, int nt,
+                            const InstInfo* info, int ws, const double* phi, const double* q,
+                            double* partial, hipStream_t st) {
+    CHHS_DISPATCH(dim, k_energy_partials, nt, b, t, info, ws, phi, q, partial);
 }
 
-void launch_reduce_energy(const double* partial, int nblocks, double* out, hipStream_t st) {
-    hipLaunchKernelGGL(k_reduce_energy, dim3(1), dim3(kBlock), 0, st, partial, nblocks, out);
+void launch_energy_reduce(const double* partial, const Range* ranges, const InstInfo* info,
+                          double* out, int n_inst, hipStream_t st) {
+    hipLaunchKernelGGL(k_energy_reduce, dim3(n_inst), dim3(kBlock), 0, st, partial, ranges, info,
+                       out);
+}
+
+void launch_copy_out(const Batch<double>& b, const CellTask* t, int nt, const InstInfo* info,
+                     double* phi_prev, double* phi_cur, double* mu, double* p, hipStream_t st) {
+    if (nt > 0)
+        hipLaunchKernelGGL(k_copy_out, dim3(nt), dim3(kBlock), 0, st, b, t, info, phi_prev,
+                           phi_cur, mu, p);
+}
+
+void launch_get_solution(const Batch<double>& b, const CellTask* t, int nt, const InstInfo* info,
+                         double* phi, double* mu, double* p, hipStream_t st) {
+    if (nt > 0)
+        hipLaunchKernelGGL(k_get_solution, dim3(nt), dim3(kBlock), 0, st, b, t, info, phi, mu, p);
+}
+
+void launch_fill_int(int* dst, int n, int value, hipStream_t st) {
+    if (n > 0) hipLaunchKernelGGL(k_fill_int, dim3(blocks_for(n)), dim3(kBlock), 0, st, dst, n, value);
+}
+
+void launch_copy_int(int* dst, const int* src, int n, hipStream_t st) {
+    if (n > 0) hipLaunchKernelGGL(k_copy_int, dim3(blocks_for(n)), dim3(kBlock), 0, st, dst, src, n);
 }
 
 }  // namespace chhs

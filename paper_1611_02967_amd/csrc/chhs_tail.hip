@@ -1,7 +1,8 @@
 // Coarse tail of the V-cycle in one workgroup.
 //
-// Every level from the tail's top level down to the coarsest grid is staged in
-// LDS (11 fields per level), and the V-cycle over those levels -- smoothing,
+// One workgroup per instance.  Every level from the instance's tail level
+// down to the coarsest grid is staged in LDS (11 fields per level), and the
+// V-cycle over those levels -- smoothing,
 // residual + restriction, FAS coarse right-hand side, the coarsest-grid
 // smoothing steps, prolongation + correction -- runs inside a single
 // workgroup with a barrier between dependent phases.  Launch latency of the
@@ -14,14 +15,7 @@ namespace {
 
 constexpr int kTailThreads = 1024;
 
-template <typename T>
-struct TailArgs {
-    Level<T> lv[kMaxTailLevels];
-    int nlev;
-    int nu1, nu2, coarse_sweeps;
-};
-
-template <int DIM, typename T>
+template <int DIM, typename T, bool CORR>
 __device__ void tail_smooth(const Level<T>& L) {
     for (int color = 0; color < 2; ++color) {
         for (int idx = threadIdx.x; idx < L.n; idx += blockDim.x) {
@@ -29,7 +23,7 @@ __device__ void tail_smooth(const Level<T>& L) {
             decode<DIM>(idx, L.nx, L.ny, i, j, k);
             if (((i + j + k) & 1) != color) continue;
             T phi, mu, p;
-            cell_solve<DIM>(L, idx, i, j, k, phi, mu, p);
+            cell_solve<DIM, T, CORR>(L, idx, i, j, k, phi, mu, p);
             L.phi[idx] = phi;
             L.mu[idx] = mu;
             L.p[idx] = p;
@@ -38,12 +32,12 @@ __device__ void tail_smooth(const Level<T>& L) {
     }
 }
 
-template <int DIM, typename T>
+template <int DIM, typename T, bool CORR>
 __device__ void tail_restrict(const Level<T>& F, const Level<T>& C) {
     for (int idx = threadIdx.x; idx < C.n; idx += blockDim.x) {
         int ci, cj, ck;
         decode<DIM>(idx, C.nx, C.ny, ci, cj, ck);
-        T su0 = 0, su1 = 0, su2 = 0, sr0 = 0, sr1 = 0, sr2 = 0;
+        T su0 = 0, su1 = 0, su2 = 0, sr0 = 0, sr1 = 0, sr2 = 0, sb = 0;
 #pragma unroll 1
         for (int dz = 0; dz < (DIM == 3 ? 2 : 1); ++dz)
 #pragma unroll 1
@@ -52,15 +46,17 @@ __device__ void tail_restrict(const Level<T>& F, const Level<T>& C) {
                     const int fi = 2 * ci + dx, fj = 2 * cj + dy, fk = 2 * ck + dz;
                     const int f = (fk * F.ny + fj) * F.nx + fi;
                     T n0, n1, n2;
-                    cell_operator<DIM>(F, f, fi, fj, fk, n0, n1, n2);
+                    cell_operator<DIM, T, CORR>(F, f, fi, fj, fk, n0, n1, n2);
                     sr0 += F.f0[f] - n0;
                     sr1 += F.f1[f] - n1;
                     sr2 += F.f2[f] - n2;
                     su0 += F.phi[f];
                     su1 += F.mu[f];
                     su2 += F.p[f];
+                    if (CORR) sb += F.b[f];
                 }
         const T w = DIM == 3 ? T(0.125) : T(0.25);
+        if (CORR) C.b[idx] = sb * w;
         C.phi[idx] = C.ub0[idx] = su0 * w;
         C.mu[idx] = C.ub1[idx] = su1 * w;
         C.p[idx] = C.ub2[idx] = su2 * w;
@@ -73,7 +69,7 @@ __device__ void tail_restrict(const Level<T>& F, const Level<T>& C) {
         int i, j, k;
         decode<DIM>(idx, C.nx, C.ny, i, j, k);
         T n0, n1, n2;
-        cell_operator<DIM>(C, idx, i, j, k, n0, n1, n2);
+        cell_operator<DIM, T, CORR>(C, idx, i, j, k, n0, n1, n2);
         C.f0[idx] += n0;
         C.f1[idx] += n1;
         C.f2[idx] += n2;
@@ -94,13 +90,16 @@ __device__ void tail_prolong(const Level<T>& F, const Level<T>& C) {
     __syncthreads();
 }
 
-// LDS view of tail level l: the global descriptor with its 11 arrays placed
-// one after another in LDS, levels one after another.
-template <typename T>
-__device__ __forceinline__ Level<T> lds_view(const TailArgs<T>& a, int l, T* base) {
+// LDS view of tail level l (a level index of the instance, l >= tail): the
+// level's descriptor with its 11 arrays (12 with the base state b of the
+// correction form) placed one after another in LDS, levels one after another
+// from the tail's top level.
+template <typename T, bool CORR>
+__device__ __forceinline__ Level<T> lds_view(const LevelDesc<T>* d, int tail, int l, T* base) {
+    constexpr int NF = CORR ? 12 : 11;
     size_t off = 0;
-    for (int k = 0; k < l; ++k) off += size_t(11) * a.lv[k].n;
-    Level<T> v = a.lv[l];
+    for (int k = tail; k < l; ++k) off += size_t(NF) * d[k].n;
+    Level<T> v = make_view(d[l], 0);
     const int n = v.n;
     T* b = base + off;
     v.phi = b;
@@ -114,19 +113,31 @@ __device__ __forceinline__ Level<T> lds_view(const TailArgs<T>& a, int l, T* bas
     v.f2 = b + 8 * n;
     v.pstar = b + 9 * n;
     v.psi = b + 10 * n;
+    v.b = CORR ? b + 11 * n : nullptr;
+    v.phi_alt = v.mu_alt = v.p_alt = nullptr;
     return v;
 }
 
-template <int DIM, typename T>
-__global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs<T> a) {
+template <int DIM, typename T, bool CORR>
+__global__ __launch_bounds__(kTailThreads) void k_tail(const LevelDesc<T>* __restrict__ desc,
+                                                       const InstInfo* __restrict__ info,
+                                                       const int* __restrict__ insts,
+                                                       const int* __restrict__ active,
+                                                       unsigned cur_mask, int nu1, int nu2,
+                                                       int coarse_sweeps) {
     extern __shared__ __align__(16) unsigned char tail_lds[];
     T* base = reinterpret_cast<T*>(tail_lds);
+    const int inst = insts[blockIdx.x];
+    if (active != nullptr && active[inst] == 0) return;
+    const InstInfo in = info[inst];
+    const LevelDesc<T>* d = desc + inst * kMaxLevels;
+    const int top = in.tail, nlev = in.nlev;
 
     // stage the top level's iterate and right-hand side, and every level's
     // frozen data
+    const Level<T> G = make_view(d[top], (cur_mask >> top) & 1u);
     {
-        const Level<T>& G = a.lv[0];
-        const Level<T> S = lds_view(a, 0, base);
+        const Level<T> S = lds_view<T, CORR>(d, top, top, base);
         for (int idx = threadIdx.x; idx < G.n; idx += blockDim.x) {
             S.phi[idx] = G.phi[idx];
             S.mu[idx] = G.mu[idx];
@@ -134,35 +145,36 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs<T> a) {
             S.f0[idx] = G.f0[idx];
             S.f1[idx] = G.f1[idx];
             S.f2[idx] = G.f2[idx];
+            if (CORR) S.b[idx] = G.b[idx];
         }
-        for (int l = 0; l < a.nlev; ++l) {
-            const Level<T> V = lds_view(a, l, base);
+        for (int l = top; l < nlev; ++l) {
+            const Level<T> V = lds_view<T, CORR>(d, top, l, base);
+            const LevelDesc<T>& D = d[l];
             for (int idx = threadIdx.x; idx < V.n; idx += blockDim.x) {
-                V.pstar[idx] = a.lv[l].pstar[idx];
-                V.psi[idx] = a.lv[l].psi[idx];
+                V.pstar[idx] = D.pstar[idx];
+                V.psi[idx] = D.psi[idx];
             }
         }
     }
     __syncthreads();
 
-    const int last = a.nlev - 1;
-    for (int l = 0; l < last; ++l) {
-        const Level<T> F = lds_view(a, l, base);
-        for (int s = 0; s < a.nu1; ++s) tail_smooth<DIM>(F);
-        tail_restrict<DIM>(F, lds_view(a, l + 1, base));
+    const int last = nlev - 1;
+    for (int l = top; l < last; ++l) {
+        const Level<T> F = lds_view<T, CORR>(d, top, l, base);
+        for (int s = 0; s < nu1; ++s) tail_smooth<DIM, T, CORR>(F);
+        tail_restrict<DIM, T, CORR>(F, lds_view<T, CORR>(d, top, l + 1, base));
     }
     {
-        const Level<T> B = lds_view(a, last, base);
-        for (int s = 0; s < a.coarse_sweeps; ++s) tail_smooth<DIM>(B);
+        const Level<T> B = lds_view<T, CORR>(d, top, last, base);
+        for (int s = 0; s < coarse_sweeps; ++s) tail_smooth<DIM, T, CORR>(B);
     }
-    for (int l = last - 1; l >= 0; --l) {
-        const Level<T> F = lds_view(a, l, base);
-        tail_prolong<DIM>(F, lds_view(a, l + 1, base));
-        for (int s = 0; s < a.nu2; ++s) tail_smooth<DIM>(F);
+    for (int l = last - 1; l >= top; --l) {
+        const Level<T> F = lds_view<T, CORR>(d, top, l, base);
+        tail_prolong<DIM>(F, lds_view<T, CORR>(d, top, l + 1, base));
+        for (int s = 0; s < nu2; ++s) tail_smooth<DIM, T, CORR>(F);
     }
 
-    const Level<T>& G = a.lv[0];
-    const Level<T> S = lds_view(a, 0, base);
+    const Level<T> S = lds_view<T, CORR>(d, top, top, base);
     for (int idx = threadIdx.x; idx < G.n; idx += blockDim.x) {
         G.phi[idx] = S.phi[idx];
         G.mu[idx] = S.mu[idx];
@@ -172,41 +184,44 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs<T> a) {
 
 }  // namespace
 
-size_t tail_lds_bytes(const int* cells, int nlev, size_t elem) {
+size_t tail_lds_bytes(const int* cells, int nlev, size_t elem, int nfields) {
     size_t b = 0;
-    for (int l = 0; l < nlev; ++l) b += size_t(cells[l]) * 11 * elem;
+    for (int l = 0; l < nlev; ++l) b += size_t(cells[l]) * nfields * elem;
     return b;
 }
 
-template <typename T>
+template <typename T, bool CORR>
 int prepare_tail(int dim, size_t lds_bytes) {
     hipError_t e;
     if (dim == 2)
-        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tail<2, T>),
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tail<2, T, CORR>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_bytes));
     else
-        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tail<3, T>),
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tail<3, T, CORR>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_bytes));
     return e == hipSuccess ? 0 : -1;
 }
 
-template <typename T>
-void launch_tail(int dim, const Level<T>* levels, int nlev, int nu1, int nu2, int coarse_sweeps,
-                 size_t lds_bytes, hipStream_t st) {
-    TailArgs<T> a{};
-    for (int l = 0; l < nlev; ++l) a.lv[l] = levels[l];
-    a.nlev = nlev;
-    a.nu1 = nu1;
-    a.nu2 = nu2;
-    a.coarse_sweeps = coarse_sweeps;
+template <typename T, bool CORR>
+void launch_tail(int dim, const LevelDesc<T>* desc, const InstInfo* info, const int* insts,
+                 int ninst, const int* active, unsigned cur_mask, int nu1, int nu2,
+                 int coarse_sweeps, size_t lds_bytes, hipStream_t st) {
+    if (ninst <= 0) return;
     if (dim == 2)
-        hipLaunchKernelGGL((k_tail<2, T>), dim3(1), dim3(kTailThreads), lds_bytes, st, a);
+        hipLaunchKernelGGL((k_tail<2, T, CORR>), dim3(ninst), dim3(kTailThreads), lds_bytes, st,
+                           desc, info, insts, active, cur_mask, nu1, nu2, coarse_sweeps);
     else
-        hipLaunchKernelGGL((k_tail<3, T>), dim3(1), dim3(kTailThreads), lds_bytes, st, a);
+        hipLaunchKernelGGL((k_tail<3, T, CORR>), dim3(ninst), dim3(kTailThreads), lds_bytes, st,
+                           desc, info, insts, active, cur_mask, nu1, nu2, coarse_sweeps);
 }
 
-template int prepare_tail<double>(int, size_t);
-template void launch_tail<double>(int, const Level<double>*, int, int, int, int, size_t,
-                                  hipStream_t);
+template int prepare_tail<double, false>(int, size_t);
+template int prepare_tail<float, true>(int, size_t);
+template void launch_tail<double, false>(int, const LevelDesc<double>*, const InstInfo*,
+                                         const int*, int, const int*, unsigned, int, int, int,
+                                         size_t, hipStream_t);
+template void launch_tail<float, true>(int, const LevelDesc<float>*, const InstInfo*, const int*,
+                                       int, const int*, unsigned, int, int, int, size_t,
+                                       hipStream_t);
 
 }  // namespace chhs

@@ -1,17 +1,17 @@
-// LDS-tiled smoothing kernels for 2D levels.
+// LDS-tiled smoothing kernels for 2D levels, batched over instances.
 //
-// One workgroup owns a TX x TY block of cells and stages it in LDS together
-// with a halo of H cells.  It runs NS fused smoothing steps (each a red and a
-// black collective (phi, mu, p) cell update, the same update as k_smooth) on
-// shrinking rings: phase q of the 2 NS phases updates every cell of its color
-// within ring X + 2 NS - 1 - q of the block, so after the last phase the
-// block and X extra rings hold exactly what two-launch red-black sweeps would
-// produce.  Halo cells are recomputed redundantly by the neighbouring blocks
-// with identical arithmetic.
+// One workgroup owns a TX x TY block of cells of one instance (a TileTask) and
+// stages it in LDS together with a halo of H cells.  It runs NS fused smoothing
+// steps (each a red and a black collective (phi, mu, p) cell update, the same
+// update as k_smooth) on shrinking rings: phase q of the 2 NS phases updates
+// every cell of its color within ring X + 2 NS - 1 - q of the block, so after
+// the last phase the block and X extra rings hold exactly what two-launch
+// red-black sweeps would produce.  Halo cells are recomputed redundantly by the
+// neighbouring blocks with identical arithmetic.
 //
 // The kernel is out of place: it reads u = (phi, mu, p) and writes the block
-// into (phi_alt, mu_alt, p_alt), so a block never loads a halo that another
-// block has already overwritten; the host swaps the two copies afterwards.
+// into the other copy of u, so a block never loads a halo that another block
+// has already overwritten; the host then makes the written copy current.
 //
 // Optional fused parts:
 //   PRO    prologue: u += P(u_c - ub_c) (piecewise-constant prolongation of the
@@ -20,6 +20,8 @@
 //          cell averaging to the coarse level: u_c = ub_c = R u, f_c = R R
 //          (the N_c(u_c) part follows in a coarse kernel).
 //   EPI 2  epilogue: per-block partial sums of R_phi^2, R_mu^2, R_p^2 and p.
+//   CORR   correction form of the mixed-precision inner solve (chhs_cell.hpp):
+//          the base state b is read per cell and restricted with u.
 //
 // Threads own pairs of horizontally adjacent cells (x even, x + 1) so that
 // exactly one cell of every pair has the color of a phase: all lanes work in
@@ -27,13 +29,13 @@
 // LDS each row is stored as its even columns followed by its odd columns; all
 // pairs of a row update the same member in a phase, so the lanes of a wave
 // touch consecutive LDS words.
-#include "chhs_internal.hpp"
+#include "chhs_cell.hpp"
 
 namespace chhs {
 namespace {
 
-constexpr int kTX = 64;     // block width (cells)
-constexpr int kTY = 16;     // block height (cells)
+constexpr int kTX = kTileX;     // block width (cells)
+constexpr int kTY = kTileY;     // block height (cells)
 constexpr int kThreads = 256;
 
 template <int NS, int EPI>
@@ -52,52 +54,50 @@ struct Geometry {
 template <int PW>
 __device__ __forceinline__ int lds(int r, int x) { return (2 * r + (x & 1)) * PW + (x >> 1); }
 
-template <typename T>
-__device__ __forceinline__ T chi_of(T x, T y) { return T(0.25) * (x * x + y * y) * (x + y); }
-template <typename T>
-__device__ __forceinline__ T dchi_of(T x, T y) {
-    return T(0.25) * (T(3) * x * x + T(2) * x * y + y * y);
-}
-
-template <typename T, bool LEVEL0, int NS, int EPI, bool PRO>
-__global__ __launch_bounds__(kThreads) void k_tile2d(Level<T> L, Level<T> C, double* partial,
-                                                     int tiles_x, int ntiles) {
+template <typename T, bool LEVEL0, int NS, int EPI, bool PRO, bool CORR>
+__global__ __launch_bounds__(kThreads) void k_tile2d(Batch<T> bt, const TileTask* __restrict__ tasks,
+                                                     int ntiles, double* partial) {
     using G = Geometry<NS, EPI>;
     constexpr int W = G::W, R = G::R, H = G::H, HX = G::HX;
-    constexpr int PW = G::PW;
+    constexpr int PW = G::PW, KP = G::KP, NP = G::NP;
     __shared__ T s_phi[R * W];
     __shared__ T s_mu[R * W];
     __shared__ T s_p[R * W];
     __shared__ T s_ps[R * W];
 
     // Workgroups are dispatched round-robin over the 8 XCDs.  Give XCD x a
-    // contiguous range of blocks (a bijection of [0, ntiles)) so that
+    // contiguous range of tasks (a bijection of [0, ntiles)) so that
     // neighbouring blocks share their halo through the same L2.
     const int bid = blockIdx.x;
-    const int xcd = bid % 8, j = bid / 8;
+    const int xcd = bid % 8, jj = bid / 8;
     const int q8 = ntiles / 8, rem = ntiles % 8;
-    const int tile = xcd * q8 + (xcd < rem ? xcd : rem) + j;
-    const int bx = tile % tiles_x, by = tile / tiles_x;
-    const int x0 = bx * kTX - HX, y0 = by * kTY - H;     // region origin in global cells
+    const int tile = xcd * q8 + (xcd < rem ? xcd : rem) + jj;
+    const TileTask tk = tasks[tile];
+    if (bt.active != nullptr && bt.active[tk.inst] == 0) return;
+    const Level<T> L = make_view(bt.desc[tk.inst * kMaxLevels + bt.level], bt.cur);
+    const Level<T> C = make_view(bt.desc[tk.inst * kMaxLevels + bt.level + 1], bt.cur_c);
+    const int x0 = tk.bx * kTX - HX, y0 = tk.by * kTY - H;     // region origin in cells
     const int nx = L.nx, ny = L.ny;
     const int tid = threadIdx.x;
 
     // own-cell data of the thread's pairs, stored by color (index 0 = the red
     // member, 1 = the black member) so that every phase reads them with
     // compile-time indices: psi, f0, f1, f2
-    T o_psi[2][G::KP], o_f0[2][G::KP], o_f1[2][G::KP], o_f2[2][G::KP];
+    T o_psi[2][KP], o_f0[2][KP], o_f1[2][KP], o_f2[2][KP], o_b[2][KP];
+    // staged values of the pairs before they go to LDS
+    T v_phi[KP][2], v_mu[KP][2], v_p[KP][2], v_ps[KP][2];
 
+    // 1) issue every global load of the region first ...
 #pragma unroll
-    for (int k = 0; k < G::KP; ++k) {
+    for (int k = 0; k < KP; ++k) {
         const int q = tid + k * kThreads;
-        if (q >= G::NP) continue;
-        const int r = q / G::PW, x = 2 * (q % G::PW);
+        const int r = q / PW, x = 2 * (q % PW);
         const int gy = y0 + r;
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
             const int gx = x0 + x + e;
-            T phi = 0, mu = 0, p = 0, ps = 0, psi = 0, f0 = 0, f1 = 0, f2 = 0;
-            if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
+            T phi = 0, mu = 0, p = 0, ps = 0, psi = 0, f0 = 0, f1 = 0, f2 = 0, bs = 0;
+            if (q < NP && gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
                 const int g = gy * nx + gx;
                 phi = L.phi[g];
                 mu = L.mu[g];
@@ -111,6 +111,7 @@ __global__ __launch_bounds__(kThreads) void k_tile2d(Level<T> L, Level<T> C, dou
                     f0 = L.f0[g];
                     f2 = L.f2[g];
                 }
+                if (CORR) bs = L.b[g];
                 if (PRO) {
                     const int c = (gy >> 1) * C.nx + (gx >> 1);
                     phi += C.phi[c] - C.ub0[c];
@@ -118,45 +119,60 @@ __global__ __launch_bounds__(kThreads) void k_tile2d(Level<T> L, Level<T> C, dou
                     p += C.p[c] - C.ub2[c];
                 }
             }
-            const int w = lds<PW>(r, x + e);
-            s_phi[w] = phi;
-            s_mu[w] = mu;
-            s_p[w] = p;
-            s_ps[w] = ps;
+            v_phi[k][e] = phi;
+            v_mu[k][e] = mu;
+            v_p[k][e] = p;
+            v_ps[k][e] = ps;
             // member e has color (e + gy) & 1 because x0 + x is even
             const bool red = ((e + gy) & 1) == 0;
             if (e == 0) {
-                o_psi[0][k] = psi;
-                o_f0[0][k] = f0;
-                o_f1[0][k] = f1;
-                o_f2[0][k] = f2;
-                o_psi[1][k] = psi;
-                o_f0[1][k] = f0;
-                o_f1[1][k] = f1;
-                o_f2[1][k] = f2;
+                o_psi[0][k] = o_psi[1][k] = psi;
+                o_f0[0][k] = o_f0[1][k] = f0;
+                o_f1[0][k] = o_f1[1][k] = f1;
+                o_f2[0][k] = o_f2[1][k] = f2;
+                o_b[0][k] = o_b[1][k] = bs;
+            } else {
+                o_b[0][k] = red ? bs : o_b[0][k];
+                o_b[1][k] = red ? o_b[1][k] : bs;
+                o_psi[0][k] = red ? psi : o_psi[0][k];
+                o_f0[0][k] = red ? f0 : o_f0[0][k];
+                o_f1[0][k] = red ? f1 : o_f1[0][k];
+                o_f2[0][k] = red ? f2 : o_f2[0][k];
+                o_psi[1][k] = red ? o_psi[1][k] : psi;
+                o_f0[1][k] = red ? o_f0[1][k] : f0;
+                o_f1[1][k] = red ? o_f1[1][k] : f1;
+                o_f2[1][k] = red ? o_f2[1][k] : f2;
             }
-            o_psi[0][k] = red ? psi : o_psi[0][k];
-            o_f0[0][k] = red ? f0 : o_f0[0][k];
-            o_f1[0][k] = red ? f1 : o_f1[0][k];
-            o_f2[0][k] = red ? f2 : o_f2[0][k];
-            o_psi[1][k] = red ? o_psi[1][k] : psi;
-            o_f0[1][k] = red ? o_f0[1][k] : f0;
-            o_f1[1][k] = red ? o_f1[1][k] : f1;
-            o_f2[1][k] = red ? o_f2[1][k] : f2;
+        }
+    }
+    // 2) ... then stage them in LDS
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+        const int q = tid + k * kThreads;
+        if (q >= NP) continue;
+        const int r = q / PW, x = 2 * (q % PW);
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int w = lds<PW>(r, x + e);
+            s_phi[w] = v_phi[k][e];
+            s_mu[w] = v_mu[k][e];
+            s_p[w] = v_p[k][e];
+            s_ps[w] = v_ps[k][e];
         }
     }
     __syncthreads();
 
     const T lam = L.lam, kap = L.kap, gam = L.gamma;
+    const T inv_lam = T(1) / lam;
 #pragma unroll
     for (int ph = 0; ph < 2 * NS; ++ph) {
         const int color = ph & 1;
         const int ring = G::X + 2 * NS - 1 - ph;
 #pragma unroll
-        for (int k = 0; k < G::KP; ++k) {
+        for (int k = 0; k < KP; ++k) {
             const int q = tid + k * kThreads;
-            if (q >= G::NP) continue;
-            const int r = q / G::PW, xp = 2 * (q % G::PW);
+            if (q >= NP) continue;
+            const int r = q / PW, xp = 2 * (q % PW);
             const int gy = y0 + r;
             // the pair member with this color (x0 + xp is even): same for a whole row
             const int e = (gy & 1) ^ color;
@@ -169,14 +185,15 @@ __global__ __launch_bounds__(kThreads) void k_tile2d(Level<T> L, Level<T> C, dou
 
             const int wc = lds<PW>(r, x);
             const T psc = s_ps[wc];
-            T nf = 0, sa = 0, sa2 = 0, smmu = 0, sphi = 0, sp = 0, sap = 0, samu = 0;
+            int nf = 0;
+            T sa = 0, sa2 = 0, smmu = 0, sphi = 0, sp = 0, sap = 0, samu = 0;
             auto nb_acc = [&](int rr, int xx) {
                 const int w = lds<PW>(rr, xx);
                 const T a = T(0.5) * (psc + s_ps[w]);
                 const T m = T(1) + gam * a * a;
                 const T munb = s_mu[w];
                 const T pnb = s_p[w];
-                nf += T(1);
+                nf += 1;
                 sa += a;
                 sa2 += a * a;
                 smmu += m * munb;
@@ -189,36 +206,37 @@ __global__ __launch_bounds__(kThreads) void k_tile2d(Level<T> L, Level<T> C, dou
             if (gx < nx - 1) nb_acc(r, x + 1);
             if (gy > 0) nb_acc(r - 1, x);
             if (gy < ny - 1) nb_acc(r + 1, x);
+            const T fnf = T(nf);
+            const T inv_nf = nf == 4 ? T(0.25) : (nf == 3 ? T(1) / T(3) : (nf == 2 ? T(0.5) : T(1)));
             const T phit = s_phi[wc];
             const T psi = o_psi[color][k];
             const T f0 = o_f0[color][k];
             const T f1 = o_f1[color][k];
             const T f2 = o_f2[color][k];
-            const T dchi = dchi_of(phit, psi);
-            const T chi = chi_of(phit, psi);
+            const T base = o_b[color][k];
+            const T dchi = dnonlin<T, CORR>(phit, psi, base);
+            const T chi = nonlin<T, CORR>(phit, psi, base);
             const T b1 = f0 + lam * smmu + lam * sap;
             const T b2 = f1 + chi - dchi * phit - kap * sphi;
             const T b3 = f2 - lam * sp - lam * gam * samu;
-            const T ared = lam * (nf + gam * (sa2 - sa * sa / nf));
-            const T b1r = b1 + (sa / nf) * b3;
-            const T bb = dchi + kap * nf;
-            const T det = T(1) + ared * bb;
-            const T phin = (b1r - ared * b2) / det;
-            const T mun = (b2 + bb * b1r) / det;
-            const T pn = -(b3 + lam * gam * sa * mun) / (lam * nf);
-            s_phi[wc] = phin;
+            const T ared = lam * (fnf + gam * (sa2 - sa * sa * inv_nf));
+            const T b1r = b1 + (sa * inv_nf) * b3;
+            const T bb = dchi + kap * fnf;
+            const T inv_det = T(1) / (T(1) + ared * bb);
+            const T mun = (b2 + bb * b1r) * inv_det;
+            s_phi[wc] = (b1r - ared * b2) * inv_det;
             s_mu[wc] = mun;
-            s_p[wc] = pn;
+            s_p[wc] = -(b3 * inv_lam + gam * sa * mun) * inv_nf;
         }
         __syncthreads();
     }
 
-    // write back the block
+    // write the block into the other copy of u
 #pragma unroll
-    for (int k = 0; k < G::KP; ++k) {
+    for (int k = 0; k < KP; ++k) {
         const int q = tid + k * kThreads;
-        if (q >= G::NP) continue;
-        const int r = q / G::PW, xp = 2 * (q % G::PW);
+        if (q >= NP) continue;
+        const int r = q / PW, xp = 2 * (q % PW);
         if (r < H || r >= H + kTY || xp < HX || xp >= HX + kTX) continue;
         const int gy = y0 + r;
 #pragma unroll
@@ -235,14 +253,19 @@ __global__ __launch_bounds__(kThreads) void k_tile2d(Level<T> L, Level<T> C, dou
 
     if (EPI == 0) return;
 
-    // residual on the block: thread t owns the 2x2 children of one coarse cell
-    const int cxl = tid % (kTX / 2), cyl = tid / (kTX / 2);   // 32 x 8 coarse cells
+    // residual on the block.  Slot s (512 per block) is the pair of
+    // horizontally adjacent fine cells in row cy of coarse cell (cxl, cyl);
+    // slots s and s ^ 32 -- lanes l and l ^ 32 of one wave -- are the two rows
+    // of the same coarse cell.
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    T su[3] = {0, 0, 0}, sr[3] = {0, 0, 0};
-    const int gcx = (x0 + HX) / 2 + cxl, gcy = (y0 + H) / 2 + cyl;
-    const bool live = 2 * gcx < nx && 2 * gcy < ny;
-    if (live) {
-        for (int cy = 0; cy < 2; ++cy)
+#pragma unroll
+    for (int j = 0; j < 512 / kThreads; ++j) {
+        const int slot = tid + j * kThreads;
+        const int cxl = slot & 31, cy = (slot >> 5) & 1, cyl = slot >> 6;   // 32 x 8 coarse cells
+        T su[3] = {0, 0, 0}, sr[3] = {0, 0, 0}, sb = 0;
+        const int gcx = (x0 + HX) / 2 + cxl, gcy = (y0 + H) / 2 + cyl;
+        const bool live = 2 * gcx < nx && 2 * gcy < ny;
+        if (live) {
             for (int cx = 0; cx < 2; ++cx) {
                 const int r = H + 2 * cyl + cy, x = HX + 2 * cxl + cx;
                 const int gx = x0 + x, gy = y0 + r;
@@ -270,8 +293,9 @@ __global__ __launch_bounds__(kThreads) void k_tile2d(Level<T> L, Level<T> C, dou
                 const T f0 = LEVEL0 ? psi : L.f0[g];
                 const T f1 = L.f1[g];
                 const T f2 = LEVEL0 ? T(0) : L.f2[g];
+                const T bg = CORR ? L.b[g] : T(0);
                 const T r0 = f0 - (phic - lam * smm - lam * sap);
-                const T r1 = f1 - (muc - chi_of(phic, psi) + kap * sphi);
+                const T r1 = f1 - (muc - nonlin<T, CORR>(phic, psi, bg) + kap * sphi);
                 const T r2 = f2 - (lam * sp + lam * gam * samu);
                 if (EPI == 1) {
                     sr[0] += r0;
@@ -280,6 +304,7 @@ __global__ __launch_bounds__(kThreads) void k_tile2d(Level<T> L, Level<T> C, dou
                     su[0] += phic;
                     su[1] += muc;
                     su[2] += pc;
+                    sb += bg;
                 } else {
                     acc[0] += double(r0) * double(r0);
                     acc[1] += double(r1) * double(r1);
@@ -287,20 +312,29 @@ __global__ __launch_bounds__(kThreads) void k_tile2d(Level<T> L, Level<T> C, dou
                     acc[3] += double(pc);
                 }
             }
-    }
-    if (EPI == 1) {
-        if (live) {
-            const int c = gcy * C.nx + gcx;
-            const T w = T(0.25);
-            C.phi[c] = C.ub0[c] = su[0] * w;
-            C.mu[c] = C.ub1[c] = su[1] * w;
-            C.p[c] = C.ub2[c] = su[2] * w;
-            C.f0[c] = sr[0] * w;
-            C.f1[c] = sr[1] * w;
-            C.f2[c] = sr[2] * w;
         }
-        return;
+        if (EPI == 1) {
+            // combine the two rows (lane ^ 32); row 0 writes the coarse cell
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                sr[c] += __shfl_xor(sr[c], 32, 64);
+                su[c] += __shfl_xor(su[c], 32, 64);
+            }
+            if (CORR) sb += __shfl_xor(sb, 32, 64);
+            if (live && cy == 0) {
+                const int c = gcy * C.nx + gcx;
+                const T w = T(0.25);
+                C.phi[c] = C.ub0[c] = su[0] * w;
+                C.mu[c] = C.ub1[c] = su[1] * w;
+                C.p[c] = C.ub2[c] = su[2] * w;
+                C.f0[c] = sr[0] * w;
+                C.f1[c] = sr[1] * w;
+                C.f2[c] = sr[2] * w;
+                if (CORR) C.b[c] = sb * w;
+            }
+        }
     }
+    if (EPI == 1) return;
     // EPI == 2: block partial sums in a fixed order
     for (int off = 32; off > 0; off >>= 1)
         for (int c = 0; c < 4; ++c) acc[c] += __shfl_xor(acc[c], off, 64);
@@ -312,32 +346,27 @@ __global__ __launch_bounds__(kThreads) void k_tile2d(Level<T> L, Level<T> C, dou
         for (int c = 0; c < 4; ++c) {
             double s = 0.0;
             for (int w = 0; w < kThreads / 64; ++w) s += red[c][w];
-            partial[bid * kPartialStride + c] = s;
+            partial[tile * kPartialStride + c] = s;
         }
 }
 
-template <typename T, bool LEVEL0, int NS, int EPI, bool PRO>
-int launch_one(const Level<T>& L, const Level<T>& C, double* partial, hipStream_t st) {
-    const int tx = (L.nx + kTX - 1) / kTX, ty = (L.ny + kTY - 1) / kTY;
-    const int nt = tx * ty;
-    hipLaunchKernelGGL((k_tile2d<T, LEVEL0, NS, EPI, PRO>), dim3(nt), dim3(kThreads), 0, st, L, C,
-                       partial, tx, nt);
-    return nt;
+template <typename T, bool LEVEL0, int NS, int EPI, bool PRO, bool CORR>
+void launch_one(const Batch<T>& b, const TileTask* t, int nt, double* partial, hipStream_t st) {
+    hipLaunchKernelGGL((k_tile2d<T, LEVEL0, NS, EPI, PRO, CORR>), dim3(nt), dim3(kThreads), 0, st,
+                       b, t, nt, partial);
 }
 
 }  // namespace
 
-int tile2d_blocks(int nx, int ny) { return ((nx + kTX - 1) / kTX) * ((ny + kTY - 1) / kTY); }
-
-// One tiled launch: ns in {1, 2} fused smoothing steps on L, epilogue epi
-// (0 none, 1 residual + restriction into C, 2 residual-norm partials), pro =
-// prolongation of C's correction first.  Returns the number of blocks.
-template <typename T>
-int launch_tile2d(const Level<T>& L, const Level<T>& C, bool level0, int ns, int epi, bool pro,
-                  double* partial, hipStream_t st) {
+template <>
+void launch_tile2d<double>(const Batch<double>& b, const TileTask* t, int nt, bool level0, int ns,
+                           int epi, bool pro, double* partial, hipStream_t st) {
+    if (nt <= 0) return;
 #define CHHS_TILE_CASE(L0, NS, EPI, PRO)                                          \
-    if (level0 == L0 && ns == NS && epi == EPI && pro == PRO)                     \
-        return launch_one<T, L0, NS, EPI, PRO>(L, C, partial, st);
+    if (level0 == L0 && ns == NS && epi == EPI && pro == PRO) {                   \
+        launch_one<double, L0, NS, EPI, PRO, false>(b, t, nt, partial, st);       \
+        return;                                                                   \
+    }
 #define CHHS_TILE_PRO(L0, NS, EPI) CHHS_TILE_CASE(L0, NS, EPI, false) CHHS_TILE_CASE(L0, NS, EPI, true)
 #define CHHS_TILE_EPI(L0, NS) CHHS_TILE_PRO(L0, NS, 0) CHHS_TILE_PRO(L0, NS, 1) CHHS_TILE_PRO(L0, NS, 2)
     CHHS_TILE_EPI(true, 1)
@@ -347,10 +376,27 @@ int launch_tile2d(const Level<T>& L, const Level<T>& C, bool level0, int ns, int
 #undef CHHS_TILE_EPI
 #undef CHHS_TILE_PRO
 #undef CHHS_TILE_CASE
-    return -1;
 }
 
-template int launch_tile2d<double>(const Level<double>&, const Level<double>&, bool, int, int,
-                                   bool, double*, hipStream_t);
+// FP32 correction form (mixed-precision inner solve): general right-hand
+// sides, no norm epilogue.
+template <>
+void launch_tile2d<float>(const Batch<float>& b, const TileTask* t, int nt, bool level0, int ns,
+                          int epi, bool pro, double* partial, hipStream_t st) {
+    (void)level0;
+    if (nt <= 0) return;
+#define CHHS_TILE_CASE(NS, EPI, PRO)                                              \
+    if (ns == NS && epi == EPI && pro == PRO) {                                   \
+        launch_one<float, false, NS, EPI, PRO, true>(b, t, nt, partial, st);      \
+        return;                                                                   \
+    }
+    CHHS_TILE_CASE(1, 0, false)
+    CHHS_TILE_CASE(1, 0, true)
+    CHHS_TILE_CASE(1, 1, false)
+    CHHS_TILE_CASE(2, 0, false)
+    CHHS_TILE_CASE(2, 0, true)
+    CHHS_TILE_CASE(2, 1, false)
+#undef CHHS_TILE_CASE
+}
 
 }  // namespace chhs

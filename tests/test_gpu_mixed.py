@@ -1,0 +1,123 @@
+"""GPU tests of the mixed-precision path (FP32 correction-form V-cycles inside
+FP64 residual + correction + reductions, iterative refinement).
+
+The refined solution solves the FP64 system (2.5)-(2.7) to the same residual
+tolerance as the plain path, so it must agree with the FP64 oracle (and with the
+FP64 GPU path) to <= 1e-8 max-abs in phi at tol 1e-10, and it must reach
+residuals far below FP32 precision.
+"""
+import numpy as np
+import pytest
+
+from oracle import fas, grid, scheme
+from workloads import uniform_field
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def chhs():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_1611_02967_amd import chhs as binding
+    return binding
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def _pack(arrays):
+    return np.concatenate([a.ravel() for a in arrays])
+
+
+def _unpack(flat, shapes):
+    out, o = [], 0
+    for s in shapes:
+        n = int(np.prod(s))
+        out.append(flat[o:o + n].reshape(s))
+        o += n
+    return out
+
+
+def _steps(chhs, spec, phi0s, nsteps, **opts):
+    probs = [chhs.make_problem(sh, 1.0 / sh[-1], e, g, s) for sh, e, g, s in spec]
+    sv = chhs.Solver(probs, chhs.chhs_default_opts(**opts))
+    tp, tc = dev(_pack(phi0s)), dev(_pack(phi0s))
+    z = np.zeros(tp.numel())
+    tm, tpp = dev(z), dev(z)
+    hist = []
+    for _ in range(nsteps):
+        prev, cur, mu_in, p_in = host(tp), host(tc), host(tm), host(tpp)
+        _, st = sv.step(tp, tc, tm, tpp, 1)
+        hist.append(dict(prev=prev, cur=cur, mu_in=mu_in, p_in=p_in, phi=host(tc), mu=host(tm),
+                         p=host(tpp), stats=st))
+    return hist
+
+
+SPECS = {
+    "2d-64": [((64, 64), 0.05, 1.0, 1e-3)],
+    "2d-ragged": [((128, 128), 0.02, 1.0, 1e-4), ((96, 160), 0.03, 2.0, 5e-4),
+                  ((32, 32), 0.05, 3.0, 5e-4)],
+    "3d-16": [((16, 16, 16), 0.05, 2.0, 5e-4)],
+    "3d-ragged": [((32, 32, 32), 0.04, 2.0, 5e-4), ((16, 16, 32), 0.05, 1.0, 1e-3)],
+}
+
+
+@pytest.mark.parametrize("name", list(SPECS))
+def test_mixed_matches_fp64_oracle_per_step(chhs, name):
+    spec = SPECS[name]
+    shapes = [s[0] for s in spec]
+    phi0s = [uniform_field(sh, 4000 + i, mean=0.1, amp=0.05) for i, sh in enumerate(shapes)]
+    hist = _steps(chhs, spec, phi0s, 3, precision=1, tol=1e-10)
+    for h in hist:
+        prevs, curs = _unpack(h["prev"], shapes), _unpack(h["cur"], shapes)
+        mus_in, ps_in = _unpack(h["mu_in"], shapes), _unpack(h["p_in"], shapes)
+        phis = _unpack(h["phi"], shapes)
+        for i, (sh, e, g, s) in enumerate(spec):
+            assert h["stats"][i]["res_norm"] <= 1e-10
+            prm = scheme.Params(eps=e, gamma=g, s=s, h=1.0 / sh[-1])
+            r = fas.solve_step(prevs[i], curs[i], mus_in[i], ps_in[i], prm, fas.Opts(tol=1e-10))
+            assert np.max(np.abs(phis[i] - r.phi)) <= 1e-8, (name, i)
+
+
+@pytest.mark.parametrize("shape", [(256, 256), (64, 64, 64)])
+def test_mixed_matches_fp64_gpu_path(chhs, shape):
+    spec = [(shape, 0.02, 2.0, 5e-4)]
+    phi0s = [uniform_field(shape, 4100, mean=0.1, amp=0.05)]
+    a = _steps(chhs, spec, phi0s, 2, precision=1, tol=1e-10)
+    b = _steps(chhs, spec, phi0s, 2, precision=0, tol=1e-10)
+    for ha, hb in zip(a, b):
+        assert np.max(np.abs(ha["phi"] - hb["phi"])) <= 1e-8
+
+
+def test_refinement_reaches_below_fp32_precision(chhs):
+    """tol 1e-12 (well below FP32 roundoff of the O(1) fields): the FP64 outer
+    residual drives the error down, and the result is the oracle's to 1e-11."""
+    shape = (64, 64)
+    spec = [(shape, 0.05, 1.0, 1e-3)]
+    phi0 = uniform_field(shape, 4200, amp=0.05)
+    h = _steps(chhs, spec, [phi0], 1, precision=1, tol=1e-12)[0]
+    assert h["stats"][0]["res_norm"] <= 1e-12
+    prm = scheme.Params(eps=0.05, gamma=1.0, s=1e-3, h=1.0 / 64)
+    z = np.zeros(shape)
+    r = fas.solve_step(phi0, phi0, z, z, prm, fas.Opts(tol=1e-13))
+    assert np.max(np.abs(h["phi"].reshape(shape) - r.phi)) <= 1e-11
+    # mass: (phi^{m+1},1) - (phi^m,1) = -(R_phi,1) exactly, |.| <= ||R_phi||
+    assert abs(grid.mass(h["phi"].reshape(shape), prm.h) - grid.mass(phi0, prm.h)) <= 1e-12
+
+
+def test_mixed_graph_replay_equals_eager(chhs):
+    spec = SPECS["2d-ragged"]
+    shapes = [s[0] for s in spec]
+    phi0s = [uniform_field(sh, 4300 + i, mean=0.1, amp=0.05) for i, sh in enumerate(shapes)]
+    a = _steps(chhs, spec, phi0s, 2, precision=1, use_graph=1)
+    b = _steps(chhs, spec, phi0s, 2, precision=1, use_graph=0)
+    for ha, hb in zip(a, b):
+        for k in ("phi", "mu", "p"):
+            assert np.array_equal(ha[k], hb[k])
