@@ -27,23 +27,34 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def launch_bytes_per_cell(dim, cls, nu):
-    """Algorithmic bytes per fine cell of one finest-level launch of a kernel class.
+def launch_bytes_per_cell(dim, cls, mixed=False):
+    """Algorithmic bytes per finest cell of one finest-level launch of a kernel class.
 
-    FP64 (8 B per value).  On the finest level f_phi = phi^m and f_p = 0, so a
-    smoothing step must read phi, mu, p, phi_*, phi^m, f_mu and write phi, mu, p.
-    2D (one tiled launch per pre- and per post-smoothing group of nu steps):
-      pre0  : 6 reads + 3 writes, plus the restricted u_c, ub_c and R(r) on
-              the coarse grid (9 values per 4 fine cells)            = 90 B
-      post0 : 6 reads + 3 writes, plus the coarse u_c and ub_c read
-              for the prolonged correction (6 values per 4 cells)     = 84 B
-    3D (per-cell kernels, one launch per color): half of a smoothing step,
-      (6 reads + 3 writes) / 2                                        = 36 B
+    FP64 plain path (8 B per value).  On the finest level f_phi = phi^m and
+    f_p = 0, so a smoothing step reads phi, mu, p, phi_*, phi^m, f_mu and writes
+    phi, mu, p.
+      2D pre0  : one launch = nu1 fused steps + residual + restriction:
+                 6 reads + 3 writes, plus u_c, ub_c and R(r) written on the
+                 coarse grid (9 values per 4 fine cells)                    = 90 B
+      2D post0 : one launch = prolongation + nu2 fused steps + norm partials:
+                 6 reads + 3 writes, plus u_c, ub_c read (6 per 4 cells)    = 84 B
+      3D       : one launch = one color of one step: the other color's phi,
+                 mu, p, phi_* (4 values per 2 cells), the color's phi, phi_*,
+                 phi^m, f_phi, f_mu, f_p (6 per 2 cells) and its new phi, mu,
+                 p (3 per 2 cells)                                          = 52 B
+    Mixed precision, FP32 correction form (4 B per value; general right-hand
+    sides and the base state b on every level):
+      2D pre0  : 9 reads + 3 writes, plus u_c, ub_c, R(r), b_c (10 per 4)   = 58 B
+      2D post0 : 9 reads + 3 writes, plus u_c, ub_c read (6 per 4)          = 54 B
+      3D       : (4 + 7 + 3) values per 2 cells                             = 28 B
     """
-    w = 8
+    if mixed:
+        if dim == 2:
+            return {"pre0": (12 + 10 / 4) * 4, "post0": (12 + 6 / 4) * 4}[cls]
+        return (4 + 7 + 3) / 2 * 4
     if dim == 2:
-        return {"pre0": (9 + 9 / 4) * w, "post0": (9 + 6 / 4) * w}[cls]
-    return 9 * w / 2.0
+        return {"pre0": (9 + 9 / 4) * 8, "post0": (9 + 6 / 4) * 8}[cls]
+    return (4 + 6 + 3) / 2 * 8
 
 
 def cpu_model():
@@ -83,6 +94,107 @@ def oracle_sample(phi_prev, phi_cur, mu, p, w, cycles_per_step):
     return phi_cur.size / t_step, desc, t3 - t0
 
 
+def run_batched(args):
+    """64 independent 2D instances (16 each of 128^2, 256^2, 512^2, 1024^2, random
+    eps, gamma, s, mean) advanced together by the batched mixed-precision path
+    (FP32 inner V-cycles, FP64 residual and correction, graph replay), against
+    the plain FP64 path run as a sequential loop over single-instance contexts."""
+    import numpy as np
+    import torch
+    from paper_1611_02967_amd import chhs
+    from workloads import batched_instances
+
+    insts = batched_instances(count=64)
+    probs = [chhs.make_problem(it.shape, it.h, it.eps, it.gamma, it.s) for it in insts]
+    phi0s = [it.phi0() for it in insts]
+    sizes = [int(np.prod(it.shape)) for it in insts]
+    cells = sum(sizes)
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    log(f"batched: {len(insts)} instances, {cells} cells")
+
+    flat = np.concatenate([a.ravel() for a in phi0s])
+    tp = torch.from_numpy(flat).cuda()
+    tc = tp.clone()
+    tm = torch.zeros_like(tp)
+    tpp = torch.zeros_like(tp)
+    sv = chhs.Solver(probs, chhs.chhs_default_opts(tol=1e-10, precision=1, timing=1,
+                                                   smoother=args.smoother))
+    for k in range(args.warmup):
+        _, st = sv.step(tp, tc, tm, tpp, 1)
+        log(f"warmup step {k + 1}/{args.warmup}: max {max(x['vcycles'] for x in st)} refinement steps")
+    start = [t.clone() for t in (tp, tc, tm, tpp)]
+    sv.timing(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, st = sv.step(tp, tc, tm, tpp, args.steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    tim = sv.timing()
+    refine = sum(x["total_vcycles"] for x in st)
+    log(f"batched mixed: {args.steps} steps in {elapsed:.3f}s, {refine} instance refinement steps")
+
+    # sequential plain FP64: one context per instance, one step each in turn
+    seq = []
+    for i, pr in enumerate(probs):
+        o = chhs.chhs_default_opts(tol=1e-10, precision=0, smoother=args.smoother)
+        seq.append(chhs.Solver(pr, o))
+    views = lambda ts, i: [t[offs[i]:offs[i + 1]] for t in ts]
+    sp = [t.clone() for t in start]
+    for i, s1 in enumerate(seq):       # warm-up: one step each (graph capture)
+        s1.step(*[v.clone() for v in views(sp, i)], 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        for i, s1 in enumerate(seq):
+            s1.step(*views(sp, i), 1)
+    torch.cuda.synchronize()
+    elapsed_seq = time.perf_counter() - t0
+    log(f"sequential fp64: {args.steps} rounds in {elapsed_seq:.3f}s")
+
+    # error of the batched mixed step against the FP64 path from the same state
+    a = [t.clone() for t in start]
+    sv.step(*a, 1)
+    err = 0.0
+    for i, s1 in enumerate(seq):
+        b = [v.clone() for v in views(start, i)]
+        s1.step(*b, 1)
+        err = max(err, float((a[1][offs[i]:offs[i + 1]] - b[1]).abs().max()))
+    log(f"max |phi_mixed - phi_fp64| over instances after one step: {err:.2e}")
+
+    cls = max(("pre0", "post0"), key=lambda k: tim[k][0])
+    ms_k, n_k = tim[cls]
+    avg = ms_k / 1e3 / max(1, n_k)
+    b_launch = launch_bytes_per_cell(2, cls, mixed=True) * cells
+    achieved = b_launch / avg / 1e9 if n_k else 0.0
+    inst_steps = len(insts) * args.steps
+    out = {
+        "metric": METRIC,
+        "value": cells * args.steps / elapsed,
+        "unit": "cell-updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "batched-64-2d-mixed", "instances": len(insts),
+                   "grids": [128, 256, 512, 1024], "cells": cells, "tol": 1e-10,
+                   "cycle": "V(2,2)", "precision": "fp32 inner + fp64 refinement"},
+        "instance_steps_per_s": inst_steps / elapsed,
+        "refinement_steps": refine,
+        "sequential_fp64": {"instance_steps_per_s": inst_steps / elapsed_seq,
+                            "cell_updates_per_s": cells * args.steps / elapsed_seq,
+                            "ms_per_round": elapsed_seq / args.steps * 1e3},
+        "speedup_vs_sequential_fp64": elapsed_seq / elapsed,
+        "max_abs_err_phi_vs_fp64": err,
+        "kernel_ms": {k: round(v[0], 3) for k, v in tim.items() if v[1]},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": f"finest-level FP32 {'pre' if cls == 'pre0' else 'post'}-smoothing launch over the batch",
+                     "avg_launch_us": round(avg * 1e6, 2), "launches": n_k,
+                     "algorithmic_bytes_per_launch": b_launch},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,6 +203,8 @@ def main():
     ap.add_argument("--workload", default="2d-2048-fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--smoother", type=int, default=0,
+                    help="2D smoother: 0 default (strips on the finest level), 1 tiles, 2 strips")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -109,6 +223,9 @@ def main():
     from workloads import WORKLOADS, uniform_field
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    if args.workload == "batched-64-2d-mixed":
+        run_batched(args)
+        return
     w = WORKLOADS[args.workload]
     n, dim = w["n"], w["dim"]
     shape = (n,) * dim
@@ -117,7 +234,9 @@ def main():
 
     phi0 = uniform_field(shape, w["seed"], mean=w["mean"], amp=0.05)
     prob = chhs.make_problem(shape, 1.0 / n, w["eps"], w["gamma"], w["s"])
-    opts = chhs.chhs_default_opts(tol=1e-10, timing=1)
+    mixed = args.workload.endswith("-mixed")
+    opts = chhs.chhs_default_opts(tol=1e-10, timing=1, smoother=args.smoother,
+                                  precision=1 if mixed else 0)
     sv = chhs.Solver(prob, opts)
     tp = torch.from_numpy(phi0).cuda()
     tc = tp.clone()
@@ -146,7 +265,7 @@ def main():
     cls = max(("pre0", "post0"), key=lambda k: tim[k][0])
     ms_k, n_k = tim[cls]
     avg_launch_s = ms_k / 1e3 / max(1, n_k)
-    bytes_launch = launch_bytes_per_cell(dim, cls, 2) * cells
+    bytes_launch = launch_bytes_per_cell(dim, cls, mixed) * cells
     achieved = bytes_launch / avg_launch_s / 1e9 if n_k else 0.0
     names = {"pre0": "finest-level pre-smoothing launch" + (
                  " (2 fused red-black steps + residual + restriction)" if dim == 2 else " (one color)"),
@@ -159,7 +278,7 @@ def main():
     other = "post0" if cls == "pre0" else "pre0"
     if tim[other][1]:
         avg_o = tim[other][0] / 1e3 / tim[other][1]
-        b_o = launch_bytes_per_cell(dim, other, 2) * cells
+        b_o = launch_bytes_per_cell(dim, other, mixed) * cells
         roofline["other_kernel"] = {"kernel": names[other], "avg_launch_us": round(avg_o * 1e6, 2),
                                     "achieved": round(b_o / avg_o / 1e9, 1),
                                     "algorithmic_bytes_per_launch": b_o}
@@ -176,11 +295,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32+f64" if mixed else "f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "grid": list(shape), "eps": w["eps"],
                    "gamma": w["gamma"], "s": w["s"], "tol": 1e-10, "cycle": "V(2,2)",
-                   "precision": "fp64"},
+                   "precision": "fp32 inner + fp64 refinement" if mixed else "fp64"},
         "vcycles_per_s": vcyc / elapsed,
         "steps_per_s": args.steps / elapsed,
         "vcycles_per_step": vcyc / args.steps,
@@ -192,14 +311,14 @@ def main():
     if not args.no_parity:
         # parity of the same workload at a size the oracle solves in seconds
         from oracle import fas, scheme
-        m = 128
+        m = 128 if dim == 2 else 32
         sm = (m,) * dim
         prm = scheme.Params(eps=w["eps"], gamma=w["gamma"], s=w["s"], h=1.0 / m)
         ph0 = uniform_field(sm, w["seed"], mean=w["mean"], amp=0.05)
         z = np.zeros(sm)
         ref = fas.solve_step(ph0, ph0, z, z, prm, fas.Opts(tol=1e-10))
         sv2 = chhs.Solver(chhs.make_problem(sm, prm.h, prm.eps, prm.gamma, prm.s),
-                          chhs.chhs_default_opts(tol=1e-10))
+                          chhs.chhs_default_opts(tol=1e-10, precision=1 if mixed else 0))
         a = torch.from_numpy(ph0).cuda()
         b = a.clone()
         zm, zp = torch.zeros_like(a), torch.zeros_like(a)

@@ -68,14 +68,21 @@ typedef struct chhs_problem {
  * precision 0 = FP64 throughout, 1 = FP32 smoothing/transfer inside FP64
  * residual + correction (iterative refinement), use_graph = 1 (default) replays each
  * V-cycle as a captured HIP graph, timing = 1 brackets every launch of the
- * timed kernel classes with HIP events (see chhs_get_timing). */
+ * timed kernel classes with HIP events (see chhs_get_timing).  smoother selects
+ * the 2D smoothing kernels of the levels above the single-workgroup tail:
+ * 0 = default (row-streaming strips on the finest level, square LDS tiles on
+ * coarser ones), 1 = tiles everywhere, 2 = strips on every level (including
+ * the explicit smoothing calls on tail levels).  Both
+ * kernels perform the same red-black updates in the same arithmetic.
+ * reserved must be zero. */
 typedef struct chhs_opts {
     int32_t nu1, nu2, max_vcycles, coarse_sweeps;
     double tol;
     int32_t precision;
     int32_t use_graph;
     int32_t timing;
-    int32_t reserved[5];
+    int32_t smoother;
+    int32_t reserved[4];
 } chhs_opts;
 
 /* Kernel classes of chhs_timing. */

@@ -18,7 +18,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libchhs.so")
 ARCH = "gfx950"
 
-SOURCES = ["chhs_api.hip", "chhs_kernels.hip", "chhs_tile2d.hip", "chhs_tail.hip"]
+SOURCES = ["chhs_api.hip", "chhs_kernels.hip", "chhs_tile2d.hip", "chhs_stream2d.hip",
+           "chhs_tail.hip"]
 
 # -packed-fp32-ops: keep the compiler from forming packed FP32 instructions
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
@@ -33,13 +34,15 @@ def hipcc():
     raise RuntimeError("hipcc not found: the HIP library cannot be built")
 
 
-def build(verbose=False):
-    """Compile every source and link libchhs.so; raises on any compiler error."""
+def build(verbose=False, out=None, defines=()):
+    """Compile every source and link libchhs.so (or ``out``, with extra -D
+    ``defines`` for kernel variants); raises on any compiler error."""
     cc = hipcc()
+    target = out or LIB
     with tempfile.TemporaryDirectory(prefix="chhs_build_") as tmp:
         def compile_one(src):
             obj = os.path.join(tmp, os.path.splitext(src)[0] + ".o")
-            cmd = [cc, *COMMON, "-c", os.path.join(CSRC, src), "-o", obj]
+            cmd = [cc, *COMMON, *[f"-D{d}" for d in defines], "-c", os.path.join(CSRC, src), "-o", obj]
             if verbose:
                 print(" ".join(cmd), flush=True)
             r = subprocess.run(cmd, capture_output=True, text=True)
@@ -53,9 +56,9 @@ def build(verbose=False):
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
-        shutil.copyfile(out_tmp, LIB + ".tmp")
-        os.replace(LIB + ".tmp", LIB)
-    return LIB
+        shutil.copyfile(out_tmp, target + ".tmp")
+        os.replace(target + ".tmp", target)
+    return target
 
 
 if __name__ == "__main__":

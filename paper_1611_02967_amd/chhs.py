@@ -13,7 +13,8 @@ import os
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libchhs.so")
+# CHHS_LIBRARY selects another build of the same library (kernel variants).
+LIB_PATH = os.environ.get("CHHS_LIBRARY") or os.path.join(HERE, "libchhs.so")
 
 CHHS_OK = 0
 CHHS_E_INVAL = -1
@@ -35,7 +36,7 @@ class chhs_opts(ctypes.Structure):
                 ("max_vcycles", ctypes.c_int32), ("coarse_sweeps", ctypes.c_int32),
                 ("tol", ctypes.c_double), ("precision", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("timing", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 5)]
+                ("smoother", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
 
 
 K_CLASSES = ["pre0", "post0", "transfer0", "coarse", "norm", "setup", "k6", "k7"]

@@ -22,6 +22,7 @@ using chhs::InstInfo;
 using chhs::Level;
 using chhs::LevelDesc;
 using chhs::Range;
+using chhs::StripTask;
 using chhs::TileTask;
 using chhs::kMaxLevels;
 
@@ -45,6 +46,8 @@ struct Layout {
     std::vector<InstInfo> info;
     std::vector<std::vector<CellTask>> A, B, Bc;
     std::vector<std::vector<TileTask>> T, Tall;
+    std::vector<std::vector<StripTask>> S, Sall;
+    bool strip[kMaxLevels] = {};            // level smoothed by the row-streaming kernel
     std::vector<int> tail_insts;
     std::vector<CellTask> A0n;              // finest-level cells of instances without a fused norm
     std::vector<Range> rngA0, rngT0, rngA0n;
@@ -56,7 +59,7 @@ struct Layout {
     size_t off_A0n = 0, off_partial_t = 0;
     size_t off_partial = 0, off_res = 0, off_eres = 0, off_act_cycle = 0, off_act_next = 0,
            off_cycles = 0;
-    std::vector<size_t> off_A, off_B, off_Bc, off_T, off_Tall;
+    std::vector<size_t> off_A, off_B, off_Bc, off_T, off_Tall, off_S, off_Sall;
     int partial_cap = 0, partial_t_cap = 0;
 };
 
@@ -77,6 +80,7 @@ struct chhs_ctx {
     InstInfo* dinfo = nullptr;
     Table<CellTask> A[kMaxLevels], B[kMaxLevels], Bc[kMaxLevels];
     Table<TileTask> T[kMaxLevels], Tall[kMaxLevels];
+    Table<StripTask> S[kMaxLevels], Sall[kMaxLevels];
     Table<CellTask> A0n;
     int* tail_insts = nullptr;
     Range* rngA0 = nullptr;
@@ -136,6 +140,7 @@ bool valid_opts(const chhs_opts* o) {
     if (o->max_vcycles < 1 || o->coarse_sweeps < 1) return false;
     if (!(o->tol > 0.0) || !std::isfinite(o->tol)) return false;
     if (o->precision != 0 && o->precision != 1) return false;
+    if (o->smoother < 0 || o->smoother > 2) return false;
     return true;
 }
 
@@ -190,6 +195,42 @@ void tile_tasks(std::vector<TileTask>& out, int inst, int nx, int ny) {
         for (int bx = 0; bx < tx; ++bx) out.push_back({inst, bx, by});
 }
 
+// Strip tasks of one level over the instances listed (extents nx, ny, -1 =
+// skip): strips of kStripWO columns, segments of seg rows.
+void strip_tasks(std::vector<StripTask>& out, const std::vector<int>& nxs,
+                 const std::vector<int>& nys, int seg) {
+    for (size_t i = 0; i < nxs.size(); ++i) {
+        if (nxs[i] < 0) continue;
+        const int sxn = (nxs[i] + chhs::kStripWO - 1) / chhs::kStripWO;
+        for (int sx = 0; sx < sxn; ++sx)
+            for (int y0 = 0; y0 < nys[i]; y0 += seg)
+                out.push_back({int(i), sx, y0, std::min(nys[i], y0 + seg)});
+    }
+}
+
+// Segment height (even, >= 8) for one launch over the listed instances: the
+// smallest that keeps the tasks within one wave of `slots` resident blocks,
+// as short as possible otherwise (shorter segments mean more blocks in
+// flight, taller ones fewer recomputed halo rows).
+int strip_seg(const std::vector<int>& nxs, const std::vector<int>& nys, int slots) {
+    int maxny = 8;
+    for (size_t i = 0; i < nys.size(); ++i)
+        if (nxs[i] >= 0) maxny = std::max(maxny, nys[i]);
+    for (int seg = 8;; seg += 2) {
+        long tasks = 0;
+        for (size_t i = 0; i < nxs.size(); ++i) {
+            if (nxs[i] < 0) continue;
+            tasks += long((nxs[i] + chhs::kStripWO - 1) / chhs::kStripWO) *
+                     ((nys[i] + seg - 1) / seg);
+        }
+        if (tasks <= slots || seg >= maxny) return seg;
+    }
+}
+
+// Resident blocks of the row-streaming kernel across the device (256 compute
+// units): two per unit when its LDS ring fits twice, else one.
+int strip_slots(bool finest_fp64, bool mixed) { return (finest_fp64 || mixed) ? 512 : 256; }
+
 void ranges_of(std::vector<Range>& r, int n_inst, const std::vector<CellTask>& t) {
     r.assign(n_inst, Range{0, 0});
     for (int q = 0; q < int(t.size()); ++q) {
@@ -209,6 +250,12 @@ bool plan(const chhs_problem* p, int n_inst, const chhs_opts* o, char* base, Lay
     L.Bc.resize(kMaxLevels);
     L.T.resize(kMaxLevels);
     L.Tall.resize(kMaxLevels);
+    L.S.resize(kMaxLevels);
+    L.Sall.resize(kMaxLevels);
+    // level extents per instance (-1: no such level) for the strip planner
+    std::vector<std::vector<int>> lnx(kMaxLevels, std::vector<int>(n_inst, -1));
+    std::vector<std::vector<int>> lny(kMaxLevels, std::vector<int>(n_inst, -1));
+    std::vector<std::vector<int>> lnx_t(kMaxLevels, std::vector<int>(n_inst, -1));
     L.desc.assign(size_t(n_inst) * kMaxLevels, LevelDesc<double>{});
     if (mixed) L.desc32.assign(size_t(n_inst) * kMaxLevels, LevelDesc<float>{});
     size_t off = 0;
@@ -299,22 +346,44 @@ bool plan(const chhs_problem* p, int n_inst, const chhs_opts* o, char* base, Lay
             if (l < tail) cell_tasks(L.B[l], i, n);
             if (dim == 2) tile_tasks(L.Tall[l], i, d.nx, d.ny);
             if (dim == 2 && l < tail) tile_tasks(L.T[l], i, d.nx, d.ny);
+            lnx[l][i] = d.nx;
+            lny[l][i] = d.ny;
+            if (l < tail) lnx_t[l][i] = d.nx;
         }
         for (int l = 0; l + 1 < nlev && l < tail; ++l) cell_tasks(L.Bc[l], i, cells[l + 1]);
         if (!in.fused) cell_tasks(L.A0n, i, cells[0]);
         L.tail_insts.push_back(i);
     }
+    // 2D smoother per level: row-streaming strips or square tiles (the same
+    // choice for the FP64 and the FP32 hierarchy)
+    if (dim == 2)
+        for (int l = 0; l < kMaxLevels; ++l) {
+            const int slots = strip_slots(l == 0 && !mixed, mixed);
+            strip_tasks(L.Sall[l], lnx[l], lny[l], strip_seg(lnx[l], lny[l], slots));
+            strip_tasks(L.S[l], lnx_t[l], lny[l], strip_seg(lnx_t[l], lny[l], slots));
+            // default: strips on the finest level (long segments, two blocks
+            // per compute unit), tiles below, where more and shorter blocks
+            // hide latency better
+            L.strip[l] = o->smoother == 2 ? !L.Sall[l].empty()
+                                          : (o->smoother == 0 && l == 0 && !L.T[l].empty());
+        }
     // per-instance ranges of the finest-level partial buffers
     ranges_of(L.rngA0, n_inst, L.A[0]);
     ranges_of(L.rngA0n, n_inst, L.A0n);
     L.rngT0.assign(n_inst, Range{0, 0});
-    for (int q = 0; q < int(L.T[0].size()); ++q) {
-        Range& r = L.rngT0[L.T[0][q].inst];
-        if (r.end == 0) r.begin = q;
-        r.end = q + 1;
-    }
+    auto fused_ranges = [&](const auto& tasks) {
+        for (int q = 0; q < int(tasks.size()); ++q) {
+            Range& r = L.rngT0[tasks[q].inst];
+            if (r.end == 0) r.begin = q;
+            r.end = q + 1;
+        }
+    };
+    if (L.strip[0])
+        fused_ranges(L.S[0]);
+    else
+        fused_ranges(L.T[0]);
     L.partial_cap = int(L.A[0].size());
-    L.partial_t_cap = int(std::max<size_t>(1, L.T[0].size()));
+    L.partial_t_cap = int(std::max<size_t>(1, std::max(L.T[0].size(), L.S[0].size())));
     L.off_desc = take(L.desc.size() * sizeof(LevelDesc<double>));
     L.off_desc32 = take(std::max<size_t>(1, L.desc32.size()) * sizeof(LevelDesc<float>));
     L.off_info = take(L.info.size() * sizeof(InstInfo));
@@ -329,6 +398,8 @@ bool plan(const chhs_problem* p, int n_inst, const chhs_opts* o, char* base, Lay
         L.off_Bc.push_back(take(L.Bc[l].size() * sizeof(CellTask)));
         L.off_T.push_back(take(L.T[l].size() * sizeof(TileTask)));
         L.off_Tall.push_back(take(L.Tall[l].size() * sizeof(TileTask)));
+        L.off_S.push_back(take(L.S[l].size() * sizeof(StripTask)));
+        L.off_Sall.push_back(take(L.Sall[l].size() * sizeof(StripTask)));
     }
     L.off_partial = take(size_t(L.partial_cap) * chhs::kPartialStride * sizeof(double));
     L.off_partial_t = take(size_t(L.partial_t_cap) * chhs::kPartialStride * sizeof(double));
@@ -454,15 +525,24 @@ struct Hier {
 Hier<double> hier64(chhs_ctx* c) { return {c->ddesc, &c->lay.desc, c->cur, c->lay.tail_lds}; }
 Hier<float> hier32(chhs_ctx* c) { return {c->ddesc32, &c->lay.desc32, c->cur32, c->lay.tail_lds32}; }
 
-// One tiled launch on level l; flips the level's current copy.
+// One 2D smoothing launch on level l (row-streaming strips or tiles, as
+// planned; all = every instance, else those whose tail starts below l);
+// flips the level's current copy.
 template <typename T>
-void tiled(chhs_ctx* c, const Hier<T>& H, const Table<TileTask>& tt, int l, int ns, int epi,
-           bool pro, const int* active, int cls) {
+void tiled(chhs_ctx* c, const Hier<T>& H, bool all, int l, int ns, int epi, bool pro,
+           const int* active, int cls) {
     Batch<T> b = make_batch(H.dev, H.cur, l, active);
+    const bool level0 = std::is_same<T, double>::value && l == 0;
+    double* part = epi == 2 ? c->partial_t : nullptr;
     {
         TimedScope t(c, cls);
-        chhs::launch_tile2d<T>(b, tt.dev, tt.n, std::is_same<T, double>::value && l == 0, ns, epi,
-                               pro, epi == 2 ? c->partial_t : nullptr, c->stream);
+        if (c->lay.strip[l]) {
+            const Table<StripTask>& st = all ? c->Sall[l] : c->S[l];
+            chhs::launch_stream2d<T>(b, st.dev, st.n, level0, ns, epi, pro, part, c->stream);
+        } else {
+            const Table<TileTask>& tt = all ? c->Tall[l] : c->T[l];
+            chhs::launch_tile2d<T>(b, tt.dev, tt.n, level0, ns, epi, pro, part, c->stream);
+        }
     }
     H.cur[l] ^= 1;
 }
@@ -488,7 +568,7 @@ void smooth_steps(chhs_ctx* c, int l, int nsweeps, const int* active, int cls) {
         while (nsweeps > 0) {
             const int k = nsweeps >= 2 ? 2 : 1;
             nsweeps -= k;
-            tiled(c, hier64(c), c->Tall[l], l, k, 0, false, active, cls);
+            tiled(c, hier64(c), true, l, k, 0, false, active, cls);
         }
         return;
     }
@@ -516,10 +596,10 @@ void enqueue_vcycle(chhs_ctx* c, const Hier<T>& H) {
         if (dim == 2 && o.nu1 > 0) {
             int rem = o.nu1;
             while (rem > 2) {
-                tiled(c, H, c->T[d], d, 2, 0, false, act, pre_cls);
+                tiled(c, H, false, d, 2, 0, false, act, pre_cls);
                 rem -= 2;
             }
-            tiled(c, H, c->T[d], d, rem, 1, false, act, pre_cls);
+            tiled(c, H, false, d, rem, 1, false, act, pre_cls);
         } else {
             if (dim == 3)
                 for (int s = 0; s < o.nu1; ++s)
@@ -553,7 +633,7 @@ void enqueue_vcycle(chhs_ctx* c, const Hier<T>& H) {
                 const int k = rem >= 2 ? 2 : 1;
                 rem -= k;
                 const bool norm = kPlain && d == 0 && rem == 0 && c->fused_norm;
-                tiled(c, H, c->T[d], d, k, norm ? 2 : 0, first, act, post_cls);
+                tiled(c, H, false, d, k, norm ? 2 : 0, first, act, post_cls);
                 first = false;
             }
         } else {
@@ -848,6 +928,8 @@ int chhs_init(const chhs_problem* p, int32_t n_inst, const chhs_opts* o, void* w
         rc |= upload(c->Bc[l], b, L.off_Bc[l], L.Bc[l], st);
         rc |= upload(c->T[l], b, L.off_T[l], L.T[l], st);
         rc |= upload(c->Tall[l], b, L.off_Tall[l], L.Tall[l], st);
+        rc |= upload(c->S[l], b, L.off_S[l], L.S[l], st);
+        rc |= upload(c->Sall[l], b, L.off_Sall[l], L.Sall[l], st);
     }
     rc |= upload(c->A0n, b, L.off_A0n, L.A0n, st);
     if (rc) return fail(CHHS_E_HIP);

@@ -16,6 +16,24 @@
 
 namespace chhs {
 
+// Global-memory access through pointers read from device-side descriptors.
+// Without the address-space cast they would be flat accesses, which the
+// hardware counts together with LDS accesses, so that every wait for an LDS
+// read would also wait for outstanding global loads and stores.  The element
+// index becomes a 32-bit unsigned byte offset (every field is below 4 GiB), so
+// that a wave-uniform base stays in scalar registers and the address is one
+// 32-bit vector register.
+template <typename T>
+__device__ __forceinline__ T gload(const T* p, int i) {
+    const unsigned off = unsigned(i) * unsigned(sizeof(T));
+    return *(const __attribute__((address_space(1))) T*)((const __attribute__((address_space(1))) char*)p + off);
+}
+template <typename T>
+__device__ __forceinline__ void gstore(T* p, int i, T v) {
+    const unsigned off = unsigned(i) * unsigned(sizeof(T));
+    *(__attribute__((address_space(1))) T*)((__attribute__((address_space(1))) char*)p + off) = v;
+}
+
 template <int DIM>
 __device__ __forceinline__ void decode(int idx, int nx, int ny, int& i, int& j, int& k) {
     i = idx % nx;

@@ -110,6 +110,7 @@ struct InstInfo {
 
 struct CellTask { int inst; int cell0; };      // kBlock consecutive cells of one level
 struct TileTask { int inst; int bx; int by; }; // one tile of a 2D level
+struct StripTask { int inst; int sx; int y0; int y1; };   // rows [y0, y1) of strip sx
 struct Range { int begin; int end; };          // an instance's blocks in a partial buffer
 
 // Arguments common to every batched launch.
@@ -192,8 +193,11 @@ void launch_fill_int(int* dst, int n, int value, hipStream_t st);
 void launch_copy_int(int* dst, const int* src, int n, hipStream_t st);
 
 // ---- tiled 2D smoothing (chhs_tile2d.hip) ------------------------------------------
+#ifndef CHHS_TILE_Y
+#define CHHS_TILE_Y 16
+#endif
 constexpr int kTileX = 64;
-constexpr int kTileY = 16;
+constexpr int kTileY = CHHS_TILE_Y;
 // ns fused smoothing steps on level b.level of every tasked instance, read from
 // copy b.cur and written to the other copy; epi 0 none, 1 residual + restriction
 // into level + 1 (copy b.cur_c), 2 residual-norm partials (4 per block, in task
@@ -202,6 +206,17 @@ constexpr int kTileY = 16;
 template <typename T>
 void launch_tile2d(const Batch<T>& b, const TileTask* t, int nt, bool level0, int ns, int epi,
                    bool pro, double* partial, hipStream_t st);
+
+// ---- row-streaming 2D smoothing (chhs_stream2d.hip) ---------------------------------
+// Strip sx owns columns [sx kStripWO, (sx + 1) kStripWO) and stages kStripW
+// columns from sx kStripWO - kStripHX.  Segments start at even rows.
+constexpr int kStripW = 128;
+constexpr int kStripHX = 6;
+constexpr int kStripWO = kStripW - 2 * kStripHX;
+// Same contract as launch_tile2d over strip tasks; partial gets 4 sums per task.
+template <typename T>
+void launch_stream2d(const Batch<T>& b, const StripTask* t, int nt, bool level0, int ns, int epi,
+                     bool pro, double* partial, hipStream_t st);
 
 // ---- single-workgroup coarse tail (chhs_tail.hip) ----------------------------------
 size_t tail_lds_bytes(const int* cells, int nlev, size_t elem, int nfields);

@@ -1,0 +1,135 @@
+"""GPU tests of the row-streaming 2D smoother against the tiled one and the oracle.
+
+Both kernels perform the same ordered red-black collective updates, so their
+iterates agree to rounding; smoothing steps on every kind of level (finest,
+coarse with general right-hand sides, odd tail extents) and whole steps are
+compared with the oracle as well.
+"""
+import numpy as np
+import pytest
+
+from oracle import fas, scheme
+from workloads import uniform_field
+
+pytestmark = pytest.mark.gpu
+
+TILES, STRIPS_ALL = 1, 2
+
+
+@pytest.fixture(scope="module")
+def chhs():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_1611_02967_amd import chhs as binding
+    return binding
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def _inputs(shape, seed):
+    prev = uniform_field(shape, seed, amp=0.6)
+    cur = prev + uniform_field(shape, seed + 1, amp=0.1)
+    mu0 = uniform_field(shape, seed + 2, amp=0.3)
+    p0 = uniform_field(shape, seed + 3, amp=0.01)
+    return prev, cur, mu0, p0
+
+
+def _prm(shape, eps=0.05, gamma=2.0, s=1e-3):
+    return scheme.Params(eps=eps, gamma=gamma, s=s, h=1.0 / shape[-1])
+
+
+def _solver(chhs, shape, prm, **opts):
+    prob = chhs.make_problem(shape, prm.h, prm.eps, prm.gamma, prm.s)
+    return chhs.Solver(prob, chhs.chhs_default_opts(**opts))
+
+
+# (ny, nx): several strips with a ragged last one (320 = 2 x 116 + 88), a single
+# narrow strip, segments ending inside the grid, odd coarse extents
+SHAPES = [(64, 64), (48, 40), (192, 320), (96, 160), (512, 256), (40, 24)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("level", [0, 1, 2])
+@pytest.mark.parametrize("nsweeps", [1, 2, 3])
+def test_strip_smoothing_matches_oracle_and_tiles(chhs, shape, level, nsweeps):
+    prm = _prm(shape)
+    prev, cur, mu0, p0 = _inputs(shape, 500 + level)
+    out = {}
+    for mode in (TILES, STRIPS_ALL):
+        sv = _solver(chhs, shape, prm, smoother=mode)
+        sv.setup_step(dev(prev), dev(cur), dev(mu0), dev(p0))
+        nyl, nxl = (n >> level for n in shape)
+        if level > 0:
+            u = [uniform_field((nyl, nxl), 510 + k, amp=0.5) for k in range(3)]
+            f = [uniform_field((nyl, nxl), 520 + k, amp=0.5) for k in range(3)]
+            for name, val in zip(("phi", "mu", "p", "f_phi", "f_mu", "f_p"), u + f):
+                sv.write_field(level, name, dev(val))
+        sv.smooth(level, nsweeps)
+        out[mode] = [host(sv.read_field(level, n)) for n in ("phi", "mu", "p")]
+        if level > 0:
+            lvl = scheme.Level(h=prm.h * 2 ** level, phi_star=host(sv.read_field(level, "phi_star")),
+                               psi=host(sv.read_field(level, "psi")), f=f)
+        else:
+            phi_star, f0 = scheme.step_rhs(prev, cur, prm)
+            lvl = scheme.Level(h=prm.h, phi_star=phi_star, psi=cur.copy(), f=f0)
+            u = [cur.copy(), mu0.copy(), p0 - p0.mean()]
+    for _ in range(nsweeps):
+        fas.sweep(u, lvl, prm)
+    for k, want in enumerate(u):
+        scale = max(1.0, np.max(np.abs(want)))
+        assert np.max(np.abs(out[STRIPS_ALL][k] - want)) <= 1e-11 * scale, k
+        assert np.max(np.abs(out[STRIPS_ALL][k] - out[TILES][k])) <= 1e-13 * scale, k
+
+
+def _steps(chhs, shape, prm, phi0, nsteps, **opts):
+    sv = _solver(chhs, shape, prm, **opts)
+    tp, tc = dev(phi0), dev(phi0)
+    tm, tpp = dev(np.zeros(shape)), dev(np.zeros(shape))
+    hist = []
+    for _ in range(nsteps):
+        prev, cur = host(tp), host(tc)
+        mu_in, p_in = host(tm), host(tpp)
+        _, st = sv.step(tp, tc, tm, tpp, 1)
+        hist.append(dict(prev=prev, cur=cur, mu_in=mu_in, p_in=p_in, phi=host(tc),
+                         vcycles=st[0]["vcycles"]))
+    return hist
+
+
+@pytest.mark.parametrize("shape", [(256, 256), (192, 320)])
+def test_steps_with_strips_match_tiles_and_oracle(chhs, shape):
+    prm = _prm(shape, eps=0.02, gamma=1.5, s=5e-4)
+    phi0 = uniform_field(shape, 530, mean=0.1, amp=0.05)
+    a = _steps(chhs, shape, prm, phi0, 2, smoother=0)
+    b = _steps(chhs, shape, prm, phi0, 2, smoother=TILES)
+    for ha, hb in zip(a, b):
+        assert np.max(np.abs(ha["phi"] - hb["phi"])) <= 1e-11
+    for h in a:
+        r = fas.solve_step(h["prev"], h["cur"], h["mu_in"], h["p_in"], prm, fas.Opts(tol=1e-10))
+        assert np.max(np.abs(h["phi"] - r.phi)) <= 1e-10
+        assert h["vcycles"] == r.vcycles
+
+
+def test_full_size_vcycle_strips_match_tiles(chhs):
+    """2048^2 (18 strips, segments sized to fill the device): one V-cycle from
+    the same state through either smoother."""
+    shape = (2048, 2048)
+    prm = _prm(shape, eps=0.01, gamma=1.0, s=1e-4)
+    phi0 = uniform_field(shape, 540, amp=0.05)
+    z = np.zeros(shape)
+    res = {}
+    for mode in (0, TILES):
+        sv = _solver(chhs, shape, prm, smoother=mode)
+        sv.setup_step(dev(phi0), dev(phi0), dev(z), dev(z))
+        r = sv.fas_vcycle()
+        res[mode] = (r, [host(sv.read_field(0, n)) for n in ("phi", "mu", "p")])
+    assert abs(res[0][0][0] - res[TILES][0][0]) <= 1e-6 * res[TILES][0][0]
+    for k in range(3):
+        d = np.max(np.abs(res[0][1][k] - res[TILES][1][k]))
+        assert d <= 1e-12 * max(1.0, np.max(np.abs(res[TILES][1][k]))), k
