@@ -67,8 +67,10 @@ typedef struct chhs_problem {
  * max_vcycles = 100, coarse_sweeps = 4 (smoothing steps on the coarsest grid),
  * precision 0 = FP64 throughout, 1 = FP32 smoothing/transfer inside FP64
  * residual + correction (iterative refinement), use_graph = 1 (default) replays each
- * V-cycle as a captured HIP graph, timing = 1 brackets every launch of the
- * timed kernel classes with HIP events (see chhs_get_timing).  smoother selects
+ * V-cycle as a captured HIP graph, timing = 1 brackets every launch of every
+ * kernel class with HIP events (see chhs_get_timing); any other nonzero value
+ * is a mask of classes, bit (class + 1) set for each class to time.  Each
+ * event pair delays the next launch by a few microseconds.  smoother selects
  * the 2D smoothing kernels of the levels above the single-workgroup tail:
  * 0 = default (row-streaming strips on the finest level, square LDS tiles on
  * coarser ones), 1 = tiles everywhere, 2 = strips on every level (including

@@ -42,6 +42,14 @@ class chhs_opts(ctypes.Structure):
 K_CLASSES = ["pre0", "post0", "transfer0", "coarse", "norm", "setup", "k6", "k7"]
 
 
+def timing_mask(*classes):
+    """opts.timing value that times only the named kernel classes."""
+    m = 0
+    for c in classes:
+        m |= 1 << (K_CLASSES.index(c) + 1)
+    return m
+
+
 class chhs_timing(ctypes.Structure):
     _fields_ = [("ms", ctypes.c_double * 8), ("launches", ctypes.c_int64 * 8)]
 

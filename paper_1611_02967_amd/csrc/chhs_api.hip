@@ -228,8 +228,9 @@ int strip_seg(const std::vector<int>& nxs, const std::vector<int>& nys, int slot
 }
 
 // Resident blocks of the row-streaming kernel across the device (256 compute
-// units): two per unit when its LDS ring fits twice, else one.
-int strip_slots(bool finest_fp64, bool mixed) { return (finest_fp64 || mixed) ? 512 : 256; }
+// units): three per unit for the finest FP64 variant (LDS ring and registers
+// both allow it), four for the FP32 ones, two otherwise.
+int strip_slots(bool finest_fp64, bool mixed) { return mixed ? 1024 : (finest_fp64 ? 768 : 512); }
 
 void ranges_of(std::vector<Range>& r, int n_inst, const std::vector<CellTask>& t) {
     r.assign(n_inst, Range{0, 0});
@@ -364,8 +365,12 @@ bool plan(const chhs_problem* p, int n_inst, const chhs_opts* o, char* base, Lay
             // default: strips on the finest level (long segments, two blocks
             // per compute unit), tiles below, where more and shorter blocks
             // hide latency better
-            L.strip[l] = o->smoother == 2 ? !L.Sall[l].empty()
-                                          : (o->smoother == 0 && l == 0 && !L.T[l].empty());
+            // the strip kernel loads pairs of cells: every grid of the level
+            // needs an even x extent
+            bool even = true;
+            for (int i = 0; i < n_inst; ++i) even = even && (lnx[l][i] < 0 || lnx[l][i] % 2 == 0);
+            L.strip[l] = even && (o->smoother == 2 ? !L.Sall[l].empty()
+                                                   : (o->smoother == 0 && l == 0 && !L.T[l].empty()));
         }
     // per-instance ranges of the finest-level partial buffers
     ranges_of(L.rngA0, n_inst, L.A[0]);
@@ -442,18 +447,27 @@ hipEvent_t pooled_event(chhs_ctx* c) {
     return e;
 }
 
+// opts.timing: 1 times every class, any other nonzero value is a mask of
+// (1 << (class + 1)) bits.  Every event pair adds a few microseconds between
+// launches, so timing only the classes of interest keeps the schedule close to
+// the untimed one.
+bool timed(const chhs_ctx* c, int cls) {
+    const int t = c->opts.timing;
+    return t == 1 || (t != 0 && ((t >> (cls + 1)) & 1));
+}
+
 // Brackets the launches issued during its lifetime with a pair of events on
 // the context stream when timing is enabled (captured into the graph when a
 // cycle is being captured).
 class TimedScope {
   public:
     TimedScope(chhs_ctx* c, int cls) : c_(c), cls_(cls) {
-        if (!c_->opts.timing) return;
+        if (!timed(c_, cls_)) return;
         a_ = pooled_event(c_);
         if (a_) (void)hipEventRecord(a_, c_->stream);
     }
     ~TimedScope() {
-        if (!c_->opts.timing || a_ == nullptr) return;
+        if (!timed(c_, cls_) || a_ == nullptr) return;
         hipEvent_t b = pooled_event(c_);
         if (b == nullptr) return;
         (void)hipEventRecord(b, c_->stream);

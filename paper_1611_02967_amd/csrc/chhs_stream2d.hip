@@ -19,6 +19,12 @@
 // neighbouring segments, global loads are issued at least two rows ahead of
 // their use, and every wave reads consecutive LDS words.
 //
+// Only the fields that neighbours read (phi, mu, p, phi_*) live in the ring;
+// a cell's own data (phi^m and the right-hand sides) is loaded by the wave
+// that updates it, kU iterations ahead, as pairs of adjacent cells.  The ring
+// of 4 NS + 5 rows then takes 52 KB in FP64, so that three workgroups share
+// a compute unit.
+//
 // The kernel is out of place: it reads u = (phi, mu, p) from copy b.cur and
 // writes the owned cells into the other copy.
 //
@@ -36,35 +42,56 @@ namespace {
 constexpr int kW = kStripW;          // region columns: one pair per lane of a wave
 constexpr int kHalf = kW / 2;
 constexpr int kThreads = 256;        // four waves
-constexpr int kD = 2;                // rows per register bank of loads in flight
+constexpr int kD = 2;                // rows per register bank of ring loads in flight
+constexpr int kU = 2 * kD;           // iterations per loop body; own data is kU rows ahead
 
-// Field slots of the LDS ring.  On the finest level f_phi = phi^m (slot PSI)
-// and f_p = 0 are implied.
+// Ring fields (read by neighbours).
+constexpr int PHI = 0, MU = 1, P = 2, PS = 3, NRF = 4;
+
+// Own fields of a cell, in load order: the finest level has f_phi = phi^m and
+// f_p = 0 implied.
 template <bool LEVEL0, bool CORR>
-struct Slots {
-    static constexpr int PHI = 0, MU = 1, P = 2, PS = 3, PSI = 4, F1 = 5;
-    static constexpr int F0 = LEVEL0 ? PSI : 6;
-    static constexpr int F2 = LEVEL0 ? -1 : 7;
-    static constexpr int B = CORR ? (LEVEL0 ? 6 : 8) : -1;
-    static constexpr int N = 6 + (LEVEL0 ? 0 : 2) + (CORR ? 1 : 0);
+struct Own {
+    static constexpr int N = LEVEL0 ? 2 : (CORR ? 5 : 4);
+    // index of psi, f0, f1, f2, b in the load order (-1: implied)
+    static constexpr int PSI = 0;
+    static constexpr int F0 = LEVEL0 ? 0 : 1;
+    static constexpr int F1 = LEVEL0 ? 1 : 2;
+    static constexpr int F2 = LEVEL0 ? -1 : 3;
+    static constexpr int B = CORR ? 4 : -1;
 };
+
+template <typename T>
+struct Pair {
+    T a, b;
+};
+
+// Pair k (cells 2 k, 2 k + 1) of a field: one 2-element vector load.
+template <typename T>
+__device__ __forceinline__ Pair<T> gload_pair(const T* p, int k) {
+    typedef T V __attribute__((ext_vector_type(2)));
+    const V v = gload(reinterpret_cast<const V*>(p), k);
+    return Pair<T>{v.x, v.y};
+}
 
 // LDS word of region column c within a row: even columns, then odd columns.
 __device__ __forceinline__ int col(int c) { return (c & 1) * kHalf + (c >> 1); }
 
+// Three workgroups per compute unit (the LDS ring allows it) need at most 168
+// VGPRs: requested for the finest-level variants.
 template <typename T, bool LEVEL0, int NS, int EPI, bool PRO, bool CORR>
-__global__ __launch_bounds__(kThreads) void k_stream2d(Batch<T> bt,
+__global__ __launch_bounds__(kThreads)
+__attribute__((amdgpu_waves_per_eu(LEVEL0 || CORR ? 3 : 1))) void k_stream2d(Batch<T> bt,
                                                        const StripTask* __restrict__ tasks,
                                                        int ntasks, double* partial) {
-    using S = Slots<LEVEL0, CORR>;
-    constexpr int NF = S::N;
+    using O = Own<LEVEL0, CORR>;
+    constexpr int NO = O::N;
     constexpr int X = EPI ? 1 : 0;
     constexpr int H = X + 2 * NS;          // halo rows
     constexpr int NPH = 2 * NS;            // phases = waves with phase work
     constexpr int LAG = 4 * NS + 1;        // rows (t - LAG, t - LAG + 1) leave at iteration t
     constexpr int RING = 4 * NS + 5;       // rows t - LAG - 1 .. t + 2 are live
-    constexpr int JL = (NF + 1) / 2;       // fields a thread loads per row
-    __shared__ T s[RING][NF][kW];
+    __shared__ T s[RING][NRF][kW];
 
     // XCD-aware order: XCD x runs a contiguous range of tasks (a bijection)
     const int bid = blockIdx.x;
@@ -84,37 +111,30 @@ __global__ __launch_bounds__(kThreads) void k_stream2d(Batch<T> bt,
     const int rhi = ye == ny ? ny - 1 : ye - 2;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);    // uniform per wave
+    // every region column but the outermost two has both x neighbours in the grid
+    const bool xin = x0 >= 0 && x0 + kW - 1 <= nx - 1;
 
-    // ---- loader: thread owns region column lc, fields 2 j + half -------------------
+    const T* own_src[NO];
+    if (LEVEL0) {
+        own_src[0] = L.psi;
+        own_src[1] = L.f1;
+    } else {
+        own_src[0] = L.psi;
+        own_src[1] = L.f0;
+        own_src[2] = L.f1;
+        own_src[3] = L.f2;
+        if (CORR) own_src[NO - 1] = L.b;
+    }
+
+    // ---- ring loader: thread owns region column lc, fields 2 j + half ---------------
     // lanes 0-31 of a wave take even columns, 32-63 odd ones: a load covers 64
     // consecutive values of a row and a store 2 x 32 consecutive LDS words
     const int half = wave >> 1;
     const int lc = 2 * ((lane & 31) + 32 * (wave & 1)) + (lane >> 5);
     const int lgx = x0 + lc;
     const bool lcol = lgx >= 0 && lgx < nx;
-    const T* src[JL];
-#pragma unroll
-    for (int j = 0; j < JL; ++j) {
-        const T* fp[2];
-#pragma unroll
-        for (int hh = 0; hh < 2; ++hh) {
-            const int f = 2 * j + hh;
-            const T* p = nullptr;
-            if (f == S::PHI) p = L.phi;
-            if (f == S::MU) p = L.mu;
-            if (f == S::P) p = L.p;
-            if (f == S::PS) p = L.pstar;
-            if (f == S::PSI) p = L.psi;
-            if (f == S::F1) p = L.f1;
-            if (!LEVEL0 && f == S::F0) p = L.f0;
-            if (!LEVEL0 && f == S::F2) p = L.f2;
-            if (CORR && f == S::B) p = L.b;
-            fp[hh] = p;
-        }
-        // a missing field (odd field count) reads the other half's and drops it
-        src[j] = (half && fp[1] != nullptr) ? fp[1] : fp[0];
-    }
-    // prolongation sources for the u fields (slots 0..2): j = 0 (phi | mu), j = 1 (p)
+    // j = 0: phi | mu, j = 1: p | phi_*
+    const T* src[2] = {half ? L.mu : L.phi, half ? L.pstar : L.p};
     const T* csrc[2] = {nullptr, nullptr};
     const T* cbar[2] = {nullptr, nullptr};
     if (PRO) {
@@ -123,16 +143,16 @@ __global__ __launch_bounds__(kThreads) void k_stream2d(Batch<T> bt,
         csrc[1] = C.p;
         cbar[1] = C.ub2;
     }
-    T rv[2][kD][JL], rc[2][kD][2], rb[2][kD][2];
+    T rv[2][kD][2], rc[2][kD][2], rb[2][kD][2];
 
     // Loads are unconditional (cells outside the loaded rows or the grid read
     // element 0 and are dropped) so that the compiler can wait for exactly the
     // row it stores, not for every load in flight.
-    auto load_row = [&](T (&v)[JL], T (&vc)[2], T (&vb)[2], int r) {
+    auto load_row = [&](T (&v)[2], T (&vc)[2], T (&vb)[2], int r) {
         const bool ok = lcol && r >= ys && r < ye;
         const int g = ok ? r * nx + lgx : 0;
 #pragma unroll
-        for (int j = 0; j < JL; ++j) v[j] = gload(src[j], g);
+        for (int j = 0; j < 2; ++j) v[j] = gload(src[j], g);
         if (PRO) {
             const int cg = ok ? (r >> 1) * C.nx + (lgx >> 1) : 0;
 #pragma unroll
@@ -142,85 +162,120 @@ __global__ __launch_bounds__(kThreads) void k_stream2d(Batch<T> bt,
             }
         }
     };
-    auto store_row = [&](const T (&v)[JL], const T (&vc)[2], const T (&vb)[2], int r) {
+    auto store_row = [&](const T (&v)[2], const T (&vc)[2], const T (&vb)[2], int r) {
         if (r >= ye) return;
-        const bool ok = lcol;
         const int slot = r % RING;
         const int w = col(lc);
 #pragma unroll
-        for (int j = 0; j < JL; ++j) {
-            const int f = 2 * j + half;
-            if (f >= NF) continue;
-            T x = ok ? v[j] : T(0);
-            if (PRO && j < 2 && f < 3 && ok) x += vc[j] - vb[j];
-            s[slot][f][w] = x;
+        for (int j = 0; j < 2; ++j) {
+            T x = lcol ? v[j] : T(0);
+            // prolongation of the correction onto phi, mu, p (not phi_*)
+            if (PRO && lcol && (j == 0 || half == 0)) x += vc[j] - vb[j];
+            s[slot][2 * j + half][w] = x;
         }
+    };
+
+    // ---- own data of the rows a phase wave updates: pairs (2 lane, 2 lane + 1) ---------
+    // prefetch distance in iterations (and slots): kU, or 2 when the
+    // prolongation's coarse loads also wait in registers
+    constexpr int KO = PRO ? 2 : kU;
+    Pair<T> od[KO][NO];
+    const int pgx = x0 + 2 * lane;
+    const bool pcol = pgx >= 0 && pgx < nx;            // nx is even on these levels
+    auto load_own = [&](Pair<T> (&o)[NO], int r) {
+        const bool ok = pcol && r >= rlo && r <= rhi;
+        const int g2 = ok ? (r * nx + pgx) >> 1 : 0;
+#pragma unroll
+        for (int k = 0; k < NO; ++k) o[k] = gload_pair(own_src[k], g2);
     };
 
     const T lam = L.lam, kap = L.kap, gam = L.gamma;
     const T inv_lam = T(1) / lam;
 
+    // sums over the faces of a cell, in the order x - 1, x + 1, y - 1, y + 1
+    struct Sums {
+        int nf;
+        T sa, sa2, smmu, sphi, sp, sap, samu;
+    };
+    auto face = [&](Sums& q, T psc, T psn, T mun, T pn, T phin) {
+        const T a = T(0.5) * (psc + psn);
+        const T m = T(1) + gam * a * a;
+        q.nf += 1;
+        q.sa += a;
+        q.sa2 += a * a;
+        q.smmu += m * mun;
+        q.sphi += phin;
+        q.sp += pn;
+        q.sap += a * pn;
+        q.samu += a * mun;
+    };
+    auto face_if = [&](Sums& q, bool h, T psc, T psn, T mun, T pn, T phin) {
+        Sums t = q;
+        face(t, psc, psn, mun, pn, phin);
+        q.nf = h ? t.nf : q.nf;
+        q.sa = h ? t.sa : q.sa;
+        q.sa2 = h ? t.sa2 : q.sa2;
+        q.smmu = h ? t.smmu : q.smmu;
+        q.sphi = h ? t.sphi : q.sphi;
+        q.sp = h ? t.sp : q.sp;
+        q.sap = h ? t.sap : q.sap;
+        q.samu = h ? t.samu : q.samu;
+    };
+
     // ---- phase q on row r: the collective update of the q & 1 colored cells ----------
-    auto phase = [&](int q, int r) {
+    auto phase = [&](int q, int r, const Pair<T> (&o)[NO]) {
         if (r < rlo || r > rhi) return;
         const int e = (r & 1) ^ (q & 1);           // pair member with this color
         const int c = 2 * lane + e;
         const int gx = x0 + c;
         if (c < 1 || c > kW - 2 || gx < 0 || gx >= nx) return;
         const int sc = r % RING, sd = (r + RING - 1) % RING, su = (r + 1) % RING;
-        const int wc = col(c);
-        const T psc = s[sc][S::PS][wc];
-        // the four neighbours (x - 1, x + 1, y - 1, y + 1) are read without
-        // branches so that their LDS reads issue together; a neighbour across
-        // the boundary reads in-bounds ring words whose terms the selects drop
-        const int nsl[4] = {sc, sc, sd, su};
-        const int nw[4] = {col(c - 1), col(c + 1), wc, wc};
-        const bool nh[4] = {gx > 0, gx < nx - 1, r > 0, r < ny - 1};
-        T vps[4], vmu[4], vp[4], vphi[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            vps[k] = s[nsl[k]][S::PS][nw[k]];
-            vmu[k] = s[nsl[k]][S::MU][nw[k]];
-            vp[k] = s[nsl[k]][S::P][nw[k]];
-            vphi[k] = s[nsl[k]][S::PHI][nw[k]];
+        const int wc = col(c), wl = col(c - 1), wr = col(c + 1);
+        const T psc = s[sc][PS][wc];
+        // every neighbour is read (rows across the boundary read in-bounds ring
+        // words) so that the reads issue together; missing faces add nothing
+        const T lps = s[sc][PS][wl], lmu = s[sc][MU][wl], lp = s[sc][P][wl], lphi = s[sc][PHI][wl];
+        const T rps = s[sc][PS][wr], rmu = s[sc][MU][wr], rp = s[sc][P][wr], rphi = s[sc][PHI][wr];
+        const T dps = s[sd][PS][wc], dmu = s[sd][MU][wc], dp = s[sd][P][wc], dphi = s[sd][PHI][wc];
+        const T ups = s[su][PS][wc], umu = s[su][MU][wc], up = s[su][P][wc], uphi = s[su][PHI][wc];
+        const T phit = s[sc][PHI][wc];
+        Sums q4{0, 0, 0, 0, 0, 0, 0, 0};
+        if (xin) {
+            face(q4, psc, lps, lmu, lp, lphi);
+            face(q4, psc, rps, rmu, rp, rphi);
+        } else {
+            face_if(q4, gx > 0, psc, lps, lmu, lp, lphi);
+            face_if(q4, gx < nx - 1, psc, rps, rmu, rp, rphi);
         }
-        int nf = 0;
-        T sa = 0, sa2 = 0, smmu = 0, sphi = 0, sp = 0, sap = 0, samu = 0;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const T a = T(0.5) * (psc + vps[k]);
-            const T m = T(1) + gam * a * a;
-            const bool h = nh[k];
-            nf += h ? 1 : 0;
-            sa = h ? sa + a : sa;
-            sa2 = h ? sa2 + a * a : sa2;
-            smmu = h ? smmu + m * vmu[k] : smmu;
-            sphi = h ? sphi + vphi[k] : sphi;
-            sp = h ? sp + vp[k] : sp;
-            sap = h ? sap + a * vp[k] : sap;
-            samu = h ? samu + a * vmu[k] : samu;
-        }
+        if (r > 0) face(q4, psc, dps, dmu, dp, dphi);
+        if (r < ny - 1) face(q4, psc, ups, umu, up, uphi);
+        const int nf = q4.nf;
         const T fnf = T(nf);
         const T inv_nf = nf == 4 ? T(0.25) : (nf == 3 ? T(1) / T(3) : (nf == 2 ? T(0.5) : T(1)));
-        const T phit = s[sc][S::PHI][wc];
-        const T psi = s[sc][S::PSI][wc];
-        const T f0 = s[sc][S::F0][wc];
-        const T f1 = s[sc][S::F1][wc];
-        const T f2 = LEVEL0 ? T(0) : s[sc][S::F2 < 0 ? 0 : S::F2][wc];
-        const T base = CORR ? s[sc][S::B < 0 ? 0 : S::B][wc] : T(0);
+        // select values, not member addresses, so that the pairs stay in registers
+        auto pick = [&](int k) {
+            if (k < 0) return T(0);
+            const T va = o[k].a, vb = o[k].b;
+            return e ? vb : va;
+        };
+        const T psi = pick(O::PSI);
+        const T f0 = pick(O::F0);
+        const T f1 = pick(O::F1);
+        const T f2 = pick(O::F2);
+        const T base = pick(O::B);
         const T dchi = dnonlin<T, CORR>(phit, psi, base);
         const T chi = nonlin<T, CORR>(phit, psi, base);
-        const T b1 = f0 + lam * smmu + lam * sap;
-        const T b2 = f1 + chi - dchi * phit - kap * sphi;
-        const T b3 = f2 - lam * sp - lam * gam * samu;
-        const T ared = lam * (fnf + gam * (sa2 - sa * sa * inv_nf));
-        const T b1r = b1 + (sa * inv_nf) * b3;
+        const T b1 = f0 + lam * q4.smmu + lam * q4.sap;
+        const T b2 = f1 + chi - dchi * phit - kap * q4.sphi;
+        const T b3 = f2 - lam * q4.sp - lam * gam * q4.samu;
+        const T ared = lam * (fnf + gam * (q4.sa2 - q4.sa * q4.sa * inv_nf));
+        const T b1r = b1 + (q4.sa * inv_nf) * b3;
         const T bb = dchi + kap * fnf;
         const T inv_det = T(1) / (T(1) + ared * bb);
         const T mun = (b2 + bb * b1r) * inv_det;
-        s[sc][S::PHI][wc] = (b1r - ared * b2) * inv_det;
-        s[sc][S::MU][wc] = mun;
-        s[sc][S::P][wc] = -(b3 * inv_lam + gam * sa * mun) * inv_nf;
+        s[sc][PHI][wc] = (b1r - ared * b2) * inv_det;
+        s[sc][MU][wc] = mun;
+        s[sc][P][wc] = -(b3 * inv_lam + gam * q4.sa * mun) * inv_nf;
     };
 
     // ---- rows (k2, k2 + 1) leave: write-back, residual, restriction / norm -----------
@@ -232,14 +287,23 @@ __global__ __launch_bounds__(kThreads) void k_stream2d(Batch<T> bt,
     const int oc = 2 * ocl + odx;
     const int ogx = x0 + oc;
     const bool own_col = oc >= kStripHX && oc < kStripHX + kStripWO && ogx < nx;
+    const bool ocol = ogx >= 0 && ogx < nx;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    T lo[NO];                                          // own data of the leaving cell
+
+    auto load_leave = [&](int k2) {
+        const int r = k2 + ody;
+        const int g = (ocol && r < ny) ? r * nx + ogx : 0;
+#pragma unroll
+        for (int k = 0; k < NO; ++k) lo[k] = gload(own_src[k], g);
+    };
 
     auto leave = [&](int k2) {
         const int r = k2 + ody;
         const bool own = own_col && r < ny;
         const int sc = r % RING;
         const int wc = col(oc);
-        const T phic = s[sc][S::PHI][wc], muc = s[sc][S::MU][wc], pc = s[sc][S::P][wc];
+        const T phic = s[sc][PHI][wc], muc = s[sc][MU][wc], pc = s[sc][P][wc];
         const int g = r * nx + ogx;
         if (own) {
             gstore(L.phi_alt, g, phic);
@@ -249,43 +313,55 @@ __global__ __launch_bounds__(kThreads) void k_stream2d(Batch<T> bt,
         if (EPI == 0) return;
         // computed by every lane (halo lanes read clamped, in-bounds words);
         // only owned cells are stored or summed
-        T r0 = 0, r1 = 0, r2 = 0, bg = 0;
-        {
-            const T psc = s[sc][S::PS][wc];
-            const int nsl[4] = {sc, sc, (r + RING - 1) % RING, (r + 1) % RING};
-            const int nw[4] = {col(oc > 0 ? oc - 1 : 0), col(oc < kW - 1 ? oc + 1 : kW - 1), wc, wc};
-            const bool nh[4] = {ogx > 0, ogx < nx - 1, r > 0, r < ny - 1};
-            T vps[4], vmu[4], vp[4], vphi[4];
+        const int sd = (r + RING - 1) % RING, su = (r + 1) % RING;
+        const int wl = col(oc > 0 ? oc - 1 : 0), wr = col(oc < kW - 1 ? oc + 1 : kW - 1);
+        const T psc = s[sc][PS][wc];
+        T nps[4], nmu[4], np[4], nphi[4];
+        const int nsl[4] = {sc, sc, sd, su};
+        const int nw[4] = {wl, wr, wc, wc};
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                vps[k] = s[nsl[k]][S::PS][nw[k]];
-                vmu[k] = s[nsl[k]][S::MU][nw[k]];
-                vp[k] = s[nsl[k]][S::P][nw[k]];
-                vphi[k] = s[nsl[k]][S::PHI][nw[k]];
-            }
-            T smm = 0, sap = 0, sphi = 0, sp = 0, samu = 0;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const T a = T(0.5) * (psc + vps[k]);
-                const T m = T(1) + gam * a * a;
-                const T dmu = vmu[k] - muc;
-                const T dp = vp[k] - pc;
-                const bool h = nh[k];
-                smm = h ? smm + m * dmu : smm;
-                sap = h ? sap + a * dp : sap;
-                sphi = h ? sphi + (vphi[k] - phic) : sphi;
-                sp = h ? sp + dp : sp;
-                samu = h ? samu + a * dmu : samu;
-            }
-            const T psi = s[sc][S::PSI][wc];
-            const T f0 = s[sc][S::F0][wc];
-            const T f1 = s[sc][S::F1][wc];
-            const T f2 = LEVEL0 ? T(0) : s[sc][S::F2 < 0 ? 0 : S::F2][wc];
-            bg = CORR ? s[sc][S::B < 0 ? 0 : S::B][wc] : T(0);
-            r0 = f0 - (phic - lam * smm - lam * sap);
-            r1 = f1 - (muc - nonlin<T, CORR>(phic, psi, bg) + kap * sphi);
-            r2 = f2 - (lam * sp + lam * gam * samu);
+        for (int k = 0; k < 4; ++k) {
+            nps[k] = s[nsl[k]][PS][nw[k]];
+            nmu[k] = s[nsl[k]][MU][nw[k]];
+            np[k] = s[nsl[k]][P][nw[k]];
+            nphi[k] = s[nsl[k]][PHI][nw[k]];
         }
+        T smm = 0, sap = 0, sphi = 0, sp = 0, samu = 0;
+        auto rface = [&](int k) {
+            const T a = T(0.5) * (psc + nps[k]);
+            const T m = T(1) + gam * a * a;
+            const T dmu = nmu[k] - muc;
+            const T dp = np[k] - pc;
+            smm += m * dmu;
+            sap += a * dp;
+            sphi += nphi[k] - phic;
+            sp += dp;
+            samu += a * dmu;
+        };
+        if (xin && k2 > 0 && k2 + 2 < ny) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) rface(k);
+        } else {
+            const bool nh[4] = {ogx > 0, ogx < nx - 1, r > 0, r < ny - 1};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const T s0 = smm, s1 = sap, s2 = sphi, s3 = sp, s4 = samu;
+                rface(k);
+                smm = nh[k] ? smm : s0;
+                sap = nh[k] ? sap : s1;
+                sphi = nh[k] ? sphi : s2;
+                sp = nh[k] ? sp : s3;
+                samu = nh[k] ? samu : s4;
+            }
+        }
+        const T psi = lo[O::PSI];
+        const T f0 = lo[O::F0];
+        const T f1 = lo[O::F1];
+        const T f2 = O::F2 < 0 ? T(0) : lo[O::F2 < 0 ? 0 : O::F2];
+        const T bg = O::B < 0 ? T(0) : lo[O::B < 0 ? 0 : O::B];
+        const T r0 = f0 - (phic - lam * smm - lam * sap);
+        const T r1 = f1 - (muc - nonlin<T, CORR>(phic, psi, bg) + kap * sphi);
+        const T r2 = f2 - (lam * sp + lam * gam * samu);
         if (EPI == 2) {
             if (own) {
                 acc[0] += double(r0) * double(r0);
@@ -320,13 +396,14 @@ __global__ __launch_bounds__(kThreads) void k_stream2d(Batch<T> bt,
     };
 
     // ---- the pipeline -------------------------------------------------------------------
-    // Loaded rows wait in two register banks of kD rows each.  At the first
+    // Ring rows wait in two register banks of kD rows each.  At the first
     // iteration that drains bank b the other bank is refilled with the rows
     // needed kD iterations later, after the wait for the row being stored:
     // whatever the compiler waits for at the loop head, the loads it waits
-    // for were issued kD iterations earlier.
+    // for were issued kD iterations earlier.  A phase wave's own data for
+    // iteration t + KO is loaded at iteration t into the slot it just used.
     {
-        T v[JL], vc[2], vb[2];
+        T v[2], vc[2], vb[2];
         load_row(v, vc, vb, ys);
         store_row(v, vc, vb, ys);
         load_row(v, vc, vb, ys + 1);
@@ -334,27 +411,34 @@ __global__ __launch_bounds__(kThreads) void k_stream2d(Batch<T> bt,
     }
 #pragma unroll
     for (int u = 0; u < kD; ++u) load_row(rv[0][u], rc[0][u], rb[0][u], ys + 2 + u);
+    if (wave < NPH) {
+#pragma unroll
+        for (int i = 0; i < KO; ++i) load_own(od[i], ys + i - 2 * wave);
+    }
     __syncthreads();
 
     const int t_last = y0 + 2 * ((y1 - y0 + 1) / 2 - 1) + LAG;   // the last pair of rows leaves
-    for (int tb = ys; tb <= t_last; tb += 2 * kD) {
+    for (int tb = ys; tb <= t_last; tb += kU) {
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
+        for (int i = 0; i < kU; ++i) {
+            const int b = i / kD, u = i % kD;
+            const int t = tb + i;
+            if (t > t_last) goto drained;
+            const int k2 = t - LAG;
+            const bool lv = k2 >= y0 && ((k2 - y0) & 1) == 0;
+            if (EPI != 0 && lv) load_leave(k2);
+            store_row(rv[b][u], rc[b][u], rb[b][u], t + 2);
+            if (u == 0) {
 #pragma unroll
-            for (int u = 0; u < kD; ++u) {
-                const int t = tb + b * kD + u;
-                if (t > t_last) goto drained;
-                store_row(rv[b][u], rc[b][u], rb[b][u], t + 2);
-                if (u == 0) {
-#pragma unroll
-                    for (int w = 0; w < kD; ++w)
-                        load_row(rv[b ^ 1][w], rc[b ^ 1][w], rb[b ^ 1][w], t + 2 + kD + w);
-                }
-                if (wave < NPH) phase(wave, t - 2 * wave);
-                const int k2 = t - LAG;
-                if (k2 >= y0 && ((k2 - y0) & 1) == 0) leave(k2);
-                __syncthreads();
+                for (int w = 0; w < kD; ++w)
+                    load_row(rv[b ^ 1][w], rc[b ^ 1][w], rb[b ^ 1][w], t + 2 + kD + w);
             }
+            if (wave < NPH) {
+                phase(wave, t - 2 * wave, od[i % KO]);
+                load_own(od[i % KO], t + KO - 2 * wave);
+            }
+            if (lv) leave(k2);
+            __syncthreads();
         }
     }
 drained:
