@@ -29,6 +29,9 @@ using chhs::kMaxLevels;
 namespace {
 
 constexpr size_t kAlign = 256;
+// Tiled launches of at most this many blocks (at most one per compute unit)
+// use 1024-thread blocks: their time is the latency of one block.
+constexpr int kWideTiles = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 // A table of block tasks in device memory.
@@ -555,7 +558,8 @@ void tiled(chhs_ctx* c, const Hier<T>& H, bool all, int l, int ns, int epi, bool
             chhs::launch_stream2d<T>(b, st.dev, st.n, level0, ns, epi, pro, part, c->stream);
         } else {
             const Table<TileTask>& tt = all ? c->Tall[l] : c->T[l];
-            chhs::launch_tile2d<T>(b, tt.dev, tt.n, level0, ns, epi, pro, part, c->stream);
+            chhs::launch_tile2d<T>(b, tt.dev, tt.n, level0, ns, epi, pro, tt.n <= kWideTiles, part,
+                                   c->stream);
         }
     }
     H.cur[l] ^= 1;

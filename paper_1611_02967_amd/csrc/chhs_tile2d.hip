@@ -36,9 +36,13 @@ namespace {
 
 constexpr int kTX = kTileX;     // block width (cells)
 constexpr int kTY = kTileY;     // block height (cells)
-constexpr int kThreads = 256;
+constexpr int kSlots = kTX * kTY / 2;   // pairs of the block (epilogue work items)
 
-template <int NS, int EPI>
+// NT threads per block: 256 (four pairs per thread, two blocks per compute
+// unit) on levels with many tiles; 1024 (one pair per thread) on levels with
+// fewer tiles than compute units, where the time of one block is the time of
+// the launch.
+template <int NS, int EPI, int NT>
 struct Geometry {
     static constexpr int X = EPI ? 1 : 0;          // extra valid rings after the last phase
     static constexpr int H = X + 2 * NS;           // halo depth needed by phase 0
@@ -47,17 +51,18 @@ struct Geometry {
     static constexpr int R = kTY + 2 * H;          // region height
     static constexpr int PW = W / 2;               // pairs per row
     static constexpr int NP = PW * R;              // pairs in the region
-    static constexpr int KP = (NP + kThreads - 1) / kThreads;   // pairs per thread
+    static constexpr int KP = (NP + NT - 1) / NT;   // pairs per thread
 };
 
 // LDS word of region cell (r, x): even columns of row r, then odd columns.
 template <int PW>
 __device__ __forceinline__ int lds(int r, int x) { return (2 * r + (x & 1)) * PW + (x >> 1); }
 
-template <typename T, bool LEVEL0, int NS, int EPI, bool PRO, bool CORR>
-__global__ __launch_bounds__(kThreads) void k_tile2d(Batch<T> bt, const TileTask* __restrict__ tasks,
-                                                     int ntiles, double* partial) {
-    using G = Geometry<NS, EPI>;
+template <typename T, bool LEVEL0, int NS, int EPI, bool PRO, bool CORR, int NT>
+__global__ __launch_bounds__(NT) void k_tile2d(Batch<T> bt, const TileTask* __restrict__ tasks,
+                                               int ntiles, double* partial) {
+    using G = Geometry<NS, EPI, NT>;
+    constexpr int kThreads = NT;
     constexpr int W = G::W, R = G::R, H = G::H, HX = G::HX;
     constexpr int PW = G::PW, KP = G::KP, NP = G::NP;
     __shared__ T s_phi[R * W];
@@ -99,24 +104,24 @@ __global__ __launch_bounds__(kThreads) void k_tile2d(Batch<T> bt, const TileTask
             T phi = 0, mu = 0, p = 0, ps = 0, psi = 0, f0 = 0, f1 = 0, f2 = 0, bs = 0;
             if (q < NP && gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
                 const int g = gy * nx + gx;
-                phi = L.phi[g];
-                mu = L.mu[g];
-                p = L.p[g];
-                ps = L.pstar[g];
-                psi = L.psi[g];
-                f1 = L.f1[g];
+                phi = gload(L.phi, g);
+                mu = gload(L.mu, g);
+                p = gload(L.p, g);
+                ps = gload(L.pstar, g);
+                psi = gload(L.psi, g);
+                f1 = gload(L.f1, g);
                 if (LEVEL0) {
                     f0 = psi;
                 } else {
-                    f0 = L.f0[g];
-                    f2 = L.f2[g];
+                    f0 = gload(L.f0, g);
+                    f2 = gload(L.f2, g);
                 }
-                if (CORR) bs = L.b[g];
+                if (CORR) bs = gload(L.b, g);
                 if (PRO) {
                     const int c = (gy >> 1) * C.nx + (gx >> 1);
-                    phi += C.phi[c] - C.ub0[c];
-                    mu += C.mu[c] - C.ub1[c];
-                    p += C.p[c] - C.ub2[c];
+                    phi += gload(C.phi, c) - gload(C.ub0, c);
+                    mu += gload(C.mu, c) - gload(C.ub1, c);
+                    p += gload(C.p, c) - gload(C.ub2, c);
                 }
             }
             v_phi[k][e] = phi;
@@ -245,9 +250,9 @@ __global__ __launch_bounds__(kThreads) void k_tile2d(Batch<T> bt, const TileTask
             if (gx >= nx || gy >= ny) continue;
             const int g = gy * nx + gx;
             const int w = lds<PW>(r, xp + e);
-            L.phi_alt[g] = s_phi[w];
-            L.mu_alt[g] = s_mu[w];
-            L.p_alt[g] = s_p[w];
+            gstore(L.phi_alt, g, s_phi[w]);
+            gstore(L.mu_alt, g, s_mu[w]);
+            gstore(L.p_alt, g, s_p[w]);
         }
     }
 
@@ -259,8 +264,9 @@ __global__ __launch_bounds__(kThreads) void k_tile2d(Batch<T> bt, const TileTask
     // of the same coarse cell.
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int j = 0; j < 512 / kThreads; ++j) {
+    for (int j = 0; j < (kSlots + kThreads - 1) / kThreads; ++j) {
         const int slot = tid + j * kThreads;
+        if (slot >= kSlots) break;      // whole waves
         const int cxl = slot & 31, cy = (slot >> 5) & 1, cyl = slot >> 6;   // 32 x 8 coarse cells
         T su[3] = {0, 0, 0}, sr[3] = {0, 0, 0}, sb = 0;
         const int gcx = (x0 + HX) / 2 + cxl, gcy = (y0 + H) / 2 + cyl;
@@ -289,11 +295,11 @@ __global__ __launch_bounds__(kThreads) void k_tile2d(Batch<T> bt, const TileTask
                 if (gx < nx - 1) nb_res(r, x + 1);
                 if (gy > 0) nb_res(r - 1, x);
                 if (gy < ny - 1) nb_res(r + 1, x);
-                const T psi = L.psi[g];
-                const T f0 = LEVEL0 ? psi : L.f0[g];
-                const T f1 = L.f1[g];
-                const T f2 = LEVEL0 ? T(0) : L.f2[g];
-                const T bg = CORR ? L.b[g] : T(0);
+                const T psi = gload(L.psi, g);
+                const T f0 = LEVEL0 ? psi : gload(L.f0, g);
+                const T f1 = gload(L.f1, g);
+                const T f2 = LEVEL0 ? T(0) : gload(L.f2, g);
+                const T bg = CORR ? gload(L.b, g) : T(0);
                 const T r0 = f0 - (phic - lam * smm - lam * sap);
                 const T r1 = f1 - (muc - nonlin<T, CORR>(phic, psi, bg) + kap * sphi);
                 const T r2 = f2 - (lam * sp + lam * gam * samu);
@@ -324,13 +330,16 @@ __global__ __launch_bounds__(kThreads) void k_tile2d(Batch<T> bt, const TileTask
             if (live && cy == 0) {
                 const int c = gcy * C.nx + gcx;
                 const T w = T(0.25);
-                C.phi[c] = C.ub0[c] = su[0] * w;
-                C.mu[c] = C.ub1[c] = su[1] * w;
-                C.p[c] = C.ub2[c] = su[2] * w;
-                C.f0[c] = sr[0] * w;
-                C.f1[c] = sr[1] * w;
-                C.f2[c] = sr[2] * w;
-                if (CORR) C.b[c] = sb * w;
+                gstore(C.phi, c, su[0] * w);
+                gstore(C.ub0, c, su[0] * w);
+                gstore(C.mu, c, su[1] * w);
+                gstore(C.ub1, c, su[1] * w);
+                gstore(C.p, c, su[2] * w);
+                gstore(C.ub2, c, su[2] * w);
+                gstore(C.f0, c, sr[0] * w);
+                gstore(C.f1, c, sr[1] * w);
+                gstore(C.f2, c, sr[2] * w);
+                if (CORR) gstore(C.b, c, sb * w);
             }
         }
     }
@@ -346,25 +355,30 @@ __global__ __launch_bounds__(kThreads) void k_tile2d(Batch<T> bt, const TileTask
         for (int c = 0; c < 4; ++c) {
             double s = 0.0;
             for (int w = 0; w < kThreads / 64; ++w) s += red[c][w];
-            partial[tile * kPartialStride + c] = s;
+            gstore(partial, tile * kPartialStride + c, s);
         }
 }
 
 template <typename T, bool LEVEL0, int NS, int EPI, bool PRO, bool CORR>
-void launch_one(const Batch<T>& b, const TileTask* t, int nt, double* partial, hipStream_t st) {
-    hipLaunchKernelGGL((k_tile2d<T, LEVEL0, NS, EPI, PRO, CORR>), dim3(nt), dim3(kThreads), 0, st,
-                       b, t, nt, partial);
+void launch_one(const Batch<T>& b, const TileTask* t, int nt, bool wide, double* partial,
+                hipStream_t st) {
+    if (wide)
+        hipLaunchKernelGGL((k_tile2d<T, LEVEL0, NS, EPI, PRO, CORR, 1024>), dim3(nt), dim3(1024), 0,
+                           st, b, t, nt, partial);
+    else
+        hipLaunchKernelGGL((k_tile2d<T, LEVEL0, NS, EPI, PRO, CORR, 256>), dim3(nt), dim3(256), 0,
+                           st, b, t, nt, partial);
 }
 
 }  // namespace
 
 template <>
 void launch_tile2d<double>(const Batch<double>& b, const TileTask* t, int nt, bool level0, int ns,
-                           int epi, bool pro, double* partial, hipStream_t st) {
+                           int epi, bool pro, bool wide, double* partial, hipStream_t st) {
     if (nt <= 0) return;
 #define CHHS_TILE_CASE(L0, NS, EPI, PRO)                                          \
     if (level0 == L0 && ns == NS && epi == EPI && pro == PRO) {                   \
-        launch_one<double, L0, NS, EPI, PRO, false>(b, t, nt, partial, st);       \
+        launch_one<double, L0, NS, EPI, PRO, false>(b, t, nt, wide, partial, st); \
         return;                                                                   \
     }
 #define CHHS_TILE_PRO(L0, NS, EPI) CHHS_TILE_CASE(L0, NS, EPI, false) CHHS_TILE_CASE(L0, NS, EPI, true)
@@ -382,12 +396,12 @@ void launch_tile2d<double>(const Batch<double>& b, const TileTask* t, int nt, bo
 // sides, no norm epilogue.
 template <>
 void launch_tile2d<float>(const Batch<float>& b, const TileTask* t, int nt, bool level0, int ns,
-                          int epi, bool pro, double* partial, hipStream_t st) {
+                          int epi, bool pro, bool wide, double* partial, hipStream_t st) {
     (void)level0;
     if (nt <= 0) return;
 #define CHHS_TILE_CASE(NS, EPI, PRO)                                              \
     if (ns == NS && epi == EPI && pro == PRO) {                                   \
-        launch_one<float, false, NS, EPI, PRO, true>(b, t, nt, partial, st);      \
+        launch_one<float, false, NS, EPI, PRO, true>(b, t, nt, wide, partial, st); \
         return;                                                                   \
     }
     CHHS_TILE_CASE(1, 0, false)
