@@ -47,18 +47,23 @@ __device__ __forceinline__ void decode(int idx, int nx, int ny, int& i, int& j, 
     }
 }
 
-// Calls fn(nb) for every neighbour across an interior face of cell (i, j, k).
+// Calls fn(has, nb) for the 2 DIM faces of cell (i, j, k) in the order x - 1,
+// x + 1, y - 1, y + 1 (, z - 1, z + 1): has = the face is interior, nb = the
+// neighbour's index (the cell's own index across a boundary face, so that
+// every read stays in bounds).  Callers read every neighbour unconditionally,
+// which lets all the reads be in flight together, and drop the terms of
+// boundary faces with selects.
 template <int DIM, typename Fn>
-__device__ __forceinline__ void for_each_nb(int i, int j, int k, int nx, int ny, int nz,
-                                            int idx, Fn&& fn) {
-    if (i > 0) fn(idx - 1);
-    if (i < nx - 1) fn(idx + 1);
-    if (j > 0) fn(idx - nx);
-    if (j < ny - 1) fn(idx + nx);
+__device__ __forceinline__ void for_each_face(int i, int j, int k, int nx, int ny, int nz,
+                                              int idx, Fn&& fn) {
+    fn(i > 0, i > 0 ? idx - 1 : idx);
+    fn(i < nx - 1, i < nx - 1 ? idx + 1 : idx);
+    fn(j > 0, j > 0 ? idx - nx : idx);
+    fn(j < ny - 1, j < ny - 1 ? idx + nx : idx);
     if (DIM == 3) {
         const int sz = nx * ny;
-        if (k > 0) fn(idx - sz);
-        if (k < nz - 1) fn(idx + sz);
+        fn(k > 0, k > 0 ? idx - sz : idx);
+        fn(k < nz - 1, k < nz - 1 ? idx + sz : idx);
     }
 }
 
@@ -85,16 +90,17 @@ __device__ __forceinline__ void cell_operator(const Level<T>& L, int idx, int i,
                                               T& n0, T& n1, T& n2) {
     const T phic = L.phi[idx], muc = L.mu[idx], pc = L.p[idx], psc = L.pstar[idx];
     T smm = 0, sap = 0, sphi = 0, sp = 0, samu = 0;
-    for_each_nb<DIM>(i, j, k, L.nx, L.ny, L.nz, idx, [&](int nb) {
+    for_each_face<DIM>(i, j, k, L.nx, L.ny, L.nz, idx, [&](bool h, int nb) {
         const T a = T(0.5) * (psc + L.pstar[nb]);
         const T m = T(1) + L.gamma * a * a;
         const T dmu = L.mu[nb] - muc;
         const T dp = L.p[nb] - pc;
-        smm += m * dmu;
-        sap += a * dp;
-        sphi += L.phi[nb] - phic;
-        sp += dp;
-        samu += a * dmu;
+        const T dphi = L.phi[nb] - phic;
+        smm = h ? smm + m * dmu : smm;
+        sap = h ? sap + a * dp : sap;
+        sphi = h ? sphi + dphi : sphi;
+        sp = h ? sp + dp : sp;
+        samu = h ? samu + a * dmu : samu;
     });
     const T psi = L.psi[idx];
     const T chi = nonlin<T, CORR>(phic, psi, CORR ? L.b[idx] : T(0));
@@ -110,40 +116,51 @@ __device__ __forceinline__ void cell_operator(const Level<T>& L, int idx, int i,
 //   -lam gamma Sa mu - lam nF p       = b3
 // are solved by eliminating p; the reduced 2x2 determinant is
 // 1 + lam (nF + gamma (Sa2 - Sa^2/nF)) (chi' + kap nF) >= 1.
+//
+// Written with one reciprocal of the determinant and 1/nF by cases, in the
+// same operation order as the tiled and row-streaming 2D kernels, so that
+// every path performs bitwise the same update.  inv_lam = 1 / lam.
 template <int DIM, typename T, bool CORR = false>
 __device__ __forceinline__ void cell_solve(const Level<T>& L, int idx, int i, int j, int k,
-                                           T& phi_o, T& mu_o, T& p_o) {
+                                           T inv_lam, T& phi_o, T& mu_o, T& p_o) {
     const T psc = L.pstar[idx];
-    T nf = 0, sa = 0, sa2 = 0, smmu = 0, sphi = 0, sp = 0, sap = 0, samu = 0;
-    for_each_nb<DIM>(i, j, k, L.nx, L.ny, L.nz, idx, [&](int nb) {
+    const T lam = L.lam, kap = L.kap, gam = L.gamma;
+    int nf = 0;
+    T sa = 0, sa2 = 0, smmu = 0, sphi = 0, sp = 0, sap = 0, samu = 0;
+    for_each_face<DIM>(i, j, k, L.nx, L.ny, L.nz, idx, [&](bool h, int nb) {
         const T a = T(0.5) * (psc + L.pstar[nb]);
-        const T m = T(1) + L.gamma * a * a;
+        const T m = T(1) + gam * a * a;
         const T munb = L.mu[nb];
         const T pnb = L.p[nb];
-        nf += T(1);
-        sa += a;
-        sa2 += a * a;
-        smmu += m * munb;
-        sphi += L.phi[nb];
-        sp += pnb;
-        sap += a * pnb;
-        samu += a * munb;
+        const T phinb = L.phi[nb];
+        nf += h ? 1 : 0;
+        sa = h ? sa + a : sa;
+        sa2 = h ? sa2 + a * a : sa2;
+        smmu = h ? smmu + m * munb : smmu;
+        sphi = h ? sphi + phinb : sphi;
+        sp = h ? sp + pnb : sp;
+        sap = h ? sap + a * pnb : sap;
+        samu = h ? samu + a * munb : samu;
     });
+    const T fnf = T(nf);
+    const T inv_nf = nf == 6 ? T(1) / T(6)
+                   : (nf == 5 ? T(1) / T(5)
+                   : (nf == 4 ? T(0.25) : (nf == 3 ? T(1) / T(3) : (nf == 2 ? T(0.5) : T(1)))));
     const T phit = L.phi[idx];
     const T psi = L.psi[idx];
     const T base = CORR ? L.b[idx] : T(0);
     const T dchi = dnonlin<T, CORR>(phit, psi, base);
     const T chi = nonlin<T, CORR>(phit, psi, base);
-    const T b1 = L.f0[idx] + L.lam * smmu + L.lam * sap;
-    const T b2 = L.f1[idx] + chi - dchi * phit - L.kap * sphi;
-    const T b3 = L.f2[idx] - L.lam * sp - L.lam * L.gamma * samu;
-    const T ared = L.lam * (nf + L.gamma * (sa2 - sa * sa / nf));
-    const T b1r = b1 + (sa / nf) * b3;
-    const T bb = dchi + L.kap * nf;
-    const T det = T(1) + ared * bb;
-    phi_o = (b1r - ared * b2) / det;
-    mu_o = (b2 + bb * b1r) / det;
-    p_o = -(b3 + L.lam * L.gamma * sa * mu_o) / (L.lam * nf);
+    const T b1 = L.f0[idx] + lam * smmu + lam * sap;
+    const T b2 = L.f1[idx] + chi - dchi * phit - kap * sphi;
+    const T b3 = L.f2[idx] - lam * sp - lam * gam * samu;
+    const T ared = lam * (fnf + gam * (sa2 - sa * sa * inv_nf));
+    const T b1r = b1 + (sa * inv_nf) * b3;
+    const T bb = dchi + kap * fnf;
+    const T inv_det = T(1) / (T(1) + ared * bb);
+    mu_o = (b2 + bb * b1r) * inv_det;
+    phi_o = (b1r - ared * b2) * inv_det;
+    p_o = -(b3 * inv_lam + gam * sa * mu_o) * inv_nf;
 }
 
 }  // namespace chhs

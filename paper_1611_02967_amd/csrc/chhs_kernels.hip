@@ -37,8 +37,10 @@ __global__ __launch_bounds__(kBlock) void k_setup(Batch<double> b, const CellTas
     const double pm = phi_prev[g];
     const double pc = phi_cur[g];
     double lap = 0.0;
-    for_each_nb<DIM>(i, j, k, L.nx, L.ny, L.nz, idx,
-                     [&](int nb) { lap += phi_prev[in.off + nb] - pm; });
+    for_each_face<DIM>(i, j, k, L.nx, L.ny, L.nz, idx, [&](bool h, int nb) {
+        const double d = phi_prev[in.off + nb] - pm;
+        lap = h ? lap + d : lap;
+    });
     const double q = 0.25 * in.eps * in.eps / (in.h * in.h);
     const double ps = 1.5 * pc - 0.5 * pm;           // phi_*, (2.4)
     L.pstar[idx] = ps;
@@ -87,7 +89,7 @@ __global__ __launch_bounds__(kBlock) void k_smooth(Batch<T> b, const CellTask* _
     decode<DIM>(idx, L.nx, L.ny, i, j, k);
     if (((i + j + k) & 1) != color) return;
     T phi, mu, p;
-    cell_solve<DIM, T, CORR>(L, idx, i, j, k, phi, mu, p);
+    cell_solve<DIM, T, CORR>(L, idx, i, j, k, T(1) / L.lam, phi, mu, p);
     L.phi[idx] = phi;
     L.mu[idx] = mu;
     L.p[idx] = p;
@@ -231,18 +233,19 @@ __global__ __launch_bounds__(kBlock) void k_mixed_residual(Batch<double> b64, Ba
             u_at(idx, phic, muc, pc);
             const double psc = L.pstar[idx];
             double smm = 0, sap = 0, sphi = 0, sp = 0, samu = 0;
-            for_each_nb<DIM>(i, j, k, L.nx, L.ny, L.nz, idx, [&](int nb) {
+            for_each_face<DIM>(i, j, k, L.nx, L.ny, L.nz, idx, [&](bool h, int nb) {
                 double phn, mun, pn;
                 u_at(nb, phn, mun, pn);
                 const double a = 0.5 * (psc + L.pstar[nb]);
                 const double m = 1.0 + L.gamma * a * a;
                 const double dmu = mun - muc;
                 const double dp = pn - pc;
-                smm += m * dmu;
-                sap += a * dp;
-                sphi += phn - phic;
-                sp += dp;
-                samu += a * dmu;
+                const double dphi = phn - phic;
+                smm = h ? smm + m * dmu : smm;
+                sap = h ? sap + a * dp : sap;
+                sphi = h ? sphi + dphi : sphi;
+                sp = h ? sp + dp : sp;
+                samu = h ? samu + a * dmu : samu;
             });
             const double psi = L.psi[idx];
             const double r0 = psi - (phic - L.lam * smm - L.lam * sap);

@@ -15,15 +15,35 @@ namespace {
 
 constexpr int kTailThreads = 1024;
 
+// (i, j, k) of cell idx of a tail level: a float reciprocal replaces the
+// integer divisions; exact while idx < 2^20 (a tail level holds at most a few
+// thousand cells), since (idx + 1/2) / n is never within 2^-21 of an integer.
+template <int DIM>
+__device__ __forceinline__ void tail_decode(int idx, int nx, int ny, float rnx, float rnxy, int& i,
+                                            int& j, int& k) {
+    if (DIM == 2) {
+        j = int((float(idx) + 0.5f) * rnx);
+        i = idx - j * nx;
+        k = 0;
+    } else {
+        k = int((float(idx) + 0.5f) * rnxy);
+        const int r = idx - k * nx * ny;
+        j = int((float(r) + 0.5f) * rnx);
+        i = r - j * nx;
+    }
+}
+
 template <int DIM, typename T, bool CORR>
 __device__ void tail_smooth(const Level<T>& L) {
+    const float rnx = 1.0f / float(L.nx), rnxy = 1.0f / float(L.nx * L.ny);
+    const T inv_lam = T(1) / L.lam;
     for (int color = 0; color < 2; ++color) {
         for (int idx = threadIdx.x; idx < L.n; idx += blockDim.x) {
             int i, j, k;
-            decode<DIM>(idx, L.nx, L.ny, i, j, k);
+            tail_decode<DIM>(idx, L.nx, L.ny, rnx, rnxy, i, j, k);
             if (((i + j + k) & 1) != color) continue;
             T phi, mu, p;
-            cell_solve<DIM, T, CORR>(L, idx, i, j, k, phi, mu, p);
+            cell_solve<DIM, T, CORR>(L, idx, i, j, k, inv_lam, phi, mu, p);
             L.phi[idx] = phi;
             L.mu[idx] = mu;
             L.p[idx] = p;
@@ -34,9 +54,10 @@ __device__ void tail_smooth(const Level<T>& L) {
 
 template <int DIM, typename T, bool CORR>
 __device__ void tail_restrict(const Level<T>& F, const Level<T>& C) {
+    const float rnx = 1.0f / float(C.nx), rnxy = 1.0f / float(C.nx * C.ny);
     for (int idx = threadIdx.x; idx < C.n; idx += blockDim.x) {
         int ci, cj, ck;
-        decode<DIM>(idx, C.nx, C.ny, ci, cj, ck);
+        tail_decode<DIM>(idx, C.nx, C.ny, rnx, rnxy, ci, cj, ck);
         T su0 = 0, su1 = 0, su2 = 0, sr0 = 0, sr1 = 0, sr2 = 0, sb = 0;
 #pragma unroll 1
         for (int dz = 0; dz < (DIM == 3 ? 2 : 1); ++dz)
@@ -67,7 +88,7 @@ __device__ void tail_restrict(const Level<T>& F, const Level<T>& C) {
     __syncthreads();
     for (int idx = threadIdx.x; idx < C.n; idx += blockDim.x) {
         int i, j, k;
-        decode<DIM>(idx, C.nx, C.ny, i, j, k);
+        tail_decode<DIM>(idx, C.nx, C.ny, rnx, rnxy, i, j, k);
         T n0, n1, n2;
         cell_operator<DIM, T, CORR>(C, idx, i, j, k, n0, n1, n2);
         C.f0[idx] += n0;
@@ -79,9 +100,10 @@ __device__ void tail_restrict(const Level<T>& F, const Level<T>& C) {
 
 template <int DIM, typename T>
 __device__ void tail_prolong(const Level<T>& F, const Level<T>& C) {
+    const float rnx = 1.0f / float(F.nx), rnxy = 1.0f / float(F.nx * F.ny);
     for (int idx = threadIdx.x; idx < F.n; idx += blockDim.x) {
         int i, j, k;
-        decode<DIM>(idx, F.nx, F.ny, i, j, k);
+        tail_decode<DIM>(idx, F.nx, F.ny, rnx, rnxy, i, j, k);
         const int c = ((k >> 1) * C.ny + (j >> 1)) * C.nx + (i >> 1);
         F.phi[idx] += C.phi[c] - C.ub0[c];
         F.mu[idx] += C.mu[c] - C.ub1[c];
