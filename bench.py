@@ -21,6 +21,7 @@ if ROOT not in sys.path:
 
 METRIC = "FAS cell-updates/s + HBM roofline %; batched FP32+refine vs plain FP64 at tol"
 HBM_PEAK_GBS = 8000.0
+COPY_BYTES = 256 << 20
 
 
 def log(msg):
@@ -57,6 +58,36 @@ def launch_bytes_per_cell(dim, cls, mixed=False):
     return (4 + 6 + 3) / 2 * 8
 
 
+# Sources of the finest-level 2D smoothing kernels: HBM traffic measured with
+# rocprofv3 counters is reported only while these are unchanged.
+KERNEL_SOURCES = ["chhs_stream2d.hip", "chhs_cell.hpp", "chhs_internal.hpp"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_stream2d_2048_fp64.json")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1611_02967_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, cls):
+    """Scaled FETCH_SIZE + WRITE_SIZE bytes per launch of a kernel class, from the
+    committed counter measurement, or None if it does not cover this workload
+    or the kernel sources changed since it was taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("workload") != workload or rec.get("source_sha256") != kernel_source_hash():
+        return None
+    entry = rec.get("launches", {}).get(cls)
+    return None if entry is None else entry["bytes_per_launch"]
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as fh:
@@ -84,13 +115,16 @@ def oracle_sample(phi_prev, phi_cur, mu, p, w, cycles_per_step):
     t1 = time.perf_counter()
     scheme.residual_norm(scheme.residual(u, f, levels[0], prm), prm.h)
     t2 = time.perf_counter()
-    fas.vcycle(levels, us, 0, prm, fas.Opts())
+    ncyc = 3
+    for _ in range(ncyc):
+        fas.vcycle(levels, us, 0, prm, fas.Opts())
     t3 = time.perf_counter()
-    t_step = (t1 - t0) + (t2 - t1) * (cycles_per_step + 1) + (t3 - t2) * cycles_per_step
+    t_cycle = (t3 - t2) / ncyc
+    t_step = (t1 - t0) + (t2 - t1) * (cycles_per_step + 1) + t_cycle * cycles_per_step
     desc = (f"oracle on the first timed step's input at {n}^2: setup {t1 - t0:.2f}s, one "
-            f"residual {t2 - t1:.2f}s, one V(2,2) cycle {t3 - t2:.2f}s, timed once each; "
-            f"step time = setup + {cycles_per_step:.2f} x (cycle + residual) + residual, "
-            f"with the GPU's mean V-cycles per step")
+            f"residual {t2 - t1:.2f}s, {ncyc} V(2,2) cycles {t3 - t2:.2f}s; step time = setup + "
+            f"{cycles_per_step:.2f} x (cycle + residual) + residual, with the GPU's mean "
+            f"V-cycles per step")
     return phi_cur.size / t_step, desc, t3 - t0
 
 
@@ -204,6 +238,9 @@ def main():
     ap.add_argument("--workload", default="2d-2048-fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="before the timed region, copy a 256 MiB device buffer three times "
+                         "(the known-size kernel that scales rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     ap.add_argument("--no-breakdown", action="store_true",
                     help="skip the per-class timing pass after the timed region")
     ap.add_argument("--smoother", type=int, default=0,
@@ -251,6 +288,14 @@ def main():
     for k in range(args.warmup):
         _, st = sv.step(tp, tc, tm, tpp, 1)
         log(f"warmup step {k + 1}/{args.warmup}: {st[0]['vcycles']} V-cycles, res {st[0]['res_norm']:.2e}")
+    if args.copy_calibration:
+        src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 device copies of {COPY_BYTES} bytes")
+        del src, dst
     torch.cuda.synchronize()
     start_state = [t.cpu().numpy() for t in (tp, tc, tm, tpp)]
     sv.timing(reset=True)
@@ -276,8 +321,9 @@ def main():
                  " (2 fused red-black steps + residual + restriction)" if dim == 2 else " (one color)"),
              "post0": "finest-level post-smoothing launch" + (
                  " (prolongation + 2 fused red-black steps + residual norm)" if dim == 2 else " (one color)")}
+    traffic = measured_traffic(args.workload, cls) if args.smoother == 0 else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": names[cls], "avg_launch_us": round(avg_launch_s * 1e6, 2),
                 "launches": n_k, "algorithmic_bytes_per_launch": bytes_launch}
     other = "post0" if cls == "pre0" else "pre0"
@@ -286,7 +332,9 @@ def main():
         b_o = launch_bytes_per_cell(dim, other, mixed) * cells
         roofline["other_kernel"] = {"kernel": names[other], "avg_launch_us": round(avg_o * 1e6, 2),
                                     "achieved": round(b_o / avg_o / 1e9, 1),
-                                    "algorithmic_bytes_per_launch": b_o}
+                                    "algorithmic_bytes_per_launch": b_o,
+                                    "traffic": measured_traffic(args.workload, other)
+                                    if args.smoother == 0 else None}
     # per-class device time of a few more steps from the same state, every
     # class timed (outside the timed region)
     kernel_ms = {}

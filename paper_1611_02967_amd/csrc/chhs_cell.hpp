@@ -33,6 +33,23 @@ __device__ __forceinline__ void gstore(T* p, int i, T v) {
     const unsigned off = unsigned(i) * unsigned(sizeof(T));
     *(__attribute__((address_space(1))) T*)((__attribute__((address_space(1))) char*)p + off) = v;
 }
+// Streaming variants (non-temporal hint).  Loads: data read once per launch,
+// kept from displacing data that the launch reads again through L2.  Stores:
+// results written once, without the line fills that partially written lines
+// otherwise cause (measured on the strip kernel's write-back: less total
+// traffic although the written bytes grow).
+template <typename T>
+__device__ __forceinline__ T gload_stream(const T* p, int i) {
+    const unsigned off = unsigned(i) * unsigned(sizeof(T));
+    return __builtin_nontemporal_load(
+        (const __attribute__((address_space(1))) T*)((const __attribute__((address_space(1))) char*)p + off));
+}
+template <typename T>
+__device__ __forceinline__ void gstore_stream(T* p, int i, T v) {
+    const unsigned off = unsigned(i) * unsigned(sizeof(T));
+    __builtin_nontemporal_store(
+        v, (__attribute__((address_space(1))) T*)((__attribute__((address_space(1))) char*)p + off));
+}
 
 template <int DIM>
 __device__ __forceinline__ void decode(int idx, int nx, int ny, int& i, int& j, int& k) {

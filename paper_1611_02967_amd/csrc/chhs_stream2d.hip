@@ -152,7 +152,7 @@ __attribute__((amdgpu_waves_per_eu(LEVEL0 || CORR ? 3 : 1))) void k_stream2d(Bat
         const bool ok = lcol && r >= ys && r < ye;
         const int g = ok ? r * nx + lgx : 0;
 #pragma unroll
-        for (int j = 0; j < 2; ++j) v[j] = gload(src[j], g);
+        for (int j = 0; j < 2; ++j) v[j] = gload_stream(src[j], g);
         if (PRO) {
             const int cg = ok ? (r >> 1) * C.nx + (lgx >> 1) : 0;
 #pragma unroll
@@ -306,9 +306,9 @@ __attribute__((amdgpu_waves_per_eu(LEVEL0 || CORR ? 3 : 1))) void k_stream2d(Bat
         const T phic = s[sc][PHI][wc], muc = s[sc][MU][wc], pc = s[sc][P][wc];
         const int g = r * nx + ogx;
         if (own) {
-            gstore(L.phi_alt, g, phic);
-            gstore(L.mu_alt, g, muc);
-            gstore(L.p_alt, g, pc);
+            gstore_stream(L.phi_alt, g, phic);
+            gstore_stream(L.mu_alt, g, muc);
+            gstore_stream(L.p_alt, g, pc);
         }
         if (EPI == 0) return;
         // computed by every lane (halo lanes read clamped, in-bounds words);
