@@ -73,16 +73,19 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(workload, cls):
+def measured_traffic(workload, cls, level0_kernel):
     """Scaled FETCH_SIZE + WRITE_SIZE bytes per launch of a kernel class, from the
-    committed counter measurement, or None if it does not cover this workload
-    or the kernel sources changed since it was taken."""
+    committed counter measurement, or None if it does not cover this workload,
+    the finest level runs another kernel configuration, or the kernel sources
+    changed since it was taken."""
     try:
         with open(TRAFFIC_FILE) as fh:
             rec = json.load(fh)
     except (OSError, ValueError):
         return None
     if rec.get("workload") != workload or rec.get("source_sha256") != kernel_source_hash():
+        return None
+    if list(rec.get("level0_kernel", [])) != list(level0_kernel):
         return None
     entry = rec.get("launches", {}).get(cls)
     return None if entry is None else entry["bytes_per_launch"]
@@ -153,7 +156,8 @@ def run_batched(args):
     tpp = torch.zeros_like(tp)
     sv = chhs.Solver(probs, chhs.chhs_default_opts(tol=1e-10, precision=1,
                                                    timing=chhs.timing_mask("pre0", "post0"),
-                                                   smoother=args.smoother))
+                                                   smoother=args.smoother,
+                                                   autotune=int(args.autotune)))
     for k in range(args.warmup):
         _, st = sv.step(tp, tc, tm, tpp, 1)
         log(f"warmup step {k + 1}/{args.warmup}: max {max(x['vcycles'] for x in st)} refinement steps")
@@ -171,7 +175,8 @@ def run_batched(args):
     # sequential plain FP64: one context per instance, one step each in turn
     seq = []
     for i, pr in enumerate(probs):
-        o = chhs.chhs_default_opts(tol=1e-10, precision=0, smoother=args.smoother)
+        o = chhs.chhs_default_opts(tol=1e-10, precision=0, smoother=args.smoother,
+                                   autotune=int(args.autotune))
         seq.append(chhs.Solver(pr, o))
     views = lambda ts, i: [t[offs[i]:offs[i + 1]] for t in ts]
     sp = [t.clone() for t in start]
@@ -219,6 +224,7 @@ def run_batched(args):
                             "cell_updates_per_s": cells * args.steps / elapsed_seq,
                             "ms_per_round": elapsed_seq / args.steps * 1e3},
         "speedup_vs_sequential_fp64": elapsed_seq / elapsed,
+        "level_kernels": [list(k) for k in sv.level_kernels()],
         "max_abs_err_phi_vs_fp64": err,
         "kernel_ms_timed": {k: round(v[0], 3) for k, v in tim.items() if v[1]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
@@ -243,6 +249,9 @@ def main():
                          "(the known-size kernel that scales rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     ap.add_argument("--no-breakdown", action="store_true",
                     help="skip the per-class timing pass after the timed region")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="use the default smoothing kernels instead of letting chhs_init time "
+                         "the candidates per level and keep the fastest")
     ap.add_argument("--smoother", type=int, default=0,
                     help="2D smoother: 0 default (strips on the finest level), 1 tiles, 2 strips")
     args = ap.parse_args()
@@ -278,7 +287,8 @@ def main():
     # only the finest-level smoothing launches carry HIP events in the timed
     # region (each event pair delays the following launch by a few us)
     opts = chhs.chhs_default_opts(tol=1e-10, timing=chhs.timing_mask("pre0", "post0"),
-                                  smoother=args.smoother, precision=1 if mixed else 0)
+                                  smoother=args.smoother, precision=1 if mixed else 0,
+                                  autotune=int(args.autotune))
     sv = chhs.Solver(prob, opts)
     tp = torch.from_numpy(phi0).cuda()
     tc = tp.clone()
@@ -321,7 +331,8 @@ def main():
                  " (2 fused red-black steps + residual + restriction)" if dim == 2 else " (one color)"),
              "post0": "finest-level post-smoothing launch" + (
                  " (prolongation + 2 fused red-black steps + residual norm)" if dim == 2 else " (one color)")}
-    traffic = measured_traffic(args.workload, cls) if args.smoother == 0 else None
+    level_kernels = sv.level_kernels()
+    traffic = measured_traffic(args.workload, cls, level_kernels[0])
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": names[cls], "avg_launch_us": round(avg_launch_s * 1e6, 2),
@@ -333,14 +344,15 @@ def main():
         roofline["other_kernel"] = {"kernel": names[other], "avg_launch_us": round(avg_o * 1e6, 2),
                                     "achieved": round(b_o / avg_o / 1e9, 1),
                                     "algorithmic_bytes_per_launch": b_o,
-                                    "traffic": measured_traffic(args.workload, other)
-                                    if args.smoother == 0 else None}
+                                    "traffic": measured_traffic(args.workload, other,
+                                                                level_kernels[0])}
     # per-class device time of a few more steps from the same state, every
     # class timed (outside the timed region)
     kernel_ms = {}
     if not args.no_breakdown:
         sb = chhs.Solver(prob, chhs.chhs_default_opts(tol=1e-10, timing=1, smoother=args.smoother,
-                                                      precision=1 if mixed else 0))
+                                                      precision=1 if mixed else 0,
+                                                      autotune=int(args.autotune)))
         st_b = [torch.from_numpy(a).cuda() for a in start_state]
         nb = min(args.steps, 5)
         sb.step(*st_b, 1)
@@ -370,6 +382,7 @@ def main():
         "vcycles_per_step": vcyc / args.steps,
         "res_norm_last": s0["res_norm"],
         "kernel_ms_per_step": kernel_ms,
+        "level_kernels": [list(k) for k in level_kernels],
         "roofline": roofline,
     }
 

@@ -76,6 +76,10 @@ typedef struct chhs_problem {
  * coarser ones), 1 = tiles everywhere, 2 = strips on every level (including
  * the explicit smoothing calls on tail levels).  Both
  * kernels perform the same red-black updates in the same arithmetic.
+ * autotune = 1 (2D, smoother = 0, nu1, nu2 >= 1): chhs_init times, on the problem at hand,
+ * each level's smoothing launches with tiles of 256 and 1024 threads and with
+ * strips of 1, 2 and 4 times the default segment height, and keeps the fastest
+ * per level (the choice then depends on the device; results agree to rounding).
  * reserved must be zero. */
 typedef struct chhs_opts {
     int32_t nu1, nu2, max_vcycles, coarse_sweeps;
@@ -84,7 +88,8 @@ typedef struct chhs_opts {
     int32_t use_graph;
     int32_t timing;
     int32_t smoother;
-    int32_t reserved[4];
+    int32_t autotune;
+    int32_t reserved[3];
 } chhs_opts;
 
 /* Kernel classes of chhs_timing. */
@@ -180,6 +185,14 @@ int chhs_energy_mass(chhs_ctx* c, const double* phi, const double* phi_prev, dou
  * dir 1: dev -> level.  Single-instance contexts only. */
 int chhs_level_count(chhs_ctx* c, int32_t* levels);
 int chhs_level_shape(chhs_ctx* c, int32_t level, int32_t* nxyz3);
+
+/* The smoothing kernel the V-cycle uses on level `level` (counted from the
+ * finest) of the batch: out3[0] = 0 square tiles (out3[1] = threads per block),
+ * 1 row-streaming strips (out3[1] = rows per segment), 2 per-cell kernels (3D),
+ * 3 inside the one-workgroup coarse tail for every instance (out3[1] = 0);
+ * out3[2] = blocks per launch (0 for the tail).  Reflects the autotuner's
+ * choice.  Any batch size; CHHS_E_INVAL for a level no instance has. */
+int chhs_level_kernel(chhs_ctx* c, int32_t level, int32_t* out3);
 int chhs_copy_field(chhs_ctx* c, int32_t level, int32_t field, double* dev, int32_t dir);
 
 /* One smoothing step (red then black collective cell update) on one level,

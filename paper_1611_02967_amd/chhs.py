@@ -36,7 +36,8 @@ class chhs_opts(ctypes.Structure):
                 ("max_vcycles", ctypes.c_int32), ("coarse_sweeps", ctypes.c_int32),
                 ("tol", ctypes.c_double), ("precision", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("timing", ctypes.c_int32),
-                ("smoother", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+                ("smoother", ctypes.c_int32), ("autotune", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
 
 
 K_CLASSES = ["pre0", "post0", "transfer0", "coarse", "norm", "setup", "k6", "k7"]
@@ -84,6 +85,7 @@ _SIGS = {
     "chhs_energy_mass": (_I, [_P, _P, _P, ctypes.POINTER(ctypes.c_double)]),
     "chhs_level_count": (_I, [_P, ctypes.POINTER(ctypes.c_int32)]),
     "chhs_level_shape": (_I, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
+    "chhs_level_kernel": (_I, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     "chhs_copy_field": (_I, [_P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int32]),
     "chhs_smooth": (_I, [_P, ctypes.c_int32, ctypes.c_int32]),
     "chhs_restrict": (_I, [_P, ctypes.c_int32]),
@@ -199,6 +201,16 @@ def chhs_level_count(ctx):
     return n.value
 
 
+KERNEL_KINDS = ["tiles", "strips", "per-cell", "tail"]
+
+
+def chhs_level_kernel(ctx, level):
+    """(kind, threads per block | rows per segment, blocks per launch) of a level."""
+    out = (ctypes.c_int32 * 3)()
+    _check(_lib.chhs_level_kernel(ctx, level, out), "chhs_level_kernel")
+    return KERNEL_KINDS[out[0]], out[1], out[2]
+
+
 def chhs_level_shape(ctx, level):
     out = (ctypes.c_int32 * 3)()
     _check(_lib.chhs_level_shape(ctx, level, out), "chhs_level_shape")
@@ -282,6 +294,17 @@ class Solver:
 
     def timing(self, reset=False):
         return chhs_get_timing(self.ctx, reset)
+
+    def level_kernels(self):
+        """Per level of the batch: (kind, parameter, blocks) as chhs_level_kernel."""
+        out = []
+        level = 0
+        while True:
+            try:
+                out.append(chhs_level_kernel(self.ctx, level))
+            except ChhsError:
+                return out
+            level += 1
 
     def levels(self):
         return [chhs_level_shape(self.ctx, l) for l in range(chhs_level_count(self.ctx))]

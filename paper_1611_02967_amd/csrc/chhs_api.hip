@@ -51,6 +51,10 @@ struct Layout {
     std::vector<std::vector<TileTask>> T, Tall;
     std::vector<std::vector<StripTask>> S, Sall;
     bool strip[kMaxLevels] = {};            // level smoothed by the row-streaming kernel
+    int wide[kMaxLevels] = {};              // tiles: 1 = 1024-thread blocks, 0 = 256, -1 = by count
+    int seg[kMaxLevels] = {};               // rows per strip segment of S[l]
+    // per level and instance: x / y extent of the grids in S[l] (-1: not listed)
+    std::vector<std::vector<int>> snx, sny;
     std::vector<int> tail_insts;
     std::vector<CellTask> A0n;              // finest-level cells of instances without a fused norm
     std::vector<Range> rngA0, rngT0, rngA0n;
@@ -144,6 +148,7 @@ bool valid_opts(const chhs_opts* o) {
     if (!(o->tol > 0.0) || !std::isfinite(o->tol)) return false;
     if (o->precision != 0 && o->precision != 1) return false;
     if (o->smoother < 0 || o->smoother > 2) return false;
+    if (o->autotune < 0 || o->autotune > 1) return false;
     return true;
 }
 
@@ -242,6 +247,25 @@ void ranges_of(std::vector<Range>& r, int n_inst, const std::vector<CellTask>& t
         if (x.end == 0) x.begin = q;
         x.end = q + 1;
     }
+}
+
+// Per-instance ranges of the finest level's smoothing tasks (strips or tiles)
+// in the fused norm partials.
+template <typename Task>
+void task_ranges(std::vector<Range>& r, int n_inst, const std::vector<Task>& tasks) {
+    r.assign(n_inst, Range{0, 0});
+    for (int q = 0; q < int(tasks.size()); ++q) {
+        Range& x = r[tasks[q].inst];
+        if (x.end == 0) x.begin = q;
+        x.end = q + 1;
+    }
+}
+
+void fused_ranges(Layout& L, int n_inst) {
+    if (L.strip[0])
+        task_ranges(L.rngT0, n_inst, L.S[0]);
+    else
+        task_ranges(L.rngT0, n_inst, L.T[0]);
 }
 
 // Builds the layout; base != nullptr fills the device pointers of the descriptors.
@@ -364,7 +388,9 @@ bool plan(const chhs_problem* p, int n_inst, const chhs_opts* o, char* base, Lay
         for (int l = 0; l < kMaxLevels; ++l) {
             const int slots = strip_slots(l == 0 && !mixed, mixed);
             strip_tasks(L.Sall[l], lnx[l], lny[l], strip_seg(lnx[l], lny[l], slots));
-            strip_tasks(L.S[l], lnx_t[l], lny[l], strip_seg(lnx_t[l], lny[l], slots));
+            L.seg[l] = strip_seg(lnx_t[l], lny[l], slots);
+            strip_tasks(L.S[l], lnx_t[l], lny[l], L.seg[l]);
+            L.wide[l] = -1;
             // default: strips on the finest level (long segments, two blocks
             // per compute unit), tiles below, where more and shorter blocks
             // hide latency better
@@ -375,21 +401,12 @@ bool plan(const chhs_problem* p, int n_inst, const chhs_opts* o, char* base, Lay
             L.strip[l] = even && (o->smoother == 2 ? !L.Sall[l].empty()
                                                    : (o->smoother == 0 && l == 0 && !L.T[l].empty()));
         }
+    L.snx = lnx_t;
+    L.sny = lny;
     // per-instance ranges of the finest-level partial buffers
     ranges_of(L.rngA0, n_inst, L.A[0]);
     ranges_of(L.rngA0n, n_inst, L.A0n);
-    L.rngT0.assign(n_inst, Range{0, 0});
-    auto fused_ranges = [&](const auto& tasks) {
-        for (int q = 0; q < int(tasks.size()); ++q) {
-            Range& r = L.rngT0[tasks[q].inst];
-            if (r.end == 0) r.begin = q;
-            r.end = q + 1;
-        }
-    };
-    if (L.strip[0])
-        fused_ranges(L.S[0]);
-    else
-        fused_ranges(L.T[0]);
+    fused_ranges(L, n_inst);
     L.partial_cap = int(L.A[0].size());
     L.partial_t_cap = int(std::max<size_t>(1, std::max(L.T[0].size(), L.S[0].size())));
     L.off_desc = take(L.desc.size() * sizeof(LevelDesc<double>));
@@ -558,8 +575,9 @@ void tiled(chhs_ctx* c, const Hier<T>& H, bool all, int l, int ns, int epi, bool
             chhs::launch_stream2d<T>(b, st.dev, st.n, level0, ns, epi, pro, part, c->stream);
         } else {
             const Table<TileTask>& tt = all ? c->Tall[l] : c->T[l];
-            chhs::launch_tile2d<T>(b, tt.dev, tt.n, level0, ns, epi, pro, tt.n <= kWideTiles, part,
-                                   c->stream);
+            const int w = all ? -1 : c->lay.wide[l];
+            chhs::launch_tile2d<T>(b, tt.dev, tt.n, level0, ns, epi, pro,
+                                   w < 0 ? tt.n <= kWideTiles : w == 1, part, c->stream);
         }
     }
     H.cur[l] ^= 1;
@@ -670,6 +688,112 @@ void enqueue_vcycle(chhs_ctx* c, const Hier<T>& H) {
         }
         if (H.cur[d] != 0) restore_copy0(c, H, d);
     }
+}
+
+// ---- autotuning of the 2D smoothing kernels ----------------------------------------------
+
+// Device time (ms) of one level's pre- and post-smoothing launches as a V-cycle
+// issues them, the best of `reps` repetitions.
+template <typename T>
+float time_level(chhs_ctx* c, const Hier<T>& H, int l, int reps, hipEvent_t ea, hipEvent_t eb) {
+    const chhs_opts& o = c->opts;
+    const bool norm = std::is_same<T, double>::value && l == 0 && c->fused_norm;
+    float best = 1e30f;
+    for (int r = 0; r < reps; ++r) {
+        if (hipEventRecord(ea, c->stream) != hipSuccess) return -1.0f;
+        int rem = o.nu1;
+        while (rem > 2) {
+            tiled(c, H, false, l, 2, 0, false, nullptr, CHHS_K_PRE0);
+            rem -= 2;
+        }
+        tiled(c, H, false, l, rem, 1, false, nullptr, CHHS_K_PRE0);
+        rem = o.nu2;
+        bool first = true;
+        while (rem > 0) {
+            const int k = rem >= 2 ? 2 : 1;
+            rem -= k;
+            tiled(c, H, false, l, k, norm && rem == 0 ? 2 : 0, first, nullptr, CHHS_K_POST0);
+            first = false;
+        }
+        if (hipEventRecord(eb, c->stream) != hipSuccess || hipEventSynchronize(eb) != hipSuccess)
+            return -1.0f;
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, ea, eb) != hipSuccess) return -1.0f;
+        best = std::min(best, ms);
+    }
+    if (H.cur[l] != 0) restore_copy0(c, H, l);
+    return best;
+}
+
+// Picks, per 2D level above the tail, the fastest of: tiles with 256 or 1024
+// threads, strips with 1, 2 or 4 times the default segment height.  Runs the
+// candidates on the workspace as it is (its contents do not matter for the
+// timing and are rewritten by the next setup).
+int autotune(chhs_ctx* c) {
+    Layout& L = c->lay;
+    const chhs_opts saved = c->opts;
+    c->opts.timing = 0;
+    hipEvent_t ea = nullptr, eb = nullptr;
+    if (hipEventCreate(&ea) != hipSuccess || hipEventCreate(&eb) != hipSuccess) return CHHS_E_HIP;
+    int rc = CHHS_OK;
+    for (int l = 0; l < L.depth && rc == CHHS_OK; ++l) {
+        if (c->T[l].n == 0) continue;
+        struct Cand {
+            bool strip;
+            int wide, seg;
+        };
+        std::vector<Cand> cands = {{false, 0, 0}, {false, 1, 0}};
+        bool even = true;
+        int maxny = 0;
+        for (int i = 0; i < c->n_inst; ++i)
+            if (L.snx[l][i] >= 0) {
+                even = even && L.snx[l][i] % 2 == 0;
+                maxny = std::max(maxny, L.sny[l][i]);
+            }
+        const int seg0 = L.seg[l];
+        if (even && c->S[l].n > 0)
+            for (int m = 1; m <= 4; m *= 2) {
+                const int sg = std::min(seg0 * m, (maxny + 1) & ~1);
+                if (m == 1 || sg > cands.back().seg) cands.push_back({true, -1, sg});
+            }
+        const int cap = c->S[l].n;
+        auto apply = [&](const Cand& k) -> int {
+            L.strip[l] = k.strip;
+            L.wide[l] = k.wide;
+            if (!k.strip) return CHHS_OK;
+            L.seg[l] = k.seg;
+            L.S[l].clear();
+            strip_tasks(L.S[l], L.snx[l], L.sny[l], k.seg);
+            if (int(L.S[l].size()) > cap) return CHHS_E_INVAL;
+            c->S[l].n = int(L.S[l].size());
+            HIP_TRY(hipMemcpyAsync(c->S[l].dev, L.S[l].data(), L.S[l].size() * sizeof(StripTask),
+                                   hipMemcpyHostToDevice, c->stream));
+            return CHHS_OK;
+        };
+        float best = 1e30f;
+        int pick = 0;
+        for (int k = 0; k < int(cands.size()) && rc == CHHS_OK; ++k) {
+            rc = apply(cands[k]);
+            if (rc) break;
+            const float ms = c->mixed ? time_level(c, hier32(c), l, 3, ea, eb)
+                                      : time_level(c, hier64(c), l, 3, ea, eb);
+            if (ms < 0.0f) rc = CHHS_E_HIP;
+            if (ms >= 0.0f && ms < best) {
+                best = ms;
+                pick = k;
+            }
+        }
+        if (rc == CHHS_OK) rc = apply(cands[pick]);
+    }
+    (void)hipEventDestroy(ea);
+    (void)hipEventDestroy(eb);
+    c->opts = saved;
+    if (rc) return rc;
+    fused_ranges(L, c->n_inst);
+    HIP_TRY(hipMemcpyAsync(c->rngT0, L.rngT0.data(), c->n_inst * sizeof(Range),
+                           hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return check_launch();
 }
 
 // Plain FP64: one V-cycle, the residual norms (p normalised to mean zero).
@@ -964,6 +1088,10 @@ int chhs_init(const chhs_problem* p, int32_t n_inst, const chhs_opts* o, void* w
     c->heres = c->hres + nres + nint;
     c->fused_norm = !c->mixed && c->dim == 2 && o->nu2 > 0;
     if (hipStreamSynchronize(st) != hipSuccess) return fail(CHHS_E_HIP);
+    if (o->autotune && o->smoother == 0 && c->dim == 2 && o->nu1 > 0 && o->nu2 > 0) {
+        const int arc = autotune(c);
+        if (arc) return fail(arc);
+    }
     *out = c;
     return CHHS_OK;
 }
@@ -1103,6 +1231,31 @@ int chhs_level_shape(chhs_ctx* c, int32_t level, int32_t* nxyz3) {
     nxyz3[0] = d.nx;
     nxyz3[1] = d.ny;
     nxyz3[2] = d.nz;
+    return CHHS_OK;
+}
+
+int chhs_level_kernel(chhs_ctx* c, int32_t level, int32_t* out3) {
+    if (c == nullptr || out3 == nullptr || level < 0 || level >= c->lay.max_nlev)
+        return CHHS_E_INVAL;
+    if (level >= c->lay.depth) {
+        out3[0] = 3;
+        out3[1] = 0;
+        out3[2] = 0;
+    } else if (c->dim == 3) {
+        out3[0] = 2;
+        out3[1] = chhs::kBlock;
+        out3[2] = c->B[level].n;
+    } else if (c->lay.strip[level]) {
+        out3[0] = 1;
+        out3[1] = c->lay.seg[level];
+        out3[2] = c->S[level].n;
+    } else {
+        const int w = c->lay.wide[level];
+        const bool wide = w < 0 ? c->T[level].n <= kWideTiles : w == 1;
+        out3[0] = 0;
+        out3[1] = wide ? 1024 : 256;
+        out3[2] = c->T[level].n;
+    }
     return CHHS_OK;
 }
 

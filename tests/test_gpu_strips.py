@@ -133,3 +133,34 @@ def test_full_size_vcycle_strips_match_tiles(chhs):
     for k in range(3):
         d = np.max(np.abs(res[0][1][k] - res[TILES][1][k]))
         assert d <= 1e-12 * max(1.0, np.max(np.abs(res[TILES][1][k]))), k
+
+
+@pytest.mark.parametrize("spec", [[((256, 256), 0.02, 1.5, 5e-4)],
+                                  [((128, 128), 0.02, 1.0, 1e-4), ((96, 160), 0.03, 2.0, 5e-4),
+                                   ((512, 256), 0.01, 3.0, 1e-4)]], ids=["single", "ragged"])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_autotuned_kernels_match_default_choice(chhs, spec, precision):
+    """chhs_init's autotuner may pick other kernels or segment heights per
+    level; the steps agree with the default choice to rounding and converge
+    to the same tolerance."""
+    shapes = [sp[0] for sp in spec]
+    phi0s = [uniform_field(sh, 550 + i, mean=0.1, amp=0.05) for i, sh in enumerate(shapes)]
+
+    def run(**opts):
+        probs = [chhs.make_problem(sh, 1.0 / sh[-1], e, g, s_) for sh, e, g, s_ in spec]
+        sv = chhs.Solver(probs, chhs.chhs_default_opts(precision=precision, **opts))
+        flat = np.concatenate([a.ravel() for a in phi0s])
+        tp, tc = dev(flat), dev(flat)
+        tm, tpp = dev(np.zeros(flat.size)), dev(np.zeros(flat.size))
+        out = []
+        for _ in range(2):
+            _, st = sv.step(tp, tc, tm, tpp, 1)
+            assert all(x["res_norm"] <= 1e-10 for x in st)
+            out.append(host(tc))
+        return out
+
+    a = run(autotune=1)
+    b = run(autotune=0)
+    tol = 1e-10 if precision == 0 else 1e-8
+    for x, y in zip(a, b):
+        assert np.max(np.abs(x - y)) <= tol
