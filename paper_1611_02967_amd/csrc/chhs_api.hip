@@ -47,7 +47,7 @@ struct Layout {
     std::vector<LevelDesc<double>> desc;       // [inst * kMaxLevels + l] (device pointers)
     std::vector<LevelDesc<float>> desc32;      // FP32 correction hierarchy (mixed precision)
     std::vector<InstInfo> info;
-    std::vector<std::vector<CellTask>> A, B, Bc;
+    std::vector<std::vector<CellTask>> A, B, Bc, Bh;
     std::vector<std::vector<TileTask>> T, Tall;
     std::vector<std::vector<StripTask>> S, Sall;
     bool strip[kMaxLevels] = {};            // level smoothed by the row-streaming kernel
@@ -66,7 +66,7 @@ struct Layout {
     size_t off_A0n = 0, off_partial_t = 0;
     size_t off_partial = 0, off_res = 0, off_eres = 0, off_act_cycle = 0, off_act_next = 0,
            off_cycles = 0;
-    std::vector<size_t> off_A, off_B, off_Bc, off_T, off_Tall, off_S, off_Sall;
+    std::vector<size_t> off_A, off_B, off_Bc, off_Bh, off_T, off_Tall, off_S, off_Sall;
     int partial_cap = 0, partial_t_cap = 0;
 };
 
@@ -85,7 +85,7 @@ struct chhs_ctx {
     LevelDesc<double>* ddesc = nullptr;
     LevelDesc<float>* ddesc32 = nullptr;
     InstInfo* dinfo = nullptr;
-    Table<CellTask> A[kMaxLevels], B[kMaxLevels], Bc[kMaxLevels];
+    Table<CellTask> A[kMaxLevels], B[kMaxLevels], Bc[kMaxLevels], Bh[kMaxLevels];
     Table<TileTask> T[kMaxLevels], Tall[kMaxLevels];
     Table<StripTask> S[kMaxLevels], Sall[kMaxLevels];
     Table<CellTask> A0n;
@@ -100,7 +100,11 @@ struct chhs_ctx {
     int* act_cycle = nullptr;
     int* act_next = nullptr;
     int* cycles = nullptr;
-    // pinned host mirror: res | eres | act_next | cycles
+    // pinned host mirrors of the result block (res | act_next | cycles): two
+    // buffers (the second is the readback target of graph slot 1 of the
+    // pipelined plain cycle loop) and the current view into one of them;
+    // the energies follow the first
+    double* hbuf[2] = {nullptr, nullptr};
     double* hres = nullptr;
     double* heres = nullptr;
     int* hact = nullptr;
@@ -121,6 +125,7 @@ struct chhs_ctx {
     std::vector<Pending> pending;        // resolved and recycled after each sync
     std::vector<Pending> graph_pairs[2]; // recorded by every replay of a graph slot
     int last_slot = -1;                  // slot replayed since the last synchronisation
+    hipEvent_t cycle_done[2] = {nullptr, nullptr};   // end of a pipelined cycle per slot
     double t_ms[CHHS_K_COUNT] = {};
     int64_t t_n[CHHS_K_COUNT] = {};
 };
@@ -276,6 +281,7 @@ bool plan(const chhs_problem* p, int n_inst, const chhs_opts* o, char* base, Lay
     L.A.resize(kMaxLevels);
     L.B.resize(kMaxLevels);
     L.Bc.resize(kMaxLevels);
+    L.Bh.resize(kMaxLevels);
     L.T.resize(kMaxLevels);
     L.Tall.resize(kMaxLevels);
     L.S.resize(kMaxLevels);
@@ -372,6 +378,8 @@ bool plan(const chhs_problem* p, int n_inst, const chhs_opts* o, char* base, Lay
             h *= 2.0;
             cell_tasks(L.A[l], i, n);
             if (l < tail) cell_tasks(L.B[l], i, n);
+            // levels above the tail have even extents: n / 2 cells per color
+            if (l < tail) cell_tasks(L.Bh[l], i, n / 2);
             if (dim == 2) tile_tasks(L.Tall[l], i, d.nx, d.ny);
             if (dim == 2 && l < tail) tile_tasks(L.T[l], i, d.nx, d.ny);
             lnx[l][i] = d.nx;
@@ -420,6 +428,7 @@ bool plan(const chhs_problem* p, int n_inst, const chhs_opts* o, char* base, Lay
     for (int l = 0; l < kMaxLevels; ++l) {
         L.off_A.push_back(take(L.A[l].size() * sizeof(CellTask)));
         L.off_B.push_back(take(L.B[l].size() * sizeof(CellTask)));
+        L.off_Bh.push_back(take(L.Bh[l].size() * sizeof(CellTask)));
         L.off_Bc.push_back(take(L.Bc[l].size() * sizeof(CellTask)));
         L.off_T.push_back(take(L.T[l].size() * sizeof(TileTask)));
         L.off_Tall.push_back(take(L.Tall[l].size() * sizeof(TileTask)));
@@ -641,8 +650,8 @@ void enqueue_vcycle(chhs_ctx* c, const Hier<T>& H) {
                 for (int s = 0; s < o.nu1; ++s)
                     for (int color = 0; color < 2; ++color) {
                         TimedScope t(c, pre_cls);
-                        chhs::launch_smooth(3, make_batch(H.dev, H.cur, d, act), c->B[d].dev,
-                                            c->B[d].n, color, c->stream);
+                        chhs::launch_smooth_color(3, make_batch(H.dev, H.cur, d, act),
+                                                  c->Bh[d].dev, c->Bh[d].n, color, c->stream);
                     }
             TimedScope t(c, xfer_cls);
             chhs::launch_restrict_residual(dim, make_batch(H.dev, H.cur, d, act), c->Bc[d].dev,
@@ -682,8 +691,8 @@ void enqueue_vcycle(chhs_ctx* c, const Hier<T>& H) {
                 for (int s = 0; s < o.nu2; ++s)
                     for (int color = 0; color < 2; ++color) {
                         TimedScope t(c, post_cls);
-                        chhs::launch_smooth(3, make_batch(H.dev, H.cur, d, act), c->B[d].dev,
-                                            c->B[d].n, color, c->stream);
+                        chhs::launch_smooth_color(3, make_batch(H.dev, H.cur, d, act),
+                                                  c->Bh[d].dev, c->Bh[d].n, color, c->stream);
                     }
         }
         if (H.cur[d] != 0) restore_copy0(c, H, d);
@@ -841,13 +850,21 @@ void enqueue_cycle(chhs_ctx* c, bool count) {
         enqueue_plain_cycle(c, count);
 }
 
-// Readback of res | act_next | cycles (contiguous on both sides) into the
-// pinned mirror (enqueued).
-int enqueue_readback(chhs_ctx* c) {
+// Readback of res | act_next | cycles (contiguous on both sides) into pinned
+// mirror `buf` (enqueued).
+int enqueue_readback(chhs_ctx* c, int buf = 0) {
     const int n = c->n_inst;
     const size_t bytes = size_t(n) * chhs::kResStride * sizeof(double) + 2 * n * sizeof(int);
-    HIP_TRY(hipMemcpyAsync(c->hres, c->res, bytes, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->hbuf[buf], c->res, bytes, hipMemcpyDeviceToHost, c->stream));
     return CHHS_OK;
+}
+
+// Points the host view (hres, hact, hcyc) at mirror `buf`.
+void view_results(chhs_ctx* c, int buf) {
+    const size_t nres = size_t(c->n_inst) * chhs::kResStride;
+    c->hres = c->hbuf[buf];
+    c->hact = reinterpret_cast<int*>(c->hres + nres);
+    c->hcyc = c->hact + c->n_inst;
 }
 
 int sync_results(chhs_ctx* c) {
@@ -874,31 +891,38 @@ void drop_graphs(chhs_ctx* c) {
 // readback, replayed from a captured graph when enabled; returns after the
 // results are on the host.  The graph slot is the FP64 finest level's current
 // copy, which a mixed refinement step flips.
+// Captures the counted cycle into graph slot `slot` (reading back into mirror
+// `buf`) unless already captured; on failure graphs are disabled for the
+// context and the eager path is used.
+void ensure_graph(chhs_ctx* c, int slot, int buf) {
+    if (!c->opts.use_graph || c->graph_failed || c->gexec[slot] != nullptr) return;
+    c->capturing = slot;
+    const int saved_cur0 = c->cur[0];
+    bool ok = hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed) == hipSuccess;
+    hipGraph_t g = nullptr;
+    if (ok) {
+        enqueue_cycle(c, true);
+        ok = enqueue_readback(c, buf) == CHHS_OK;
+        ok = (hipStreamEndCapture(c->stream, &g) == hipSuccess) && ok && g != nullptr;
+    }
+    c->capturing = -1;
+    if (ok && hipGraphInstantiate(&c->gexec[slot], g, nullptr, nullptr, 0) != hipSuccess) {
+        c->gexec[slot] = nullptr;
+        ok = false;
+    }
+    c->graph[slot] = g;
+    (void)hipGetLastError();
+    c->cur[0] = saved_cur0;   // the capture did not run anything
+    if (!ok) {
+        c->graph_failed = true;
+        drop_graphs(c);
+    }
+}
+
 int run_cycle(chhs_ctx* c, bool count) {
     const int slot = c->mixed ? c->cur[0] : 0;
-    if (count && c->opts.use_graph && !c->graph_failed && c->gexec[slot] == nullptr) {
-        c->capturing = slot;
-        const int saved_cur0 = c->cur[0];
-        bool ok = hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed) == hipSuccess;
-        hipGraph_t g = nullptr;
-        if (ok) {
-            enqueue_cycle(c, count);
-            ok = enqueue_readback(c) == CHHS_OK;
-            ok = (hipStreamEndCapture(c->stream, &g) == hipSuccess) && ok && g != nullptr;
-        }
-        c->capturing = -1;
-        if (ok && hipGraphInstantiate(&c->gexec[slot], g, nullptr, nullptr, 0) != hipSuccess) {
-            c->gexec[slot] = nullptr;
-            ok = false;
-        }
-        c->graph[slot] = g;
-        (void)hipGetLastError();
-        c->cur[0] = saved_cur0;   // the capture did not run anything
-        if (!ok) {
-            c->graph_failed = true;
-            drop_graphs(c);
-        }
-    }
+    view_results(c, 0);
+    if (count) ensure_graph(c, slot, 0);
     if (count && c->gexec[slot] != nullptr) {
         HIP_TRY(hipGraphLaunch(c->gexec[slot], c->stream));
         c->last_slot = slot;
@@ -911,6 +935,65 @@ int run_cycle(chhs_ctx* c, bool count) {
         if (rc) return rc;
     }
     return sync_results(c);
+}
+
+bool any_active(chhs_ctx* c) {
+    for (int i = 0; i < c->n_inst; ++i)
+        if (c->hact[i]) return true;
+    return false;
+}
+
+// The counted cycles of one step until no instance is active.  Plain FP64
+// with graphs: cycles are pipelined -- cycle k + 1 is enqueued before the
+// host reads cycle k's results, through two graph slots reading back into two
+// mirrors, so the device never waits for the host's stopping test.  The
+// cycle enqueued after the last one finds every instance inactive on the
+// device and does nothing; its timing events are dropped.  Otherwise one
+// cycle at a time.
+int run_cycles(chhs_ctx* c) {
+    if (c->mixed || !c->opts.use_graph || c->graph_failed) {
+        while (any_active(c)) {
+            const int rc = run_cycle(c, true);
+            if (rc) return rc;
+        }
+        return CHHS_OK;
+    }
+    if (!any_active(c)) return CHHS_OK;
+    ensure_graph(c, 0, 0);
+    ensure_graph(c, 1, 1);
+    if (c->gexec[0] == nullptr || c->gexec[1] == nullptr) {
+        while (any_active(c)) {
+            const int rc = run_cycle(c, true);
+            if (rc) return rc;
+        }
+        return CHHS_OK;
+    }
+    for (int s = 0; s < 2; ++s)
+        if (c->cycle_done[s] == nullptr && hipEventCreateWithFlags(&c->cycle_done[s],
+                                                                    hipEventDisableTiming) != hipSuccess)
+            return CHHS_E_HIP;
+    for (int s = 0; s < 2; ++s) {
+        HIP_TRY(hipGraphLaunch(c->gexec[s], c->stream));
+        HIP_TRY(hipEventRecord(c->cycle_done[s], c->stream));
+    }
+    int s = 0;
+    for (;;) {
+        HIP_TRY(hipEventSynchronize(c->cycle_done[s]));
+        for (auto& pe : c->graph_pairs[s]) accumulate(c, pe);
+        view_results(c, s);
+        if (!any_active(c)) {
+            // the cycle in flight in the other slot has no active instance
+            HIP_TRY(hipEventSynchronize(c->cycle_done[s ^ 1]));
+            break;
+        }
+        HIP_TRY(hipGraphLaunch(c->gexec[s], c->stream));
+        HIP_TRY(hipEventRecord(c->cycle_done[s], c->stream));
+        s ^= 1;
+    }
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->last_slot = -1;
+    resolve_timing(c);
+    return CHHS_OK;
 }
 
 // Setup of every instance's step system, p normalised to mean zero, and the
@@ -950,7 +1033,8 @@ int setup(chhs_ctx* c, const double* phi_prev, const double* phi_cur, const doub
     }
     int rc = check_launch();
     if (rc) return rc;
-    rc = enqueue_readback(c);
+    view_results(c, 0);
+    rc = enqueue_readback(c, 0);
     if (rc) return rc;
     c->loaded = true;
     return sync_results(c);
@@ -973,11 +1057,6 @@ int energies(chhs_ctx* c, int ws, const double* phi, const double* q) {
 
 const double* hres_of(chhs_ctx* c, int i) { return c->hres + size_t(i) * chhs::kResStride; }
 
-bool any_active(chhs_ctx* c) {
-    for (int i = 0; i < c->n_inst; ++i)
-        if (c->hact[i]) return true;
-    return false;
-}
 
 }  // namespace
 extern "C" {
@@ -1025,7 +1104,8 @@ int chhs_init(const chhs_problem* p, int32_t n_inst, const chhs_opts* o, void* w
     char* b = c->base;
     int rc = CHHS_OK;
     auto fail = [&](int code) {
-        if (c->hres) (void)hipHostFree(c->hres);
+        for (int k = 0; k < 2; ++k)
+            if (c->hbuf[k]) (void)hipHostFree(c->hbuf[k]);
         delete c;
         return code;
     };
@@ -1067,6 +1147,7 @@ int chhs_init(const chhs_problem* p, int32_t n_inst, const chhs_opts* o, void* w
     for (int l = 0; l < kMaxLevels; ++l) {
         rc |= upload(c->A[l], b, L.off_A[l], L.A[l], st);
         rc |= upload(c->B[l], b, L.off_B[l], L.B[l], st);
+        rc |= upload(c->Bh[l], b, L.off_Bh[l], L.Bh[l], st);
         rc |= upload(c->Bc[l], b, L.off_Bc[l], L.Bc[l], st);
         rc |= upload(c->T[l], b, L.off_T[l], L.T[l], st);
         rc |= upload(c->Tall[l], b, L.off_Tall[l], L.Tall[l], st);
@@ -1080,12 +1161,13 @@ int chhs_init(const chhs_problem* p, int32_t n_inst, const chhs_opts* o, void* w
     const size_t nres = size_t(n_inst) * chhs::kResStride;
     const size_t nint = (2 * size_t(n_inst) * sizeof(int) + sizeof(double) - 1) / sizeof(double);
     const size_t hbytes = (2 * nres + nint) * sizeof(double);
-    if (hipHostMalloc(reinterpret_cast<void**>(&c->hres), hbytes, hipHostMallocDefault) !=
-        hipSuccess)
+    if (hipHostMalloc(reinterpret_cast<void**>(&c->hbuf[0]), hbytes, hipHostMallocDefault) !=
+            hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&c->hbuf[1]), (nres + nint) * sizeof(double),
+                      hipHostMallocDefault) != hipSuccess)
         return fail(CHHS_E_HIP);
-    c->hact = reinterpret_cast<int*>(c->hres + nres);
-    c->hcyc = c->hact + n_inst;
-    c->heres = c->hres + nres + nint;
+    view_results(c, 0);
+    c->heres = c->hbuf[0] + nres + nint;
     c->fused_norm = !c->mixed && c->dim == 2 && o->nu2 > 0;
     if (hipStreamSynchronize(st) != hipSuccess) return fail(CHHS_E_HIP);
     if (o->autotune && o->smoother == 0 && c->dim == 2 && o->nu1 > 0 && o->nu2 > 0) {
@@ -1158,10 +1240,7 @@ int chhs_step(chhs_ctx* c, double* phi_prev, double* phi_cur, double* mu, double
         rc = setup(c, phi_prev, phi_cur, mu, p);
         if (rc) break;
         for (int i = 0; i < n; ++i) st[i].res0 = hres_of(c, i)[3];
-        while (any_active(c)) {
-            rc = run_cycle(c, true);
-            if (rc) break;
-        }
+        rc = run_cycles(c);
         if (rc) break;
         for (int i = 0; i < n; ++i) {
             const double* r = hres_of(c, i);
@@ -1244,7 +1323,7 @@ int chhs_level_kernel(chhs_ctx* c, int32_t level, int32_t* out3) {
     } else if (c->dim == 3) {
         out3[0] = 2;
         out3[1] = chhs::kBlock;
-        out3[2] = c->B[level].n;
+        out3[2] = c->Bh[level].n;
     } else if (c->lay.strip[level]) {
         out3[0] = 1;
         out3[1] = c->lay.seg[level];
@@ -1328,7 +1407,10 @@ void chhs_destroy(chhs_ctx* c) {
     resolve_timing(c);
     drop_graphs(c);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
-    if (c->hres) (void)hipHostFree(c->hres);
+    for (int k = 0; k < 2; ++k) {
+        if (c->cycle_done[k]) (void)hipEventDestroy(c->cycle_done[k]);
+        if (c->hbuf[k]) (void)hipHostFree(c->hbuf[k]);
+    }
     delete c;
 }
 

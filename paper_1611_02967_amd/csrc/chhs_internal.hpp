@@ -137,6 +137,12 @@ void launch_smooth(int dim, const Batch<double>& b, const CellTask* t, int nt, i
                    hipStream_t st);
 void launch_smooth(int dim, const Batch<float>& b, const CellTask* t, int nt, int color,
                    hipStream_t st);
+// One color of one step with one thread per cell of the color (even nx; task
+// cell0 counts cells of the color).
+void launch_smooth_color(int dim, const Batch<double>& b, const CellTask* t, int nt, int color,
+                         hipStream_t st);
+void launch_smooth_color(int dim, const Batch<float>& b, const CellTask* t, int nt, int color,
+                         hipStream_t st);
 void launch_restrict_residual(int dim, const Batch<double>& b, const CellTask* t, int nt,
                               hipStream_t st);
 void launch_restrict_residual(int dim, const Batch<float>& b, const CellTask* t, int nt,

@@ -95,6 +95,32 @@ __global__ __launch_bounds__(kBlock) void k_smooth(Batch<T> b, const CellTask* _
     L.p[idx] = p;
 }
 
+// The same update with threads mapped to the cells of one color only (levels
+// with an even x extent: every row holds nx / 2 cells of each color), so that
+// no lane of a launch idles on the other color.  Task cell0 counts cells of
+// the color.
+template <int DIM, typename T, bool CORR>
+__global__ __launch_bounds__(kBlock) void k_smooth_color(Batch<T> b, const CellTask* __restrict__ t,
+                                                         int color) {
+    const CellTask tk = t[blockIdx.x];
+    if (inactive(b.active, tk.inst)) return;
+    const Level<T> L = view_at(b, tk.inst, b.level, b.cur);
+    const int q = tk.cell0 + threadIdx.x;
+    if (q >= L.n / 2) return;
+    const int hx = L.nx / 2;
+    const int row = q / hx;                       // row index over (j, k)
+    const int m = q - row * hx;
+    const int j = DIM == 2 ? row : row % L.ny;
+    const int k = DIM == 2 ? 0 : row / L.ny;
+    const int i = 2 * m + ((j + k + color) & 1);
+    const int idx = row * L.nx + i;
+    T phi, mu, p;
+    cell_solve<DIM, T, CORR>(L, idx, i, j, k, T(1) / L.lam, phi, mu, p);
+    L.phi[idx] = phi;
+    L.mu[idx] = mu;
+    L.p[idx] = p;
+}
+
 // Per coarse cell: u_c = R u, ub_c = u_c, f_c = R(f - N(u)) (the N_c(u_c) part
 // is added by k_coarse_rhs once all of u_c is written).
 template <int DIM, typename T, bool CORR>
@@ -552,6 +578,10 @@ void launch_smooth(int dim, const Batch<double>& b, const CellTask* t, int nt, i
                    hipStream_t st) {
     CHHS_DISPATCH_T(dim, k_smooth, nt, b, t, color);
 }
+void launch_smooth_color(int dim, const Batch<double>& b, const CellTask* t, int nt, int color,
+                         hipStream_t st) {
+    CHHS_DISPATCH_T(dim, k_smooth_color, nt, b, t, color);
+}
 void launch_restrict_residual(int dim, const Batch<double>& b, const CellTask* t, int nt,
                               hipStream_t st) {
     CHHS_DISPATCH_T(dim, k_restrict_residual, nt, b, t);
@@ -564,6 +594,10 @@ void launch_coarse_rhs(int dim, const Batch<double>& b, const CellTask* t, int n
 void launch_smooth(int dim, const Batch<float>& b, const CellTask* t, int nt, int color,
                    hipStream_t st) {
     CHHS_DISPATCH_T(dim, k_smooth, nt, b, t, color);
+}
+void launch_smooth_color(int dim, const Batch<float>& b, const CellTask* t, int nt, int color,
+                         hipStream_t st) {
+    CHHS_DISPATCH_T(dim, k_smooth_color, nt, b, t, color);
 }
 void launch_restrict_residual(int dim, const Batch<float>& b, const CellTask* t, int nt,
                               hipStream_t st) {
