@@ -47,7 +47,7 @@ struct Layout {
     std::vector<LevelDesc<double>> desc;       // [inst * kMaxLevels + l] (device pointers)
     std::vector<LevelDesc<float>> desc32;      // FP32 correction hierarchy (mixed precision)
     std::vector<InstInfo> info;
-    std::vector<std::vector<CellTask>> A, B, Bc, Bh;
+    std::vector<std::vector<CellTask>> A, B, Bc, Bh, Bcs;
     std::vector<std::vector<TileTask>> T, Tall;
     std::vector<std::vector<StripTask>> S, Sall;
     bool strip[kMaxLevels] = {};            // level smoothed by the row-streaming kernel
@@ -66,7 +66,7 @@ struct Layout {
     size_t off_A0n = 0, off_partial_t = 0;
     size_t off_partial = 0, off_res = 0, off_eres = 0, off_act_cycle = 0, off_act_next = 0,
            off_cycles = 0;
-    std::vector<size_t> off_A, off_B, off_Bc, off_Bh, off_T, off_Tall, off_S, off_Sall;
+    std::vector<size_t> off_A, off_B, off_Bc, off_Bh, off_Bcs, off_T, off_Tall, off_S, off_Sall;
     int partial_cap = 0, partial_t_cap = 0;
 };
 
@@ -85,7 +85,8 @@ struct chhs_ctx {
     LevelDesc<double>* ddesc = nullptr;
     LevelDesc<float>* ddesc32 = nullptr;
     InstInfo* dinfo = nullptr;
-    Table<CellTask> A[kMaxLevels], B[kMaxLevels], Bc[kMaxLevels], Bh[kMaxLevels];
+    Table<CellTask> A[kMaxLevels], B[kMaxLevels], Bc[kMaxLevels], Bh[kMaxLevels],
+        Bcs[kMaxLevels];
     Table<TileTask> T[kMaxLevels], Tall[kMaxLevels];
     Table<StripTask> S[kMaxLevels], Sall[kMaxLevels];
     Table<CellTask> A0n;
@@ -282,6 +283,7 @@ bool plan(const chhs_problem* p, int n_inst, const chhs_opts* o, char* base, Lay
     L.B.resize(kMaxLevels);
     L.Bc.resize(kMaxLevels);
     L.Bh.resize(kMaxLevels);
+    L.Bcs.resize(kMaxLevels);
     L.T.resize(kMaxLevels);
     L.Tall.resize(kMaxLevels);
     L.S.resize(kMaxLevels);
@@ -348,6 +350,7 @@ bool plan(const chhs_problem* p, int n_inst, const chhs_opts* o, char* base, Lay
             if (l > 0)
                 for (int k = 0; k < 3; ++k) d.ub[k] = ptr(take(nb));
             for (int k = 0; k < 3; ++k) d.f[k] = ptr(take(nb));
+            for (int k = 0; k < 3; ++k) d.fr[k] = l > 0 ? ptr(take(nb)) : nullptr;
             d.pstar = ptr(take(nb));
             d.psi = ptr(take(nb));
             d.b = nullptr;
@@ -367,6 +370,7 @@ bool plan(const chhs_problem* p, int n_inst, const chhs_opts* o, char* base, Lay
                 if (l > 0)
                     for (int k = 0; k < 3; ++k) e.ub[k] = ptr32(take(nf));
                 for (int k = 0; k < 3; ++k) e.f[k] = ptr32(take(nf));
+                for (int k = 0; k < 3; ++k) e.fr[k] = l > 0 ? ptr32(take(nf)) : nullptr;
                 e.pstar = ptr32(take(nf));
                 e.psi = ptr32(take(nf));
                 e.b = ptr32(take(nf));
@@ -387,6 +391,8 @@ bool plan(const chhs_problem* p, int n_inst, const chhs_opts* o, char* base, Lay
             if (l < tail) lnx_t[l][i] = d.nx;
         }
         for (int l = 0; l + 1 < nlev && l < tail; ++l) cell_tasks(L.Bc[l], i, cells[l + 1]);
+        // coarse levels above the tail (the tail forms its top level's f itself)
+        for (int l = 0; l + 1 < tail; ++l) cell_tasks(L.Bcs[l], i, cells[l + 1]);
         if (!in.fused) cell_tasks(L.A0n, i, cells[0]);
         L.tail_insts.push_back(i);
     }
@@ -429,6 +435,7 @@ bool plan(const chhs_problem* p, int n_inst, const chhs_opts* o, char* base, Lay
         L.off_A.push_back(take(L.A[l].size() * sizeof(CellTask)));
         L.off_B.push_back(take(L.B[l].size() * sizeof(CellTask)));
         L.off_Bh.push_back(take(L.Bh[l].size() * sizeof(CellTask)));
+        L.off_Bcs.push_back(take(L.Bcs[l].size() * sizeof(CellTask)));
         L.off_Bc.push_back(take(L.Bc[l].size() * sizeof(CellTask)));
         L.off_T.push_back(take(L.T[l].size() * sizeof(TileTask)));
         L.off_Tall.push_back(take(L.Tall[l].size() * sizeof(TileTask)));
@@ -573,7 +580,7 @@ Hier<float> hier32(chhs_ctx* c) { return {c->ddesc32, &c->lay.desc32, c->cur32, 
 // flips the level's current copy.
 template <typename T>
 void tiled(chhs_ctx* c, const Hier<T>& H, bool all, int l, int ns, int epi, bool pro,
-           const int* active, int cls) {
+           const int* active, int cls, bool rhs = false) {
     Batch<T> b = make_batch(H.dev, H.cur, l, active);
     const bool level0 = std::is_same<T, double>::value && l == 0;
     double* part = epi == 2 ? c->partial_t : nullptr;
@@ -586,7 +593,7 @@ void tiled(chhs_ctx* c, const Hier<T>& H, bool all, int l, int ns, int epi, bool
             const Table<TileTask>& tt = all ? c->Tall[l] : c->T[l];
             const int w = all ? -1 : c->lay.wide[l];
             chhs::launch_tile2d<T>(b, tt.dev, tt.n, level0, ns, epi, pro,
-                                   w < 0 ? tt.n <= kWideTiles : w == 1, part, c->stream);
+                                   w < 0 ? tt.n <= kWideTiles : w == 1, rhs, part, c->stream);
         }
     }
     H.cur[l] ^= 1;
@@ -639,12 +646,16 @@ void enqueue_vcycle(chhs_ctx* c, const Hier<T>& H) {
         const int pre_cls = d == 0 ? CHHS_K_PRE0 : CHHS_K_COARSE;
         const int xfer_cls = d == 0 ? CHHS_K_TRANSFER0 : CHHS_K_COARSE;
         if (dim == 2 && o.nu1 > 0) {
+            // on a tiled coarse level the first launch forms f = fr + N(u)
+            const bool rhs = d > 0 && !c->lay.strip[d];
+            bool first = true;
             int rem = o.nu1;
             while (rem > 2) {
-                tiled(c, H, false, d, 2, 0, false, act, pre_cls);
+                tiled(c, H, false, d, 2, 0, false, act, pre_cls, rhs && first);
+                first = false;
                 rem -= 2;
             }
-            tiled(c, H, false, d, rem, 1, false, act, pre_cls);
+            tiled(c, H, false, d, rem, 1, false, act, pre_cls, rhs && first);
         } else {
             if (dim == 3)
                 for (int s = 0; s < o.nu1; ++s)
@@ -657,9 +668,14 @@ void enqueue_vcycle(chhs_ctx* c, const Hier<T>& H) {
             chhs::launch_restrict_residual(dim, make_batch(H.dev, H.cur, d, act), c->Bc[d].dev,
                                            c->Bc[d].n, c->stream);
         }
-        TimedScope t(c, xfer_cls);
-        chhs::launch_coarse_rhs(dim, make_batch(H.dev, H.cur, d, act), c->Bc[d].dev, c->Bc[d].n,
-                                c->stream);
+        // level d + 1's right-hand side f = fr + N(u), unless its first tiled
+        // launch forms it (tail levels: the tail does)
+        const bool fused_next = dim == 2 && o.nu1 > 0 && d + 1 < depth && !c->lay.strip[d + 1];
+        if (!fused_next && c->Bcs[d].n > 0) {
+            TimedScope t(c, xfer_cls);
+            chhs::launch_coarse_rhs(dim, make_batch(H.dev, H.cur, d, act), c->Bcs[d].dev,
+                                    c->Bcs[d].n, c->stream);
+        }
     }
     {
         // an instance's tail level is only ever written by the restriction into
@@ -710,19 +726,27 @@ float time_level(chhs_ctx* c, const Hier<T>& H, int l, int reps, hipEvent_t ea, 
     float best = 1e30f;
     for (int r = 0; r < reps; ++r) {
         if (hipEventRecord(ea, c->stream) != hipSuccess) return -1.0f;
+        // the level's right-hand side: formed by its first tiled launch, or
+        // by a separate launch before strips
+        const bool rhs = l > 0 && !c->lay.strip[l];
+        if (l > 0 && c->lay.strip[l] && c->Bcs[l - 1].n > 0)
+            chhs::launch_coarse_rhs(2, make_batch(H.dev, H.cur, l - 1, nullptr), c->Bcs[l - 1].dev,
+                                    c->Bcs[l - 1].n, c->stream);
+        bool first = true;
         int rem = o.nu1;
         while (rem > 2) {
-            tiled(c, H, false, l, 2, 0, false, nullptr, CHHS_K_PRE0);
+            tiled(c, H, false, l, 2, 0, false, nullptr, CHHS_K_PRE0, rhs && first);
+            first = false;
             rem -= 2;
         }
-        tiled(c, H, false, l, rem, 1, false, nullptr, CHHS_K_PRE0);
+        tiled(c, H, false, l, rem, 1, false, nullptr, CHHS_K_PRE0, rhs && first);
         rem = o.nu2;
-        bool first = true;
+        bool pro = true;
         while (rem > 0) {
             const int k = rem >= 2 ? 2 : 1;
             rem -= k;
-            tiled(c, H, false, l, k, norm && rem == 0 ? 2 : 0, first, nullptr, CHHS_K_POST0);
-            first = false;
+            tiled(c, H, false, l, k, norm && rem == 0 ? 2 : 0, pro, nullptr, CHHS_K_POST0);
+            pro = false;
         }
         if (hipEventRecord(eb, c->stream) != hipSuccess || hipEventSynchronize(eb) != hipSuccess)
             return -1.0f;
@@ -1148,6 +1172,7 @@ int chhs_init(const chhs_problem* p, int32_t n_inst, const chhs_opts* o, void* w
         rc |= upload(c->A[l], b, L.off_A[l], L.A[l], st);
         rc |= upload(c->B[l], b, L.off_B[l], L.B[l], st);
         rc |= upload(c->Bh[l], b, L.off_Bh[l], L.Bh[l], st);
+        rc |= upload(c->Bcs[l], b, L.off_Bcs[l], L.Bcs[l], st);
         rc |= upload(c->Bc[l], b, L.off_Bc[l], L.Bc[l], st);
         rc |= upload(c->T[l], b, L.off_T[l], L.T[l], st);
         rc |= upload(c->Tall[l], b, L.off_Tall[l], L.Tall[l], st);

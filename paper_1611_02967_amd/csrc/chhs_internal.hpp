@@ -30,6 +30,10 @@ constexpr int kResStride = 16;       // doubles per instance in the result area
 //                         copy, written by out-of-place kernels
 //   ub                    u as restricted from the finer level (FAS)
 //   f                     right-hand side of the three rows of (2.5)-(2.7)
+//   fr                    coarse levels: the restricted residual R(f - N(u)) of
+//                         the finer level, from which the FAS right-hand side
+//                         f = fr + N(u) is formed (out of place, so that a
+//                         kernel forming f never races a neighbour's read)
 //   pstar, psi            phi_* (2.4) and phi^m (second argument of chi), cell
 //                         averages of the finer level's on coarse levels
 //   b                     base state of the correction form (mixed precision
@@ -46,6 +50,9 @@ struct Level {
     T* f0;
     T* f1;
     T* f2;
+    T* fr0;
+    T* fr1;
+    T* fr2;
     T* pstar;
     T* psi;
     T* b;
@@ -63,6 +70,7 @@ struct LevelDesc {
     T* u[2][3];
     T* ub[3];
     T* f[3];
+    T* fr[3];
     T* pstar;
     T* psi;
     T* b;
@@ -85,6 +93,9 @@ __host__ __device__ inline Level<T> make_view(const LevelDesc<T>& d, int cur) {
     v.f0 = d.f[0];
     v.f1 = d.f[1];
     v.f2 = d.f[2];
+    v.fr0 = d.fr[0];
+    v.fr1 = d.fr[1];
+    v.fr2 = d.fr[2];
     v.pstar = d.pstar;
     v.psi = d.psi;
     v.b = d.b;
@@ -209,10 +220,12 @@ constexpr int kTileY = CHHS_TILE_Y;
 // into level + 1 (copy b.cur_c), 2 residual-norm partials (4 per block, in task
 // order); pro: prolongation of level + 1's correction first; level0: f_phi =
 // phi^m and f_p = 0 implied; wide: 1024 threads per block (one pair of cells
-// per thread) instead of 256, for levels with fewer tiles than compute units.
+// per thread) instead of 256, for levels with fewer tiles than compute units;
+// rhs: first pre-smoothing launch on a coarse level, which first forms the FAS
+// right-hand side f += N(u) (not with level0, pro or epi 2).
 template <typename T>
 void launch_tile2d(const Batch<T>& b, const TileTask* t, int nt, bool level0, int ns, int epi,
-                   bool pro, bool wide, double* partial, hipStream_t st);
+                   bool pro, bool wide, bool rhs, double* partial, hipStream_t st);
 
 // ---- row-streaming 2D smoothing (chhs_stream2d.hip) ---------------------------------
 // Strip sx owns columns [sx kStripWO, (sx + 1) kStripWO) and stages kStripW

@@ -156,9 +156,9 @@ __global__ __launch_bounds__(kBlock) void k_restrict_residual(Batch<T> b,
     C.phi[idx] = C.ub0[idx] = su0 * w;
     C.mu[idx] = C.ub1[idx] = su1 * w;
     C.p[idx] = C.ub2[idx] = su2 * w;
-    C.f0[idx] = sr0 * w;
-    C.f1[idx] = sr1 * w;
-    C.f2[idx] = sr2 * w;
+    C.fr0[idx] = sr0 * w;
+    C.fr1[idx] = sr1 * w;
+    C.fr2[idx] = sr2 * w;
 }
 
 // tasks over coarse cells: f_c += N_c(u_c)
@@ -174,9 +174,9 @@ __global__ __launch_bounds__(kBlock) void k_coarse_rhs(Batch<T> b,
     decode<DIM>(idx, C.nx, C.ny, i, j, k);
     T n0, n1, n2;
     cell_operator<DIM, T, CORR>(C, idx, i, j, k, n0, n1, n2);
-    C.f0[idx] += n0;
-    C.f1[idx] += n1;
-    C.f2[idx] += n2;
+    C.f0[idx] = C.fr0[idx] + n0;
+    C.f1[idx] = C.fr1[idx] + n1;
+    C.f2[idx] = C.fr2[idx] + n2;
 }
 
 // tasks over fine cells: u += P(u_c - ub_c)

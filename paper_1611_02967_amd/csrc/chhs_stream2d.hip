@@ -31,7 +31,7 @@
 // Optional fused parts, as in the tiled kernel:
 //   PRO    u += P(u_c - ub_c) applied while loading (halo included).
 //   EPI 1  residual R = f - N(u) on the owned cells restricted by cell
-//          averaging: u_c = ub_c = R u, f_c = R R on level + 1 (copy b.cur_c).
+//          averaging: u_c = ub_c = R u, fr_c = R R on level + 1 (copy b.cur_c).
 //   EPI 2  per-task partial sums of R_phi^2, R_mu^2, R_p^2 and p.
 //   CORR   correction form of the mixed-precision inner solve.
 #include "chhs_cell.hpp"
@@ -388,9 +388,9 @@ __attribute__((amdgpu_waves_per_eu(LEVEL0 || CORR ? 3 : 1))) void k_stream2d(Bat
             gstore(C.ub1, cgi, v[4] * w);
             gstore(C.p, cgi, v[5] * w);
             gstore(C.ub2, cgi, v[5] * w);
-            gstore(C.f0, cgi, v[0] * w);
-            gstore(C.f1, cgi, v[1] * w);
-            gstore(C.f2, cgi, v[2] * w);
+            gstore(C.fr0, cgi, v[0] * w);
+            gstore(C.fr1, cgi, v[1] * w);
+            gstore(C.fr2, cgi, v[2] * w);
             if (CORR) gstore(C.b, cgi, v[6] * w);
         }
     };

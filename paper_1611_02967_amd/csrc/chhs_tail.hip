@@ -133,6 +133,7 @@ __device__ __forceinline__ Level<T> lds_view(const LevelDesc<T>* d, int tail, in
     v.f0 = b + 6 * n;
     v.f1 = b + 7 * n;
     v.f2 = b + 8 * n;
+    v.fr0 = v.fr1 = v.fr2 = nullptr;
     v.pstar = b + 9 * n;
     v.psi = b + 10 * n;
     v.b = CORR ? b + 11 * n : nullptr;
@@ -159,14 +160,19 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(const LevelDesc<T>* __res
     // frozen data
     const Level<T> G = make_view(d[top], (cur_mask >> top) & 1u);
     {
+        // a top level below the finest one holds the restricted residual fr;
+        // its FAS right-hand side f = fr + N(u) is formed below
         const Level<T> S = lds_view<T, CORR>(d, top, top, base);
+        const T* g0 = top > 0 ? G.fr0 : G.f0;
+        const T* g1 = top > 0 ? G.fr1 : G.f1;
+        const T* g2 = top > 0 ? G.fr2 : G.f2;
         for (int idx = threadIdx.x; idx < G.n; idx += blockDim.x) {
             S.phi[idx] = G.phi[idx];
             S.mu[idx] = G.mu[idx];
             S.p[idx] = G.p[idx];
-            S.f0[idx] = G.f0[idx];
-            S.f1[idx] = G.f1[idx];
-            S.f2[idx] = G.f2[idx];
+            S.f0[idx] = g0[idx];
+            S.f1[idx] = g1[idx];
+            S.f2[idx] = g2[idx];
             if (CORR) S.b[idx] = G.b[idx];
         }
         for (int l = top; l < nlev; ++l) {
@@ -179,6 +185,20 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(const LevelDesc<T>* __res
         }
     }
     __syncthreads();
+    if (top > 0) {
+        const Level<T> S = lds_view<T, CORR>(d, top, top, base);
+        const float rnx = 1.0f / float(S.nx), rnxy = 1.0f / float(S.nx * S.ny);
+        for (int idx = threadIdx.x; idx < S.n; idx += blockDim.x) {
+            int i, j, k;
+            tail_decode<DIM>(idx, S.nx, S.ny, rnx, rnxy, i, j, k);
+            T n0, n1, n2;
+            cell_operator<DIM, T, CORR>(S, idx, i, j, k, n0, n1, n2);
+            S.f0[idx] += n0;
+            S.f1[idx] += n1;
+            S.f2[idx] += n2;
+        }
+        __syncthreads();
+    }
 
     const int last = nlev - 1;
     for (int l = top; l < last; ++l) {

@@ -17,11 +17,16 @@
 //   PRO    prologue: u += P(u_c - ub_c) (piecewise-constant prolongation of the
 //          coarse correction) applied while loading, halo included.
 //   EPI 1  epilogue: residual R = f - N(u) on the block (X = 1) restricted by
-//          cell averaging to the coarse level: u_c = ub_c = R u, f_c = R R
-//          (the N_c(u_c) part follows in a coarse kernel).
+//          cell averaging to the coarse level: u_c = ub_c = R u, fr_c = R R
+//          (f_c = fr_c + N_c(u_c) is formed by the coarse level's first
+//          launch, the coarse tail, or a coarse kernel).
 //   EPI 2  epilogue: per-block partial sums of R_phi^2, R_mu^2, R_p^2 and p.
 //   CORR   correction form of the mixed-precision inner solve (chhs_cell.hpp):
 //          the base state b is read per cell and restricted with u.
+//   RHS    prologue of the first smoothing launch on a coarse level: the FAS
+//          right-hand side f += N(u) (u = the restricted iterate, f = the
+//          restricted residual) on every cell a phase may update, the block's
+//          cells written back; replaces a separate launch over the level.
 //
 // Threads own pairs of horizontally adjacent cells (x even, x + 1) so that
 // exactly one cell of every pair has the color of a phase: all lanes work in
@@ -58,7 +63,7 @@ struct Geometry {
 template <int PW>
 __device__ __forceinline__ int lds(int r, int x) { return (2 * r + (x & 1)) * PW + (x >> 1); }
 
-template <typename T, bool LEVEL0, int NS, int EPI, bool PRO, bool CORR, int NT>
+template <typename T, bool LEVEL0, int NS, int EPI, bool PRO, bool CORR, int NT, bool RHS>
 __global__ __launch_bounds__(NT) void k_tile2d(Batch<T> bt, const TileTask* __restrict__ tasks,
                                                int ntiles, double* partial) {
     using G = Geometry<NS, EPI, NT>;
@@ -109,12 +114,13 @@ __global__ __launch_bounds__(NT) void k_tile2d(Batch<T> bt, const TileTask* __re
                 p = gload(L.p, g);
                 ps = gload(L.pstar, g);
                 psi = gload(L.psi, g);
-                f1 = gload(L.f1, g);
+                // the first launch on a coarse level forms f from the restricted residual
+                f1 = gload(RHS ? L.fr1 : L.f1, g);
                 if (LEVEL0) {
                     f0 = psi;
                 } else {
-                    f0 = gload(L.f0, g);
-                    f2 = gload(L.f2, g);
+                    f0 = gload(RHS ? L.fr0 : L.f0, g);
+                    f2 = gload(RHS ? L.fr2 : L.f2, g);
                 }
                 if (CORR) bs = gload(L.b, g);
                 if (PRO) {
@@ -169,6 +175,74 @@ __global__ __launch_bounds__(NT) void k_tile2d(Batch<T> bt, const TileTask* __re
 
     const T lam = L.lam, kap = L.kap, gam = L.gamma;
     const T inv_lam = T(1) / lam;
+
+    if (RHS) {
+        // f += N(u) on every cell within ring H - 1 of the block (the cells
+        // the phases update; their neighbours are in the region)
+#pragma unroll
+        for (int k = 0; k < KP; ++k) {
+            const int q = tid + k * kThreads;
+            if (q >= NP) continue;
+            const int r = q / PW, xp = 2 * (q % PW);
+            const int gy = y0 + r;
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const int x = xp + e;
+                const int gx = x0 + x;
+                if (gx < 0 || gx >= nx || gy < 0 || gy >= ny) continue;
+                const int dx = x < HX ? HX - x : (x >= HX + kTX ? x - (HX + kTX - 1) : 0);
+                const int dy = r < H ? H - r : (r >= H + kTY ? r - (H + kTY - 1) : 0);
+                if ((dx > dy ? dx : dy) > H - 1) continue;
+                const bool red = ((e + gy) & 1) == 0;
+                const int wc = lds<PW>(r, x);
+                const T phic = s_phi[wc], muc = s_mu[wc], pc = s_p[wc], psc = s_ps[wc];
+                T smm = 0, sap = 0, sphi = 0, sp = 0, samu = 0;
+                auto nb_n = [&](int rr, int xx) {
+                    const int w = lds<PW>(rr, xx);
+                    const T a = T(0.5) * (psc + s_ps[w]);
+                    const T m = T(1) + gam * a * a;
+                    const T dmu = s_mu[w] - muc;
+                    const T dp = s_p[w] - pc;
+                    smm += m * dmu;
+                    sap += a * dp;
+                    sphi += s_phi[w] - phic;
+                    sp += dp;
+                    samu += a * dmu;
+                };
+                if (gx > 0) nb_n(r, x - 1);
+                if (gx < nx - 1) nb_n(r, x + 1);
+                if (gy > 0) nb_n(r - 1, x);
+                if (gy < ny - 1) nb_n(r + 1, x);
+                // select values, not addresses, so that the arrays stay in registers
+                const T psi0 = o_psi[0][k], psi1 = o_psi[1][k], b0 = o_b[0][k], b1 = o_b[1][k];
+                const T fa0 = o_f0[0][k], fb0 = o_f0[1][k], fa1 = o_f1[0][k], fb1 = o_f1[1][k];
+                const T fa2 = o_f2[0][k], fb2 = o_f2[1][k];
+                const T psi = red ? psi0 : psi1;
+                const T bg = red ? b0 : b1;
+                const T n0 = phic - lam * smm - lam * sap;
+                const T n1 = muc - nonlin<T, CORR>(phic, psi, bg) + kap * sphi;
+                const T n2 = lam * sp + lam * gam * samu;
+                const T f0 = (red ? fa0 : fb0) + n0;
+                const T f1 = (red ? fa1 : fb1) + n1;
+                const T f2 = (red ? fa2 : fb2) + n2;
+                o_f0[0][k] = red ? f0 : fa0;
+                o_f0[1][k] = red ? fb0 : f0;
+                o_f1[0][k] = red ? f1 : fa1;
+                o_f1[1][k] = red ? fb1 : f1;
+                o_f2[0][k] = red ? f2 : fa2;
+                o_f2[1][k] = red ? fb2 : f2;
+                if (r >= H && r < H + kTY && x >= HX && x < HX + kTX) {
+                    const int g = gy * nx + gx;
+                    gstore(L.f0, g, f0);
+                    gstore(L.f1, g, f1);
+                    gstore(L.f2, g, f2);
+                }
+            }
+        }
+        // the first phase overwrites cells whose values other waves still read here
+        __syncthreads();
+    }
+
 #pragma unroll
     for (int ph = 0; ph < 2 * NS; ++ph) {
         const int color = ph & 1;
@@ -336,9 +410,9 @@ __global__ __launch_bounds__(NT) void k_tile2d(Batch<T> bt, const TileTask* __re
                 gstore(C.ub1, c, su[1] * w);
                 gstore(C.p, c, su[2] * w);
                 gstore(C.ub2, c, su[2] * w);
-                gstore(C.f0, c, sr[0] * w);
-                gstore(C.f1, c, sr[1] * w);
-                gstore(C.f2, c, sr[2] * w);
+                gstore(C.fr0, c, sr[0] * w);
+                gstore(C.fr1, c, sr[1] * w);
+                gstore(C.fr2, c, sr[2] * w);
                 if (CORR) gstore(C.b, c, sb * w);
             }
         }
@@ -359,23 +433,39 @@ __global__ __launch_bounds__(NT) void k_tile2d(Batch<T> bt, const TileTask* __re
         }
 }
 
-template <typename T, bool LEVEL0, int NS, int EPI, bool PRO, bool CORR>
+template <typename T, bool LEVEL0, int NS, int EPI, bool PRO, bool CORR, bool RHS = false>
 void launch_one(const Batch<T>& b, const TileTask* t, int nt, bool wide, double* partial,
                 hipStream_t st) {
     if (wide)
-        hipLaunchKernelGGL((k_tile2d<T, LEVEL0, NS, EPI, PRO, CORR, 1024>), dim3(nt), dim3(1024), 0,
-                           st, b, t, nt, partial);
+        hipLaunchKernelGGL((k_tile2d<T, LEVEL0, NS, EPI, PRO, CORR, 1024, RHS>), dim3(nt), dim3(1024),
+                           0, st, b, t, nt, partial);
     else
-        hipLaunchKernelGGL((k_tile2d<T, LEVEL0, NS, EPI, PRO, CORR, 256>), dim3(nt), dim3(256), 0,
-                           st, b, t, nt, partial);
+        hipLaunchKernelGGL((k_tile2d<T, LEVEL0, NS, EPI, PRO, CORR, 256, RHS>), dim3(nt), dim3(256),
+                           0, st, b, t, nt, partial);
 }
 
 }  // namespace
 
 template <>
 void launch_tile2d<double>(const Batch<double>& b, const TileTask* t, int nt, bool level0, int ns,
-                           int epi, bool pro, bool wide, double* partial, hipStream_t st) {
+                           int epi, bool pro, bool wide, bool rhs, double* partial,
+                           hipStream_t st) {
     if (nt <= 0) return;
+    if (rhs) {
+        // first pre-smoothing launch of a coarse level (no prolongation)
+        if (level0 || pro || epi == 2) return;
+#define CHHS_TILE_RHS(NS, EPI)                                                    \
+    if (ns == NS && epi == EPI) {                                                 \
+        launch_one<double, false, NS, EPI, false, false, true>(b, t, nt, wide, partial, st); \
+        return;                                                                   \
+    }
+        CHHS_TILE_RHS(1, 0)
+        CHHS_TILE_RHS(1, 1)
+        CHHS_TILE_RHS(2, 0)
+        CHHS_TILE_RHS(2, 1)
+#undef CHHS_TILE_RHS
+        return;
+    }
 #define CHHS_TILE_CASE(L0, NS, EPI, PRO)                                          \
     if (level0 == L0 && ns == NS && epi == EPI && pro == PRO) {                   \
         launch_one<double, L0, NS, EPI, PRO, false>(b, t, nt, wide, partial, st); \
@@ -396,9 +486,24 @@ void launch_tile2d<double>(const Batch<double>& b, const TileTask* t, int nt, bo
 // sides, no norm epilogue.
 template <>
 void launch_tile2d<float>(const Batch<float>& b, const TileTask* t, int nt, bool level0, int ns,
-                          int epi, bool pro, bool wide, double* partial, hipStream_t st) {
+                          int epi, bool pro, bool wide, bool rhs, double* partial,
+                          hipStream_t st) {
     (void)level0;
     if (nt <= 0) return;
+    if (rhs) {
+        if (pro || epi == 2) return;
+#define CHHS_TILE_RHS(NS, EPI)                                                    \
+    if (ns == NS && epi == EPI) {                                                 \
+        launch_one<float, false, NS, EPI, false, true, true>(b, t, nt, wide, partial, st); \
+        return;                                                                   \
+    }
+        CHHS_TILE_RHS(1, 0)
+        CHHS_TILE_RHS(1, 1)
+        CHHS_TILE_RHS(2, 0)
+        CHHS_TILE_RHS(2, 1)
+#undef CHHS_TILE_RHS
+        return;
+    }
 #define CHHS_TILE_CASE(NS, EPI, PRO)                                              \
     if (ns == NS && epi == EPI && pro == PRO) {                                   \
         launch_one<float, false, NS, EPI, PRO, true>(b, t, nt, wide, partial, st); \
