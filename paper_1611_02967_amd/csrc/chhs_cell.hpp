@@ -97,6 +97,24 @@ __device__ __forceinline__ T dnonlin(T x, T psi, T b) {
     return T(0.25) * (T(3) * y * y + T(2) * y * psi + psi * psi);
 }
 
+// 1 / x for x >= 1 (the determinant of the collective cell solve): the
+// hardware reciprocal estimate refined by Newton steps r <- r + r (1 - x r),
+// each of which squares the relative error: two in FP64, one in FP32.  Within
+// an ulp or so of the quotient, at half the instructions of a correctly
+// rounded division; every kernel uses this same sequence.
+__device__ __forceinline__ double recip_ge1(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = __builtin_fma(-x, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-x, r, 1.0);
+    return __builtin_fma(r, e, r);
+}
+__device__ __forceinline__ float recip_ge1(float x) {
+    const float r = __builtin_amdgcn_rcpf(x);
+    const float e = __builtin_fmaf(-x, r, 1.0f);
+    return __builtin_fmaf(r, e, r);
+}
+
 // N(u) at one cell for the three rows of (2.5)-(2.7), the pressure row times s:
 //   N_phi = phi - lam sum M_f (mu_nb - mu) - lam sum a_f (p_nb - p)
 //   N_mu  = mu - chi(phi, psi) + kap sum (phi_nb - phi)
@@ -134,7 +152,7 @@ __device__ __forceinline__ void cell_operator(const Level<T>& L, int idx, int i,
 // are solved by eliminating p; the reduced 2x2 determinant is
 // 1 + lam (nF + gamma (Sa2 - Sa^2/nF)) (chi' + kap nF) >= 1.
 //
-// Written with one reciprocal of the determinant and 1/nF by cases, in the
+// Written with one reciprocal of the determinant (recip_ge1) and 1/nF by cases, in the
 // same operation order as the tiled and row-streaming 2D kernels, so that
 // every path performs bitwise the same update.  inv_lam = 1 / lam.
 template <int DIM, typename T, bool CORR = false>
@@ -174,7 +192,7 @@ __device__ __forceinline__ void cell_solve(const Level<T>& L, int idx, int i, in
     const T ared = lam * (fnf + gam * (sa2 - sa * sa * inv_nf));
     const T b1r = b1 + (sa * inv_nf) * b3;
     const T bb = dchi + kap * fnf;
-    const T inv_det = T(1) / (T(1) + ared * bb);
+    const T inv_det = recip_ge1(T(1) + ared * bb);
     mu_o = (b2 + bb * b1r) * inv_det;
     phi_o = (b1r - ared * b2) * inv_det;
     p_o = -(b3 * inv_lam + gam * sa * mu_o) * inv_nf;

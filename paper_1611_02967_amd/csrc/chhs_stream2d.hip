@@ -34,6 +34,8 @@
 //          averaging: u_c = ub_c = R u, fr_c = R R on level + 1 (copy b.cur_c).
 //   EPI 2  per-task partial sums of R_phi^2, R_mu^2, R_p^2 and p.
 //   CORR   correction form of the mixed-precision inner solve.
+#include <type_traits>
+
 #include "chhs_cell.hpp"
 
 namespace chhs {
@@ -223,7 +225,10 @@ __attribute__((amdgpu_waves_per_eu(LEVEL0 || CORR ? 3 : 1))) void k_stream2d(Bat
     };
 
     // ---- phase q on row r: the collective update of the q & 1 colored cells ----------
-    auto phase = [&](int q, int r, const Pair<T> (&o)[NO]) {
+    // XIN (strips away from the x boundaries): every cell the phase updates has
+    // both x faces, so the face count is the same for the whole row
+    auto phase = [&](auto xin_c, int q, int r, const Pair<T> (&o)[NO]) {
+        constexpr bool XIN = decltype(xin_c)::value;
         if (r < rlo || r > rhi) return;
         const int e = (r & 1) ^ (q & 1);           // pair member with this color
         const int c = 2 * lane + e;
@@ -240,7 +245,7 @@ __attribute__((amdgpu_waves_per_eu(LEVEL0 || CORR ? 3 : 1))) void k_stream2d(Bat
         const T ups = s[su][PS][wc], umu = s[su][MU][wc], up = s[su][P][wc], uphi = s[su][PHI][wc];
         const T phit = s[sc][PHI][wc];
         Sums q4{0, 0, 0, 0, 0, 0, 0, 0};
-        if (xin) {
+        if (XIN) {
             face(q4, psc, lps, lmu, lp, lphi);
             face(q4, psc, rps, rmu, rp, rphi);
         } else {
@@ -249,7 +254,7 @@ __attribute__((amdgpu_waves_per_eu(LEVEL0 || CORR ? 3 : 1))) void k_stream2d(Bat
         }
         if (r > 0) face(q4, psc, dps, dmu, dp, dphi);
         if (r < ny - 1) face(q4, psc, ups, umu, up, uphi);
-        const int nf = q4.nf;
+        const int nf = XIN ? 2 + (r > 0 ? 1 : 0) + (r < ny - 1 ? 1 : 0) : q4.nf;
         const T fnf = T(nf);
         const T inv_nf = nf == 4 ? T(0.25) : (nf == 3 ? T(1) / T(3) : (nf == 2 ? T(0.5) : T(1)));
         // select values, not member addresses, so that the pairs stay in registers
@@ -271,7 +276,7 @@ __attribute__((amdgpu_waves_per_eu(LEVEL0 || CORR ? 3 : 1))) void k_stream2d(Bat
         const T ared = lam * (fnf + gam * (q4.sa2 - q4.sa * q4.sa * inv_nf));
         const T b1r = b1 + (q4.sa * inv_nf) * b3;
         const T bb = dchi + kap * fnf;
-        const T inv_det = T(1) / (T(1) + ared * bb);
+        const T inv_det = recip_ge1(T(1) + ared * bb);
         const T mun = (b2 + bb * b1r) * inv_det;
         s[sc][PHI][wc] = (b1r - ared * b2) * inv_det;
         s[sc][MU][wc] = mun;
@@ -293,7 +298,7 @@ __attribute__((amdgpu_waves_per_eu(LEVEL0 || CORR ? 3 : 1))) void k_stream2d(Bat
 
     auto load_leave = [&](int k2) {
         const int r = k2 + ody;
-        const int g = (ocol && r < ny) ? r * nx + ogx : 0;
+        const int g = (ocol && r >= 0 && r < ny) ? r * nx + ogx : 0;
 #pragma unroll
         for (int k = 0; k < NO; ++k) lo[k] = gload(own_src[k], g);
     };
@@ -415,6 +420,7 @@ __attribute__((amdgpu_waves_per_eu(LEVEL0 || CORR ? 3 : 1))) void k_stream2d(Bat
 #pragma unroll
         for (int i = 0; i < KO; ++i) load_own(od[i], ys + i - 2 * wave);
     }
+    if (EPI != 0) load_leave(y0);
     __syncthreads();
 
     const int t_last = y0 + 2 * ((y1 - y0 + 1) / 2 - 1) + LAG;   // the last pair of rows leaves
@@ -426,7 +432,6 @@ __attribute__((amdgpu_waves_per_eu(LEVEL0 || CORR ? 3 : 1))) void k_stream2d(Bat
             if (t > t_last) goto drained;
             const int k2 = t - LAG;
             const bool lv = k2 >= y0 && ((k2 - y0) & 1) == 0;
-            if (EPI != 0 && lv) load_leave(k2);
             store_row(rv[b][u], rc[b][u], rb[b][u], t + 2);
             if (u == 0) {
 #pragma unroll
@@ -434,10 +439,17 @@ __attribute__((amdgpu_waves_per_eu(LEVEL0 || CORR ? 3 : 1))) void k_stream2d(Bat
                     load_row(rv[b ^ 1][w], rc[b ^ 1][w], rb[b ^ 1][w], t + 2 + kD + w);
             }
             if (wave < NPH) {
-                phase(wave, t - 2 * wave, od[i % KO]);
+                if (xin)
+                    phase(std::true_type{}, wave, t - 2 * wave, od[i % KO]);
+                else
+                    phase(std::false_type{}, wave, t - 2 * wave, od[i % KO]);
                 load_own(od[i % KO], t + KO - 2 * wave);
             }
-            if (lv) leave(k2);
+            if (lv) {
+                leave(k2);
+                // own data of the next pair of rows to leave, two iterations ahead
+                if (EPI != 0) load_leave(k2 + 2);
+            }
             __syncthreads();
         }
     }

@@ -301,7 +301,7 @@ __global__ __launch_bounds__(NT) void k_tile2d(Batch<T> bt, const TileTask* __re
             const T ared = lam * (fnf + gam * (sa2 - sa * sa * inv_nf));
             const T b1r = b1 + (sa * inv_nf) * b3;
             const T bb = dchi + kap * fnf;
-            const T inv_det = T(1) / (T(1) + ared * bb);
+            const T inv_det = recip_ge1(T(1) + ared * bb);
             const T mun = (b2 + bb * b1r) * inv_det;
             s_phi[wc] = (b1r - ared * b2) * inv_det;
             s_mu[wc] = mun;
