@@ -97,6 +97,41 @@ __device__ __forceinline__ T dnonlin(T x, T psi, T b) {
     return T(0.25) * (T(3) * y * y + T(2) * y * psi + psi * psi);
 }
 
+// v + (v of lane l ^ 16) and v + (v of lane l ^ 32) with the lane-row swaps
+// of gfx950 (VALU, no LDS traffic): swapping a value with itself leaves one
+// lane of each exchanged pair in either result, so their sum is the pairwise
+// sum at every lane, the same operands as v + __shfl_xor(v, 16 or 32).  Every
+// lane of the wave must be active.
+__device__ __forceinline__ double rows_sum(double v, bool by32) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = unsigned(b), hi = unsigned(b >> 32);
+    unsigned a0, a1, c0, c1;
+    if (by32) {
+        const auto l = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+        const auto h = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+        a0 = l[0], a1 = h[0], c0 = l[1], c1 = h[1];
+    } else {
+        const auto l = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+        const auto h = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+        a0 = l[0], a1 = h[0], c0 = l[1], c1 = h[1];
+    }
+    const double a = __builtin_bit_cast(double, (unsigned long long)a0 | ((unsigned long long)a1 << 32));
+    const double c = __builtin_bit_cast(double, (unsigned long long)c0 | ((unsigned long long)c1 << 32));
+    return a + c;
+}
+__device__ __forceinline__ float rows_sum(float v, bool by32) {
+    const unsigned x = __builtin_bit_cast(unsigned, v);
+    unsigned a, c;
+    if (by32) {
+        const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+        a = r[0], c = r[1];
+    } else {
+        const auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+        a = r[0], c = r[1];
+    }
+    return __builtin_bit_cast(float, a) + __builtin_bit_cast(float, c);
+}
+
 // 1 / x for x >= 1 (the determinant of the collective cell solve): the
 // hardware reciprocal estimate refined by Newton steps r <- r + r (1 - x r),
 // each of which squares the relative error: two in FP64, one in FP32.  Within

@@ -93,6 +93,7 @@ __attribute__((amdgpu_waves_per_eu(LEVEL0 || CORR ? 3 : 1))) void k_stream2d(Bat
     constexpr int NPH = 2 * NS;            // phases = waves with phase work
     constexpr int LAG = 4 * NS + 1;        // rows (t - LAG, t - LAG + 1) leave at iteration t
     constexpr int RING = 4 * NS + 5;       // rows t - LAG - 1 .. t + 2 are live
+    static_assert(kStripHX >= 2 * NS + 2, "halo columns must cover the phases and the residual");
     __shared__ T s[RING][NRF][kW];
 
     // XCD-aware order: XCD x runs a contiguous range of tasks (a bijection)
@@ -233,9 +234,17 @@ __attribute__((amdgpu_waves_per_eu(LEVEL0 || CORR ? 3 : 1))) void k_stream2d(Bat
         const int e = (r & 1) ^ (q & 1);           // pair member with this color
         const int c = 2 * lane + e;
         const int gx = x0 + c;
-        if (c < 1 || c > kW - 2 || gx < 0 || gx >= nx) return;
+        // Away from the x boundaries every lane updates its cell, the two
+        // outermost columns with an in-bounds word of the row as their missing
+        // neighbour: the error spreads one column per phase and reaches column
+        // 2 NS from the edge with the residual, inside the kStripHX >= 2 NS + 2
+        // halo columns (owned cells never depend on it).  The words are
+        // col(c - 1), col(c), col(c + 1), wrapped within the row at the edges.
+        if (!XIN && (c < 1 || c > kW - 2 || gx < 0 || gx >= nx)) return;
         const int sc = r % RING, sd = (r + RING - 1) % RING, su = (r + 1) % RING;
-        const int wc = col(c), wl = col(c - 1), wr = col(c + 1);
+        const int wc = XIN ? lane + kHalf * e : col(c);
+        const int wl = XIN ? lane + (kHalf - 1) * (1 - e) : col(c - 1);
+        const int wr = XIN ? lane + kHalf - (kHalf - 1) * e : col(c + 1);
         const T psc = s[sc][PS][wc];
         // every neighbour is read (rows across the boundary read in-bounds ring
         // words) so that the reads issue together; missing faces add nothing
@@ -381,8 +390,8 @@ __attribute__((amdgpu_waves_per_eu(LEVEL0 || CORR ? 3 : 1))) void k_stream2d(Bat
 #pragma unroll
         for (int c = 0; c < 7; ++c) {
             if (!CORR && c == 6) continue;
-            v[c] += __shfl_xor(v[c], 16, 64);
-            v[c] += __shfl_xor(v[c], 32, 64);
+            v[c] = rows_sum(v[c], false);
+            v[c] = rows_sum(v[c], true);
         }
         if (own && odx == 0 && ody == 0) {
             const int cgi = (k2 >> 1) * C.nx + (ogx >> 1);

@@ -397,10 +397,10 @@ __global__ __launch_bounds__(NT) void k_tile2d(Batch<T> bt, const TileTask* __re
             // combine the two rows (lane ^ 32); row 0 writes the coarse cell
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                sr[c] += __shfl_xor(sr[c], 32, 64);
-                su[c] += __shfl_xor(su[c], 32, 64);
+                sr[c] = rows_sum(sr[c], true);
+                su[c] = rows_sum(su[c], true);
             }
-            if (CORR) sb += __shfl_xor(sb, 32, 64);
+            if (CORR) sb = rows_sum(sb, true);
             if (live && cy == 0) {
                 const int c = gcy * C.nx + gcx;
                 const T w = T(0.25);
