@@ -38,7 +38,7 @@ from dataclasses import dataclass
 import numpy as np
 
 from . import grid
-from .scheme import (Level, apply_N, chi, dchi, face_coefficients, normalise_p,
+from .scheme import (Level, apply_N, face_coefficients, nonlinearity, normalise_p,
                      residual, residual_norm, step_rhs)
 
 
@@ -102,7 +102,8 @@ def smooth_cell(u, lvl, prm, color):
     h = lvl.h
     g = prm.gamma
     lam = prm.s / (h * h)
-    kap = 0.75 * prm.eps ** 2 / (h * h)
+    chi_fn, dchi_fn, c_eps = nonlinearity(prm)
+    kap = c_eps * prm.eps ** 2 / (h * h)
     a, m = face_coefficients(lvl.phi_star, g)
     ones = [np.ones_like(af) for af in a]
     _, s_mmu = face_sums(m, mu)
@@ -112,8 +113,8 @@ def smooth_cell(u, lvl, prm, color):
     _, s_amu = face_sums(a, mu)
     sa2, _ = face_sums([af * af for af in a], mu)
     b1 = f_phi + lam * s_mmu + lam * s_ap
-    dc = dchi(phi, lvl.psi)
-    b2 = f_mu + chi(phi, lvl.psi) - dc * phi - kap * s_phi
+    dc = dchi_fn(phi, lvl.psi)
+    b2 = f_mu + chi_fn(phi, lvl.psi) - dc * phi - kap * s_phi
     b3 = f_p - lam * s_p - lam * g * s_amu
     # eliminate p:  p = -(b3 + lam gamma Sa mu) / (lam nF)
     a_red = lam * (nf + g * (sa2 - sa * sa / nf))

@@ -20,6 +20,14 @@ Readings of points the paper leaves open (each is also listed in the design doc):
 * p is defined up to an additive constant (Neumann Poisson problem); results are
   normalised to mean zero.
 * The first step uses phi^{-1} := phi^0 (one of the options of Remark 2.2).
+* ``order = 1`` (``Params.order``) is the other option of Remark 2.2, a
+  first-order convex-splitting step from phi^0 to phi^1.  The paper cites its
+  form without writing it; the reading here keeps the three rows and the face
+  coefficients above and makes the splitting first order: phi_* := phi^m, the
+  convex part of the double well implicit, chi(phi) = phi^3, the whole
+  eps^2 Lap phi implicit and the concave part explicit, f_mu = -phi^m:
+
+    N_mu(u) = mu - phi^3 + eps^2 Lap phi = -phi^m.
 
 The same operator N is used on every multigrid level; a ``Level`` carries that
 level's spacing and its copies of phi_* and phi^m (the frozen data).
@@ -33,11 +41,13 @@ from . import grid
 
 @dataclass
 class Params:
-    """Physical and time-step parameters: eps, gamma of (1.2)-(1.4), step s, spacing h."""
+    """Physical and time-step parameters: eps, gamma of (1.2)-(1.4), step s, spacing h;
+    order 2 = the scheme (2.4)-(2.7), order 1 = the first-order step (module doc)."""
     eps: float
     gamma: float
     s: float
     h: float
+    order: int = 2
 
 
 @dataclass
@@ -59,6 +69,25 @@ def dchi(phi, psi):
     return 0.25 * (3.0 * phi * phi + 2.0 * phi * psi + psi * psi)
 
 
+def chi_cubic(phi, psi=None):
+    """The implicit convex part of the double well in the first-order step: phi^3."""
+    return phi * phi * phi
+
+
+def dchi_cubic(phi, psi=None):
+    """d/d phi of phi^3."""
+    return 3.0 * phi * phi
+
+
+def nonlinearity(prm):
+    """(chi, dchi, c) of the step: the nonlinear term of the mu row, its phi
+    derivative, and the implicit share c of eps^2 Lap phi (3/4 for (2.4)-(2.6),
+    1 for the first-order step)."""
+    if prm.order == 1:
+        return chi_cubic, dchi_cubic, 1.0
+    return chi, dchi, 0.75
+
+
 def face_coefficients(phi_star, gamma):
     """a = A_h phi_* and M(a) = 1 + gamma a^2 on interior faces (text after (2.5)-(2.7))."""
     a = grid.avg(phi_star)
@@ -69,8 +98,12 @@ def face_coefficients(phi_star, gamma):
 def step_rhs(phi_prev, phi_cur, prm):
     """Frozen data and right-hand side of one step, from (2.4) and (2.5)-(2.7).
 
-    Returns (phi_star, f) with f = [phi^m, -phi_* - eps^2/4 Lap phi^{m-1}, 0].
+    Returns (phi_star, f) with f = [phi^m, -phi_* - eps^2/4 Lap phi^{m-1}, 0];
+    for the first-order step phi_* = phi^m and f = [phi^m, -phi^m, 0]
+    (phi_prev unused).
     """
+    if prm.order == 1:
+        return phi_cur.copy(), [phi_cur.copy(), -phi_cur, np.zeros_like(phi_cur)]
     phi_star = 1.5 * phi_cur - 0.5 * phi_prev
     f_mu = -phi_star - 0.25 * prm.eps ** 2 * grid.lap(phi_prev, prm.h)
     return phi_star, [phi_cur.copy(), f_mu, np.zeros_like(phi_cur)]
@@ -81,8 +114,9 @@ def apply_N(u, lvl, prm):
     phi, mu, p = u
     h, s, g, e2 = lvl.h, prm.s, prm.gamma, prm.eps ** 2
     a, m = face_coefficients(lvl.phi_star, g)
+    chi_fn, _, c_eps = nonlinearity(prm)
     n_phi = phi - s * grid.div_c_grad(m, mu, h) - s * grid.div_c_grad(a, p, h)
-    n_mu = mu - chi(phi, lvl.psi) + 0.75 * e2 * grid.lap(phi, h)
+    n_mu = mu - chi_fn(phi, lvl.psi) + c_eps * e2 * grid.lap(phi, h)
     n_p = s * grid.lap(p, h) + s * g * grid.div_c_grad(a, mu, h)
     return [n_phi, n_mu, n_p]
 

@@ -259,7 +259,7 @@ def test_planted_chi_error_is_caught(monkeypatch):
     n = 16
     prm = scheme.Params(eps=0.1, gamma=2.0, s=0.01, h=1.0 / n)
     phi0 = uniform_field((n, n), 92, mean=0.3, amp=0.3)
-    monkeypatch.setattr(fas, "chi", lambda a, b: 0.25 * (a ** 3 + a * a * b + a * b * b))
+    # both the smoother and the residual take chi through scheme.nonlinearity
     monkeypatch.setattr(scheme, "chi", lambda a, b: 0.25 * (a ** 3 + a * a * b + a * b * b))
     steps = _march(phi0, prm, 2, tol=1e-12)
     prev, cur, r = steps[-1]

@@ -19,6 +19,14 @@ def uniform_field(shape, seed, mean=0.0, amp=0.05):
     return mean + amp * (2.0 * rng.random(shape) - 1.0)
 
 
+def cosine_mode(shape, k, mean, amp):
+    """mean + amp cos(pi k (i + 1/2) / nx) along x (the last axis), constant
+    along the other axes: a single cosine mode of the cell-centred Neumann grid."""
+    nx = shape[-1]
+    v = np.cos(np.pi * k * (np.arange(nx) + 0.5) / nx)
+    return mean + amp * np.broadcast_to(v, shape).copy()
+
+
 def _centres(n, length):
     h = length / n
     return (np.arange(n) + 0.5) * h
