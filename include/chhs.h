@@ -80,7 +80,14 @@ typedef struct chhs_problem {
  * each level's smoothing launches with tiles of 256 and 1024 threads and with
  * strips of 1, 2 and 4 times the default segment height, and keeps the fastest
  * per level (the choice then depends on the device; results agree to rounding).
- * reserved must be zero. */
+ * order = 2 (default; 0 means the same) solves the second-order scheme
+ * (2.4)-(2.7).  order = 1 solves instead the first-order convex-splitting step
+ * that Remark 2.2 names as a way to obtain phi^1 from phi^0 (its form is cited,
+ * not written, in the paper; the reading here): the same three rows with
+ * phi_* := phi^m, the convex part of chi fully implicit, chi(phi) = phi^3, the
+ * whole eps^2 Lap phi implicit (kap = eps^2/h^2) and f_mu = -phi^m; phi_prev
+ * is not read.  order = 1 needs precision = 0 and smooths every level with the
+ * per-cell red-black kernels.  reserved must be zero. */
 typedef struct chhs_opts {
     int32_t nu1, nu2, max_vcycles, coarse_sweeps;
     double tol;
@@ -89,7 +96,8 @@ typedef struct chhs_opts {
     int32_t timing;
     int32_t smoother;
     int32_t autotune;
-    int32_t reserved[3];
+    int32_t order;
+    int32_t reserved[2];
 } chhs_opts;
 
 /* Kernel classes of chhs_timing. */

@@ -37,7 +37,7 @@ class chhs_opts(ctypes.Structure):
                 ("tol", ctypes.c_double), ("precision", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("timing", ctypes.c_int32),
                 ("smoother", ctypes.c_int32), ("autotune", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 3)]
+                ("order", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
 
 K_CLASSES = ["pre0", "post0", "transfer0", "coarse", "norm", "setup", "k6", "k7"]

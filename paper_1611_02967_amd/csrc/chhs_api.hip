@@ -155,6 +155,8 @@ bool valid_opts(const chhs_opts* o) {
     if (o->precision != 0 && o->precision != 1) return false;
     if (o->smoother < 0 || o->smoother > 2) return false;
     if (o->autotune < 0 || o->autotune > 1) return false;
+    if (o->order < 0 || o->order > 2) return false;
+    if (o->order == 1 && o->precision != 0) return false;
     return true;
 }
 
@@ -324,7 +326,9 @@ bool plan(const chhs_problem* p, int n_inst, const chhs_opts* o, char* base, Lay
         in.tail = tail;
         in.off = packed;
         in.n0 = cells[0];
-        in.fused = (!mixed && dim == 2 && o->nu2 > 0 && tail > 0) ? 1 : 0;
+        const bool first = o->order == 1;
+        in.order = first ? 1 : 2;
+        in.fused = (!mixed && !first && dim == 2 && o->nu2 > 0 && tail > 0) ? 1 : 0;
         in.h = p[i].h;
         in.eps = p[i].eps;
         in.gamma = p[i].gamma;
@@ -356,7 +360,9 @@ bool plan(const chhs_problem* p, int n_inst, const chhs_opts* o, char* base, Lay
             d.b = nullptr;
             d.h = h;
             d.lam = p[i].dt / (h * h);
-            d.kap = 0.75 * p[i].eps * p[i].eps / (h * h);
+            // the whole eps^2 Lap phi is implicit in the first-order step
+            d.kap = (first ? 1.0 : 0.75) * p[i].eps * p[i].eps / (h * h);
+            d.order = in.order;
             d.gamma = p[i].gamma;
             if (mixed) {
                 LevelDesc<float>& e = L.desc32[size_t(i) * kMaxLevels + l];
@@ -377,6 +383,7 @@ bool plan(const chhs_problem* p, int n_inst, const chhs_opts* o, char* base, Lay
                 e.h = float(h);
                 e.lam = float(d.lam);
                 e.kap = float(d.kap);
+                e.order = d.order;
                 e.gamma = float(d.gamma);
             }
             h *= 2.0;
@@ -412,7 +419,8 @@ bool plan(const chhs_problem* p, int n_inst, const chhs_opts* o, char* base, Lay
             // needs an even x extent
             bool even = true;
             for (int i = 0; i < n_inst; ++i) even = even && (lnx[l][i] < 0 || lnx[l][i] % 2 == 0);
-            L.strip[l] = even && (o->smoother == 2 ? !L.Sall[l].empty()
+            L.strip[l] = even && o->order != 1 &&
+                         (o->smoother == 2 ? !L.Sall[l].empty()
                                                    : (o->smoother == 0 && l == 0 && !L.T[l].empty()));
         }
     L.snx = lnx_t;
@@ -613,10 +621,15 @@ void restore_copy0(chhs_ctx* c, const Hier<T>& H, int l) {
     H.cur[l] = 0;
 }
 
+// 2D levels above the tail are smoothed by the fused tiled / strip kernels
+// (the second-order scheme); otherwise by the per-cell red-black kernels.
+bool tiled2d(const chhs_ctx* c) { return c->dim == 2 && c->opts.order != 1; }
+
 // nsweeps smoothing steps on level l of the FP64 hierarchy (2D: tiled,
-// including levels inside the tail for kernel tests; 3D: per-cell red-black).
+// including levels inside the tail for kernel tests; 3D and the first-order
+// step: per-cell red-black).
 void smooth_steps(chhs_ctx* c, int l, int nsweeps, const int* active, int cls) {
-    if (c->dim == 2) {
+    if (tiled2d(c)) {
         while (nsweeps > 0) {
             const int k = nsweeps >= 2 ? 2 : 1;
             nsweeps -= k;
@@ -628,7 +641,7 @@ void smooth_steps(chhs_ctx* c, int l, int nsweeps, const int* active, int cls) {
     for (int s = 0; s < nsweeps; ++s)
         for (int color = 0; color < 2; ++color) {
             TimedScope t(c, cls);
-            chhs::launch_smooth(3, b, c->A[l].dev, c->A[l].n, color, c->stream);
+            chhs::launch_smooth(c->dim, b, c->A[l].dev, c->A[l].n, color, c->stream);
         }
 }
 
@@ -645,7 +658,7 @@ void enqueue_vcycle(chhs_ctx* c, const Hier<T>& H) {
     for (int d = 0; d < depth; ++d) {
         const int pre_cls = d == 0 ? CHHS_K_PRE0 : CHHS_K_COARSE;
         const int xfer_cls = d == 0 ? CHHS_K_TRANSFER0 : CHHS_K_COARSE;
-        if (dim == 2 && o.nu1 > 0) {
+        if (tiled2d(c) && o.nu1 > 0) {
             // on a tiled coarse level the first launch forms f = fr + N(u)
             const bool rhs = d > 0 && !c->lay.strip[d];
             bool first = true;
@@ -657,11 +670,11 @@ void enqueue_vcycle(chhs_ctx* c, const Hier<T>& H) {
             }
             tiled(c, H, false, d, rem, 1, false, act, pre_cls, rhs && first);
         } else {
-            if (dim == 3)
+            if (!tiled2d(c))
                 for (int s = 0; s < o.nu1; ++s)
                     for (int color = 0; color < 2; ++color) {
                         TimedScope t(c, pre_cls);
-                        chhs::launch_smooth_color(3, make_batch(H.dev, H.cur, d, act),
+                        chhs::launch_smooth_color(dim, make_batch(H.dev, H.cur, d, act),
                                                   c->Bh[d].dev, c->Bh[d].n, color, c->stream);
                     }
             TimedScope t(c, xfer_cls);
@@ -670,7 +683,7 @@ void enqueue_vcycle(chhs_ctx* c, const Hier<T>& H) {
         }
         // level d + 1's right-hand side f = fr + N(u), unless its first tiled
         // launch forms it (tail levels: the tail does)
-        const bool fused_next = dim == 2 && o.nu1 > 0 && d + 1 < depth && !c->lay.strip[d + 1];
+        const bool fused_next = tiled2d(c) && o.nu1 > 0 && d + 1 < depth && !c->lay.strip[d + 1];
         if (!fused_next && c->Bcs[d].n > 0) {
             TimedScope t(c, xfer_cls);
             chhs::launch_coarse_rhs(dim, make_batch(H.dev, H.cur, d, act), c->Bcs[d].dev,
@@ -687,7 +700,7 @@ void enqueue_vcycle(chhs_ctx* c, const Hier<T>& H) {
     for (int d = depth - 1; d >= 0; --d) {
         const int post_cls = d == 0 ? CHHS_K_POST0 : CHHS_K_COARSE;
         const int xfer_cls = d == 0 ? CHHS_K_TRANSFER0 : CHHS_K_COARSE;
-        if (dim == 2 && o.nu2 > 0) {
+        if (tiled2d(c) && o.nu2 > 0) {
             int rem = o.nu2;
             bool first = true;
             while (rem > 0) {
@@ -703,11 +716,11 @@ void enqueue_vcycle(chhs_ctx* c, const Hier<T>& H) {
                 chhs::launch_prolong(dim, make_batch(H.dev, H.cur, d, act), c->B[d].dev, c->B[d].n,
                                      c->stream);
             }
-            if (dim == 3)
+            if (!tiled2d(c))
                 for (int s = 0; s < o.nu2; ++s)
                     for (int color = 0; color < 2; ++color) {
                         TimedScope t(c, post_cls);
-                        chhs::launch_smooth_color(3, make_batch(H.dev, H.cur, d, act),
+                        chhs::launch_smooth_color(dim, make_batch(H.dev, H.cur, d, act),
                                                   c->Bh[d].dev, c->Bh[d].n, color, c->stream);
                     }
         }
@@ -1096,6 +1109,7 @@ void chhs_default_opts(chhs_opts* o) {
     o->precision = 0;
     o->use_graph = 1;
     o->timing = 0;
+    o->order = 2;
 }
 
 size_t chhs_workspace_bytes(const chhs_problem* p, int32_t n_inst, const chhs_opts* o) {
@@ -1193,9 +1207,10 @@ int chhs_init(const chhs_problem* p, int32_t n_inst, const chhs_opts* o, void* w
         return fail(CHHS_E_HIP);
     view_results(c, 0);
     c->heres = c->hbuf[0] + nres + nint;
-    c->fused_norm = !c->mixed && c->dim == 2 && o->nu2 > 0;
+    c->fused_norm = !c->mixed && c->dim == 2 && o->nu2 > 0 && o->order != 1;
     if (hipStreamSynchronize(st) != hipSuccess) return fail(CHHS_E_HIP);
-    if (o->autotune && o->smoother == 0 && c->dim == 2 && o->nu1 > 0 && o->nu2 > 0) {
+    if (o->autotune && o->smoother == 0 && c->dim == 2 && o->nu1 > 0 && o->nu2 > 0 &&
+        o->order != 1) {
         const int arc = autotune(c);
         if (arc) return fail(arc);
     }
@@ -1345,7 +1360,7 @@ int chhs_level_kernel(chhs_ctx* c, int32_t level, int32_t* out3) {
         out3[0] = 3;
         out3[1] = 0;
         out3[2] = 0;
-    } else if (c->dim == 3) {
+    } else if (!tiled2d(c)) {
         out3[0] = 2;
         out3[1] = chhs::kBlock;
         out3[2] = c->Bh[level].n;

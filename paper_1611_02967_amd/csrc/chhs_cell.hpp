@@ -173,7 +173,8 @@ __device__ __forceinline__ void cell_operator(const Level<T>& L, int idx, int i,
         samu = h ? samu + a * dmu : samu;
     });
     const T psi = L.psi[idx];
-    const T chi = nonlin<T, CORR>(phic, psi, CORR ? L.b[idx] : T(0));
+    const T chi = !CORR && L.order == 1 ? phic * phic * phic
+                                        : nonlin<T, CORR>(phic, psi, CORR ? L.b[idx] : T(0));
     n0 = phic - L.lam * smm - L.lam * sap;
     n1 = muc - chi + L.kap * sphi;
     n2 = L.lam * sp + L.lam * L.gamma * samu;
@@ -219,8 +220,10 @@ __device__ __forceinline__ void cell_solve(const Level<T>& L, int idx, int i, in
     const T phit = L.phi[idx];
     const T psi = L.psi[idx];
     const T base = CORR ? L.b[idx] : T(0);
-    const T dchi = dnonlin<T, CORR>(phit, psi, base);
-    const T chi = nonlin<T, CORR>(phit, psi, base);
+    // the first-order step (order 1): chi(phi) = phi^3, implicit
+    const bool cubic = !CORR && L.order == 1;
+    const T dchi = cubic ? T(3) * phit * phit : dnonlin<T, CORR>(phit, psi, base);
+    const T chi = cubic ? phit * phit * phit : nonlin<T, CORR>(phit, psi, base);
     const T b1 = L.f0[idx] + lam * smmu + lam * sap;
     const T b2 = L.f1[idx] + chi - dchi * phit - kap * sphi;
     const T b3 = L.f2[idx] - lam * sp - lam * gam * samu;

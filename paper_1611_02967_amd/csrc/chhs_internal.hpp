@@ -38,7 +38,9 @@ constexpr int kResStride = 16;       // doubles per instance in the result area
 //                         averages of the finer level's on coarse levels
 //   b                     base state of the correction form (mixed precision
 //                         inner solve); null in the plain form
-// lam = s/h^2, kap = 3/4 eps^2 / h^2, gamma as in (1.3).
+// lam = s/h^2, kap = 3/4 eps^2 / h^2, gamma as in (1.3).  order = 2: chi of
+// (2.4); order = 1 (the first-order bootstrap step): chi(phi) = phi^3 and
+// kap = eps^2 / h^2.
 template <typename T>
 struct Level {
     T* phi;
@@ -60,6 +62,7 @@ struct Level {
     T* mu_alt;
     T* p_alt;
     int nx, ny, nz, n;
+    int order;
     T lam, kap, gamma, h;
 };
 
@@ -75,6 +78,7 @@ struct LevelDesc {
     T* psi;
     T* b;
     int nx, ny, nz, n;
+    int order;
     T lam, kap, gamma, h;
 };
 
@@ -103,6 +107,7 @@ __host__ __device__ inline Level<T> make_view(const LevelDesc<T>& d, int cur) {
     v.ny = d.ny;
     v.nz = d.nz;
     v.n = d.n;
+    v.order = d.order;
     v.lam = d.lam;
     v.kap = d.kap;
     v.gamma = d.gamma;
@@ -116,6 +121,7 @@ struct InstInfo {
     int off;               // offset of the instance in packed caller arrays
     int n0;                // cells of the finest level
     int fused;             // the finest-level post launch yields the norm partials
+    int order;             // 2: the scheme (2.4)-(2.7); 1: the first-order step
     double h, eps, gamma, dt;
 };
 

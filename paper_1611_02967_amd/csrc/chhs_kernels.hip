@@ -42,11 +42,13 @@ __global__ __launch_bounds__(kBlock) void k_setup(Batch<double> b, const CellTas
         lap = h ? lap + d : lap;
     });
     const double q = 0.25 * in.eps * in.eps / (in.h * in.h);
-    const double ps = 1.5 * pc - 0.5 * pm;           // phi_*, (2.4)
+    // the first-order step (order 1): phi_* := phi^m and f_mu = -phi^m
+    const bool first = in.order == 1;
+    const double ps = first ? pc : 1.5 * pc - 0.5 * pm;   // phi_*, (2.4)
     L.pstar[idx] = ps;
     L.psi[idx] = pc;
     L.f0[idx] = pc;                                   // (2.5): phi^m
-    L.f1[idx] = -ps - q * lap;                        // (2.6): -phi_* - eps^2/4 Lap phi^{m-1}
+    L.f1[idx] = first ? -pc : -ps - q * lap;          // (2.6): -phi_* - eps^2/4 Lap phi^{m-1}
     L.f2[idx] = 0.0;                                  // (2.7)
     L.phi[idx] = pc;                                  // initial guess phi^m
     L.mu[idx] = mu[g];
