@@ -113,6 +113,11 @@ struct chhs_ctx {
     int cur[kMaxLevels] = {};       // current copy of u per FP64 level
     int cur32[kMaxLevels] = {};     // current copy of u per FP32 level
     bool fused_norm = false;
+    // plain 2D path with pre-smoothing: p's mean is not subtracted by a launch
+    // of its own after a cycle; the next cycle's first finest-level launch
+    // (or the tail, holding that level) subtracts it as it loads p, and the
+    // copy to the caller's arrays subtracts what is still pending
+    bool defer_shift = false;
     bool loaded = false;
     // graph replay of one cycle; two slots in mixed precision (the FP64 finest
     // level alternates its copy once per refinement step)
@@ -559,6 +564,7 @@ Batch<T> make_batch(const LevelDesc<T>* desc, const int* cur, int level, const i
     b.level = level;
     b.cur = cur[level];
     b.cur_c = 0;    // a coarser level is always at copy 0 when a transfer touches it
+    b.pshift = nullptr;
     return b;
 }
 
@@ -588,8 +594,9 @@ Hier<float> hier32(chhs_ctx* c) { return {c->ddesc32, &c->lay.desc32, c->cur32, 
 // flips the level's current copy.
 template <typename T>
 void tiled(chhs_ctx* c, const Hier<T>& H, bool all, int l, int ns, int epi, bool pro,
-           const int* active, int cls, bool rhs = false) {
+           const int* active, int cls, bool rhs = false, const double* pshift = nullptr) {
     Batch<T> b = make_batch(H.dev, H.cur, l, active);
+    b.pshift = pshift;
     const bool level0 = std::is_same<T, double>::value && l == 0;
     double* part = epi == 2 ? c->partial_t : nullptr;
     {
@@ -661,14 +668,16 @@ void enqueue_vcycle(chhs_ctx* c, const Hier<T>& H) {
         if (tiled2d(c) && o.nu1 > 0) {
             // on a tiled coarse level the first launch forms f = fr + N(u)
             const bool rhs = d > 0 && !c->lay.strip[d];
+            // ... and on the finest level it subtracts a deferred p shift
+            const double* psh = kPlain && d == 0 && c->defer_shift ? c->res : nullptr;
             bool first = true;
             int rem = o.nu1;
             while (rem > 2) {
-                tiled(c, H, false, d, 2, 0, false, act, pre_cls, rhs && first);
+                tiled(c, H, false, d, 2, 0, false, act, pre_cls, rhs && first, first ? psh : nullptr);
                 first = false;
                 rem -= 2;
             }
-            tiled(c, H, false, d, rem, 1, false, act, pre_cls, rhs && first);
+            tiled(c, H, false, d, rem, 1, false, act, pre_cls, rhs && first, first ? psh : nullptr);
         } else {
             if (!tiled2d(c))
                 for (int s = 0; s < o.nu1; ++s)
@@ -695,7 +704,9 @@ void enqueue_vcycle(chhs_ctx* c, const Hier<T>& H) {
         // it (copy 0) and by the tail itself: it is always read from copy 0
         TimedScope t(c, depth == 0 ? CHHS_K_PRE0 : CHHS_K_COARSE);
         chhs::launch_tail<T, !kPlain>(dim, H.dev, c->dinfo, c->tail_insts, c->n_inst, act, 0u,
-                                      o.nu1, o.nu2, o.coarse_sweeps, H.tail_lds, c->stream);
+                                      o.nu1, o.nu2, o.coarse_sweeps,
+                                      kPlain && c->defer_shift ? c->res : nullptr, H.tail_lds,
+                                      c->stream);
     }
     for (int d = depth - 1; d >= 0; --d) {
         const int post_cls = d == 0 ? CHHS_K_POST0 : CHHS_K_COARSE;
@@ -855,7 +866,14 @@ void enqueue_plain_cycle(chhs_ctx* c, bool count) {
     chhs::launch_inst_reduce(c->partial, c->rngA0n, c->partial_t, c->rngT0, 1, c->dinfo, act,
                              c->act_next, c->cycles, c->res, c->n_inst, o.tol,
                              count ? o.max_vcycles : 1 << 30, count ? 1 : 0, c->stream);
-    chhs::launch_shift_p(batch(c, 0, act), c->A[0].dev, c->A[0].n, c->res, c->stream);
+    if (!c->defer_shift)
+        chhs::launch_shift_p(batch(c, 0, act), c->A[0].dev, c->A[0].n, c->res, c->stream);
+}
+
+// Applies a deferred p shift to the finest level's p and clears it.
+void apply_pshift(chhs_ctx* c) {
+    chhs::launch_shift_p(batch(c, 0, nullptr), c->A[0].dev, c->A[0].n, c->res, c->stream);
+    chhs::launch_clear_pshift(c->res, c->n_inst, c->stream);
 }
 
 // Mixed precision, one refinement step: zero FP32 correction, one FP32
@@ -1035,8 +1053,10 @@ int run_cycles(chhs_ctx* c) {
 
 // Setup of every instance's step system, p normalised to mean zero, and the
 // norms of the initial guess on the host.
+// defer: leave the mean of the initial p pending (the step loop) rather than
+// subtract it at once (callers that read the level's fields).
 int setup(chhs_ctx* c, const double* phi_prev, const double* phi_cur, const double* mu,
-          const double* p) {
+          const double* p, bool defer = false) {
     const int dim = c->dim;
     {
         TimedScope t(c, CHHS_K_SETUP);
@@ -1066,7 +1086,10 @@ int setup(chhs_ctx* c, const double* phi_prev, const double* phi_cur, const doub
         chhs::launch_inst_reduce(c->partial, c->rngA0, nullptr, nullptr, 0, c->dinfo, nullptr,
                                  c->act_next, c->cycles, c->res, c->n_inst, c->opts.tol,
                                  c->opts.max_vcycles, 0, c->stream);
-        chhs::launch_shift_p(batch(c, 0, nullptr), c->A[0].dev, c->A[0].n, c->res, c->stream);
+        if (!c->defer_shift)
+            chhs::launch_shift_p(batch(c, 0, nullptr), c->A[0].dev, c->A[0].n, c->res, c->stream);
+        else if (!defer)
+            apply_pshift(c);
     }
     int rc = check_launch();
     if (rc) return rc;
@@ -1208,6 +1231,7 @@ int chhs_init(const chhs_problem* p, int32_t n_inst, const chhs_opts* o, void* w
     view_results(c, 0);
     c->heres = c->hbuf[0] + nres + nint;
     c->fused_norm = !c->mixed && c->dim == 2 && o->nu2 > 0 && o->order != 1;
+    c->defer_shift = !c->mixed && tiled2d(c) && o->nu1 > 0;
     if (hipStreamSynchronize(st) != hipSuccess) return fail(CHHS_E_HIP);
     if (o->autotune && o->smoother == 0 && c->dim == 2 && o->nu1 > 0 && o->nu2 > 0 &&
         o->order != 1) {
@@ -1233,6 +1257,12 @@ int chhs_fas_vcycle(chhs_ctx* c, double* res_norm_host) {
     chhs::launch_fill_int(c->act_next, c->n_inst, 1, c->stream);
     int rc = run_cycle(c, false);
     if (rc) return rc;
+    // the level's fields after this call hold the normalised p
+    if (c->defer_shift) {
+        apply_pshift(c);
+        rc = check_launch();
+        if (rc) return rc;
+    }
     bool finite = true;
     for (int i = 0; i < c->n_inst; ++i) {
         if (res_norm_host) res_norm_host[i] = hres_of(c, i)[3];
@@ -1262,8 +1292,9 @@ int chhs_residual_norms(chhs_ctx* c, double* out_host) {
 int chhs_get_solution(chhs_ctx* c, double* phi, double* mu, double* p) {
     if (c == nullptr) return CHHS_E_INVAL;
     if (!c->loaded) return CHHS_E_STATE;
-    chhs::launch_get_solution(batch(c, 0, nullptr), c->A[0].dev, c->A[0].n, c->dinfo, phi, mu, p,
-                              c->stream);
+    Batch<double> b = batch(c, 0, nullptr);
+    b.pshift = c->defer_shift ? c->res : nullptr;
+    chhs::launch_get_solution(b, c->A[0].dev, c->A[0].n, c->dinfo, phi, mu, p, c->stream);
     return check_launch();
 }
 
@@ -1277,7 +1308,7 @@ int chhs_step(chhs_ctx* c, double* phi_prev, double* phi_cur, double* mu, double
     for (auto& s : st) std::memset(&s, 0, sizeof(s));
     int rc = CHHS_OK;
     for (int m = 0; m < nsteps && rc == CHHS_OK; ++m) {
-        rc = setup(c, phi_prev, phi_cur, mu, p);
+        rc = setup(c, phi_prev, phi_cur, mu, p, true);
         if (rc) break;
         for (int i = 0; i < n; ++i) st[i].res0 = hres_of(c, i)[3];
         rc = run_cycles(c);
@@ -1310,8 +1341,10 @@ int chhs_step(chhs_ctx* c, double* phi_prev, double* phi_cur, double* mu, double
             }
         }
         // rotate: (phi^{m-1}, phi^m) <- (phi^m, phi^{m+1}); mu, p <- this step's
-        chhs::launch_copy_out(batch(c, 0, nullptr), c->A[0].dev, c->A[0].n, c->dinfo, phi_prev,
-                              phi_cur, mu, p, c->stream);
+        Batch<double> bo = batch(c, 0, nullptr);
+        bo.pshift = c->defer_shift ? c->res : nullptr;
+        chhs::launch_copy_out(bo, c->A[0].dev, c->A[0].n, c->dinfo, phi_prev, phi_cur, mu, p,
+                              c->stream);
         rc = check_launch();
         if (rc) break;
         for (int i = 0; i < n; ++i) ++st[i].steps_done;

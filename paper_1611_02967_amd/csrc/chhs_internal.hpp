@@ -138,6 +138,10 @@ struct Batch {
     int level;                  // level of the launch (the finer one for transfers)
     int cur;                    // current copy of u on `level`
     int cur_c;                  // current copy of u on level + 1
+    // Deferred p shift: the finest level's p is stored before subtracting its
+    // mean pshift[inst * kResStride + 4]; a launch given pshift subtracts it
+    // where it reads that p (nullptr: nothing pending).
+    const double* pshift;
 };
 
 // ---- per-cell kernels (chhs_kernels.hip); dim is 2 or 3 ----------------------------
@@ -191,6 +195,8 @@ void launch_inst_reduce(const double* partial, const Range* ranges, const double
                         const int* active, int* act_next, int* cycles, double* res, int n_inst,
                         double tol, int max_cycles, int count, hipStream_t st);
 // p -= mean(p) (res slot 4) on the finest level of active instances.
+// res[i * kResStride + 4] = 0 for every instance (a deferred p shift applied)
+void launch_clear_pshift(double* res, int n_inst, hipStream_t st);
 void launch_shift_p(const Batch<double>& b, const CellTask* t, int nt, const double* res,
                     hipStream_t st);
 // Energy partials over the finest level: ws != 0 takes phi = u, q = phi^m and
@@ -254,6 +260,6 @@ int prepare_tail(int dim, size_t lds_bytes);
 template <typename T, bool CORR>
 void launch_tail(int dim, const LevelDesc<T>* desc, const InstInfo* info, const int* insts,
                  int ninst, const int* active, unsigned cur_mask, int nu1, int nu2,
-                 int coarse_sweeps, size_t lds_bytes, hipStream_t st);
+                 int coarse_sweeps, double* pend, size_t lds_bytes, hipStream_t st);
 
 }  // namespace chhs

@@ -497,10 +497,16 @@ __global__ __launch_bounds__(kBlock) void k_copy_out(Batch<double> b, const Cell
     const int idx = tk.cell0 + threadIdx.x;
     if (idx >= L.n) return;
     const int g = info[tk.inst].off + idx;
+    const double psh = b.pshift != nullptr ? b.pshift[tk.inst * kResStride + 4] : 0.0;
     phi_prev[g] = phi_cur[g];
     phi_cur[g] = L.phi[idx];
     mu[g] = L.mu[idx];
-    p[g] = L.p[idx];
+    p[g] = L.p[idx] - psh;
+}
+
+__global__ void k_clear_pshift(double* res, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) res[i * kResStride + 4] = 0.0;
 }
 
 __global__ __launch_bounds__(kBlock) void k_get_solution(Batch<double> b,
@@ -514,7 +520,7 @@ __global__ __launch_bounds__(kBlock) void k_get_solution(Batch<double> b,
     const int g = info[tk.inst].off + idx;
     if (phi) phi[g] = L.phi[idx];
     if (mu) mu[g] = L.mu[idx];
-    if (p) p[g] = L.p[idx];
+    if (p) p[g] = L.p[idx] - (b.pshift != nullptr ? b.pshift[tk.inst * kResStride + 4] : 0.0);
 }
 
 __global__ __launch_bounds__(kBlock) void k_fill_int(int* dst, int n, int value) {
@@ -636,6 +642,10 @@ void launch_inst_reduce(const double* partial, const Range* ranges, const double
     hipLaunchKernelGGL(k_inst_reduce, dim3(n_inst), dim3(kBlock), 0, st, partial, ranges,
                        partial_t, ranges_t, use_fused, info, active, act_next, cycles, res, tol,
                        max_cycles, count);
+}
+
+void launch_clear_pshift(double* res, int n_inst, hipStream_t st) {
+    hipLaunchKernelGGL(k_clear_pshift, dim3(blocks_for(n_inst)), dim3(kBlock), 0, st, res, n_inst);
 }
 
 void launch_shift_p(const Batch<double>& b, const CellTask* t, int nt, const double* res,

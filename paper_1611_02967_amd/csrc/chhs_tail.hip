@@ -147,7 +147,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(const LevelDesc<T>* __res
                                                        const int* __restrict__ insts,
                                                        const int* __restrict__ active,
                                                        unsigned cur_mask, int nu1, int nu2,
-                                                       int coarse_sweeps) {
+                                                       int coarse_sweeps, double* pend) {
     extern __shared__ __align__(16) unsigned char tail_lds[];
     T* base = reinterpret_cast<T*>(tail_lds);
     const int inst = insts[blockIdx.x];
@@ -166,10 +166,14 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(const LevelDesc<T>* __res
         const T* g0 = top > 0 ? G.fr0 : G.f0;
         const T* g1 = top > 0 ? G.fr1 : G.f1;
         const T* g2 = top > 0 ? G.fr2 : G.f2;
+        // a deferred shift of the finest p: subtracted here when the tail
+        // holds the finest level, then cleared (the finest level's first
+        // smoothing launch has already subtracted it otherwise)
+        const T psh = pend != nullptr && top == 0 ? T(pend[inst * kResStride + 4]) : T(0);
         for (int idx = threadIdx.x; idx < G.n; idx += blockDim.x) {
             S.phi[idx] = G.phi[idx];
             S.mu[idx] = G.mu[idx];
-            S.p[idx] = G.p[idx];
+            S.p[idx] = G.p[idx] - psh;
             S.f0[idx] = g0[idx];
             S.f1[idx] = g1[idx];
             S.f2[idx] = g2[idx];
@@ -185,6 +189,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(const LevelDesc<T>* __res
         }
     }
     __syncthreads();
+    if (pend != nullptr && threadIdx.x == 0) pend[inst * kResStride + 4] = 0.0;
     if (top > 0) {
         const Level<T> S = lds_view<T, CORR>(d, top, top, base);
         const float rnx = 1.0f / float(S.nx), rnxy = 1.0f / float(S.nx * S.ny);
@@ -247,23 +252,23 @@ int prepare_tail(int dim, size_t lds_bytes) {
 template <typename T, bool CORR>
 void launch_tail(int dim, const LevelDesc<T>* desc, const InstInfo* info, const int* insts,
                  int ninst, const int* active, unsigned cur_mask, int nu1, int nu2,
-                 int coarse_sweeps, size_t lds_bytes, hipStream_t st) {
+                 int coarse_sweeps, double* pend, size_t lds_bytes, hipStream_t st) {
     if (ninst <= 0) return;
     if (dim == 2)
         hipLaunchKernelGGL((k_tail<2, T, CORR>), dim3(ninst), dim3(kTailThreads), lds_bytes, st,
-                           desc, info, insts, active, cur_mask, nu1, nu2, coarse_sweeps);
+                           desc, info, insts, active, cur_mask, nu1, nu2, coarse_sweeps, pend);
     else
         hipLaunchKernelGGL((k_tail<3, T, CORR>), dim3(ninst), dim3(kTailThreads), lds_bytes, st,
-                           desc, info, insts, active, cur_mask, nu1, nu2, coarse_sweeps);
+                           desc, info, insts, active, cur_mask, nu1, nu2, coarse_sweeps, pend);
 }
 
 template int prepare_tail<double, false>(int, size_t);
 template int prepare_tail<float, true>(int, size_t);
 template void launch_tail<double, false>(int, const LevelDesc<double>*, const InstInfo*,
                                          const int*, int, const int*, unsigned, int, int, int,
-                                         size_t, hipStream_t);
+                                         double*, size_t, hipStream_t);
 template void launch_tail<float, true>(int, const LevelDesc<float>*, const InstInfo*, const int*,
-                                       int, const int*, unsigned, int, int, int, size_t,
-                                       hipStream_t);
+                                       int, const int*, unsigned, int, int, int, double*,
+                                       size_t, hipStream_t);
 
 }  // namespace chhs

@@ -89,6 +89,8 @@ __global__ __launch_bounds__(NT) void k_tile2d(Batch<T> bt, const TileTask* __re
     const int x0 = tk.bx * kTX - HX, y0 = tk.by * kTY - H;     // region origin in cells
     const int nx = L.nx, ny = L.ny;
     const int tid = threadIdx.x;
+    // a deferred shift of p (Batch::pshift), subtracted as p loads
+    const T psh = bt.pshift != nullptr ? T(bt.pshift[tk.inst * kResStride + 4]) : T(0);
 
     // own-cell data of the thread's pairs, stored by color (index 0 = the red
     // member, 1 = the black member) so that every phase reads them with
@@ -111,7 +113,7 @@ __global__ __launch_bounds__(NT) void k_tile2d(Batch<T> bt, const TileTask* __re
                 const int g = gy * nx + gx;
                 phi = gload(L.phi, g);
                 mu = gload(L.mu, g);
-                p = gload(L.p, g);
+                p = gload(L.p, g) - psh;
                 ps = gload(L.pstar, g);
                 psi = gload(L.psi, g);
                 // the first launch on a coarse level forms f from the restricted residual
