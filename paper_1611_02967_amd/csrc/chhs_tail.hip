@@ -37,16 +37,39 @@ template <int DIM, typename T, bool CORR>
 __device__ void tail_smooth(const Level<T>& L) {
     const float rnx = 1.0f / float(L.nx), rnxy = 1.0f / float(L.nx * L.ny);
     const T inv_lam = T(1) / L.lam;
+    const bool even = (L.nx & 1) == 0;
+    const int hx = L.nx >> 1;
+    const float rhx = 1.0f / float(hx > 0 ? hx : 1), rny = 1.0f / float(L.ny);
     for (int color = 0; color < 2; ++color) {
-        for (int idx = threadIdx.x; idx < L.n; idx += blockDim.x) {
-            int i, j, k;
-            tail_decode<DIM>(idx, L.nx, L.ny, rnx, rnxy, i, j, k);
-            if (((i + j + k) & 1) != color) continue;
-            T phi, mu, p;
-            cell_solve<DIM, T, CORR>(L, idx, i, j, k, inv_lam, phi, mu, p);
-            L.phi[idx] = phi;
-            L.mu[idx] = mu;
-            L.p[idx] = p;
+        if (even) {
+            // thread q takes the q-th cell of the color: every active lane works
+            for (int q = threadIdx.x; q < L.n / 2; q += blockDim.x) {
+                const int row = int((float(q) + 0.5f) * rhx);      // over (j, k)
+                const int m = q - row * hx;
+                int j = row, k = 0;
+                if (DIM == 3) {
+                    k = int((float(row) + 0.5f) * rny);
+                    j = row - k * L.ny;
+                }
+                const int i = 2 * m + ((j + k + color) & 1);
+                const int idx = row * L.nx + i;
+                T phi, mu, p;
+                cell_solve<DIM, T, CORR>(L, idx, i, j, k, inv_lam, phi, mu, p);
+                L.phi[idx] = phi;
+                L.mu[idx] = mu;
+                L.p[idx] = p;
+            }
+        } else {
+            for (int idx = threadIdx.x; idx < L.n; idx += blockDim.x) {
+                int i, j, k;
+                tail_decode<DIM>(idx, L.nx, L.ny, rnx, rnxy, i, j, k);
+                if (((i + j + k) & 1) != color) continue;
+                T phi, mu, p;
+                cell_solve<DIM, T, CORR>(L, idx, i, j, k, inv_lam, phi, mu, p);
+                L.phi[idx] = phi;
+                L.mu[idx] = mu;
+                L.p[idx] = p;
+            }
         }
         __syncthreads();
     }
@@ -55,35 +78,41 @@ __device__ void tail_smooth(const Level<T>& L) {
 template <int DIM, typename T, bool CORR>
 __device__ void tail_restrict(const Level<T>& F, const Level<T>& C) {
     const float rnx = 1.0f / float(C.nx), rnxy = 1.0f / float(C.nx * C.ny);
-    for (int idx = threadIdx.x; idx < C.n; idx += blockDim.x) {
+    // one thread per (coarse cell, child): the 2^DIM children of a coarse cell
+    // are consecutive lanes of one wave, summed by lane exchanges in the fixed
+    // order ((c0 + c1) + (c2 + c3)) [+ the same for the upper four in 3D]
+    constexpr int NCH = DIM == 3 ? 8 : 4;
+    const int nwork = C.n * NCH;
+    const int span = (nwork + 63) & ~63;               // whole waves take part
+    for (int q = threadIdx.x; q < span; q += blockDim.x) {
+        const bool live = q < nwork;
+        const int idx = live ? q / NCH : 0;
+        const int ch = q % NCH;
         int ci, cj, ck;
         tail_decode<DIM>(idx, C.nx, C.ny, rnx, rnxy, ci, cj, ck);
-        T su0 = 0, su1 = 0, su2 = 0, sr0 = 0, sr1 = 0, sr2 = 0, sb = 0;
-#pragma unroll 1
-        for (int dz = 0; dz < (DIM == 3 ? 2 : 1); ++dz)
-#pragma unroll 1
-            for (int dy = 0; dy < 2; ++dy)
-                for (int dx = 0; dx < 2; ++dx) {
-                    const int fi = 2 * ci + dx, fj = 2 * cj + dy, fk = 2 * ck + dz;
-                    const int f = (fk * F.ny + fj) * F.nx + fi;
-                    T n0, n1, n2;
-                    cell_operator<DIM, T, CORR>(F, f, fi, fj, fk, n0, n1, n2);
-                    sr0 += F.f0[f] - n0;
-                    sr1 += F.f1[f] - n1;
-                    sr2 += F.f2[f] - n2;
-                    su0 += F.phi[f];
-                    su1 += F.mu[f];
-                    su2 += F.p[f];
-                    if (CORR) sb += F.b[f];
-                }
-        const T w = DIM == 3 ? T(0.125) : T(0.25);
-        if (CORR) C.b[idx] = sb * w;
-        C.phi[idx] = C.ub0[idx] = su0 * w;
-        C.mu[idx] = C.ub1[idx] = su1 * w;
-        C.p[idx] = C.ub2[idx] = su2 * w;
-        C.f0[idx] = sr0 * w;
-        C.f1[idx] = sr1 * w;
-        C.f2[idx] = sr2 * w;
+        const int fi = 2 * ci + (ch & 1), fj = 2 * cj + ((ch >> 1) & 1), fk = 2 * ck + (ch >> 2);
+        const int f = (fk * F.ny + fj) * F.nx + fi;
+        T n0, n1, n2;
+        cell_operator<DIM, T, CORR>(F, f, fi, fj, fk, n0, n1, n2);
+        T v[7] = {F.f0[f] - n0, F.f1[f] - n1, F.f2[f] - n2, F.phi[f], F.mu[f], F.p[f],
+                  CORR ? F.b[f] : T(0)};
+#pragma unroll
+        for (int c = 0; c < 7; ++c) {
+            if (!CORR && c == 6) continue;
+            v[c] += __shfl_xor(v[c], 1, 64);
+            v[c] += __shfl_xor(v[c], 2, 64);
+            if (DIM == 3) v[c] += __shfl_xor(v[c], 4, 64);
+        }
+        if (live && ch == 0) {
+            const T w = DIM == 3 ? T(0.125) : T(0.25);
+            if (CORR) C.b[idx] = v[6] * w;
+            C.phi[idx] = C.ub0[idx] = v[3] * w;
+            C.mu[idx] = C.ub1[idx] = v[4] * w;
+            C.p[idx] = C.ub2[idx] = v[5] * w;
+            C.f0[idx] = v[0] * w;
+            C.f1[idx] = v[1] * w;
+            C.f2[idx] = v[2] * w;
+        }
     }
     __syncthreads();
     for (int idx = threadIdx.x; idx < C.n; idx += blockDim.x) {
