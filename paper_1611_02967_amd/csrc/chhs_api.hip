@@ -32,6 +32,7 @@ constexpr size_t kAlign = 256;
 // Tiled launches of at most this many blocks (at most one per compute unit)
 // use 1024-thread blocks: their time is the latency of one block.
 constexpr int kWideTiles = 256;
+constexpr long kSmallTileLevel = 128;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 // A table of block tasks in device memory.
@@ -52,6 +53,7 @@ struct Layout {
     std::vector<std::vector<StripTask>> S, Sall;
     bool strip[kMaxLevels] = {};            // level smoothed by the row-streaming kernel
     int wide[kMaxLevels] = {};              // tiles: 1 = 1024-thread blocks, 0 = 256, -1 = by count
+    int tile_y[kMaxLevels] = {};            // tile height of the level's tasks
     int seg[kMaxLevels] = {};               // rows per strip segment of S[l]
     // per level and instance: x / y extent of the grids in S[l] (-1: not listed)
     std::vector<std::vector<int>> snx, sny;
@@ -209,9 +211,9 @@ void cell_tasks(std::vector<CellTask>& out, int inst, int n) {
     for (int c = 0; c < n; c += chhs::kBlock) out.push_back({inst, c});
 }
 
-void tile_tasks(std::vector<TileTask>& out, int inst, int nx, int ny) {
+void tile_tasks(std::vector<TileTask>& out, int inst, int nx, int ny, int tile_y) {
     const int tx = (nx + chhs::kTileX - 1) / chhs::kTileX;
-    const int ty = (ny + chhs::kTileY - 1) / chhs::kTileY;
+    const int ty = (ny + tile_y - 1) / tile_y;
     for (int by = 0; by < ty; ++by)
         for (int bx = 0; bx < tx; ++bx) out.push_back({inst, bx, by});
 }
@@ -313,6 +315,22 @@ bool plan(const chhs_problem* p, int n_inst, const chhs_opts* o, char* base, Lay
     auto ptr32 = [&](size_t o2) -> float* {
         return base ? reinterpret_cast<float*>(base + o2) : nullptr;
     };
+    // tile height per 2D level: 64 x 8 on coarse levels with at most
+    // kSmallTileLevel 64 x 16 tiles over the batch (more, smaller blocks, each
+    // a shorter launch), 64 x 16 elsewhere
+    for (int l = 0; l < kMaxLevels; ++l) L.tile_y[l] = chhs::kTileY;
+    if (dim == 2) {
+        std::vector<long> tiles16(kMaxLevels, 0);
+        for (int i = 0; i < n_inst; ++i) {
+            std::vector<int> ext;
+            if (!valid_problem(&p[i]) || !level_extents(&p[i], ext)) continue;
+            for (size_t l = 0; l < ext.size() / 3; ++l)
+                tiles16[l] += long((ext[3 * l] + chhs::kTileX - 1) / chhs::kTileX) *
+                              ((ext[3 * l + 1] + chhs::kTileY - 1) / chhs::kTileY);
+        }
+        for (int l = 1; l < kMaxLevels; ++l)
+            if (tiles16[l] <= kSmallTileLevel) L.tile_y[l] = chhs::kTileYSmall;
+    }
     int packed = 0;
     for (int i = 0; i < n_inst; ++i) {
         if (!valid_problem(&p[i]) || p[i].dim != dim) return false;
@@ -396,8 +414,8 @@ bool plan(const chhs_problem* p, int n_inst, const chhs_opts* o, char* base, Lay
             if (l < tail) cell_tasks(L.B[l], i, n);
             // levels above the tail have even extents: n / 2 cells per color
             if (l < tail) cell_tasks(L.Bh[l], i, n / 2);
-            if (dim == 2) tile_tasks(L.Tall[l], i, d.nx, d.ny);
-            if (dim == 2 && l < tail) tile_tasks(L.T[l], i, d.nx, d.ny);
+            if (dim == 2) tile_tasks(L.Tall[l], i, d.nx, d.ny, L.tile_y[l]);
+            if (dim == 2 && l < tail) tile_tasks(L.T[l], i, d.nx, d.ny, L.tile_y[l]);
             lnx[l][i] = d.nx;
             lny[l][i] = d.ny;
             if (l < tail) lnx_t[l][i] = d.nx;
@@ -608,7 +626,8 @@ void tiled(chhs_ctx* c, const Hier<T>& H, bool all, int l, int ns, int epi, bool
             const Table<TileTask>& tt = all ? c->Tall[l] : c->T[l];
             const int w = all ? -1 : c->lay.wide[l];
             chhs::launch_tile2d<T>(b, tt.dev, tt.n, level0, ns, epi, pro,
-                                   w < 0 ? tt.n <= kWideTiles : w == 1, rhs, part, c->stream);
+                                   w < 0 ? tt.n <= kWideTiles : w == 1, rhs, c->lay.tile_y[l], part,
+                                   c->stream);
         }
     }
     H.cur[l] ^= 1;

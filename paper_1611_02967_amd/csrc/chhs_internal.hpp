@@ -222,11 +222,11 @@ void launch_fill_int(int* dst, int n, int value, hipStream_t st);
 void launch_copy_int(int* dst, const int* src, int n, hipStream_t st);
 
 // ---- tiled 2D smoothing (chhs_tile2d.hip) ------------------------------------------
-#ifndef CHHS_TILE_Y
-#define CHHS_TILE_Y 16
-#endif
+// Tiles are 64 x 16 cells, or 64 x 8 on coarse levels with few tiles (more,
+// smaller blocks: there the time of one block is the time of the launch).
 constexpr int kTileX = 64;
-constexpr int kTileY = CHHS_TILE_Y;
+constexpr int kTileY = 16;
+constexpr int kTileYSmall = 8;
 // ns fused smoothing steps on level b.level of every tasked instance, read from
 // copy b.cur and written to the other copy; epi 0 none, 1 residual + restriction
 // into level + 1 (copy b.cur_c), 2 residual-norm partials (4 per block, in task
@@ -234,10 +234,11 @@ constexpr int kTileY = CHHS_TILE_Y;
 // phi^m and f_p = 0 implied; wide: 1024 threads per block (one pair of cells
 // per thread) instead of 256, for levels with fewer tiles than compute units;
 // rhs: first pre-smoothing launch on a coarse level, which first forms the FAS
-// right-hand side f += N(u) (not with level0, pro or epi 2).
+// right-hand side f += N(u) (not with level0, pro or epi 2); ty: tile height,
+// kTileY or (not with level0) kTileYSmall, as the tasks were cut.
 template <typename T>
 void launch_tile2d(const Batch<T>& b, const TileTask* t, int nt, bool level0, int ns, int epi,
-                   bool pro, bool wide, bool rhs, double* partial, hipStream_t st);
+                   bool pro, bool wide, bool rhs, int ty, double* partial, hipStream_t st);
 
 // ---- row-streaming 2D smoothing (chhs_stream2d.hip) ---------------------------------
 // Strip sx owns columns [sx kStripWO, (sx + 1) kStripWO) and stages kStripW

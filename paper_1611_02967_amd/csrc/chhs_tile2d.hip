@@ -40,20 +40,18 @@ namespace chhs {
 namespace {
 
 constexpr int kTX = kTileX;     // block width (cells)
-constexpr int kTY = kTileY;     // block height (cells)
-constexpr int kSlots = kTX * kTY / 2;   // pairs of the block (epilogue work items)
 
 // NT threads per block: 256 (four pairs per thread, two blocks per compute
 // unit) on levels with many tiles; 1024 (one pair per thread) on levels with
 // fewer tiles than compute units, where the time of one block is the time of
 // the launch.
-template <int NS, int EPI, int NT>
+template <int NS, int EPI, int NT, int TY>
 struct Geometry {
     static constexpr int X = EPI ? 1 : 0;          // extra valid rings after the last phase
     static constexpr int H = X + 2 * NS;           // halo depth needed by phase 0
     static constexpr int HX = (H + 1) & ~1;        // x halo padded to keep pairs aligned
     static constexpr int W = kTX + 2 * HX;         // region width
-    static constexpr int R = kTY + 2 * H;          // region height
+    static constexpr int R = TY + 2 * H;           // region height
     static constexpr int PW = W / 2;               // pairs per row
     static constexpr int NP = PW * R;              // pairs in the region
     static constexpr int KP = (NP + NT - 1) / NT;   // pairs per thread
@@ -63,10 +61,12 @@ struct Geometry {
 template <int PW>
 __device__ __forceinline__ int lds(int r, int x) { return (2 * r + (x & 1)) * PW + (x >> 1); }
 
-template <typename T, bool LEVEL0, int NS, int EPI, bool PRO, bool CORR, int NT, bool RHS>
+template <typename T, bool LEVEL0, int NS, int EPI, bool PRO, bool CORR, int NT, bool RHS, int TY>
 __global__ __launch_bounds__(NT) void k_tile2d(Batch<T> bt, const TileTask* __restrict__ tasks,
                                                int ntiles, double* partial) {
-    using G = Geometry<NS, EPI, NT>;
+    using G = Geometry<NS, EPI, NT, TY>;
+    constexpr int kTY = TY;                        // block height (cells)
+    constexpr int kSlots = kTX * kTY / 2;          // pairs of the block (epilogue work items)
     constexpr int kThreads = NT;
     constexpr int W = G::W, R = G::R, H = G::H, HX = G::HX;
     constexpr int PW = G::PW, KP = G::KP, NP = G::NP;
@@ -435,22 +435,35 @@ __global__ __launch_bounds__(NT) void k_tile2d(Batch<T> bt, const TileTask* __re
         }
 }
 
-template <typename T, bool LEVEL0, int NS, int EPI, bool PRO, bool CORR, bool RHS = false>
-void launch_one(const Batch<T>& b, const TileTask* t, int nt, bool wide, double* partial,
-                hipStream_t st) {
+template <typename T, bool LEVEL0, int NS, int EPI, bool PRO, bool CORR, bool RHS, int TY>
+void launch_ty(const Batch<T>& b, const TileTask* t, int nt, bool wide, double* partial,
+               hipStream_t st) {
     if (wide)
-        hipLaunchKernelGGL((k_tile2d<T, LEVEL0, NS, EPI, PRO, CORR, 1024, RHS>), dim3(nt), dim3(1024),
-                           0, st, b, t, nt, partial);
+        hipLaunchKernelGGL((k_tile2d<T, LEVEL0, NS, EPI, PRO, CORR, 1024, RHS, TY>), dim3(nt),
+                           dim3(1024), 0, st, b, t, nt, partial);
     else
-        hipLaunchKernelGGL((k_tile2d<T, LEVEL0, NS, EPI, PRO, CORR, 256, RHS>), dim3(nt), dim3(256),
-                           0, st, b, t, nt, partial);
+        hipLaunchKernelGGL((k_tile2d<T, LEVEL0, NS, EPI, PRO, CORR, 256, RHS, TY>), dim3(nt),
+                           dim3(256), 0, st, b, t, nt, partial);
+}
+
+// Finest-level variants exist for 64 x 16 tiles only.
+template <typename T, bool LEVEL0, int NS, int EPI, bool PRO, bool CORR, bool RHS = false>
+void launch_one(const Batch<T>& b, const TileTask* t, int nt, bool wide, int ty, double* partial,
+                hipStream_t st) {
+    if constexpr (!LEVEL0) {
+        if (ty == kTileYSmall) {
+            launch_ty<T, LEVEL0, NS, EPI, PRO, CORR, RHS, kTileYSmall>(b, t, nt, wide, partial, st);
+            return;
+        }
+    }
+    launch_ty<T, LEVEL0, NS, EPI, PRO, CORR, RHS, kTileY>(b, t, nt, wide, partial, st);
 }
 
 }  // namespace
 
 template <>
 void launch_tile2d<double>(const Batch<double>& b, const TileTask* t, int nt, bool level0, int ns,
-                           int epi, bool pro, bool wide, bool rhs, double* partial,
+                           int epi, bool pro, bool wide, bool rhs, int ty, double* partial,
                            hipStream_t st) {
     if (nt <= 0) return;
     if (rhs) {
@@ -458,7 +471,7 @@ void launch_tile2d<double>(const Batch<double>& b, const TileTask* t, int nt, bo
         if (level0 || pro || epi == 2) return;
 #define CHHS_TILE_RHS(NS, EPI)                                                    \
     if (ns == NS && epi == EPI) {                                                 \
-        launch_one<double, false, NS, EPI, false, false, true>(b, t, nt, wide, partial, st); \
+        launch_one<double, false, NS, EPI, false, false, true>(b, t, nt, wide, ty, partial, st); \
         return;                                                                   \
     }
         CHHS_TILE_RHS(1, 0)
@@ -470,7 +483,7 @@ void launch_tile2d<double>(const Batch<double>& b, const TileTask* t, int nt, bo
     }
 #define CHHS_TILE_CASE(L0, NS, EPI, PRO)                                          \
     if (level0 == L0 && ns == NS && epi == EPI && pro == PRO) {                   \
-        launch_one<double, L0, NS, EPI, PRO, false>(b, t, nt, wide, partial, st); \
+        launch_one<double, L0, NS, EPI, PRO, false>(b, t, nt, wide, ty, partial, st); \
         return;                                                                   \
     }
 #define CHHS_TILE_PRO(L0, NS, EPI) CHHS_TILE_CASE(L0, NS, EPI, false) CHHS_TILE_CASE(L0, NS, EPI, true)
@@ -488,7 +501,7 @@ void launch_tile2d<double>(const Batch<double>& b, const TileTask* t, int nt, bo
 // sides, no norm epilogue.
 template <>
 void launch_tile2d<float>(const Batch<float>& b, const TileTask* t, int nt, bool level0, int ns,
-                          int epi, bool pro, bool wide, bool rhs, double* partial,
+                          int epi, bool pro, bool wide, bool rhs, int ty, double* partial,
                           hipStream_t st) {
     (void)level0;
     if (nt <= 0) return;
@@ -496,7 +509,7 @@ void launch_tile2d<float>(const Batch<float>& b, const TileTask* t, int nt, bool
         if (pro || epi == 2) return;
 #define CHHS_TILE_RHS(NS, EPI)                                                    \
     if (ns == NS && epi == EPI) {                                                 \
-        launch_one<float, false, NS, EPI, false, true, true>(b, t, nt, wide, partial, st); \
+        launch_one<float, false, NS, EPI, false, true, true>(b, t, nt, wide, ty, partial, st); \
         return;                                                                   \
     }
         CHHS_TILE_RHS(1, 0)
@@ -508,7 +521,7 @@ void launch_tile2d<float>(const Batch<float>& b, const TileTask* t, int nt, bool
     }
 #define CHHS_TILE_CASE(NS, EPI, PRO)                                              \
     if (ns == NS && epi == EPI && pro == PRO) {                                   \
-        launch_one<float, false, NS, EPI, PRO, true>(b, t, nt, wide, partial, st); \
+        launch_one<float, false, NS, EPI, PRO, true>(b, t, nt, wide, ty, partial, st); \
         return;                                                                   \
     }
     CHHS_TILE_CASE(1, 0, false)
