@@ -1082,8 +1082,9 @@ int setup(chhs_ctx* c, const double* phi_prev, const double* phi_cur, const doub
         chhs::launch_fill_int(c->act_next, c->n_inst, 1, c->stream);
         chhs::launch_fill_int(c->cycles, c->n_inst, 0, c->stream);
         chhs::launch_copy_int(c->act_cycle, c->act_next, c->n_inst, c->stream);
+        // the plain path forms the initial residual's norm partials in the same pass
         chhs::launch_setup(dim, batch(c, 0, nullptr), c->A[0].dev, c->A[0].n, c->dinfo, phi_prev,
-                           phi_cur, mu, p, c->stream);
+                           phi_cur, mu, p, c->mixed ? nullptr : c->partial, c->stream);
         if (c->mixed) {
             chhs::launch_mixed_frozen(batch(c, 0, nullptr), batch32(c, 0, nullptr), c->A[0].dev,
                                       c->A[0].n, c->stream);
@@ -1100,8 +1101,6 @@ int setup(chhs_ctx* c, const double* phi_prev, const double* phi_cur, const doub
         enqueue_refinement(c, false, false);
     } else {
         TimedScope t(c, CHHS_K_NORM);
-        chhs::launch_residual_partials(dim, batch(c, 0, nullptr), c->A[0].dev, c->A[0].n,
-                                       c->partial, c->stream);
         chhs::launch_inst_reduce(c->partial, c->rngA0, nullptr, nullptr, 0, c->dinfo, nullptr,
                                  c->act_next, c->cycles, c->res, c->n_inst, c->opts.tol,
                                  c->opts.max_vcycles, 0, c->stream);

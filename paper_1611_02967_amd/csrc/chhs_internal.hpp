@@ -145,9 +145,11 @@ struct Batch {
 };
 
 // ---- per-cell kernels (chhs_kernels.hip); dim is 2 or 3 ----------------------------
+// With partial: also the norm partials of the initial guess's residual, as
+// launch_residual_partials gives them (one per task).
 void launch_setup(int dim, const Batch<double>& b, const CellTask* t, int nt, const InstInfo* info,
                   const double* phi_prev, const double* phi_cur, const double* mu,
-                  const double* p, hipStream_t st);
+                  const double* p, double* partial, hipStream_t st);
 // FP64 overloads act on the plain form, FP32 overloads on the correction form
 // of the mixed-precision inner solve (restriction then also averages b).
 void launch_restrict_frozen(int dim, const Batch<double>& b, const CellTask* t, int nt,

@@ -19,40 +19,84 @@ __device__ __forceinline__ Level<T> view_at(const Batch<T>& b, int inst, int lev
     return make_view(b.desc[inst * kMaxLevels + level], cur);
 }
 
+template <int NC>
+__device__ __forceinline__ void block_sum(double (&v)[NC], double* out);
+
+// Per-step setup of the finest level, and with `partial` the residual of the
+// initial guess u = (phi^m, mu, p) in the same pass: its norm partials (R_phi^2,
+// R_mu^2, R_p^2, p) per block, as k_residual_partials gives them, formed from
+// the caller's arrays (the values the level receives here), with N(u) written
+// as cell_operator writes it.
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_setup(Batch<double> b, const CellTask* __restrict__ t,
                                                   const InstInfo* __restrict__ info,
                                                   const double* __restrict__ phi_prev,
                                                   const double* __restrict__ phi_cur,
                                                   const double* __restrict__ mu,
-                                                  const double* __restrict__ p) {
+                                                  const double* __restrict__ p, double* partial) {
     const CellTask tk = t[blockIdx.x];
     const Level<double> L = view_at(b, tk.inst, 0, b.cur);
     const int idx = tk.cell0 + threadIdx.x;
-    if (idx >= L.n) return;
-    const InstInfo in = info[tk.inst];
-    const int g = in.off + idx;
-    int i, j, k;
-    decode<DIM>(idx, L.nx, L.ny, i, j, k);
-    const double pm = phi_prev[g];
-    const double pc = phi_cur[g];
-    double lap = 0.0;
-    for_each_face<DIM>(i, j, k, L.nx, L.ny, L.nz, idx, [&](bool h, int nb) {
-        const double d = phi_prev[in.off + nb] - pm;
-        lap = h ? lap + d : lap;
-    });
-    const double q = 0.25 * in.eps * in.eps / (in.h * in.h);
-    // the first-order step (order 1): phi_* := phi^m and f_mu = -phi^m
-    const bool first = in.order == 1;
-    const double ps = first ? pc : 1.5 * pc - 0.5 * pm;   // phi_*, (2.4)
-    L.pstar[idx] = ps;
-    L.psi[idx] = pc;
-    L.f0[idx] = pc;                                   // (2.5): phi^m
-    L.f1[idx] = first ? -pc : -ps - q * lap;          // (2.6): -phi_* - eps^2/4 Lap phi^{m-1}
-    L.f2[idx] = 0.0;                                  // (2.7)
-    L.phi[idx] = pc;                                  // initial guess phi^m
-    L.mu[idx] = mu[g];
-    L.p[idx] = p[g];
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    if (idx < L.n) {
+        const InstInfo in = info[tk.inst];
+        const int g = in.off + idx;
+        int i, j, k;
+        decode<DIM>(idx, L.nx, L.ny, i, j, k);
+        const double pm = phi_prev[g];
+        const double pc = phi_cur[g];
+        const double muc = mu[g], pp = p[g];
+        // the first-order step (order 1): phi_* := phi^m and f_mu = -phi^m
+        const bool first = in.order == 1;
+        const double ps = first ? pc : 1.5 * pc - 0.5 * pm;   // phi_*, (2.4)
+        double lap = 0.0;
+        double smm = 0, sap = 0, sphi = 0, sp = 0, samu = 0;
+        for_each_face<DIM>(i, j, k, L.nx, L.ny, L.nz, idx, [&](bool h, int nb) {
+            const int gn = in.off + nb;
+            const double pmn = phi_prev[gn];
+            const double d = pmn - pm;
+            lap = h ? lap + d : lap;
+            if (partial != nullptr) {
+                const double pcn = phi_cur[gn];
+                const double a = 0.5 * (ps + (first ? pcn : 1.5 * pcn - 0.5 * pmn));
+                const double m = 1.0 + L.gamma * a * a;
+                const double dmu = mu[gn] - muc;
+                const double dp = p[gn] - pp;
+                const double dphi = pcn - pc;
+                smm = h ? smm + m * dmu : smm;
+                sap = h ? sap + a * dp : sap;
+                sphi = h ? sphi + dphi : sphi;
+                sp = h ? sp + dp : sp;
+                samu = h ? samu + a * dmu : samu;
+            }
+        });
+        const double q = 0.25 * in.eps * in.eps / (in.h * in.h);
+        const double f1 = first ? -pc : -ps - q * lap;
+        L.pstar[idx] = ps;
+        L.psi[idx] = pc;
+        L.f0[idx] = pc;                                   // (2.5): phi^m
+        L.f1[idx] = f1;                                   // (2.6): -phi_* - eps^2/4 Lap phi^{m-1}
+        L.f2[idx] = 0.0;                                  // (2.7)
+        L.phi[idx] = pc;                                  // initial guess phi^m
+        L.mu[idx] = muc;
+        L.p[idx] = pp;
+        if (partial != nullptr) {
+            const double chi = first ? pc * pc * pc : nonlin<double, false>(pc, pc, 0.0);
+            const double n0 = pc - L.lam * smm - L.lam * sap;
+            const double n1 = muc - chi + L.kap * sphi;
+            const double n2 = L.lam * sp + L.lam * L.gamma * samu;
+            const double r0 = pc - n0, r1 = f1 - n1, r2 = -n2;
+            v[0] = r0 * r0;
+            v[1] = r1 * r1;
+            v[2] = r2 * r2;
+            v[3] = pp;
+        }
+    }
+    if (partial == nullptr) return;
+    double out[4];
+    block_sum<4>(v, out);
+    if (threadIdx.x == 0)
+        for (int c = 0; c < 4; ++c) partial[blockIdx.x * kPartialStride + c] = out[c];
 }
 
 // tasks over coarse cells (level b.level + 1)
@@ -548,8 +592,8 @@ inline int blocks_for(int n) { return (n + kBlock - 1) / kBlock; }
 
 void launch_setup(int dim, const Batch<double>& b, const CellTask* t, int nt, const InstInfo* info,
                   const double* phi_prev, const double* phi_cur, const double* mu,
-                  const double* p, hipStream_t st) {
-    CHHS_DISPATCH(dim, k_setup, nt, b, t, info, phi_prev, phi_cur, mu, p);
+                  const double* p, double* partial, hipStream_t st) {
+    CHHS_DISPATCH(dim, k_setup, nt, b, t, info, phi_prev, phi_cur, mu, p, partial);
 }
 
 #define CHHS_DISPATCH_T(dim, KERNEL, GRID, ...)                                           \
