@@ -13,7 +13,7 @@ extrapolation and nonlinearity of (2.4):
     N_mu(u)  = mu - chi(phi, phi^m) + 3/4 eps^2 Lap phi          = -phi_* - 1/4 eps^2 Lap phi^{m-1}
     N_p(u)   = s Lap p + s gamma div(a grad mu)                   = 0
 
-Readings of points the paper leaves open (each is also listed in the design doc):
+Readings of points the paper leaves open:
 * The pressure equation (2.7) enters the residual multiplied by s, so all three
   components have an O(1)-scaled roundoff floor; the residual norm is the
   h^d-weighted l2 norm of App. A.2 summed over the three components.
