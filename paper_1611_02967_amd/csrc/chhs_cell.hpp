@@ -97,40 +97,49 @@ __device__ __forceinline__ T dnonlin(T x, T psi, T b) {
     return T(0.25) * (T(3) * y * y + T(2) * y * psi + psi * psi);
 }
 
-// v + (v of lane l ^ 16) and v + (v of lane l ^ 32) with the lane-row swaps
-// of gfx950 (VALU, no LDS traffic): swapping a value with itself leaves one
-// lane of each exchanged pair in either result, so their sum is the pairwise
-// sum at every lane, the same operands as v + __shfl_xor(v, 16 or 32).  Every
-// lane of the wave must be active.
-__device__ __forceinline__ double rows_sum(double v, bool by32) {
-    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
-    const unsigned lo = unsigned(b), hi = unsigned(b >> 32);
+// Lane-row exchanges of gfx950 (VALU, no LDS traffic) summed: with rows of
+// 16 lanes, v_permlane16_swap trades the odd rows of its first operand for
+// the even rows of its second, and v_permlane32_swap the upper 32 lanes of the
+// first for the lower 32 of the second.  Adding the two swapped registers gives
+//   by32 = false: rows 0-3 hold x0 + x1, y0 + y1, x2 + x3, y2 + y3
+//   by32 = true:  lanes 0-31 hold x_lo + x_hi, lanes 32-63 y_lo + y_hi
+// (xi = x in row i, lane by lane), so one exchange sums two values across
+// lanes l, l ^ 16 (or l ^ 32) at once.  With x = y every lane gets
+// v + (v of lane l ^ 16 or ^ 32): rows_sum.  Every lane of the wave must be
+// active.
+__device__ __forceinline__ double swap_sum(double x, double y, bool by32) {
+    const unsigned long long bx = __builtin_bit_cast(unsigned long long, x);
+    const unsigned long long by = __builtin_bit_cast(unsigned long long, y);
+    const unsigned xl = unsigned(bx), xh = unsigned(bx >> 32);
+    const unsigned yl = unsigned(by), yh = unsigned(by >> 32);
     unsigned a0, a1, c0, c1;
     if (by32) {
-        const auto l = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
-        const auto h = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+        const auto l = __builtin_amdgcn_permlane32_swap(xl, yl, false, false);
+        const auto h = __builtin_amdgcn_permlane32_swap(xh, yh, false, false);
         a0 = l[0], a1 = h[0], c0 = l[1], c1 = h[1];
     } else {
-        const auto l = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
-        const auto h = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+        const auto l = __builtin_amdgcn_permlane16_swap(xl, yl, false, false);
+        const auto h = __builtin_amdgcn_permlane16_swap(xh, yh, false, false);
         a0 = l[0], a1 = h[0], c0 = l[1], c1 = h[1];
     }
     const double a = __builtin_bit_cast(double, (unsigned long long)a0 | ((unsigned long long)a1 << 32));
     const double c = __builtin_bit_cast(double, (unsigned long long)c0 | ((unsigned long long)c1 << 32));
     return a + c;
 }
-__device__ __forceinline__ float rows_sum(float v, bool by32) {
-    const unsigned x = __builtin_bit_cast(unsigned, v);
+__device__ __forceinline__ float swap_sum(float x, float y, bool by32) {
+    const unsigned xb = __builtin_bit_cast(unsigned, x), yb = __builtin_bit_cast(unsigned, y);
     unsigned a, c;
     if (by32) {
-        const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+        const auto r = __builtin_amdgcn_permlane32_swap(xb, yb, false, false);
         a = r[0], c = r[1];
     } else {
-        const auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+        const auto r = __builtin_amdgcn_permlane16_swap(xb, yb, false, false);
         a = r[0], c = r[1];
     }
     return __builtin_bit_cast(float, a) + __builtin_bit_cast(float, c);
 }
+template <typename T>
+__device__ __forceinline__ T rows_sum(T v, bool by32) { return swap_sum(v, v, by32); }
 
 // 1 / x for x >= 1 (the determinant of the collective cell solve): the
 // hardware reciprocal estimate refined by Newton steps r <- r + r (1 - x r),

@@ -245,9 +245,10 @@ __attribute__((amdgpu_waves_per_eu(LEVEL0 || CORR ? 3 : 1))) void k_stream2d(Bat
         // col(c - 1), col(c), col(c + 1), wrapped within the row at the edges.
         if (!XIN && (c < 1 || c > kW - 2 || gx < 0 || gx >= nx)) return;
         const int sc = r % RING, sd = (r + RING - 1) % RING, su = (r + 1) % RING;
-        const int wc = XIN ? lane + kHalf * e : col(c);
-        const int wl = XIN ? lane + (kHalf - 1) * (1 - e) : col(c - 1);
-        const int wr = XIN ? lane + kHalf - (kHalf - 1) * e : col(c + 1);
+        // (e is uniform: the offsets are scalar selects)
+        const int wc = XIN ? lane + (e ? kHalf : 0) : col(c);
+        const int wl = XIN ? lane + (e ? 0 : kHalf - 1) : col(c - 1);
+        const int wr = XIN ? lane + (e ? 1 : kHalf) : col(c + 1);
         const T psc = s[sc][PS][wc];
         // every neighbour is read (rows across the boundary read in-bounds ring
         // words) so that the reads issue together; missing faces add nothing
@@ -305,12 +306,15 @@ __attribute__((amdgpu_waves_per_eu(LEVEL0 || CORR ? 3 : 1))) void k_stream2d(Bat
     const int ogx = x0 + oc;
     const bool own_col = oc >= kStripHX && oc < kStripHX + kStripWO && ogx < nx;
     const bool ocol = ogx >= 0 && ogx < nx;
+    // the coarse cell of lane column ocl (its children's columns are owned together)
+    const bool own_coarse = 2 * ocl >= kStripHX && 2 * ocl < kStripHX + kStripWO && x0 + 2 * ocl < nx;
+    const int orow = (ody ? nx : 0) + ogx;             // offset of the cell from row k2
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     T lo[NO];                                          // own data of the leaving cell
 
     auto load_leave = [&](int k2) {
         const int r = k2 + ody;
-        const int g = (ocol && r >= 0 && r < ny) ? r * nx + ogx : 0;
+        const int g = (ocol && r >= 0 && r < ny) ? k2 * nx + orow : 0;
 #pragma unroll
         for (int k = 0; k < NO; ++k) lo[k] = gload(own_src[k], g);
     };
@@ -318,10 +322,13 @@ __attribute__((amdgpu_waves_per_eu(LEVEL0 || CORR ? 3 : 1))) void k_stream2d(Bat
     auto leave = [&](int k2) {
         const int r = k2 + ody;
         const bool own = own_col && r < ny;
-        const int sc = r % RING;
+        // ring slots of rows k2 - 1 .. k2 + 2 (uniform), then per lane row
+        const int sl_m = (k2 + RING - 1) % RING, sl_0 = k2 % RING;
+        const int sl_1 = (k2 + 1) % RING, sl_2 = (k2 + 2) % RING;
+        const int sc = ody ? sl_1 : sl_0;
         const int wc = col(oc);
         const T phic = s[sc][PHI][wc], muc = s[sc][MU][wc], pc = s[sc][P][wc];
-        const int g = r * nx + ogx;
+        const int g = k2 * nx + orow;
         if (own) {
             gstore_stream(L.phi_alt, g, phic);
             gstore_stream(L.mu_alt, g, muc);
@@ -330,7 +337,7 @@ __attribute__((amdgpu_waves_per_eu(LEVEL0 || CORR ? 3 : 1))) void k_stream2d(Bat
         if (EPI == 0) return;
         // computed by every lane (halo lanes read clamped, in-bounds words);
         // only owned cells are stored or summed
-        const int sd = (r + RING - 1) % RING, su = (r + 1) % RING;
+        const int sd = ody ? sl_0 : sl_m, su = ody ? sl_2 : sl_1;
         const int wl = col(oc > 0 ? oc - 1 : 0), wr = col(oc < kW - 1 ? oc + 1 : kW - 1);
         const T psc = s[sc][PS][wc];
         T nps[4], nmu[4], np[4], nphi[4];
@@ -388,27 +395,34 @@ __attribute__((amdgpu_waves_per_eu(LEVEL0 || CORR ? 3 : 1))) void k_stream2d(Bat
             }
             return;
         }
-        // EPI 1: sum the children, columns first, then rows
-        T v[7] = {r0, r1, r2, phic, muc, pc, bg};
-#pragma unroll
-        for (int c = 0; c < 7; ++c) {
-            if (!CORR && c == 6) continue;
-            v[c] = rows_sum(v[c], false);
-            v[c] = rows_sum(v[c], true);
-        }
-        if (own && odx == 0 && ody == 0) {
-            const int cgi = (k2 >> 1) * C.nx + (ogx >> 1);
-            const T w = T(0.25);
-            gstore(C.phi, cgi, v[3] * w);
-            gstore(C.ub0, cgi, v[3] * w);
-            gstore(C.mu, cgi, v[4] * w);
-            gstore(C.ub1, cgi, v[4] * w);
-            gstore(C.p, cgi, v[5] * w);
-            gstore(C.ub2, cgi, v[5] * w);
-            gstore(C.fr0, cgi, v[0] * w);
-            gstore(C.fr1, cgi, v[1] * w);
-            gstore(C.fr2, cgi, v[2] * w);
-            if (CORR) gstore(C.b, cgi, v[6] * w);
+        // EPI 1: sum the children, columns (lanes l, l ^ 16) first, then rows
+        // (l, l ^ 32), two fields per exchange.  Rows of 16 lanes after the
+        // column sums: (r0, r1, r0, r1), (r2, phi, r2, phi), (mu, p, mu, p),
+        // the last two rows being fine row k2 + 1; after the row sums:
+        // (r0, r1, r2, phi) and (mu, p, mu, p) for coarse column ocl.
+        const T w = T(0.25);
+        const T c01 = swap_sum(r0, r1, false);
+        const T c2u = swap_sum(r2, phic, false);
+        const T cmp = swap_sum(muc, pc, false);
+        const T q1 = swap_sum(c01, c2u, true) * w;
+        const T q2 = swap_sum(cmp, cmp, true) * w;
+        const T qb = CORR ? rows_sum(rows_sum(bg, false), true) * w : T(0);
+        if (own_coarse && k2 < ny) {
+            const int cgi = (k2 >> 1) * C.nx + (x0 >> 1) + ocl;
+            // one store per destination, each by the lanes of one row
+            // (separate conditions, so that no store is merged into one
+            // through a selected address)
+            const int rw = lane >> 4;
+            if (rw == 0) gstore(C.fr0, cgi, q1);
+            if (rw == 1) gstore(C.fr1, cgi, q1);
+            if (rw == 2) gstore(C.fr2, cgi, q1);
+            if (rw == 3) gstore(C.phi, cgi, q1);
+            if (rw == 3) gstore(C.ub0, cgi, q1);
+            if (rw == 0) gstore(C.mu, cgi, q2);
+            if (rw == 1) gstore(C.p, cgi, q2);
+            if (rw == 2) gstore(C.ub1, cgi, q2);
+            if (rw == 3) gstore(C.ub2, cgi, q2);
+            if (CORR && rw == 0) gstore(C.b, cgi, qb);
         }
     };
 

@@ -396,26 +396,27 @@ __global__ __launch_bounds__(NT) void k_tile2d(Batch<T> bt, const TileTask* __re
             }
         }
         if (EPI == 1) {
-            // combine the two rows (lane ^ 32); row 0 writes the coarse cell
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                sr[c] = rows_sum(sr[c], true);
-                su[c] = rows_sum(su[c], true);
-            }
-            if (CORR) sb = rows_sum(sb, true);
-            if (live && cy == 0) {
+            // combine the two rows (lane ^ 32), two fields per exchange: lanes
+            // 0-31 then hold r0, r2, mu and lanes 32-63 r1, phi, p of the coarse cell
+            const T w = T(0.25);
+            const T q0 = swap_sum(sr[0], sr[1], true) * w;
+            const T q1 = swap_sum(sr[2], su[0], true) * w;
+            const T q2 = swap_sum(su[1], su[2], true) * w;
+            const T qb = CORR ? rows_sum(sb, true) * w : T(0);
+            if (live) {
                 const int c = gcy * C.nx + gcx;
-                const T w = T(0.25);
-                gstore(C.phi, c, su[0] * w);
-                gstore(C.ub0, c, su[0] * w);
-                gstore(C.mu, c, su[1] * w);
-                gstore(C.ub1, c, su[1] * w);
-                gstore(C.p, c, su[2] * w);
-                gstore(C.ub2, c, su[2] * w);
-                gstore(C.fr0, c, sr[0] * w);
-                gstore(C.fr1, c, sr[1] * w);
-                gstore(C.fr2, c, sr[2] * w);
-                if (CORR) gstore(C.b, c, sb * w);
+                // separate conditions, so that no two stores merge into one
+                // through a selected address
+                if (cy == 0) gstore(C.fr0, c, q0);
+                if (cy == 1) gstore(C.fr1, c, q0);
+                if (cy == 0) gstore(C.fr2, c, q1);
+                if (cy == 1) gstore(C.phi, c, q1);
+                if (cy == 1) gstore(C.ub0, c, q1);
+                if (cy == 0) gstore(C.mu, c, q2);
+                if (cy == 0) gstore(C.ub1, c, q2);
+                if (cy == 1) gstore(C.p, c, q2);
+                if (cy == 1) gstore(C.ub2, c, q2);
+                if (CORR && cy == 0) gstore(C.b, c, qb);
             }
         }
     }
