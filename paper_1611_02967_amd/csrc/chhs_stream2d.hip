@@ -138,7 +138,8 @@ __attribute__((amdgpu_waves_per_eu(LEVEL0 || CORR ? 3 : 1))) void k_stream2d(Bat
     const bool lcol = lgx >= 0 && lgx < nx;
     // j = 0: phi | mu, j = 1: p | phi_*
     const T* src[2] = {half ? L.mu : L.phi, half ? L.pstar : L.p};
-    // a deferred shift of p (Batch::pshift), subtracted from field p as it loads
+    // a deferred shift of p (Batch::pshift), subtracted from field p as it
+    // enters the ring (not at the load, which would wait for the load at once)
     const T psh = bt.pshift != nullptr && half == 0 ? T(bt.pshift[tk.inst * kResStride + 4]) : T(0);
     const T* csrc[2] = {nullptr, nullptr};
     const T* cbar[2] = {nullptr, nullptr};
@@ -158,7 +159,6 @@ __attribute__((amdgpu_waves_per_eu(LEVEL0 || CORR ? 3 : 1))) void k_stream2d(Bat
         const int g = ok ? r * nx + lgx : 0;
 #pragma unroll
         for (int j = 0; j < 2; ++j) v[j] = gload_stream(src[j], g);
-        v[1] -= psh;
         if (PRO) {
             const int cg = ok ? (r >> 1) * C.nx + (lgx >> 1) : 0;
 #pragma unroll
@@ -174,7 +174,7 @@ __attribute__((amdgpu_waves_per_eu(LEVEL0 || CORR ? 3 : 1))) void k_stream2d(Bat
         const int w = col(lc);
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-            T x = lcol ? v[j] : T(0);
+            T x = lcol ? (j == 1 ? v[j] - psh : v[j]) : T(0);
             // prolongation of the correction onto phi, mu, p (not phi_*)
             if (PRO && lcol && (j == 0 || half == 0)) x += vc[j] - vb[j];
             s[slot][2 * j + half][w] = x;
