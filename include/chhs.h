@@ -76,8 +76,11 @@ typedef struct chhs_problem {
  * coarser ones), 1 = tiles everywhere, 2 = strips on every level (including
  * the explicit smoothing calls on tail levels).  Both
  * kernels perform the same red-black updates in the same arithmetic.
+ * tile_threads = 0 (default) gives tiled levels 1024-thread blocks when they
+ * have at most 256 tiles and 256-thread blocks otherwise; 256, 512 or 1024
+ * fixes the block size of every tiled level (the same arithmetic per cell).
  * autotune = 1 (2D, smoother = 0, nu1, nu2 >= 1): chhs_init times, on the problem at hand,
- * each level's smoothing launches with tiles of 256 and 1024 threads and with
+ * each level's smoothing launches with tiles of 256, 512 and 1024 threads and with
  * strips of 1, 2 and 4 times the default segment height, and keeps the fastest
  * per level (the choice then depends on the device; results agree to rounding).
  * order = 2 (default; 0 means the same) solves the second-order scheme
@@ -97,7 +100,8 @@ typedef struct chhs_opts {
     int32_t smoother;
     int32_t autotune;
     int32_t order;
-    int32_t reserved[2];
+    int32_t tile_threads;
+    int32_t reserved[1];
 } chhs_opts;
 
 /* Kernel classes of chhs_timing. */

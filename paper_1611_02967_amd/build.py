@@ -21,11 +21,9 @@ ARCH = "gfx950"
 SOURCES = ["chhs_api.hip", "chhs_kernels.hip", "chhs_tile2d.hip", "chhs_stream2d.hip",
            "chhs_tail.hip"]
 
-# -packed-fp32-ops: keep the compiler from forming packed FP32 instructions;
-# -fno-signed-zeros: lets sums that start at 0 begin with their first term
-# (x + 0 -> x), which changes no value other than the sign of a zero
+# -packed-fp32-ops: keep the compiler from forming packed FP32 instructions
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
-          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-fno-signed-zeros",
+          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wall", "-Wno-unused-function", f"-I{INCLUDE}", f"-I{CSRC}"]
 
 

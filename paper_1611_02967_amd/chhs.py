@@ -37,7 +37,8 @@ class chhs_opts(ctypes.Structure):
                 ("tol", ctypes.c_double), ("precision", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("timing", ctypes.c_int32),
                 ("smoother", ctypes.c_int32), ("autotune", ctypes.c_int32),
-                ("order", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+                ("order", ctypes.c_int32), ("tile_threads", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 1)]
 
 
 K_CLASSES = ["pre0", "post0", "transfer0", "coarse", "norm", "setup", "k6", "k7"]

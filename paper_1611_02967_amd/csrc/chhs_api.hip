@@ -33,6 +33,11 @@ constexpr size_t kAlign = 256;
 // use 1024-thread blocks: their time is the latency of one block.
 constexpr int kWideTiles = 256;
 constexpr long kSmallTileLevel = 128;
+// Threads per tile block: the autotuned choice (256, 512 or 1024), else by
+// the number of tiles.
+int tile_block(int chosen, int ntiles) {
+    return chosen > 0 ? chosen : (ntiles <= kWideTiles ? 1024 : 256);
+}
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 // A table of block tasks in device memory.
@@ -52,7 +57,7 @@ struct Layout {
     std::vector<std::vector<TileTask>> T, Tall;
     std::vector<std::vector<StripTask>> S, Sall;
     bool strip[kMaxLevels] = {};            // level smoothed by the row-streaming kernel
-    int wide[kMaxLevels] = {};              // tiles: 1 = 1024-thread blocks, 0 = 256, -1 = by count
+    int tile_threads[kMaxLevels] = {};      // tiles: threads per block, 0 = by the tile count
     int tile_y[kMaxLevels] = {};            // tile height of the level's tasks
     int seg[kMaxLevels] = {};               // rows per strip segment of S[l]
     // per level and instance: x / y extent of the grids in S[l] (-1: not listed)
@@ -164,6 +169,9 @@ bool valid_opts(const chhs_opts* o) {
     if (o->autotune < 0 || o->autotune > 1) return false;
     if (o->order < 0 || o->order > 2) return false;
     if (o->order == 1 && o->precision != 0) return false;
+    if (o->tile_threads != 0 && o->tile_threads != 256 && o->tile_threads != 512 &&
+        o->tile_threads != 1024)
+        return false;
     return true;
 }
 
@@ -434,7 +442,7 @@ bool plan(const chhs_problem* p, int n_inst, const chhs_opts* o, char* base, Lay
             strip_tasks(L.Sall[l], lnx[l], lny[l], strip_seg(lnx[l], lny[l], slots));
             L.seg[l] = strip_seg(lnx_t[l], lny[l], slots);
             strip_tasks(L.S[l], lnx_t[l], lny[l], L.seg[l]);
-            L.wide[l] = -1;
+            L.tile_threads[l] = o->tile_threads;
             // default: strips on the finest level (long segments, two blocks
             // per compute unit), tiles below, where more and shorter blocks
             // hide latency better
@@ -624,10 +632,9 @@ void tiled(chhs_ctx* c, const Hier<T>& H, bool all, int l, int ns, int epi, bool
             chhs::launch_stream2d<T>(b, st.dev, st.n, level0, ns, epi, pro, part, c->stream);
         } else {
             const Table<TileTask>& tt = all ? c->Tall[l] : c->T[l];
-            const int w = all ? -1 : c->lay.wide[l];
             chhs::launch_tile2d<T>(b, tt.dev, tt.n, level0, ns, epi, pro,
-                                   w < 0 ? tt.n <= kWideTiles : w == 1, rhs, c->lay.tile_y[l], part,
-                                   c->stream);
+                                   tile_block(all ? 0 : c->lay.tile_threads[l], tt.n), rhs,
+                                   c->lay.tile_y[l], part, c->stream);
         }
     }
     H.cur[l] ^= 1;
@@ -801,8 +808,8 @@ float time_level(chhs_ctx* c, const Hier<T>& H, int l, int reps, hipEvent_t ea, 
     return best;
 }
 
-// Picks, per 2D level above the tail, the fastest of: tiles with 256 or 1024
-// threads, strips with 1, 2 or 4 times the default segment height.  Runs the
+// Picks, per 2D level above the tail, the fastest of: tiles with 256, 512 or
+// 1024 threads, strips with 1, 2 or 4 times the default segment height.  Runs the
 // candidates on the workspace as it is (its contents do not matter for the
 // timing and are rewritten by the next setup).
 int autotune(chhs_ctx* c) {
@@ -816,9 +823,9 @@ int autotune(chhs_ctx* c) {
         if (c->T[l].n == 0) continue;
         struct Cand {
             bool strip;
-            int wide, seg;
+            int threads, seg;
         };
-        std::vector<Cand> cands = {{false, 0, 0}, {false, 1, 0}};
+        std::vector<Cand> cands = {{false, 256, 0}, {false, 512, 0}, {false, 1024, 0}};
         bool even = true;
         int maxny = 0;
         for (int i = 0; i < c->n_inst; ++i)
@@ -830,12 +837,12 @@ int autotune(chhs_ctx* c) {
         if (even && c->S[l].n > 0)
             for (int m = 1; m <= 4; m *= 2) {
                 const int sg = std::min(seg0 * m, (maxny + 1) & ~1);
-                if (m == 1 || sg > cands.back().seg) cands.push_back({true, -1, sg});
+                if (m == 1 || sg > cands.back().seg) cands.push_back({true, 0, sg});
             }
         const int cap = c->S[l].n;
         auto apply = [&](const Cand& k) -> int {
             L.strip[l] = k.strip;
-            L.wide[l] = k.wide;
+            L.tile_threads[l] = k.threads;
             if (!k.strip) return CHHS_OK;
             L.seg[l] = k.seg;
             L.S[l].clear();
@@ -1420,10 +1427,8 @@ int chhs_level_kernel(chhs_ctx* c, int32_t level, int32_t* out3) {
         out3[1] = c->lay.seg[level];
         out3[2] = c->S[level].n;
     } else {
-        const int w = c->lay.wide[level];
-        const bool wide = w < 0 ? c->T[level].n <= kWideTiles : w == 1;
         out3[0] = 0;
-        out3[1] = wide ? 1024 : 256;
+        out3[1] = tile_block(c->lay.tile_threads[level], c->T[level].n);
         out3[2] = c->T[level].n;
     }
     return CHHS_OK;

@@ -199,7 +199,9 @@ __device__ __forceinline__ void cell_operator(const Level<T>& L, int idx, int i,
 //
 // Written with one reciprocal of the determinant (recip_ge1) and 1/nF by cases, in the
 // same operation order as the tiled and row-streaming 2D kernels, so that
-// every path performs bitwise the same update.  inv_lam = 1 / lam.
+// every path performs the same update; kernels differ at most in which
+// products the compiler fuses into multiply-adds, i.e. they agree to
+// rounding.  inv_lam = 1 / lam.
 template <int DIM, typename T, bool CORR = false>
 __device__ __forceinline__ void cell_solve(const Level<T>& L, int idx, int i, int j, int k,
                                            T inv_lam, T& phi_o, T& mu_o, T& p_o) {

@@ -233,14 +233,14 @@ constexpr int kTileYSmall = 8;
 // copy b.cur and written to the other copy; epi 0 none, 1 residual + restriction
 // into level + 1 (copy b.cur_c), 2 residual-norm partials (4 per block, in task
 // order); pro: prolongation of level + 1's correction first; level0: f_phi =
-// phi^m and f_p = 0 implied; wide: 1024 threads per block (one pair of cells
-// per thread) instead of 256, for levels with fewer tiles than compute units;
+// phi^m and f_p = 0 implied; threads: 256, 512 or 1024 per block (four, two
+// or one pair of cells per thread);
 // rhs: first pre-smoothing launch on a coarse level, which first forms the FAS
 // right-hand side f += N(u) (not with level0, pro or epi 2); ty: tile height,
 // kTileY or (not with level0) kTileYSmall, as the tasks were cut.
 template <typename T>
 void launch_tile2d(const Batch<T>& b, const TileTask* t, int nt, bool level0, int ns, int epi,
-                   bool pro, bool wide, bool rhs, int ty, double* partial, hipStream_t st);
+                   bool pro, int threads, bool rhs, int ty, double* partial, hipStream_t st);
 
 // ---- row-streaming 2D smoothing (chhs_stream2d.hip) ---------------------------------
 // Strip sx owns columns [sx kStripWO, (sx + 1) kStripWO) and stages kStripW

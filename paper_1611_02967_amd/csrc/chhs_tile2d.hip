@@ -41,10 +41,10 @@ namespace {
 
 constexpr int kTX = kTileX;     // block width (cells)
 
-// NT threads per block: 256 (four pairs per thread, two blocks per compute
-// unit) on levels with many tiles; 1024 (one pair per thread) on levels with
-// fewer tiles than compute units, where the time of one block is the time of
-// the launch.
+// NT threads per block: 256, 512 or 1024 (four, two or one pair per thread),
+// chosen per level by the autotuner; without it 1024 on levels with fewer
+// tiles than compute units, where the time of one block is the time of the
+// launch, and 256 elsewhere.
 template <int NS, int EPI, int NT, int TY>
 struct Geometry {
     static constexpr int X = EPI ? 1 : 0;          // extra valid rings after the last phase
@@ -437,11 +437,14 @@ __global__ __launch_bounds__(NT) void k_tile2d(Batch<T> bt, const TileTask* __re
 }
 
 template <typename T, bool LEVEL0, int NS, int EPI, bool PRO, bool CORR, bool RHS, int TY>
-void launch_ty(const Batch<T>& b, const TileTask* t, int nt, bool wide, double* partial,
+void launch_ty(const Batch<T>& b, const TileTask* t, int nt, int threads, double* partial,
                hipStream_t st) {
-    if (wide)
+    if (threads == 1024)
         hipLaunchKernelGGL((k_tile2d<T, LEVEL0, NS, EPI, PRO, CORR, 1024, RHS, TY>), dim3(nt),
                            dim3(1024), 0, st, b, t, nt, partial);
+    else if (threads == 512)
+        hipLaunchKernelGGL((k_tile2d<T, LEVEL0, NS, EPI, PRO, CORR, 512, RHS, TY>), dim3(nt),
+                           dim3(512), 0, st, b, t, nt, partial);
     else
         hipLaunchKernelGGL((k_tile2d<T, LEVEL0, NS, EPI, PRO, CORR, 256, RHS, TY>), dim3(nt),
                            dim3(256), 0, st, b, t, nt, partial);
@@ -449,22 +452,22 @@ void launch_ty(const Batch<T>& b, const TileTask* t, int nt, bool wide, double* 
 
 // Finest-level variants exist for 64 x 16 tiles only.
 template <typename T, bool LEVEL0, int NS, int EPI, bool PRO, bool CORR, bool RHS = false>
-void launch_one(const Batch<T>& b, const TileTask* t, int nt, bool wide, int ty, double* partial,
+void launch_one(const Batch<T>& b, const TileTask* t, int nt, int threads, int ty, double* partial,
                 hipStream_t st) {
     if constexpr (!LEVEL0) {
         if (ty == kTileYSmall) {
-            launch_ty<T, LEVEL0, NS, EPI, PRO, CORR, RHS, kTileYSmall>(b, t, nt, wide, partial, st);
+            launch_ty<T, LEVEL0, NS, EPI, PRO, CORR, RHS, kTileYSmall>(b, t, nt, threads, partial, st);
             return;
         }
     }
-    launch_ty<T, LEVEL0, NS, EPI, PRO, CORR, RHS, kTileY>(b, t, nt, wide, partial, st);
+    launch_ty<T, LEVEL0, NS, EPI, PRO, CORR, RHS, kTileY>(b, t, nt, threads, partial, st);
 }
 
 }  // namespace
 
 template <>
 void launch_tile2d<double>(const Batch<double>& b, const TileTask* t, int nt, bool level0, int ns,
-                           int epi, bool pro, bool wide, bool rhs, int ty, double* partial,
+                           int epi, bool pro, int threads, bool rhs, int ty, double* partial,
                            hipStream_t st) {
     if (nt <= 0) return;
     if (rhs) {
@@ -472,7 +475,7 @@ void launch_tile2d<double>(const Batch<double>& b, const TileTask* t, int nt, bo
         if (level0 || pro || epi == 2) return;
 #define CHHS_TILE_RHS(NS, EPI)                                                    \
     if (ns == NS && epi == EPI) {                                                 \
-        launch_one<double, false, NS, EPI, false, false, true>(b, t, nt, wide, ty, partial, st); \
+        launch_one<double, false, NS, EPI, false, false, true>(b, t, nt, threads, ty, partial, st); \
         return;                                                                   \
     }
         CHHS_TILE_RHS(1, 0)
@@ -484,7 +487,7 @@ void launch_tile2d<double>(const Batch<double>& b, const TileTask* t, int nt, bo
     }
 #define CHHS_TILE_CASE(L0, NS, EPI, PRO)                                          \
     if (level0 == L0 && ns == NS && epi == EPI && pro == PRO) {                   \
-        launch_one<double, L0, NS, EPI, PRO, false>(b, t, nt, wide, ty, partial, st); \
+        launch_one<double, L0, NS, EPI, PRO, false>(b, t, nt, threads, ty, partial, st); \
         return;                                                                   \
     }
 #define CHHS_TILE_PRO(L0, NS, EPI) CHHS_TILE_CASE(L0, NS, EPI, false) CHHS_TILE_CASE(L0, NS, EPI, true)
@@ -502,7 +505,7 @@ void launch_tile2d<double>(const Batch<double>& b, const TileTask* t, int nt, bo
 // sides, no norm epilogue.
 template <>
 void launch_tile2d<float>(const Batch<float>& b, const TileTask* t, int nt, bool level0, int ns,
-                          int epi, bool pro, bool wide, bool rhs, int ty, double* partial,
+                          int epi, bool pro, int threads, bool rhs, int ty, double* partial,
                           hipStream_t st) {
     (void)level0;
     if (nt <= 0) return;
@@ -510,7 +513,7 @@ void launch_tile2d<float>(const Batch<float>& b, const TileTask* t, int nt, bool
         if (pro || epi == 2) return;
 #define CHHS_TILE_RHS(NS, EPI)                                                    \
     if (ns == NS && epi == EPI) {                                                 \
-        launch_one<float, false, NS, EPI, false, true, true>(b, t, nt, wide, ty, partial, st); \
+        launch_one<float, false, NS, EPI, false, true, true>(b, t, nt, threads, ty, partial, st); \
         return;                                                                   \
     }
         CHHS_TILE_RHS(1, 0)
@@ -522,7 +525,7 @@ void launch_tile2d<float>(const Batch<float>& b, const TileTask* t, int nt, bool
     }
 #define CHHS_TILE_CASE(NS, EPI, PRO)                                              \
     if (ns == NS && epi == EPI && pro == PRO) {                                   \
-        launch_one<float, false, NS, EPI, PRO, true>(b, t, nt, wide, ty, partial, st); \
+        launch_one<float, false, NS, EPI, PRO, true>(b, t, nt, threads, ty, partial, st); \
         return;                                                                   \
     }
     CHHS_TILE_CASE(1, 0, false)

@@ -135,6 +135,31 @@ def test_full_size_vcycle_strips_match_tiles(chhs):
         assert d <= 1e-12 * max(1.0, np.max(np.abs(res[TILES][1][k]))), k
 
 
+@pytest.mark.parametrize("shape", [(512, 256), (96, 160)])
+def test_tile_block_sizes_give_the_same_vcycle(chhs, shape):
+    """Tile blocks of 256, 512 and 1024 threads (opts.tile_threads) perform the
+    same cell updates: one V-cycle from the same state leaves the same fields
+    on the finest level and the same residual norm to rounding (the variants
+    may fuse different products into multiply-adds, and the block sums of the
+    norm and of mean(p) run in a block-size dependent order)."""
+    prm = _prm(shape, eps=0.02, gamma=1.5, s=5e-4)
+    phi0 = uniform_field(shape, 560, mean=0.1, amp=0.05)
+    z = np.zeros(shape)
+    res = {}
+    for nt in (256, 512, 1024):
+        sv = _solver(chhs, shape, prm, smoother=TILES, tile_threads=nt)
+        assert all(k[0] != 0 or k[1] == nt for k in sv.level_kernels())
+        sv.setup_step(dev(phi0), dev(phi0), dev(z), dev(z))
+        r = sv.fas_vcycle()
+        res[nt] = (r, [host(sv.read_field(0, n)) for n in ("phi", "mu", "p")])
+    for nt in (512, 1024):
+        assert abs(res[nt][0][0] - res[256][0][0]) <= 1e-12 * res[256][0][0]
+        for k in range(3):
+            ref = res[256][1][k]
+            d = np.max(np.abs(res[nt][1][k] - ref))
+            assert d <= 1e-13 * max(1.0, np.max(np.abs(ref))), (nt, k, d)
+
+
 @pytest.mark.parametrize("spec", [[((256, 256), 0.02, 1.5, 5e-4)],
                                   [((128, 128), 0.02, 1.0, 1e-4), ((96, 160), 0.03, 2.0, 5e-4),
                                    ((512, 256), 0.01, 3.0, 1e-4)]], ids=["single", "ragged"])
