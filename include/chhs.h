@@ -26,8 +26,11 @@
  * Batches of independent instances are packed one after another in instance
  * order.  All field pointers below are DEVICE pointers owned by the caller.
  *
- * Streams: all device work is enqueued on the stream given to chhs_init.
- * Calls that return host results synchronise that stream before returning.
+ * Streams: all device work is enqueued on the stream given to chhs_init, or,
+ * when that is NULL, on a stream the context creates (with default flags, so
+ * that it stays ordered with the legacy null stream, which cannot be captured
+ * into a graph).  Calls that return host results synchronise that stream
+ * before returning.
  *
  * Errors: every int-returning call returns CHHS_OK (0) or a negative code;
  * no call aborts or throws.  chhs_strerror gives a static message.
@@ -67,7 +70,8 @@ typedef struct chhs_problem {
  * max_vcycles = 100, coarse_sweeps = 4 (smoothing steps on the coarsest grid),
  * precision 0 = FP64 throughout, 1 = FP32 smoothing/transfer inside FP64
  * residual + correction (iterative refinement), use_graph = 1 (default) replays each
- * V-cycle as a captured HIP graph, timing = 1 brackets every launch of every
+ * V-cycle as a captured HIP graph (contexts with timing != 0 launch directly),
+ * timing = 1 brackets every launch of every
  * kernel class with HIP events (see chhs_get_timing); any other nonzero value
  * is a mask of classes, bit (class + 1) set for each class to time.  Each
  * event pair delays the next launch by a few microseconds.  smoother selects
@@ -151,9 +155,9 @@ size_t chhs_workspace_bytes(const chhs_problem* p, int32_t n_inst, const chhs_op
 
 /* Creates a context.  workspace_dev: caller-owned device memory of ws_bytes
  * >= chhs_workspace_bytes(...), 256-byte aligned, kept alive until
- * chhs_destroy.  hip_stream: a hipStream_t (NULL = the null stream).  The
- * context itself (host memory, pinned staging, captured graphs) is owned by
- * the library.  Returns CHHS_E_INVAL, CHHS_E_NOMEM or CHHS_E_HIP on failure,
+ * chhs_destroy.  hip_stream: a hipStream_t (NULL = a stream of the context's
+ * own, ordered with the null stream).  The context itself (host memory,
+ * pinned staging, captured graphs, that stream) is owned by the library.  Returns CHHS_E_INVAL, CHHS_E_NOMEM or CHHS_E_HIP on failure,
  * with *out = NULL. */
 int chhs_init(const chhs_problem* p, int32_t n_inst, const chhs_opts* o,
               void* workspace_dev, size_t ws_bytes, void* hip_stream, chhs_ctx** out);

@@ -86,6 +86,7 @@ struct chhs_ctx {
     int dim = 2;
     bool mixed = false;
     hipStream_t stream = nullptr;
+    bool own_stream = false;        // created by chhs_init (no stream given)
     Layout lay;
     char* base = nullptr;
     // device views
@@ -974,9 +975,11 @@ void drop_graphs(chhs_ctx* c) {
 // copy, which a mixed refinement step flips.
 // Captures the counted cycle into graph slot `slot` (reading back into mirror
 // `buf`) unless already captured; on failure graphs are disabled for the
-// context and the eager path is used.
+// context and the eager path is used.  Timed contexts are not captured (event
+// records inside a capture are not reliable here); they launch directly.
 void ensure_graph(chhs_ctx* c, int slot, int buf) {
-    if (!c->opts.use_graph || c->graph_failed || c->gexec[slot] != nullptr) return;
+    if (!c->opts.use_graph || c->opts.timing != 0 || c->graph_failed || c->gexec[slot] != nullptr)
+        return;
     c->capturing = slot;
     const int saved_cur0 = c->cur[0];
     bool ok = hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed) == hipSuccess;
@@ -1024,15 +1027,30 @@ bool any_active(chhs_ctx* c) {
     return false;
 }
 
-// The counted cycles of one step until no instance is active.  Plain FP64
-// with graphs: cycles are pipelined -- cycle k + 1 is enqueued before the
-// host reads cycle k's results, through two graph slots reading back into two
-// mirrors, so the device never waits for the host's stopping test.  The
-// cycle enqueued after the last one finds every instance inactive on the
-// device and does nothing; its timing events are dropped.  Otherwise one
-// cycle at a time.
+// Whether the cycle in flight is expected to leave some instance unconverged:
+// its residual after the last cycle read, times the contraction that cycle
+// showed (rho, per instance), still more than three times the tolerance.
+bool expect_more(const chhs_ctx* c, const std::vector<double>& rho) {
+    for (int i = 0; i < c->n_inst; ++i) {
+        if (!c->hact[i]) continue;
+        const double r = c->hres[size_t(i) * chhs::kResStride + 3];
+        if (r * rho[i] > 3.0 * c->opts.tol) return true;
+    }
+    return false;
+}
+
+// The counted cycles of one step until no instance is active.  Plain FP64:
+// while the cycle in flight is not expected to converge, the next one is
+// enqueued before the host reads its results (two pinned mirrors, cycles
+// alternating between them), so the device does not wait for the host's
+// stopping test; near convergence the host reads each cycle first, so that
+// no cycle runs for nothing.  A cycle enqueued all the same after the last
+// one finds every instance inactive on the device and does nothing; its timing
+// events are dropped.  Cycles replay captured graphs (one per mirror) when
+// the stream can be captured and no class is timed, else launch directly.
+// Mixed precision: one refinement step at a time.
 int run_cycles(chhs_ctx* c) {
-    if (c->mixed || !c->opts.use_graph || c->graph_failed) {
+    if (c->mixed) {
         while (any_active(c)) {
             const int rc = run_cycle(c, true);
             if (rc) return rc;
@@ -1040,36 +1058,69 @@ int run_cycles(chhs_ctx* c) {
         return CHHS_OK;
     }
     if (!any_active(c)) return CHHS_OK;
-    ensure_graph(c, 0, 0);
-    ensure_graph(c, 1, 1);
-    if (c->gexec[0] == nullptr || c->gexec[1] == nullptr) {
-        while (any_active(c)) {
-            const int rc = run_cycle(c, true);
-            if (rc) return rc;
-        }
-        return CHHS_OK;
-    }
     for (int s = 0; s < 2; ++s)
         if (c->cycle_done[s] == nullptr && hipEventCreateWithFlags(&c->cycle_done[s],
                                                                     hipEventDisableTiming) != hipSuccess)
             return CHHS_E_HIP;
-    for (int s = 0; s < 2; ++s) {
-        HIP_TRY(hipGraphLaunch(c->gexec[s], c->stream));
+    ensure_graph(c, 0, 0);
+    ensure_graph(c, 1, 1);
+    const bool graphs = c->gexec[0] != nullptr && c->gexec[1] != nullptr;
+    std::vector<double> prev(c->n_inst), rho(c->n_inst, 0.1);
+    for (int i = 0; i < c->n_inst; ++i) prev[i] = c->hres[size_t(i) * chhs::kResStride + 3];
+    size_t mark[2] = {0, 0};       // pending timing pairs before each mirror's latest cycle
+    int queue[2], nq = 0, next = 0;
+    auto launch = [&]() -> int {
+        const int s = next;
+        mark[s] = c->pending.size();
+        if (graphs) {
+            HIP_TRY(hipGraphLaunch(c->gexec[s], c->stream));
+        } else {
+            enqueue_cycle(c, true);
+            int rc = check_launch();
+            if (rc == CHHS_OK) rc = enqueue_readback(c, s);
+            if (rc) return rc;
+        }
         HIP_TRY(hipEventRecord(c->cycle_done[s], c->stream));
-    }
-    int s = 0;
+        queue[nq++] = s;
+        next ^= 1;
+        return CHHS_OK;
+    };
+    int rc = launch();
+    if (rc) return rc;
     for (;;) {
+        if (nq == 1 && expect_more(c, rho)) {
+            rc = launch();
+            if (rc) return rc;
+        }
+        const int s = queue[0];
+        queue[0] = queue[1];
+        --nq;
         HIP_TRY(hipEventSynchronize(c->cycle_done[s]));
-        for (auto& pe : c->graph_pairs[s]) accumulate(c, pe);
+        if (graphs)
+            for (auto& pe : c->graph_pairs[s]) accumulate(c, pe);
         view_results(c, s);
+        for (int i = 0; i < c->n_inst; ++i) {
+            const double r = c->hres[size_t(i) * chhs::kResStride + 3];
+            if (prev[i] > 0.0 && std::isfinite(r)) rho[i] = r / prev[i];
+            prev[i] = r;
+        }
         if (!any_active(c)) {
-            // the cycle in flight in the other slot has no active instance
-            HIP_TRY(hipEventSynchronize(c->cycle_done[s ^ 1]));
+            if (nq == 1) {
+                // enqueued before this result: it runs with no active instance
+                const int d = queue[0];
+                HIP_TRY(hipEventSynchronize(c->cycle_done[d]));
+                for (size_t i = mark[d]; i < c->pending.size(); ++i) {
+                    c->ev_pool.push_back(c->pending[i].a);
+                    c->ev_pool.push_back(c->pending[i].b);
+                }
+                c->pending.resize(mark[d]);
+            }
             break;
         }
-        HIP_TRY(hipGraphLaunch(c->gexec[s], c->stream));
-        HIP_TRY(hipEventRecord(c->cycle_done[s], c->stream));
-        s ^= 1;
+        if (nq == 0) {
+            rc = launch();
+            if (rc) return rc;
+        }
     }
     HIP_TRY(hipStreamSynchronize(c->stream));
     c->last_slot = -1;
@@ -1184,14 +1235,26 @@ int chhs_init(const chhs_problem* p, int32_t n_inst, const chhs_opts* o, void* w
     c->dim = p[0].dim;
     c->mixed = o->precision == 1;
     c->stream = static_cast<hipStream_t>(hip_stream);
+    // The legacy null stream cannot be captured into a graph: without a stream
+    // from the caller the context makes one with default flags, which keeps
+    // its work ordered with the caller's work on the null stream.
+    if (c->stream == nullptr) {
+        if (hipStreamCreate(&c->stream) != hipSuccess) {
+            delete c;
+            return CHHS_E_HIP;
+        }
+        c->own_stream = true;
+    }
     c->base = static_cast<char*>(workspace_dev);
     plan(p, n_inst, o, c->base, c->lay);
     Layout& L = c->lay;
     char* b = c->base;
     int rc = CHHS_OK;
     auto fail = [&](int code) {
+        (void)hipStreamSynchronize(c->stream);
         for (int k = 0; k < 2; ++k)
             if (c->hbuf[k]) (void)hipHostFree(c->hbuf[k]);
+        if (c->own_stream) (void)hipStreamDestroy(c->stream);
         delete c;
         return code;
     };
@@ -1507,6 +1570,7 @@ void chhs_destroy(chhs_ctx* c) {
         if (c->cycle_done[k]) (void)hipEventDestroy(c->cycle_done[k]);
         if (c->hbuf[k]) (void)hipHostFree(c->hbuf[k]);
     }
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
 
