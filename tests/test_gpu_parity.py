@@ -316,6 +316,30 @@ def test_repeat_runs_are_bitwise_identical(chhs):
         assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("use_graph", [1, 0])
+def test_caller_stream_gives_the_same_steps(chhs, use_graph):
+    """A context on a stream the caller created (graphs captured there, or
+    direct launches) computes bitwise the same steps as one given the null
+    stream (which runs on a stream of the context's own)."""
+    import torch
+    shape = (128, 96)
+    prm = _prm(shape)
+    prev, cur, mu0, p0 = _inputs(shape, 710)
+    outs = []
+    for stream in (None, torch.cuda.Stream()):
+        prob = chhs.make_problem(shape, prm.h, prm.eps, prm.gamma, prm.s)
+        sv = chhs.Solver(prob, chhs.chhs_default_opts(use_graph=use_graph), stream=stream)
+        tp, tc, tm, tpp = dev(prev), dev(cur), dev(mu0), dev(p0)
+        torch.cuda.synchronize()          # the inputs were written on the null stream
+        _, st = sv.step(tp, tc, tm, tpp, 3)
+        torch.cuda.synchronize()
+        outs.append((host(tc), host(tm), host(tpp), st[0]["vcycles"]))
+        sv.close()
+    for a, b in zip(outs[0][:3], outs[1][:3]):
+        assert np.array_equal(a, b)
+    assert outs[0][3] == outs[1][3]
+
+
 def test_nonfinite_input_is_reported_and_state_kept(chhs):
     shape = (32, 32)
     prm = _prm(shape)
