@@ -110,10 +110,10 @@ struct chhs_ctx {
     int* act_next = nullptr;
     int* cycles = nullptr;
     // pinned host mirrors of the result block (res | act_next | cycles): two
-    // buffers (the second is the readback target of graph slot 1 of the
-    // pipelined plain cycle loop) and the current view into one of them;
-    // the energies follow the first
-    double* hbuf[2] = {nullptr, nullptr};
+    // that the cycles of the pipelined plain loop alternate between, a third
+    // for the setup of a step that the loop reads with its first cycle, and
+    // the current view into one of them; the energies follow the first
+    double* hbuf[3] = {nullptr, nullptr, nullptr};
     double* hres = nullptr;
     double* heres = nullptr;
     int* hact = nullptr;
@@ -1049,7 +1049,10 @@ bool expect_more(const chhs_ctx* c, const std::vector<double>& rho) {
 // events are dropped.  Cycles replay captured graphs (one per mirror) when
 // the stream can be captured and no class is timed, else launch directly.
 // Mixed precision: one refinement step at a time.
-int run_cycles(chhs_ctx* c) {
+// setup_pending: the step's setup was enqueued without waiting, its norms
+// arriving in the third mirror (plain FP64 only); the first cycle is then
+// enqueued at once (it does nothing for an instance that is converged already).
+int run_cycles(chhs_ctx* c, bool setup_pending = false) {
     if (c->mixed) {
         while (any_active(c)) {
             const int rc = run_cycle(c, true);
@@ -1057,7 +1060,7 @@ int run_cycles(chhs_ctx* c) {
         }
         return CHHS_OK;
     }
-    if (!any_active(c)) return CHHS_OK;
+    if (!setup_pending && !any_active(c)) return CHHS_OK;
     for (int s = 0; s < 2; ++s)
         if (c->cycle_done[s] == nullptr && hipEventCreateWithFlags(&c->cycle_done[s],
                                                                     hipEventDisableTiming) != hipSuccess)
@@ -1065,8 +1068,9 @@ int run_cycles(chhs_ctx* c) {
     ensure_graph(c, 0, 0);
     ensure_graph(c, 1, 1);
     const bool graphs = c->gexec[0] != nullptr && c->gexec[1] != nullptr;
-    std::vector<double> prev(c->n_inst), rho(c->n_inst, 0.1);
-    for (int i = 0; i < c->n_inst; ++i) prev[i] = c->hres[size_t(i) * chhs::kResStride + 3];
+    std::vector<double> prev(c->n_inst, 0.0), rho(c->n_inst, 0.1);
+    if (!setup_pending)
+        for (int i = 0; i < c->n_inst; ++i) prev[i] = c->hres[size_t(i) * chhs::kResStride + 3];
     size_t mark[2] = {0, 0};       // pending timing pairs before each mirror's latest cycle
     int queue[2], nq = 0, next = 0;
     auto launch = [&]() -> int {
@@ -1088,7 +1092,7 @@ int run_cycles(chhs_ctx* c) {
     int rc = launch();
     if (rc) return rc;
     for (;;) {
-        if (nq == 1 && expect_more(c, rho)) {
+        if (nq == 1 && (setup_pending || expect_more(c, rho))) {
             rc = launch();
             if (rc) return rc;
         }
@@ -1099,6 +1103,11 @@ int run_cycles(chhs_ctx* c) {
         if (graphs)
             for (auto& pe : c->graph_pairs[s]) accumulate(c, pe);
         view_results(c, s);
+        if (setup_pending) {
+            // the setup ran before this cycle: its norms are on the host now
+            for (int i = 0; i < c->n_inst; ++i) prev[i] = c->hbuf[2][size_t(i) * chhs::kResStride + 3];
+            setup_pending = false;
+        }
         for (int i = 0; i < c->n_inst; ++i) {
             const double r = c->hres[size_t(i) * chhs::kResStride + 3];
             if (prev[i] > 0.0 && std::isfinite(r)) rho[i] = r / prev[i];
@@ -1131,9 +1140,11 @@ int run_cycles(chhs_ctx* c) {
 // Setup of every instance's step system, p normalised to mean zero, and the
 // norms of the initial guess on the host.
 // defer: leave the mean of the initial p pending (the step loop) rather than
-// subtract it at once (callers that read the level's fields).
+// subtract it at once (callers that read the level's fields).  wait = false
+// (the plain step loop): the norms go to the third mirror and nothing is
+// synchronised; the cycle loop reads them with its first cycle.
 int setup(chhs_ctx* c, const double* phi_prev, const double* phi_cur, const double* mu,
-          const double* p, bool defer = false) {
+          const double* p, bool defer = false, bool wait = true) {
     const int dim = c->dim;
     {
         TimedScope t(c, CHHS_K_SETUP);
@@ -1169,10 +1180,11 @@ int setup(chhs_ctx* c, const double* phi_prev, const double* phi_cur, const doub
     }
     int rc = check_launch();
     if (rc) return rc;
+    c->loaded = true;
+    if (!wait) return enqueue_readback(c, 2);
     view_results(c, 0);
     rc = enqueue_readback(c, 0);
     if (rc) return rc;
-    c->loaded = true;
     return sync_results(c);
 }
 
@@ -1252,7 +1264,7 @@ int chhs_init(const chhs_problem* p, int32_t n_inst, const chhs_opts* o, void* w
     int rc = CHHS_OK;
     auto fail = [&](int code) {
         (void)hipStreamSynchronize(c->stream);
-        for (int k = 0; k < 2; ++k)
+        for (int k = 0; k < 3; ++k)
             if (c->hbuf[k]) (void)hipHostFree(c->hbuf[k]);
         if (c->own_stream) (void)hipStreamDestroy(c->stream);
         delete c;
@@ -1314,6 +1326,8 @@ int chhs_init(const chhs_problem* p, int32_t n_inst, const chhs_opts* o, void* w
     if (hipHostMalloc(reinterpret_cast<void**>(&c->hbuf[0]), hbytes, hipHostMallocDefault) !=
             hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&c->hbuf[1]), (nres + nint) * sizeof(double),
+                      hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&c->hbuf[2]), (nres + nint) * sizeof(double),
                       hipHostMallocDefault) != hipSuccess)
         return fail(CHHS_E_HIP);
     view_results(c, 0);
@@ -1396,11 +1410,16 @@ int chhs_step(chhs_ctx* c, double* phi_prev, double* phi_cur, double* mu, double
     for (auto& s : st) std::memset(&s, 0, sizeof(s));
     int rc = CHHS_OK;
     for (int m = 0; m < nsteps && rc == CHHS_OK; ++m) {
-        rc = setup(c, phi_prev, phi_cur, mu, p, true);
+        // plain FP64: the setup is not waited for; its norms come with the first cycle
+        const bool early = !c->mixed;
+        rc = setup(c, phi_prev, phi_cur, mu, p, true, !early);
         if (rc) break;
-        for (int i = 0; i < n; ++i) st[i].res0 = hres_of(c, i)[3];
-        rc = run_cycles(c);
+        if (!early)
+            for (int i = 0; i < n; ++i) st[i].res0 = hres_of(c, i)[3];
+        rc = run_cycles(c, early);
         if (rc) break;
+        if (early)
+            for (int i = 0; i < n; ++i) st[i].res0 = c->hbuf[2][size_t(i) * chhs::kResStride + 3];
         for (int i = 0; i < n; ++i) {
             const double* r = hres_of(c, i);
             st[i].vcycles = c->hcyc[i];
@@ -1566,10 +1585,10 @@ void chhs_destroy(chhs_ctx* c) {
     resolve_timing(c);
     drop_graphs(c);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < 2; ++k)
         if (c->cycle_done[k]) (void)hipEventDestroy(c->cycle_done[k]);
+    for (int k = 0; k < 3; ++k)
         if (c->hbuf[k]) (void)hipHostFree(c->hbuf[k]);
-    }
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }

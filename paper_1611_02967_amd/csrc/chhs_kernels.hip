@@ -416,6 +416,9 @@ __global__ __launch_bounds__(kBlock) void k_inst_reduce(const double* __restrict
     const Range rg = fused ? ranges_t[i] : ranges[i];
     const double* src = fused ? partial_t : partial;
     double v[4] = {0.0, 0.0, 0.0, 0.0};
+    // unrolled so that the loads of several partials are in flight together
+    // (the sums keep their order)
+#pragma unroll 8
     for (int q = rg.begin + threadIdx.x; q < rg.end; q += kBlock)
         for (int c = 0; c < 4; ++c) v[c] += src[q * kPartialStride + c];
     double s[4];
