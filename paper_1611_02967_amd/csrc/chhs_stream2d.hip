@@ -429,10 +429,12 @@ __attribute__((amdgpu_waves_per_eu(LEVEL0 || CORR ? 3 : 1))) void k_stream2d(Bat
     // ---- the pipeline -------------------------------------------------------------------
     // Ring rows wait in two register banks of kD rows each.  At the first
     // iteration that drains bank b the other bank is refilled with the rows
-    // needed kD iterations later, after the wait for the row being stored:
-    // whatever the compiler waits for at the loop head, the loads it waits
-    // for were issued kD iterations earlier.  A phase wave's own data for
-    // iteration t + KO is loaded at iteration t into the slot it just used.
+    // needed kD iterations later, after the wait for the row being stored,
+    // so that this wait does not cover them.  (Global stores share the
+    // vector-memory counter with loads: after the leave's stores the compiler
+    // waits for every outstanding load at the next use of loaded data.)  A
+    // phase wave's own data for iteration t + KO is loaded at iteration t
+    // into the slot it just used.
     {
         T v[2], vc[2], vb[2];
         load_row(v, vc, vb, ys);
