@@ -209,6 +209,13 @@ int chhs_level_shape(chhs_ctx* c, int32_t level, int32_t* nxyz3);
  * out3[2] = blocks per launch (0 for the tail).  Reflects the autotuner's
  * choice.  Any batch size; CHHS_E_INVAL for a level no instance has. */
 int chhs_level_kernel(chhs_ctx* c, int32_t level, int32_t* out3);
+
+/* How the counted cycles run: *graphs = the number of cycle graphs captured
+ * and instantiated so far (0 before the first step, 2 for the plain FP64
+ * loop, 1 or 2 for mixed precision), 0 when they launch directly
+ * (use_graph = 0, timing != 0, or a capture that failed, which disables
+ * graphs for the context).  CHHS_E_INVAL for a null argument. */
+int chhs_graph_count(chhs_ctx* c, int32_t* graphs);
 int chhs_copy_field(chhs_ctx* c, int32_t level, int32_t field, double* dev, int32_t dir);
 
 /* One smoothing step (red then black collective cell update) on one level,

@@ -87,6 +87,7 @@ _SIGS = {
     "chhs_level_count": (_I, [_P, ctypes.POINTER(ctypes.c_int32)]),
     "chhs_level_shape": (_I, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     "chhs_level_kernel": (_I, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
+    "chhs_graph_count": (_I, [_P, ctypes.POINTER(ctypes.c_int32)]),
     "chhs_copy_field": (_I, [_P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int32]),
     "chhs_smooth": (_I, [_P, ctypes.c_int32, ctypes.c_int32]),
     "chhs_restrict": (_I, [_P, ctypes.c_int32]),
@@ -212,6 +213,13 @@ def chhs_level_kernel(ctx, level):
     return KERNEL_KINDS[out[0]], out[1], out[2]
 
 
+def chhs_graph_count(ctx):
+    """Number of captured cycle graphs (0 when cycles launch directly)."""
+    out = ctypes.c_int32(0)
+    _check(_lib.chhs_graph_count(ctx, ctypes.byref(out)), "chhs_graph_count")
+    return out.value
+
+
 def chhs_level_shape(ctx, level):
     out = (ctypes.c_int32 * 3)()
     _check(_lib.chhs_level_shape(ctx, level, out), "chhs_level_shape")
@@ -306,6 +314,9 @@ class Solver:
             except ChhsError:
                 return out
             level += 1
+
+    def graph_count(self):
+        return chhs_graph_count(self.ctx)
 
     def levels(self):
         return [chhs_level_shape(self.ctx, l) for l in range(chhs_level_count(self.ctx))]

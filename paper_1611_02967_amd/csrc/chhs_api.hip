@@ -1493,6 +1493,12 @@ int chhs_level_shape(chhs_ctx* c, int32_t level, int32_t* nxyz3) {
     return CHHS_OK;
 }
 
+int chhs_graph_count(chhs_ctx* c, int32_t* graphs) {
+    if (c == nullptr || graphs == nullptr) return CHHS_E_INVAL;
+    *graphs = (c->gexec[0] != nullptr ? 1 : 0) + (c->gexec[1] != nullptr ? 1 : 0);
+    return CHHS_OK;
+}
+
 int chhs_level_kernel(chhs_ctx* c, int32_t level, int32_t* out3) {
     if (c == nullptr || out3 == nullptr || level < 0 || level >= c->lay.max_nlev)
         return CHHS_E_INVAL;

@@ -340,6 +340,22 @@ def test_caller_stream_gives_the_same_steps(chhs, use_graph):
     assert outs[0][3] == outs[1][3]
 
 
+@pytest.mark.parametrize("opts,want", [({}, 2), ({"use_graph": 0}, 0),
+                                       ({"timing": 1}, 0), ({"precision": 1}, 2)])
+def test_cycles_replay_graphs_unless_disabled(chhs, opts, want):
+    """Given torch's (null) current stream, the context captures its cycles on
+    a stream of its own: two graphs for the pipelined plain loop (mixed: one per
+    copy of the finest level); none with use_graph = 0 or with timing."""
+    shape = (64, 64)
+    prm = _prm(shape)
+    prev, cur, mu0, p0 = _inputs(shape, 720)
+    sv = _solver(chhs, shape, prm, **opts)
+    assert sv.graph_count() == 0
+    tp, tc, tm, tpp = dev(prev), dev(cur), dev(mu0), dev(p0)
+    sv.step(tp, tc, tm, tpp, 2)
+    assert sv.graph_count() == want
+
+
 def test_nonfinite_input_is_reported_and_state_kept(chhs):
     shape = (32, 32)
     prm = _prm(shape)
