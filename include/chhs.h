@@ -79,7 +79,7 @@ typedef struct chhs_problem {
  * 0 = default (row-streaming strips on the finest level, square LDS tiles on
  * coarser ones), 1 = tiles everywhere, 2 = strips on every level (including
  * the explicit smoothing calls on tail levels).  Both
- * kernels perform the same red-black updates in the same arithmetic.
+ * kernels perform the same red-black updates (results agree to rounding).
  * tile_threads = 0 (default) gives tiled levels 1024-thread blocks when they
  * have at most 256 tiles and 256-thread blocks otherwise; 256, 512 or 1024
  * fixes the block size of every tiled level (the same arithmetic per cell).
@@ -157,8 +157,9 @@ size_t chhs_workspace_bytes(const chhs_problem* p, int32_t n_inst, const chhs_op
  * >= chhs_workspace_bytes(...), 256-byte aligned, kept alive until
  * chhs_destroy.  hip_stream: a hipStream_t (NULL = a stream of the context's
  * own, ordered with the null stream).  The context itself (host memory,
- * pinned staging, captured graphs, that stream) is owned by the library.  Returns CHHS_E_INVAL, CHHS_E_NOMEM or CHHS_E_HIP on failure,
- * with *out = NULL. */
+ * pinned staging, captured graphs, that stream) is owned by the library.
+ * Returns CHHS_E_INVAL, CHHS_E_NOMEM or CHHS_E_HIP on failure, with
+ * *out = NULL. */
 int chhs_init(const chhs_problem* p, int32_t n_inst, const chhs_opts* o,
               void* workspace_dev, size_t ws_bytes, void* hip_stream, chhs_ctx** out);
 
@@ -209,6 +210,7 @@ int chhs_level_shape(chhs_ctx* c, int32_t level, int32_t* nxyz3);
  * out3[2] = blocks per launch (0 for the tail).  Reflects the autotuner's
  * choice.  Any batch size; CHHS_E_INVAL for a level no instance has. */
 int chhs_level_kernel(chhs_ctx* c, int32_t level, int32_t* out3);
+int chhs_copy_field(chhs_ctx* c, int32_t level, int32_t field, double* dev, int32_t dir);
 
 /* How the counted cycles run: *graphs = the number of cycle graphs captured
  * and instantiated so far (0 before the first step, 2 for the plain FP64
@@ -216,7 +218,6 @@ int chhs_level_kernel(chhs_ctx* c, int32_t level, int32_t* out3);
  * (use_graph = 0, timing != 0, or a capture that failed, which disables
  * graphs for the context).  CHHS_E_INVAL for a null argument. */
 int chhs_graph_count(chhs_ctx* c, int32_t* graphs);
-int chhs_copy_field(chhs_ctx* c, int32_t level, int32_t field, double* dev, int32_t dir);
 
 /* One smoothing step (red then black collective cell update) on one level,
  * and the restriction + FAS coarse right-hand side from level to level+1.
