@@ -83,8 +83,13 @@ typedef struct chhs_problem {
  * tile_threads = 0 (default) gives tiled levels 1024-thread blocks when they
  * have at most 256 tiles and 256-thread blocks otherwise; 256, 512 or 1024
  * fixes the block size of every tiled level (the same arithmetic per cell).
+ * tile_rows = 0 (default) cuts coarse tiled levels into 64 x 8 tiles when they
+ * have at most 128 tiles of 64 x 16 (over the batch) and into 64 x 16 tiles
+ * otherwise; 16, 8 or 4 fixes the tile height of every coarse tiled level
+ * (the finest level always has 64 x 16 tiles).
  * autotune = 1 (2D, smoother = 0, nu1, nu2 >= 1): chhs_init times, on the problem at hand,
- * each level's smoothing launches with tiles of 256, 512 and 1024 threads and with
+ * each level's smoothing launches with tiles of 256, 512 and 1024 threads (on
+ * coarse levels each with 16, 8 and 4 rows) and with
  * strips of 1, 2 and 4 times the default segment height, and keeps the fastest
  * per level (the choice then depends on the device; results agree to rounding).
  * order = 2 (default; 0 means the same) solves the second-order scheme
@@ -94,7 +99,7 @@ typedef struct chhs_problem {
  * phi_* := phi^m, the convex part of chi fully implicit, chi(phi) = phi^3, the
  * whole eps^2 Lap phi implicit (kap = eps^2/h^2) and f_mu = -phi^m; phi_prev
  * is not read.  order = 1 needs precision = 0 and smooths every level with the
- * per-cell red-black kernels.  reserved must be zero. */
+ * per-cell red-black kernels. */
 typedef struct chhs_opts {
     int32_t nu1, nu2, max_vcycles, coarse_sweeps;
     double tol;
@@ -105,7 +110,7 @@ typedef struct chhs_opts {
     int32_t autotune;
     int32_t order;
     int32_t tile_threads;
-    int32_t reserved[1];
+    int32_t tile_rows;
 } chhs_opts;
 
 /* Kernel classes of chhs_timing. */

@@ -38,7 +38,7 @@ class chhs_opts(ctypes.Structure):
                 ("use_graph", ctypes.c_int32), ("timing", ctypes.c_int32),
                 ("smoother", ctypes.c_int32), ("autotune", ctypes.c_int32),
                 ("order", ctypes.c_int32), ("tile_threads", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 1)]
+                ("tile_rows", ctypes.c_int32)]
 
 
 K_CLASSES = ["pre0", "post0", "transfer0", "coarse", "norm", "setup", "k6", "k7"]

@@ -58,7 +58,9 @@ struct Layout {
     std::vector<std::vector<StripTask>> S, Sall;
     bool strip[kMaxLevels] = {};            // level smoothed by the row-streaming kernel
     int tile_threads[kMaxLevels] = {};      // tiles: threads per block, 0 = by the tile count
-    int tile_y[kMaxLevels] = {};            // tile height of the level's tasks
+    int tile_y[kMaxLevels] = {};            // tile height of the level's tasks (T)
+    int tile_y_all[kMaxLevels] = {};        // tile height of the tasks over every instance (Tall)
+    size_t cap_T[kMaxLevels] = {};          // capacity of T: tasks of the smallest tile height
     int seg[kMaxLevels] = {};               // rows per strip segment of S[l]
     // per level and instance: x / y extent of the grids in S[l] (-1: not listed)
     std::vector<std::vector<int>> snx, sny;
@@ -172,6 +174,9 @@ bool valid_opts(const chhs_opts* o) {
     if (o->order == 1 && o->precision != 0) return false;
     if (o->tile_threads != 0 && o->tile_threads != 256 && o->tile_threads != 512 &&
         o->tile_threads != 1024)
+        return false;
+    if (o->tile_rows != 0 && o->tile_rows != chhs::kTileY && o->tile_rows != chhs::kTileYSmall &&
+        o->tile_rows != chhs::kTileYTiny)
         return false;
     return true;
 }
@@ -324,9 +329,10 @@ bool plan(const chhs_problem* p, int n_inst, const chhs_opts* o, char* base, Lay
     auto ptr32 = [&](size_t o2) -> float* {
         return base ? reinterpret_cast<float*>(base + o2) : nullptr;
     };
-    // tile height per 2D level: 64 x 8 on coarse levels with at most
-    // kSmallTileLevel 64 x 16 tiles over the batch (more, smaller blocks, each
-    // a shorter launch), 64 x 16 elsewhere
+    // tile height per 2D level: opts.tile_rows on coarse levels if given, else
+    // 64 x 8 on coarse levels with at most kSmallTileLevel 64 x 16 tiles over
+    // the batch (more, smaller blocks, each a shorter launch), 64 x 16
+    // elsewhere; the autotuner may cut coarse levels anew
     for (int l = 0; l < kMaxLevels; ++l) L.tile_y[l] = chhs::kTileY;
     if (dim == 2) {
         std::vector<long> tiles16(kMaxLevels, 0);
@@ -338,7 +344,8 @@ bool plan(const chhs_problem* p, int n_inst, const chhs_opts* o, char* base, Lay
                               ((ext[3 * l + 1] + chhs::kTileY - 1) / chhs::kTileY);
         }
         for (int l = 1; l < kMaxLevels; ++l)
-            if (tiles16[l] <= kSmallTileLevel) L.tile_y[l] = chhs::kTileYSmall;
+            L.tile_y[l] = o->tile_rows != 0 ? o->tile_rows
+                        : (tiles16[l] <= kSmallTileLevel ? chhs::kTileYSmall : chhs::kTileY);
     }
     int packed = 0;
     for (int i = 0; i < n_inst; ++i) {
@@ -424,7 +431,13 @@ bool plan(const chhs_problem* p, int n_inst, const chhs_opts* o, char* base, Lay
             // levels above the tail have even extents: n / 2 cells per color
             if (l < tail) cell_tasks(L.Bh[l], i, n / 2);
             if (dim == 2) tile_tasks(L.Tall[l], i, d.nx, d.ny, L.tile_y[l]);
-            if (dim == 2 && l < tail) tile_tasks(L.T[l], i, d.nx, d.ny, L.tile_y[l]);
+            if (dim == 2 && l < tail) {
+                tile_tasks(L.T[l], i, d.nx, d.ny, L.tile_y[l]);
+                // the autotuner may cut coarse levels into shorter tiles
+                const int ymin = l > 0 ? chhs::kTileYTiny : chhs::kTileY;
+                L.cap_T[l] += size_t((d.nx + chhs::kTileX - 1) / chhs::kTileX) *
+                              size_t((d.ny + ymin - 1) / ymin);
+            }
             lnx[l][i] = d.nx;
             lny[l][i] = d.ny;
             if (l < tail) lnx_t[l][i] = d.nx;
@@ -477,7 +490,8 @@ bool plan(const chhs_problem* p, int n_inst, const chhs_opts* o, char* base, Lay
         L.off_Bh.push_back(take(L.Bh[l].size() * sizeof(CellTask)));
         L.off_Bcs.push_back(take(L.Bcs[l].size() * sizeof(CellTask)));
         L.off_Bc.push_back(take(L.Bc[l].size() * sizeof(CellTask)));
-        L.off_T.push_back(take(L.T[l].size() * sizeof(TileTask)));
+        L.tile_y_all[l] = L.tile_y[l];
+        L.off_T.push_back(take(std::max(L.T[l].size(), L.cap_T[l]) * sizeof(TileTask)));
         L.off_Tall.push_back(take(L.Tall[l].size() * sizeof(TileTask)));
         L.off_S.push_back(take(L.S[l].size() * sizeof(StripTask)));
         L.off_Sall.push_back(take(L.Sall[l].size() * sizeof(StripTask)));
@@ -635,7 +649,8 @@ void tiled(chhs_ctx* c, const Hier<T>& H, bool all, int l, int ns, int epi, bool
             const Table<TileTask>& tt = all ? c->Tall[l] : c->T[l];
             chhs::launch_tile2d<T>(b, tt.dev, tt.n, level0, ns, epi, pro,
                                    tile_block(all ? 0 : c->lay.tile_threads[l], tt.n), rhs,
-                                   c->lay.tile_y[l], part, c->stream);
+                                   all ? c->lay.tile_y_all[l] : c->lay.tile_y[l], part,
+                                   c->stream);
         }
     }
     H.cur[l] ^= 1;
@@ -810,7 +825,7 @@ float time_level(chhs_ctx* c, const Hier<T>& H, int l, int reps, hipEvent_t ea, 
 }
 
 // Picks, per 2D level above the tail, the fastest of: tiles with 256, 512 or
-// 1024 threads, strips with 1, 2 or 4 times the default segment height.  Runs the
+// 1024 threads (on coarse levels each also 16, 8 and 4 rows high), strips with 1, 2 or 4 times the default segment height.  Runs the
 // candidates on the workspace as it is (its contents do not matter for the
 // timing and are rewritten by the next setup).
 int autotune(chhs_ctx* c) {
@@ -824,9 +839,13 @@ int autotune(chhs_ctx* c) {
         if (c->T[l].n == 0) continue;
         struct Cand {
             bool strip;
-            int threads, seg;
+            int threads, seg, ty;
         };
-        std::vector<Cand> cands = {{false, 256, 0}, {false, 512, 0}, {false, 1024, 0}};
+        std::vector<Cand> cands;
+        for (int ty : {chhs::kTileY, chhs::kTileYSmall, chhs::kTileYTiny}) {
+            if (l == 0 && ty != chhs::kTileY) continue;     // the finest level has 64 x 16 tiles
+            for (int nt : {256, 512, 1024}) cands.push_back({false, nt, 0, ty});
+        }
         bool even = true;
         int maxny = 0;
         for (int i = 0; i < c->n_inst; ++i)
@@ -838,13 +857,25 @@ int autotune(chhs_ctx* c) {
         if (even && c->S[l].n > 0)
             for (int m = 1; m <= 4; m *= 2) {
                 const int sg = std::min(seg0 * m, (maxny + 1) & ~1);
-                if (m == 1 || sg > cands.back().seg) cands.push_back({true, 0, sg});
+                if (m == 1 || sg > cands.back().seg) cands.push_back({true, 0, sg, 0});
             }
         const int cap = c->S[l].n;
         auto apply = [&](const Cand& k) -> int {
             L.strip[l] = k.strip;
             L.tile_threads[l] = k.threads;
-            if (!k.strip) return CHHS_OK;
+            if (!k.strip) {
+                if (k.ty == L.tile_y[l]) return CHHS_OK;
+                // re-cut the level's tiles (same instance order as the plan)
+                L.T[l].clear();
+                for (int i = 0; i < c->n_inst; ++i)
+                    if (L.snx[l][i] >= 0) tile_tasks(L.T[l], i, L.snx[l][i], L.sny[l][i], k.ty);
+                if (L.T[l].size() > L.cap_T[l]) return CHHS_E_INVAL;
+                L.tile_y[l] = k.ty;
+                c->T[l].n = int(L.T[l].size());
+                HIP_TRY(hipMemcpyAsync(c->T[l].dev, L.T[l].data(), L.T[l].size() * sizeof(TileTask),
+                                       hipMemcpyHostToDevice, c->stream));
+                return CHHS_OK;
+            }
             L.seg[l] = k.seg;
             L.S[l].clear();
             strip_tasks(L.S[l], L.snx[l], L.sny[l], k.seg);

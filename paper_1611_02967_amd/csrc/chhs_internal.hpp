@@ -224,11 +224,13 @@ void launch_fill_int(int* dst, int n, int value, hipStream_t st);
 void launch_copy_int(int* dst, const int* src, int n, hipStream_t st);
 
 // ---- tiled 2D smoothing (chhs_tile2d.hip) ------------------------------------------
-// Tiles are 64 x 16 cells, or 64 x 8 on coarse levels with few tiles (more,
-// smaller blocks: there the time of one block is the time of the launch).
+// Tiles are 64 x 16 cells, or on coarse levels 64 x 8 or 64 x 4 (more,
+// smaller blocks: on levels with few tiles the time of one block is the time
+// of the launch).
 constexpr int kTileX = 64;
 constexpr int kTileY = 16;
 constexpr int kTileYSmall = 8;
+constexpr int kTileYTiny = 4;
 // ns fused smoothing steps on level b.level of every tasked instance, read from
 // copy b.cur and written to the other copy; epi 0 none, 1 residual + restriction
 // into level + 1 (copy b.cur_c), 2 residual-norm partials (4 per block, in task
@@ -237,7 +239,7 @@ constexpr int kTileYSmall = 8;
 // or one pair of cells per thread);
 // rhs: first pre-smoothing launch on a coarse level, which first forms the FAS
 // right-hand side f += N(u) (not with level0, pro or epi 2); ty: tile height,
-// kTileY or (not with level0) kTileYSmall, as the tasks were cut.
+// kTileY or (not with level0) kTileYSmall or kTileYTiny, as the tasks were cut.
 template <typename T>
 void launch_tile2d(const Batch<T>& b, const TileTask* t, int nt, bool level0, int ns, int epi,
                    bool pro, int threads, bool rhs, int ty, double* partial, hipStream_t st);

@@ -459,6 +459,10 @@ void launch_one(const Batch<T>& b, const TileTask* t, int nt, int threads, int t
             launch_ty<T, LEVEL0, NS, EPI, PRO, CORR, RHS, kTileYSmall>(b, t, nt, threads, partial, st);
             return;
         }
+        if (ty == kTileYTiny) {
+            launch_ty<T, LEVEL0, NS, EPI, PRO, CORR, RHS, kTileYTiny>(b, t, nt, threads, partial, st);
+            return;
+        }
     }
     launch_ty<T, LEVEL0, NS, EPI, PRO, CORR, RHS, kTileY>(b, t, nt, threads, partial, st);
 }

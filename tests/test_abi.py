@@ -59,7 +59,7 @@ def test_struct_layouts_match_the_c_compiler(binding):
 #include "chhs.h"
 int main(void) {
   printf("%zu %zu %zu\n", sizeof(chhs_problem), sizeof(chhs_opts), sizeof(chhs_stats));
-  printf("%zu %zu %zu %zu %zu %zu %zu\n", offsetof(chhs_problem, h), offsetof(chhs_opts, tol), offsetof(chhs_opts, smoother), offsetof(chhs_opts, autotune), offsetof(chhs_opts, order), offsetof(chhs_opts, tile_threads), offsetof(chhs_opts, reserved));
+  printf("%zu %zu %zu %zu %zu %zu %zu\n", offsetof(chhs_problem, h), offsetof(chhs_opts, tol), offsetof(chhs_opts, smoother), offsetof(chhs_opts, autotune), offsetof(chhs_opts, order), offsetof(chhs_opts, tile_threads), offsetof(chhs_opts, tile_rows));
   printf("%zu %zu %zu\n", offsetof(chhs_stats, res), offsetof(chhs_stats, max_abs_phi), offsetof(chhs_stats, res0));
   return 0;
 }
@@ -76,7 +76,7 @@ int main(void) {
             binding.chhs_problem.h.offset, binding.chhs_opts.tol.offset,
             binding.chhs_opts.smoother.offset, binding.chhs_opts.autotune.offset,
             binding.chhs_opts.order.offset, binding.chhs_opts.tile_threads.offset,
-            binding.chhs_opts.reserved.offset,
+            binding.chhs_opts.tile_rows.offset,
             binding.chhs_stats.res.offset, binding.chhs_stats.max_abs_phi.offset,
             binding.chhs_stats.res0.offset]
     assert got == want

@@ -160,6 +160,28 @@ def test_tile_block_sizes_give_the_same_vcycle(chhs, shape):
             assert d <= 1e-13 * max(1.0, np.max(np.abs(ref))), (nt, k, d)
 
 
+@pytest.mark.parametrize("shape", [(512, 256), (96, 160)])
+def test_tile_heights_give_the_same_vcycle(chhs, shape):
+    """Coarse levels cut into 64 x 16, 64 x 8 or 64 x 4 tiles (opts.tile_rows)
+    perform the same cell updates: one V-cycle from the same state agrees to
+    rounding on the finest level."""
+    prm = _prm(shape, eps=0.02, gamma=1.5, s=5e-4)
+    phi0 = uniform_field(shape, 570, mean=0.1, amp=0.05)
+    z = np.zeros(shape)
+    res = {}
+    for rows in (16, 8, 4):
+        sv = _solver(chhs, shape, prm, smoother=TILES, tile_threads=512, tile_rows=rows)
+        sv.setup_step(dev(phi0), dev(phi0), dev(z), dev(z))
+        r = sv.fas_vcycle()
+        res[rows] = (r, [host(sv.read_field(0, n)) for n in ("phi", "mu", "p")])
+    for rows in (8, 4):
+        assert abs(res[rows][0][0] - res[16][0][0]) <= 1e-12 * res[16][0][0]
+        for k in range(3):
+            ref = res[16][1][k]
+            d = np.max(np.abs(res[rows][1][k] - ref))
+            assert d <= 1e-13 * max(1.0, np.max(np.abs(ref))), (rows, k, d)
+
+
 @pytest.mark.parametrize("spec", [[((256, 256), 0.02, 1.5, 5e-4)],
                                   [((128, 128), 0.02, 1.0, 1e-4), ((96, 160), 0.03, 2.0, 5e-4),
                                    ((512, 256), 0.01, 3.0, 1e-4)]], ids=["single", "ragged"])
