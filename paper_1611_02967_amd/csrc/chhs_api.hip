@@ -1099,6 +1099,8 @@ int run_cycles(chhs_ctx* c, bool setup_pending = false) {
     ensure_graph(c, 0, 0);
     ensure_graph(c, 1, 1);
     const bool graphs = c->gexec[0] != nullptr && c->gexec[1] != nullptr;
+    // last residual read and the contraction of the last cycle per instance
+    // (a typical V-cycle contraction until one has been measured)
     std::vector<double> prev(c->n_inst, 0.0), rho(c->n_inst, 0.1);
     if (!setup_pending)
         for (int i = 0; i < c->n_inst; ++i) prev[i] = c->hres[size_t(i) * chhs::kResStride + 3];
