@@ -234,6 +234,12 @@ int chhs_restrict(chhs_ctx* c, int32_t level);
  * Synchronises the stream.  All zero unless opts.timing = 1. */
 int chhs_get_timing(chhs_ctx* c, chhs_timing* out, int32_t reset);
 
+/* Replaces opts.timing (same meaning; >= 0) from the next launch on, for
+ * example to time only one class in a measured stretch.  Captured cycle
+ * graphs are dropped when the mask changes (they are captured again when
+ * timing is 0).  CHHS_E_INVAL for a negative mask. */
+int chhs_set_timing(chhs_ctx* c, int32_t timing);
+
 /* Releases the context (not the caller's workspace).  NULL is ignored. */
 void chhs_destroy(chhs_ctx* c);
 

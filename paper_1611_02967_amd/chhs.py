@@ -92,6 +92,7 @@ _SIGS = {
     "chhs_smooth": (_I, [_P, ctypes.c_int32, ctypes.c_int32]),
     "chhs_restrict": (_I, [_P, ctypes.c_int32]),
     "chhs_get_timing": (_I, [_P, ctypes.POINTER(chhs_timing), ctypes.c_int32]),
+    "chhs_set_timing": (_I, [_P, ctypes.c_int32]),
     "chhs_destroy": (None, [_P]),
     "chhs_strerror": (ctypes.c_char_p, [_I]),
 }
@@ -245,6 +246,11 @@ def chhs_get_timing(ctx, reset=False):
     return {K_CLASSES[k]: (t.ms[k], t.launches[k]) for k in range(8)}
 
 
+def chhs_set_timing(ctx, timing):
+    """Replaces opts.timing from the next launch on."""
+    _check(_lib.chhs_set_timing(ctx, int(timing)), "chhs_set_timing")
+
+
 def chhs_destroy(ctx):
     _lib.chhs_destroy(ctx)
 
@@ -303,6 +309,9 @@ class Solver:
 
     def timing(self, reset=False):
         return chhs_get_timing(self.ctx, reset)
+
+    def set_timing(self, timing):
+        chhs_set_timing(self.ctx, timing)
 
     def level_kernels(self):
         """Per level of the batch: (kind, parameter, blocks) as chhs_level_kernel."""

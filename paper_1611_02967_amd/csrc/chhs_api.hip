@@ -1618,6 +1618,17 @@ int chhs_get_timing(chhs_ctx* c, chhs_timing* out, int32_t reset) {
     return CHHS_OK;
 }
 
+int chhs_set_timing(chhs_ctx* c, int32_t timing) {
+    if (c == nullptr || timing < 0) return CHHS_E_INVAL;
+    if (timing == c->opts.timing) return CHHS_OK;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    resolve_timing(c);
+    // graphs carry the events of the mask they were captured with
+    drop_graphs(c);
+    c->opts.timing = timing;
+    return CHHS_OK;
+}
+
 void chhs_destroy(chhs_ctx* c) {
     if (c == nullptr) return;
     (void)hipStreamSynchronize(c->stream);

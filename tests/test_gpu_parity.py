@@ -356,6 +356,35 @@ def test_cycles_replay_graphs_unless_disabled(chhs, opts, want):
     assert sv.graph_count() == want
 
 
+def test_set_timing_switches_the_timed_classes(chhs):
+    """chhs_set_timing: one class timed after the switch; back to 0, the
+    cycles are captured as graphs again; the steps themselves do not change."""
+    shape = (64, 64)
+    prm = _prm(shape)
+    prev, cur, mu0, p0 = _inputs(shape, 730)
+    sv = _solver(chhs, shape, prm, timing=chhs.timing_mask("pre0", "post0"))
+    ref = _solver(chhs, shape, prm)
+    a = [dev(x) for x in (prev, cur, mu0, p0)]
+    b = [dev(x) for x in (prev, cur, mu0, p0)]
+    sv.step(*a, 1)
+    ref.step(*b, 1)
+    t = sv.timing(reset=True)
+    assert t["pre0"][1] > 0 and t["post0"][1] > 0
+    sv.set_timing(chhs.timing_mask("post0"))
+    sv.step(*a, 1)
+    ref.step(*b, 1)
+    t = sv.timing(reset=True)
+    assert t["pre0"][1] == 0 and t["post0"][1] > 0
+    assert sv.graph_count() == 0
+    sv.set_timing(0)
+    sv.step(*a, 1)
+    ref.step(*b, 1)
+    assert sv.graph_count() == 2
+    assert sum(v[1] for v in sv.timing().values()) == 0
+    for x, y in zip(a, b):
+        assert np.array_equal(host(x), host(y))
+
+
 def test_nonfinite_input_is_reported_and_state_kept(chhs):
     shape = (32, 32)
     prm = _prm(shape)
