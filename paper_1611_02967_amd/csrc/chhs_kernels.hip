@@ -335,6 +335,16 @@ __global__ __launch_bounds__(kBlock) void k_mixed_residual(Batch<double> b64, Ba
             v[2] = r2 * r2;
             v[3] = pc;
         }
+    } else if (add) {
+        // an instance that has converged keeps its iterate in both copies, so
+        // that it is still the current one after the step flips the copies
+        const Level<double> L = view_at(b64, tk.inst, 0, b64.cur);
+        const int idx = tk.cell0 + threadIdx.x;
+        if (idx < L.n) {
+            L.phi_alt[idx] = L.phi[idx];
+            L.mu_alt[idx] = L.mu[idx];
+            L.p_alt[idx] = L.p[idx];
+        }
     }
     double out[4];
     block_sum<4>(v, out);

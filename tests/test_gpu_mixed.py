@@ -121,3 +121,25 @@ def test_mixed_graph_replay_equals_eager(chhs):
     for ha, hb in zip(a, b):
         for k in ("phi", "mu", "p"):
             assert np.array_equal(ha[k], hb[k])
+
+
+@pytest.mark.parametrize("name", ["2d-ragged", "3d-ragged"])
+def test_mixed_batch_equals_single_instance_runs(chhs, name):
+    """Instances of a mixed-precision batch converge after different numbers
+    of refinement steps; one that has converged must keep its iterate while the
+    others go on (the finest FP64 level alternates between two copies each
+    refinement step).  Every instance of the batch equals its own single run
+    bitwise, step by step, with the same refinement count."""
+    spec = SPECS[name]
+    shapes = [s[0] for s in spec]
+    phi0s = [uniform_field(sh, 4400 + i, mean=0.1, amp=0.05) for i, sh in enumerate(shapes)]
+    batch = _steps(chhs, spec, phi0s, 3, precision=1)
+    counts = set()
+    for i in range(len(spec)):
+        single = _steps(chhs, [spec[i]], [phi0s[i]], 3, precision=1)
+        for hb, hs in zip(batch, single):
+            for k in ("phi", "mu", "p"):
+                assert np.array_equal(_unpack(hb[k], shapes)[i], hs[k].reshape(shapes[i])), (i, k)
+            assert hb["stats"][i]["vcycles"] == hs["stats"][0]["vcycles"]
+            counts.add(hb["stats"][i]["vcycles"])
+    assert len(counts) > 1       # the instances do converge after different counts
