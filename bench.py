@@ -410,8 +410,11 @@ def main():
 
     if not args.no_cpu_baseline:
         log("timing the oracle on a bounded sample (single-threaded NumPy)")
+        cpu0 = time.process_time()
         rate, desc, wall = oracle_sample(*start_state, w, vcyc / args.steps)
-        out["cpu_baseline"] = {"value": rate, "unit": "cell-updates/s", "cores": 1,
+        # threads actually used: process CPU time over wall time of the sample
+        cores = max(1, round((time.process_time() - cpu0) / max(wall, 1e-9)))
+        out["cpu_baseline"] = {"value": rate, "unit": "cell-updates/s", "cores": cores,
                                "kind": "oracle", "sample": desc,
                                "host": {"cpu": cpu_model(), "os_cpu_count": os.cpu_count(),
                                         "omp_threads": os.environ.get("OMP_NUM_THREADS")},
