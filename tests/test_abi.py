@@ -104,6 +104,17 @@ def test_workspace_bytes_rejects_invalid_problems(binding):
     assert binding.chhs_workspace_bytes([good], binding.chhs_default_opts(order=1, precision=1)) == 0
     assert binding.chhs_workspace_bytes([good], binding.chhs_default_opts(order=3)) == 0
     assert binding.chhs_default_opts().order == 2
+    # tile block sizes and heights: 0 (by the tile count) or one of the kernels' sizes
+    o = binding.chhs_default_opts()
+    assert o.tile_threads == 0 and o.tile_rows == 0
+    for nt in (256, 512, 1024):
+        assert binding.chhs_workspace_bytes([good], binding.chhs_default_opts(tile_threads=nt)) > 0
+    for nt in (128, 768, -1):
+        assert binding.chhs_workspace_bytes([good], binding.chhs_default_opts(tile_threads=nt)) == 0
+    for rows in (4, 8, 16):
+        assert binding.chhs_workspace_bytes([good], binding.chhs_default_opts(tile_rows=rows)) > 0
+    for rows in (2, 32, -4):
+        assert binding.chhs_workspace_bytes([good], binding.chhs_default_opts(tile_rows=rows)) == 0
 
 
 def test_workspace_accounts_for_every_level(binding):
@@ -145,4 +156,6 @@ def test_entry_points_reject_null_context(binding):
     assert binding._lib.chhs_fas_vcycle(None, None) == binding.CHHS_E_INVAL
     assert binding._lib.chhs_step(None, None, None, None, None, 1, None) == binding.CHHS_E_INVAL
     assert binding._lib.chhs_energy_mass(None, None, None, None) == binding.CHHS_E_INVAL
+    assert binding._lib.chhs_graph_count(None, None) == binding.CHHS_E_INVAL
+    assert binding._lib.chhs_set_timing(None, 0) == binding.CHHS_E_INVAL
     binding._lib.chhs_destroy(None)
