@@ -830,10 +830,13 @@ float time_level(chhs_ctx* c, const Hier<T>& H, int l, int reps, hipEvent_t ea, 
 // timing and are rewritten by the next setup).
 int autotune(chhs_ctx* c) {
     Layout& L = c->lay;
+    hipEvent_t ea = nullptr, eb = nullptr;
+    if (hipEventCreate(&ea) != hipSuccess || hipEventCreate(&eb) != hipSuccess) {
+        if (ea) (void)hipEventDestroy(ea);
+        return CHHS_E_HIP;
+    }
     const chhs_opts saved = c->opts;
     c->opts.timing = 0;
-    hipEvent_t ea = nullptr, eb = nullptr;
-    if (hipEventCreate(&ea) != hipSuccess || hipEventCreate(&eb) != hipSuccess) return CHHS_E_HIP;
     int rc = CHHS_OK;
     for (int l = 0; l < L.depth && rc == CHHS_OK; ++l) {
         if (c->T[l].n == 0) continue;
