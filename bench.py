@@ -58,6 +58,56 @@ def launch_bytes_per_cell(dim, cls, mixed=False):
     return (4 + 6 + 3) / 2 * 8
 
 
+def vcycle_bytes(dim, shape, level_kernels):
+    """Algorithmic bytes of one FP64 V(2,2) cycle over every level.
+
+    Per cell of level l (n_l cells, r = 2^dim children per coarse cell, 8 B per
+    value), what each launch of the cycle must move at minimum:
+      finest level, fused kernels : the pre and post launches above (174 B, 2D)
+      coarse fused, first launch  : u, phi_*, phi^m and the restricted residual
+                                    fr read, u and f = fr + N(u) written, the
+                                    restriction to level l + 1 (9 per r)
+                                    = (14 + 9/r) 8
+      coarse fused, strips        : a separate launch forms f (u, fr, phi_*,
+                                    phi^m read, f written: 11 values), the
+                                    first launch then reads f: (11 + 9/r) 8
+      coarse fused, post launch   : u, phi_*, phi^m, f read, u written, u_c and
+                                    ub_c read (6 per r)  = (11 + 6/r) 8
+      per-cell kernels            : 2 (nu1 + nu2) color launches of 52 B; the
+                                    residual + restriction (8 + 9/r) 8; the
+                                    right-hand side of level l + 1 unless the
+                                    tail forms it, 11/r 8; the prolongation
+                                    (6 + 6/r) 8
+      tail (one launch)           : u and fr of its top level read, u written,
+                                    phi_* and phi^m of every tail level read
+    The norm reduction and the per-cycle readback (a few KB) are left out.
+    """
+    r = 2 ** dim
+    n0 = 1
+    for s in shape:
+        n0 *= s
+    kinds = [k[0] if isinstance(k, (list, tuple)) else k for k in level_kernels]
+    total = 0.0
+    for l, kind in enumerate(kinds):
+        n = n0 / r ** l
+        if kind == "tail":
+            rest = sum(n0 / r ** k for k in range(l, len(kinds)))
+            total += 8 * (9 * n + 2 * rest)
+            break
+        if kind == "per-cell":
+            next_tail = l + 1 < len(kinds) and kinds[l + 1] == "tail"
+            b = 2 * (2 + 2) * 52 + (8 + 9 / r) * 8 + (6 + 6 / r) * 8
+            b += 0 if next_tail else 11 / r * 8
+        elif l == 0:
+            b = launch_bytes_per_cell(dim, "pre0") + launch_bytes_per_cell(dim, "post0")
+        elif kind == "strips":
+            b = 11 * 8 + (11 + 9 / r) * 8 + (11 + 6 / r) * 8
+        else:
+            b = (14 + 9 / r) * 8 + (11 + 6 / r) * 8
+        total += b * n
+    return total
+
+
 # Sources of the finest-level 2D smoothing kernels: HBM traffic measured with
 # rocprofv3 counters is reported only while these are unchanged.
 KERNEL_SOURCES = ["chhs_stream2d.hip", "chhs_cell.hpp", "chhs_internal.hpp"]
@@ -387,7 +437,16 @@ def main():
         "kernel_ms_per_step": kernel_ms,
         "level_kernels": [list(k) for k in level_kernels],
         "roofline": roofline,
+        "per_vcycle": None,
     }
+    if not mixed and vcyc:
+        # HBM fraction of whole V-cycles: the cycle's algorithmic bytes over the
+        # wall time per cycle (the per-step setup, copy-out and energies included)
+        vb = vcycle_bytes(dim, shape, level_kernels)
+        t_cyc = elapsed / vcyc
+        out["per_vcycle"] = {"algorithmic_bytes": round(vb), "wall_us": round(t_cyc * 1e6, 2),
+                             "achieved": round(vb / t_cyc / 1e9, 1), "peak": HBM_PEAK_GBS,
+                             "unit": "GB/s", "frac": round(vb / t_cyc / 1e9 / HBM_PEAK_GBS, 4)}
 
     if not args.no_parity:
         # parity of the same workload at a size the oracle solves in seconds
