@@ -18,6 +18,7 @@
 
 using chhs::Batch;
 using chhs::CellTask;
+using chhs::FoldTask;
 using chhs::InstInfo;
 using chhs::Level;
 using chhs::LevelDesc;
@@ -67,12 +68,17 @@ struct Layout {
     std::vector<int> tail_insts;
     std::vector<CellTask> A0n;              // finest-level cells of instances without a fused norm
     std::vector<Range> rngA0, rngT0, rngA0n;
+    // folds of the partials over A[0] / A0n (empty when no instance has more
+    // than kFold of them) and the per-instance ranges of the folded partials
+    std::vector<FoldTask> FA0, FA0n;
+    std::vector<Range> rngA0f, rngA0nf;
     int max_nlev = 0, depth = 0;
     size_t tail_lds = 0, tail_lds32 = 0;
     // offsets into the workspace
     size_t off_desc = 0, off_desc32 = 0, off_info = 0, off_tail = 0, off_rngA0 = 0, off_rngT0 = 0,
            off_rngA0n = 0;
     size_t off_A0n = 0, off_partial_t = 0;
+    size_t off_FA0 = 0, off_FA0n = 0, off_rngA0f = 0, off_rngA0nf = 0, off_partial_f = 0;
     size_t off_partial = 0, off_res = 0, off_eres = 0, off_act_cycle = 0, off_act_next = 0,
            off_cycles = 0;
     std::vector<size_t> off_A, off_B, off_Bc, off_Bh, off_Bcs, off_T, off_Tall, off_S, off_Sall;
@@ -100,11 +106,15 @@ struct chhs_ctx {
     Table<TileTask> T[kMaxLevels], Tall[kMaxLevels];
     Table<StripTask> S[kMaxLevels], Sall[kMaxLevels];
     Table<CellTask> A0n;
+    Table<FoldTask> FA0, FA0n;
     int* tail_insts = nullptr;
     Range* rngA0 = nullptr;
     Range* rngT0 = nullptr;
     Range* rngA0n = nullptr;
+    Range* rngA0f = nullptr;
+    Range* rngA0nf = nullptr;
     double* partial = nullptr;
+    double* partial_f = nullptr;    // folded per-cell partials
     double* partial_t = nullptr;    // norm partials of the fused finest-level launch
     double* res = nullptr;          // [n_inst][kResStride]
     double* eres = nullptr;         // [n_inst][kResStride]
@@ -275,6 +285,28 @@ void ranges_of(std::vector<Range>& r, int n_inst, const std::vector<CellTask>& t
         Range& x = r[t[q].inst];
         if (x.end == 0) x.begin = q;
         x.end = q + 1;
+    }
+}
+
+// Per-cell norm partials per folded partial.  A single workgroup per instance
+// sums an instance's partials; above this many it would spend tens of
+// microseconds loading them one stride after another.
+constexpr int kFold = 1024;
+
+// Runs of kFold partials within each instance's range (relative to the
+// range's start, so an instance's sum does not depend on the batch), and the
+// ranges of the folded partials; nothing when no range is longer than kFold.
+void fold_of(const std::vector<Range>& r, std::vector<FoldTask>& t, std::vector<Range>& rf) {
+    t.clear();
+    rf.assign(r.size(), Range{0, 0});
+    bool need = false;
+    for (const Range& x : r) need = need || x.end - x.begin > kFold;
+    if (!need) return;
+    for (int i = 0; i < int(r.size()); ++i) {
+        rf[i].begin = int(t.size());
+        for (int q = r[i].begin; q < r[i].end; q += kFold)
+            t.push_back(FoldTask{i, q, std::min(q + kFold, r[i].end)});
+        rf[i].end = int(t.size());
     }
 }
 
@@ -473,6 +505,8 @@ bool plan(const chhs_problem* p, int n_inst, const chhs_opts* o, char* base, Lay
     // per-instance ranges of the finest-level partial buffers
     ranges_of(L.rngA0, n_inst, L.A[0]);
     ranges_of(L.rngA0n, n_inst, L.A0n);
+    fold_of(L.rngA0, L.FA0, L.rngA0f);
+    fold_of(L.rngA0n, L.FA0n, L.rngA0nf);
     fused_ranges(L, n_inst);
     L.partial_cap = int(L.A[0].size());
     L.partial_t_cap = int(std::max<size_t>(1, std::max(L.T[0].size(), L.S[0].size())));
@@ -484,6 +518,10 @@ bool plan(const chhs_problem* p, int n_inst, const chhs_opts* o, char* base, Lay
     L.off_rngT0 = take(n_inst * sizeof(Range));
     L.off_rngA0n = take(n_inst * sizeof(Range));
     L.off_A0n = take(L.A0n.size() * sizeof(CellTask));
+    L.off_FA0 = take(L.FA0.size() * sizeof(FoldTask));
+    L.off_FA0n = take(L.FA0n.size() * sizeof(FoldTask));
+    L.off_rngA0f = take(n_inst * sizeof(Range));
+    L.off_rngA0nf = take(n_inst * sizeof(Range));
     for (int l = 0; l < kMaxLevels; ++l) {
         L.off_A.push_back(take(L.A[l].size() * sizeof(CellTask)));
         L.off_B.push_back(take(L.B[l].size() * sizeof(CellTask)));
@@ -498,6 +536,8 @@ bool plan(const chhs_problem* p, int n_inst, const chhs_opts* o, char* base, Lay
     }
     L.off_partial = take(size_t(L.partial_cap) * chhs::kPartialStride * sizeof(double));
     L.off_partial_t = take(size_t(L.partial_t_cap) * chhs::kPartialStride * sizeof(double));
+    L.off_partial_f = take(std::max<size_t>(1, std::max(L.FA0.size(), L.FA0n.size())) *
+                           chhs::kPartialStride * sizeof(double));
     // res | act_next | cycles contiguous: one readback per cycle
     L.off_res = take(size_t(n_inst) * chhs::kResStride * sizeof(double) + 2 * n_inst * sizeof(int));
     L.off_act_next = L.off_res + size_t(n_inst) * chhs::kResStride * sizeof(double);
@@ -914,6 +954,19 @@ int autotune(chhs_ctx* c) {
     return check_launch();
 }
 
+// The partials that the per-instance reduction reads for the finest level's
+// per-cell tasks (n_only: the tasks of instances without a fused norm, else
+// every instance's), folded first when an instance has more than kFold.
+void fold_cells(chhs_ctx* c, bool n_only, const int* act, const double** src, const Range** rng) {
+    const Table<FoldTask>& F = n_only ? c->FA0n : c->FA0;
+    *src = c->partial;
+    *rng = n_only ? c->rngA0n : c->rngA0;
+    if (F.n == 0) return;
+    chhs::launch_fold_partials(c->partial, F.dev, F.n, act, c->partial_f, c->stream);
+    *src = c->partial_f;
+    *rng = n_only ? c->rngA0nf : c->rngA0f;
+}
+
 // Plain FP64: one V-cycle, the residual norms (p normalised to mean zero).
 void enqueue_plain_cycle(chhs_ctx* c, bool count) {
     const int* act = c->act_cycle;
@@ -924,7 +977,10 @@ void enqueue_plain_cycle(chhs_ctx* c, bool count) {
     // instances without a fused finest-level norm: per-cell residual partials
     chhs::launch_residual_partials(c->dim, batch(c, 0, act), c->A0n.dev, c->A0n.n, c->partial,
                                    c->stream);
-    chhs::launch_inst_reduce(c->partial, c->rngA0n, c->partial_t, c->rngT0, 1, c->dinfo, act,
+    const double* src;
+    const Range* rng;
+    fold_cells(c, true, act, &src, &rng);
+    chhs::launch_inst_reduce(src, rng, c->partial_t, c->rngT0, 1, c->dinfo, act,
                              c->act_next, c->cycles, c->res, c->n_inst, o.tol,
                              count ? o.max_vcycles : 1 << 30, count ? 1 : 0, c->stream);
     if (!c->defer_shift)
@@ -952,7 +1008,10 @@ void enqueue_refinement(chhs_ctx* c, bool count, bool add) {
     chhs::launch_mixed_residual(c->dim, batch(c, 0, add ? act : nullptr), batch32(c, 0, act),
                                 c->A[0].dev, c->A[0].n, add ? 1 : 0, c->partial, c->stream);
     c->cur[0] ^= 1;
-    chhs::launch_inst_reduce(c->partial, c->rngA0, nullptr, nullptr, 0, c->dinfo,
+    const double* src;
+    const Range* rng;
+    fold_cells(c, false, add ? act : nullptr, &src, &rng);
+    chhs::launch_inst_reduce(src, rng, nullptr, nullptr, 0, c->dinfo,
                              add ? act : nullptr, c->act_next, c->cycles, c->res, c->n_inst,
                              o.tol, count ? o.max_vcycles : 1 << 30, count ? 1 : 0, c->stream);
     chhs::launch_shift_p(batch(c, 0, add ? act : nullptr), c->A[0].dev, c->A[0].n, c->res,
@@ -1206,7 +1265,10 @@ int setup(chhs_ctx* c, const double* phi_prev, const double* phi_cur, const doub
         enqueue_refinement(c, false, false);
     } else {
         TimedScope t(c, CHHS_K_NORM);
-        chhs::launch_inst_reduce(c->partial, c->rngA0, nullptr, nullptr, 0, c->dinfo, nullptr,
+        const double* src;
+        const Range* rng;
+        fold_cells(c, false, nullptr, &src, &rng);
+        chhs::launch_inst_reduce(src, rng, nullptr, nullptr, 0, c->dinfo, nullptr,
                                  c->act_next, c->cycles, c->res, c->n_inst, c->opts.tol,
                                  c->opts.max_vcycles, 0, c->stream);
         if (!c->defer_shift)
@@ -1318,6 +1380,9 @@ int chhs_init(const chhs_problem* p, int32_t n_inst, const chhs_opts* o, void* w
     c->rngA0n = reinterpret_cast<Range*>(b + L.off_rngA0n);
     c->partial_t = reinterpret_cast<double*>(b + L.off_partial_t);
     c->partial = reinterpret_cast<double*>(b + L.off_partial);
+    c->partial_f = reinterpret_cast<double*>(b + L.off_partial_f);
+    c->rngA0f = reinterpret_cast<Range*>(b + L.off_rngA0f);
+    c->rngA0nf = reinterpret_cast<Range*>(b + L.off_rngA0nf);
     c->res = reinterpret_cast<double*>(b + L.off_res);
     c->eres = reinterpret_cast<double*>(b + L.off_eres);
     c->act_cycle = reinterpret_cast<int*>(b + L.off_act_cycle);
@@ -1353,6 +1418,13 @@ int chhs_init(const chhs_problem* p, int32_t n_inst, const chhs_opts* o, void* w
         rc |= upload(c->Sall[l], b, L.off_Sall[l], L.Sall[l], st);
     }
     rc |= upload(c->A0n, b, L.off_A0n, L.A0n, st);
+    rc |= upload(c->FA0, b, L.off_FA0, L.FA0, st);
+    rc |= upload(c->FA0n, b, L.off_FA0n, L.FA0n, st);
+    if (hipMemcpyAsync(c->rngA0f, L.rngA0f.data(), n_inst * sizeof(Range), hipMemcpyHostToDevice,
+                       st) != hipSuccess ||
+        hipMemcpyAsync(c->rngA0nf, L.rngA0nf.data(), n_inst * sizeof(Range),
+                       hipMemcpyHostToDevice, st) != hipSuccess)
+        rc = CHHS_E_HIP;
     if (rc) return fail(CHHS_E_HIP);
     // pinned mirror, same layout as the device result block: res | act_next |
     // cycles, then the energies
@@ -1414,7 +1486,10 @@ int chhs_residual_norms(chhs_ctx* c, double* out_host) {
     if (!c->loaded) return CHHS_E_STATE;
     chhs::launch_residual_partials(c->dim, batch(c, 0, nullptr), c->A[0].dev, c->A[0].n,
                                    c->partial, c->stream);
-    chhs::launch_inst_reduce(c->partial, c->rngA0, nullptr, nullptr, 0, c->dinfo, nullptr,
+    const double* src;
+    const Range* rng;
+    fold_cells(c, false, nullptr, &src, &rng);
+    chhs::launch_inst_reduce(src, rng, nullptr, nullptr, 0, c->dinfo, nullptr,
                              c->act_next, c->cycles, c->res, c->n_inst, c->opts.tol, 1 << 30, 0,
                              c->stream);
     int rc = check_launch();

@@ -129,6 +129,7 @@ struct CellTask { int inst; int cell0; };      // kBlock consecutive cells of on
 struct TileTask { int inst; int bx; int by; }; // one tile of a 2D level
 struct StripTask { int inst; int sx; int y0; int y1; };   // rows [y0, y1) of strip sx
 struct Range { int begin; int end; };          // an instance's blocks in a partial buffer
+struct FoldTask { int inst; int begin; int end; };   // partials [begin, end) of one instance
 
 // Arguments common to every batched launch.
 template <typename T>
@@ -192,6 +193,11 @@ void launch_residual_partials(int dim, const Batch<double>& b, const CellTask* t
 // ||R_mu||, ||R_p||, combined norm; 4 = mean(p); 5 = 1 if the norm is not
 // finite; count != 0: cycles[i] += 1; act_next[i] = norm > tol, finite and
 // cycles[i] < max_cycles.  Inactive instances keep their results.
+// dst[q] = the sum of src[t[q].begin .. t[q].end) (4 doubles per partial, in
+// index order within each thread's stride, then over the block), for the
+// tasks of active instances.
+void launch_fold_partials(const double* src, const FoldTask* t, int nt, const int* active,
+                          double* dst, hipStream_t st);
 void launch_inst_reduce(const double* partial, const Range* ranges, const double* partial_t,
                         const Range* ranges_t, int use_fused, const InstInfo* info,
                         const int* active, int* act_next, int* cycles, double* res, int n_inst,

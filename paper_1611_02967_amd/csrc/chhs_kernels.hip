@@ -410,6 +410,24 @@ __global__ __launch_bounds__(kBlock) void k_residual_partials(Batch<double> b,
         for (int c = 0; c < 4; ++c) partial[blockIdx.x * kPartialStride + c] = out[c];
 }
 
+// Sums runs of consecutive norm partials of one instance into one partial, so
+// that the per-instance reduction (one workgroup per instance) reads a few
+// partials instead of thousands of scattered ones.
+__global__ __launch_bounds__(kBlock) void k_fold_partials(const double* __restrict__ src,
+                                                          const FoldTask* __restrict__ t,
+                                                          const int* active, double* dst) {
+    const FoldTask ft = t[blockIdx.x];
+    if (inactive(active, ft.inst)) return;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int q = ft.begin + threadIdx.x; q < ft.end; q += kBlock)
+        for (int c = 0; c < 4; ++c) v[c] += src[q * kPartialStride + c];
+    double s[4];
+    block_sum<4>(v, s);
+    if (threadIdx.x == 0)
+        for (int c = 0; c < 4; ++c) dst[blockIdx.x * kPartialStride + c] = s[c];
+}
+
 __global__ __launch_bounds__(kBlock) void k_inst_reduce(const double* __restrict__ partial,
                                                         const Range* __restrict__ ranges,
                                                         const double* __restrict__ partial_t,
@@ -690,6 +708,12 @@ void launch_mixed_residual(int dim, const Batch<double>& b64, const Batch<float>
 void launch_residual_partials(int dim, const Batch<double>& b, const CellTask* t, int nt,
                               double* partial, hipStream_t st) {
     CHHS_DISPATCH(dim, k_residual_partials, nt, b, t, partial);
+}
+
+void launch_fold_partials(const double* src, const FoldTask* t, int nt, const int* active,
+                          double* dst, hipStream_t st) {
+    if (nt <= 0) return;
+    hipLaunchKernelGGL(k_fold_partials, dim3(nt), dim3(kBlock), 0, st, src, t, active, dst);
 }
 
 void launch_inst_reduce(const double* partial, const Range* ranges, const double* partial_t,
