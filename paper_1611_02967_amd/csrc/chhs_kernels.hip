@@ -10,6 +10,17 @@
 namespace chhs {
 namespace {
 
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.
+// The task of this workgroup: XCD x = b mod 8 takes a contiguous range of the
+// tasks (a bijection on [0, gridDim.x)), so the neighbouring rows and planes
+// that consecutive tasks' stencils share are read through one L2.
+__device__ __forceinline__ int xcd_task() {
+    const int n = int(gridDim.x), bid = int(blockIdx.x);
+    const int q8 = n / 8, rem = n % 8;
+    const int xcd = bid % 8, jj = bid / 8;
+    return xcd * q8 + (xcd < rem ? xcd : rem) + jj;
+}
+
 __device__ __forceinline__ bool inactive(const int* active, int inst) {
     return active != nullptr && active[inst] == 0;
 }
@@ -19,7 +30,7 @@ __device__ __forceinline__ Level<T> view_at(const Batch<T>& b, int inst, int lev
     return make_view(b.desc[inst * kMaxLevels + level], cur);
 }
 
-template <int NC>
+template <int NC, int NT = kBlock>
 __device__ __forceinline__ void block_sum(double (&v)[NC], double* out);
 
 // Per-step setup of the finest level, and with `partial` the residual of the
@@ -34,7 +45,8 @@ __global__ __launch_bounds__(kBlock) void k_setup(Batch<double> b, const CellTas
                                                   const double* __restrict__ phi_cur,
                                                   const double* __restrict__ mu,
                                                   const double* __restrict__ p, double* partial) {
-    const CellTask tk = t[blockIdx.x];
+    const int task = xcd_task();
+    const CellTask tk = t[task];
     const Level<double> L = view_at(b, tk.inst, 0, b.cur);
     const int idx = tk.cell0 + threadIdx.x;
     double v[4] = {0.0, 0.0, 0.0, 0.0};
@@ -96,14 +108,15 @@ __global__ __launch_bounds__(kBlock) void k_setup(Batch<double> b, const CellTas
     double out[4];
     block_sum<4>(v, out);
     if (threadIdx.x == 0)
-        for (int c = 0; c < 4; ++c) partial[blockIdx.x * kPartialStride + c] = out[c];
+        for (int c = 0; c < 4; ++c) partial[task * kPartialStride + c] = out[c];
 }
 
 // tasks over coarse cells (level b.level + 1)
 template <int DIM, typename T>
 __global__ __launch_bounds__(kBlock) void k_restrict_frozen(Batch<T> b,
                                                             const CellTask* __restrict__ t) {
-    const CellTask tk = t[blockIdx.x];
+    const int task = xcd_task();
+    const CellTask tk = t[task];
     const Level<T> F = view_at(b, tk.inst, b.level, 0);
     const Level<T> C = view_at(b, tk.inst, b.level + 1, 0);
     const int idx = tk.cell0 + threadIdx.x;
@@ -126,7 +139,8 @@ __global__ __launch_bounds__(kBlock) void k_restrict_frozen(Batch<T> b,
 template <int DIM, typename T, bool CORR>
 __global__ __launch_bounds__(kBlock) void k_smooth(Batch<T> b, const CellTask* __restrict__ t,
                                                    int color) {
-    const CellTask tk = t[blockIdx.x];
+    const int task = xcd_task();
+    const CellTask tk = t[task];
     if (inactive(b.active, tk.inst)) return;
     const Level<T> L = view_at(b, tk.inst, b.level, b.cur);
     const int idx = tk.cell0 + threadIdx.x;
@@ -148,7 +162,8 @@ __global__ __launch_bounds__(kBlock) void k_smooth(Batch<T> b, const CellTask* _
 template <int DIM, typename T, bool CORR>
 __global__ __launch_bounds__(kBlock) void k_smooth_color(Batch<T> b, const CellTask* __restrict__ t,
                                                          int color) {
-    const CellTask tk = t[blockIdx.x];
+    const int task = xcd_task();
+    const CellTask tk = t[task];
     if (inactive(b.active, tk.inst)) return;
     const Level<T> L = view_at(b, tk.inst, b.level, b.cur);
     const int q = tk.cell0 + threadIdx.x;
@@ -172,7 +187,8 @@ __global__ __launch_bounds__(kBlock) void k_smooth_color(Batch<T> b, const CellT
 template <int DIM, typename T, bool CORR>
 __global__ __launch_bounds__(kBlock) void k_restrict_residual(Batch<T> b,
                                                               const CellTask* __restrict__ t) {
-    const CellTask tk = t[blockIdx.x];
+    const int task = xcd_task();
+    const CellTask tk = t[task];
     if (inactive(b.active, tk.inst)) return;
     const Level<T> F = view_at(b, tk.inst, b.level, b.cur);
     const Level<T> C = view_at(b, tk.inst, b.level + 1, b.cur_c);
@@ -211,7 +227,8 @@ __global__ __launch_bounds__(kBlock) void k_restrict_residual(Batch<T> b,
 template <int DIM, typename T, bool CORR>
 __global__ __launch_bounds__(kBlock) void k_coarse_rhs(Batch<T> b,
                                                        const CellTask* __restrict__ t) {
-    const CellTask tk = t[blockIdx.x];
+    const int task = xcd_task();
+    const CellTask tk = t[task];
     if (inactive(b.active, tk.inst)) return;
     const Level<T> C = view_at(b, tk.inst, b.level + 1, b.cur_c);
     const int idx = tk.cell0 + threadIdx.x;
@@ -228,7 +245,8 @@ __global__ __launch_bounds__(kBlock) void k_coarse_rhs(Batch<T> b,
 // tasks over fine cells: u += P(u_c - ub_c)
 template <int DIM, typename T>
 __global__ __launch_bounds__(kBlock) void k_prolong(Batch<T> b, const CellTask* __restrict__ t) {
-    const CellTask tk = t[blockIdx.x];
+    const int task = xcd_task();
+    const CellTask tk = t[task];
     if (inactive(b.active, tk.inst)) return;
     const Level<T> F = view_at(b, tk.inst, b.level, b.cur);
     const Level<T> C = view_at(b, tk.inst, b.level + 1, b.cur_c);
@@ -242,15 +260,13 @@ __global__ __launch_bounds__(kBlock) void k_prolong(Batch<T> b, const CellTask* 
     F.p[idx] += C.p[c] - C.ub2[c];
 }
 
-template <int NC>
-__device__ __forceinline__ void block_sum(double (&v)[NC], double* out);
-
 // ---- mixed precision: FP64 outer work around the FP32 correction solve ---------------
 
 // FP32 copies of the finest level's frozen data (phi_*, phi^m).
 __global__ __launch_bounds__(kBlock) void k_mixed_frozen(Batch<double> b64, Batch<float> b32,
                                                          const CellTask* __restrict__ t) {
-    const CellTask tk = t[blockIdx.x];
+    const int task = xcd_task();
+    const CellTask tk = t[task];
     const Level<double> L = view_at(b64, tk.inst, 0, 0);
     const Level<float> E = view_at(b32, tk.inst, 0, 0);
     const int idx = tk.cell0 + threadIdx.x;
@@ -262,7 +278,8 @@ __global__ __launch_bounds__(kBlock) void k_mixed_frozen(Batch<double> b64, Batc
 // Zero correction on the FP32 finest level (current copy).
 __global__ __launch_bounds__(kBlock) void k_zero_correction(Batch<float> b32,
                                                             const CellTask* __restrict__ t) {
-    const CellTask tk = t[blockIdx.x];
+    const int task = xcd_task();
+    const CellTask tk = t[task];
     if (inactive(b32.active, tk.inst)) return;
     const Level<float> E = view_at(b32, tk.inst, 0, b32.cur);
     const int idx = tk.cell0 + threadIdx.x;
@@ -278,87 +295,154 @@ __global__ __launch_bounds__(kBlock) void k_zero_correction(Batch<float> b32,
 // written as u' into the other FP64 copy, R and b = u'_phi rounded to FP32
 // into the FP32 finest level's right-hand side and base state, and the block
 // partial sums of R^2 and p'.
+// A thread takes a pair of x-adjacent cells (2 q, 2 q + 1): the finest level
+// has a coarser one, so its x extent is even and a task's 256 cells are 128
+// whole pairs of one row each.  The pair's own values and its y (and z)
+// neighbours load as 2-element vectors, the pair's outer x neighbours as
+// single values; each cell sums its faces in the order of for_each_face.
+constexpr int kPairThreads = kBlock / 2;
+
 template <int DIM>
-__global__ __launch_bounds__(kBlock) void k_mixed_residual(Batch<double> b64, Batch<float> b32,
-                                                           const CellTask* __restrict__ t,
-                                                           int add, double* partial) {
-    const CellTask tk = t[blockIdx.x];
+__global__ __launch_bounds__(kPairThreads) void k_mixed_residual(Batch<double> b64,
+                                                                 Batch<float> b32,
+                                                                 const CellTask* __restrict__ t,
+                                                                 int add, double* partial) {
+    typedef double D2 __attribute__((ext_vector_type(2)));
+    typedef float F2 __attribute__((ext_vector_type(2)));
+    const int task = xcd_task();
+    const CellTask tk = t[task];
     double v[4] = {0.0, 0.0, 0.0, 0.0};
+    const int idx = tk.cell0 + 2 * int(threadIdx.x);      // first cell of the pair
+    const Level<double> L = view_at(b64, tk.inst, 0, b64.cur);
     if (!inactive(b64.active, tk.inst)) {
-        const Level<double> L = view_at(b64, tk.inst, 0, b64.cur);
         const Level<float> E = view_at(b32, tk.inst, 0, b32.cur);
-        const int idx = tk.cell0 + threadIdx.x;
         if (idx < L.n) {
             int i, j, k;
             decode<DIM>(idx, L.nx, L.ny, i, j, k);
-            auto u_at = [&](int q, double& ph, double& m, double& pp) {
-                ph = L.phi[q];
-                m = L.mu[q];
-                pp = L.p[q];
+            // u + e of the pair at q (even), and of the single cell q
+            auto u_pair = [&](int q, D2& ph, D2& m, D2& pp) {
+                ph = gload(reinterpret_cast<const D2*>(L.phi), q >> 1);
+                m = gload(reinterpret_cast<const D2*>(L.mu), q >> 1);
+                pp = gload(reinterpret_cast<const D2*>(L.p), q >> 1);
                 if (add) {
-                    ph += double(E.phi[q]);
-                    m += double(E.mu[q]);
-                    pp += double(E.p[q]);
+                    const F2 e0 = gload(reinterpret_cast<const F2*>(E.phi), q >> 1);
+                    const F2 e1 = gload(reinterpret_cast<const F2*>(E.mu), q >> 1);
+                    const F2 e2 = gload(reinterpret_cast<const F2*>(E.p), q >> 1);
+                    ph.x += double(e0.x);
+                    ph.y += double(e0.y);
+                    m.x += double(e1.x);
+                    m.y += double(e1.y);
+                    pp.x += double(e2.x);
+                    pp.y += double(e2.y);
                 }
             };
-            double phic, muc, pc;
-            u_at(idx, phic, muc, pc);
-            const double psc = L.pstar[idx];
-            double smm = 0, sap = 0, sphi = 0, sp = 0, samu = 0;
-            for_each_face<DIM>(i, j, k, L.nx, L.ny, L.nz, idx, [&](bool h, int nb) {
-                double phn, mun, pn;
-                u_at(nb, phn, mun, pn);
-                const double a = 0.5 * (psc + L.pstar[nb]);
+            auto u_one = [&](int q, double& ph, double& m, double& pp) {
+                ph = gload(L.phi, q);
+                m = gload(L.mu, q);
+                pp = gload(L.p, q);
+                if (add) {
+                    ph += double(gload(E.phi, q));
+                    m += double(gload(E.mu, q));
+                    pp += double(gload(E.p, q));
+                }
+            };
+            D2 phc, muc, pc;
+            u_pair(idx, phc, muc, pc);
+            const D2 psc = gload(reinterpret_cast<const D2*>(L.pstar), idx >> 1);
+            // outer x neighbours (the cell itself across a boundary face)
+            const bool hl = i > 0, hr = i + 2 < L.nx;
+            const int ql = hl ? idx - 1 : idx, qr = hr ? idx + 2 : idx + 1;
+            double phl, mul, pl, phr, mur, pr;
+            u_one(ql, phl, mul, pl);
+            u_one(qr, phr, mur, pr);
+            const double psl = gload(L.pstar, ql), psr = gload(L.pstar, qr);
+            // y (and z) neighbour pairs: -y, +y (, -z, +z)
+            constexpr int NP = 2 * (DIM - 1);
+            D2 phn[NP], mun[NP], pn[NP], psn[NP];
+            bool hn[NP];
+            {
+                const int sz = L.nx * L.ny;
+                const int off[4] = {-L.nx, L.nx, -sz, sz};
+                const bool has[4] = {j > 0, j < L.ny - 1, k > 0, k < L.nz - 1};
+#pragma unroll
+                for (int f = 0; f < NP; ++f) {
+                    hn[f] = has[f];
+                    const int q = has[f] ? idx + off[f] : idx;
+                    u_pair(q, phn[f], mun[f], pn[f]);
+                    psn[f] = gload(reinterpret_cast<const D2*>(L.pstar), q >> 1);
+                }
+            }
+            struct Sums {
+                double smm = 0, sap = 0, sphi = 0, sp = 0, samu = 0;
+            };
+            auto face = [&](Sums& s, bool h, double ph0, double mu0, double p0, double ps0,
+                            double ph1, double mu1, double p1, double ps1) {
+                const double a = 0.5 * (ps0 + ps1);
                 const double m = 1.0 + L.gamma * a * a;
-                const double dmu = mun - muc;
-                const double dp = pn - pc;
-                const double dphi = phn - phic;
-                smm = h ? smm + m * dmu : smm;
-                sap = h ? sap + a * dp : sap;
-                sphi = h ? sphi + dphi : sphi;
-                sp = h ? sp + dp : sp;
-                samu = h ? samu + a * dmu : samu;
-            });
-            const double psi = L.psi[idx];
-            const double r0 = psi - (phic - L.lam * smm - L.lam * sap);
-            const double r1 = L.f1[idx] - (muc - nonlin<double, false>(phic, psi, 0.0) + L.kap * sphi);
-            const double r2 = -(L.lam * sp + L.lam * L.gamma * samu);
-            L.phi_alt[idx] = phic;
-            L.mu_alt[idx] = muc;
-            L.p_alt[idx] = pc;
-            E.f0[idx] = float(r0);
-            E.f1[idx] = float(r1);
-            E.f2[idx] = float(r2);
-            E.b[idx] = float(phic);
-            v[0] = r0 * r0;
-            v[1] = r1 * r1;
-            v[2] = r2 * r2;
-            v[3] = pc;
+                const double dmu = mu1 - mu0;
+                const double dp = p1 - p0;
+                const double dphi = ph1 - ph0;
+                s.smm = h ? s.smm + m * dmu : s.smm;
+                s.sap = h ? s.sap + a * dp : s.sap;
+                s.sphi = h ? s.sphi + dphi : s.sphi;
+                s.sp = h ? s.sp + dp : s.sp;
+                s.samu = h ? s.samu + a * dmu : s.samu;
+            };
+            Sums sa, sb;
+            face(sa, hl, phc.x, muc.x, pc.x, psc.x, phl, mul, pl, psl);
+            face(sa, true, phc.x, muc.x, pc.x, psc.x, phc.y, muc.y, pc.y, psc.y);
+            face(sb, true, phc.y, muc.y, pc.y, psc.y, phc.x, muc.x, pc.x, psc.x);
+            face(sb, hr, phc.y, muc.y, pc.y, psc.y, phr, mur, pr, psr);
+#pragma unroll
+            for (int f = 0; f < NP; ++f) {
+                face(sa, hn[f], phc.x, muc.x, pc.x, psc.x, phn[f].x, mun[f].x, pn[f].x, psn[f].x);
+                face(sb, hn[f], phc.y, muc.y, pc.y, psc.y, phn[f].y, mun[f].y, pn[f].y, psn[f].y);
+            }
+            const D2 psi = gload(reinterpret_cast<const D2*>(L.psi), idx >> 1);
+            const D2 f1 = gload(reinterpret_cast<const D2*>(L.f1), idx >> 1);
+            auto resid = [&](const Sums& s, double ph, double mu, double pp, double ps, double f,
+                             double& r0, double& r1, double& r2) {
+                r0 = ps - (ph - L.lam * s.smm - L.lam * s.sap);
+                r1 = f - (mu - nonlin<double, false>(ph, ps, 0.0) + L.kap * s.sphi);
+                r2 = -(L.lam * s.sp + L.lam * L.gamma * s.samu);
+            };
+            double ra0, ra1, ra2, rb0, rb1, rb2;
+            resid(sa, phc.x, muc.x, pc.x, psi.x, f1.x, ra0, ra1, ra2);
+            resid(sb, phc.y, muc.y, pc.y, psi.y, f1.y, rb0, rb1, rb2);
+            const int h = idx >> 1;
+            gstore(reinterpret_cast<D2*>(L.phi_alt), h, phc);
+            gstore(reinterpret_cast<D2*>(L.mu_alt), h, muc);
+            gstore(reinterpret_cast<D2*>(L.p_alt), h, pc);
+            gstore(reinterpret_cast<F2*>(E.f0), h, F2{float(ra0), float(rb0)});
+            gstore(reinterpret_cast<F2*>(E.f1), h, F2{float(ra1), float(rb1)});
+            gstore(reinterpret_cast<F2*>(E.f2), h, F2{float(ra2), float(rb2)});
+            gstore(reinterpret_cast<F2*>(E.b), h, F2{float(phc.x), float(phc.y)});
+            v[0] = ra0 * ra0 + rb0 * rb0;
+            v[1] = ra1 * ra1 + rb1 * rb1;
+            v[2] = ra2 * ra2 + rb2 * rb2;
+            v[3] = pc.x + pc.y;
         }
-    } else if (add) {
+    } else if (add && idx < L.n) {
         // an instance that has converged keeps its iterate in both copies, so
         // that it is still the current one after the step flips the copies
-        const Level<double> L = view_at(b64, tk.inst, 0, b64.cur);
-        const int idx = tk.cell0 + threadIdx.x;
-        if (idx < L.n) {
-            L.phi_alt[idx] = L.phi[idx];
-            L.mu_alt[idx] = L.mu[idx];
-            L.p_alt[idx] = L.p[idx];
-        }
+        const int h = idx >> 1;
+        gstore(reinterpret_cast<D2*>(L.phi_alt), h, gload(reinterpret_cast<const D2*>(L.phi), h));
+        gstore(reinterpret_cast<D2*>(L.mu_alt), h, gload(reinterpret_cast<const D2*>(L.mu), h));
+        gstore(reinterpret_cast<D2*>(L.p_alt), h, gload(reinterpret_cast<const D2*>(L.p), h));
     }
     double out[4];
-    block_sum<4>(v, out);
+    block_sum<4, kPairThreads>(v, out);
     if (threadIdx.x == 0)
-        for (int c = 0; c < 4; ++c) partial[blockIdx.x * kPartialStride + c] = out[c];
+        for (int c = 0; c < 4; ++c) partial[task * kPartialStride + c] = out[c];
 }
 
 // ---- deterministic reductions --------------------------------------------------------
 
-template <int NC>
+template <int NC, int NT>
 __device__ __forceinline__ void block_sum(double (&v)[NC], double* out) {
     for (int off = 32; off > 0; off >>= 1)
         for (int c = 0; c < NC; ++c) v[c] += __shfl_xor(v[c], off, 64);
-    __shared__ double sh[NC][kBlock / 64];
+    __shared__ double sh[NC][NT / 64];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     if (lane == 0)
         for (int c = 0; c < NC; ++c) sh[c][wid] = v[c];
@@ -366,7 +450,7 @@ __device__ __forceinline__ void block_sum(double (&v)[NC], double* out) {
     if (threadIdx.x == 0)
         for (int c = 0; c < NC; ++c) {
             double s = 0.0;
-            for (int w = 0; w < kBlock / 64; ++w) s += sh[c][w];
+            for (int w = 0; w < NT / 64; ++w) s += sh[c][w];
             out[c] = s;
         }
     __syncthreads();
@@ -387,7 +471,8 @@ template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_residual_partials(Batch<double> b,
                                                               const CellTask* __restrict__ t,
                                                               double* partial) {
-    const CellTask tk = t[blockIdx.x];
+    const int task = xcd_task();
+    const CellTask tk = t[task];
     double v[4] = {0.0, 0.0, 0.0, 0.0};
     if (!inactive(b.active, tk.inst)) {
         const Level<double> L = view_at(b, tk.inst, 0, b.cur);
@@ -407,7 +492,7 @@ __global__ __launch_bounds__(kBlock) void k_residual_partials(Batch<double> b,
     double out[4];
     block_sum<4>(v, out);
     if (threadIdx.x == 0)
-        for (int c = 0; c < 4; ++c) partial[blockIdx.x * kPartialStride + c] = out[c];
+        for (int c = 0; c < 4; ++c) partial[task * kPartialStride + c] = out[c];
 }
 
 // Sums runs of consecutive norm partials of one instance into one partial, so
@@ -471,7 +556,8 @@ __global__ __launch_bounds__(kBlock) void k_inst_reduce(const double* __restrict
 
 __global__ __launch_bounds__(kBlock) void k_shift_p(Batch<double> b, const CellTask* __restrict__ t,
                                                     const double* __restrict__ res) {
-    const CellTask tk = t[blockIdx.x];
+    const int task = xcd_task();
+    const CellTask tk = t[task];
     if (inactive(b.active, tk.inst)) return;
     const Level<double> L = view_at(b, tk.inst, 0, b.cur);
     const int idx = tk.cell0 + threadIdx.x;
@@ -486,7 +572,8 @@ __global__ __launch_bounds__(kBlock) void k_energy_partials(Batch<double> b,
                                                             int ws, const double* __restrict__ phi_c,
                                                             const double* __restrict__ q_c,
                                                             double* partial) {
-    const CellTask tk = t[blockIdx.x];
+    const int task = xcd_task();
+    const CellTask tk = t[task];
     const Level<double> L = view_at(b, tk.inst, 0, b.cur);
     const int off = info[tk.inst].off;
     const double gamma = L.gamma;
@@ -527,7 +614,7 @@ __global__ __launch_bounds__(kBlock) void k_energy_partials(Batch<double> b,
     block_sum<8>(v, out);
     const double m = block_max(vmax);
     if (threadIdx.x == 0) {
-        double* pp = partial + blockIdx.x * kPartialStride;
+        double* pp = partial + task * kPartialStride;
         for (int c = 0; c < 8; ++c) pp[c] = out[c];
         pp[8] = m;
     }
@@ -567,7 +654,8 @@ __global__ __launch_bounds__(kBlock) void k_copy_out(Batch<double> b, const Cell
                                                      const InstInfo* __restrict__ info,
                                                      double* phi_prev, double* phi_cur, double* mu,
                                                      double* p) {
-    const CellTask tk = t[blockIdx.x];
+    const int task = xcd_task();
+    const CellTask tk = t[task];
     const Level<double> L = view_at(b, tk.inst, 0, b.cur);
     const int idx = tk.cell0 + threadIdx.x;
     if (idx >= L.n) return;
@@ -588,7 +676,8 @@ __global__ __launch_bounds__(kBlock) void k_get_solution(Batch<double> b,
                                                          const CellTask* __restrict__ t,
                                                          const InstInfo* __restrict__ info,
                                                          double* phi, double* mu, double* p) {
-    const CellTask tk = t[blockIdx.x];
+    const int task = xcd_task();
+    const CellTask tk = t[task];
     const Level<double> L = view_at(b, tk.inst, 0, b.cur);
     const int idx = tk.cell0 + threadIdx.x;
     if (idx >= L.n) return;
@@ -702,7 +791,13 @@ void launch_zero_correction(const Batch<float>& b32, const CellTask* t, int nt, 
 
 void launch_mixed_residual(int dim, const Batch<double>& b64, const Batch<float>& b32,
                            const CellTask* t, int nt, int add, double* partial, hipStream_t st) {
-    CHHS_DISPATCH(dim, k_mixed_residual, nt, b64, b32, t, add, partial);
+    if (nt <= 0) return;
+    if (dim == 2)
+        hipLaunchKernelGGL(k_mixed_residual<2>, dim3(nt), dim3(kPairThreads), 0, st, b64, b32, t,
+                           add, partial);
+    else
+        hipLaunchKernelGGL(k_mixed_residual<3>, dim3(nt), dim3(kPairThreads), 0, st, b64, b32, t,
+                           add, partial);
 }
 
 void launch_residual_partials(int dim, const Batch<double>& b, const CellTask* t, int nt,
