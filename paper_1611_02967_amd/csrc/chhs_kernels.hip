@@ -223,6 +223,59 @@ __global__ __launch_bounds__(kBlock) void k_restrict_residual(Batch<T> b,
     C.fr2[idx] = sr2 * w;
 }
 
+// Launches of at most this many tasks use the lane-parallel restriction below
+// (3D 128^3 FP64: the launches into 32^3, 16^3 and 8^3 take 10.5, 4.8 and 5.0
+// us against 15.1, 13.6 and 12.5 with the serial loop; into 64^3, 1024 tasks,
+// the serial loop is faster).
+constexpr int kLaneRestrictTasks = 256;
+
+// The same for levels with few coarse cells, where the serial loop over the
+// children above is the latency of the launch.  One thread per
+// (coarse cell, child): the 2^DIM children of a coarse cell are consecutive
+// lanes, summed by lane exchanges in the fixed order ((c0 + c1) + (c2 + c3))
+// [+ the same for c4 .. c7 in 3D].  A workgroup covers 256 / 2^DIM coarse
+// cells of a task, so a launch has 2^DIM workgroups per task.
+template <int DIM, typename T, bool CORR>
+__global__ __launch_bounds__(kBlock) void k_restrict_residual_lanes(Batch<T> b,
+                                                                    const CellTask* __restrict__ t) {
+    constexpr int NCH = DIM == 3 ? 8 : 4;
+    const int w = xcd_task();
+    const CellTask tk = t[w / NCH];
+    if (inactive(b.active, tk.inst)) return;
+    const Level<T> F = view_at(b, tk.inst, b.level, b.cur);
+    const Level<T> C = view_at(b, tk.inst, b.level + 1, b.cur_c);
+    const int q = tk.cell0 + (w % NCH) * (kBlock / NCH) + int(threadIdx.x) / NCH;
+    const int ch = int(threadIdx.x) % NCH;
+    // every lane of a child group computes (a group past the level's end on
+    // coarse cell 0), so that the exchanges read only computing lanes
+    const bool live = q < C.n;
+    const int idx = live ? q : 0;
+    int ci, cj, ck;
+    decode<DIM>(idx, C.nx, C.ny, ci, cj, ck);
+    const int fi = 2 * ci + (ch & 1), fj = 2 * cj + ((ch >> 1) & 1), fk = 2 * ck + (ch >> 2);
+    const int f = (fk * F.ny + fj) * F.nx + fi;
+    T n0, n1, n2;
+    cell_operator<DIM, T, CORR>(F, f, fi, fj, fk, n0, n1, n2);
+    T v[7] = {F.f0[f] - n0, F.f1[f] - n1, F.f2[f] - n2, F.phi[f], F.mu[f], F.p[f],
+              CORR ? F.b[f] : T(0)};
+#pragma unroll
+    for (int c = 0; c < 7; ++c) {
+        if (!CORR && c == 6) continue;
+        v[c] += __shfl_xor(v[c], 1, 64);
+        v[c] += __shfl_xor(v[c], 2, 64);
+        if (DIM == 3) v[c] += __shfl_xor(v[c], 4, 64);
+    }
+    if (!live || ch != 0) return;
+    const T wt = DIM == 3 ? T(0.125) : T(0.25);
+    if (CORR) C.b[idx] = v[6] * wt;
+    C.phi[idx] = C.ub0[idx] = v[3] * wt;
+    C.mu[idx] = C.ub1[idx] = v[4] * wt;
+    C.p[idx] = C.ub2[idx] = v[5] * wt;
+    C.fr0[idx] = v[0] * wt;
+    C.fr1[idx] = v[1] * wt;
+    C.fr2[idx] = v[2] * wt;
+}
+
 // tasks over coarse cells: f_c += N_c(u_c)
 template <int DIM, typename T, bool CORR>
 __global__ __launch_bounds__(kBlock) void k_coarse_rhs(Batch<T> b,
@@ -756,7 +809,10 @@ void launch_smooth_color(int dim, const Batch<double>& b, const CellTask* t, int
 }
 void launch_restrict_residual(int dim, const Batch<double>& b, const CellTask* t, int nt,
                               hipStream_t st) {
-    CHHS_DISPATCH_T(dim, k_restrict_residual, nt, b, t);
+    if (nt <= kLaneRestrictTasks)
+        CHHS_DISPATCH_T(dim, k_restrict_residual_lanes, nt * (dim == 3 ? 8 : 4), b, t);
+    else
+        CHHS_DISPATCH_T(dim, k_restrict_residual, nt, b, t);
 }
 void launch_coarse_rhs(int dim, const Batch<double>& b, const CellTask* t, int nt, hipStream_t st) {
     CHHS_DISPATCH_T(dim, k_coarse_rhs, nt, b, t);
@@ -773,7 +829,10 @@ void launch_smooth_color(int dim, const Batch<float>& b, const CellTask* t, int 
 }
 void launch_restrict_residual(int dim, const Batch<float>& b, const CellTask* t, int nt,
                               hipStream_t st) {
-    CHHS_DISPATCH_T(dim, k_restrict_residual, nt, b, t);
+    if (nt <= kLaneRestrictTasks)
+        CHHS_DISPATCH_T(dim, k_restrict_residual_lanes, nt * (dim == 3 ? 8 : 4), b, t);
+    else
+        CHHS_DISPATCH_T(dim, k_restrict_residual, nt, b, t);
 }
 void launch_coarse_rhs(int dim, const Batch<float>& b, const CellTask* t, int nt, hipStream_t st) {
     CHHS_DISPATCH_T(dim, k_coarse_rhs, nt, b, t);
