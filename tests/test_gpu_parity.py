@@ -195,6 +195,23 @@ def test_one_vcycle_at_full_size_matches_oracle(chhs, n):
     assert abs(res_gpu - res_or) <= 1e-8 * res_or + 1e-14
 
 
+@pytest.mark.parametrize("shape", [(1024, 1024), (128, 128, 128)])
+def test_residual_norms_of_many_partials_match_oracle(chhs, shape):
+    """Norms of the initial guess where an instance has 4096 / 8192 per-cell
+    partials (folded in runs before the per-instance reduction): every
+    component against the oracle's h^d-weighted l2 norms."""
+    prm = _prm(shape)
+    prev, cur, mu0, p0 = _inputs(shape, 300)
+    sv = _solver(chhs, shape, prm)
+    sv.setup_step(dev(prev), dev(cur), dev(mu0), dev(p0))
+    got = sv.residual_norms()[0]
+    lvl, u = _oracle_level0(prev, cur, mu0, p0, prm)
+    r = scheme.residual(u, lvl.f, lvl, prm)
+    want = [np.sqrt(grid.ip(rk, rk, prm.h)) for rk in r] + [scheme.residual_norm(r, prm.h)]
+    for g, w in zip(got, want):
+        assert abs(g - w) <= 1e-10 * w + 1e-14, (got, want)
+
+
 def test_full_size_2048_steps_satisfy_the_scheme(chhs):
     """Bench configuration (2048^2, eps 0.01, gamma 1, s 1e-4, tol 1e-10): the GPU
     steps satisfy (2.5)-(2.7) to tol (oracle residual of the GPU output), conserve
