@@ -73,6 +73,11 @@ struct Layout {
     std::vector<FoldTask> FA0, FA0n;
     std::vector<Range> rngA0f, rngA0nf;
     int max_nlev = 0, depth = 0;
+    // the setup's restriction of phi_* and phi^m runs level by level down to
+    // chain_from, then in one workgroup per instance (levels of at most
+    // kChainCells cells in every instance)
+    int chain_from = 0;
+    std::vector<int> max_cells;
     size_t tail_lds = 0, tail_lds32 = 0;
     // offsets into the workspace
     size_t off_desc = 0, off_desc32 = 0, off_info = 0, off_tail = 0, off_rngA0 = 0, off_rngT0 = 0,
@@ -293,6 +298,10 @@ void ranges_of(std::vector<Range>& r, int n_inst, const std::vector<CellTask>& t
 // microseconds loading them one stride after another.
 constexpr int kFold = 1024;
 
+// Coarse levels whose frozen data the setup restricts in one workgroup per
+// instance (four cells per thread at most).
+constexpr int kChainCells = 4096;
+
 // Runs of kFold partials within each instance's range (relative to the
 // range's start, so an instance's sum does not depend on the batch), and the
 // ranges of the folded partials; nothing when no range is longer than kFold.
@@ -408,6 +417,8 @@ bool plan(const chhs_problem* p, int n_inst, const chhs_opts* o, char* base, Lay
         packed += cells[0];
         L.max_nlev = std::max(L.max_nlev, nlev);
         L.depth = std::max(L.depth, tail);
+        if (L.max_cells.size() < size_t(nlev)) L.max_cells.resize(nlev, 0);
+        for (int l = 0; l < nlev; ++l) L.max_cells[l] = std::max(L.max_cells[l], cells[l]);
         double h = p[i].h;
         for (int l = 0; l < nlev; ++l) {
             const int n = cells[l];
@@ -501,6 +512,12 @@ bool plan(const chhs_problem* p, int n_inst, const chhs_opts* o, char* base, Lay
                                                    : (o->smoother == 0 && l == 0 && !L.T[l].empty()));
         }
     L.snx = lnx_t;
+    L.chain_from = L.max_nlev - 1;
+    for (int l = 0; l + 1 < L.max_nlev; ++l)
+        if (L.max_cells[l + 1] <= kChainCells) {
+            L.chain_from = l;
+            break;
+        }
     L.sny = lny;
     // per-instance ranges of the finest-level partial buffers
     ranges_of(L.rngA0, n_inst, L.A[0]);
@@ -1252,13 +1269,17 @@ int setup(chhs_ctx* c, const double* phi_prev, const double* phi_cur, const doub
         if (c->mixed) {
             chhs::launch_mixed_frozen(batch(c, 0, nullptr), batch32(c, 0, nullptr), c->A[0].dev,
                                       c->A[0].n, c->stream);
-            for (int l = 0; l + 1 < c->lay.max_nlev; ++l)
+            for (int l = 0; l < c->lay.chain_from; ++l)
                 chhs::launch_restrict_frozen(dim, batch32(c, l, nullptr), c->A[l + 1].dev,
                                              c->A[l + 1].n, c->stream);
+            chhs::launch_restrict_frozen_chain(dim, c->ddesc32, c->dinfo, c->n_inst,
+                                               c->lay.chain_from, c->stream);
         } else {
-            for (int l = 0; l + 1 < c->lay.max_nlev; ++l)
+            for (int l = 0; l < c->lay.chain_from; ++l)
                 chhs::launch_restrict_frozen(dim, batch(c, l, nullptr), c->A[l + 1].dev,
                                              c->A[l + 1].n, c->stream);
+            chhs::launch_restrict_frozen_chain(dim, c->ddesc, c->dinfo, c->n_inst,
+                                               c->lay.chain_from, c->stream);
         }
     }
     if (c->mixed) {

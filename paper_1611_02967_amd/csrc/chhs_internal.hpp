@@ -157,6 +157,12 @@ void launch_restrict_frozen(int dim, const Batch<double>& b, const CellTask* t, 
                             hipStream_t st);
 void launch_restrict_frozen(int dim, const Batch<float>& b, const CellTask* t, int nt,
                             hipStream_t st);
+// The same restriction from level `from` down to each instance's coarsest
+// level, one workgroup per instance (levels below a few thousand cells).
+void launch_restrict_frozen_chain(int dim, const LevelDesc<double>* desc, const InstInfo* info,
+                                  int n_inst, int from, hipStream_t st);
+void launch_restrict_frozen_chain(int dim, const LevelDesc<float>* desc, const InstInfo* info,
+                                  int n_inst, int from, hipStream_t st);
 void launch_smooth(int dim, const Batch<double>& b, const CellTask* t, int nt, int color,
                    hipStream_t st);
 void launch_smooth(int dim, const Batch<float>& b, const CellTask* t, int nt, int color,

@@ -136,6 +136,35 @@ __global__ __launch_bounds__(kBlock) void k_restrict_frozen(Batch<T> b,
     C.psi[idx] = sph * w;
 }
 
+constexpr int kChainThreads = 1024;
+
+template <int DIM, typename T>
+__global__ __launch_bounds__(kChainThreads) void k_restrict_frozen_chain(
+    const LevelDesc<T>* __restrict__ desc, const InstInfo* __restrict__ info, int from) {
+    const int nlev = info[blockIdx.x].nlev;
+    const LevelDesc<T>* d = desc + blockIdx.x * kMaxLevels;
+    for (int l = from; l + 1 < nlev; ++l) {
+        const Level<T> F = make_view(d[l], 0);
+        const Level<T> C = make_view(d[l + 1], 0);
+        for (int idx = threadIdx.x; idx < C.n; idx += blockDim.x) {
+            int ci, cj, ck;
+            decode<DIM>(idx, C.nx, C.ny, ci, cj, ck);
+            T sps = 0, sph = 0;
+            for (int dz = 0; dz < (DIM == 3 ? 2 : 1); ++dz)
+                for (int dy = 0; dy < 2; ++dy)
+                    for (int dx = 0; dx < 2; ++dx) {
+                        const int f = ((2 * ck + dz) * F.ny + (2 * cj + dy)) * F.nx + 2 * ci + dx;
+                        sps += F.pstar[f];
+                        sph += F.psi[f];
+                    }
+            const T w = DIM == 3 ? T(0.125) : T(0.25);
+            C.pstar[idx] = sps * w;
+            C.psi[idx] = sph * w;
+        }
+        __syncthreads();
+    }
+}
+
 template <int DIM, typename T, bool CORR>
 __global__ __launch_bounds__(kBlock) void k_smooth(Batch<T> b, const CellTask* __restrict__ t,
                                                    int color) {
@@ -781,6 +810,26 @@ void launch_setup(int dim, const Batch<double>& b, const CellTask* t, int nt, co
     } while (0)
 
 #define CHHS_TARGS double
+template <typename T>
+void chain_launch(int dim, const LevelDesc<T>* desc, const InstInfo* info, int n_inst, int from,
+                  hipStream_t st) {
+    if (n_inst <= 0) return;
+    if (dim == 2)
+        hipLaunchKernelGGL((k_restrict_frozen_chain<2, T>), dim3(n_inst), dim3(kChainThreads), 0,
+                           st, desc, info, from);
+    else
+        hipLaunchKernelGGL((k_restrict_frozen_chain<3, T>), dim3(n_inst), dim3(kChainThreads), 0,
+                           st, desc, info, from);
+}
+void launch_restrict_frozen_chain(int dim, const LevelDesc<double>* desc, const InstInfo* info,
+                                  int n_inst, int from, hipStream_t st) {
+    chain_launch(dim, desc, info, n_inst, from, st);
+}
+void launch_restrict_frozen_chain(int dim, const LevelDesc<float>* desc, const InstInfo* info,
+                                  int n_inst, int from, hipStream_t st) {
+    chain_launch(dim, desc, info, n_inst, from, st);
+}
+
 void launch_restrict_frozen(int dim, const Batch<double>& b, const CellTask* t, int nt,
                             hipStream_t st) {
     CHHS_DISPATCH_T(dim, k_restrict_frozen, nt, b, t);
