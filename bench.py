@@ -1,10 +1,19 @@
 #!/usr/bin/env python3
 """Throughput of the per-step FAS solve of the second-order CHHS scheme on one GPU.
 
-One "step" is one time step of (2.4)-(2.7): setup, FAS V(2,2) cycles to the
-residual tolerance, energy/mass reductions and the state rotation, all through
-the C ABI of libchhs.  The default workload is the 2D spinodal quench on
-(0,1)^2 at 2048^2 (eps 0.01, gamma 1, s 1e-4, phi0 = 0.05 (2U - 1), FP64).
+One "step" is one time step of (2.4)-(2.7) for every instance: setup, FAS
+V(2,2) cycles to the residual tolerance, the post-step reductions (mass, E_h,
+F_h, dissipation terms) and the state rotation, all through the C ABI of
+libchhs (chhs_step_log: the reductions run every step).
+
+The default workload is the ragged batch: 64 independent 2D instances, 16 each
+of 128^2, 256^2, 512^2 and 1024^2 on (0,1)^2, eps ~ U[0.01, 0.05],
+gamma ~ U[0.5, 5], s in {1e-4, 5e-4}, phi0 = m + 0.05 (2U - 1), m ~ U[-0.3, 0.3],
+advanced together by the batched mixed-precision path (FP32 inner V-cycles,
+FP64 residual, correction and reductions, graph-replayed cycles) and, beside it,
+by the plain FP64 path as a sequential loop over single-instance contexts.
+The single-grid 2D FP64 spinodal workload at 2048^2 is measured too and
+reported under extra keys.  ``--workload`` selects another single workload.
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
@@ -22,6 +31,9 @@ if ROOT not in sys.path:
 METRIC = "FAS cell-updates/s + HBM roofline %; batched FP32+refine vs plain FP64 at tol"
 HBM_PEAK_GBS = 8000.0
 COPY_BYTES = 256 << 20
+BATCHED = "batched-64-2d-mixed"
+# worker processes of the oracle's process pool (the machine's CPU share)
+MAX_POOL = 16
 
 
 def log(msg):
@@ -48,7 +60,14 @@ def launch_bytes_per_cell(dim, cls, mixed=False):
       2D pre0  : 9 reads + 3 writes, plus u_c, ub_c, R(r), b_c (10 per 4)   = 58 B
       2D post0 : 9 reads + 3 writes, plus u_c, ub_c read (6 per 4)          = 54 B
       3D       : (4 + 7 + 3) values per 2 cells                             = 28 B
+      refine   : the FP64 refinement launch: u (FP64), e (FP32), phi_*,
+                 phi^m, f_mu (FP64) read; u + e (FP64), the three FP32
+                 right-hand sides and b written:
+                 24 + 12 + 24 + 24 + 12 + 4                                 = 100 B
+                 (88 B in the launch of the step's setup, which reads no e)
     """
+    if cls == "refine":
+        return 100.0
     if mixed:
         if dim == 2:
             return {"pre0": (12 + 10 / 4) * 4, "post0": (12 + 6 / 4) * 4}[cls]
@@ -108,37 +127,38 @@ def vcycle_bytes(dim, shape, level_kernels):
     return total
 
 
-# Sources of the finest-level 2D smoothing kernels: HBM traffic measured with
-# rocprofv3 counters is reported only while these are unchanged.
-KERNEL_SOURCES = ["chhs_stream2d.hip", "chhs_cell.hpp", "chhs_internal.hpp"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_stream2d_2048_fp64.json")
+# HBM traffic measured with rocprofv3 counters, one record per workload; a
+# record lists the sources of the kernels it covers and is reported only while
+# they hash as they did when the counters were taken.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
-def kernel_source_hash():
+def kernel_source_hash(sources):
     import hashlib
     h = hashlib.sha256()
-    for name in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_1611_02967_amd", "csrc", name), "rb") as fh:
+    for name in sources:
+        with open(os.path.join(ROOT, name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
 def measured_traffic(workload, cls, level0_kernel):
-    """Scaled FETCH_SIZE + WRITE_SIZE bytes per launch of a kernel class, from the
-    committed counter measurement, or None if it does not cover this workload,
+    """The committed counter record of a launch class of a workload: the scaled
+    FETCH_SIZE + WRITE_SIZE bytes per launch and the algorithmic bytes of the
+    same launches, or None if there is no record for this workload and class,
     the finest level runs another kernel configuration, or the kernel sources
     changed since it was taken."""
     try:
         with open(TRAFFIC_FILE) as fh:
-            rec = json.load(fh)
+            recs = json.load(fh)
     except (OSError, ValueError):
         return None
-    if rec.get("workload") != workload or rec.get("source_sha256") != kernel_source_hash():
+    rec = recs.get(workload)
+    if rec is None or rec.get("source_sha256") != kernel_source_hash(rec.get("sources", [])):
         return None
     if list(rec.get("level0_kernel", [])) != list(level0_kernel):
         return None
-    entry = rec.get("launches", {}).get(cls)
-    return None if entry is None else entry["bytes_per_launch"]
+    return rec.get("launches", {}).get(cls)
 
 
 def cpu_model():
@@ -152,8 +172,35 @@ def cpu_model():
     return platform.processor() or "unknown"
 
 
+def host_info():
+    return {"cpu": cpu_model(), "os_cpu_count": os.cpu_count(),
+            "omp_threads": os.environ.get("OMP_NUM_THREADS")}
+
+
+# ---- the oracle on the host ------------------------------------------------------------
+
+def _oracle_step(job):
+    """One oracle time step of one instance (worker of the process pool)."""
+    import numpy as np
+    from oracle import fas, scheme
+    prev, cur, mu, p, eps, gamma, s, h = job
+    prm = scheme.Params(eps=eps, gamma=gamma, s=s, h=h)
+    t0 = time.perf_counter()
+    r = fas.solve_step(prev, cur, mu, p, prm, fas.Opts(tol=1e-10))
+    return np.asarray(r.phi), r.vcycles, time.perf_counter() - t0
+
+
+def make_pool(workers):
+    """A pool of single-threaded worker processes, forked before this process
+    touches the GPU (the workers run NumPy only)."""
+    import multiprocessing as mp
+    for var in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[var] = "1"
+    return mp.get_context("fork").Pool(workers)
+
+
 def oracle_sample(phi_prev, phi_cur, mu, p, w, cycles_per_step):
-    """Time the oracle on a bounded sample of the same step: setup, one V-cycle
+    """Time the oracle on a bounded sample of one 2D step: setup, one V-cycle
     and one residual evaluation; return (cell-updates/s estimate, description)."""
     import numpy as np
     from oracle import fas, scheme
@@ -181,11 +228,33 @@ def oracle_sample(phi_prev, phi_cur, mu, p, w, cycles_per_step):
     return phi_cur.size / t_step, desc, t3 - t0
 
 
-def run_batched(args):
-    """64 independent 2D instances (16 each of 128^2, 256^2, 512^2, 1024^2, random
-    eps, gamma, s, mean) advanced together by the batched mixed-precision path
-    (FP32 inner V-cycles, FP64 residual and correction, graph replay), against
-    the plain FP64 path run as a sequential loop over single-instance contexts."""
+# ---- timing helpers ----------------------------------------------------------------------
+
+def dominant_class(tim, classes):
+    """The kernel class with the largest device time among those timed."""
+    return max(classes, key=lambda k: tim[k][0])
+
+
+def roofline_record(cls, tim, bytes_per_launch, name, traffic):
+    ms_k, n_k = tim[cls]
+    avg = ms_k / 1e3 / max(1, n_k)
+    achieved = bytes_per_launch / avg / 1e9 if n_k else 0.0
+    rec = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4),
+           "traffic": None if traffic is None else traffic["bytes_per_launch"],
+           "kernel": name, "avg_launch_us": round(avg * 1e6, 2), "launches": n_k,
+           "algorithmic_bytes_per_launch": round(bytes_per_launch)}
+    if traffic is not None:
+        rec["traffic_record"] = traffic
+    return rec
+
+
+# ---- the batched workload ----------------------------------------------------------------
+
+def run_batched(args, pool):
+    """64 ragged 2D instances by the batched mixed-precision path, against the
+    plain FP64 path as a sequential loop over single-instance contexts (same
+    library, same inputs, the reductions every step on both sides)."""
     import numpy as np
     import torch
     from paper_1611_02967_amd import chhs
@@ -196,66 +265,121 @@ def run_batched(args):
     phi0s = [it.phi0() for it in insts]
     sizes = [int(np.prod(it.shape)) for it in insts]
     cells = sum(sizes)
-    offs = np.concatenate([[0], np.cumsum(sizes)])
-    log(f"batched: {len(insts)} instances, {cells} cells")
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(int)
+    log(f"{BATCHED}: {len(insts)} instances, {cells} cells")
 
     flat = np.concatenate([a.ravel() for a in phi0s])
     tp = torch.from_numpy(flat).cuda()
     tc = tp.clone()
     tm = torch.zeros_like(tp)
     tpp = torch.zeros_like(tp)
+    # the warm-up steps time the finest-level FP32 smoothing launches and the
+    # FP64 refinement launch; the timed region times only the dominant one
+    cand = ("pre0", "post0", "refine")
     sv = chhs.Solver(probs, chhs.chhs_default_opts(tol=1e-10, precision=1,
-                                                   timing=chhs.timing_mask("pre0", "post0"),
+                                                   timing=chhs.timing_mask(*cand),
                                                    smoother=args.smoother,
                                                    autotune=int(args.autotune)))
     for k in range(args.warmup):
-        _, st = sv.step(tp, tc, tm, tpp, 1)
-        log(f"warmup step {k + 1}/{args.warmup}: max {max(x['vcycles'] for x in st)} refinement steps")
+        _, lg = sv.step_log(tp, tc, tm, tpp, 1)
+        log(f"warmup step {k + 1}/{args.warmup}: max {max(x['vcycles'] for x in lg[0])} "
+            f"refinement steps")
+    tim_w = sv.timing(reset=True)
+    cls = dominant_class(tim_w, cand)
+    sv.set_timing(chhs.timing_mask(cls))
+    torch.cuda.synchronize()
     start = [t.clone() for t in (tp, tc, tm, tpp)]
-    sv.timing(reset=True)
+    start_host = [t.cpu().numpy() for t in start]
+
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    _, st = sv.step(tp, tc, tm, tpp, args.steps)
+    _, lg = sv.step_log(tp, tc, tm, tpp, args.steps)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     tim = sv.timing()
-    refine = sum(x["total_vcycles"] for x in st)
-    log(f"batched mixed: {args.steps} steps in {elapsed:.3f}s, {refine} instance refinement steps")
+    refine = [[rec["vcycles"] for rec in step] for step in lg]
+    total_refine = sum(sum(r) for r in refine)
+    log(f"batched mixed: {args.steps} steps in {elapsed:.3f}s, {total_refine} instance "
+        f"refinement steps")
+    f_ok = all(lg[m][i]["F_h"] <= (lg[m - 1][i]["F_h"] if m else np.inf) + 1e-12
+               for m in range(len(lg)) for i in range(len(insts)))
 
-    # sequential plain FP64: one context per instance, one step each in turn
-    seq = []
-    for i, pr in enumerate(probs):
-        o = chhs.chhs_default_opts(tol=1e-10, precision=0, smoother=args.smoother,
-                                   autotune=int(args.autotune))
-        seq.append(chhs.Solver(pr, o))
+    # algorithmic bytes of the timed class's launches in the timed region: each
+    # launch covers the instances still active in that refinement step
+    if cls == "refine":
+        per_launch_cells = cells * args.steps * 88 + sum(
+            sizes[i] * refine[m][i] for m in range(args.steps) for i in range(len(insts))) * 100
+        bytes_launch = per_launch_cells / max(1, tim[cls][1])
+        name = ("finest-level FP64 refinement launch over the batch (u += e, residual of "
+                "(2.5)-(2.7), FP32 right-hand side and base state, norm partials)")
+    else:
+        active_cells = sum(sizes[i] * refine[m][i] for m in range(args.steps)
+                           for i in range(len(insts)))
+        bytes_launch = launch_bytes_per_cell(2, cls, mixed=True) * active_cells / max(1, tim[cls][1])
+        name = (f"finest-level FP32 {'pre' if cls == 'pre0' else 'post'}-smoothing launch "
+                f"over the batch (correction form)")
+    level_kernels = [list(k) for k in sv.level_kernels()]
+    traffic = measured_traffic(BATCHED, cls, level_kernels[0])
+    roofline = roofline_record(cls, tim, bytes_launch, name, traffic)
+    others = {}
+    for k in cand:
+        if k != cls and tim_w[k][1]:
+            others[k] = {"avg_launch_us_warmup": round(tim_w[k][0] / tim_w[k][1] * 1e3, 2),
+                         "launches_warmup": tim_w[k][1]}
+    roofline["other_classes"] = others
+
+    # per-class device time per step from the same start state, every class
+    # timed (outside the timed region)
+    kernel_ms = {}
+    if not args.no_breakdown:
+        sb = chhs.Solver(probs, chhs.chhs_default_opts(tol=1e-10, precision=1, timing=1,
+                                                       smoother=args.smoother,
+                                                       autotune=int(args.autotune)))
+        st_b = [t.clone() for t in start]
+        sb.step_log(*st_b, 1)
+        sb.timing(reset=True)
+        nb = 2
+        sb.step_log(*st_b, nb)
+        kernel_ms = {k: round(v[0] / nb, 4) for k, v in sb.timing().items() if v[1]}
+        sb.close()
+        del st_b
+
+    # the sequential plain FP64 loop: one context per instance, one step each
+    # per round, with the reductions every step
+    seq = [chhs.Solver(pr, chhs.chhs_default_opts(tol=1e-10, precision=0, smoother=args.smoother,
+                                                  autotune=int(args.autotune)))
+           for pr in probs]
     views = lambda ts, i: [t[offs[i]:offs[i + 1]] for t in ts]
     sp = [t.clone() for t in start]
     for i, s1 in enumerate(seq):       # warm-up: one step each (graph capture)
-        s1.step(*[v.clone() for v in views(sp, i)], 1)
+        s1.step_log(*[v.clone() for v in views(sp, i)], 1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    seq_cycles = 0
     for _ in range(args.steps):
         for i, s1 in enumerate(seq):
-            s1.step(*views(sp, i), 1)
+            _, lq = s1.step_log(*views(sp, i), 1)
+            seq_cycles += lq[0][0]["vcycles"]
     torch.cuda.synchronize()
     elapsed_seq = time.perf_counter() - t0
-    log(f"sequential fp64: {args.steps} rounds in {elapsed_seq:.3f}s")
+    log(f"sequential fp64: {args.steps} rounds in {elapsed_seq:.3f}s, {seq_cycles} V-cycles")
 
-    # error of the batched mixed step against the FP64 path from the same state
+    # one step of both paths from the timed region's start state
     a = [t.clone() for t in start]
     sv.step(*a, 1)
+    mixed_phi = a[1].cpu().numpy()
     err = 0.0
+    fp64_phi = []
     for i, s1 in enumerate(seq):
         b = [v.clone() for v in views(start, i)]
         s1.step(*b, 1)
-        err = max(err, float((a[1][offs[i]:offs[i + 1]] - b[1]).abs().max()))
+        fp64_phi.append(b[1].cpu().numpy())
+        err = max(err, float(np.max(np.abs(mixed_phi[offs[i]:offs[i + 1]] - fp64_phi[i]))))
     log(f"max |phi_mixed - phi_fp64| over instances after one step: {err:.2e}")
+    for s1 in seq:
+        s1.close()
+    sv.close()
 
-    cls = max(("pre0", "post0"), key=lambda k: tim[k][0])
-    ms_k, n_k = tim[cls]
-    avg = ms_k / 1e3 / max(1, n_k)
-    b_launch = launch_bytes_per_cell(2, cls, mixed=True) * cells
-    achieved = b_launch / avg / 1e9 if n_k else 0.0
     inst_steps = len(insts) * args.steps
     out = {
         "metric": METRIC,
@@ -265,79 +389,88 @@ def run_batched(args):
         "ms_per_step": elapsed / args.steps * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32+f64", "data": "synthetic",
-        "config": {"workload": "batched-64-2d-mixed", "instances": len(insts),
-                   "grids": [128, 256, 512, 1024], "cells": cells, "tol": 1e-10,
-                   "cycle": "V(2,2)", "precision": "fp32 inner + fp64 refinement"},
+        "config": {"workload": BATCHED, "instances": len(insts),
+                   "grids": [128, 256, 512, 1024], "cells": cells, "eps": "U[0.01,0.05]",
+                   "gamma": "U[0.5,5]", "s": "{1e-4,5e-4}", "tol": 1e-10, "cycle": "V(2,2)",
+                   "precision": "fp32 inner + fp64 refinement",
+                   "reductions": "mass, E_h, F_h, dissipation every step"},
         "instance_steps_per_s": inst_steps / elapsed,
-        "refinement_steps": refine,
-        "sequential_fp64": {"instance_steps_per_s": inst_steps / elapsed_seq,
-                            "cell_updates_per_s": cells * args.steps / elapsed_seq,
-                            "ms_per_round": elapsed_seq / args.steps * 1e3},
+        "refinement_steps_per_instance_step": total_refine / inst_steps,
+        "sequential_fp64": {"value": cells * args.steps / elapsed_seq,
+                            "unit": "cell-updates/s",
+                            "instance_steps_per_s": inst_steps / elapsed_seq,
+                            "ms_per_round": elapsed_seq / args.steps * 1e3,
+                            "vcycles_per_instance_step": seq_cycles / inst_steps},
         "speedup_vs_sequential_fp64": elapsed_seq / elapsed,
-        "level_kernels": [list(k) for k in sv.level_kernels()],
         "max_abs_err_phi_vs_fp64": err,
-        "kernel_ms_timed": {k: round(v[0], 3) for k, v in tim.items() if v[1]},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": f"finest-level FP32 {'pre' if cls == 'pre0' else 'post'}-smoothing launch over the batch",
-                     "avg_launch_us": round(avg * 1e6, 2), "launches": n_k,
-                     "algorithmic_bytes_per_launch": b_launch},
+        "energy_F_nonincreasing": bool(f_ok),
+        "level_kernels": level_kernels,
+        "kernel_ms_per_step": kernel_ms,
+        "roofline": roofline,
     }
-    print(json.dumps(out), flush=True)
+
+    if pool is not None:
+        # the oracle: one time step of instances 0..7 (two of each grid size)
+        # from the timed region's start state, in the process pool
+        sample = list(range(8))
+        jobs = []
+        for i in sample:
+            it = insts[i]
+            sl = slice(offs[i], offs[i + 1])
+            jobs.append(tuple(x[sl].reshape(it.shape).copy() for x in start_host)
+                        + (it.eps, it.gamma, it.s, it.h))
+        log(f"timing the oracle: one step of instances {sample[0]}..{sample[-1]} in a pool of "
+            f"{pool._processes} processes")
+        import resource
+        ru0 = resource.getrusage(resource.RUSAGE_CHILDREN)
+        t0 = time.perf_counter()
+        res = pool.map(_oracle_step, jobs, chunksize=1)
+        wall = time.perf_counter() - t0
+        ru1 = resource.getrusage(resource.RUSAGE_CHILDREN)
+        worker_s = sum(r[2] for r in res)
+        sample_cells = sum(sizes[i] for i in sample)
+        err_or = max(float(np.max(np.abs(mixed_phi[offs[i]:offs[i + 1]] - res[k][0].ravel())))
+                     for k, i in enumerate(sample))
+        err_or64 = max(float(np.max(np.abs(fp64_phi[i] - res[k][0].ravel())))
+                       for k, i in enumerate(sample))
+        out["cpu_baseline"] = {
+            "value": sample_cells / wall, "unit": "cell-updates/s", "cores": pool._processes,
+            "kind": "oracle",
+            "sample": (f"one time step (FAS V(2,2) to tol 1e-10) of instances {sample[0]}-"
+                       f"{sample[-1]} of the batch ({sample_cells} cells: two each of 128^2, "
+                       f"256^2, 512^2, 1024^2) from the timed region's start state, single-threaded "
+                       f"NumPy per process, {pool._processes} processes; value = cells / wall"),
+            "wall_s": round(wall, 2), "worker_cpu_s": round(worker_s, 2),
+            "children_cpu_s": round((ru1.ru_utime + ru1.ru_stime) - (ru0.ru_utime + ru0.ru_stime), 2),
+            "host": host_info()}
+        out["parity"] = {"instances": sample, "steps": 1,
+                         "max_abs_err_phi_mixed_vs_oracle": err_or,
+                         "max_abs_err_phi_fp64_vs_oracle": err_or64}
+        log(f"oracle: {sample_cells / wall:.3e} cell-updates/s ({wall:.1f}s wall); "
+            f"max|phi_mixed - oracle| = {err_or:.2e}, max|phi_fp64 - oracle| = {err_or64:.2e}")
+    return out
 
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__)
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="2d-2048-fp64")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-parity", action="store_true")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="before the timed region, copy a 256 MiB device buffer three times "
-                         "(the known-size kernel that scales rocprofv3 FETCH_SIZE / WRITE_SIZE)")
-    ap.add_argument("--no-breakdown", action="store_true",
-                    help="skip the per-class timing pass after the timed region")
-    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
-                    help="use the default smoothing kernels instead of letting chhs_init time "
-                         "the candidates per level and keep the fastest")
-    ap.add_argument("--smoother", type=int, default=0,
-                    help="2D smoother: 0 default (strips on the finest level), 1 tiles, 2 strips")
-    args = ap.parse_args()
+# ---- one grid ---------------------------------------------------------------------------
 
-    if args.gpus != 1:
-        print(f"bench.py: this build runs one GPU only (--gpus {args.gpus} requested); "
-              "the batched and single-grid paths are measured on one MI355X", file=sys.stderr)
-        sys.exit(2)
-
+def run_single(args, name, cpu_baseline=True, parity=True, breakdown=True, copy_calibration=False):
+    """One named workload (one grid) through chhs_step_log; returns the record."""
     import numpy as np
     import torch
-
-    from paper_1611_02967_amd import build as _build
-    if not os.path.exists(_build.LIB):
-        log("libchhs.so missing: building")
-        _build.build()
     from paper_1611_02967_amd import chhs
     from workloads import WORKLOADS, uniform_field
 
-    assert torch.cuda.is_available(), "bench.py needs a HIP device"
-    if args.workload == "batched-64-2d-mixed":
-        run_batched(args)
-        return
-    w = WORKLOADS[args.workload]
+    w = WORKLOADS[name]
     n, dim = w["n"], w["dim"]
     shape = (n,) * dim
     cells = n ** dim
-    log(f"workload {args.workload}: {shape}, eps {w['eps']}, gamma {w['gamma']}, s {w['s']}")
+    log(f"workload {name}: {shape}, eps {w['eps']}, gamma {w['gamma']}, s {w['s']}")
 
     phi0 = uniform_field(shape, w["seed"], mean=w["mean"], amp=0.05)
     prob = chhs.make_problem(shape, 1.0 / n, w["eps"], w["gamma"], w["s"])
-    mixed = args.workload.endswith("-mixed")
-    # only finest-level smoothing launches carry HIP events (each event pair
-    # delays the following launch by a few us): both classes in the warm-up
-    # steps, then only the dominant one in the timed region
-    opts = chhs.chhs_default_opts(tol=1e-10, timing=chhs.timing_mask("pre0", "post0"),
+    mixed = name.endswith("-mixed")
+    cand = ("pre0", "post0", "refine") if mixed else ("pre0", "post0")
+    opts = chhs.chhs_default_opts(tol=1e-10, timing=chhs.timing_mask(*cand),
                                   smoother=args.smoother, precision=1 if mixed else 0,
                                   autotune=int(args.autotune))
     sv = chhs.Solver(prob, opts)
@@ -347,9 +480,10 @@ def main():
     tpp = torch.zeros_like(tp)
 
     for k in range(args.warmup):
-        _, st = sv.step(tp, tc, tm, tpp, 1)
-        log(f"warmup step {k + 1}/{args.warmup}: {st[0]['vcycles']} V-cycles, res {st[0]['res_norm']:.2e}")
-    if args.copy_calibration:
+        _, lg = sv.step_log(tp, tc, tm, tpp, 1)
+        log(f"warmup step {k + 1}/{args.warmup}: {lg[0][0]['vcycles']} V-cycles, "
+            f"res {lg[0][0]['res_norm']:.2e}")
+    if copy_calibration:
         src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(3):
@@ -359,60 +493,57 @@ def main():
         del src, dst
     torch.cuda.synchronize()
     start_state = [t.cpu().numpy() for t in (tp, tc, tm, tpp)]
-    # dominant finest-level kernel class by device time in the warm-up steps
     tim_w = sv.timing(reset=True)
-    cls = max(("pre0", "post0"), key=lambda k: tim_w[k][0])
+    cls = dominant_class(tim_w, cand)
     sv.set_timing(chhs.timing_mask(cls))
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    _, st = sv.step(tp, tc, tm, tpp, args.steps)
+    _, lg = sv.step_log(tp, tc, tm, tpp, args.steps)
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    elapsed = t1 - t0
+    elapsed = time.perf_counter() - t0
     tim = sv.timing()
-    s0 = st[0]
-    vcyc = s0["total_vcycles"]
-    log(f"timed {args.steps} steps in {elapsed:.3f}s, {vcyc} V-cycles, last res {s0['res_norm']:.2e}")
+    vcyc = sum(step[0]["vcycles"] for step in lg)
+    log(f"timed {args.steps} steps in {elapsed:.3f}s, {vcyc} V-cycles, last res "
+        f"{lg[-1][0]['res_norm']:.2e}")
 
-    ms_k, n_k = tim[cls]
-    avg_launch_s = ms_k / 1e3 / max(1, n_k)
-    bytes_launch = launch_bytes_per_cell(dim, cls, mixed) * cells
-    achieved = bytes_launch / avg_launch_s / 1e9 if n_k else 0.0
     names = {"pre0": "finest-level pre-smoothing launch" + (
                  " (2 fused red-black steps + residual + restriction)" if dim == 2 else " (one color)"),
              "post0": "finest-level post-smoothing launch" + (
-                 " (prolongation + 2 fused red-black steps + residual norm)" if dim == 2 else " (one color)")}
+                 " (prolongation + 2 fused red-black steps + residual norm)" if dim == 2 else " (one color)"),
+             "refine": "finest-level FP64 refinement launch"}
+    if cls == "refine":
+        bytes_launch = (cells * 88 * args.steps + cells * 100 * vcyc) / max(1, tim[cls][1])
+    else:
+        bytes_launch = launch_bytes_per_cell(dim, cls, mixed) * cells
     level_kernels = sv.level_kernels()
-    traffic = measured_traffic(args.workload, cls, level_kernels[0])
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": names[cls], "avg_launch_us": round(avg_launch_s * 1e6, 2),
-                "launches": n_k, "algorithmic_bytes_per_launch": bytes_launch}
-    other = "post0" if cls == "pre0" else "pre0"
-    if tim_w[other][1]:
-        avg_o = tim_w[other][0] / 1e3 / tim_w[other][1]
-        b_o = launch_bytes_per_cell(dim, other, mixed) * cells
-        roofline["other_kernel"] = {"kernel": names[other] + ", timed in the warm-up steps",
-                                    "avg_launch_us": round(avg_o * 1e6, 2),
-                                    "achieved": round(b_o / avg_o / 1e9, 1),
-                                    "algorithmic_bytes_per_launch": b_o,
-                                    "traffic": measured_traffic(args.workload, other,
-                                                                level_kernels[0])}
-    # per-class device time of a few more steps from the same state, every
-    # class timed (outside the timed region)
+    traffic = measured_traffic(name, cls, level_kernels[0])
+    roofline = roofline_record(cls, tim, bytes_launch, names[cls], traffic)
+    for other in cand:
+        if other != cls and tim_w[other][1]:
+            avg_o = tim_w[other][0] / 1e3 / tim_w[other][1]
+            if other == "refine":
+                continue
+            b_o = launch_bytes_per_cell(dim, other, mixed) * cells
+            roofline.setdefault("other_kernels", {})[other] = {
+                "kernel": names[other] + ", timed in the warm-up steps",
+                "avg_launch_us": round(avg_o * 1e6, 2),
+                "achieved": round(b_o / avg_o / 1e9, 1),
+                "algorithmic_bytes_per_launch": b_o,
+                "traffic": measured_traffic(name, other, level_kernels[0])}
     kernel_ms = {}
-    if not args.no_breakdown:
+    if breakdown:
         sb = chhs.Solver(prob, chhs.chhs_default_opts(tol=1e-10, timing=1, smoother=args.smoother,
                                                       precision=1 if mixed else 0,
                                                       autotune=int(args.autotune)))
         st_b = [torch.from_numpy(a).cuda() for a in start_state]
         nb = min(args.steps, 5)
-        sb.step(*st_b, 1)
+        sb.step_log(*st_b, 1)
         sb.timing(reset=True)
-        sb.step(*st_b, nb)
+        sb.step_log(*st_b, nb)
         kernel_ms = {k: round(v[0] / nb, 4) for k, v in sb.timing().items() if v[1]}
-        del sb
+        sb.close()
+    sv.close()
 
     out = {
         "metric": METRIC,
@@ -427,13 +558,14 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64" if mixed else "f64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "grid": list(shape), "eps": w["eps"],
+        "config": {"workload": name, "grid": list(shape), "eps": w["eps"],
                    "gamma": w["gamma"], "s": w["s"], "tol": 1e-10, "cycle": "V(2,2)",
-                   "precision": "fp32 inner + fp64 refinement" if mixed else "fp64"},
+                   "precision": "fp32 inner + fp64 refinement" if mixed else "fp64",
+                   "reductions": "mass, E_h, F_h, dissipation every step"},
         "vcycles_per_s": vcyc / elapsed,
         "steps_per_s": args.steps / elapsed,
         "vcycles_per_step": vcyc / args.steps,
-        "res_norm_last": s0["res_norm"],
+        "res_norm_last": lg[-1][0]["res_norm"],
         "kernel_ms_per_step": kernel_ms,
         "level_kernels": [list(k) for k in level_kernels],
         "roofline": roofline,
@@ -448,7 +580,7 @@ def main():
                              "achieved": round(vb / t_cyc / 1e9, 1), "peak": HBM_PEAK_GBS,
                              "unit": "GB/s", "frac": round(vb / t_cyc / 1e9 / HBM_PEAK_GBS, 4)}
 
-    if not args.no_parity:
+    if parity:
         # parity of the same workload at a size the oracle solves in seconds
         from oracle import fas, scheme
         m = 128 if dim == 2 else 32
@@ -466,20 +598,86 @@ def main():
         err = float(np.max(np.abs(b.cpu().numpy() - ref.phi)))
         out["parity"] = {"grid": list(sm), "steps": 1, "max_abs_err_phi_vs_oracle": err}
         log(f"parity at {m}^{dim}: max|phi - oracle| = {err:.2e}")
+        sv2.close()
 
-    if not args.no_cpu_baseline:
+    if cpu_baseline:
         log("timing the oracle on a bounded sample (single-threaded NumPy)")
         cpu0 = time.process_time()
         rate, desc, wall = oracle_sample(*start_state, w, vcyc / args.steps)
-        # threads actually used: process CPU time over wall time of the sample
         cores = max(1, round((time.process_time() - cpu0) / max(wall, 1e-9)))
         out["cpu_baseline"] = {"value": rate, "unit": "cell-updates/s", "cores": cores,
-                               "kind": "oracle", "sample": desc,
-                               "host": {"cpu": cpu_model(), "os_cpu_count": os.cpu_count(),
-                                        "omp_threads": os.environ.get("OMP_NUM_THREADS")},
+                               "kind": "oracle", "sample": desc, "host": host_info(),
                                "wall_s": round(wall, 2)}
         log(f"oracle: {rate:.3e} cell-updates/s ({wall:.1f}s of CPU work)")
+    return out
 
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default=BATCHED,
+                    help=f"{BATCHED} (default) or a single-grid workload name")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--no-fp64-2048", action="store_true",
+                    help="with the batched workload, skip the 2048^2 FP64 extra measurement")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="before the timed region, copy a 256 MiB device buffer three times "
+                         "(the known-size kernel that scales rocprofv3 FETCH_SIZE / WRITE_SIZE)")
+    ap.add_argument("--no-breakdown", action="store_true",
+                    help="skip the per-class timing pass after the timed region")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="use the default smoothing kernels instead of letting chhs_init time "
+                         "the candidates per level and keep the fastest")
+    ap.add_argument("--smoother", type=int, default=0,
+                    help="2D smoother: 0 default (strips on the finest level), 1 tiles, 2 strips")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build runs one GPU only (--gpus {args.gpus} requested); "
+              "the batched and single-grid paths are measured on one MI355X", file=sys.stderr)
+        sys.exit(2)
+
+    batched = args.workload == BATCHED
+    # the oracle's worker processes are forked before anything touches the GPU
+    pool = None
+    if batched and not args.no_cpu_baseline:
+        pool = make_pool(max(1, min(8, MAX_POOL, os.cpu_count() or 1)))
+
+    import torch
+
+    from paper_1611_02967_amd import build as _build
+    if not os.path.exists(_build.LIB):
+        log("libchhs.so missing: building")
+        _build.build()
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+
+    try:
+        if batched:
+            out = run_batched(args, pool)
+            if args.copy_calibration:
+                src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+                dst = torch.empty_like(src)
+                for _ in range(3):
+                    dst.copy_(src)
+                torch.cuda.synchronize()
+                del src, dst
+            if not args.no_fp64_2048:
+                one = run_single(args, "2d-2048-fp64", cpu_baseline=False, parity=False,
+                                 breakdown=False)
+                out["fp64_2048"] = {k: one[k] for k in (
+                    "value", "unit", "ms_per_step", "steps_per_s", "vcycles_per_step",
+                    "vcycles_per_s", "config", "roofline", "per_vcycle", "level_kernels")}
+        else:
+            out = run_single(args, args.workload, cpu_baseline=not args.no_cpu_baseline,
+                             parity=not args.no_parity, breakdown=not args.no_breakdown,
+                             copy_calibration=args.copy_calibration)
+    finally:
+        if pool is not None:
+            pool.close()
+            pool.join()
     print(json.dumps(out), flush=True)
 
 

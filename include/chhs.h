@@ -60,7 +60,11 @@ enum {
 /* One instance: dim = 2 or 3 (nz = 1 for 2D); h = L/N in every direction
  * (Section 2: one spacing for all directions); eps, gamma > 0 of (1.2)-(1.4)
  * (gamma = 0 allowed: no flow); dt = the time step s.  Extents must halve
- * together: nx = cx 2^k, ny = cy 2^k (, nz = cz 2^k) with the same k >= 1. */
+ * together: nx = cx 2^k, ny = cy 2^k (, nz = cz 2^k) with the same k >= 1.
+ * Size limits of the 32-bit indexing: fewer than 2^29 cells per instance (an
+ * FP64 field below 4 GiB) and at most 2^31 - 1 cells over a batch; larger
+ * problems are rejected (chhs_workspace_bytes returns 0, chhs_init
+ * CHHS_E_INVAL) before anything is allocated or launched. */
 typedef struct chhs_problem {
     int32_t dim, nx, ny, nz;
     double h, eps, gamma, dt;
@@ -123,6 +127,9 @@ enum {
     CHHS_K_COARSE = 3,     /* every launch on coarser levels (incl. the tail)   */
     CHHS_K_NORM = 4,       /* standalone residual-norm reductions and p shift   */
     CHHS_K_SETUP = 5,      /* per-step setup and energy reductions              */
+    CHHS_K_REFINE = 6,     /* mixed precision: the FP64 refinement launch on the
+                              finest level (u += e, residual, FP32 right-hand
+                              side and base state, norm partials)               */
     CHHS_K_COUNT = 8
 };
 
@@ -172,11 +179,26 @@ int chhs_init(const chhs_problem* p, int32_t n_inst, const chhs_opts* o,
  * in/out): (phi^{m-1}, phi^m) on entry, (phi^{m+n-1}, phi^{m+n}) on success;
  * pass identical contents for the first step (phi^{-1} := phi^0, Remark 2.2).
  * mu, p (device, in/out): initial guess in, mu^{m+n-1/2}, p^{m+n-1/2} (mean
- * zero) out.  stats_host: n_inst records of the last step, or NULL.  On
+ * zero) out.  stats_host: n_inst records of the last step, or NULL (the
+ * energies are those of the last step only; chhs_step_log gives every step's).  On
  * CHHS_E_NOCONV / CHHS_E_NONFINITE the failing step is not applied: the four
  * arrays hold the state before that step. */
 int chhs_step(chhs_ctx* c, double* phi_prev, double* phi_cur, double* mu, double* p,
               int32_t nsteps, chhs_stats* stats_host);
+
+/* chhs_step with the post-step reductions of every step (discrete mass (phi,1)
+ * of Section 4, E_h (2.8), F_h (2.9) and the two dissipation terms of the energy
+ * law of Theorem 2.1): per_step_host (host, nsteps * n_inst records, record
+ * m * n_inst + i = step m of instance i; required when nsteps > 0) receives for
+ * every step its cycle count, residuals and energies.  The reductions are
+ * enqueued on the stream after each step's solve and read back once, at the end
+ * of the call (the context keeps pinned host memory for nsteps records,
+ * allocated on the first call that needs more).  On CHHS_E_NOCONV /
+ * CHHS_E_NONFINITE the record of the failing step carries its status and
+ * residuals, later records stay zero (steps_done = 0), and the state holds the
+ * last step that succeeded. */
+int chhs_step_log(chhs_ctx* c, double* phi_prev, double* phi_cur, double* mu, double* p,
+                  int32_t nsteps, chhs_stats* per_step_host);
 
 /* Loads the system of one step (setup of (2.4)-(2.7): phi_*, right-hand side,
  * cell averages on all levels) from (phi_prev, phi_cur) and the initial guess

@@ -2,8 +2,11 @@
 
 The library is a plain C ABI (``include/chhs.h``); no PyTorch extension is
 involved.  Every translation unit is compiled to an object in parallel and
-linked into ``paper_1611_02967_amd/libchhs.so``.
+linked into ``paper_1611_02967_amd/libchhs.so``.  Next to it, ``libchhs.so.sha256``
+records the digest of the sources, the header and the compiler flags it was
+built from; the binding refuses a library whose digest no longer matches.
 """
+import hashlib
 import os
 import shutil
 import subprocess
@@ -16,6 +19,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libchhs.so")
+STAMP = LIB + ".sha256"
 ARCH = "gfx950"
 
 SOURCES = ["chhs_api.hip", "chhs_kernels.hip", "chhs_tile2d.hip", "chhs_stream2d.hip",
@@ -25,6 +29,30 @@ SOURCES = ["chhs_api.hip", "chhs_kernels.hip", "chhs_tile2d.hip", "chhs_stream2d
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wall", "-Wno-unused-function", f"-I{INCLUDE}", f"-I{CSRC}"]
+
+
+def source_digest(defines=()):
+    """sha256 over every file of csrc/, the public header and the build flags."""
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        with open(os.path.join(CSRC, name), "rb") as fh:
+            h.update(name.encode() + b"\0" + fh.read())
+    with open(os.path.join(INCLUDE, "chhs.h"), "rb") as fh:
+        h.update(fh.read())
+    # flags without the include directories (absolute paths differ between
+    # copies of the tree)
+    flags = [f for f in COMMON if not f.startswith("-I")] + [f"-D{d}" for d in defines]
+    h.update(" ".join(flags).encode())
+    return h.hexdigest()
+
+
+def is_current(path=LIB):
+    """True if ``path`` exists and was built from the sources as they are now."""
+    try:
+        with open(path + ".sha256") as fh:
+            return os.path.exists(path) and fh.read().strip() == source_digest()
+    except OSError:
+        return False
 
 
 def hipcc():
@@ -58,6 +86,9 @@ def build(verbose=False, out=None, defines=()):
             raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
         shutil.copyfile(out_tmp, target + ".tmp")
         os.replace(target + ".tmp", target)
+        with open(target + ".sha256.tmp", "w") as fh:
+            fh.write(source_digest(defines) + "\n")
+        os.replace(target + ".sha256.tmp", target + ".sha256")
     return target
 
 

@@ -41,7 +41,7 @@ class chhs_opts(ctypes.Structure):
                 ("tile_rows", ctypes.c_int32)]
 
 
-K_CLASSES = ["pre0", "post0", "transfer0", "coarse", "norm", "setup", "k6", "k7"]
+K_CLASSES = ["pre0", "post0", "transfer0", "coarse", "norm", "setup", "refine", "k7"]
 
 
 def timing_mask(*classes):
@@ -79,6 +79,7 @@ _SIGS = {
     "chhs_init": (_I, [ctypes.POINTER(chhs_problem), ctypes.c_int32, ctypes.POINTER(chhs_opts),
                        _P, ctypes.c_size_t, _P, ctypes.POINTER(_P)]),
     "chhs_step": (_I, [_P, _P, _P, _P, _P, ctypes.c_int32, ctypes.POINTER(chhs_stats)]),
+    "chhs_step_log": (_I, [_P, _P, _P, _P, _P, ctypes.c_int32, ctypes.POINTER(chhs_stats)]),
     "chhs_setup_step": (_I, [_P, _P, _P, _P, _P]),
     "chhs_fas_vcycle": (_I, [_P, ctypes.POINTER(ctypes.c_double)]),
     "chhs_residual_norms": (_I, [_P, ctypes.POINTER(ctypes.c_double)]),
@@ -99,9 +100,16 @@ _SIGS = {
 
 
 def load_library(path=LIB_PATH):
-    """dlopen libchhs.so and declare every exported signature."""
+    """dlopen libchhs.so and declare every exported signature.  The in-tree
+    library must have been built from the sources as they are now (its
+    recorded digest is compared); a stale build is refused, not run."""
     if not os.path.exists(path):
         raise ImportError(f"libchhs.so is not built ({path}); run paper_1611_02967_amd.build.build()")
+    if os.path.abspath(path) == os.path.abspath(os.path.join(HERE, "libchhs.so")):
+        from . import build as _build
+        if not _build.is_current(path):
+            raise ImportError(f"{path} was built from other sources than the current ones; "
+                              "rebuild with paper_1611_02967_amd.build.build()")
     lib = ctypes.CDLL(path)
     for name, (res, args) in _SIGS.items():
         fn = getattr(lib, name)
@@ -169,6 +177,15 @@ def chhs_step(ctx, phi_prev, phi_cur, mu, p, nsteps, n_inst=1, check=True):
     if check:
         _check(rc, "chhs_step")
     return rc, [s.as_dict() for s in stats]
+
+
+def chhs_step_log(ctx, phi_prev, phi_cur, mu, p, nsteps, n_inst=1, check=True):
+    """Steps with every step's statistics: a list over steps of lists over instances."""
+    recs = (chhs_stats * max(1, nsteps * n_inst))()
+    rc = _lib.chhs_step_log(ctx, _ptr(phi_prev), _ptr(phi_cur), _ptr(mu), _ptr(p), nsteps, recs)
+    if check:
+        _check(rc, "chhs_step_log")
+    return rc, [[recs[m * n_inst + i].as_dict() for i in range(n_inst)] for m in range(nsteps)]
 
 
 def chhs_setup_step(ctx, phi_prev, phi_cur, mu, p):
@@ -277,6 +294,19 @@ class Solver:
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
         self.stream = torch.cuda.current_stream() if stream is None else stream
         self.ctx = chhs_init(self.problems, self.opts, self.workspace, self.stream)
+        # packed cells of all instances: the length of every state array
+        self.cells = sum(int(q.nx) * int(q.ny) * int(q.nz) for q in self.problems)
+
+    def _check_arrays(self, *ts):
+        """Every array must hold the packed cells of all instances and live on
+        the workspace's device (the kernels index it up to that length)."""
+        for t in ts:
+            if t is None:
+                continue
+            if t.device != self.workspace.device:
+                raise ValueError(f"array on {t.device}, workspace on {self.workspace.device}")
+            if t.numel() != self.cells:
+                raise ValueError(f"array holds {t.numel()} values, the instances {self.cells} cells")
 
     def close(self):
         if self.ctx is not None:
@@ -290,9 +320,15 @@ class Solver:
             pass
 
     def step(self, phi_prev, phi_cur, mu, p, nsteps=1, check=True):
+        self._check_arrays(phi_prev, phi_cur, mu, p)
         return chhs_step(self.ctx, phi_prev, phi_cur, mu, p, nsteps, self.n_inst, check)
 
+    def step_log(self, phi_prev, phi_cur, mu, p, nsteps=1, check=True):
+        self._check_arrays(phi_prev, phi_cur, mu, p)
+        return chhs_step_log(self.ctx, phi_prev, phi_cur, mu, p, nsteps, self.n_inst, check)
+
     def setup_step(self, phi_prev, phi_cur, mu, p):
+        self._check_arrays(phi_prev, phi_cur, mu, p)
         chhs_setup_step(self.ctx, phi_prev, phi_cur, mu, p)
 
     def fas_vcycle(self):
@@ -302,9 +338,11 @@ class Solver:
         return chhs_residual_norms(self.ctx, self.n_inst)
 
     def get_solution(self, phi=None, mu=None, p=None):
+        self._check_arrays(phi, mu, p)
         chhs_get_solution(self.ctx, phi, mu, p)
 
     def energy_mass(self, phi, phi_prev):
+        self._check_arrays(phi, phi_prev)
         return chhs_energy_mass(self.ctx, phi, phi_prev, self.n_inst)
 
     def timing(self, reset=False):

@@ -30,6 +30,10 @@ using chhs::kMaxLevels;
 namespace {
 
 constexpr size_t kAlign = 256;
+// Limits of the 32-bit indexing: cells per instance (an FP64 field < 4 GiB)
+// and cells of a whole batch (packed offsets are int).
+constexpr long long kMaxCellsPerInstance = 1LL << 29;
+constexpr long long kMaxPackedCells = 2147483647LL;
 // Tiled launches of at most this many blocks (at most one per compute unit)
 // use 1024-thread blocks: their time is the latency of one block.
 constexpr int kWideTiles = 256;
@@ -67,6 +71,7 @@ struct Layout {
     std::vector<std::vector<int>> snx, sny;
     std::vector<int> tail_insts;
     std::vector<CellTask> A0n;              // finest-level cells of instances without a fused norm
+    std::vector<CellTask> A0t;              // finest-level cells of instances held by the tail
     std::vector<Range> rngA0, rngT0, rngA0n;
     // folds of the partials over A[0] / A0n (empty when no instance has more
     // than kFold of them) and the per-instance ranges of the folded partials
@@ -82,10 +87,10 @@ struct Layout {
     // offsets into the workspace
     size_t off_desc = 0, off_desc32 = 0, off_info = 0, off_tail = 0, off_rngA0 = 0, off_rngT0 = 0,
            off_rngA0n = 0;
-    size_t off_A0n = 0, off_partial_t = 0;
+    size_t off_A0n = 0, off_A0t = 0, off_partial_t = 0;
     size_t off_FA0 = 0, off_FA0n = 0, off_rngA0f = 0, off_rngA0nf = 0, off_partial_f = 0;
     size_t off_partial = 0, off_res = 0, off_eres = 0, off_act_cycle = 0, off_act_next = 0,
-           off_cycles = 0;
+           off_cycles = 0, off_act_last = 0;
     std::vector<size_t> off_A, off_B, off_Bc, off_Bh, off_Bcs, off_T, off_Tall, off_S, off_Sall;
     int partial_cap = 0, partial_t_cap = 0;
 };
@@ -110,7 +115,7 @@ struct chhs_ctx {
         Bcs[kMaxLevels];
     Table<TileTask> T[kMaxLevels], Tall[kMaxLevels];
     Table<StripTask> S[kMaxLevels], Sall[kMaxLevels];
-    Table<CellTask> A0n;
+    Table<CellTask> A0n, A0t;
     Table<FoldTask> FA0, FA0n;
     int* tail_insts = nullptr;
     Range* rngA0 = nullptr;
@@ -125,6 +130,7 @@ struct chhs_ctx {
     double* eres = nullptr;         // [n_inst][kResStride]
     int* act_cycle = nullptr;
     int* act_next = nullptr;
+    int* act_last = nullptr;        // mixed: act_cycle of the previous refinement
     int* cycles = nullptr;
     // pinned host mirrors of the result block (res | act_next | cycles): two
     // that the cycles of the pipelined plain loop alternate between, a third
@@ -133,6 +139,9 @@ struct chhs_ctx {
     double* hbuf[3] = {nullptr, nullptr, nullptr};
     double* hres = nullptr;
     double* heres = nullptr;
+    // per-step energies of chhs_step_log (pinned, grown on demand)
+    double* hlog = nullptr;
+    size_t hlog_cap = 0;
     int* hact = nullptr;
     int* hcyc = nullptr;
     int cur[kMaxLevels] = {};       // current copy of u per FP64 level
@@ -173,8 +182,18 @@ bool valid_problem(const chhs_problem* p) {
     if (!std::isfinite(p->h) || !std::isfinite(p->eps) || !std::isfinite(p->gamma) ||
         !std::isfinite(p->dt))
         return false;
+    // Kernels address a field with a 32-bit unsigned byte offset: an FP64 field
+    // must stay below 4 GiB, i.e. below 2^29 cells.
     const double cells = double(p->nx) * p->ny * p->nz;
-    return cells < 1073741824.0;
+    return cells < double(kMaxCellsPerInstance);
+}
+
+// Cells of all instances together: packed caller arrays are indexed with
+// 32-bit signed offsets.
+bool valid_total(const chhs_problem* p, int n_inst) {
+    double total = 0.0;
+    for (int i = 0; i < n_inst; ++i) total += double(p[i].nx) * p[i].ny * p[i].nz;
+    return total <= double(kMaxPackedCells);
 }
 
 bool valid_opts(const chhs_opts* o) {
@@ -341,6 +360,10 @@ void fused_ranges(Layout& L, int n_inst) {
 // Builds the layout; base != nullptr fills the device pointers of the descriptors.
 bool plan(const chhs_problem* p, int n_inst, const chhs_opts* o, char* base, Layout& L) {
     L = Layout();
+    // every size check before any per-cell table is built
+    for (int i = 0; i < n_inst; ++i)
+        if (!valid_problem(&p[i])) return false;
+    if (!valid_total(p, n_inst)) return false;
     const int dim = p[0].dim;
     const bool mixed = o->precision == 1;
     L.A.resize(kMaxLevels);
@@ -489,6 +512,7 @@ bool plan(const chhs_problem* p, int n_inst, const chhs_opts* o, char* base, Lay
         // coarse levels above the tail (the tail forms its top level's f itself)
         for (int l = 0; l + 1 < tail; ++l) cell_tasks(L.Bcs[l], i, cells[l + 1]);
         if (!in.fused) cell_tasks(L.A0n, i, cells[0]);
+        if (tail == 0) cell_tasks(L.A0t, i, cells[0]);
         L.tail_insts.push_back(i);
     }
     // 2D smoother per level: row-streaming strips or square tiles (the same
@@ -535,6 +559,7 @@ bool plan(const chhs_problem* p, int n_inst, const chhs_opts* o, char* base, Lay
     L.off_rngT0 = take(n_inst * sizeof(Range));
     L.off_rngA0n = take(n_inst * sizeof(Range));
     L.off_A0n = take(L.A0n.size() * sizeof(CellTask));
+    L.off_A0t = take(L.A0t.size() * sizeof(CellTask));
     L.off_FA0 = take(L.FA0.size() * sizeof(FoldTask));
     L.off_FA0n = take(L.FA0n.size() * sizeof(FoldTask));
     L.off_rngA0f = take(n_inst * sizeof(Range));
@@ -561,6 +586,7 @@ bool plan(const chhs_problem* p, int n_inst, const chhs_opts* o, char* base, Lay
     L.off_cycles = L.off_act_next + n_inst * sizeof(int);
     L.off_eres = take(size_t(n_inst) * chhs::kResStride * sizeof(double));
     L.off_act_cycle = take(n_inst * sizeof(int));
+    L.off_act_last = take(n_inst * sizeof(int));
     L.bytes = off;
     return true;
 }
@@ -692,7 +718,8 @@ Hier<float> hier32(chhs_ctx* c) { return {c->ddesc32, &c->lay.desc32, c->cur32, 
 // flips the level's current copy.
 template <typename T>
 void tiled(chhs_ctx* c, const Hier<T>& H, bool all, int l, int ns, int epi, bool pro,
-           const int* active, int cls, bool rhs = false, const double* pshift = nullptr) {
+           const int* active, int cls, bool rhs = false, const double* pshift = nullptr,
+           bool zero = false) {
     Batch<T> b = make_batch(H.dev, H.cur, l, active);
     b.pshift = pshift;
     const bool level0 = std::is_same<T, double>::value && l == 0;
@@ -701,12 +728,12 @@ void tiled(chhs_ctx* c, const Hier<T>& H, bool all, int l, int ns, int epi, bool
         TimedScope t(c, cls);
         if (c->lay.strip[l]) {
             const Table<StripTask>& st = all ? c->Sall[l] : c->S[l];
-            chhs::launch_stream2d<T>(b, st.dev, st.n, level0, ns, epi, pro, part, c->stream);
+            chhs::launch_stream2d<T>(b, st.dev, st.n, level0, ns, epi, pro, zero, part, c->stream);
         } else {
             const Table<TileTask>& tt = all ? c->Tall[l] : c->T[l];
             chhs::launch_tile2d<T>(b, tt.dev, tt.n, level0, ns, epi, pro,
                                    tile_block(all ? 0 : c->lay.tile_threads[l], tt.n), rhs,
-                                   all ? c->lay.tile_y_all[l] : c->lay.tile_y[l], part,
+                                   all ? c->lay.tile_y_all[l] : c->lay.tile_y[l], zero, part,
                                    c->stream);
         }
     }
@@ -767,16 +794,21 @@ void enqueue_vcycle(chhs_ctx* c, const Hier<T>& H) {
         if (tiled2d(c) && o.nu1 > 0) {
             // on a tiled coarse level the first launch forms f = fr + N(u)
             const bool rhs = d > 0 && !c->lay.strip[d];
-            // ... and on the finest level it subtracts a deferred p shift
+            // ... and on the finest level it subtracts a deferred p shift, or,
+            // for a correction cycle, takes the zero starting correction as
+            // implied
             const double* psh = kPlain && d == 0 && c->defer_shift ? c->res : nullptr;
+            const bool zero = !kPlain && d == 0;
             bool first = true;
             int rem = o.nu1;
             while (rem > 2) {
-                tiled(c, H, false, d, 2, 0, false, act, pre_cls, rhs && first, first ? psh : nullptr);
+                tiled(c, H, false, d, 2, 0, false, act, pre_cls, rhs && first, first ? psh : nullptr,
+                      zero && first);
                 first = false;
                 rem -= 2;
             }
-            tiled(c, H, false, d, rem, 1, false, act, pre_cls, rhs && first, first ? psh : nullptr);
+            tiled(c, H, false, d, rem, 1, false, act, pre_cls, rhs && first, first ? psh : nullptr,
+                  zero && first);
         } else {
             if (!tiled2d(c))
                 for (int s = 0; s < o.nu1; ++s)
@@ -855,14 +887,18 @@ float time_level(chhs_ctx* c, const Hier<T>& H, int l, int reps, hipEvent_t ea, 
         if (l > 0 && c->lay.strip[l] && c->Bcs[l - 1].n > 0)
             chhs::launch_coarse_rhs(2, make_batch(H.dev, H.cur, l - 1, nullptr), c->Bcs[l - 1].dev,
                                     c->Bcs[l - 1].n, c->stream);
+        // the FP32 finest level's first launch takes a zero correction as implied
+        const bool zero = !std::is_same<T, double>::value && l == 0;
         bool first = true;
         int rem = o.nu1;
         while (rem > 2) {
-            tiled(c, H, false, l, 2, 0, false, nullptr, CHHS_K_PRE0, rhs && first);
+            tiled(c, H, false, l, 2, 0, false, nullptr, CHHS_K_PRE0, rhs && first, nullptr,
+                  zero && first);
             first = false;
             rem -= 2;
         }
-        tiled(c, H, false, l, rem, 1, false, nullptr, CHHS_K_PRE0, rhs && first);
+        tiled(c, H, false, l, rem, 1, false, nullptr, CHHS_K_PRE0, rhs && first, nullptr,
+              zero && first);
         rem = o.nu2;
         bool pro = true;
         while (rem > 0) {
@@ -1013,17 +1049,34 @@ void apply_pshift(chhs_ctx* c) {
 // Mixed precision, one refinement step: zero FP32 correction, one FP32
 // correction-form V-cycle, then in FP64 u += e, the residual of the full
 // system (into the FP32 right-hand side) and its norms.
+// The first FP32 launch of a correction cycle on the finest level is a tiled
+// pre-smoothing launch that takes the zero starting correction as implied
+// (2D with nu1 > 0); otherwise the correction is cleared by a pass of its own,
+// as it is for instances whose finest level the one-workgroup tail holds.
+bool zero_start(const chhs_ctx* c) { return tiled2d(c) && c->opts.nu1 > 0; }
+
+// p's mean is not subtracted here: N(u) depends on p through differences only,
+// so the residual and the cycle do not change; res slot 4 holds the mean of the
+// stored p (the reduction of p'), and the copy to the caller's arrays (or
+// apply_pshift) subtracts it.
 void enqueue_refinement(chhs_ctx* c, bool count, bool add) {
     const int* act = c->act_cycle;
     const chhs_opts& o = c->opts;
-    chhs::launch_copy_int(c->act_cycle, c->act_next, c->n_inst, c->stream);
+    // this refinement's flags from the last reduction; the previous ones kept
+    // for the instances that have just converged
+    chhs::launch_roll_flags(c->act_last, c->act_cycle, c->act_next, c->n_inst, c->stream);
     if (add) {
-        chhs::launch_zero_correction(batch32(c, 0, act), c->A[0].dev, c->A[0].n, c->stream);
+        const Table<CellTask>& z = zero_start(c) ? c->A0t : c->A[0];
+        chhs::launch_zero_correction(batch32(c, 0, act), z.dev, z.n, c->stream);
         enqueue_vcycle(c, hier32(c));
     }
+    {
+        TimedScope t(c, CHHS_K_REFINE);
+        chhs::launch_mixed_residual(c->dim, batch(c, 0, add ? act : nullptr), batch32(c, 0, act),
+                                    c->A[0].dev, c->A[0].n, add ? 1 : 0,
+                                    add ? c->act_last : nullptr, c->partial, c->stream);
+    }
     TimedScope t(c, CHHS_K_NORM);
-    chhs::launch_mixed_residual(c->dim, batch(c, 0, add ? act : nullptr), batch32(c, 0, act),
-                                c->A[0].dev, c->A[0].n, add ? 1 : 0, c->partial, c->stream);
     c->cur[0] ^= 1;
     const double* src;
     const Range* rng;
@@ -1031,8 +1084,6 @@ void enqueue_refinement(chhs_ctx* c, bool count, bool add) {
     chhs::launch_inst_reduce(src, rng, nullptr, nullptr, 0, c->dinfo,
                              add ? act : nullptr, c->act_next, c->cycles, c->res, c->n_inst,
                              o.tol, count ? o.max_vcycles : 1 << 30, count ? 1 : 0, c->stream);
-    chhs::launch_shift_p(batch(c, 0, add ? act : nullptr), c->A[0].dev, c->A[0].n, c->res,
-                         c->stream);
 }
 
 void enqueue_cycle(chhs_ctx* c, bool count) {
@@ -1294,9 +1345,8 @@ int setup(chhs_ctx* c, const double* phi_prev, const double* phi_cur, const doub
                                  c->opts.max_vcycles, 0, c->stream);
         if (!c->defer_shift)
             chhs::launch_shift_p(batch(c, 0, nullptr), c->A[0].dev, c->A[0].n, c->res, c->stream);
-        else if (!defer)
-            apply_pshift(c);
     }
+    if (c->defer_shift && !defer) apply_pshift(c);
     int rc = check_launch();
     if (rc) return rc;
     c->loaded = true;
@@ -1307,8 +1357,12 @@ int setup(chhs_ctx* c, const double* phi_prev, const double* phi_cur, const doub
     return sync_results(c);
 }
 
-// Energies into heres (per instance): workspace mode or caller arrays.
-int energies(chhs_ctx* c, int ws, const double* phi, const double* q) {
+const double* hres_of(chhs_ctx* c, int i) { return c->hres + size_t(i) * chhs::kResStride; }
+
+// Enqueues the energies (per instance, kResStride doubles each) and their
+// copy into pinned host memory `dst`: workspace mode (ws != 0: the finest
+// level's iterate, phi^m and the flow terms) or caller arrays.
+int enqueue_energies(chhs_ctx* c, int ws, const double* phi, const double* q, double* dst) {
     {
         TimedScope t(c, CHHS_K_SETUP);
         chhs::launch_energy_partials(c->dim, batch(c, 0, nullptr), c->A[0].dev, c->A[0].n,
@@ -1317,12 +1371,120 @@ int energies(chhs_ctx* c, int ws, const double* phi, const double* q) {
     }
     int rc = check_launch();
     if (rc) return rc;
-    HIP_TRY(hipMemcpyAsync(c->heres, c->eres, size_t(c->n_inst) * chhs::kResStride * sizeof(double),
+    HIP_TRY(hipMemcpyAsync(dst, c->eres, size_t(c->n_inst) * chhs::kResStride * sizeof(double),
                            hipMemcpyDeviceToHost, c->stream));
+    return CHHS_OK;
+}
+
+// Energies into heres (per instance), waited for.
+int energies(chhs_ctx* c, int ws, const double* phi, const double* q) {
+    const int rc = enqueue_energies(c, ws, phi, q, c->heres);
+    if (rc) return rc;
     return sync_results(c);
 }
 
-const double* hres_of(chhs_ctx* c, int i) { return c->hres + size_t(i) * chhs::kResStride; }
+// Pinned host records of the per-step energies of nsteps steps (kept by the
+// context and grown on demand).
+int reserve_log(chhs_ctx* c, int nsteps) {
+    const size_t need = size_t(nsteps) * size_t(c->n_inst) * chhs::kResStride;
+    if (need <= c->hlog_cap) return CHHS_OK;
+    if (c->hlog != nullptr) {
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        (void)hipHostFree(c->hlog);
+        c->hlog = nullptr;
+        c->hlog_cap = 0;
+    }
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&c->hlog), need * sizeof(double),
+                          hipHostMallocDefault));
+    c->hlog_cap = need;
+    return CHHS_OK;
+}
+
+void fill_energies(chhs_stats& s, const double* e) {
+    s.mass = e[0];
+    s.E_h = e[1];
+    s.F_h = e[2];
+    s.diss_mu = e[3];
+    s.diss_u = e[4];
+    s.max_abs_phi = e[5];
+}
+
+// The time-step loop of chhs_step / chhs_step_log.  last: n_inst records of
+// the last step (energies of that step), or null; log: nsteps x n_inst records,
+// one per step with that step's energies (enqueued after each step's solve,
+// read once at the end), or null.
+int step_loop(chhs_ctx* c, double* phi_prev, double* phi_cur, double* mu, double* p,
+              int nsteps, chhs_stats* last, chhs_stats* log) {
+    const int n = c->n_inst;
+    std::vector<chhs_stats> st(n);
+    for (auto& s : st) std::memset(&s, 0, sizeof(s));
+    if (log != nullptr) std::memset(log, 0, size_t(nsteps) * n * sizeof(chhs_stats));
+    int rc = log != nullptr ? reserve_log(c, nsteps) : CHHS_OK;
+    int done = 0;
+    for (int m = 0; m < nsteps && rc == CHHS_OK; ++m) {
+        // plain FP64: the setup is not waited for; its norms come with the first cycle
+        const bool early = !c->mixed;
+        rc = setup(c, phi_prev, phi_cur, mu, p, true, !early);
+        if (rc) break;
+        if (!early)
+            for (int i = 0; i < n; ++i) st[i].res0 = hres_of(c, i)[3];
+        rc = run_cycles(c, early);
+        if (rc) break;
+        if (early)
+            for (int i = 0; i < n; ++i) st[i].res0 = c->hbuf[2][size_t(i) * chhs::kResStride + 3];
+        for (int i = 0; i < n; ++i) {
+            const double* r = hres_of(c, i);
+            st[i].vcycles = c->hcyc[i];
+            st[i].total_vcycles += c->hcyc[i];
+            for (int k = 0; k < 3; ++k) st[i].res[k] = r[k];
+            st[i].res_norm = r[3];
+            st[i].status = CHHS_OK;
+            if (!std::isfinite(r[3]))
+                st[i].status = CHHS_E_NONFINITE;
+            else if (r[3] > c->opts.tol)
+                st[i].status = CHHS_E_NOCONV;
+            if (st[i].status != CHHS_OK && rc == CHHS_OK) rc = st[i].status;
+        }
+        if (rc) {
+            if (log != nullptr)
+                for (int i = 0; i < n; ++i) log[size_t(m) * n + i] = st[i];
+            break;
+        }
+        if (log != nullptr) {
+            rc = enqueue_energies(c, 1, nullptr, nullptr,
+                                  c->hlog + size_t(m) * n * chhs::kResStride);
+            if (rc) break;
+        } else if (m == nsteps - 1 && last != nullptr) {
+            rc = energies(c, 1, nullptr, nullptr);
+            if (rc) break;
+            for (int i = 0; i < n; ++i) fill_energies(st[i], c->heres + size_t(i) * chhs::kResStride);
+        }
+        // rotate: (phi^{m-1}, phi^m) <- (phi^m, phi^{m+1}); mu, p <- this step's
+        Batch<double> bo = batch(c, 0, nullptr);
+        bo.pshift = c->defer_shift ? c->res : nullptr;
+        chhs::launch_copy_out(bo, c->A[0].dev, c->A[0].n, c->dinfo, phi_prev, phi_cur, mu, p,
+                              c->stream);
+        rc = check_launch();
+        if (rc) break;
+        for (int i = 0; i < n; ++i) {
+            ++st[i].steps_done;
+            if (log != nullptr) log[size_t(m) * n + i] = st[i];
+        }
+        done = m + 1;
+    }
+    if (hipStreamSynchronize(c->stream) != hipSuccess && rc == CHHS_OK) rc = CHHS_E_HIP;
+    if (log != nullptr)
+        for (int m = 0; m < done; ++m)
+            for (int i = 0; i < n; ++i)
+                fill_energies(log[size_t(m) * n + i], c->hlog + (size_t(m) * n + i) * chhs::kResStride);
+    if (last != nullptr) {
+        if (log != nullptr && done > 0)
+            for (int i = 0; i < n; ++i) fill_energies(st[i], c->hlog + (size_t(done - 1) * n + i) * chhs::kResStride);
+        for (int i = 0; i < n; ++i) last[i] = st[i];
+    }
+    return rc;
+}
+
 
 
 }  // namespace
@@ -1407,6 +1569,7 @@ int chhs_init(const chhs_problem* p, int32_t n_inst, const chhs_opts* o, void* w
     c->res = reinterpret_cast<double*>(b + L.off_res);
     c->eres = reinterpret_cast<double*>(b + L.off_eres);
     c->act_cycle = reinterpret_cast<int*>(b + L.off_act_cycle);
+    c->act_last = reinterpret_cast<int*>(b + L.off_act_last);
     c->act_next = reinterpret_cast<int*>(b + L.off_act_next);
     c->cycles = reinterpret_cast<int*>(b + L.off_cycles);
     hipStream_t st = c->stream;
@@ -1439,6 +1602,7 @@ int chhs_init(const chhs_problem* p, int32_t n_inst, const chhs_opts* o, void* w
         rc |= upload(c->Sall[l], b, L.off_Sall[l], L.Sall[l], st);
     }
     rc |= upload(c->A0n, b, L.off_A0n, L.A0n, st);
+    rc |= upload(c->A0t, b, L.off_A0t, L.A0t, st);
     rc |= upload(c->FA0, b, L.off_FA0, L.FA0, st);
     rc |= upload(c->FA0n, b, L.off_FA0n, L.FA0n, st);
     if (hipMemcpyAsync(c->rngA0f, L.rngA0f.data(), n_inst * sizeof(Range), hipMemcpyHostToDevice,
@@ -1462,7 +1626,8 @@ int chhs_init(const chhs_problem* p, int32_t n_inst, const chhs_opts* o, void* w
     view_results(c, 0);
     c->heres = c->hbuf[0] + nres + nint;
     c->fused_norm = !c->mixed && c->dim == 2 && o->nu2 > 0 && o->order != 1;
-    c->defer_shift = !c->mixed && tiled2d(c) && o->nu1 > 0;
+    // the mixed path never subtracts p's mean inside its cycles
+    c->defer_shift = c->mixed || (tiled2d(c) && o->nu1 > 0);
     if (hipStreamSynchronize(st) != hipSuccess) return fail(CHHS_E_HIP);
     if (o->autotune && o->smoother == 0 && c->dim == 2 && o->nu1 > 0 && o->nu2 > 0 &&
         o->order != 1) {
@@ -1537,61 +1702,15 @@ int chhs_step(chhs_ctx* c, double* phi_prev, double* phi_cur, double* mu, double
     if (c == nullptr || phi_prev == nullptr || phi_cur == nullptr || mu == nullptr ||
         p == nullptr || nsteps < 0)
         return CHHS_E_INVAL;
-    const int n = c->n_inst;
-    std::vector<chhs_stats> st(n);
-    for (auto& s : st) std::memset(&s, 0, sizeof(s));
-    int rc = CHHS_OK;
-    for (int m = 0; m < nsteps && rc == CHHS_OK; ++m) {
-        // plain FP64: the setup is not waited for; its norms come with the first cycle
-        const bool early = !c->mixed;
-        rc = setup(c, phi_prev, phi_cur, mu, p, true, !early);
-        if (rc) break;
-        if (!early)
-            for (int i = 0; i < n; ++i) st[i].res0 = hres_of(c, i)[3];
-        rc = run_cycles(c, early);
-        if (rc) break;
-        if (early)
-            for (int i = 0; i < n; ++i) st[i].res0 = c->hbuf[2][size_t(i) * chhs::kResStride + 3];
-        for (int i = 0; i < n; ++i) {
-            const double* r = hres_of(c, i);
-            st[i].vcycles = c->hcyc[i];
-            st[i].total_vcycles += c->hcyc[i];
-            for (int k = 0; k < 3; ++k) st[i].res[k] = r[k];
-            st[i].res_norm = r[3];
-            st[i].status = CHHS_OK;
-            if (!std::isfinite(r[3]))
-                st[i].status = CHHS_E_NONFINITE;
-            else if (r[3] > c->opts.tol)
-                st[i].status = CHHS_E_NOCONV;
-            if (st[i].status != CHHS_OK && rc == CHHS_OK) rc = st[i].status;
-        }
-        if (rc) break;
-        if (m == nsteps - 1 && stats_host != nullptr) {
-            rc = energies(c, 1, nullptr, nullptr);
-            if (rc) break;
-            for (int i = 0; i < n; ++i) {
-                const double* e = c->heres + size_t(i) * chhs::kResStride;
-                st[i].mass = e[0];
-                st[i].E_h = e[1];
-                st[i].F_h = e[2];
-                st[i].diss_mu = e[3];
-                st[i].diss_u = e[4];
-                st[i].max_abs_phi = e[5];
-            }
-        }
-        // rotate: (phi^{m-1}, phi^m) <- (phi^m, phi^{m+1}); mu, p <- this step's
-        Batch<double> bo = batch(c, 0, nullptr);
-        bo.pshift = c->defer_shift ? c->res : nullptr;
-        chhs::launch_copy_out(bo, c->A[0].dev, c->A[0].n, c->dinfo, phi_prev, phi_cur, mu, p,
-                              c->stream);
-        rc = check_launch();
-        if (rc) break;
-        for (int i = 0; i < n; ++i) ++st[i].steps_done;
-    }
-    if (stats_host != nullptr)
-        for (int i = 0; i < n; ++i) stats_host[i] = st[i];
-    if (hipStreamSynchronize(c->stream) != hipSuccess && rc == CHHS_OK) rc = CHHS_E_HIP;
-    return rc;
+    return step_loop(c, phi_prev, phi_cur, mu, p, nsteps, stats_host, nullptr);
+}
+
+int chhs_step_log(chhs_ctx* c, double* phi_prev, double* phi_cur, double* mu, double* p,
+                  int32_t nsteps, chhs_stats* per_step_host) {
+    if (c == nullptr || phi_prev == nullptr || phi_cur == nullptr || mu == nullptr ||
+        p == nullptr || nsteps < 0 || (nsteps > 0 && per_step_host == nullptr))
+        return CHHS_E_INVAL;
+    return step_loop(c, phi_prev, phi_cur, mu, p, nsteps, nullptr, per_step_host);
 }
 
 int chhs_energy_mass(chhs_ctx* c, const double* phi, const double* phi_prev, double* out_host) {
@@ -1738,6 +1857,7 @@ void chhs_destroy(chhs_ctx* c) {
         if (c->cycle_done[k]) (void)hipEventDestroy(c->cycle_done[k]);
     for (int k = 0; k < 3; ++k)
         if (c->hbuf[k]) (void)hipHostFree(c->hbuf[k]);
+    if (c->hlog) (void)hipHostFree(c->hlog);
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }

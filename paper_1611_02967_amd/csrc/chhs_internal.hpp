@@ -184,12 +184,15 @@ void launch_prolong(int dim, const Batch<float>& b, const CellTask* t, int nt, h
 // Mixed precision (finest level): FP32 copies of phi_*, phi^m; a zero FP32
 // correction; the FP64 outer step u' = u (+ e), R = f - N(u') written as u'
 // (other FP64 copy), R and b = phi' in FP32, and norm partials (as
-// launch_residual_partials).
+// launch_residual_partials); an instance inactive now but flagged in
+// was_active (its flags of the previous refinement; nullptr: every inactive
+// instance) copies its iterate into the other copy.
 void launch_mixed_frozen(const Batch<double>& b64, const Batch<float>& b32, const CellTask* t,
                          int nt, hipStream_t st);
 void launch_zero_correction(const Batch<float>& b32, const CellTask* t, int nt, hipStream_t st);
 void launch_mixed_residual(int dim, const Batch<double>& b64, const Batch<float>& b32,
-                           const CellTask* t, int nt, int add, double* partial, hipStream_t st);
+                           const CellTask* t, int nt, int add, const int* was_active,
+                           double* partial, hipStream_t st);
 // partial[block][0..3] = sum R_phi^2, R_mu^2, R_p^2, p over the block's cells
 void launch_residual_partials(int dim, const Batch<double>& b, const CellTask* t, int nt,
                               double* partial, hipStream_t st);
@@ -234,6 +237,8 @@ void launch_get_solution(const Batch<double>& b, const CellTask* t, int nt, cons
                          double* phi, double* mu, double* p, hipStream_t st);
 void launch_fill_int(int* dst, int n, int value, hipStream_t st);
 void launch_copy_int(int* dst, const int* src, int n, hipStream_t st);
+// last <- cur, cur <- next (per-instance flags)
+void launch_roll_flags(int* last, int* cur, const int* next, int n, hipStream_t st);
 
 // ---- tiled 2D smoothing (chhs_tile2d.hip) ------------------------------------------
 // Tiles are 64 x 16 cells, or on coarse levels 64 x 8 or 64 x 4 (more,
@@ -251,10 +256,13 @@ constexpr int kTileYTiny = 4;
 // or one pair of cells per thread);
 // rhs: first pre-smoothing launch on a coarse level, which first forms the FAS
 // right-hand side f += N(u) (not with level0, pro or epi 2); ty: tile height,
-// kTileY or (not with level0) kTileYSmall or kTileYTiny, as the tasks were cut.
+// kTileY or (not with level0) kTileYSmall or kTileYTiny, as the tasks were cut;
+// zero (FP32 only, the finest level's first launch of a correction cycle, 64 x
+// 16 tiles, not with pro, rhs or epi 2): u is taken as zero instead of read.
 template <typename T>
 void launch_tile2d(const Batch<T>& b, const TileTask* t, int nt, bool level0, int ns, int epi,
-                   bool pro, int threads, bool rhs, int ty, double* partial, hipStream_t st);
+                   bool pro, int threads, bool rhs, int ty, bool zero, double* partial,
+                   hipStream_t st);
 
 // ---- row-streaming 2D smoothing (chhs_stream2d.hip) ---------------------------------
 // Strip sx owns columns [sx kStripWO, (sx + 1) kStripWO) and stages kStripW
@@ -265,7 +273,7 @@ constexpr int kStripWO = kStripW - 2 * kStripHX;
 // Same contract as launch_tile2d over strip tasks; partial gets 4 sums per task.
 template <typename T>
 void launch_stream2d(const Batch<T>& b, const StripTask* t, int nt, bool level0, int ns, int epi,
-                     bool pro, double* partial, hipStream_t st);
+                     bool pro, bool zero, double* partial, hipStream_t st);
 
 // ---- single-workgroup coarse tail (chhs_tail.hip) ----------------------------------
 size_t tail_lds_bytes(const int* cells, int nlev, size_t elem, int nfields);

@@ -211,8 +211,29 @@ __global__ __launch_bounds__(kBlock) void k_smooth_color(Batch<T> b, const CellT
     L.p[idx] = p;
 }
 
+// The seven values a fine cell contributes to its coarse cell: the residual
+// f - N(u) of the three rows, u, and (CORR) the base state b.
+template <int DIM, typename T, bool CORR>
+__device__ __forceinline__ void child_values(const Level<T>& F, int fi, int fj, int fk,
+                                             T (&v)[7]) {
+    const int f = (fk * F.ny + fj) * F.nx + fi;
+    T n0, n1, n2;
+    cell_operator<DIM, T, CORR>(F, f, fi, fj, fk, n0, n1, n2);
+    v[0] = F.f0[f] - n0;
+    v[1] = F.f1[f] - n1;
+    v[2] = F.f2[f] - n2;
+    v[3] = F.phi[f];
+    v[4] = F.mu[f];
+    v[5] = F.p[f];
+    v[6] = CORR ? F.b[f] : T(0);
+}
+
 // Per coarse cell: u_c = R u, ub_c = u_c, f_c = R(f - N(u)) (the N_c(u_c) part
-// is added by k_coarse_rhs once all of u_c is written).
+// is added by k_coarse_rhs once all of u_c is written).  Child c = dx + 2 dy
+// + 4 dz; the children are added in the tree ((c0 + c1) + (c2 + c3)) [+ ((c4
+// + c5) + (c6 + c7)) in 3D], the order of the lane exchanges of
+// k_restrict_residual_lanes, so that both kernels give the same bits and an
+// instance's restriction does not depend on which one its batch launches.
 template <int DIM, typename T, bool CORR>
 __global__ __launch_bounds__(kBlock) void k_restrict_residual(Batch<T> b,
                                                               const CellTask* __restrict__ t) {
@@ -225,31 +246,34 @@ __global__ __launch_bounds__(kBlock) void k_restrict_residual(Batch<T> b,
     if (idx >= C.n) return;
     int ci, cj, ck;
     decode<DIM>(idx, C.nx, C.ny, ci, cj, ck);
-    T su0 = 0, su1 = 0, su2 = 0, sr0 = 0, sr1 = 0, sr2 = 0, sb = 0;
+    T acc[7], half[7];
 #pragma unroll 1
-    for (int dz = 0; dz < (DIM == 3 ? 2 : 1); ++dz)
-        for (int dy = 0; dy < 2; ++dy)
-            for (int dx = 0; dx < 2; ++dx) {
-                const int fi = 2 * ci + dx, fj = 2 * cj + dy, fk = 2 * ck + dz;
-                const int f = (fk * F.ny + fj) * F.nx + fi;
-                T n0, n1, n2;
-                cell_operator<DIM, T, CORR>(F, f, fi, fj, fk, n0, n1, n2);
-                sr0 += F.f0[f] - n0;
-                sr1 += F.f1[f] - n1;
-                sr2 += F.f2[f] - n2;
-                su0 += F.phi[f];
-                su1 += F.mu[f];
-                su2 += F.p[f];
-                if (CORR) sb += F.b[f];
+    for (int q = 0; q < (DIM == 3 ? 4 : 2); ++q) {    // q = 2 dz + dy: one x pair
+        const int dy = q & 1, dz = q >> 1;
+        T a[7], c[7];
+        child_values<DIM, T, CORR>(F, 2 * ci, 2 * cj + dy, 2 * ck + dz, a);
+        child_values<DIM, T, CORR>(F, 2 * ci + 1, 2 * cj + dy, 2 * ck + dz, c);
+#pragma unroll
+        for (int k = 0; k < 7; ++k) a[k] = a[k] + c[k];
+        if (dy == 0) {
+#pragma unroll
+            for (int k = 0; k < 7; ++k) half[k] = a[k];
+        } else {
+#pragma unroll
+            for (int k = 0; k < 7; ++k) {
+                const T s = half[k] + a[k];
+                acc[k] = dz == 0 ? s : acc[k] + s;
             }
+        }
+    }
     const T w = DIM == 3 ? T(0.125) : T(0.25);
-    if (CORR) C.b[idx] = sb * w;
-    C.phi[idx] = C.ub0[idx] = su0 * w;
-    C.mu[idx] = C.ub1[idx] = su1 * w;
-    C.p[idx] = C.ub2[idx] = su2 * w;
-    C.fr0[idx] = sr0 * w;
-    C.fr1[idx] = sr1 * w;
-    C.fr2[idx] = sr2 * w;
+    if (CORR) C.b[idx] = acc[6] * w;
+    C.phi[idx] = C.ub0[idx] = acc[3] * w;
+    C.mu[idx] = C.ub1[idx] = acc[4] * w;
+    C.p[idx] = C.ub2[idx] = acc[5] * w;
+    C.fr0[idx] = acc[0] * w;
+    C.fr1[idx] = acc[1] * w;
+    C.fr2[idx] = acc[2] * w;
 }
 
 // Launches of at most this many tasks use the lane-parallel restriction below
@@ -282,11 +306,8 @@ __global__ __launch_bounds__(kBlock) void k_restrict_residual_lanes(Batch<T> b,
     int ci, cj, ck;
     decode<DIM>(idx, C.nx, C.ny, ci, cj, ck);
     const int fi = 2 * ci + (ch & 1), fj = 2 * cj + ((ch >> 1) & 1), fk = 2 * ck + (ch >> 2);
-    const int f = (fk * F.ny + fj) * F.nx + fi;
-    T n0, n1, n2;
-    cell_operator<DIM, T, CORR>(F, f, fi, fj, fk, n0, n1, n2);
-    T v[7] = {F.f0[f] - n0, F.f1[f] - n1, F.f2[f] - n2, F.phi[f], F.mu[f], F.p[f],
-              CORR ? F.b[f] : T(0)};
+    T v[7];
+    child_values<DIM, T, CORR>(F, fi, fj, fk, v);
 #pragma unroll
     for (int c = 0; c < 7; ++c) {
         if (!CORR && c == 6) continue;
@@ -376,7 +397,10 @@ __global__ __launch_bounds__(kBlock) void k_zero_correction(Batch<float> b32,
 //   R  = f - N(u') with the plain (2.5)-(2.7) operator,
 // written as u' into the other FP64 copy, R and b = u'_phi rounded to FP32
 // into the FP32 finest level's right-hand side and base state, and the block
-// partial sums of R^2 and p'.
+// partial sums of R^2 and p'.  An instance inactive in this refinement but
+// active in the previous one (was_active) copies its iterate into the other
+// copy, so that both copies hold it from then on and the alternation of the
+// copies leaves it current; later refinements skip it.
 // A thread takes a pair of x-adjacent cells (2 q, 2 q + 1): the finest level
 // has a coarser one, so its x extent is even and a task's 256 cells are 128
 // whole pairs of one row each.  The pair's own values and its y (and z)
@@ -388,7 +412,8 @@ template <int DIM>
 __global__ __launch_bounds__(kPairThreads) void k_mixed_residual(Batch<double> b64,
                                                                  Batch<float> b32,
                                                                  const CellTask* __restrict__ t,
-                                                                 int add, double* partial) {
+                                                                 int add, const int* was_active,
+                                                                 double* partial) {
     typedef double D2 __attribute__((ext_vector_type(2)));
     typedef float F2 __attribute__((ext_vector_type(2)));
     const int task = xcd_task();
@@ -504,9 +529,9 @@ __global__ __launch_bounds__(kPairThreads) void k_mixed_residual(Batch<double> b
             v[2] = ra2 * ra2 + rb2 * rb2;
             v[3] = pc.x + pc.y;
         }
-    } else if (add && idx < L.n) {
-        // an instance that has converged keeps its iterate in both copies, so
-        // that it is still the current one after the step flips the copies
+    } else if (add && idx < L.n && (was_active == nullptr || was_active[tk.inst] != 0)) {
+        // an instance that has just converged keeps its iterate in both copies,
+        // so that it is still the current one after the step flips the copies
         const int h = idx >> 1;
         gstore(reinterpret_cast<D2*>(L.phi_alt), h, gload(reinterpret_cast<const D2*>(L.phi), h));
         gstore(reinterpret_cast<D2*>(L.mu_alt), h, gload(reinterpret_cast<const D2*>(L.mu), h));
@@ -779,6 +804,14 @@ __global__ __launch_bounds__(kBlock) void k_copy_int(int* dst, const int* src, i
     if (i < n) dst[i] = src[i];
 }
 
+__global__ __launch_bounds__(kBlock) void k_roll_flags(int* last, int* cur, const int* next, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        last[i] = cur[i];
+        cur[i] = next[i];
+    }
+}
+
 inline int blocks_for(int n) { return (n + kBlock - 1) / kBlock; }
 
 }  // namespace
@@ -898,14 +931,15 @@ void launch_zero_correction(const Batch<float>& b32, const CellTask* t, int nt, 
 }
 
 void launch_mixed_residual(int dim, const Batch<double>& b64, const Batch<float>& b32,
-                           const CellTask* t, int nt, int add, double* partial, hipStream_t st) {
+                           const CellTask* t, int nt, int add, const int* was_active,
+                           double* partial, hipStream_t st) {
     if (nt <= 0) return;
     if (dim == 2)
         hipLaunchKernelGGL(k_mixed_residual<2>, dim3(nt), dim3(kPairThreads), 0, st, b64, b32, t,
-                           add, partial);
+                           add, was_active, partial);
     else
         hipLaunchKernelGGL(k_mixed_residual<3>, dim3(nt), dim3(kPairThreads), 0, st, b64, b32, t,
-                           add, partial);
+                           add, was_active, partial);
 }
 
 void launch_residual_partials(int dim, const Batch<double>& b, const CellTask* t, int nt,
@@ -968,6 +1002,11 @@ void launch_fill_int(int* dst, int n, int value, hipStream_t st) {
 
 void launch_copy_int(int* dst, const int* src, int n, hipStream_t st) {
     if (n > 0) hipLaunchKernelGGL(k_copy_int, dim3(blocks_for(n)), dim3(kBlock), 0, st, dst, src, n);
+}
+
+void launch_roll_flags(int* last, int* cur, const int* next, int n, hipStream_t st) {
+    if (n > 0)
+        hipLaunchKernelGGL(k_roll_flags, dim3(blocks_for(n)), dim3(kBlock), 0, st, last, cur, next, n);
 }
 
 }  // namespace chhs

@@ -34,6 +34,8 @@
 //          averaging: u_c = ub_c = R u, fr_c = R R on level + 1 (copy b.cur_c).
 //   EPI 2  per-task partial sums of R_phi^2, R_mu^2, R_p^2 and p.
 //   CORR   correction form of the mixed-precision inner solve.
+//   ZERO   first launch of a correction cycle on the finest level (CORR): the
+//          correction starts at zero and is not read.
 #include <type_traits>
 
 #include "chhs_cell.hpp"
@@ -81,7 +83,7 @@ __device__ __forceinline__ int col(int c) { return (c & 1) * kHalf + (c >> 1); }
 
 // Three workgroups per compute unit (the LDS ring allows it) need at most 168
 // VGPRs: requested for the finest-level variants.
-template <typename T, bool LEVEL0, int NS, int EPI, bool PRO, bool CORR>
+template <typename T, bool LEVEL0, int NS, int EPI, bool PRO, bool CORR, bool ZERO>
 __global__ __launch_bounds__(kThreads)
 __attribute__((amdgpu_waves_per_eu(LEVEL0 || CORR ? 3 : 1))) void k_stream2d(Batch<T> bt,
                                                        const StripTask* __restrict__ tasks,
@@ -157,8 +159,15 @@ __attribute__((amdgpu_waves_per_eu(LEVEL0 || CORR ? 3 : 1))) void k_stream2d(Bat
     auto load_row = [&](T (&v)[2], T (&vc)[2], T (&vb)[2], int r) {
         const bool ok = lcol && r >= ys && r < ye;
         const int g = ok ? r * nx + lgx : 0;
+        // ZERO: only phi_* is read (by both halves, so that every wave issues
+        // the same loads; the second read of a row hits the cache)
+        if (ZERO) {
+            v[0] = T(0);
+            v[1] = gload_stream(L.pstar, g);
+        } else {
 #pragma unroll
-        for (int j = 0; j < 2; ++j) v[j] = gload_stream(src[j], g);
+            for (int j = 0; j < 2; ++j) v[j] = gload_stream(src[j], g);
+        }
         if (PRO) {
             const int cg = ok ? (r >> 1) * C.nx + (lgx >> 1) : 0;
 #pragma unroll
@@ -175,6 +184,7 @@ __attribute__((amdgpu_waves_per_eu(LEVEL0 || CORR ? 3 : 1))) void k_stream2d(Bat
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
             T x = lcol ? (j == 1 ? v[j] - psh : v[j]) : T(0);
+            if (ZERO && (j == 0 || half == 0)) x = T(0);
             // prolongation of the correction onto phi, mu, p (not phi_*)
             if (PRO && lcol && (j == 0 || half == 0)) x += vc[j] - vb[j];
             s[slot][2 * j + half][w] = x;
@@ -499,17 +509,18 @@ drained:
         }
 }
 
-template <typename T, bool LEVEL0, int NS, int EPI, bool PRO, bool CORR>
+template <typename T, bool LEVEL0, int NS, int EPI, bool PRO, bool CORR, bool ZERO = false>
 void launch_one(const Batch<T>& b, const StripTask* t, int nt, double* partial, hipStream_t st) {
-    hipLaunchKernelGGL((k_stream2d<T, LEVEL0, NS, EPI, PRO, CORR>), dim3(nt), dim3(kThreads), 0,
-                       st, b, t, nt, partial);
+    hipLaunchKernelGGL((k_stream2d<T, LEVEL0, NS, EPI, PRO, CORR, ZERO>), dim3(nt), dim3(kThreads),
+                       0, st, b, t, nt, partial);
 }
 
 }  // namespace
 
 template <>
 void launch_stream2d<double>(const Batch<double>& b, const StripTask* t, int nt, bool level0,
-                             int ns, int epi, bool pro, double* partial, hipStream_t st) {
+                             int ns, int epi, bool pro, bool zero, double* partial, hipStream_t st) {
+    (void)zero;
     if (nt <= 0) return;
 #define CHHS_STRIP_CASE(L0, NS, EPI, PRO)                                         \
     if (level0 == L0 && ns == NS && epi == EPI && pro == PRO) {                   \
@@ -529,9 +540,23 @@ void launch_stream2d<double>(const Batch<double>& b, const StripTask* t, int nt,
 
 template <>
 void launch_stream2d<float>(const Batch<float>& b, const StripTask* t, int nt, bool level0, int ns,
-                            int epi, bool pro, double* partial, hipStream_t st) {
+                            int epi, bool pro, bool zero, double* partial, hipStream_t st) {
     (void)level0;
     if (nt <= 0) return;
+    if (zero) {
+        if (pro || epi == 2) return;
+#define CHHS_STRIP_ZERO(NS, EPI)                                                  \
+    if (ns == NS && epi == EPI) {                                                 \
+        launch_one<float, false, NS, EPI, false, true, true>(b, t, nt, partial, st); \
+        return;                                                                   \
+    }
+        CHHS_STRIP_ZERO(1, 0)
+        CHHS_STRIP_ZERO(1, 1)
+        CHHS_STRIP_ZERO(2, 0)
+        CHHS_STRIP_ZERO(2, 1)
+#undef CHHS_STRIP_ZERO
+        return;
+    }
 #define CHHS_STRIP_CASE(NS, EPI, PRO)                                             \
     if (ns == NS && epi == EPI && pro == PRO) {                                   \
         launch_one<float, false, NS, EPI, PRO, true>(b, t, nt, partial, st);      \

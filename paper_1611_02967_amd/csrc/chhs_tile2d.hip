@@ -27,6 +27,9 @@
 //          right-hand side f += N(u) (u = the restricted iterate, f = the
 //          restricted residual) on every cell a phase may update, the block's
 //          cells written back; replaces a separate launch over the level.
+//   ZERO   the first launch of an inner correction cycle on the finest level
+//          (CORR): the correction starts at zero, so u is not read but taken
+//          as 0 (and no pass clears it beforehand).
 //
 // Threads own pairs of horizontally adjacent cells (x even, x + 1) so that
 // exactly one cell of every pair has the color of a phase: all lanes work in
@@ -61,7 +64,8 @@ struct Geometry {
 template <int PW>
 __device__ __forceinline__ int lds(int r, int x) { return (2 * r + (x & 1)) * PW + (x >> 1); }
 
-template <typename T, bool LEVEL0, int NS, int EPI, bool PRO, bool CORR, int NT, bool RHS, int TY>
+template <typename T, bool LEVEL0, int NS, int EPI, bool PRO, bool CORR, int NT, bool RHS, int TY,
+          bool ZERO>
 __global__ __launch_bounds__(NT) void k_tile2d(Batch<T> bt, const TileTask* __restrict__ tasks,
                                                int ntiles, double* partial) {
     using G = Geometry<NS, EPI, NT, TY>;
@@ -111,9 +115,9 @@ __global__ __launch_bounds__(NT) void k_tile2d(Batch<T> bt, const TileTask* __re
             T phi = 0, mu = 0, p = 0, ps = 0, psi = 0, f0 = 0, f1 = 0, f2 = 0, bs = 0;
             if (q < NP && gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
                 const int g = gy * nx + gx;
-                phi = gload(L.phi, g);
-                mu = gload(L.mu, g);
-                p = gload(L.p, g) - psh;
+                phi = ZERO ? T(0) : gload(L.phi, g);
+                mu = ZERO ? T(0) : gload(L.mu, g);
+                p = ZERO ? T(0) : gload(L.p, g) - psh;
                 ps = gload(L.pstar, g);
                 psi = gload(L.psi, g);
                 // the first launch on a coarse level forms f from the restricted residual
@@ -436,43 +440,48 @@ __global__ __launch_bounds__(NT) void k_tile2d(Batch<T> bt, const TileTask* __re
         }
 }
 
-template <typename T, bool LEVEL0, int NS, int EPI, bool PRO, bool CORR, bool RHS, int TY>
+template <typename T, bool LEVEL0, int NS, int EPI, bool PRO, bool CORR, bool RHS, int TY,
+          bool ZERO>
 void launch_ty(const Batch<T>& b, const TileTask* t, int nt, int threads, double* partial,
                hipStream_t st) {
     if (threads == 1024)
-        hipLaunchKernelGGL((k_tile2d<T, LEVEL0, NS, EPI, PRO, CORR, 1024, RHS, TY>), dim3(nt),
+        hipLaunchKernelGGL((k_tile2d<T, LEVEL0, NS, EPI, PRO, CORR, 1024, RHS, TY, ZERO>), dim3(nt),
                            dim3(1024), 0, st, b, t, nt, partial);
     else if (threads == 512)
-        hipLaunchKernelGGL((k_tile2d<T, LEVEL0, NS, EPI, PRO, CORR, 512, RHS, TY>), dim3(nt),
+        hipLaunchKernelGGL((k_tile2d<T, LEVEL0, NS, EPI, PRO, CORR, 512, RHS, TY, ZERO>), dim3(nt),
                            dim3(512), 0, st, b, t, nt, partial);
     else
-        hipLaunchKernelGGL((k_tile2d<T, LEVEL0, NS, EPI, PRO, CORR, 256, RHS, TY>), dim3(nt),
+        hipLaunchKernelGGL((k_tile2d<T, LEVEL0, NS, EPI, PRO, CORR, 256, RHS, TY, ZERO>), dim3(nt),
                            dim3(256), 0, st, b, t, nt, partial);
 }
 
-// Finest-level variants exist for 64 x 16 tiles only.
-template <typename T, bool LEVEL0, int NS, int EPI, bool PRO, bool CORR, bool RHS = false>
+// Finest-level variants (LEVEL0, ZERO) exist for 64 x 16 tiles only.
+template <typename T, bool LEVEL0, int NS, int EPI, bool PRO, bool CORR, bool RHS = false,
+          bool ZERO = false>
 void launch_one(const Batch<T>& b, const TileTask* t, int nt, int threads, int ty, double* partial,
                 hipStream_t st) {
-    if constexpr (!LEVEL0) {
+    if constexpr (!LEVEL0 && !ZERO) {
         if (ty == kTileYSmall) {
-            launch_ty<T, LEVEL0, NS, EPI, PRO, CORR, RHS, kTileYSmall>(b, t, nt, threads, partial, st);
+            launch_ty<T, LEVEL0, NS, EPI, PRO, CORR, RHS, kTileYSmall, false>(b, t, nt, threads,
+                                                                             partial, st);
             return;
         }
         if (ty == kTileYTiny) {
-            launch_ty<T, LEVEL0, NS, EPI, PRO, CORR, RHS, kTileYTiny>(b, t, nt, threads, partial, st);
+            launch_ty<T, LEVEL0, NS, EPI, PRO, CORR, RHS, kTileYTiny, false>(b, t, nt, threads,
+                                                                            partial, st);
             return;
         }
     }
-    launch_ty<T, LEVEL0, NS, EPI, PRO, CORR, RHS, kTileY>(b, t, nt, threads, partial, st);
+    launch_ty<T, LEVEL0, NS, EPI, PRO, CORR, RHS, kTileY, ZERO>(b, t, nt, threads, partial, st);
 }
 
 }  // namespace
 
 template <>
 void launch_tile2d<double>(const Batch<double>& b, const TileTask* t, int nt, bool level0, int ns,
-                           int epi, bool pro, int threads, bool rhs, int ty, double* partial,
-                           hipStream_t st) {
+                           int epi, bool pro, int threads, bool rhs, int ty, bool zero,
+                           double* partial, hipStream_t st) {
+    (void)zero;
     if (nt <= 0) return;
     if (rhs) {
         // first pre-smoothing launch of a coarse level (no prolongation)
@@ -509,10 +518,25 @@ void launch_tile2d<double>(const Batch<double>& b, const TileTask* t, int nt, bo
 // sides, no norm epilogue.
 template <>
 void launch_tile2d<float>(const Batch<float>& b, const TileTask* t, int nt, bool level0, int ns,
-                          int epi, bool pro, int threads, bool rhs, int ty, double* partial,
-                          hipStream_t st) {
+                          int epi, bool pro, int threads, bool rhs, int ty, bool zero,
+                          double* partial, hipStream_t st) {
     (void)level0;
     if (nt <= 0) return;
+    if (zero) {
+        // first launch of a correction cycle on the finest level (64 x 16 tiles)
+        if (pro || rhs || epi == 2 || ty != kTileY) return;
+#define CHHS_TILE_ZERO(NS, EPI)                                                   \
+    if (ns == NS && epi == EPI) {                                                 \
+        launch_one<float, false, NS, EPI, false, true, false, true>(b, t, nt, threads, ty, partial, st); \
+        return;                                                                   \
+    }
+        CHHS_TILE_ZERO(1, 0)
+        CHHS_TILE_ZERO(1, 1)
+        CHHS_TILE_ZERO(2, 0)
+        CHHS_TILE_ZERO(2, 1)
+#undef CHHS_TILE_ZERO
+        return;
+    }
     if (rhs) {
         if (pro || epi == 2) return;
 #define CHHS_TILE_RHS(NS, EPI)                                                    \

@@ -117,6 +117,28 @@ def test_workspace_bytes_rejects_invalid_problems(binding):
         assert binding.chhs_workspace_bytes([good], binding.chhs_default_opts(tile_rows=rows)) == 0
 
 
+def test_sizes_beyond_32_bit_indexing_are_rejected_on_the_host(binding):
+    """Kernels address a field with a 32-bit byte offset and packed caller
+    arrays with int offsets: an instance of 2^29 cells or more (an FP64 field of
+    4 GiB) and a batch of more than 2^31 - 1 cells are refused before any
+    table is built or any device work is enqueued."""
+    o = binding.chhs_default_opts()
+    below = binding.make_problem((256, 1024, 1024), 1 / 1024, 0.05, 1.0, 1e-3)   # 2^28 cells
+    at = binding.make_problem((512, 1024, 1024), 1 / 1024, 0.05, 1.0, 1e-3)     # 2^29 cells
+    wide = binding.make_problem((768, 1024, 1024), 1 / 1024, 0.05, 1.0, 1e-3)   # 768 = 3 * 2^8
+    assert binding.chhs_workspace_bytes([below], o) > 0
+    assert binding.chhs_workspace_bytes([at], o) == 0
+    assert binding.chhs_workspace_bytes([wide], o) == 0
+    # eight instances of 2^28 cells: each passes alone, together they hold
+    # 2^31 cells, one more than int offsets reach (refused before the tables)
+    assert binding.chhs_workspace_bytes([below] * 8, o) == 0
+    arr = (binding.chhs_problem * 1)(at)
+    handle = ctypes.c_void_p()
+    rc = binding._lib.chhs_init(arr, 1, ctypes.byref(o), ctypes.c_void_p(1 << 20), 1 << 62, None,
+                                ctypes.byref(handle))
+    assert rc == binding.CHHS_E_INVAL and not handle.value
+
+
 def test_workspace_accounts_for_every_level(binding):
     """11 arrays per coarse level and 8 on the finest, 256-byte aligned."""
     o = binding.chhs_default_opts()
@@ -155,6 +177,7 @@ def test_strerror_covers_every_code(binding):
 def test_entry_points_reject_null_context(binding):
     assert binding._lib.chhs_fas_vcycle(None, None) == binding.CHHS_E_INVAL
     assert binding._lib.chhs_step(None, None, None, None, None, 1, None) == binding.CHHS_E_INVAL
+    assert binding._lib.chhs_step_log(None, None, None, None, None, 1, None) == binding.CHHS_E_INVAL
     assert binding._lib.chhs_energy_mass(None, None, None, None) == binding.CHHS_E_INVAL
     assert binding._lib.chhs_graph_count(None, None) == binding.CHHS_E_INVAL
     assert binding._lib.chhs_set_timing(None, 0) == binding.CHHS_E_INVAL

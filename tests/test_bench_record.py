@@ -1,40 +1,51 @@
 """Host checks of bench.py's measurement records (no GPU).
 
-The committed counter record of the finest-level launches
-(profiles/traffic_k_stream2d_2048_fp64.json) must carry every key that
-bench.measured_traffic compares before it reports `traffic`: the workload, the
-hash of the kernel sources it was measured on, the finest level's kernel
-configuration and the bytes of each launch class.  A record missing one of
-them makes the bench report `traffic: null` whatever the sources.
+The committed counter records (profiles/traffic.json, one per workload) must
+carry every key that bench.measured_traffic compares before it reports
+`traffic`: the sources the counters were taken on and their hash, the finest
+level's kernel configuration and the bytes of each launch class.  A record
+missing one of them makes the bench report `traffic: null` whatever the
+sources.
 """
 import json
+import os
 
 import bench
 
 
-def test_traffic_record_has_what_the_bench_compares():
+def _records():
     with open(bench.TRAFFIC_FILE) as fh:
-        rec = json.load(fh)
-    assert rec["workload"] == "2d-2048-fp64"
-    assert len(rec["source_sha256"]) == 64
-    kind, param, blocks = rec["level0_kernel"]
-    assert kind in ("strips", "tiles") and param > 0 and blocks > 0
-    for cls in ("pre0", "post0"):
-        e = rec["launches"][cls]
-        assert e["bytes_per_launch"] > e["algorithmic_bytes_per_launch"] > 0
+        return json.load(fh)
+
+
+def test_traffic_records_have_what_the_bench_compares():
+    recs = _records()
+    assert recs, "no counter record"
+    for workload, rec in recs.items():
+        assert rec["workload"] == workload
+        assert len(rec["source_sha256"]) == 64
+        assert rec["sources"] and all(os.path.exists(os.path.join(bench.ROOT, f))
+                                      for f in rec["sources"])
+        kind, param, blocks = rec["level0_kernel"]
+        assert kind in ("strips", "tiles") and param > 0 and blocks > 0
+        assert rec["launches"]
+        for cls, e in rec["launches"].items():
+            assert cls in ("pre0", "post0", "refine")
+            assert e["bytes_per_launch"] > 0 and e["algorithmic_bytes_per_launch"] > 0
 
 
 def test_measured_traffic_is_reported_only_for_the_measured_configuration(monkeypatch):
-    with open(bench.TRAFFIC_FILE) as fh:
-        rec = json.load(fh)
-    monkeypatch.setattr(bench, "kernel_source_hash", lambda: rec["source_sha256"])
+    recs = _records()
+    workload, rec = next(iter(recs.items()))
+    cls = next(iter(rec["launches"]))
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda sources: rec["source_sha256"])
     lk = rec["level0_kernel"]
-    got = bench.measured_traffic("2d-2048-fp64", "post0", tuple(lk))
-    assert got == rec["launches"]["post0"]["bytes_per_launch"]
-    assert bench.measured_traffic("2d-1024-fp64", "post0", tuple(lk)) is None
-    assert bench.measured_traffic("2d-2048-fp64", "post0", ("tiles", 512, 4096)) is None
-    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 64)
-    assert bench.measured_traffic("2d-2048-fp64", "post0", tuple(lk)) is None
+    got = bench.measured_traffic(workload, cls, tuple(lk))
+    assert got["bytes_per_launch"] == rec["launches"][cls]["bytes_per_launch"]
+    assert bench.measured_traffic("no-such-workload", cls, tuple(lk)) is None
+    assert bench.measured_traffic(workload, cls, ("tiles", 7, 4096)) is None
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda sources: "0" * 64)
+    assert bench.measured_traffic(workload, cls, tuple(lk)) is None
 
 
 def test_vcycle_bytes_counts_every_launch_of_the_cycle():
