@@ -224,6 +224,23 @@ int chhs_get_solution(chhs_ctx* c, double* phi, double* mu, double* p);
  * are those given to chhs_init. */
 int chhs_energy_mass(chhs_ctx* c, const double* phi, const double* phi_prev, double* out_host);
 
+/* The mass, E_h and F_h of chhs_energy_mass for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops): no
+ * context, no hipMalloc / hipFree or other allocating call.  p[0..n_inst-1]:
+ * the instances (dim 2 or 3, one dim for all, extents >= 1, h > 0, eps > 0;
+ * only these fields are read), at most 32 instances, fewer than 2^29 cells
+ * each and at most 2^31 - 1 in all; CHHS_E_INVAL otherwise.  phi, phi_prev:
+ * device arrays packed instance after instance as everywhere in this ABI.
+ * out_dev: DEVICE memory, [n_inst][3] = mass, E_h, F_h, written on
+ * hip_stream (NULL = the null stream) when the work enqueued there runs; the
+ * call returns after enqueuing and does not synchronise.  The partial sums live
+ * in a fixed 512 KiB device array of the library (one per GPU, held until the
+ * process ends); calls that overlap on one GPU race for it and must be
+ * ordered by the caller (one stream, or events).  CHHS_E_HIP if a launch
+ * fails. */
+int chhs_energy_mass_noalloc(const chhs_problem* p, int32_t n_inst, const double* phi,
+                             const double* phi_prev, double* out_dev, void* hip_stream);
+
 /* Level-by-level access for kernel-level tests.  field: 0 phi, 1 mu, 2 p,
  * 3 f_phi, 4 f_mu, 5 f_p, 6 phi_*, 7 phi^m (psi).  dir 0: level -> dev,
  * dir 1: dev -> level.  Single-instance contexts only. */

@@ -85,6 +85,8 @@ _SIGS = {
     "chhs_residual_norms": (_I, [_P, ctypes.POINTER(ctypes.c_double)]),
     "chhs_get_solution": (_I, [_P, _P, _P, _P]),
     "chhs_energy_mass": (_I, [_P, _P, _P, ctypes.POINTER(ctypes.c_double)]),
+    "chhs_energy_mass_noalloc": (_I, [ctypes.POINTER(chhs_problem), ctypes.c_int32, _P, _P, _P,
+                                      _P]),
     "chhs_level_count": (_I, [_P, ctypes.POINTER(ctypes.c_int32)]),
     "chhs_level_shape": (_I, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     "chhs_level_kernel": (_I, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
@@ -213,6 +215,17 @@ def chhs_energy_mass(ctx, phi, phi_prev, n_inst=1):
     out = (ctypes.c_double * (3 * n_inst))()
     _check(_lib.chhs_energy_mass(ctx, _ptr(phi), _ptr(phi_prev), out), "chhs_energy_mass")
     return [list(out[3 * i:3 * i + 3]) for i in range(n_inst)]
+
+
+def chhs_energy_mass_noalloc(problems, phi, phi_prev, out, stream=None):
+    """Enqueues mass, E_h, F_h of every instance into ``out`` (a float64 device
+    tensor of 3 * len(problems) values) on ``stream`` (torch's current stream
+    by default); allocates nothing."""
+    arr = (chhs_problem * len(problems))(*problems)
+    st = torch.cuda.current_stream() if stream is None else stream
+    _check(_lib.chhs_energy_mass_noalloc(arr, len(problems), _ptr(phi), _ptr(phi_prev), _ptr(out),
+                                         ctypes.c_void_p(st.cuda_stream)),
+           "chhs_energy_mass_noalloc")
 
 
 def chhs_level_count(ctx):
