@@ -103,7 +103,14 @@ typedef struct chhs_problem {
  * phi_* := phi^m, the convex part of chi fully implicit, chi(phi) = phi^3, the
  * whole eps^2 Lap phi implicit (kap = eps^2/h^2) and f_mu = -phi^m; phi_prev
  * is not read.  order = 1 needs precision = 0 and smooths every level with the
- * per-cell red-black kernels. */
+ * per-cell red-black kernels.
+ * nu1_coarse, nu2_coarse: smoothing steps before / after the coarse
+ * correction on the levels between the finest and the coarsest (0 = nu1,
+ * nu2 as on the finest level; Section 5 uses V(2,2) on every level).
+ * prolong = 0 (default) prolongs the coarse correction by piecewise-constant
+ * injection, 1 by cell-centred bi/trilinear interpolation (3/4, 1/4 along each
+ * axis, continued evenly across the boundary); Section 5 leaves the transfer
+ * operators open, and both converge to the same solution (Theorem 2.1). */
 typedef struct chhs_opts {
     int32_t nu1, nu2, max_vcycles, coarse_sweeps;
     double tol;
@@ -115,6 +122,8 @@ typedef struct chhs_opts {
     int32_t order;
     int32_t tile_threads;
     int32_t tile_rows;
+    int32_t nu1_coarse, nu2_coarse;
+    int32_t prolong;
 } chhs_opts;
 
 /* Kernel classes of chhs_timing. */
@@ -278,6 +287,25 @@ int chhs_get_timing(chhs_ctx* c, chhs_timing* out, int32_t reset);
  * graphs are dropped when the mask changes (they are captured again when
  * timing is 0).  CHHS_E_INVAL for a negative mask. */
 int chhs_set_timing(chhs_ctx* c, int32_t timing);
+
+/* Chooses the sweeps per level and the prolongation by time to tolerance:
+ * on the system of the step from (phi_prev, phi_cur) with initial guess (mu,
+ * p) (device arrays, read only; the state is not advanced), solves the step
+ * to tol once for each of a fixed set of candidates (nu1, nu2 on the finest
+ * level, nu1_coarse, nu2_coarse below it, prolong), times the solve (setup
+ * and cycles, after one untimed solve that captures the cycle graphs) and
+ * keeps the fastest in the context's options.  Candidates that do not reach
+ * tol within max_vcycles are skipped.  The solution is the same to tol for
+ * every candidate (Theorem 2.1: one solution per step); only the time and the
+ * cycle count differ.  choice_out (host, or NULL): the kept nu1, nu2,
+ * nu1_coarse, nu2_coarse, prolong.  CHHS_E_NOCONV if no candidate converges
+ * (options unchanged). */
+int chhs_tune_sweeps(chhs_ctx* c, const double* phi_prev, const double* phi_cur, const double* mu,
+                     const double* p, int32_t* choice_out);
+
+/* The context's options as they are now (after chhs_tune_sweeps or
+ * chhs_set_timing). */
+int chhs_get_opts(chhs_ctx* c, chhs_opts* out);
 
 /* Releases the context (not the caller's workspace).  NULL is ignored. */
 void chhs_destroy(chhs_ctx* c);

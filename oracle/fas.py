@@ -21,7 +21,12 @@ tol = 1e-10, and omits everything else.  The reading written out here:
   the gamma a^2 part of M and the a grad p flux nearly cancel in the true
   operator but not in the lagged one.
 * Transfers: restriction = average of the 2^d children; prolongation =
-  piecewise-constant injection of the coarse correction.
+  piecewise-constant injection of the coarse correction (``Opts.prolong =
+  "bilinear"``: cell-centred bi/trilinear interpolation of the correction,
+  weights 3/4 and 1/4 along each axis, the coarse correction continued evenly
+  across the boundary as the Neumann ghost cells of App. A.1 continue a field).
+* Sweeps per level: nu1, nu2 on the finest level; ``Opts.nu1_coarse`` /
+  ``nu2_coarse`` (0: the same) on the coarser levels above the coarsest.
 * FAS coarse problem: u_c = R u, f_c = R(f - N(u)) + N_c(u_c); after the coarse
   solve u += P(u_c_new - u_c).
 * Coarsest level: a fixed number of smoothing steps (default 4; 2 to 50 give
@@ -49,6 +54,15 @@ class Opts:
     tol: float = 1e-10
     max_vcycles: int = 100
     coarse_sweeps: int = 4
+    nu1_coarse: int = 0          # 0: nu1 on every level
+    nu2_coarse: int = 0          # 0: nu2 on every level
+    prolong: str = "constant"    # or "bilinear"
+
+    def sweeps(self, l):
+        """(pre, post) smoothing steps on level l (l = 0 the finest)."""
+        if l == 0:
+            return self.nu1, self.nu2
+        return self.nu1_coarse or self.nu1, self.nu2_coarse or self.nu2
 
 
 def color_mask(shape, color):
@@ -155,6 +169,31 @@ def prolong(v):
     return out
 
 
+def prolong_bilinear(v):
+    """Cell-centred linear interpolation along every axis in turn: fine cell 2i
+    takes 3/4 of coarse cell i and 1/4 of cell i - 1, fine cell 2i + 1 3/4 of
+    cell i and 1/4 of cell i + 1; beyond the boundary the coarse cell itself
+    (even continuation)."""
+    out = v
+    for ax in range(v.ndim):
+        n = out.shape[ax]
+        lo = np.take(out, np.maximum(np.arange(n) - 1, 0), axis=ax)
+        hi = np.take(out, np.minimum(np.arange(n) + 1, n - 1), axis=ax)
+        even = 0.75 * out + 0.25 * lo
+        odd = 0.75 * out + 0.25 * hi
+        shape = list(out.shape)
+        shape[ax] = 2 * n
+        new = np.empty(shape)
+        idx_even = [slice(None)] * out.ndim
+        idx_odd = [slice(None)] * out.ndim
+        idx_even[ax] = slice(0, 2 * n, 2)
+        idx_odd[ax] = slice(1, 2 * n, 2)
+        new[tuple(idx_even)] = even
+        new[tuple(idx_odd)] = odd
+        out = new
+    return out
+
+
 def coarsenable(shape):
     return all(n % 2 == 0 and n // 2 >= 2 for n in shape)
 
@@ -175,7 +214,8 @@ def vcycle(levels, us, l, prm, opts):
         for _ in range(opts.coarse_sweeps):
             sweep(u, lvl, prm)
         return
-    for _ in range(opts.nu1):
+    nu1, nu2 = opts.sweeps(l)
+    for _ in range(nu1):
         sweep(u, lvl, prm)
     r = residual(u, lvl.f, lvl, prm)
     c = levels[l + 1]
@@ -185,9 +225,10 @@ def vcycle(levels, us, l, prm, opts):
     c.f = [restrict(r[k]) + nc[k] for k in range(3)]
     us[l + 1] = uc
     vcycle(levels, us, l + 1, prm, opts)
+    interp = prolong_bilinear if opts.prolong == "bilinear" else prolong
     for k in range(3):
-        u[k] += prolong(us[l + 1][k] - ubar[k])
-    for _ in range(opts.nu2):
+        u[k] += interp(us[l + 1][k] - ubar[k])
+    for _ in range(nu2):
         sweep(u, lvl, prm)
 
 

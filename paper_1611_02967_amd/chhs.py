@@ -38,7 +38,8 @@ class chhs_opts(ctypes.Structure):
                 ("use_graph", ctypes.c_int32), ("timing", ctypes.c_int32),
                 ("smoother", ctypes.c_int32), ("autotune", ctypes.c_int32),
                 ("order", ctypes.c_int32), ("tile_threads", ctypes.c_int32),
-                ("tile_rows", ctypes.c_int32)]
+                ("tile_rows", ctypes.c_int32), ("nu1_coarse", ctypes.c_int32),
+                ("nu2_coarse", ctypes.c_int32), ("prolong", ctypes.c_int32)]
 
 
 K_CLASSES = ["pre0", "post0", "transfer0", "coarse", "norm", "setup", "refine", "k7"]
@@ -96,6 +97,8 @@ _SIGS = {
     "chhs_restrict": (_I, [_P, ctypes.c_int32]),
     "chhs_get_timing": (_I, [_P, ctypes.POINTER(chhs_timing), ctypes.c_int32]),
     "chhs_set_timing": (_I, [_P, ctypes.c_int32]),
+    "chhs_tune_sweeps": (_I, [_P, _P, _P, _P, _P, ctypes.POINTER(ctypes.c_int32)]),
+    "chhs_get_opts": (_I, [_P, ctypes.POINTER(chhs_opts)]),
     "chhs_destroy": (None, [_P]),
     "chhs_strerror": (ctypes.c_char_p, [_I]),
 }
@@ -281,6 +284,21 @@ def chhs_set_timing(ctx, timing):
     _check(_lib.chhs_set_timing(ctx, int(timing)), "chhs_set_timing")
 
 
+def chhs_tune_sweeps(ctx, phi_prev, phi_cur, mu, p):
+    """Sweeps per level and prolongation chosen by time to tolerance; returns the
+    kept (nu1, nu2, nu1_coarse, nu2_coarse, prolong)."""
+    out = (ctypes.c_int32 * 5)()
+    _check(_lib.chhs_tune_sweeps(ctx, _ptr(phi_prev), _ptr(phi_cur), _ptr(mu), _ptr(p), out),
+           "chhs_tune_sweeps")
+    return tuple(out)
+
+
+def chhs_get_opts(ctx):
+    o = chhs_opts()
+    _check(_lib.chhs_get_opts(ctx, ctypes.byref(o)), "chhs_get_opts")
+    return o
+
+
 def chhs_destroy(ctx):
     _lib.chhs_destroy(ctx)
 
@@ -357,6 +375,13 @@ class Solver:
     def energy_mass(self, phi, phi_prev):
         self._check_arrays(phi, phi_prev)
         return chhs_energy_mass(self.ctx, phi, phi_prev, self.n_inst)
+
+    def tune_sweeps(self, phi_prev, phi_cur, mu, p):
+        self._check_arrays(phi_prev, phi_cur, mu, p)
+        return chhs_tune_sweeps(self.ctx, phi_prev, phi_cur, mu, p)
+
+    def get_opts(self):
+        return chhs_get_opts(self.ctx)
 
     def timing(self, reset=False):
         return chhs_get_timing(self.ctx, reset)

@@ -7,6 +7,7 @@
 // cycle), the mixed-precision iterative refinement, and the time-step loop
 // with its state rotation.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <type_traits>
@@ -72,6 +73,10 @@ struct Layout {
     std::vector<int> tail_insts;
     std::vector<CellTask> A0n;              // finest-level cells of instances without a fused norm
     std::vector<CellTask> A0t;              // finest-level cells of instances held by the tail
+    std::vector<StripTask> M0;              // 2D mixed: row-marching refinement tasks
+    std::vector<Range> rngM0, rngM0f;
+    std::vector<FoldTask> FM0;
+    int march_seg = 0;
     std::vector<Range> rngA0, rngT0, rngA0n;
     // folds of the partials over A[0] / A0n (empty when no instance has more
     // than kFold of them) and the per-instance ranges of the folded partials
@@ -88,6 +93,7 @@ struct Layout {
     size_t off_desc = 0, off_desc32 = 0, off_info = 0, off_tail = 0, off_rngA0 = 0, off_rngT0 = 0,
            off_rngA0n = 0;
     size_t off_A0n = 0, off_A0t = 0, off_partial_t = 0;
+    size_t off_M0 = 0, off_rngM0 = 0, off_rngM0f = 0, off_FM0 = 0;
     size_t off_FA0 = 0, off_FA0n = 0, off_rngA0f = 0, off_rngA0nf = 0, off_partial_f = 0;
     size_t off_partial = 0, off_res = 0, off_eres = 0, off_act_cycle = 0, off_act_next = 0,
            off_cycles = 0, off_act_last = 0;
@@ -116,6 +122,10 @@ struct chhs_ctx {
     Table<TileTask> T[kMaxLevels], Tall[kMaxLevels];
     Table<StripTask> S[kMaxLevels], Sall[kMaxLevels];
     Table<CellTask> A0n, A0t;
+    Table<StripTask> M0;
+    Table<FoldTask> FM0;
+    Range* rngM0 = nullptr;
+    Range* rngM0f = nullptr;
     Table<FoldTask> FA0, FA0n;
     int* tail_insts = nullptr;
     Range* rngA0 = nullptr;
@@ -212,7 +222,17 @@ bool valid_opts(const chhs_opts* o) {
     if (o->tile_rows != 0 && o->tile_rows != chhs::kTileY && o->tile_rows != chhs::kTileYSmall &&
         o->tile_rows != chhs::kTileYTiny)
         return false;
+    if (o->nu1_coarse < 0 || o->nu2_coarse < 0) return false;
+    if (o->prolong != 0 && o->prolong != 1) return false;
     return true;
+}
+
+// Smoothing steps before / after the coarse correction on level l.
+int nu_pre(const chhs_opts& o, int l) { return l == 0 || o.nu1_coarse == 0 ? o.nu1 : o.nu1_coarse; }
+int nu_post(const chhs_opts& o, int l) { return l == 0 || o.nu2_coarse == 0 ? o.nu2 : o.nu2_coarse; }
+
+chhs::CycleShape cycle_shape(const chhs_opts& o) {
+    return chhs::CycleShape{o.nu1, o.nu2, nu_pre(o, 1), nu_post(o, 1), o.coarse_sweeps, o.prolong};
 }
 
 // Extents of every level: halve all directions while every extent is even and
@@ -355,6 +375,25 @@ void fused_ranges(Layout& L, int n_inst) {
         task_ranges(L.rngT0, n_inst, L.S[0]);
     else
         task_ranges(L.rngT0, n_inst, L.T[0]);
+}
+
+// Rows per segment of the row-marching refinement tasks: the longest segment
+// (fewer halo rows read twice) that still gives at least kMarchWavesWanted
+// waves over the batch (enough resident waves to keep loads in flight), but
+// no shorter than 16 rows.
+constexpr long kMarchWavesWanted = 4096;
+int march_seg(const std::vector<InstInfo>& info, const std::vector<LevelDesc<double>>& desc,
+              int n_inst) {
+    for (int seg : {64, 48, 32, 24}) {
+        long waves = 0;
+        for (int i = 0; i < n_inst; ++i) {
+            const LevelDesc<double>& d = desc[size_t(i) * kMaxLevels];
+            waves += long((d.nx + chhs::kMarchCols - 1) / chhs::kMarchCols) * ((d.ny + seg - 1) / seg);
+        }
+        if (waves >= kMarchWavesWanted) return seg;
+    }
+    (void)info;
+    return 16;
 }
 
 // Builds the layout; base != nullptr fills the device pointers of the descriptors.
@@ -536,6 +575,18 @@ bool plan(const chhs_problem* p, int n_inst, const chhs_opts* o, char* base, Lay
                                                    : (o->smoother == 0 && l == 0 && !L.T[l].empty()));
         }
     L.snx = lnx_t;
+    // 2D mixed precision: tasks of the row-marching refinement step over every
+    // instance's finest level (instance, then row segment, then column window)
+    if (dim == 2 && mixed) {
+        L.march_seg = march_seg(L.info, L.desc, n_inst);
+        for (int i = 0; i < n_inst; ++i) {
+            const LevelDesc<double>& d = L.desc[size_t(i) * kMaxLevels];
+            const int nw = (d.nx + chhs::kMarchCols - 1) / chhs::kMarchCols;
+            for (int y0 = 0; y0 < d.ny; y0 += L.march_seg)
+                for (int w = 0; w < nw; ++w)
+                    L.M0.push_back({i, w, y0, std::min(d.ny, y0 + L.march_seg)});
+        }
+    }
     L.chain_from = L.max_nlev - 1;
     for (int l = 0; l + 1 < L.max_nlev; ++l)
         if (L.max_cells[l + 1] <= kChainCells) {
@@ -545,11 +596,13 @@ bool plan(const chhs_problem* p, int n_inst, const chhs_opts* o, char* base, Lay
     L.sny = lny;
     // per-instance ranges of the finest-level partial buffers
     ranges_of(L.rngA0, n_inst, L.A[0]);
+    task_ranges(L.rngM0, n_inst, L.M0);
+    fold_of(L.rngM0, L.FM0, L.rngM0f);
     ranges_of(L.rngA0n, n_inst, L.A0n);
     fold_of(L.rngA0, L.FA0, L.rngA0f);
     fold_of(L.rngA0n, L.FA0n, L.rngA0nf);
     fused_ranges(L, n_inst);
-    L.partial_cap = int(L.A[0].size());
+    L.partial_cap = int(std::max(L.A[0].size(), L.M0.size()));
     L.partial_t_cap = int(std::max<size_t>(1, std::max(L.T[0].size(), L.S[0].size())));
     L.off_desc = take(L.desc.size() * sizeof(LevelDesc<double>));
     L.off_desc32 = take(std::max<size_t>(1, L.desc32.size()) * sizeof(LevelDesc<float>));
@@ -560,6 +613,10 @@ bool plan(const chhs_problem* p, int n_inst, const chhs_opts* o, char* base, Lay
     L.off_rngA0n = take(n_inst * sizeof(Range));
     L.off_A0n = take(L.A0n.size() * sizeof(CellTask));
     L.off_A0t = take(L.A0t.size() * sizeof(CellTask));
+    L.off_M0 = take(L.M0.size() * sizeof(StripTask));
+    L.off_rngM0 = take(n_inst * sizeof(Range));
+    L.off_rngM0f = take(n_inst * sizeof(Range));
+    L.off_FM0 = take(L.FM0.size() * sizeof(FoldTask));
     L.off_FA0 = take(L.FA0.size() * sizeof(FoldTask));
     L.off_FA0n = take(L.FA0n.size() * sizeof(FoldTask));
     L.off_rngA0f = take(n_inst * sizeof(Range));
@@ -578,7 +635,7 @@ bool plan(const chhs_problem* p, int n_inst, const chhs_opts* o, char* base, Lay
     }
     L.off_partial = take(size_t(L.partial_cap) * chhs::kPartialStride * sizeof(double));
     L.off_partial_t = take(size_t(L.partial_t_cap) * chhs::kPartialStride * sizeof(double));
-    L.off_partial_f = take(std::max<size_t>(1, std::max(L.FA0.size(), L.FA0n.size())) *
+    L.off_partial_f = take(std::max<size_t>(1, std::max({L.FA0.size(), L.FA0n.size(), L.FM0.size()})) *
                            chhs::kPartialStride * sizeof(double));
     // res | act_next | cycles contiguous: one readback per cycle
     L.off_res = take(size_t(n_inst) * chhs::kResStride * sizeof(double) + 2 * n_inst * sizeof(int));
@@ -791,7 +848,8 @@ void enqueue_vcycle(chhs_ctx* c, const Hier<T>& H) {
     for (int d = 0; d < depth; ++d) {
         const int pre_cls = d == 0 ? CHHS_K_PRE0 : CHHS_K_COARSE;
         const int xfer_cls = d == 0 ? CHHS_K_TRANSFER0 : CHHS_K_COARSE;
-        if (tiled2d(c) && o.nu1 > 0) {
+        const int nu1 = nu_pre(o, d);
+        if (tiled2d(c) && nu1 > 0) {
             // on a tiled coarse level the first launch forms f = fr + N(u)
             const bool rhs = d > 0 && !c->lay.strip[d];
             // ... and on the finest level it subtracts a deferred p shift, or,
@@ -800,7 +858,7 @@ void enqueue_vcycle(chhs_ctx* c, const Hier<T>& H) {
             const double* psh = kPlain && d == 0 && c->defer_shift ? c->res : nullptr;
             const bool zero = !kPlain && d == 0;
             bool first = true;
-            int rem = o.nu1;
+            int rem = nu1;
             while (rem > 2) {
                 tiled(c, H, false, d, 2, 0, false, act, pre_cls, rhs && first, first ? psh : nullptr,
                       zero && first);
@@ -811,7 +869,7 @@ void enqueue_vcycle(chhs_ctx* c, const Hier<T>& H) {
                   zero && first);
         } else {
             if (!tiled2d(c))
-                for (int s = 0; s < o.nu1; ++s)
+                for (int s = 0; s < nu1; ++s)
                     for (int color = 0; color < 2; ++color) {
                         TimedScope t(c, pre_cls);
                         chhs::launch_smooth_color(dim, make_batch(H.dev, H.cur, d, act),
@@ -823,7 +881,8 @@ void enqueue_vcycle(chhs_ctx* c, const Hier<T>& H) {
         }
         // level d + 1's right-hand side f = fr + N(u), unless its first tiled
         // launch forms it (tail levels: the tail does)
-        const bool fused_next = tiled2d(c) && o.nu1 > 0 && d + 1 < depth && !c->lay.strip[d + 1];
+        const bool fused_next =
+            tiled2d(c) && nu_pre(o, d + 1) > 0 && d + 1 < depth && !c->lay.strip[d + 1];
         if (!fused_next && c->Bcs[d].n > 0) {
             TimedScope t(c, xfer_cls);
             chhs::launch_coarse_rhs(dim, make_batch(H.dev, H.cur, d, act), c->Bcs[d].dev,
@@ -835,16 +894,25 @@ void enqueue_vcycle(chhs_ctx* c, const Hier<T>& H) {
         // it (copy 0) and by the tail itself: it is always read from copy 0
         TimedScope t(c, depth == 0 ? CHHS_K_PRE0 : CHHS_K_COARSE);
         chhs::launch_tail<T, !kPlain>(dim, H.dev, c->dinfo, c->tail_insts, c->n_inst, act, 0u,
-                                      o.nu1, o.nu2, o.coarse_sweeps,
+                                      cycle_shape(o),
                                       kPlain && c->defer_shift ? c->res : nullptr, H.tail_lds,
                                       c->stream);
     }
+    const bool bil = o.prolong == 1;
     for (int d = depth - 1; d >= 0; --d) {
         const int post_cls = d == 0 ? CHHS_K_POST0 : CHHS_K_COARSE;
         const int xfer_cls = d == 0 ? CHHS_K_TRANSFER0 : CHHS_K_COARSE;
-        if (tiled2d(c) && o.nu2 > 0) {
-            int rem = o.nu2;
-            bool first = true;
+        const int nu2 = nu_post(o, d);
+        if (tiled2d(c) && nu2 > 0) {
+            // the fused kernels prolong by injection while they load; the
+            // bilinear prolongation is a launch of its own before them
+            if (bil) {
+                TimedScope t(c, xfer_cls);
+                chhs::launch_prolong(dim, make_batch(H.dev, H.cur, d, act), c->B[d].dev, c->B[d].n,
+                                     true, c->stream);
+            }
+            int rem = nu2;
+            bool first = !bil;
             while (rem > 0) {
                 const int k = rem >= 2 ? 2 : 1;
                 rem -= k;
@@ -856,10 +924,10 @@ void enqueue_vcycle(chhs_ctx* c, const Hier<T>& H) {
             {
                 TimedScope t(c, xfer_cls);
                 chhs::launch_prolong(dim, make_batch(H.dev, H.cur, d, act), c->B[d].dev, c->B[d].n,
-                                     c->stream);
+                                     bil, c->stream);
             }
             if (!tiled2d(c))
-                for (int s = 0; s < o.nu2; ++s)
+                for (int s = 0; s < nu2; ++s)
                     for (int color = 0; color < 2; ++color) {
                         TimedScope t(c, post_cls);
                         chhs::launch_smooth_color(dim, make_batch(H.dev, H.cur, d, act),
@@ -890,7 +958,7 @@ float time_level(chhs_ctx* c, const Hier<T>& H, int l, int reps, hipEvent_t ea, 
         // the FP32 finest level's first launch takes a zero correction as implied
         const bool zero = !std::is_same<T, double>::value && l == 0;
         bool first = true;
-        int rem = o.nu1;
+        int rem = nu_pre(o, l);
         while (rem > 2) {
             tiled(c, H, false, l, 2, 0, false, nullptr, CHHS_K_PRE0, rhs && first, nullptr,
                   zero && first);
@@ -899,8 +967,8 @@ float time_level(chhs_ctx* c, const Hier<T>& H, int l, int reps, hipEvent_t ea, 
         }
         tiled(c, H, false, l, rem, 1, false, nullptr, CHHS_K_PRE0, rhs && first, nullptr,
               zero && first);
-        rem = o.nu2;
-        bool pro = true;
+        rem = nu_post(o, l);
+        bool pro = o.prolong != 1;
         while (rem > 0) {
             const int k = rem >= 2 ? 2 : 1;
             rem -= k;
@@ -1007,6 +1075,18 @@ int autotune(chhs_ctx* c) {
     return check_launch();
 }
 
+// The partials of a task table for the per-instance reduction: folded first
+// when an instance has more than kFold of them (F non-empty).
+void fold_table(chhs_ctx* c, const Table<FoldTask>& F, const Range* rng, const Range* rngf,
+                const int* act, const double** src, const Range** out) {
+    *src = c->partial;
+    *out = rng;
+    if (F.n == 0) return;
+    chhs::launch_fold_partials(c->partial, F.dev, F.n, act, c->partial_f, c->stream);
+    *src = c->partial_f;
+    *out = rngf;
+}
+
 // The partials that the per-instance reduction reads for the finest level's
 // per-cell tasks (n_only: the tasks of instances without a fused norm, else
 // every instance's), folded first when an instance has more than kFold.
@@ -1070,17 +1150,26 @@ void enqueue_refinement(chhs_ctx* c, bool count, bool add) {
         chhs::launch_zero_correction(batch32(c, 0, act), z.dev, z.n, c->stream);
         enqueue_vcycle(c, hier32(c));
     }
+    const bool rows = c->M0.n > 0;       // 2D: the row-marching kernel
     {
         TimedScope t(c, CHHS_K_REFINE);
-        chhs::launch_mixed_residual(c->dim, batch(c, 0, add ? act : nullptr), batch32(c, 0, act),
-                                    c->A[0].dev, c->A[0].n, add ? 1 : 0,
-                                    add ? c->act_last : nullptr, c->partial, c->stream);
+        if (rows)
+            chhs::launch_mixed_residual_rows(batch(c, 0, add ? act : nullptr), batch32(c, 0, act),
+                                             c->M0.dev, c->M0.n, add ? 1 : 0,
+                                             add ? c->act_last : nullptr, c->partial, c->stream);
+        else
+            chhs::launch_mixed_residual(c->dim, batch(c, 0, add ? act : nullptr),
+                                        batch32(c, 0, act), c->A[0].dev, c->A[0].n, add ? 1 : 0,
+                                        add ? c->act_last : nullptr, c->partial, c->stream);
     }
     TimedScope t(c, CHHS_K_NORM);
     c->cur[0] ^= 1;
     const double* src;
     const Range* rng;
-    fold_cells(c, false, add ? act : nullptr, &src, &rng);
+    if (rows)
+        fold_table(c, c->FM0, c->rngM0, c->rngM0f, add ? act : nullptr, &src, &rng);
+    else
+        fold_cells(c, false, add ? act : nullptr, &src, &rng);
     chhs::launch_inst_reduce(src, rng, nullptr, nullptr, 0, c->dinfo,
                              add ? act : nullptr, c->act_next, c->cycles, c->res, c->n_inst,
                              o.tol, count ? o.max_vcycles : 1 << 30, count ? 1 : 0, c->stream);
@@ -1603,6 +1692,15 @@ int chhs_init(const chhs_problem* p, int32_t n_inst, const chhs_opts* o, void* w
     }
     rc |= upload(c->A0n, b, L.off_A0n, L.A0n, st);
     rc |= upload(c->A0t, b, L.off_A0t, L.A0t, st);
+    rc |= upload(c->M0, b, L.off_M0, L.M0, st);
+    rc |= upload(c->FM0, b, L.off_FM0, L.FM0, st);
+    c->rngM0 = reinterpret_cast<Range*>(b + L.off_rngM0);
+    c->rngM0f = reinterpret_cast<Range*>(b + L.off_rngM0f);
+    if (hipMemcpyAsync(c->rngM0, L.rngM0.data(), n_inst * sizeof(Range), hipMemcpyHostToDevice,
+                       st) != hipSuccess ||
+        hipMemcpyAsync(c->rngM0f, L.rngM0f.data(), n_inst * sizeof(Range),
+                       hipMemcpyHostToDevice, st) != hipSuccess)
+        rc = CHHS_E_HIP;
     rc |= upload(c->FA0, b, L.off_FA0, L.FA0, st);
     rc |= upload(c->FA0n, b, L.off_FA0n, L.FA0n, st);
     if (hipMemcpyAsync(c->rngA0f, L.rngA0f.data(), n_inst * sizeof(Range), hipMemcpyHostToDevice,
@@ -1844,6 +1942,81 @@ int chhs_set_timing(chhs_ctx* c, int32_t timing) {
     // graphs carry the events of the mask they were captured with
     drop_graphs(c);
     c->opts.timing = timing;
+    return CHHS_OK;
+}
+
+int chhs_tune_sweeps(chhs_ctx* c, const double* phi_prev, const double* phi_cur, const double* mu,
+                     const double* p, int32_t* choice_out) {
+    if (c == nullptr || phi_prev == nullptr || phi_cur == nullptr || mu == nullptr || p == nullptr)
+        return CHHS_E_INVAL;
+    // (nu1, nu2) on the finest level, (nu1_coarse, nu2_coarse) below it
+    // (0: the same), prolongation
+    struct Cand {
+        int nu1, nu2, nu1c, nu2c, prolong;
+    };
+    static const Cand kCands[] = {{2, 2, 0, 0, 0}, {1, 1, 0, 0, 0}, {2, 1, 0, 0, 0},
+                                  {1, 2, 0, 0, 0}, {2, 2, 1, 1, 0}, {1, 1, 2, 2, 0},
+                                  {2, 2, 3, 3, 0}, {2, 2, 0, 0, 1}, {1, 1, 0, 0, 1},
+                                  {1, 2, 0, 0, 1}};
+    const chhs_opts saved = c->opts;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    resolve_timing(c);
+    c->opts.timing = 0;
+    const bool early = !c->mixed;
+    double best = 1e300;
+    int pick = -1;
+    int rc = CHHS_OK;
+    for (int k = 0; k < int(sizeof(kCands) / sizeof(kCands[0])) && rc == CHHS_OK; ++k) {
+        const Cand& q = kCands[k];
+        c->opts.nu1 = q.nu1;
+        c->opts.nu2 = q.nu2;
+        c->opts.nu1_coarse = q.nu1c;
+        c->opts.nu2_coarse = q.nu2c;
+        c->opts.prolong = q.prolong;
+        drop_graphs(c);
+        double t = 0.0;
+        bool ok = true;
+        // the first solve captures the cycle graphs; the second is timed
+        for (int r = 0; r < 2 && ok && rc == CHHS_OK; ++r) {
+            const auto t0 = std::chrono::steady_clock::now();
+            rc = setup(c, phi_prev, phi_cur, mu, p, true, !early);
+            if (rc == CHHS_OK) rc = run_cycles(c, early);
+            const auto t1 = std::chrono::steady_clock::now();
+            if (rc != CHHS_OK) break;
+            for (int i = 0; i < c->n_inst; ++i) {
+                const double res = hres_of(c, i)[3];
+                ok = ok && std::isfinite(res) && res <= c->opts.tol;
+            }
+            t = std::chrono::duration<double>(t1 - t0).count();
+        }
+        if (rc == CHHS_OK && ok && t < best) {
+            best = t;
+            pick = k;
+        }
+    }
+    c->opts = saved;
+    drop_graphs(c);
+    if (rc != CHHS_OK) return rc;
+    if (pick < 0) return CHHS_E_NOCONV;
+    const Cand& q = kCands[pick];
+    c->opts.nu1 = q.nu1;
+    c->opts.nu2 = q.nu2;
+    c->opts.nu1_coarse = q.nu1c;
+    c->opts.nu2_coarse = q.nu2c;
+    c->opts.prolong = q.prolong;
+    if (choice_out != nullptr) {
+        choice_out[0] = q.nu1;
+        choice_out[1] = q.nu2;
+        choice_out[2] = q.nu1c;
+        choice_out[3] = q.nu2c;
+        choice_out[4] = q.prolong;
+    }
+    return CHHS_OK;
+}
+
+int chhs_get_opts(chhs_ctx* c, chhs_opts* out) {
+    if (c == nullptr || out == nullptr) return CHHS_E_INVAL;
+    *out = c->opts;
     return CHHS_OK;
 }
 

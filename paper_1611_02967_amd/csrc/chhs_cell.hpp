@@ -159,6 +159,34 @@ __device__ __forceinline__ float recip_ge1(float x) {
     return __builtin_fmaf(r, e, r);
 }
 
+// Cell-centred bi/trilinear interpolation of the coarse correction cv - cb at
+// fine cell (i, j, k) (coarse extents cnx, cny, cnz): along each axis 3/4 of
+// the parent and 1/4 of the parent's neighbour towards the cell, the parent
+// itself standing in beyond the boundary (even continuation, as the Neumann
+// ghost cells continue a field), applied axis by axis in the order z, y, x.
+template <int DIM, typename T>
+__device__ __forceinline__ T bilinear_corr(const T* cv, const T* cb, int cnx, int cny, int cnz,
+                                           int i, int j, int k) {
+    const int pi = i >> 1, pj = j >> 1, pk = k >> 1;
+    const int si = pi + ((i & 1) ? 1 : -1), sj = pj + ((j & 1) ? 1 : -1), sk = pk + ((k & 1) ? 1 : -1);
+    const int ni = si < 0 ? 0 : (si >= cnx ? cnx - 1 : si);
+    const int nj = sj < 0 ? 0 : (sj >= cny ? cny - 1 : sj);
+    const int nk = sk < 0 ? 0 : (sk >= cnz ? cnz - 1 : sk);
+    auto d = [&](int kk, int jj, int ii) {
+        const int c = (kk * cny + jj) * cnx + ii;
+        return cv[c] - cb[c];
+    };
+    if (DIM == 2) {
+        const T t0 = T(0.75) * d(0, pj, pi) + T(0.25) * d(0, nj, pi);
+        const T t1 = T(0.75) * d(0, pj, ni) + T(0.25) * d(0, nj, ni);
+        return T(0.75) * t0 + T(0.25) * t1;
+    }
+    auto tz = [&](int jj, int ii) { return T(0.75) * d(pk, jj, ii) + T(0.25) * d(nk, jj, ii); };
+    const T y0 = T(0.75) * tz(pj, pi) + T(0.25) * tz(nj, pi);
+    const T y1 = T(0.75) * tz(pj, ni) + T(0.25) * tz(nj, ni);
+    return T(0.75) * y0 + T(0.25) * y1;
+}
+
 // N(u) at one cell for the three rows of (2.5)-(2.7), the pressure row times s:
 //   N_phi = phi - lam sum M_f (mu_nb - mu) - lam sum a_f (p_nb - p)
 //   N_mu  = mu - chi(phi, psi) + kap sum (phi_nb - phi)

@@ -179,8 +179,12 @@ void launch_restrict_residual(int dim, const Batch<float>& b, const CellTask* t,
                               hipStream_t st);
 void launch_coarse_rhs(int dim, const Batch<double>& b, const CellTask* t, int nt, hipStream_t st);
 void launch_coarse_rhs(int dim, const Batch<float>& b, const CellTask* t, int nt, hipStream_t st);
-void launch_prolong(int dim, const Batch<double>& b, const CellTask* t, int nt, hipStream_t st);
-void launch_prolong(int dim, const Batch<float>& b, const CellTask* t, int nt, hipStream_t st);
+// u += P(u_c - ub_c) in place on the current copy of level b.level; bilinear:
+// cell-centred bi/trilinear interpolation, else piecewise-constant injection.
+void launch_prolong(int dim, const Batch<double>& b, const CellTask* t, int nt, bool bilinear,
+                    hipStream_t st);
+void launch_prolong(int dim, const Batch<float>& b, const CellTask* t, int nt, bool bilinear,
+                    hipStream_t st);
 // Mixed precision (finest level): FP32 copies of phi_*, phi^m; a zero FP32
 // correction; the FP64 outer step u' = u (+ e), R = f - N(u') written as u'
 // (other FP64 copy), R and b = phi' in FP32, and norm partials (as
@@ -190,6 +194,13 @@ void launch_prolong(int dim, const Batch<float>& b, const CellTask* t, int nt, h
 void launch_mixed_frozen(const Batch<double>& b64, const Batch<float>& b32, const CellTask* t,
                          int nt, hipStream_t st);
 void launch_zero_correction(const Batch<float>& b32, const CellTask* t, int nt, hipStream_t st);
+// The same outer step on 2D finest levels, by row marching: task = window of
+// kMarchCols columns (StripTask::sx) x rows [y0, y1); partial[task] gets the
+// task's sums.
+constexpr int kMarchCols = 128;
+void launch_mixed_residual_rows(const Batch<double>& b64, const Batch<float>& b32,
+                                const StripTask* t, int nt, int add, const int* was_active,
+                                double* partial, hipStream_t st);
 void launch_mixed_residual(int dim, const Batch<double>& b64, const Batch<float>& b32,
                            const CellTask* t, int nt, int add, const int* was_active,
                            double* partial, hipStream_t st);
@@ -276,15 +287,22 @@ void launch_stream2d(const Batch<T>& b, const StripTask* t, int nt, bool level0,
                      bool pro, bool zero, double* partial, hipStream_t st);
 
 // ---- single-workgroup coarse tail (chhs_tail.hip) ----------------------------------
+// The cycle's shape: smoothing steps before / after the coarse correction on
+// the finest level (f) and on the coarser ones (c), steps on the coarsest
+// grid, and the prolongation (bilinear != 0: bi/trilinear, else piecewise
+// constant).
+struct CycleShape {
+    int nu1f, nu2f, nu1c, nu2c, coarse, bilinear;
+};
 size_t tail_lds_bytes(const int* cells, int nlev, size_t elem, int nfields);
 template <typename T, bool CORR>
 int prepare_tail(int dim, size_t lds_bytes);
-// One workgroup per listed instance: V(nu1, nu2) cycle over levels info.tail ..
+// One workgroup per listed instance: the V-cycle over levels info.tail ..
 // info.nlev - 1 of that instance; bit l of cur_mask = current copy of u on
 // level l.
 template <typename T, bool CORR>
 void launch_tail(int dim, const LevelDesc<T>* desc, const InstInfo* info, const int* insts,
-                 int ninst, const int* active, unsigned cur_mask, int nu1, int nu2,
-                 int coarse_sweeps, double* pend, size_t lds_bytes, hipStream_t st);
+                 int ninst, const int* active, unsigned cur_mask, const CycleShape& shape,
+                 double* pend, size_t lds_bytes, hipStream_t st);
 
 }  // namespace chhs

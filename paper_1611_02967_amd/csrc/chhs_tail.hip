@@ -128,11 +128,17 @@ __device__ void tail_restrict(const Level<T>& F, const Level<T>& C) {
 }
 
 template <int DIM, typename T>
-__device__ void tail_prolong(const Level<T>& F, const Level<T>& C) {
+__device__ void tail_prolong(const Level<T>& F, const Level<T>& C, bool bilinear) {
     const float rnx = 1.0f / float(F.nx), rnxy = 1.0f / float(F.nx * F.ny);
     for (int idx = threadIdx.x; idx < F.n; idx += blockDim.x) {
         int i, j, k;
         tail_decode<DIM>(idx, F.nx, F.ny, rnx, rnxy, i, j, k);
+        if (bilinear) {
+            F.phi[idx] += bilinear_corr<DIM>(C.phi, C.ub0, C.nx, C.ny, C.nz, i, j, k);
+            F.mu[idx] += bilinear_corr<DIM>(C.mu, C.ub1, C.nx, C.ny, C.nz, i, j, k);
+            F.p[idx] += bilinear_corr<DIM>(C.p, C.ub2, C.nx, C.ny, C.nz, i, j, k);
+            continue;
+        }
         const int c = ((k >> 1) * C.ny + (j >> 1)) * C.nx + (i >> 1);
         F.phi[idx] += C.phi[c] - C.ub0[c];
         F.mu[idx] += C.mu[c] - C.ub1[c];
@@ -175,8 +181,8 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(const LevelDesc<T>* __res
                                                        const InstInfo* __restrict__ info,
                                                        const int* __restrict__ insts,
                                                        const int* __restrict__ active,
-                                                       unsigned cur_mask, int nu1, int nu2,
-                                                       int coarse_sweeps, double* pend) {
+                                                       unsigned cur_mask, CycleShape shape,
+                                                       double* pend) {
     extern __shared__ __align__(16) unsigned char tail_lds[];
     T* base = reinterpret_cast<T*>(tail_lds);
     const int inst = insts[blockIdx.x];
@@ -237,16 +243,18 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(const LevelDesc<T>* __res
     const int last = nlev - 1;
     for (int l = top; l < last; ++l) {
         const Level<T> F = lds_view<T, CORR>(d, top, l, base);
+        const int nu1 = l == 0 ? shape.nu1f : shape.nu1c;
         for (int s = 0; s < nu1; ++s) tail_smooth<DIM, T, CORR>(F);
         tail_restrict<DIM, T, CORR>(F, lds_view<T, CORR>(d, top, l + 1, base));
     }
     {
         const Level<T> B = lds_view<T, CORR>(d, top, last, base);
-        for (int s = 0; s < coarse_sweeps; ++s) tail_smooth<DIM, T, CORR>(B);
+        for (int s = 0; s < shape.coarse; ++s) tail_smooth<DIM, T, CORR>(B);
     }
     for (int l = last - 1; l >= top; --l) {
         const Level<T> F = lds_view<T, CORR>(d, top, l, base);
-        tail_prolong<DIM>(F, lds_view<T, CORR>(d, top, l + 1, base));
+        tail_prolong<DIM>(F, lds_view<T, CORR>(d, top, l + 1, base), shape.bilinear != 0);
+        const int nu2 = l == 0 ? shape.nu2f : shape.nu2c;
         for (int s = 0; s < nu2; ++s) tail_smooth<DIM, T, CORR>(F);
     }
 
@@ -280,24 +288,24 @@ int prepare_tail(int dim, size_t lds_bytes) {
 
 template <typename T, bool CORR>
 void launch_tail(int dim, const LevelDesc<T>* desc, const InstInfo* info, const int* insts,
-                 int ninst, const int* active, unsigned cur_mask, int nu1, int nu2,
-                 int coarse_sweeps, double* pend, size_t lds_bytes, hipStream_t st) {
+                 int ninst, const int* active, unsigned cur_mask, const CycleShape& shape,
+                 double* pend, size_t lds_bytes, hipStream_t st) {
     if (ninst <= 0) return;
     if (dim == 2)
         hipLaunchKernelGGL((k_tail<2, T, CORR>), dim3(ninst), dim3(kTailThreads), lds_bytes, st,
-                           desc, info, insts, active, cur_mask, nu1, nu2, coarse_sweeps, pend);
+                           desc, info, insts, active, cur_mask, shape, pend);
     else
         hipLaunchKernelGGL((k_tail<3, T, CORR>), dim3(ninst), dim3(kTailThreads), lds_bytes, st,
-                           desc, info, insts, active, cur_mask, nu1, nu2, coarse_sweeps, pend);
+                           desc, info, insts, active, cur_mask, shape, pend);
 }
 
 template int prepare_tail<double, false>(int, size_t);
 template int prepare_tail<float, true>(int, size_t);
 template void launch_tail<double, false>(int, const LevelDesc<double>*, const InstInfo*,
-                                         const int*, int, const int*, unsigned, int, int, int,
-                                         double*, size_t, hipStream_t);
+                                         const int*, int, const int*, unsigned,
+                                         const CycleShape&, double*, size_t, hipStream_t);
 template void launch_tail<float, true>(int, const LevelDesc<float>*, const InstInfo*, const int*,
-                                       int, const int*, unsigned, int, int, int, double*,
+                                       int, const int*, unsigned, const CycleShape&, double*,
                                        size_t, hipStream_t);
 
 }  // namespace chhs

@@ -61,6 +61,7 @@ int main(void) {
   printf("%zu %zu %zu\n", sizeof(chhs_problem), sizeof(chhs_opts), sizeof(chhs_stats));
   printf("%zu %zu %zu %zu %zu %zu %zu\n", offsetof(chhs_problem, h), offsetof(chhs_opts, tol), offsetof(chhs_opts, smoother), offsetof(chhs_opts, autotune), offsetof(chhs_opts, order), offsetof(chhs_opts, tile_threads), offsetof(chhs_opts, tile_rows));
   printf("%zu %zu %zu\n", offsetof(chhs_stats, res), offsetof(chhs_stats, max_abs_phi), offsetof(chhs_stats, res0));
+  printf("%zu %zu\n", offsetof(chhs_opts, nu1_coarse), offsetof(chhs_opts, prolong));
   return 0;
 }
 """
@@ -78,7 +79,8 @@ int main(void) {
             binding.chhs_opts.order.offset, binding.chhs_opts.tile_threads.offset,
             binding.chhs_opts.tile_rows.offset,
             binding.chhs_stats.res.offset, binding.chhs_stats.max_abs_phi.offset,
-            binding.chhs_stats.res0.offset]
+            binding.chhs_stats.res0.offset,
+            binding.chhs_opts.nu1_coarse.offset, binding.chhs_opts.prolong.offset]
     assert got == want
 
 
@@ -115,6 +117,13 @@ def test_workspace_bytes_rejects_invalid_problems(binding):
         assert binding.chhs_workspace_bytes([good], binding.chhs_default_opts(tile_rows=rows)) > 0
     for rows in (2, 32, -4):
         assert binding.chhs_workspace_bytes([good], binding.chhs_default_opts(tile_rows=rows)) == 0
+    # sweeps below the finest level (0 = as on the finest) and the prolongation
+    d = binding.chhs_default_opts()
+    assert d.nu1_coarse == 0 and d.nu2_coarse == 0 and d.prolong == 0
+    assert binding.chhs_workspace_bytes([good], binding.chhs_default_opts(nu1_coarse=3, nu2_coarse=1,
+                                                                          prolong=1)) > 0
+    for bad_opts in (dict(nu1_coarse=-1), dict(nu2_coarse=-2), dict(prolong=2), dict(prolong=-1)):
+        assert binding.chhs_workspace_bytes([good], binding.chhs_default_opts(**bad_opts)) == 0
 
 
 def test_sizes_beyond_32_bit_indexing_are_rejected_on_the_host(binding):
@@ -181,4 +190,6 @@ def test_entry_points_reject_null_context(binding):
     assert binding._lib.chhs_energy_mass(None, None, None, None) == binding.CHHS_E_INVAL
     assert binding._lib.chhs_graph_count(None, None) == binding.CHHS_E_INVAL
     assert binding._lib.chhs_set_timing(None, 0) == binding.CHHS_E_INVAL
+    assert binding._lib.chhs_tune_sweeps(None, None, None, None, None, None) == binding.CHHS_E_INVAL
+    assert binding._lib.chhs_get_opts(None, None) == binding.CHHS_E_INVAL
     binding._lib.chhs_destroy(None)

@@ -4,12 +4,19 @@ L = 3.2, eps = 0.2, gamma = 2, s = 0.05 h, T = 0.8, initial condition (5.1),
 FAS V(2,2) to tol 1e-10, on 16^2 .. 512^2 (5 N time steps at N^2).  Checked:
 second-order Cauchy rates (the table prints 2.04, 2.01, 2.00, 2.00), the mass
 of (5.1), -5.12, constant in time (Section 4: the scheme conserves mass), and
-F_h non-increasing (Theorem 2.1).  The Cauchy differences themselves are
-compared with the printed ones up to one common factor: measured here they are
-7.7 times the printed values at every N from 32 on (a normalisation of the norm that
-the paper does not state; the first step, phi^{-1} := phi^0, and the transfer
-to the coarse grid, cell averaging, are readings too), so the test pins the
-ratio to be the same for every pair, i.e. the shape of the printed column.
+F_h non-increasing (Theorem 2.1).
+
+The Cauchy differences themselves are compared with the printed ones up to one
+common factor, because the absolute level depends on readings the paper leaves
+open.  Two transfers are measured: cell averaging of the fine solution onto the
+coarse grid (h_c-weighted l2 norm; 7.7 times the printed values from 32^2 on)
+and the paper's stated operator, bilinear interpolation of the coarse solution
+onto the fine grid with even reflection at the Neumann boundary (h_f-weighted
+l2 norm; 4.9 times, first rate 2.06 against the printed 2.04).  The other
+reading of the first step, a first-order convex-splitting step for phi^1
+(Remark 2.2), changes the differences by under 1%, so it does not explain the
+factor.  Each test pins the ratio to be the same for every pair, i.e. the
+shape of the printed column.
 """
 import math
 
@@ -38,6 +45,52 @@ def chhs():
 
 def _restrict(v):
     return 0.25 * (v[0::2, 0::2] + v[1::2, 0::2] + v[0::2, 1::2] + v[1::2, 1::2])
+
+
+def _bilinear_up(v):
+    """Cell-centred bilinear interpolation of a coarse field onto the grid of
+    twice the resolution, with even reflection across the boundary (the
+    Neumann ghost cells of App. A.1): a fine centre lies a quarter of a coarse
+    cell from its parent's centre, weights 9/16, 3/16, 3/16, 1/16."""
+    n = v.shape[0]
+    p = np.pad(v, 1, mode="edge")
+    out = np.empty((2 * n, 2 * n))
+    for dy, sy in ((0, -1), (1, 1)):
+        for dx, sx in ((0, -1), (1, 1)):
+            c = p[1:-1, 1:-1]
+            a = p[1 + sy:n + 1 + sy, 1:-1]
+            b = p[1:-1, 1 + sx:n + 1 + sx]
+            ab = p[1 + sy:n + 1 + sy, 1 + sx:n + 1 + sx]
+            out[dy::2, dx::2] = 9 / 16 * c + 3 / 16 * a + 3 / 16 * b + 1 / 16 * ab
+    return out
+
+
+def _run(chhs, n, first_order_start=False):
+    import torch
+    h = L / n
+    s = 0.05 * h
+    steps = int(round(T / s))
+    prob = chhs.make_problem((n, n), h, EPS, GAMMA, s)
+    sv = chhs.Solver(prob, chhs.chhs_default_opts(tol=1e-10))
+    phi0 = paper_ic_51(n, L)
+    tp = torch.from_numpy(phi0).cuda()
+    tc = tp.clone()
+    tm = torch.zeros_like(tp)
+    tpp = torch.zeros_like(tp)
+    k = steps
+    if first_order_start:
+        chhs.Solver(prob, chhs.chhs_default_opts(tol=1e-10, order=1)).step(tp, tc, tm, tpp, 1)
+        k -= 1
+    sv.step(tp, tc, tm, tpp, k)
+    return tc.cpu().numpy()
+
+
+def _bilinear_deltas(phis):
+    out = {}
+    for n in SIZES[:-1]:
+        d = phis[2 * n] - _bilinear_up(phis[n])
+        out[(n, 2 * n)] = math.sqrt(np.sum(d * d)) * (L / (2 * n))
+    return out
 
 
 @pytest.fixture(scope="module")
@@ -102,3 +155,34 @@ def test_discrete_energy_F_is_non_increasing(runs):
     for n, r in runs.items():
         dF = np.diff(r["F"])
         assert np.all(dF <= 1e-9), (n, dF.max())
+
+
+def test_cauchy_differences_with_the_papers_bilinear_interpolation(runs):
+    """delta = phi_{h_f} - I phi_{h_c} with I bilinear onto the fine grid (the
+    operator Section 5.1 names), h_f-weighted l2 norm: rates as printed and one
+    common factor to the printed differences (about 4.9) at every N."""
+    deltas = _bilinear_deltas({n: runs[n]["phi"] for n in SIZES})
+    keys = sorted(deltas)
+    rates = {b: math.log2(deltas[a] / deltas[b]) for a, b in zip(keys, keys[1:])}
+    print("bilinear deltas:", ["%.4e" % deltas[k] for k in keys],
+          "rates:", ["%.3f" % rates[k] for k in keys[1:]],
+          "/ printed:", ["%.3f" % (deltas[k] / PRINTED[k]) for k in keys])
+    for k, want in PRINTED_RATE.items():
+        assert abs(rates[k] - want) <= 0.03, (k, rates[k], want)
+    ratios = [deltas[k] / PRINTED[k] for k in keys]
+    assert max(ratios) / min(ratios) <= 1.05, ratios
+
+
+def test_first_order_start_does_not_move_the_cauchy_differences(chhs, runs):
+    """The other first step of Remark 2.2 (a first-order step for phi^1 instead
+    of phi^{-1} := phi^0) changes the Cauchy differences by under 2%: it is not
+    what sets their level against the printed ones."""
+    sizes = SIZES[1:5]
+    alt = {n: _run(chhs, n, first_order_start=True) for n in sizes}
+    base = {n: runs[n]["phi"] for n in sizes}
+    for n in sizes[:-1]:
+        a = _restrict(alt[2 * n]) - alt[n]
+        b = _restrict(base[2 * n]) - base[n]
+        da, db = math.sqrt(np.sum(a * a)), math.sqrt(np.sum(b * b))
+        print(f"{n}->{2 * n}: delta with a first-order start / with phi^-1 = phi^0: {da / db:.4f}")
+        assert abs(da / db - 1.0) <= 0.02, (n, da / db)

@@ -265,3 +265,58 @@ def test_planted_chi_error_is_caught(monkeypatch):
     prev, cur, r = steps[-1]
     lhs, rhs = scheme.energy_identity_terms(r.phi, cur, prev, r.mu, r.p, prm)
     assert abs(lhs - rhs) > 1e-8
+
+
+# ---- solver variants: sweeps per level and bilinear prolongation --------------------------
+
+VARIANTS = [dict(nu1_coarse=1, nu2_coarse=1), dict(nu1_coarse=3, nu2_coarse=3),
+            dict(nu1=1, nu2=1, nu1_coarse=2, nu2_coarse=2), dict(prolong="bilinear"),
+            dict(nu1=1, nu2=2, prolong="bilinear")]
+
+
+@pytest.mark.parametrize("shape", [(8, 8), (4, 4, 4)])
+@pytest.mark.parametrize("variant", VARIANTS, ids=lambda v: ",".join(f"{k}={x}" for k, x in v.items()))
+def test_fas_variants_reach_the_newton_solution(shape, variant):
+    """Sweeps per level and the transfer operator change the iteration, not the
+    converged step: every variant reaches the unique solution (Theorem 2.1)."""
+    prev, cur = _pair(shape, 40 + len(shape))
+    h = 1.0 / shape[-1]
+    prm = scheme.Params(eps=0.1, gamma=2.0, s=0.5, h=h)
+    z = np.zeros(shape)
+    r = fas.solve_step(prev, cur, z, z, prm, fas.Opts(tol=1e-13, max_vcycles=300, **variant))
+    phi, mu, p, _ = newton.solve(prev, cur, 0.1, 2.0, 0.5, h)
+    assert np.max(np.abs(r.phi - phi)) < 1e-12
+    assert np.max(np.abs(r.mu - mu)) < 1e-12
+
+
+def test_bilinear_prolongation_weights_by_brute_force():
+    """Every fine cell of a 2D coarse array by explicit loops: parent 9/16, the
+    parent's neighbour towards the cell along x and along y 3/16 each, the
+    diagonal one 1/16, with the parent itself standing in beyond the boundary."""
+    rng = np.random.default_rng(7)
+    v = rng.random((3, 4))
+    out = fas.prolong_bilinear(v)
+    ny, nx = v.shape
+    for J in range(2 * ny):
+        for I in range(2 * nx):
+            j, i = J // 2, I // 2
+            jn = min(max(j + (1 if J % 2 else -1), 0), ny - 1)
+            in_ = min(max(i + (1 if I % 2 else -1), 0), nx - 1)
+            want = (9 * v[j, i] + 3 * v[j, in_] + 3 * v[jn, i] + v[jn, in_]) / 16
+            assert abs(out[J, I] - want) < 1e-15
+
+
+def test_bilinear_prolongation_is_exact_for_affine_fields_away_from_the_boundary():
+    """Cell centres x = (i + 1/2) h: an affine field sampled on the coarse grid is
+    reproduced exactly at the fine centres of every cell not on the boundary
+    (second-order interpolation); constants exactly everywhere (3D)."""
+    n = 6
+    xc = (np.arange(n) + 0.5) * 2.0
+    xf = (np.arange(2 * n) + 0.5) * 1.0
+    f = lambda z, y, x: 0.3 + 1.7 * x - 0.9 * y + 0.4 * z
+    Z, Y, X = np.meshgrid(xc, xc, xc, indexing="ij")
+    out = fas.prolong_bilinear(f(Z, Y, X))
+    Zf, Yf, Xf = np.meshgrid(xf, xf, xf, indexing="ij")
+    inner = (slice(1, -1),) * 3
+    np.testing.assert_allclose(out[inner], f(Zf, Yf, Xf)[inner], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(fas.prolong_bilinear(np.full((n, n, n), 2.5)), 2.5, rtol=0, atol=0)
