@@ -40,7 +40,7 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def launch_bytes_per_cell(dim, cls, mixed=False):
+def launch_bytes_per_cell(dim, cls, mixed=False, kind=None):
     """Algorithmic bytes per finest cell of one finest-level launch of a kernel class.
 
     FP64 plain path (8 B per value).  On the finest level f_phi = phi^m and
@@ -55,11 +55,14 @@ def launch_bytes_per_cell(dim, cls, mixed=False):
                  mu, p, phi_* (4 values per 2 cells), the color's phi, phi_*,
                  phi^m, f_phi, f_mu, f_p (6 per 2 cells) and its new phi, mu,
                  p (3 per 2 cells)                                          = 52 B
+      3D fused (kind "zmarch"): one launch = one whole step: u, phi_*, phi^m
+                 and f read, u written: (8 + 3) values                      = 88 B
     Mixed precision, FP32 correction form (4 B per value; general right-hand
     sides and the base state b on every level):
       2D pre0  : 9 reads + 3 writes, plus u_c, ub_c, R(r), b_c (10 per 4)   = 58 B
       2D post0 : 9 reads + 3 writes, plus u_c, ub_c read (6 per 4)          = 54 B
       3D       : (4 + 7 + 3) values per 2 cells                             = 28 B
+      3D fused : u, phi_*, phi^m, f, b read, u written: (9 + 3) values      = 48 B
       refine   : the FP64 refinement launch: u (FP64), e (FP32), phi_*,
                  phi^m, f_mu (FP64) read; u + e (FP64), the three FP32
                  right-hand sides and b written:
@@ -71,36 +74,48 @@ def launch_bytes_per_cell(dim, cls, mixed=False):
     if mixed:
         if dim == 2:
             return {"pre0": (12 + 10 / 4) * 4, "post0": (12 + 6 / 4) * 4}[cls]
-        return (4 + 7 + 3) / 2 * 4
+        return (9 + 3) * 4 if kind == "zmarch" else (4 + 7 + 3) / 2 * 4
     if dim == 2:
         return {"pre0": (9 + 9 / 4) * 8, "post0": (9 + 6 / 4) * 8}[cls]
-    return (4 + 6 + 3) / 2 * 8
+    return (8 + 3) * 8 if kind == "zmarch" else (4 + 6 + 3) / 2 * 8
 
 
-def vcycle_bytes(dim, shape, level_kernels):
-    """Algorithmic bytes of one FP64 V(2,2) cycle over every level.
+def vcycle_bytes(dim, shape, level_kernels, sweeps=None):
+    """Algorithmic bytes of one FP64 V-cycle over every level.
 
-    Per cell of level l (n_l cells, r = 2^dim children per coarse cell, 8 B per
-    value), what each launch of the cycle must move at minimum:
-      finest level, fused kernels : the pre and post launches above (174 B, 2D)
-      coarse fused, first launch  : u, phi_*, phi^m and the restricted residual
-                                    fr read, u and f = fr + N(u) written, the
-                                    restriction to level l + 1 (9 per r)
-                                    = (14 + 9/r) 8
-      coarse fused, strips        : a separate launch forms f (u, fr, phi_*,
-                                    phi^m read, f written: 11 values), the
-                                    first launch then reads f: (11 + 9/r) 8
-      coarse fused, post launch   : u, phi_*, phi^m, f read, u written, u_c and
-                                    ub_c read (6 per r)  = (11 + 6/r) 8
+    sweeps: (nu1, nu2, nu1_coarse, nu2_coarse, prolong) as chhs_get_opts
+    reports them (default V(2,2), piecewise-constant prolongation).  Per cell
+    of level l (n_l cells, r = 2^dim children per coarse cell, 8 B per value),
+    what each launch of the cycle must move at minimum; a fused 2D launch
+    takes up to two smoothing steps, so nu steps take ceil(nu / 2) launches:
+      every fused launch          : u, phi_*, phi^m and the right-hand sides
+                                    read (finest level: f_mu only, 6 values;
+                                    coarse levels: f, 8 values), u written (3)
+      first pre launch, coarse    : reads the restricted residual fr and writes
+                                    f = fr + N(u) as well (+ 3)
+      last pre launch             : writes u_c, ub_c and R(r) on level l + 1
+                                    (+ 9/r)
+      first post launch           : reads u_c and ub_c to prolong (+ 6/r); with
+                                    the bilinear prolongation a launch of its
+                                    own instead (u read and written, u_c, ub_c
+                                    read: 6 + 6/r)
+      strips on a coarse level    : a separate launch forms f (u, fr, phi_*,
+                                    phi^m read, f written: 11), the first launch
+                                    then reads f (no + 3)
       per-cell kernels            : 2 (nu1 + nu2) color launches of 52 B; the
-                                    residual + restriction (8 + 9/r) 8; the
+                                    residual + restriction (8 + 9/r); the
                                     right-hand side of level l + 1 unless the
-                                    tail forms it, 11/r 8; the prolongation
-                                    (6 + 6/r) 8
+                                    tail forms it, 11/r; the prolongation
+                                    (6 + 6/r)
+      fused 3D steps ("zmarch")   : nu1 + nu2 launches of 88 B, the transfers
+                                    as for per-cell kernels
       tail (one launch)           : u and fr of its top level read, u written,
                                     phi_* and phi^m of every tail level read
     The norm reduction and the per-cycle readback (a few KB) are left out.
     """
+    nu1, nu2, nu1c, nu2c, prolong = sweeps if sweeps is not None else (2, 2, 0, 0, 0)
+    nu1c = nu1c or nu1
+    nu2c = nu2c or nu2
     r = 2 ** dim
     n0 = 1
     for s in shape:
@@ -109,21 +124,25 @@ def vcycle_bytes(dim, shape, level_kernels):
     total = 0.0
     for l, kind in enumerate(kinds):
         n = n0 / r ** l
+        a, b = (nu1, nu2) if l == 0 else (nu1c, nu2c)
         if kind == "tail":
             rest = sum(n0 / r ** k for k in range(l, len(kinds)))
             total += 8 * (9 * n + 2 * rest)
             break
-        if kind == "per-cell":
+        if kind in ("per-cell", "zmarch"):
             next_tail = l + 1 < len(kinds) and kinds[l + 1] == "tail"
-            b = 2 * (2 + 2) * 52 + (8 + 9 / r) * 8 + (6 + 6 / r) * 8
-            b += 0 if next_tail else 11 / r * 8
-        elif l == 0:
-            b = launch_bytes_per_cell(dim, "pre0") + launch_bytes_per_cell(dim, "post0")
-        elif kind == "strips":
-            b = 11 * 8 + (11 + 9 / r) * 8 + (11 + 6 / r) * 8
+            smooth = (a + b) * 2 * 52 / 8 if kind == "per-cell" else (a + b) * 11
+            v = smooth + (8 + 9 / r) + (6 + 6 / r)
+            v += 0 if next_tail else 11 / r
         else:
-            b = (14 + 9 / r) * 8 + (11 + 6 / r) * 8
-        total += b * n
+            read = 6 if l == 0 else 8
+            pre = -(-a // 2) * (read + 3) + 9 / r
+            if l > 0:
+                pre += 11 if kind == "strips" else 3
+            post = -(-b // 2) * (read + 3)
+            post += (6 + 6 / r) if prolong == 1 else 6 / r
+            v = pre + post
+        total += 8 * v * n
     return total
 
 
@@ -180,13 +199,18 @@ def host_info():
 # ---- the oracle on the host ------------------------------------------------------------
 
 def _oracle_step(job):
-    """One oracle time step of one instance (worker of the process pool)."""
+    """One oracle time step of one instance (worker of the process pool), with
+    the cycle (sweeps per level, prolongation) the GPU context of that instance
+    uses."""
     import numpy as np
     from oracle import fas, scheme
-    prev, cur, mu, p, eps, gamma, s, h = job
+    prev, cur, mu, p, eps, gamma, s, h, cyc = job
     prm = scheme.Params(eps=eps, gamma=gamma, s=s, h=h)
+    nu1, nu2, nu1c, nu2c, prolong = cyc
+    opts = fas.Opts(tol=1e-10, nu1=nu1, nu2=nu2, nu1_coarse=nu1c, nu2_coarse=nu2c,
+                    prolong="bilinear" if prolong == 1 else "constant")
     t0 = time.perf_counter()
-    r = fas.solve_step(prev, cur, mu, p, prm, fas.Opts(tol=1e-10))
+    r = fas.solve_step(prev, cur, mu, p, prm, opts)
     return np.asarray(r.phi), r.vcycles, time.perf_counter() - t0
 
 
@@ -246,6 +270,7 @@ def roofline_record(cls, tim, bytes_per_launch, name, traffic):
            "algorithmic_bytes_per_launch": round(bytes_per_launch)}
     if traffic is not None:
         rec["traffic_record"] = traffic
+        rec["traffic_ratio"] = round(traffic["bytes_per_launch"] / traffic["algorithmic_bytes_per_launch"], 3)
     return rec
 
 
@@ -286,6 +311,12 @@ def run_batched(args, pool):
             f"refinement steps")
     tim_w = sv.timing(reset=True)
     cls = dominant_class(tim_w, cand)
+    sweeps = None
+    if args.tune_sweeps:
+        # sweeps per level and prolongation by time to tolerance, on the
+        # current step's system (the state is not advanced)
+        sweeps = sv.tune_sweeps(tp, tc, tm, tpp)
+        log(f"tuned (nu1, nu2, nu1_coarse, nu2_coarse, prolong) = {sweeps}")
     sv.set_timing(chhs.timing_mask(cls))
     torch.cuda.synchronize()
     start = [t.clone() for t in (tp, tc, tm, tpp)]
@@ -332,9 +363,11 @@ def run_batched(args, pool):
     # timed (outside the timed region)
     kernel_ms = {}
     if not args.no_breakdown:
+        extra = {} if sweeps is None else dict(zip(
+            ("nu1", "nu2", "nu1_coarse", "nu2_coarse", "prolong"), sweeps))
         sb = chhs.Solver(probs, chhs.chhs_default_opts(tol=1e-10, precision=1, timing=1,
                                                        smoother=args.smoother,
-                                                       autotune=int(args.autotune)))
+                                                       autotune=int(args.autotune), **extra))
         st_b = [t.clone() for t in start]
         sb.step_log(*st_b, 1)
         sb.timing(reset=True)
@@ -346,12 +379,17 @@ def run_batched(args, pool):
 
     # the sequential plain FP64 loop: one context per instance, one step each
     # per round, with the reductions every step
-    seq = [chhs.Solver(pr, chhs.chhs_default_opts(tol=1e-10, precision=0, smoother=args.smoother,
-                                                  autotune=int(args.autotune)))
-           for pr in probs]
+    seq = [] if args.no_sequential else [
+        chhs.Solver(pr, chhs.chhs_default_opts(tol=1e-10, precision=0, smoother=args.smoother,
+                                               autotune=int(args.autotune)))
+        for pr in probs]
     views = lambda ts, i: [t[offs[i]:offs[i + 1]] for t in ts]
     sp = [t.clone() for t in start]
+    seq_sweeps = {}
     for i, s1 in enumerate(seq):       # warm-up: one step each (graph capture)
+        if args.tune_sweeps:
+            ch = s1.tune_sweeps(*views(sp, i))
+            seq_sweeps[str(ch)] = seq_sweeps.get(str(ch), 0) + 1
         s1.step_log(*[v.clone() for v in views(sp, i)], 1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -361,7 +399,7 @@ def run_batched(args, pool):
             _, lq = s1.step_log(*views(sp, i), 1)
             seq_cycles += lq[0][0]["vcycles"]
     torch.cuda.synchronize()
-    elapsed_seq = time.perf_counter() - t0
+    elapsed_seq = max(time.perf_counter() - t0, 1e-12)
     log(f"sequential fp64: {args.steps} rounds in {elapsed_seq:.3f}s, {seq_cycles} V-cycles")
 
     # one step of both paths from the timed region's start state
@@ -376,7 +414,10 @@ def run_batched(args, pool):
         fp64_phi.append(b[1].cpu().numpy())
         err = max(err, float(np.max(np.abs(mixed_phi[offs[i]:offs[i + 1]] - fp64_phi[i]))))
     log(f"max |phi_mixed - phi_fp64| over instances after one step: {err:.2e}")
+    seq_cycles_opts = []
     for s1 in seq:
+        o = s1.get_opts()
+        seq_cycles_opts.append((o.nu1, o.nu2, o.nu1_coarse, o.nu2_coarse, o.prolong))
         s1.close()
     sv.close()
 
@@ -400,16 +441,19 @@ def run_batched(args, pool):
                             "unit": "cell-updates/s",
                             "instance_steps_per_s": inst_steps / elapsed_seq,
                             "ms_per_round": elapsed_seq / args.steps * 1e3,
-                            "vcycles_per_instance_step": seq_cycles / inst_steps},
-        "speedup_vs_sequential_fp64": elapsed_seq / elapsed,
-        "max_abs_err_phi_vs_fp64": err,
+                            "vcycles_per_instance_step": seq_cycles / inst_steps} if seq else None,
+        "max_abs_err_phi_vs_fp64": err if seq else None,
+        "speedup_vs_sequential_fp64": elapsed_seq / elapsed if seq else None,
         "energy_F_nonincreasing": bool(f_ok),
         "level_kernels": level_kernels,
+        "sweeps": None if sweeps is None else dict(zip(
+            ("nu1", "nu2", "nu1_coarse", "nu2_coarse", "prolong"), sweeps)),
+        "sequential_fp64_sweeps": seq_sweeps or None,
         "kernel_ms_per_step": kernel_ms,
         "roofline": roofline,
     }
 
-    if pool is not None:
+    if pool is not None and seq:
         # the oracle: one time step of instances 0..7 (two of each grid size)
         # from the timed region's start state, in the process pool
         sample = list(range(8))
@@ -418,7 +462,7 @@ def run_batched(args, pool):
             it = insts[i]
             sl = slice(offs[i], offs[i + 1])
             jobs.append(tuple(x[sl].reshape(it.shape).copy() for x in start_host)
-                        + (it.eps, it.gamma, it.s, it.h))
+                        + (it.eps, it.gamma, it.s, it.h, seq_cycles_opts[i]))
         log(f"timing the oracle: one step of instances {sample[0]}..{sample[-1]} in a pool of "
             f"{pool._processes} processes")
         import resource
@@ -436,7 +480,8 @@ def run_batched(args, pool):
         out["cpu_baseline"] = {
             "value": sample_cells / wall, "unit": "cell-updates/s", "cores": pool._processes,
             "kind": "oracle",
-            "sample": (f"one time step (FAS V(2,2) to tol 1e-10) of instances {sample[0]}-"
+            "sample": (f"one time step (FAS to tol 1e-10, each instance with the sweeps its FP64 "
+                       f"GPU context uses) of instances {sample[0]}-"
                        f"{sample[-1]} of the batch ({sample_cells} cells: two each of 128^2, "
                        f"256^2, 512^2, 1024^2) from the timed region's start state, single-threaded "
                        f"NumPy per process, {pool._processes} processes; value = cells / wall"),
@@ -495,6 +540,9 @@ def run_single(args, name, cpu_baseline=True, parity=True, breakdown=True, copy_
     start_state = [t.cpu().numpy() for t in (tp, tc, tm, tpp)]
     tim_w = sv.timing(reset=True)
     cls = dominant_class(tim_w, cand)
+    sweeps = sv.tune_sweeps(tp, tc, tm, tpp) if args.tune_sweeps else None
+    if sweeps is not None:
+        log(f"tuned (nu1, nu2, nu1_coarse, nu2_coarse, prolong) = {sweeps}")
     sv.set_timing(chhs.timing_mask(cls))
 
     torch.cuda.synchronize()
@@ -507,16 +555,18 @@ def run_single(args, name, cpu_baseline=True, parity=True, breakdown=True, copy_
     log(f"timed {args.steps} steps in {elapsed:.3f}s, {vcyc} V-cycles, last res "
         f"{lg[-1][0]['res_norm']:.2e}")
 
+    one3 = " (one red-black step, z marching)" if sv.level_kernels()[0][0] == "zmarch" else " (one color)"
     names = {"pre0": "finest-level pre-smoothing launch" + (
-                 " (2 fused red-black steps + residual + restriction)" if dim == 2 else " (one color)"),
+                 " (2 fused red-black steps + residual + restriction)" if dim == 2 else one3),
              "post0": "finest-level post-smoothing launch" + (
-                 " (prolongation + 2 fused red-black steps + residual norm)" if dim == 2 else " (one color)"),
+                 " (prolongation + 2 fused red-black steps + residual norm)" if dim == 2 else one3),
              "refine": "finest-level FP64 refinement launch"}
+    level_kernels = sv.level_kernels()
+    kind0 = level_kernels[0][0]
     if cls == "refine":
         bytes_launch = (cells * 88 * args.steps + cells * 100 * vcyc) / max(1, tim[cls][1])
     else:
-        bytes_launch = launch_bytes_per_cell(dim, cls, mixed) * cells
-    level_kernels = sv.level_kernels()
+        bytes_launch = launch_bytes_per_cell(dim, cls, mixed, kind0) * cells
     traffic = measured_traffic(name, cls, level_kernels[0])
     roofline = roofline_record(cls, tim, bytes_launch, names[cls], traffic)
     for other in cand:
@@ -524,7 +574,7 @@ def run_single(args, name, cpu_baseline=True, parity=True, breakdown=True, copy_
             avg_o = tim_w[other][0] / 1e3 / tim_w[other][1]
             if other == "refine":
                 continue
-            b_o = launch_bytes_per_cell(dim, other, mixed) * cells
+            b_o = launch_bytes_per_cell(dim, other, mixed, kind0) * cells
             roofline.setdefault("other_kernels", {})[other] = {
                 "kernel": names[other] + ", timed in the warm-up steps",
                 "avg_launch_us": round(avg_o * 1e6, 2),
@@ -533,9 +583,11 @@ def run_single(args, name, cpu_baseline=True, parity=True, breakdown=True, copy_
                 "traffic": measured_traffic(name, other, level_kernels[0])}
     kernel_ms = {}
     if breakdown:
+        extra = {} if sweeps is None else dict(zip(
+            ("nu1", "nu2", "nu1_coarse", "nu2_coarse", "prolong"), sweeps))
         sb = chhs.Solver(prob, chhs.chhs_default_opts(tol=1e-10, timing=1, smoother=args.smoother,
                                                       precision=1 if mixed else 0,
-                                                      autotune=int(args.autotune)))
+                                                      autotune=int(args.autotune), **extra))
         st_b = [torch.from_numpy(a).cuda() for a in start_state]
         nb = min(args.steps, 5)
         sb.step_log(*st_b, 1)
@@ -568,13 +620,15 @@ def run_single(args, name, cpu_baseline=True, parity=True, breakdown=True, copy_
         "res_norm_last": lg[-1][0]["res_norm"],
         "kernel_ms_per_step": kernel_ms,
         "level_kernels": [list(k) for k in level_kernels],
+        "sweeps": None if sweeps is None else dict(zip(
+            ("nu1", "nu2", "nu1_coarse", "nu2_coarse", "prolong"), sweeps)),
         "roofline": roofline,
         "per_vcycle": None,
     }
     if not mixed and vcyc:
         # HBM fraction of whole V-cycles: the cycle's algorithmic bytes over the
         # wall time per cycle (the per-step setup, copy-out and energies included)
-        vb = vcycle_bytes(dim, shape, level_kernels)
+        vb = vcycle_bytes(dim, shape, level_kernels, sweeps)
         t_cyc = elapsed / vcyc
         out["per_vcycle"] = {"algorithmic_bytes": round(vb), "wall_us": round(t_cyc * 1e6, 2),
                              "achieved": round(vb / t_cyc / 1e9, 1), "peak": HBM_PEAK_GBS,
@@ -612,6 +666,86 @@ def run_single(args, name, cpu_baseline=True, parity=True, breakdown=True, copy_
     return out
 
 
+# ---- counter records --------------------------------------------------------------------
+
+# Finest-level launch classes of the batched workload and how their kernels are
+# named; a class's record is taken over its launches that cover every instance
+# (the first refinement step of each time step: no instance has converged yet),
+# whose counters are the largest of the class.
+TRAFFIC_CLASSES = {
+    "refine": ("k_mixed_residual_rows", 100.0),
+}
+TRAFFIC_SOURCES = {
+    "refine": ["paper_1611_02967_amd/csrc/chhs_refine2d.hip", "paper_1611_02967_amd/csrc/chhs_cell.hpp"],
+}
+
+
+def _counter_rows(path):
+    """(dispatch id, kernel name, value) of every row of a rocprofv3 counter
+    collection csv (a file, or the directory rocprofv3 wrote it under)."""
+    import csv
+    import glob
+    files = [path] if os.path.isfile(path) else sorted(
+        glob.glob(os.path.join(path, "**", "*counter_collection.csv"), recursive=True))
+    rows = []
+    for f in files:
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                rows.append((int(r["Dispatch_Id"]), r["Kernel_Name"], float(r["Counter_Value"])))
+    return rows
+
+
+def write_traffic_record(fetch_path, write_path, bench_json):
+    """HBM bytes per launch of the dominant finest-level class from FETCH_SIZE and
+    WRITE_SIZE (KiB per dispatch), each scaled by what it reads for the 256 MiB
+    device copy of --copy-calibration, into profiles/traffic.json."""
+    with open(bench_json) as fh:
+        line = [l for l in fh.read().splitlines() if l.startswith("{")][-1]
+    run = json.loads(line)
+    workload = run["config"]["workload"]
+    cells = run["config"]["cells"]
+    fetch = {d: (k, v) for d, k, v in _counter_rows(fetch_path)}
+    write = {d: (k, v) for d, k, v in _counter_rows(write_path)}
+    copies = [d for d, (k, v) in fetch.items() if "copyBuffer" in k and v * 1024 > 0.4 * COPY_BYTES]
+    if not copies:
+        raise SystemExit("no 256 MiB copy in the counter runs (run the bench with --copy-calibration)")
+    fk = sum(fetch[d][1] for d in copies) / len(copies)
+    wk = sum(write[d][1] for d in copies if d in write) / len(copies)
+    read_scale, write_scale = COPY_BYTES / (fk * 1024), COPY_BYTES / (wk * 1024)
+    rec = {"workload": workload, "sources": [], "level0_kernel": run["level_kernels"][0],
+           "calibration": {"kernel": "device copy of 256 MiB (torch copy_)",
+                           "bytes_copied": COPY_BYTES, "fetch_kib": round(fk, 2),
+                           "write_kib": round(wk, 2), "read_scale": read_scale,
+                           "write_scale": write_scale},
+           "launches": {}}
+    for cls, (pattern, per_cell) in TRAFFIC_CLASSES.items():
+        ds = sorted(d for d, (k, v) in fetch.items() if pattern in k)
+        if not ds:
+            continue
+        top = max(fetch[d][1] for d in ds)
+        full = [d for d in ds if fetch[d][1] >= 0.98 * top and d in write]
+        f_mean = sum(fetch[d][1] for d in full) / len(full)
+        w_mean = sum(write[d][1] for d in full) / len(full)
+        rec["launches"][cls] = {
+            "kernel": pattern, "dispatches": len(full), "of_dispatches": len(ds),
+            "fetch_kib": round(f_mean, 2), "write_kib": round(w_mean, 2),
+            "bytes_per_launch": round(f_mean * 1024 * read_scale + w_mean * 1024 * write_scale),
+            "algorithmic_bytes_per_launch": per_cell * cells,
+            "launches_covered": "every instance active (the largest counters of the class)"}
+        rec["sources"] = sorted(set(rec["sources"]) | set(TRAFFIC_SOURCES[cls]))
+    rec["source_sha256"] = kernel_source_hash(rec["sources"])
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            recs = json.load(fh)
+    except (OSError, ValueError):
+        recs = {}
+    recs[workload] = rec
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(recs, fh, indent=1)
+        fh.write("\n")
+    print(json.dumps(rec, indent=1))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -623,6 +757,13 @@ def main():
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--no-fp64-2048", action="store_true",
                     help="with the batched workload, skip the 2048^2 FP64 extra measurement")
+    ap.add_argument("--no-sequential", action="store_true",
+                    help="with the batched workload, skip the sequential FP64 loop (and the "
+                         "comparisons that need it), e.g. under a counter profiler")
+    ap.add_argument("--traffic-record", nargs=3, metavar=("FETCH", "WRITE", "BENCH_JSON"),
+                    help="no GPU work: turn two rocprofv3 counter passes of a bench run "
+                         "(FETCH_SIZE and WRITE_SIZE, csv output directories) and that run's "
+                         "JSON line into the committed traffic record of its workload")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="before the timed region, copy a 256 MiB device buffer three times "
                          "(the known-size kernel that scales rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -631,10 +772,17 @@ def main():
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="use the default smoothing kernels instead of letting chhs_init time "
                          "the candidates per level and keep the fastest")
+    ap.add_argument("--no-tune-sweeps", dest="tune_sweeps", action="store_false",
+                    help="keep V(2,2) with piecewise-constant prolongation instead of choosing the "
+                         "sweeps per level and the prolongation by time to tolerance after the "
+                         "warm-up steps")
     ap.add_argument("--smoother", type=int, default=0,
                     help="2D smoother: 0 default (strips on the finest level), 1 tiles, 2 strips")
     args = ap.parse_args()
 
+    if args.traffic_record:
+        write_traffic_record(*args.traffic_record)
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs one GPU only (--gpus {args.gpus} requested); "
               "the batched and single-grid paths are measured on one MI355X", file=sys.stderr)
@@ -669,7 +817,8 @@ def main():
                                  breakdown=False)
                 out["fp64_2048"] = {k: one[k] for k in (
                     "value", "unit", "ms_per_step", "steps_per_s", "vcycles_per_step",
-                    "vcycles_per_s", "config", "roofline", "per_vcycle", "level_kernels")}
+                    "vcycles_per_s", "config", "roofline", "per_vcycle", "level_kernels",
+                    "sweeps")}
         else:
             out = run_single(args, args.workload, cpu_baseline=not args.no_cpu_baseline,
                              parity=not args.no_parity, breakdown=not args.no_breakdown,

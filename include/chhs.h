@@ -82,8 +82,10 @@ typedef struct chhs_problem {
  * the 2D smoothing kernels of the levels above the single-workgroup tail:
  * 0 = default (row-streaming strips on the finest level, square LDS tiles on
  * coarser ones), 1 = tiles everywhere, 2 = strips on every level (including
- * the explicit smoothing calls on tail levels).  Both
- * kernels perform the same red-black updates (results agree to rounding).
+ * the explicit smoothing calls on tail levels), 3 = per-cell red-black
+ * kernels on 3D levels (one launch per color) instead of the default fused
+ * z-marching step.  All kernels perform the same red-black updates (results
+ * agree to rounding).
  * tile_threads = 0 (default) gives tiled levels 1024-thread blocks when they
  * have at most 256 tiles and 256-thread blocks otherwise; 256, 512 or 1024
  * fixes the block size of every tiled level (the same arithmetic per cell).
@@ -258,8 +260,9 @@ int chhs_level_shape(chhs_ctx* c, int32_t level, int32_t* nxyz3);
 
 /* The smoothing kernel the V-cycle uses on level `level` (counted from the
  * finest) of the batch: out3[0] = 0 square tiles (out3[1] = threads per block),
- * 1 row-streaming strips (out3[1] = rows per segment), 2 per-cell kernels (3D),
- * 3 inside the one-workgroup coarse tail for every instance (out3[1] = 0);
+ * 1 row-streaming strips (out3[1] = rows per segment), 2 per-cell kernels (one
+ * launch per color), 3 inside the one-workgroup coarse tail for every instance
+ * (out3[1] = 0), 4 fused 3D steps by z marching (out3[1] = planes per segment);
  * out3[2] = blocks per launch (0 for the tail).  Reflects the autotuner's
  * choice.  Any batch size; CHHS_E_INVAL for a level no instance has. */
 int chhs_level_kernel(chhs_ctx* c, int32_t level, int32_t* out3);
@@ -291,11 +294,12 @@ int chhs_set_timing(chhs_ctx* c, int32_t timing);
 /* Chooses the sweeps per level and the prolongation by time to tolerance:
  * on the system of the step from (phi_prev, phi_cur) with initial guess (mu,
  * p) (device arrays, read only; the state is not advanced), solves the step
- * to tol once for each of a fixed set of candidates (nu1, nu2 on the finest
- * level, nu1_coarse, nu2_coarse below it, prolong), times the solve (setup
- * and cycles, after one untimed solve that captures the cycle graphs) and
- * keeps the fastest in the context's options.  Candidates that do not reach
- * tol within max_vcycles are skipped.  The solution is the same to tol for
+ * to tol for each of a fixed set of candidates (nu1, nu2 on the finest
+ * level, nu1_coarse, nu2_coarse below it, prolong; the context's own options
+ * first), times the solve (setup and cycles; the best of three after one
+ * untimed solve that captures the cycle graphs) and keeps the fastest in the
+ * context's options, replacing the given ones only if it is more than 2%
+ * faster.  Candidates that do not reach tol within max_vcycles are skipped.  The solution is the same to tol for
  * every candidate (Theorem 2.1: one solution per step); only the time and the
  * cycle count differ.  choice_out (host, or NULL): the kept nu1, nu2,
  * nu1_coarse, nu2_coarse, prolong.  CHHS_E_NOCONV if no candidate converges

@@ -237,7 +237,7 @@ def chhs_level_count(ctx):
     return n.value
 
 
-KERNEL_KINDS = ["tiles", "strips", "per-cell", "tail"]
+KERNEL_KINDS = ["tiles", "strips", "per-cell", "tail", "zmarch"]
 
 
 def chhs_level_kernel(ctx, level):

@@ -130,6 +130,7 @@ struct TileTask { int inst; int bx; int by; }; // one tile of a 2D level
 struct StripTask { int inst; int sx; int y0; int y1; };   // rows [y0, y1) of strip sx
 struct Range { int begin; int end; };          // an instance's blocks in a partial buffer
 struct FoldTask { int inst; int begin; int end; };   // partials [begin, end) of one instance
+struct Step3Task { int inst; int bx; int by; int z0; int z1; };   // tile (bx, by), planes [z0, z1)
 
 // Arguments common to every batched launch.
 template <typename T>
@@ -285,6 +286,15 @@ constexpr int kStripWO = kStripW - 2 * kStripHX;
 template <typename T>
 void launch_stream2d(const Batch<T>& b, const StripTask* t, int nt, bool level0, int ns, int epi,
                      bool pro, bool zero, double* partial, hipStream_t st);
+
+// ---- fused 3D smoothing steps by z marching (chhs_step3d.hip) ----------------------
+// One red-black smoothing step on level b.level of every tasked instance, read
+// from copy b.cur and written to the other copy.  Tiles of (x, y) columns:
+// 16 x 16 in FP64, 32 x 16 in FP32 (correction form).
+constexpr int kStep3TX64 = 16, kStep3TY64 = 16;
+constexpr int kStep3TX32 = 32, kStep3TY32 = 16;
+void launch_step3d(const Batch<double>& b, const Step3Task* t, int nt, hipStream_t st);
+void launch_step3d(const Batch<float>& b, const Step3Task* t, int nt, hipStream_t st);
 
 // ---- single-workgroup coarse tail (chhs_tail.hip) ----------------------------------
 // The cycle's shape: smoothing steps before / after the coarse correction on

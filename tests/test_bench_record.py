@@ -72,3 +72,17 @@ def test_vcycle_bytes_counts_every_launch_of_the_cycle():
         want3 += sum(launches) * m[l]
     want3 += 8 * (9 * m[4] + 2 * sum(m[4:]))
     assert abs(bench.vcycle_bytes(3, (128,) * 3, lk3) - want3) < 1e-6 * want3
+
+
+def test_vcycle_bytes_follow_the_tuned_sweeps():
+    """(nu1, nu2) = (1, 2) on the finest level, 3 and 3 below it, bilinear
+    prolongation: one pre launch and one post launch on the finest level plus
+    the prolongation launch; two of each on the tiled coarse levels."""
+    lk = [("strips", 50, 738)] + [("tiles", 512, 1024)] * 5 + [("tail", 0, 0)] * 5
+    n = [2048 * 2048 // 4 ** l for l in range(11)]
+    want = 8 * ((9 + 9 / 4) + (9 + 6 + 6 / 4)) * n[0]
+    for l in range(1, 6):
+        want += 8 * ((2 * 11 + 3 + 9 / 4) + (2 * 11 + 6 + 6 / 4)) * n[l]
+    want += 8 * (9 * n[6] + 2 * sum(n[6:]))
+    got = bench.vcycle_bytes(2, (2048, 2048), lk, (1, 2, 3, 3, 1))
+    assert abs(got - want) < 1e-6 * want
