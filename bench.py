@@ -777,7 +777,8 @@ def main():
                          "sweeps per level and the prolongation by time to tolerance after the "
                          "warm-up steps")
     ap.add_argument("--smoother", type=int, default=0,
-                    help="2D smoother: 0 default (strips on the finest level), 1 tiles, 2 strips")
+                    help="0 default (2D strips on the finest level; 3D fused step where segments are long), "
+                         "1 2D tiles, 2 2D strips, 3 3D per-cell kernels, 4 3D fused step everywhere")
     args = ap.parse_args()
 
     if args.traffic_record:

@@ -82,10 +82,12 @@ typedef struct chhs_problem {
  * the 2D smoothing kernels of the levels above the single-workgroup tail:
  * 0 = default (row-streaming strips on the finest level, square LDS tiles on
  * coarser ones), 1 = tiles everywhere, 2 = strips on every level (including
- * the explicit smoothing calls on tail levels), 3 = per-cell red-black
- * kernels on 3D levels (one launch per color) instead of the default fused
- * z-marching step.  All kernels perform the same red-black updates (results
- * agree to rounding).
+ * the explicit smoothing calls on tail levels).  On 3D levels above the tail:
+ * 0 = the fused z-marching step on levels whose z segments hold at least 16
+ * planes, per-cell red-black kernels (one launch per color) on the others,
+ * 3 = per-cell kernels on every level, 4 = the fused step on every level
+ * (3D second-order scheme only).  All kernels perform the same red-black
+ * updates (results agree to rounding).
  * tile_threads = 0 (default) gives tiled levels 1024-thread blocks when they
  * have at most 256 tiles and 256-thread blocks otherwise; 256, 512 or 1024
  * fixes the block size of every tiled level (the same arithmetic per cell).
@@ -93,11 +95,12 @@ typedef struct chhs_problem {
  * have at most 128 tiles of 64 x 16 (over the batch) and into 64 x 16 tiles
  * otherwise; 16, 8 or 4 fixes the tile height of every coarse tiled level
  * (the finest level always has 64 x 16 tiles).
- * autotune = 1 (2D, smoother = 0, nu1, nu2 >= 1): chhs_init times, on the problem at hand,
- * each level's smoothing launches with tiles of 256, 512 and 1024 threads (on
- * coarse levels each with 16, 8 and 4 rows) and with
- * strips of 1, 2 and 4 times the default segment height, and keeps the fastest
- * per level (the choice then depends on the device; results agree to rounding).
+ * autotune = 1 (smoother = 0, second-order scheme): chhs_init times, on the
+ * problem at hand, each level's smoothing launches and keeps the fastest per
+ * level (the choice then depends on the device; results agree to rounding).
+ * 2D (nu1, nu2 >= 1): tiles of 256, 512 and 1024 threads (on coarse levels
+ * each with 16, 8 and 4 rows) and strips of 1/4, 1/2, 1, 2 and 4 times the
+ * default segment height.  3D: the fused step or the per-cell kernels.
  * order = 2 (default; 0 means the same) solves the second-order scheme
  * (2.4)-(2.7).  order = 1 solves instead the first-order convex-splitting step
  * that Remark 2.2 names as a way to obtain phi^1 from phi^0 (its form is cited,

@@ -67,11 +67,14 @@ struct Layout {
     // tile sizes) and z-segment height per level
     std::vector<std::vector<Step3Task>> Z64, Z32;
     int zseg64[kMaxLevels] = {}, zseg32[kMaxLevels] = {};
+    // 3D level smoothed by the fused step (else by one launch per color)
+    bool z3[kMaxLevels] = {};
     bool strip[kMaxLevels] = {};            // level smoothed by the row-streaming kernel
     int tile_threads[kMaxLevels] = {};      // tiles: threads per block, 0 = by the tile count
     int tile_y[kMaxLevels] = {};            // tile height of the level's tasks (T)
     int tile_y_all[kMaxLevels] = {};        // tile height of the tasks over every instance (Tall)
     size_t cap_T[kMaxLevels] = {};          // capacity of T: tasks of the smallest tile height
+    size_t cap_S[kMaxLevels] = {};          // capacity of S: tasks of the shortest tuned segment
     int seg[kMaxLevels] = {};               // rows per strip segment of S[l]
     // per level and instance: x / y extent of the grids in S[l] (-1: not listed)
     std::vector<std::vector<int>> snx, sny;
@@ -219,7 +222,7 @@ bool valid_opts(const chhs_opts* o) {
     if (o->max_vcycles < 1 || o->coarse_sweeps < 1) return false;
     if (!(o->tol > 0.0) || !std::isfinite(o->tol)) return false;
     if (o->precision != 0 && o->precision != 1) return false;
-    if (o->smoother < 0 || o->smoother > 3) return false;
+    if (o->smoother < 0 || o->smoother > 4) return false;
     if (o->autotune < 0 || o->autotune > 1) return false;
     if (o->order < 0 || o->order > 2) return false;
     if (o->order == 1 && o->precision != 0) return false;
@@ -384,10 +387,15 @@ void fused_ranges(Layout& L, int n_inst) {
         task_ranges(L.rngT0, n_inst, L.T[0]);
 }
 
-// 3D levels above the tail are smoothed by the fused z-marching step kernel
+// 3D levels above the tail may be smoothed by the fused z-marching step kernel
 // (the second-order scheme, unless opts.smoother = 3 asks for the per-cell
-// red-black kernels).
+// red-black kernels everywhere); which levels do is Layout::z3.
 bool step3d_opts(int dim, const chhs_opts* o) { return dim == 3 && o->order != 1 && o->smoother != 3; }
+
+// Planes per segment below which a level is left to the per-color kernels by
+// default: the segments of such levels are short (few planes per workgroup to
+// amortise the four halo planes) or too few workgroups fill the device.
+constexpr int kStep3MinSeg = 16;
 
 // Fused-step tasks of one 3D level over the listed instances (extents, -1 =
 // skip): tiles of tx x ty columns, z-segments of zs planes.
@@ -446,6 +454,9 @@ bool plan(const chhs_problem* p, int n_inst, const chhs_opts* o, char* base, Lay
         if (!valid_problem(&p[i])) return false;
     if (!valid_total(p, n_inst)) return false;
     const int dim = p[0].dim;
+    // smoother 4 (the fused step on every level) is a 3D choice of the
+    // second-order scheme
+    if (o->smoother == 4 && (dim != 3 || o->order == 1)) return false;
     const bool mixed = o->precision == 1;
     L.A.resize(kMaxLevels);
     L.B.resize(kMaxLevels);
@@ -609,6 +620,11 @@ bool plan(const chhs_problem* p, int n_inst, const chhs_opts* o, char* base, Lay
             strip_tasks(L.Sall[l], lnx[l], lny[l], strip_seg(lnx[l], lny[l], slots));
             L.seg[l] = strip_seg(lnx_t[l], lny[l], slots);
             strip_tasks(L.S[l], lnx_t[l], lny[l], L.seg[l]);
+            {
+                std::vector<StripTask> shortest;
+                strip_tasks(shortest, lnx_t[l], lny[l], std::max(8, (L.seg[l] / 4) & ~1));
+                L.cap_S[l] = shortest.size();
+            }
             L.tile_threads[l] = o->tile_threads;
             // default: strips on the finest level (long segments, two blocks
             // per compute unit), tiles below, where more and shorter blocks
@@ -632,6 +648,10 @@ bool plan(const chhs_problem* p, int n_inst, const chhs_opts* o, char* base, Lay
                 step3_tasks(L.Z32[l], lnx_t[l], lny[l], lnz[l], chhs::kStep3TX32, chhs::kStep3TY32,
                             L.zseg32[l]);
             }
+            // smoother 4: every level; default: levels with long enough segments
+            // (the autotuner may choose anew)
+            const int zs = mixed ? L.zseg32[l] : L.zseg64[l];
+            L.z3[l] = o->smoother == 4 || zs >= kStep3MinSeg;
         }
     // 2D mixed precision: tasks of the row-marching refinement step over every
     // instance's finest level (instance, then row segment, then column window)
@@ -688,7 +708,7 @@ bool plan(const chhs_problem* p, int n_inst, const chhs_opts* o, char* base, Lay
         L.tile_y_all[l] = L.tile_y[l];
         L.off_T.push_back(take(std::max(L.T[l].size(), L.cap_T[l]) * sizeof(TileTask)));
         L.off_Tall.push_back(take(L.Tall[l].size() * sizeof(TileTask)));
-        L.off_S.push_back(take(L.S[l].size() * sizeof(StripTask)));
+        L.off_S.push_back(take(std::max(L.S[l].size(), L.cap_S[l]) * sizeof(StripTask)));
         L.off_Sall.push_back(take(L.Sall[l].size() * sizeof(StripTask)));
         L.off_Z64.push_back(take(L.Z64[l].size() * sizeof(Step3Task)));
         L.off_Z32.push_back(take(L.Z32[l].size() * sizeof(Step3Task)));
@@ -888,6 +908,8 @@ void restore_copy0(chhs_ctx* c, const Hier<T>& H, int l) {
 // (the second-order scheme); otherwise by the per-cell red-black kernels.
 bool tiled2d(const chhs_ctx* c) { return c->dim == 2 && c->opts.order != 1; }
 bool fused3d(const chhs_ctx* c) { return step3d_opts(c->dim, &c->opts); }
+// Level l of the smoothing hierarchy takes the fused 3D step.
+bool z3_at(const chhs_ctx* c, int l) { return fused3d(c) && c->lay.z3[l]; }
 
 // nsweeps smoothing steps on level l of the FP64 hierarchy (2D: tiled,
 // including levels inside the tail for kernel tests; 3D and the first-order
@@ -901,7 +923,7 @@ void smooth_steps(chhs_ctx* c, int l, int nsweeps, const int* active, int cls) {
         }
         return;
     }
-    if (fused3d(c) && c->Z64[l].n > 0) {
+    if (z3_at(c, l) && c->Z64[l].n > 0) {
         for (int s = 0; s < nsweeps; ++s) step3(c, hier64(c), l, active, cls);
         return;
     }
@@ -946,7 +968,7 @@ void enqueue_vcycle(chhs_ctx* c, const Hier<T>& H) {
             tiled(c, H, false, d, rem, 1, false, act, pre_cls, rhs && first, first ? psh : nullptr,
                   zero && first);
         } else {
-            if (fused3d(c))
+            if (z3_at(c, d))
                 for (int s = 0; s < nu1; ++s) step3(c, H, d, act, pre_cls);
             else if (!tiled2d(c))
                 for (int s = 0; s < nu1; ++s)
@@ -1006,7 +1028,7 @@ void enqueue_vcycle(chhs_ctx* c, const Hier<T>& H) {
                 chhs::launch_prolong(dim, make_batch(H.dev, H.cur, d, act), c->B[d].dev, c->B[d].n,
                                      bil, c->stream);
             }
-            if (fused3d(c))
+            if (z3_at(c, d))
                 for (int s = 0; s < nu2; ++s) step3(c, H, d, act, post_cls);
             else if (!tiled2d(c))
                 for (int s = 0; s < nu2; ++s)
@@ -1067,6 +1089,63 @@ float time_level(chhs_ctx* c, const Hier<T>& H, int l, int reps, hipEvent_t ea, 
     return best;
 }
 
+// Device time (ms) of nu1 + nu2 smoothing steps on 3D level l of hierarchy H
+// with the level's current kernel choice, the best of `reps`.
+template <typename T>
+float time_level3(chhs_ctx* c, const Hier<T>& H, int l, int reps, hipEvent_t ea, hipEvent_t eb) {
+    const int steps = nu_pre(c->opts, l) + nu_post(c->opts, l);
+    float best = 1e30f;
+    for (int r = 0; r < reps; ++r) {
+        if (hipEventRecord(ea, c->stream) != hipSuccess) return -1.0f;
+        for (int s = 0; s < steps; ++s) {
+            if (z3_at(c, l)) {
+                step3(c, H, l, nullptr, CHHS_K_PRE0);
+            } else {
+                for (int color = 0; color < 2; ++color)
+                    chhs::launch_smooth_color(3, make_batch(H.dev, H.cur, l, nullptr), c->Bh[l].dev,
+                                              c->Bh[l].n, color, c->stream);
+            }
+        }
+        if (hipEventRecord(eb, c->stream) != hipSuccess || hipEventSynchronize(eb) != hipSuccess)
+            return -1.0f;
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, ea, eb) != hipSuccess) return -1.0f;
+        best = std::min(best, ms);
+    }
+    if (H.cur[l] != 0) restore_copy0(c, H, l);
+    return best;
+}
+
+// 3D: per level above the tail, the fused step or one launch per color,
+// whichever smooths faster on the problem at hand.
+int autotune3(chhs_ctx* c) {
+    hipEvent_t ea = nullptr, eb = nullptr;
+    if (hipEventCreate(&ea) != hipSuccess || hipEventCreate(&eb) != hipSuccess) {
+        if (ea) (void)hipEventDestroy(ea);
+        return CHHS_E_HIP;
+    }
+    const chhs_opts saved = c->opts;
+    c->opts.timing = 0;
+    int rc = CHHS_OK;
+    for (int l = 0; l < c->lay.depth && rc == CHHS_OK; ++l) {
+        if ((c->mixed ? c->Z32[l].n : c->Z64[l].n) == 0) continue;
+        float t[2];
+        for (int k = 0; k < 2 && rc == CHHS_OK; ++k) {
+            c->lay.z3[l] = k == 1;
+            t[k] = c->mixed ? time_level3(c, hier32(c), l, 3, ea, eb)
+                            : time_level3(c, hier64(c), l, 3, ea, eb);
+            if (t[k] < 0.0f) rc = CHHS_E_HIP;
+        }
+        if (rc == CHHS_OK) c->lay.z3[l] = t[1] < t[0];
+    }
+    (void)hipEventDestroy(ea);
+    (void)hipEventDestroy(eb);
+    c->opts = saved;
+    if (rc) return rc;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return check_launch();
+}
+
 // Picks, per 2D level above the tail, the fastest of: tiles with 256, 512 or
 // 1024 threads (on coarse levels each also 16, 8 and 4 rows high), strips with 1, 2 or 4 times the default segment height.  Runs the
 // candidates on the workspace as it is (its contents do not matter for the
@@ -1100,12 +1179,21 @@ int autotune(chhs_ctx* c) {
                 maxny = std::max(maxny, L.sny[l][i]);
             }
         const int seg0 = L.seg[l];
-        if (even && c->S[l].n > 0)
+        if (even && c->S[l].n > 0) {
+            // segments of a quarter, half, one, two and four times the default
+            // height (even, at least 8 rows; the strip table holds the tasks of
+            // the shortest)
+            for (int d : {4, 2}) {
+                const int sg = std::max(8, (seg0 / d) & ~1);
+                if (sg < seg0 && (cands.empty() || !cands.back().strip || sg > cands.back().seg))
+                    cands.push_back({true, 0, sg, 0});
+            }
             for (int m = 1; m <= 4; m *= 2) {
                 const int sg = std::min(seg0 * m, (maxny + 1) & ~1);
                 if (m == 1 || sg > cands.back().seg) cands.push_back({true, 0, sg, 0});
             }
-        const int cap = c->S[l].n;
+        }
+        const size_t cap = std::max(L.cap_S[l], size_t(c->S[l].n));
         auto apply = [&](const Cand& k) -> int {
             L.strip[l] = k.strip;
             L.tile_threads[l] = k.threads;
@@ -1125,7 +1213,7 @@ int autotune(chhs_ctx* c) {
             L.seg[l] = k.seg;
             L.S[l].clear();
             strip_tasks(L.S[l], L.snx[l], L.sny[l], k.seg);
-            if (int(L.S[l].size()) > cap) return CHHS_E_INVAL;
+            if (L.S[l].size() > cap) return CHHS_E_INVAL;
             c->S[l].n = int(L.S[l].size());
             HIP_TRY(hipMemcpyAsync(c->S[l].dev, L.S[l].data(), L.S[l].size() * sizeof(StripTask),
                                    hipMemcpyHostToDevice, c->stream));
@@ -1816,6 +1904,10 @@ int chhs_init(const chhs_problem* p, int32_t n_inst, const chhs_opts* o, void* w
         const int arc = autotune(c);
         if (arc) return fail(arc);
     }
+    if (o->autotune && o->smoother == 0 && fused3d(c)) {
+        const int arc = autotune3(c);
+        if (arc) return fail(arc);
+    }
     *out = c;
     return CHHS_OK;
 }
@@ -1939,7 +2031,7 @@ int chhs_level_kernel(chhs_ctx* c, int32_t level, int32_t* out3) {
         out3[0] = 3;
         out3[1] = 0;
         out3[2] = 0;
-    } else if (fused3d(c)) {
+    } else if (z3_at(c, level)) {
         out3[0] = 4;
         out3[1] = c->mixed ? c->lay.zseg32[level] : c->lay.zseg64[level];
         out3[2] = c->mixed ? c->Z32[level].n : c->Z64[level].n;
