@@ -80,10 +80,13 @@ def launch_bytes_per_cell(dim, cls, mixed=False, kind=None):
     return (8 + 3) * 8 if kind == "zmarch" else (4 + 6 + 3) / 2 * 8
 
 
+SWEEP_KEYS = ("nu1", "nu2", "nu1_coarse", "nu2_coarse", "prolong", "inner_cycles")
+
+
 def vcycle_bytes(dim, shape, level_kernels, sweeps=None):
     """Algorithmic bytes of one FP64 V-cycle over every level.
 
-    sweeps: (nu1, nu2, nu1_coarse, nu2_coarse, prolong) as chhs_get_opts
+    sweeps: (nu1, nu2, nu1_coarse, nu2_coarse, prolong[, inner_cycles]) as chhs_tune_sweeps
     reports them (default V(2,2), piecewise-constant prolongation).  Per cell
     of level l (n_l cells, r = 2^dim children per coarse cell, 8 B per value),
     what each launch of the cycle must move at minimum; a fused 2D launch
@@ -113,7 +116,7 @@ def vcycle_bytes(dim, shape, level_kernels, sweeps=None):
                                     phi_* and phi^m of every tail level read
     The norm reduction and the per-cycle readback (a few KB) are left out.
     """
-    nu1, nu2, nu1c, nu2c, prolong = sweeps if sweeps is not None else (2, 2, 0, 0, 0)
+    nu1, nu2, nu1c, nu2c, prolong = tuple(sweeps)[:5] if sweeps is not None else (2, 2, 0, 0, 0)
     nu1c = nu1c or nu1
     nu2c = nu2c or nu2
     r = 2 ** dim
@@ -206,7 +209,7 @@ def _oracle_step(job):
     from oracle import fas, scheme
     prev, cur, mu, p, eps, gamma, s, h, cyc = job
     prm = scheme.Params(eps=eps, gamma=gamma, s=s, h=h)
-    nu1, nu2, nu1c, nu2c, prolong = cyc
+    nu1, nu2, nu1c, nu2c, prolong = tuple(cyc)[:5]
     opts = fas.Opts(tol=1e-10, nu1=nu1, nu2=nu2, nu1_coarse=nu1c, nu2_coarse=nu2c,
                     prolong="bilinear" if prolong == 1 else "constant")
     t0 = time.perf_counter()
@@ -304,7 +307,8 @@ def run_batched(args, pool):
     sv = chhs.Solver(probs, chhs.chhs_default_opts(tol=1e-10, precision=1,
                                                    timing=chhs.timing_mask(*cand),
                                                    smoother=args.smoother,
-                                                   autotune=int(args.autotune)))
+                                                   autotune=int(args.autotune),
+                                                   inner_cycles=args.inner_cycles))
     for k in range(args.warmup):
         _, lg = sv.step_log(tp, tc, tm, tpp, 1)
         log(f"warmup step {k + 1}/{args.warmup}: max {max(x['vcycles'] for x in lg[0])} "
@@ -316,7 +320,7 @@ def run_batched(args, pool):
         # sweeps per level and prolongation by time to tolerance, on the
         # current step's system (the state is not advanced)
         sweeps = sv.tune_sweeps(tp, tc, tm, tpp)
-        log(f"tuned (nu1, nu2, nu1_coarse, nu2_coarse, prolong) = {sweeps}")
+        log(f"tuned {SWEEP_KEYS} = {sweeps}")
     sv.set_timing(chhs.timing_mask(cls))
     torch.cuda.synchronize()
     start = [t.clone() for t in (tp, tc, tm, tpp)]
@@ -363,8 +367,8 @@ def run_batched(args, pool):
     # timed (outside the timed region)
     kernel_ms = {}
     if not args.no_breakdown:
-        extra = {} if sweeps is None else dict(zip(
-            ("nu1", "nu2", "nu1_coarse", "nu2_coarse", "prolong"), sweeps))
+        extra = (dict(inner_cycles=args.inner_cycles) if sweeps is None
+                 else dict(zip(SWEEP_KEYS, sweeps)))
         sb = chhs.Solver(probs, chhs.chhs_default_opts(tol=1e-10, precision=1, timing=1,
                                                        smoother=args.smoother,
                                                        autotune=int(args.autotune), **extra))
@@ -434,6 +438,7 @@ def run_batched(args, pool):
                    "grids": [128, 256, 512, 1024], "cells": cells, "eps": "U[0.01,0.05]",
                    "gamma": "U[0.5,5]", "s": "{1e-4,5e-4}", "tol": 1e-10, "cycle": "V(2,2)",
                    "precision": "fp32 inner + fp64 refinement",
+                   "inner_cycles": max(1, sweeps[5] if sweeps is not None else args.inner_cycles),
                    "reductions": "mass, E_h, F_h, dissipation every step"},
         "instance_steps_per_s": inst_steps / elapsed,
         "refinement_steps_per_instance_step": total_refine / inst_steps,
@@ -446,8 +451,7 @@ def run_batched(args, pool):
         "speedup_vs_sequential_fp64": elapsed_seq / elapsed if seq else None,
         "energy_F_nonincreasing": bool(f_ok),
         "level_kernels": level_kernels,
-        "sweeps": None if sweeps is None else dict(zip(
-            ("nu1", "nu2", "nu1_coarse", "nu2_coarse", "prolong"), sweeps)),
+        "sweeps": None if sweeps is None else dict(zip(SWEEP_KEYS, sweeps)),
         "sequential_fp64_sweeps": seq_sweeps or None,
         "kernel_ms_per_step": kernel_ms,
         "roofline": roofline,
@@ -517,6 +521,7 @@ def run_single(args, name, cpu_baseline=True, parity=True, breakdown=True, copy_
     cand = ("pre0", "post0", "refine") if mixed else ("pre0", "post0")
     opts = chhs.chhs_default_opts(tol=1e-10, timing=chhs.timing_mask(*cand),
                                   smoother=args.smoother, precision=1 if mixed else 0,
+                                  inner_cycles=args.inner_cycles if mixed else 0,
                                   autotune=int(args.autotune))
     sv = chhs.Solver(prob, opts)
     tp = torch.from_numpy(phi0).cuda()
@@ -542,7 +547,7 @@ def run_single(args, name, cpu_baseline=True, parity=True, breakdown=True, copy_
     cls = dominant_class(tim_w, cand)
     sweeps = sv.tune_sweeps(tp, tc, tm, tpp) if args.tune_sweeps else None
     if sweeps is not None:
-        log(f"tuned (nu1, nu2, nu1_coarse, nu2_coarse, prolong) = {sweeps}")
+        log(f"tuned {SWEEP_KEYS} = {sweeps}")
     sv.set_timing(chhs.timing_mask(cls))
 
     torch.cuda.synchronize()
@@ -583,8 +588,8 @@ def run_single(args, name, cpu_baseline=True, parity=True, breakdown=True, copy_
                 "traffic": measured_traffic(name, other, level_kernels[0])}
     kernel_ms = {}
     if breakdown:
-        extra = {} if sweeps is None else dict(zip(
-            ("nu1", "nu2", "nu1_coarse", "nu2_coarse", "prolong"), sweeps))
+        extra = (dict(inner_cycles=args.inner_cycles if mixed else 0) if sweeps is None
+                 else dict(zip(SWEEP_KEYS, sweeps)))
         sb = chhs.Solver(prob, chhs.chhs_default_opts(tol=1e-10, timing=1, smoother=args.smoother,
                                                       precision=1 if mixed else 0,
                                                       autotune=int(args.autotune), **extra))
@@ -613,6 +618,8 @@ def run_single(args, name, cpu_baseline=True, parity=True, breakdown=True, copy_
         "config": {"workload": name, "grid": list(shape), "eps": w["eps"],
                    "gamma": w["gamma"], "s": w["s"], "tol": 1e-10, "cycle": "V(2,2)",
                    "precision": "fp32 inner + fp64 refinement" if mixed else "fp64",
+                   **({"inner_cycles": max(1, sweeps[5] if sweeps is not None else args.inner_cycles)}
+                      if mixed else {}),
                    "reductions": "mass, E_h, F_h, dissipation every step"},
         "vcycles_per_s": vcyc / elapsed,
         "steps_per_s": args.steps / elapsed,
@@ -620,8 +627,7 @@ def run_single(args, name, cpu_baseline=True, parity=True, breakdown=True, copy_
         "res_norm_last": lg[-1][0]["res_norm"],
         "kernel_ms_per_step": kernel_ms,
         "level_kernels": [list(k) for k in level_kernels],
-        "sweeps": None if sweeps is None else dict(zip(
-            ("nu1", "nu2", "nu1_coarse", "nu2_coarse", "prolong"), sweeps)),
+        "sweeps": None if sweeps is None else dict(zip(SWEEP_KEYS, sweeps)),
         "roofline": roofline,
         "per_vcycle": None,
     }
@@ -776,6 +782,8 @@ def main():
                     help="keep V(2,2) with piecewise-constant prolongation instead of choosing the "
                          "sweeps per level and the prolongation by time to tolerance after the "
                          "warm-up steps")
+    ap.add_argument("--inner-cycles", type=int, default=1,
+                    help="FP32 correction V-cycles per FP64 refinement (mixed precision)")
     ap.add_argument("--smoother", type=int, default=0,
                     help="0 default (2D strips on the finest level; 3D fused step where segments are long), "
                          "1 2D tiles, 2 2D strips, 3 3D per-cell kernels, 4 3D fused step everywhere")

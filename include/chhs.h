@@ -115,7 +115,12 @@ typedef struct chhs_problem {
  * prolong = 0 (default) prolongs the coarse correction by piecewise-constant
  * injection, 1 by cell-centred bi/trilinear interpolation (3/4, 1/4 along each
  * axis, continued evenly across the boundary); Section 5 leaves the transfer
- * operators open, and both converge to the same solution (Theorem 2.1). */
+ * operators open, and both converge to the same solution (Theorem 2.1).
+ * inner_cycles (precision = 1; 0 means 1, at most 8): FP32 correction-form
+ * V-cycles per FP64 refinement (residual, stopping test and update).  With
+ * more than one the stopping test runs every inner_cycles FP32 cycles, and
+ * chhs_stats.vcycles counts refinements; the converged solution is the same
+ * (to the tolerance). */
 typedef struct chhs_opts {
     int32_t nu1, nu2, max_vcycles, coarse_sweeps;
     double tol;
@@ -129,6 +134,7 @@ typedef struct chhs_opts {
     int32_t tile_rows;
     int32_t nu1_coarse, nu2_coarse;
     int32_t prolong;
+    int32_t inner_cycles;
 } chhs_opts;
 
 /* Kernel classes of chhs_timing. */
@@ -294,19 +300,21 @@ int chhs_get_timing(chhs_ctx* c, chhs_timing* out, int32_t reset);
  * timing is 0).  CHHS_E_INVAL for a negative mask. */
 int chhs_set_timing(chhs_ctx* c, int32_t timing);
 
-/* Chooses the sweeps per level and the prolongation by time to tolerance:
+/* Chooses the sweeps per level and the prolongation (and, in mixed precision,
+ * the FP32 cycles per refinement) by time to tolerance:
  * on the system of the step from (phi_prev, phi_cur) with initial guess (mu,
  * p) (device arrays, read only; the state is not advanced), solves the step
  * to tol for each of a fixed set of candidates (nu1, nu2 on the finest
  * level, nu1_coarse, nu2_coarse below it, prolong; the context's own options
- * first), times the solve (setup and cycles; the best of three after one
+ * first; then, for precision = 1, inner_cycles 1, 2 and 3 with the kept
+ * cycle), times the solve (setup and cycles; the best of three after one
  * untimed solve that captures the cycle graphs) and keeps the fastest in the
  * context's options, replacing the given ones only if it is more than 2%
  * faster.  Candidates that do not reach tol within max_vcycles are skipped.  The solution is the same to tol for
  * every candidate (Theorem 2.1: one solution per step); only the time and the
- * cycle count differ.  choice_out (host, or NULL): the kept nu1, nu2,
- * nu1_coarse, nu2_coarse, prolong.  CHHS_E_NOCONV if no candidate converges
- * (options unchanged). */
+ * cycle count differ.  choice_out (host, 6 values, or NULL): the kept nu1,
+ * nu2, nu1_coarse, nu2_coarse, prolong, inner_cycles.  CHHS_E_NOCONV if no
+ * candidate converges (options unchanged). */
 int chhs_tune_sweeps(chhs_ctx* c, const double* phi_prev, const double* phi_cur, const double* mu,
                      const double* p, int32_t* choice_out);
 

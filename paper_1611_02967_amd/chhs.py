@@ -39,7 +39,8 @@ class chhs_opts(ctypes.Structure):
                 ("smoother", ctypes.c_int32), ("autotune", ctypes.c_int32),
                 ("order", ctypes.c_int32), ("tile_threads", ctypes.c_int32),
                 ("tile_rows", ctypes.c_int32), ("nu1_coarse", ctypes.c_int32),
-                ("nu2_coarse", ctypes.c_int32), ("prolong", ctypes.c_int32)]
+                ("nu2_coarse", ctypes.c_int32), ("prolong", ctypes.c_int32),
+                ("inner_cycles", ctypes.c_int32)]
 
 
 K_CLASSES = ["pre0", "post0", "transfer0", "coarse", "norm", "setup", "refine", "k7"]
@@ -285,9 +286,10 @@ def chhs_set_timing(ctx, timing):
 
 
 def chhs_tune_sweeps(ctx, phi_prev, phi_cur, mu, p):
-    """Sweeps per level and prolongation chosen by time to tolerance; returns the
-    kept (nu1, nu2, nu1_coarse, nu2_coarse, prolong)."""
-    out = (ctypes.c_int32 * 5)()
+    """Sweeps per level, prolongation and (mixed precision) FP32 cycles per
+    refinement chosen by time to tolerance; returns the kept (nu1, nu2,
+    nu1_coarse, nu2_coarse, prolong, inner_cycles)."""
+    out = (ctypes.c_int32 * 6)()
     _check(_lib.chhs_tune_sweeps(ctx, _ptr(phi_prev), _ptr(phi_cur), _ptr(mu), _ptr(p), out),
            "chhs_tune_sweeps")
     return tuple(out)

@@ -234,6 +234,7 @@ bool valid_opts(const chhs_opts* o) {
         return false;
     if (o->nu1_coarse < 0 || o->nu2_coarse < 0) return false;
     if (o->prolong != 0 && o->prolong != 1) return false;
+    if (o->inner_cycles < 0 || o->inner_cycles > 8) return false;
     return true;
 }
 
@@ -880,12 +881,12 @@ void tiled(chhs_ctx* c, const Hier<T>& H, bool all, int l, int ns, int epi, bool
 // One fused 3D smoothing step on level l of a hierarchy (the instances above
 // their tail); flips the level's current copy.
 template <typename T>
-void step3(chhs_ctx* c, const Hier<T>& H, int l, const int* active, int cls) {
+void step3(chhs_ctx* c, const Hier<T>& H, int l, const int* active, int cls, int pro = 0) {
     Batch<T> b = make_batch(H.dev, H.cur, l, active);
     const Table<Step3Task>& z = std::is_same<T, double>::value ? c->Z64[l] : c->Z32[l];
     {
         TimedScope t(c, cls);
-        chhs::launch_step3d(b, z.dev, z.n, c->stream);
+        chhs::launch_step3d(b, z.dev, z.n, pro, c->stream);
     }
     H.cur[l] ^= 1;
 }
@@ -937,9 +938,11 @@ void smooth_steps(chhs_ctx* c, int l, int nsweeps, const int* active, int cls) {
 
 // Enqueues one FAS V(nu1, nu2) cycle of one hierarchy over the batch for the
 // instances in act_cycle.  FP64: the plain form, whose finest-level post
-// launch also yields the fused norm partials; FP32: the correction form.
+// launch also yields the fused norm partials; FP32: the correction form,
+// starting from a zero correction (zero_corr; the tiled finest level's first
+// launch then takes it as implied) or from the previous cycle's.
 template <typename T>
-void enqueue_vcycle(chhs_ctx* c, const Hier<T>& H) {
+void enqueue_vcycle(chhs_ctx* c, const Hier<T>& H, bool zero_corr = true) {
     constexpr bool kPlain = std::is_same<T, double>::value;
     const int dim = c->dim;
     const int* act = c->act_cycle;
@@ -956,7 +959,7 @@ void enqueue_vcycle(chhs_ctx* c, const Hier<T>& H) {
             // for a correction cycle, takes the zero starting correction as
             // implied
             const double* psh = kPlain && d == 0 && c->defer_shift ? c->res : nullptr;
-            const bool zero = !kPlain && d == 0;
+            const bool zero = !kPlain && d == 0 && zero_corr;
             bool first = true;
             int rem = nu1;
             while (rem > 2) {
@@ -1023,13 +1026,15 @@ void enqueue_vcycle(chhs_ctx* c, const Hier<T>& H) {
                 first = false;
             }
         } else {
-            {
+            // the fused 3D step takes the prolongation into its first launch
+            const bool pro3 = z3_at(c, d) && nu2 > 0;
+            if (!pro3) {
                 TimedScope t(c, xfer_cls);
                 chhs::launch_prolong(dim, make_batch(H.dev, H.cur, d, act), c->B[d].dev, c->B[d].n,
                                      bil, c->stream);
             }
             if (z3_at(c, d))
-                for (int s = 0; s < nu2; ++s) step3(c, H, d, act, post_cls);
+                for (int s = 0; s < nu2; ++s) step3(c, H, d, act, post_cls, s == 0 ? (bil ? 2 : 1) : 0);
             else if (!tiled2d(c))
                 for (int s = 0; s < nu2; ++s)
                     for (int color = 0; color < 2; ++color) {
@@ -1093,14 +1098,21 @@ float time_level(chhs_ctx* c, const Hier<T>& H, int l, int reps, hipEvent_t ea, 
 // with the level's current kernel choice, the best of `reps`.
 template <typename T>
 float time_level3(chhs_ctx* c, const Hier<T>& H, int l, int reps, hipEvent_t ea, hipEvent_t eb) {
-    const int steps = nu_pre(c->opts, l) + nu_post(c->opts, l);
+    const int n1 = nu_pre(c->opts, l), n2 = nu_post(c->opts, l);
+    const bool bil = c->opts.prolong == 1;
     float best = 1e30f;
     for (int r = 0; r < reps; ++r) {
         if (hipEventRecord(ea, c->stream) != hipSuccess) return -1.0f;
-        for (int s = 0; s < steps; ++s) {
+        // nu1 steps, the prolongation (a launch of its own unless the first
+        // fused post step takes it), nu2 steps
+        for (int s = 0; s < n1 + n2; ++s) {
+            const bool first_post = s == n1;
             if (z3_at(c, l)) {
-                step3(c, H, l, nullptr, CHHS_K_PRE0);
+                step3(c, H, l, nullptr, CHHS_K_PRE0, first_post ? (bil ? 2 : 1) : 0);
             } else {
+                if (first_post)
+                    chhs::launch_prolong(3, make_batch(H.dev, H.cur, l, nullptr), c->B[l].dev,
+                                         c->B[l].n, bil, c->stream);
                 for (int color = 0; color < 2; ++color)
                     chhs::launch_smooth_color(3, make_batch(H.dev, H.cur, l, nullptr), c->Bh[l].dev,
                                               c->Bh[l].n, color, c->stream);
@@ -1319,6 +1331,7 @@ void enqueue_refinement(chhs_ctx* c, bool count, bool add) {
         const Table<CellTask>& z = zero_start(c) ? c->A0t : c->A[0];
         chhs::launch_zero_correction(batch32(c, 0, act), z.dev, z.n, c->stream);
         enqueue_vcycle(c, hier32(c));
+        for (int k = 1; k < o.inner_cycles; ++k) enqueue_vcycle(c, hier32(c), false);
     }
     const bool rows = c->M0.n > 0;       // 2D: the row-marching kernel
     {
@@ -2130,76 +2143,103 @@ int chhs_tune_sweeps(chhs_ctx* c, const double* phi_prev, const double* phi_cur,
     if (c == nullptr || phi_prev == nullptr || phi_cur == nullptr || mu == nullptr || p == nullptr)
         return CHHS_E_INVAL;
     // (nu1, nu2) on the finest level, (nu1_coarse, nu2_coarse) below it
-    // (0: the same), prolongation; the context's own options come first
+    // (0: the same), prolongation, FP32 cycles per refinement (0: one); the
+    // context's own options come first
     struct Cand {
-        int nu1, nu2, nu1c, nu2c, prolong;
+        int nu1, nu2, nu1c, nu2c, prolong, inner;
         bool operator==(const Cand& o) const {
             return nu1 == o.nu1 && nu2 == o.nu2 && nu1c == o.nu1c && nu2c == o.nu2c &&
-                   prolong == o.prolong;
+                   prolong == o.prolong && std::max(1, inner) == std::max(1, o.inner);
         }
     };
     const chhs_opts saved = c->opts;
-    std::vector<Cand> cands = {{saved.nu1, saved.nu2, saved.nu1_coarse, saved.nu2_coarse,
-                                saved.prolong}};
-    for (const Cand& q : {Cand{2, 2, 0, 0, 0}, Cand{1, 1, 0, 0, 0}, Cand{2, 1, 0, 0, 0},
-                          Cand{1, 2, 0, 0, 0}, Cand{2, 2, 1, 1, 0}, Cand{1, 1, 2, 2, 0},
-                          Cand{2, 2, 3, 3, 0}, Cand{2, 2, 0, 0, 1}, Cand{1, 1, 0, 0, 1},
-                          Cand{1, 2, 0, 0, 1}})
-        if (std::find(cands.begin(), cands.end(), q) == cands.end()) cands.push_back(q);
+    const int own_inner = saved.inner_cycles;
     HIP_TRY(hipStreamSynchronize(c->stream));
     resolve_timing(c);
-    c->opts.timing = 0;
     const bool early = !c->mixed;
-    std::vector<double> times(cands.size(), 1e300);
-    int rc = CHHS_OK;
-    for (size_t k = 0; k < cands.size() && rc == CHHS_OK; ++k) {
-        const Cand& q = cands[k];
+    constexpr int kTuneReps = 3;
+    // time to tolerance of one candidate (1e300: it did not converge)
+    auto time_of = [&](const Cand& q, double& t) -> int {
         c->opts.nu1 = q.nu1;
         c->opts.nu2 = q.nu2;
         c->opts.nu1_coarse = q.nu1c;
         c->opts.nu2_coarse = q.nu2c;
         c->opts.prolong = q.prolong;
+        c->opts.inner_cycles = q.inner;
         drop_graphs(c);
         // the first solve captures the cycle graphs; the best of the next
         // kTuneReps is the candidate's time
-        constexpr int kTuneReps = 3;
-        double t = 1e300;
+        t = 1e300;
+        double best = 1e300;
         bool ok = true;
-        for (int r = 0; r <= kTuneReps && ok && rc == CHHS_OK; ++r) {
+        for (int r = 0; r <= kTuneReps && ok; ++r) {
             const auto t0 = std::chrono::steady_clock::now();
-            rc = setup(c, phi_prev, phi_cur, mu, p, true, !early);
+            int rc = setup(c, phi_prev, phi_cur, mu, p, true, !early);
             if (rc == CHHS_OK) rc = run_cycles(c, early);
             const auto t1 = std::chrono::steady_clock::now();
-            if (rc != CHHS_OK) break;
+            if (rc != CHHS_OK) return rc;
             for (int i = 0; i < c->n_inst; ++i) {
                 const double res = hres_of(c, i)[3];
                 ok = ok && std::isfinite(res) && res <= c->opts.tol;
             }
-            if (r > 0) t = std::min(t, std::chrono::duration<double>(t1 - t0).count());
+            if (r > 0) best = std::min(best, std::chrono::duration<double>(t1 - t0).count());
         }
-        if (rc == CHHS_OK && ok) times[k] = t;
+        if (ok) t = best;
+        return CHHS_OK;
+    };
+    // another candidate replaces the current pick only if it is faster by
+    // more than the timing noise between repetitions (2%)
+    auto choose = [](const std::vector<double>& times) {
+        int pick = times[0] < 1e300 ? 0 : -1;
+        for (size_t k = 1; k < times.size(); ++k)
+            if (times[k] < 1e300 && (pick < 0 || times[k] < 0.98 * times[pick])) pick = int(k);
+        return pick;
+    };
+    c->opts.timing = 0;
+    // the cycle shape first (with the context's own inner cycles) ...
+    std::vector<Cand> cands = {{saved.nu1, saved.nu2, saved.nu1_coarse, saved.nu2_coarse,
+                                saved.prolong, own_inner}};
+    for (const Cand& q : {Cand{2, 2, 0, 0, 0, own_inner}, Cand{1, 1, 0, 0, 0, own_inner},
+                          Cand{2, 1, 0, 0, 0, own_inner}, Cand{1, 2, 0, 0, 0, own_inner},
+                          Cand{2, 2, 1, 1, 0, own_inner}, Cand{1, 1, 2, 2, 0, own_inner},
+                          Cand{2, 2, 3, 3, 0, own_inner}, Cand{2, 2, 0, 0, 1, own_inner},
+                          Cand{1, 1, 0, 0, 1, own_inner}, Cand{1, 2, 0, 0, 1, own_inner}})
+        if (std::find(cands.begin(), cands.end(), q) == cands.end()) cands.push_back(q);
+    std::vector<double> times(cands.size(), 1e300);
+    int rc = CHHS_OK;
+    for (size_t k = 0; k < cands.size() && rc == CHHS_OK; ++k) rc = time_of(cands[k], times[k]);
+    int pick = rc == CHHS_OK ? choose(times) : -1;
+    Cand q = pick >= 0 ? cands[pick] : cands[0];
+    // ... then, for a mixed-precision context, the FP32 cycles per refinement
+    if (rc == CHHS_OK && pick >= 0 && c->mixed) {
+        std::vector<Cand> ic = {q};
+        for (int inner : {1, 2, 3}) {
+            Cand r = q;
+            r.inner = inner;
+            if (std::find(ic.begin(), ic.end(), r) == ic.end()) ic.push_back(r);
+        }
+        std::vector<double> ti(ic.size(), 1e300);
+        ti[0] = times[pick];
+        for (size_t k = 1; k < ic.size() && rc == CHHS_OK; ++k) rc = time_of(ic[k], ti[k]);
+        if (rc == CHHS_OK) q = ic[choose(ti)];
     }
     c->opts = saved;
     drop_graphs(c);
     if (rc != CHHS_OK) return rc;
-    // another candidate replaces the given options only if it is faster by
-    // more than the timing noise between repetitions (2%)
-    int pick = times[0] < 1e300 ? 0 : -1;
-    for (size_t k = 1; k < cands.size(); ++k)
-        if (times[k] < 1e300 && (pick < 0 || times[k] < 0.98 * times[pick])) pick = int(k);
     if (pick < 0) return CHHS_E_NOCONV;
-    const Cand& q = cands[pick];
     c->opts.nu1 = q.nu1;
     c->opts.nu2 = q.nu2;
     c->opts.nu1_coarse = q.nu1c;
     c->opts.nu2_coarse = q.nu2c;
     c->opts.prolong = q.prolong;
+    c->opts.inner_cycles = q.inner;
     if (choice_out != nullptr) {
         choice_out[0] = q.nu1;
         choice_out[1] = q.nu2;
         choice_out[2] = q.nu1c;
         choice_out[3] = q.nu2c;
         choice_out[4] = q.prolong;
+        choice_out[5] = q.inner;
     }
     return CHHS_OK;
 }

@@ -290,11 +290,13 @@ void launch_stream2d(const Batch<T>& b, const StripTask* t, int nt, bool level0,
 // ---- fused 3D smoothing steps by z marching (chhs_step3d.hip) ----------------------
 // One red-black smoothing step on level b.level of every tasked instance, read
 // from copy b.cur and written to the other copy.  Tiles of (x, y) columns:
-// 16 x 16 in FP64, 32 x 16 in FP32 (correction form).
+// 16 x 16 in FP64, 32 x 8 in FP32 (correction form).
 constexpr int kStep3TX64 = 16, kStep3TY64 = 16;
-constexpr int kStep3TX32 = 32, kStep3TY32 = 16;
-void launch_step3d(const Batch<double>& b, const Step3Task* t, int nt, hipStream_t st);
-void launch_step3d(const Batch<float>& b, const Step3Task* t, int nt, hipStream_t st);
+constexpr int kStep3TX32 = 32, kStep3TY32 = 8;
+// pro: 0 no prolongation, 1 piecewise-constant, 2 trilinear coarse correction
+// added to u (from level + 1, copy cur_c) as the launch loads it
+void launch_step3d(const Batch<double>& b, const Step3Task* t, int nt, int pro, hipStream_t st);
+void launch_step3d(const Batch<float>& b, const Step3Task* t, int nt, int pro, hipStream_t st);
 
 // ---- single-workgroup coarse tail (chhs_tail.hip) ----------------------------------
 // The cycle's shape: smoothing steps before / after the coarse correction on

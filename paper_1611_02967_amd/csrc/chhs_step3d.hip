@@ -14,9 +14,19 @@
 // everything.  The red phase covers the tile and one ring of halo cells (what
 // the black phase reads); the outer halo ring is only read.  Plane t - 3, done,
 // is written to the other copy of u (out of place: no workgroup reads a halo
-// another one has already overwritten).  A cell's own data (phi^m, the
-// right-hand sides, the base state of the correction form) is loaded one
-// iteration ahead into registers by the thread that updates it.
+// another one has already overwritten).  Loads run two iterations ahead: plane
+// t + 3 is loaded in iteration t into one of two register sets and stored to
+// LDS at the start of iteration t + 2, and a cell's own data (phi^m, the
+// right-hand sides, the base state of the correction form) is loaded two
+// iterations before its update by the thread that makes it, so a load's
+// latency overlaps a whole iteration of work.
+//
+// With pro != 0 the launch first prolongs the coarse correction: every
+// region cell's iterate is loaded as u + P(u_c - ub_c) (pro = 1 piecewise-
+// constant injection, 2 cell-centred trilinear interpolation), the update the
+// prolongation kernel makes, so the first post-smoothing step needs no pass of
+// its own over the fine level.  Halo cells get the same corrected values as in
+// the workgroup that owns them.
 //
 // Compared with one launch per color, every value is read once per step from
 // HBM (halo columns and planes aside) and the neighbours of the other color
@@ -54,7 +64,7 @@ struct Own {
 
 template <typename T, bool CORR, int TX, int TY>
 __global__ __launch_bounds__(kThreads) void k_step3d(Batch<T> bt, const Step3Task* __restrict__ tasks,
-                                                     int ntasks) {
+                                                     int ntasks, int pro) {
     using G = Geo<TX, TY>;
     constexpr int RX = G::RX, RY = G::RY, NR = G::NR;
     __shared__ T s[kRing][NRF][NR];
@@ -65,6 +75,9 @@ __global__ __launch_bounds__(kThreads) void k_step3d(Batch<T> bt, const Step3Tas
     const Step3Task tk = tasks[xcd * q8 + (xcd < rem ? xcd : rem) + jj];
     if (bt.active != nullptr && bt.active[tk.inst] == 0) return;
     const Level<T> L = make_view(bt.desc[tk.inst * kMaxLevels + bt.level], bt.cur);
+    // the coarse level of the prolongation (pro != 0 only)
+    const Level<T> C = make_view(bt.desc[tk.inst * kMaxLevels + bt.level + (pro != 0 ? 1 : 0)],
+                                 bt.cur_c);
     const int nx = L.nx, ny = L.ny, nz = L.nz;
     const int sxy = nx * ny;
     const int x0 = tk.bx * TX - kHalo, y0 = tk.by * TY - kHalo;   // region origin
@@ -78,8 +91,8 @@ __global__ __launch_bounds__(kThreads) void k_step3d(Batch<T> bt, const Step3Tas
     const T inv_lam = T(1) / lam;
 
     // ---- region loads: thread takes region cells tid + k kThreads ----------------------
-    T rv[G::KR][NRF];
-    auto load_plane = [&](int z) {
+    using Regs = T[G::KR][NRF];
+    auto load_plane = [&](int z, Regs& rv) {
 #pragma unroll
         for (int k = 0; k < G::KR; ++k) {
             const int q = tid + k * kThreads;
@@ -91,10 +104,20 @@ __global__ __launch_bounds__(kThreads) void k_step3d(Batch<T> bt, const Step3Tas
             rv[k][MU] = gload(L.mu, g);
             rv[k][P] = gload(L.p, g);
             rv[k][PS] = gload(L.pstar, g);
+            if (pro == 1 && ok) {
+                const int c = ((z >> 1) * C.ny + (gy >> 1)) * C.nx + (gx >> 1);
+                rv[k][PHI] += gload(C.phi, c) - gload(C.ub0, c);
+                rv[k][MU] += gload(C.mu, c) - gload(C.ub1, c);
+                rv[k][P] += gload(C.p, c) - gload(C.ub2, c);
+            } else if (pro == 2 && ok) {
+                rv[k][PHI] += bilinear_corr<3>(C.phi, C.ub0, C.nx, C.ny, C.nz, gx, gy, z);
+                rv[k][MU] += bilinear_corr<3>(C.mu, C.ub1, C.nx, C.ny, C.nz, gx, gy, z);
+                rv[k][P] += bilinear_corr<3>(C.p, C.ub2, C.nx, C.ny, C.nz, gx, gy, z);
+            }
             if (!ok) rv[k][PHI] = rv[k][MU] = rv[k][P] = rv[k][PS] = T(0);
         }
     };
-    auto store_plane = [&](int z) {
+    auto store_plane = [&](int z, const Regs& rv) {
         const int sl = z % kRing;
 #pragma unroll
         for (int k = 0; k < G::KR; ++k) {
@@ -181,45 +204,71 @@ __global__ __launch_bounds__(kThreads) void k_step3d(Batch<T> bt, const Step3Tas
         s[sc][P][w] = -(b3 * inv_lam + gam * sa * mun) * inv_nf;
     };
 
+    // the thread's k-th red / black cell of plane z (a function of z's parity)
+    auto red_cell = [&](int k, int z, int& rx, int& ry) {
+        const int i = tid + k * kThreads;
+        cell_of(i < G::NRED ? i : 0, G::WRX, kHalo - 1, kHalo - 1, 0, z, rx, ry);
+    };
+    auto blk_cell = [&](int k, int z, int& rx, int& ry) {
+        const int i = tid + k * kThreads;
+        cell_of(i < G::NBLK ? i : 0, TX, kHalo, kHalo, 1, z, rx, ry);
+    };
     // own data of the thread's red cells of plane z and black cells of plane z
-    Own<T> ored[G::KRED], oblk[G::KBLK];
-    int rxr[G::KRED], ryr[G::KRED], rxb[G::KBLK], ryb[G::KBLK];
-    auto prefetch_red = [&](int z) {
+    using OwnRed = Own<T>[G::KRED];
+    using OwnBlk = Own<T>[G::KBLK];
+    auto prefetch_red = [&](int z, OwnRed& o) {
 #pragma unroll
         for (int k = 0; k < G::KRED; ++k) {
-            const int i = tid + k * kThreads;
-            cell_of(i < G::NRED ? i : 0, G::WRX, kHalo - 1, kHalo - 1, 0, z, rxr[k], ryr[k]);
-            load_own(rxr[k], ryr[k], z, ored[k]);
+            int rx, ry;
+            red_cell(k, z, rx, ry);
+            load_own(rx, ry, z, o[k]);
         }
     };
-    auto prefetch_blk = [&](int z) {
+    auto prefetch_blk = [&](int z, OwnBlk& o) {
 #pragma unroll
         for (int k = 0; k < G::KBLK; ++k) {
-            const int i = tid + k * kThreads;
-            cell_of(i < G::NBLK ? i : 0, TX, kHalo, kHalo, 1, z, rxb[k], ryb[k]);
-            load_own(rxb[k], ryb[k], z, oblk[k]);
+            int rx, ry;
+            blk_cell(k, z, rx, ry);
+            load_own(rx, ry, z, o[k]);
         }
     };
 
     // ---- the pipeline ---------------------------------------------------------------------
-    load_plane(plo);
-    store_plane(plo);
-    if (plo + 1 <= zhi) load_plane(plo + 1);
-    prefetch_red(plo);
-    prefetch_blk(plo - 2);
+    // Iteration t takes register set t & 1: it holds plane t + 1 (stored to
+    // LDS first), the red own data of plane t and the black own data of plane
+    // t - 2; afterwards the same set receives plane t + 3, red t + 2, black t.
+    Regs rvA, rvB;
+    OwnRed oredA, oredB;
+    OwnBlk oblkA, oblkB;
+    load_plane(plo, rvA);
+    store_plane(plo, rvA);
+    if (plo + 1 <= zhi) load_plane(plo + 1, rvA);
+    if (plo + 2 <= zhi) load_plane(plo + 2, rvB);
+    prefetch_red(plo, oredA);
+    prefetch_blk(plo - 2, oblkA);
+    prefetch_red(plo + 1, oredB);
+    prefetch_blk(plo - 1, oblkB);
     const int t_last = z1 + 2;              // plane z1 - 1 is stored in iteration z1 + 2
-    for (int t = plo; t <= t_last; ++t) {
-        if (t + 1 <= zhi) store_plane(t + 1);
+    auto iteration = [&](int t, Regs& rv, OwnRed& ored, OwnBlk& oblk) {
+        if (t + 1 <= zhi) store_plane(t + 1, rv);
         __syncthreads();
         if (t >= rlo && t <= rhi)
 #pragma unroll
             for (int k = 0; k < G::KRED; ++k)
-                if (tid + k * kThreads < G::NRED) update(rxr[k], ryr[k], t, ored[k]);
+                if (tid + k * kThreads < G::NRED) {
+                    int rx, ry;
+                    red_cell(k, t, rx, ry);
+                    update(rx, ry, t, ored[k]);
+                }
         const int tb = t - 2;
         if (tb >= z0 && tb < z1)
 #pragma unroll
             for (int k = 0; k < G::KBLK; ++k)
-                if (tid + k * kThreads < G::NBLK) update(rxb[k], ryb[k], tb, oblk[k]);
+                if (tid + k * kThreads < G::NBLK) {
+                    int rx, ry;
+                    blk_cell(k, tb, rx, ry);
+                    update(rx, ry, tb, oblk[k]);
+                }
         // plane t - 3 is final: write the tile into the other copy of u
         const int to = t - 3;
         if (to >= z0 && to < z1) {
@@ -238,27 +287,31 @@ __global__ __launch_bounds__(kThreads) void k_step3d(Batch<T> bt, const Step3Tas
                 gstore(L.p_alt, g, s[sl][P][w]);
             }
         }
-        // loads for the next iteration: plane t + 2, own data of red t + 1 and
-        // black t - 1
-        if (t + 2 <= zhi) load_plane(t + 2);
-        prefetch_red(t + 1);
-        prefetch_blk(t - 1);
+        // loads for iteration t + 2: plane t + 3, own data of red t + 2 and
+        // black t
+        if (t + 3 <= zhi) load_plane(t + 3, rv);
+        prefetch_red(t + 2, ored);
+        prefetch_blk(t, oblk);
+    };
+    for (int t = plo; t <= t_last; t += 2) {
+        iteration(t, rvA, oredA, oblkA);
+        if (t + 1 <= t_last) iteration(t + 1, rvB, oredB, oblkB);
     }
 }
 
 template <typename T, bool CORR, int TX, int TY>
-void launch_tiles(const Batch<T>& b, const Step3Task* t, int nt, hipStream_t st) {
-    hipLaunchKernelGGL((k_step3d<T, CORR, TX, TY>), dim3(nt), dim3(kThreads), 0, st, b, t, nt);
+void launch_tiles(const Batch<T>& b, const Step3Task* t, int nt, int pro, hipStream_t st) {
+    hipLaunchKernelGGL((k_step3d<T, CORR, TX, TY>), dim3(nt), dim3(kThreads), 0, st, b, t, nt, pro);
 }
 
 }  // namespace
 
-void launch_step3d(const Batch<double>& b, const Step3Task* t, int nt, hipStream_t st) {
-    if (nt > 0) launch_tiles<double, false, kStep3TX64, kStep3TY64>(b, t, nt, st);
+void launch_step3d(const Batch<double>& b, const Step3Task* t, int nt, int pro, hipStream_t st) {
+    if (nt > 0) launch_tiles<double, false, kStep3TX64, kStep3TY64>(b, t, nt, pro, st);
 }
 
-void launch_step3d(const Batch<float>& b, const Step3Task* t, int nt, hipStream_t st) {
-    if (nt > 0) launch_tiles<float, true, kStep3TX32, kStep3TY32>(b, t, nt, st);
+void launch_step3d(const Batch<float>& b, const Step3Task* t, int nt, int pro, hipStream_t st) {
+    if (nt > 0) launch_tiles<float, true, kStep3TX32, kStep3TY32>(b, t, nt, pro, st);
 }
 
 }  // namespace chhs

@@ -61,7 +61,7 @@ int main(void) {
   printf("%zu %zu %zu\n", sizeof(chhs_problem), sizeof(chhs_opts), sizeof(chhs_stats));
   printf("%zu %zu %zu %zu %zu %zu %zu\n", offsetof(chhs_problem, h), offsetof(chhs_opts, tol), offsetof(chhs_opts, smoother), offsetof(chhs_opts, autotune), offsetof(chhs_opts, order), offsetof(chhs_opts, tile_threads), offsetof(chhs_opts, tile_rows));
   printf("%zu %zu %zu\n", offsetof(chhs_stats, res), offsetof(chhs_stats, max_abs_phi), offsetof(chhs_stats, res0));
-  printf("%zu %zu\n", offsetof(chhs_opts, nu1_coarse), offsetof(chhs_opts, prolong));
+  printf("%zu %zu %zu\n", offsetof(chhs_opts, nu1_coarse), offsetof(chhs_opts, prolong), offsetof(chhs_opts, inner_cycles));
   return 0;
 }
 """
@@ -80,7 +80,8 @@ int main(void) {
             binding.chhs_opts.tile_rows.offset,
             binding.chhs_stats.res.offset, binding.chhs_stats.max_abs_phi.offset,
             binding.chhs_stats.res0.offset,
-            binding.chhs_opts.nu1_coarse.offset, binding.chhs_opts.prolong.offset]
+            binding.chhs_opts.nu1_coarse.offset, binding.chhs_opts.prolong.offset,
+            binding.chhs_opts.inner_cycles.offset]
     assert got == want
 
 

@@ -143,3 +143,27 @@ def test_mixed_batch_equals_single_instance_runs(chhs, name):
             assert hb["stats"][i]["vcycles"] == hs["stats"][0]["vcycles"]
             counts.add(hb["stats"][i]["vcycles"])
     assert len(counts) > 1       # the instances do converge after different counts
+
+
+@pytest.mark.parametrize("name", ["2d-ragged", "3d-ragged"])
+@pytest.mark.parametrize("inner", [2, 3])
+def test_inner_cycles_solve_the_same_steps(chhs, name, inner):
+    """Several FP32 correction cycles per FP64 refinement: the stopping test
+    runs less often, the solution is the FP64 one (<= 1e-8 against the FP64
+    path, residual at tol), with no more refinements than one inner cycle
+    needs, and the batch still equals its single-instance runs bitwise."""
+    spec = SPECS[name]
+    shapes = [s[0] for s in spec]
+    phi0s = [uniform_field(sh, 4500 + i, mean=0.1, amp=0.05) for i, sh in enumerate(shapes)]
+    ref = _steps(chhs, spec, phi0s, 3, precision=0)
+    one = _steps(chhs, spec, phi0s, 3, precision=1)
+    got = _steps(chhs, spec, phi0s, 3, precision=1, inner_cycles=inner)
+    for hr, ho, hg in zip(ref, one, got):
+        assert np.max(np.abs(hg["phi"] - hr["phi"])) <= 1e-8
+        for sg, so in zip(hg["stats"], ho["stats"]):
+            assert sg["res_norm"] <= 1e-10
+            assert sg["vcycles"] <= so["vcycles"]
+    single = _steps(chhs, [spec[0]], [phi0s[0]], 3, precision=1, inner_cycles=inner)
+    for hg, hs in zip(got, single):
+        for k in ("phi", "mu", "p"):
+            assert np.array_equal(_unpack(hg[k], shapes)[0], hs[k].reshape(shapes[0])), k

@@ -127,3 +127,33 @@ def test_steps_agree_across_3d_smoothers(chhs, name, precision):
                 assert va == vb, opts
             assert np.max(np.abs(a - b)) <= tol, opts
 
+
+
+@pytest.mark.parametrize("shape", [(64, 64, 64), (56, 40, 40)])
+@pytest.mark.parametrize("prolong", [0, 1], ids=["constant", "trilinear"])
+@pytest.mark.parametrize("nu", [(2, 2), (1, 3)])
+def test_one_vcycle_with_fused_steps_matches_oracle(chhs, shape, prolong, nu):
+    """One V-cycle with the fused step on every level above the tail (the first
+    post step taking the prolongation in its loads): iterate by iterate with
+    the oracle (<= 1e-11) and with the per-cell kernels (<= 1e-13)."""
+    prm = _prm(shape)
+    prev, cur, mu0, p0 = _inputs(shape, 850)
+    out = {}
+    for mode in (PER_CELL, FUSED):
+        sv = _solver(chhs, shape, prm, smoother=mode, prolong=prolong, nu1=nu[0], nu2=nu[1])
+        sv.setup_step(dev(prev), dev(cur), dev(mu0), dev(p0))
+        res = sv.fas_vcycle()[0]
+        out[mode] = (res, [host(sv.read_field(0, n)) for n in ("phi", "mu", "p")])
+    phi_star, f = scheme.step_rhs(prev, cur, prm)
+    levels = fas.build_levels(phi_star, cur.copy(), f, prm.h)
+    u = [cur.copy(), mu0.copy(), p0 - p0.mean()]
+    us = [None] * len(levels)
+    us[0] = u
+    o = fas.Opts(nu1=nu[0], nu2=nu[1], prolong="bilinear" if prolong else "constant")
+    fas.vcycle(levels, us, 0, prm, o)
+    u[2] -= u[2].mean()
+    for k, want in enumerate(u):
+        scale = max(1.0, np.max(np.abs(want)))
+        assert np.max(np.abs(out[FUSED][1][k] - want)) <= 1e-11 * scale, k
+        assert np.max(np.abs(out[FUSED][1][k] - out[PER_CELL][1][k])) <= 1e-13 * scale, k
+    assert abs(out[FUSED][0] - out[PER_CELL][0]) <= 1e-12 * out[PER_CELL][0]

@@ -114,10 +114,11 @@ def test_tuned_sweeps_keep_the_state_and_solve_the_step(chhs, precision):
     a = [dev(flat), dev(flat), dev(z), dev(z)]
     b = [dev(flat), dev(flat), dev(z), dev(z)]
     choice = sv.tune_sweeps(*a)
-    nu1, nu2, nu1c, nu2c, prolong = choice
+    nu1, nu2, nu1c, nu2c, prolong, inner = choice
     assert nu1 >= 1 and nu2 >= 1 and nu1c >= 0 and nu2c >= 0 and prolong in (0, 1)
+    assert inner in ((1, 2, 3) if precision == 1 else (0,))
     o = sv.get_opts()
-    assert (o.nu1, o.nu2, o.nu1_coarse, o.nu2_coarse, o.prolong) == choice
+    assert (o.nu1, o.nu2, o.nu1_coarse, o.nu2_coarse, o.prolong, o.inner_cycles) == choice
     for x, want in zip(a, (flat, flat, z, z)):
         assert np.array_equal(host(x), want)
     for _ in range(2):
