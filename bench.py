@@ -18,6 +18,8 @@ reported under extra keys.  ``--workload`` selects another single workload.
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
 import argparse
+import contextlib
+import gc
 import json
 import os
 import platform
@@ -217,6 +219,19 @@ def _oracle_step(job):
     return np.asarray(r.phi), r.vcycles, time.perf_counter() - t0
 
 
+@contextlib.contextmanager
+def no_gc():
+    """Python's cyclic collector off while a region is timed (as timeit does):
+    a full collection over the interpreter's objects takes tens of
+    milliseconds and would otherwise land in whichever region it falls in."""
+    gc.collect()
+    gc.disable()
+    try:
+        yield
+    finally:
+        gc.enable()
+
+
 def make_pool(workers):
     """A pool of single-threaded worker processes, forked before this process
     touches the GPU (the workers run NumPy only)."""
@@ -327,10 +342,11 @@ def run_batched(args, pool):
     start_host = [t.cpu().numpy() for t in start]
 
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    _, lg = sv.step_log(tp, tc, tm, tpp, args.steps)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    with no_gc():
+        t0 = time.perf_counter()
+        _, lg = sv.step_log(tp, tc, tm, tpp, args.steps)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
     tim = sv.timing()
     refine = [[rec["vcycles"] for rec in step] for step in lg]
     total_refine = sum(sum(r) for r in refine)
@@ -396,14 +412,15 @@ def run_batched(args, pool):
             seq_sweeps[str(ch)] = seq_sweeps.get(str(ch), 0) + 1
         s1.step_log(*[v.clone() for v in views(sp, i)], 1)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    seq_cycles = 0
-    for _ in range(args.steps):
-        for i, s1 in enumerate(seq):
-            _, lq = s1.step_log(*views(sp, i), 1)
-            seq_cycles += lq[0][0]["vcycles"]
-    torch.cuda.synchronize()
-    elapsed_seq = max(time.perf_counter() - t0, 1e-12)
+    with no_gc():
+        t0 = time.perf_counter()
+        seq_cycles = 0
+        for _ in range(args.steps):
+            for i, s1 in enumerate(seq):
+                _, lq = s1.step_log(*views(sp, i), 1)
+                seq_cycles += lq[0][0]["vcycles"]
+        torch.cuda.synchronize()
+        elapsed_seq = max(time.perf_counter() - t0, 1e-12)
     log(f"sequential fp64: {args.steps} rounds in {elapsed_seq:.3f}s, {seq_cycles} V-cycles")
 
     # one step of both paths from the timed region's start state
@@ -551,10 +568,11 @@ def run_single(args, name, cpu_baseline=True, parity=True, breakdown=True, copy_
     sv.set_timing(chhs.timing_mask(cls))
 
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    _, lg = sv.step_log(tp, tc, tm, tpp, args.steps)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    with no_gc():
+        t0 = time.perf_counter()
+        _, lg = sv.step_log(tp, tc, tm, tpp, args.steps)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
     tim = sv.timing()
     vcyc = sum(step[0]["vcycles"] for step in lg)
     log(f"timed {args.steps} steps in {elapsed:.3f}s, {vcyc} V-cycles, last res "

@@ -1657,9 +1657,15 @@ int energies(chhs_ctx* c, int ws, const double* phi, const double* q) {
 
 // Pinned host records of the per-step energies of nsteps steps (kept by the
 // context and grown on demand).
+// Pinned host allocation and release synchronise the device: the log grows at
+// least twofold, and chhs_init reserves kLogSteps0 steps of it (at most
+// kLogBytes0), so that a call with a modest step count allocates nothing.
+constexpr int kLogSteps0 = 64;
+constexpr size_t kLogBytes0 = size_t(1) << 20;
 int reserve_log(chhs_ctx* c, int nsteps) {
-    const size_t need = size_t(nsteps) * size_t(c->n_inst) * chhs::kResStride;
+    size_t need = size_t(nsteps) * size_t(c->n_inst) * chhs::kResStride;
     if (need <= c->hlog_cap) return CHHS_OK;
+    need = std::max(need, 2 * c->hlog_cap);
     if (c->hlog != nullptr) {
         HIP_TRY(hipStreamSynchronize(c->stream));
         (void)hipHostFree(c->hlog);
@@ -1920,6 +1926,13 @@ int chhs_init(const chhs_problem* p, int32_t n_inst, const chhs_opts* o, void* w
     if (o->autotune && o->smoother == 0 && fused3d(c)) {
         const int arc = autotune3(c);
         if (arc) return fail(arc);
+    }
+    {
+        // the per-step log of chhs_step_log, reserved up front
+        const size_t per_step = size_t(n_inst) * chhs::kResStride * sizeof(double);
+        const size_t steps0 = std::max<size_t>(1, std::min<size_t>(kLogSteps0, kLogBytes0 / per_step));
+        const int lrc = reserve_log(c, int(steps0));
+        if (lrc) return fail(lrc);
     }
     *out = c;
     return CHHS_OK;
