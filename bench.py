@@ -180,7 +180,9 @@ def measured_traffic(workload, cls, level0_kernel):
     rec = recs.get(workload)
     if rec is None or rec.get("source_sha256") != kernel_source_hash(rec.get("sources", [])):
         return None
-    if list(rec.get("level0_kernel", [])) != list(level0_kernel):
+    # the finest level must run the same kind of kernel (tiles, strips, fused 3D
+    # step); the autotuned block size or segment height may differ between runs
+    if list(rec.get("level0_kernel", [None]))[:1] != list(level0_kernel)[:1]:
         return None
     return rec.get("launches", {}).get(cls)
 
@@ -278,17 +280,22 @@ def dominant_class(tim, classes):
 
 
 def roofline_record(cls, tim, bytes_per_launch, name, traffic):
+    """The roofline object of the timed class.  traffic: the class's counter
+    record (or None); its ratio of counted to algorithmic bytes, measured on
+    full-batch launches, scales this run's algorithmic bytes per launch."""
     ms_k, n_k = tim[cls]
     avg = ms_k / 1e3 / max(1, n_k)
     achieved = bytes_per_launch / avg / 1e9 if n_k else 0.0
+    ratio = None if traffic is None else (traffic["bytes_per_launch"]
+                                          / traffic["algorithmic_bytes_per_launch"])
     rec = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": round(achieved / HBM_PEAK_GBS, 4),
-           "traffic": None if traffic is None else traffic["bytes_per_launch"],
+           "traffic": None if traffic is None else round(ratio * bytes_per_launch),
            "kernel": name, "avg_launch_us": round(avg * 1e6, 2), "launches": n_k,
            "algorithmic_bytes_per_launch": round(bytes_per_launch)}
     if traffic is not None:
         rec["traffic_record"] = traffic
-        rec["traffic_ratio"] = round(traffic["bytes_per_launch"] / traffic["algorithmic_bytes_per_launch"], 3)
+        rec["traffic_ratio"] = round(ratio, 3)
     return rec
 
 
@@ -324,18 +331,21 @@ def run_batched(args, pool):
                                                    smoother=args.smoother,
                                                    autotune=int(args.autotune),
                                                    inner_cycles=args.inner_cycles))
+    sweeps = None
+    if args.tune_sweeps:
+        # sweeps per level, prolongation and FP32 cycles per refinement by time
+        # to tolerance on the first step's system (the state is not advanced),
+        # before the warm-up steps, which then run the kept cycle
+        sweeps = sv.tune_sweeps(tp, tc, tm, tpp)
+        log(f"tuned {SWEEP_KEYS} = {sweeps}")
+    inner = max(1, sweeps[5] if sweeps is not None else args.inner_cycles)
+    sv.timing(reset=True)
     for k in range(args.warmup):
         _, lg = sv.step_log(tp, tc, tm, tpp, 1)
         log(f"warmup step {k + 1}/{args.warmup}: max {max(x['vcycles'] for x in lg[0])} "
             f"refinement steps")
     tim_w = sv.timing(reset=True)
     cls = dominant_class(tim_w, cand)
-    sweeps = None
-    if args.tune_sweeps:
-        # sweeps per level and prolongation by time to tolerance, on the
-        # current step's system (the state is not advanced)
-        sweeps = sv.tune_sweeps(tp, tc, tm, tpp)
-        log(f"tuned {SWEEP_KEYS} = {sweeps}")
     sv.set_timing(chhs.timing_mask(cls))
     torch.cuda.synchronize()
     start = [t.clone() for t in (tp, tc, tm, tpp)]
@@ -364,9 +374,14 @@ def run_batched(args, pool):
         name = ("finest-level FP64 refinement launch over the batch (u += e, residual of "
                 "(2.5)-(2.7), FP32 right-hand side and base state, norm partials)")
     else:
+        # every refinement of an instance runs `inner` FP32 cycles; the first
+        # pre launch of each starts from a zero correction and reads no u
         active_cells = sum(sizes[i] * refine[m][i] for m in range(args.steps)
                            for i in range(len(insts)))
-        bytes_launch = launch_bytes_per_cell(2, cls, mixed=True) * active_cells / max(1, tim[cls][1])
+        per_ref = inner * launch_bytes_per_cell(2, cls, mixed=True)
+        if cls == "pre0":
+            per_ref -= 12.0
+        bytes_launch = per_ref * active_cells / max(1, tim[cls][1])
         name = (f"finest-level FP32 {'pre' if cls == 'pre0' else 'post'}-smoothing launch "
                 f"over the batch (correction form)")
     level_kernels = [list(k) for k in sv.level_kernels()]
@@ -455,7 +470,7 @@ def run_batched(args, pool):
                    "grids": [128, 256, 512, 1024], "cells": cells, "eps": "U[0.01,0.05]",
                    "gamma": "U[0.5,5]", "s": "{1e-4,5e-4}", "tol": 1e-10, "cycle": "V(2,2)",
                    "precision": "fp32 inner + fp64 refinement",
-                   "inner_cycles": max(1, sweeps[5] if sweeps is not None else args.inner_cycles),
+                   "inner_cycles": inner,
                    "reductions": "mass, E_h, F_h, dissipation every step"},
         "instance_steps_per_s": inst_steps / elapsed,
         "refinement_steps_per_instance_step": total_refine / inst_steps,
@@ -546,6 +561,13 @@ def run_single(args, name, cpu_baseline=True, parity=True, breakdown=True, copy_
     tm = torch.zeros_like(tp)
     tpp = torch.zeros_like(tp)
 
+    sweeps = None
+    if args.tune_sweeps:
+        # the cycle by time to tolerance on the first step's system, before the
+        # warm-up steps, which then run the kept cycle
+        sweeps = sv.tune_sweeps(tp, tc, tm, tpp)
+        log(f"tuned {SWEEP_KEYS} = {sweeps}")
+    sv.timing(reset=True)
     for k in range(args.warmup):
         _, lg = sv.step_log(tp, tc, tm, tpp, 1)
         log(f"warmup step {k + 1}/{args.warmup}: {lg[0][0]['vcycles']} V-cycles, "
@@ -562,9 +584,6 @@ def run_single(args, name, cpu_baseline=True, parity=True, breakdown=True, copy_
     start_state = [t.cpu().numpy() for t in (tp, tc, tm, tpp)]
     tim_w = sv.timing(reset=True)
     cls = dominant_class(tim_w, cand)
-    sweeps = sv.tune_sweeps(tp, tc, tm, tpp) if args.tune_sweeps else None
-    if sweeps is not None:
-        log(f"tuned {SWEEP_KEYS} = {sweeps}")
     sv.set_timing(chhs.timing_mask(cls))
 
     torch.cuda.synchronize()
@@ -696,12 +715,29 @@ def run_single(args, name, cpu_baseline=True, parity=True, breakdown=True, copy_
 # named; a class's record is taken over its launches that cover every instance
 # (the first refinement step of each time step: no instance has converged yet),
 # whose counters are the largest of the class.
-TRAFFIC_CLASSES = {
-    "refine": ("k_mixed_residual_rows", 100.0),
-}
-TRAFFIC_SOURCES = {
-    "refine": ["paper_1611_02967_amd/csrc/chhs_refine2d.hip", "paper_1611_02967_amd/csrc/chhs_cell.hpp"],
-}
+_CSRC = "paper_1611_02967_amd/csrc/"
+# Kernels a counter record covers: (class, dispatch-name pattern, algorithmic
+# bytes per cell of one full launch, sources).  Of the dispatches matching a
+# pattern, those within 2% of the largest FETCH_SIZE are the finest level's
+# launches over the whole batch.  FP32 tiles: the zero-start pre launch (last
+# template argument true) reads no u, 12 B less than the others.
+TRAFFIC_KERNELS = [
+    ("refine", r"k_mixed_residual_rows", 100.0, ["chhs_refine2d.hip", "chhs_cell.hpp"]),
+    ("pre0", r"k_tile2d<float, \w+, 2, 1, false, true, \d+, false, \d+, true>", 46.0,
+     ["chhs_tile2d.hip", "chhs_cell.hpp", "chhs_internal.hpp"]),
+    ("pre0", r"k_tile2d<float, \w+, 2, 1, false, true, \d+, false, \d+, false>", 58.0,
+     ["chhs_tile2d.hip", "chhs_cell.hpp", "chhs_internal.hpp"]),
+    ("post0", r"k_tile2d<float, \w+, 2, 0, true, true, \d+, false, \d+, false>", 54.0,
+     ["chhs_tile2d.hip", "chhs_cell.hpp", "chhs_internal.hpp"]),
+    ("pre0", r"k_stream2d<double, true, 2, 1,", 90.0,
+     ["chhs_stream2d.hip", "chhs_cell.hpp", "chhs_internal.hpp"]),
+    ("post0", r"k_stream2d<double, true, 2, 2,", 84.0,
+     ["chhs_stream2d.hip", "chhs_cell.hpp", "chhs_internal.hpp"]),
+    ("pre0", r"k_step3d<double", 88.0, ["chhs_step3d.hip", "chhs_cell.hpp", "chhs_internal.hpp"]),
+    ("post0", r"k_step3d<double", 88.0, ["chhs_step3d.hip", "chhs_cell.hpp", "chhs_internal.hpp"]),
+    ("pre0", r"k_step3d<float", 48.0, ["chhs_step3d.hip", "chhs_cell.hpp", "chhs_internal.hpp"]),
+    ("post0", r"k_step3d<float", 48.0, ["chhs_step3d.hip", "chhs_cell.hpp", "chhs_internal.hpp"]),
+]
 
 
 def _counter_rows(path):
@@ -742,21 +778,33 @@ def write_traffic_record(fetch_path, write_path, bench_json):
                            "write_kib": round(wk, 2), "read_scale": read_scale,
                            "write_scale": write_scale},
            "launches": {}}
-    for cls, (pattern, per_cell) in TRAFFIC_CLASSES.items():
-        ds = sorted(d for d, (k, v) in fetch.items() if pattern in k)
+    import re
+    for cls, pattern, per_cell, srcs in TRAFFIC_KERNELS:
+        ds = sorted(d for d, (k, v) in fetch.items() if re.search(pattern, k))
         if not ds:
             continue
         top = max(fetch[d][1] for d in ds)
         full = [d for d in ds if fetch[d][1] >= 0.98 * top and d in write]
-        f_mean = sum(fetch[d][1] for d in full) / len(full)
-        w_mean = sum(write[d][1] for d in full) / len(full)
-        rec["launches"][cls] = {
-            "kernel": pattern, "dispatches": len(full), "of_dispatches": len(ds),
-            "fetch_kib": round(f_mean, 2), "write_kib": round(w_mean, 2),
-            "bytes_per_launch": round(f_mean * 1024 * read_scale + w_mean * 1024 * write_scale),
-            "algorithmic_bytes_per_launch": per_cell * cells,
-            "launches_covered": "every instance active (the largest counters of the class)"}
-        rec["sources"] = sorted(set(rec["sources"]) | set(TRAFFIC_SOURCES[cls]))
+        f_sum = sum(fetch[d][1] for d in full)
+        w_sum = sum(write[d][1] for d in full)
+        counted = f_sum * 1024 * read_scale + w_sum * 1024 * write_scale
+        algo = per_cell * cells * len(full)
+        ent = rec["launches"].setdefault(cls, {"kernels": [], "dispatches": 0,
+                                               "counted_bytes": 0.0, "algorithmic_bytes": 0.0})
+        ent["kernels"].append({"pattern": pattern, "dispatches": len(full), "of_dispatches": len(ds),
+                               "fetch_kib": round(f_sum / len(full), 2),
+                               "write_kib": round(w_sum / len(full), 2),
+                               "algorithmic_bytes_per_cell": per_cell})
+        ent["dispatches"] += len(full)
+        ent["counted_bytes"] += counted
+        ent["algorithmic_bytes"] += algo
+        rec["sources"] = sorted(set(rec["sources"]) | {_CSRC + f for f in srcs})
+    for ent in rec["launches"].values():
+        # per launch of the covered mix (the ratio is what the bench applies)
+        ent["bytes_per_launch"] = round(ent["counted_bytes"] / ent["dispatches"])
+        ent["algorithmic_bytes_per_launch"] = round(ent["algorithmic_bytes"] / ent["dispatches"])
+        ent["launches_covered"] = "every instance active (within 2% of the largest counters)"
+        del ent["counted_bytes"], ent["algorithmic_bytes"]
     rec["source_sha256"] = kernel_source_hash(rec["sources"])
     try:
         with open(TRAFFIC_FILE) as fh:
@@ -797,9 +845,9 @@ def main():
                     help="use the default smoothing kernels instead of letting chhs_init time "
                          "the candidates per level and keep the fastest")
     ap.add_argument("--no-tune-sweeps", dest="tune_sweeps", action="store_false",
-                    help="keep V(2,2) with piecewise-constant prolongation instead of choosing the "
-                         "sweeps per level and the prolongation by time to tolerance after the "
-                         "warm-up steps")
+                    help="keep V(2,2) with piecewise-constant prolongation (and --inner-cycles) "
+                         "instead of choosing the sweeps per level, the prolongation and the FP32 "
+                         "cycles per refinement by time to tolerance before the warm-up steps")
     ap.add_argument("--inner-cycles", type=int, default=1,
                     help="FP32 correction V-cycles per FP64 refinement (mixed precision)")
     ap.add_argument("--smoother", type=int, default=0,

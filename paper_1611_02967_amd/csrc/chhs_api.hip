@@ -1634,11 +1634,15 @@ const double* hres_of(chhs_ctx* c, int i) { return c->hres + size_t(i) * chhs::k
 // Enqueues the energies (per instance, kResStride doubles each) and their
 // copy into pinned host memory `dst`: workspace mode (ws != 0: the finest
 // level's iterate, phi^m and the flow terms) or caller arrays.
-int enqueue_energies(chhs_ctx* c, int ws, const double* phi, const double* q, double* dst) {
+// copy (ws only): the step's copy into the caller's arrays in the same pass.
+int enqueue_energies(chhs_ctx* c, int ws, const double* phi, const double* q, double* dst,
+                     const chhs::CopyOut* copy = nullptr) {
     {
         TimedScope t(c, CHHS_K_SETUP);
-        chhs::launch_energy_partials(c->dim, batch(c, 0, nullptr), c->A[0].dev, c->A[0].n,
-                                     c->dinfo, ws, phi, q, c->partial, c->stream);
+        Batch<double> b = batch(c, 0, nullptr);
+        b.pshift = c->defer_shift ? c->res : nullptr;
+        chhs::launch_energy_partials(c->dim, b, c->A[0].dev, c->A[0].n, c->dinfo, ws, phi, q,
+                                     c->partial, c->stream, copy);
         chhs::launch_energy_reduce(c->partial, c->rngA0, c->dinfo, c->eres, c->n_inst, c->stream);
     }
     int rc = check_launch();
@@ -1728,20 +1732,24 @@ int step_loop(chhs_ctx* c, double* phi_prev, double* phi_cur, double* mu, double
                 for (int i = 0; i < n; ++i) log[size_t(m) * n + i] = st[i];
             break;
         }
+        // rotate: (phi^{m-1}, phi^m) <- (phi^m, phi^{m+1}); mu, p <- this step's
+        // (in the energy pass when the step's energies are wanted)
+        const chhs::CopyOut co{phi_prev, phi_cur, mu, p};
         if (log != nullptr) {
             rc = enqueue_energies(c, 1, nullptr, nullptr,
-                                  c->hlog + size_t(m) * n * chhs::kResStride);
+                                  c->hlog + size_t(m) * n * chhs::kResStride, &co);
             if (rc) break;
         } else if (m == nsteps - 1 && last != nullptr) {
-            rc = energies(c, 1, nullptr, nullptr);
+            rc = enqueue_energies(c, 1, nullptr, nullptr, c->heres, &co);
+            if (rc == CHHS_OK) rc = sync_results(c);
             if (rc) break;
             for (int i = 0; i < n; ++i) fill_energies(st[i], c->heres + size_t(i) * chhs::kResStride);
+        } else {
+            Batch<double> bo = batch(c, 0, nullptr);
+            bo.pshift = c->defer_shift ? c->res : nullptr;
+            chhs::launch_copy_out(bo, c->A[0].dev, c->A[0].n, c->dinfo, phi_prev, phi_cur, mu, p,
+                                  c->stream);
         }
-        // rotate: (phi^{m-1}, phi^m) <- (phi^m, phi^{m+1}); mu, p <- this step's
-        Batch<double> bo = batch(c, 0, nullptr);
-        bo.pshift = c->defer_shift ? c->res : nullptr;
-        chhs::launch_copy_out(bo, c->A[0].dev, c->A[0].n, c->dinfo, phi_prev, phi_cur, mu, p,
-                              c->stream);
         rc = check_launch();
         if (rc) break;
         for (int i = 0; i < n; ++i) {

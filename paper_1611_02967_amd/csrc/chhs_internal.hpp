@@ -233,9 +233,15 @@ void launch_shift_p(const Batch<double>& b, const CellTask* t, int nt, const dou
 // arrays phi and q and no flow terms.  partial[block][0..8]: sum phi, phi^2,
 // phi^4, |D phi|^2 h^2, (phi-q)^2, |D(phi-q)|^2 h^2, |D mu|^2 h^2, |u|^2 h^2,
 // max |phi| (interior faces only).
+// The step's copy into the caller's packed arrays, fused into the energy pass
+// over the workspace: phi_prev <- phi^m, phi_cur <- phi, mu <- mu, p <- p minus
+// the pending shift (b.pshift), as launch_copy_out.
+struct CopyOut {
+    double *phi_prev, *phi_cur, *mu, *p;
+};
 void launch_energy_partials(int dim, const Batch<double>& b, const CellTask* t, int nt,
                             const InstInfo* info, int ws, const double* phi, const double* q,
-                            double* partial, hipStream_t st);
+                            double* partial, hipStream_t st, const CopyOut* copy = nullptr);
 // Per instance: out[i*kResStride + 0..5] = mass, E_h, F_h, s||grad mu||^2,
 // (s/gamma)||u||^2, max |phi|.
 void launch_energy_reduce(const double* partial, const Range* ranges, const InstInfo* info,

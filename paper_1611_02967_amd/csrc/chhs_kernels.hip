@@ -685,7 +685,7 @@ __global__ __launch_bounds__(kBlock) void k_energy_partials(Batch<double> b,
                                                             const InstInfo* __restrict__ info,
                                                             int ws, const double* __restrict__ phi_c,
                                                             const double* __restrict__ q_c,
-                                                            double* partial) {
+                                                            double* partial, CopyOut co) {
     const int task = xcd_task();
     const CellTask tk = t[task];
     const Level<double> L = view_at(b, tk.inst, 0, b.cur);
@@ -723,6 +723,15 @@ __global__ __launch_bounds__(kBlock) void k_energy_partials(Batch<double> b,
         if (i < L.nx - 1) face(idx + 1);
         if (j < L.ny - 1) face(idx + L.nx);
         if (DIM == 3 && k < L.nz - 1) face(idx + L.nx * L.ny);
+        if (ws && co.phi_cur != nullptr) {
+            // the copy-out of the step (phi^m is the workspace's psi)
+            const int g = off + idx;
+            const double psh = b.pshift != nullptr ? b.pshift[tk.inst * kResStride + 4] : 0.0;
+            co.phi_prev[g] = q[idx];
+            co.phi_cur[g] = f;
+            co.mu[g] = L.mu[idx];
+            co.p[g] = L.p[idx] - psh;
+        }
     }
     double out[8];
     block_sum<8>(v, out);
@@ -1002,8 +1011,9 @@ void launch_shift_p(const Batch<double>& b, const CellTask* t, int nt, const dou
 
 void launch_energy_partials(int dim, const Batch<double>& b, const CellTask* t, int nt,
                             const InstInfo* info, int ws, const double* phi, const double* q,
-                            double* partial, hipStream_t st) {
-    CHHS_DISPATCH(dim, k_energy_partials, nt, b, t, info, ws, phi, q, partial);
+                            double* partial, hipStream_t st, const CopyOut* copy) {
+    const CopyOut co = copy != nullptr ? *copy : CopyOut{nullptr, nullptr, nullptr, nullptr};
+    CHHS_DISPATCH(dim, k_energy_partials, nt, b, t, info, ws, phi, q, partial, co);
 }
 
 void launch_energy_reduce(const double* partial, const Range* ranges, const InstInfo* info,

@@ -27,7 +27,7 @@ def test_traffic_records_have_what_the_bench_compares():
         assert rec["sources"] and all(os.path.exists(os.path.join(bench.ROOT, f))
                                       for f in rec["sources"])
         kind, param, blocks = rec["level0_kernel"]
-        assert kind in ("strips", "tiles") and param > 0 and blocks > 0
+        assert kind in ("strips", "tiles", "zmarch") and param > 0 and blocks > 0
         assert rec["launches"]
         for cls, e in rec["launches"].items():
             assert cls in ("pre0", "post0", "refine")
@@ -43,7 +43,10 @@ def test_measured_traffic_is_reported_only_for_the_measured_configuration(monkey
     got = bench.measured_traffic(workload, cls, tuple(lk))
     assert got["bytes_per_launch"] == rec["launches"][cls]["bytes_per_launch"]
     assert bench.measured_traffic("no-such-workload", cls, tuple(lk)) is None
-    assert bench.measured_traffic(workload, cls, ("tiles", 7, 4096)) is None
+    other = "tiles" if lk[0] != "tiles" else "strips"
+    assert bench.measured_traffic(workload, cls, (other, 7, 4096)) is None
+    # the same kind of finest-level kernel with another autotuned block size
+    assert bench.measured_traffic(workload, cls, (lk[0], lk[1] * 2, lk[2])) is not None
     monkeypatch.setattr(bench, "kernel_source_hash", lambda sources: "0" * 64)
     assert bench.measured_traffic(workload, cls, tuple(lk)) is None
 
@@ -86,3 +89,43 @@ def test_vcycle_bytes_follow_the_tuned_sweeps():
     want += 8 * (9 * n[6] + 2 * sum(n[6:]))
     got = bench.vcycle_bytes(2, (2048, 2048), lk, (1, 2, 3, 3, 1))
     assert abs(got - want) < 1e-6 * want
+
+
+def test_traffic_record_from_counter_files(tmp_path, monkeypatch):
+    """write_traffic_record: calibration by the 256 MiB copy, the finest-level
+    full launches of each pattern (within 2% of the largest counters), the
+    counted/algorithmic ratio that the bench applies to its own launches."""
+    cells = 1000
+    kib = 1024.0
+    rows = {"FETCH_SIZE": [], "WRITE_SIZE": []}
+
+    def dispatch(d, name, fetch_bytes, write_bytes):
+        # the calibration below reads FETCH_SIZE as half the bytes read
+        rows["FETCH_SIZE"].append((d, name, fetch_bytes / 2 / kib))
+        rows["WRITE_SIZE"].append((d, name, write_bytes / kib))
+
+    dispatch(1, "__amd_rocclr_copyBuffer", bench.COPY_BYTES, bench.COPY_BYTES)
+    zero = "void chhs::k_tile2d<float, false, 2, 1, false, true, 512, false, 16, true>(...)"
+    full = "void chhs::k_tile2d<float, false, 2, 1, false, true, 512, false, 16, false>(...)"
+    dispatch(2, zero, 40 * cells, 12 * cells)           # 52 B counted, 46 algorithmic
+    dispatch(3, full, 50 * cells, 12 * cells)           # 62 B counted, 58 algorithmic
+    dispatch(4, full, 10 * cells, 3 * cells)            # a coarser level: not covered
+    paths = {}
+    for name, rs in rows.items():
+        f = tmp_path / f"{name}_counter_collection.csv"
+        with open(f, "w") as fh:
+            fh.write("Dispatch_Id,Kernel_Name,Counter_Name,Counter_Value\n")
+            for d, k, v in rs:
+                fh.write(f'{d},"{k}",{name},{v}\n')
+        paths[name] = str(f)
+    run = {"config": {"workload": "w", "cells": cells}, "level_kernels": [["tiles", 512, 21]]}
+    bj = tmp_path / "bench.json"
+    bj.write_text(json.dumps(run) + "\n")
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "traffic.json"))
+    bench.write_traffic_record(paths["FETCH_SIZE"], paths["WRITE_SIZE"], str(bj))
+    rec = json.loads((tmp_path / "traffic.json").read_text())["w"]
+    pre = rec["launches"]["pre0"]
+    assert pre["dispatches"] == 2
+    assert abs(pre["bytes_per_launch"] - (52 + 62) / 2 * cells) < 1
+    assert pre["algorithmic_bytes_per_launch"] == (46 + 58) / 2 * cells
+    assert "post0" not in rec["launches"] and "refine" not in rec["launches"]
