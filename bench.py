@@ -21,6 +21,7 @@ import argparse
 import contextlib
 import gc
 import json
+import math
 import os
 import platform
 import sys
@@ -718,9 +719,13 @@ def run_single(args, name, cpu_baseline=True, parity=True, breakdown=True, copy_
 _CSRC = "paper_1611_02967_amd/csrc/"
 # Kernels a counter record covers: (class, dispatch-name pattern, algorithmic
 # bytes per cell of one full launch, sources).  Of the dispatches matching a
-# pattern, those within 2% of the largest FETCH_SIZE are the finest level's
-# launches over the whole batch.  FP32 tiles: the zero-start pre launch (last
-# template argument true) reads no u, 12 B less than the others.
+# smoothing pattern, those with the finest level's workgroup count in the timed
+# configuration (the autotuner's other candidates and the coarse levels launch
+# other counts), and of those the ones within 2% of the largest FETCH_SIZE and
+# WRITE_SIZE (every instance active), are covered; the refinement launch has its
+# own task count.
+# FP32 tiles: the zero-start pre launch (last template argument true) reads no
+# u, 12 B less than the others.
 TRAFFIC_KERNELS = [
     ("refine", r"k_mixed_residual_rows", 100.0, ["chhs_refine2d.hip", "chhs_cell.hpp"]),
     ("pre0", r"k_tile2d<float, \w+, 2, 1, false, true, \d+, false, \d+, true>", 46.0,
@@ -741,8 +746,8 @@ TRAFFIC_KERNELS = [
 
 
 def _counter_rows(path):
-    """(dispatch id, kernel name, value) of every row of a rocprofv3 counter
-    collection csv (a file, or the directory rocprofv3 wrote it under)."""
+    """(dispatch id, kernel name, value, workgroups) of every row of a rocprofv3
+    counter collection csv (a file, or the directory rocprofv3 wrote it under)."""
     import csv
     import glob
     files = [path] if os.path.isfile(path) else sorted(
@@ -751,7 +756,9 @@ def _counter_rows(path):
     for f in files:
         with open(f) as fh:
             for r in csv.DictReader(fh):
-                rows.append((int(r["Dispatch_Id"]), r["Kernel_Name"], float(r["Counter_Value"])))
+                wg = int(r.get("Workgroup_Size") or 1)
+                rows.append((int(r["Dispatch_Id"]), r["Kernel_Name"], float(r["Counter_Value"]),
+                             int(r.get("Grid_Size") or 0) // max(1, wg)))
     return rows
 
 
@@ -763,14 +770,27 @@ def write_traffic_record(fetch_path, write_path, bench_json):
         line = [l for l in fh.read().splitlines() if l.startswith("{")][-1]
     run = json.loads(line)
     workload = run["config"]["workload"]
-    cells = run["config"]["cells"]
-    fetch = {d: (k, v) for d, k, v in _counter_rows(fetch_path)}
-    write = {d: (k, v) for d, k, v in _counter_rows(write_path)}
-    copies = [d for d, (k, v) in fetch.items() if "copyBuffer" in k and v * 1024 > 0.4 * COPY_BYTES]
+    cfg = run["config"]
+    cells = cfg["cells"] if "cells" in cfg else int(math.prod(cfg["grid"]))
+    fetch = {d: (k, v) for d, k, v, _ in _counter_rows(fetch_path)}
+    write = {d: (k, v) for d, k, v, _ in _counter_rows(write_path)}
+    blocks = {d: b for d, _, _, b in _counter_rows(fetch_path)}
+    # the smoothing launches of the timed configuration: the finest level's
+    # workgroup count (the autotuner's other candidates and the coarse levels
+    # launch other counts)
+    blocks0 = int(run["level_kernels"][0][2])
+    # the calibration copies: device copies whose WRITE_SIZE is the 256 MiB
+    # they write (a streaming copy writes every line once; the run's other
+    # copies, of the state arrays, have other sizes)
+    copies = [d for d, (k, v) in fetch.items() if "copyBuffer" in k and d in write
+              and abs(write[d][1] * 1024 - COPY_BYTES) <= 0.05 * COPY_BYTES]
     if not copies:
         raise SystemExit("no 256 MiB copy in the counter runs (run the bench with --copy-calibration)")
-    fk = sum(fetch[d][1] for d in copies) / len(copies)
-    wk = sum(write[d][1] for d in copies if d in write) / len(copies)
+    # the largest of the copies' read counts: a repeated copy of the same
+    # source can find it in the 256 MB memory-side cache and read almost
+    # nothing from HBM
+    fk = max(fetch[d][1] for d in copies)
+    wk = max(write[d][1] for d in copies)
     read_scale, write_scale = COPY_BYTES / (fk * 1024), COPY_BYTES / (wk * 1024)
     rec = {"workload": workload, "sources": [], "level0_kernel": run["level_kernels"][0],
            "calibration": {"kernel": "device copy of 256 MiB (torch copy_)",
@@ -780,11 +800,17 @@ def write_traffic_record(fetch_path, write_path, bench_json):
            "launches": {}}
     import re
     for cls, pattern, per_cell, srcs in TRAFFIC_KERNELS:
-        ds = sorted(d for d, (k, v) in fetch.items() if re.search(pattern, k))
+        ds = sorted(d for d, (k, v) in fetch.items() if re.search(pattern, k)
+                    and (cls == "refine" or blocks.get(d) in (blocks0, None, 0)))
         if not ds:
             continue
+        # L2 writes back lazily: a dispatch's WRITE_SIZE can miss lines that a
+        # later one writes back, so both counters must be within 2% of their
+        # largest values
         top = max(fetch[d][1] for d in ds)
-        full = [d for d in ds if fetch[d][1] >= 0.98 * top and d in write]
+        wtop = max(write[d][1] for d in ds if d in write)
+        full = [d for d in ds if fetch[d][1] >= 0.98 * top and d in write
+                and write[d][1] >= 0.98 * wtop]
         f_sum = sum(fetch[d][1] for d in full)
         w_sum = sum(write[d][1] for d in full)
         counted = f_sum * 1024 * read_scale + w_sum * 1024 * write_scale

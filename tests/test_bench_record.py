@@ -99,24 +99,25 @@ def test_traffic_record_from_counter_files(tmp_path, monkeypatch):
     kib = 1024.0
     rows = {"FETCH_SIZE": [], "WRITE_SIZE": []}
 
-    def dispatch(d, name, fetch_bytes, write_bytes):
+    def dispatch(d, name, fetch_bytes, write_bytes, blocks=21):
         # the calibration below reads FETCH_SIZE as half the bytes read
-        rows["FETCH_SIZE"].append((d, name, fetch_bytes / 2 / kib))
-        rows["WRITE_SIZE"].append((d, name, write_bytes / kib))
+        rows["FETCH_SIZE"].append((d, name, fetch_bytes / 2 / kib, blocks))
+        rows["WRITE_SIZE"].append((d, name, write_bytes / kib, blocks))
 
-    dispatch(1, "__amd_rocclr_copyBuffer", bench.COPY_BYTES, bench.COPY_BYTES)
+    dispatch(1, "__amd_rocclr_copyBuffer", bench.COPY_BYTES, bench.COPY_BYTES, 256)
     zero = "void chhs::k_tile2d<float, false, 2, 1, false, true, 512, false, 16, true>(...)"
     full = "void chhs::k_tile2d<float, false, 2, 1, false, true, 512, false, 16, false>(...)"
     dispatch(2, zero, 40 * cells, 12 * cells)           # 52 B counted, 46 algorithmic
     dispatch(3, full, 50 * cells, 12 * cells)           # 62 B counted, 58 algorithmic
-    dispatch(4, full, 10 * cells, 3 * cells)            # a coarser level: not covered
+    dispatch(4, full, 10 * cells, 3 * cells)            # fewer instances active: not covered
+    dispatch(5, full, 90 * cells, 12 * cells, 84)       # another tile height: not covered
     paths = {}
     for name, rs in rows.items():
         f = tmp_path / f"{name}_counter_collection.csv"
         with open(f, "w") as fh:
-            fh.write("Dispatch_Id,Kernel_Name,Counter_Name,Counter_Value\n")
-            for d, k, v in rs:
-                fh.write(f'{d},"{k}",{name},{v}\n')
+            fh.write("Dispatch_Id,Kernel_Name,Grid_Size,Workgroup_Size,Counter_Name,Counter_Value\n")
+            for d, k, v, b in rs:
+                fh.write(f'{d},"{k}",{b * 512},512,{name},{v}\n')
         paths[name] = str(f)
     run = {"config": {"workload": "w", "cells": cells}, "level_kernels": [["tiles", 512, 21]]}
     bj = tmp_path / "bench.json"
