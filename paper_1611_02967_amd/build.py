@@ -24,7 +24,7 @@ ARCH = "gfx950"
 
 SOURCES = ["chhs_api.hip", "chhs_kernels.hip", "chhs_tile2d.hip", "chhs_stream2d.hip",
            "chhs_tail.hip", "chhs_noalloc.hip", "chhs_refine2d.hip",
-           "chhs_step3d.hip"]
+           "chhs_step3d.hip", "chhs_resid3d.hip"]
 
 # -packed-fp32-ops: keep the compiler from forming packed FP32 instructions
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -66,6 +66,10 @@ struct Layout {
     // 3D: fused-step tiles per level (instances above their tail; FP64 and FP32
     // tile sizes) and z-segment height per level
     std::vector<std::vector<Step3Task>> Z64, Z32;
+    // 3D restriction: z-marching tasks of the instances whose level is large
+    // enough, per-cell coarse tasks of the others
+    std::vector<std::vector<Step3Task>> ZR64, ZR32;
+    std::vector<std::vector<CellTask>> BcS;
     int zseg64[kMaxLevels] = {}, zseg32[kMaxLevels] = {};
     // 3D level smoothed by the fused step (else by one launch per color)
     bool z3[kMaxLevels] = {};
@@ -106,7 +110,7 @@ struct Layout {
     size_t off_partial = 0, off_res = 0, off_eres = 0, off_act_cycle = 0, off_act_next = 0,
            off_cycles = 0, off_act_last = 0;
     std::vector<size_t> off_A, off_B, off_Bc, off_Bh, off_Bcs, off_T, off_Tall, off_S, off_Sall,
-        off_Z64, off_Z32;
+        off_Z64, off_Z32, off_ZR64, off_ZR32, off_BcS;
     int partial_cap = 0, partial_t_cap = 0;
 };
 
@@ -130,7 +134,8 @@ struct chhs_ctx {
         Bcs[kMaxLevels];
     Table<TileTask> T[kMaxLevels], Tall[kMaxLevels];
     Table<StripTask> S[kMaxLevels], Sall[kMaxLevels];
-    Table<Step3Task> Z64[kMaxLevels], Z32[kMaxLevels];
+    Table<Step3Task> Z64[kMaxLevels], Z32[kMaxLevels], ZR64[kMaxLevels], ZR32[kMaxLevels];
+    Table<CellTask> BcS[kMaxLevels];
     Table<CellTask> A0n, A0t;
     Table<StripTask> M0;
     Table<FoldTask> FM0;
@@ -384,14 +389,19 @@ void task_ranges(std::vector<Range>& r, int n_inst, const std::vector<Task>& tas
 void fused_ranges(Layout& L, int n_inst) {
     if (L.strip[0])
         task_ranges(L.rngT0, n_inst, L.S[0]);
-    else
+    else if (!L.T[0].empty())
         task_ranges(L.rngT0, n_inst, L.T[0]);
+    else
+        task_ranges(L.rngT0, n_inst, L.Z64[0]);     // 3D
 }
 
 // 3D levels above the tail may be smoothed by the fused z-marching step kernel
 // (the second-order scheme, unless opts.smoother = 3 asks for the per-cell
 // red-black kernels everywhere); which levels do is Layout::z3.
 bool step3d_opts(int dim, const chhs_opts* o) { return dim == 3 && o->order != 1 && o->smoother != 3; }
+
+// Cells of an instance's 3D level from which it restricts by z marching.
+constexpr long kRes3MinCells = 1L << 20;
 
 // Planes per segment below which a level is left to the per-color kernels by
 // default: the segments of such levels are short (few planes per workgroup to
@@ -470,6 +480,9 @@ bool plan(const chhs_problem* p, int n_inst, const chhs_opts* o, char* base, Lay
     L.Sall.resize(kMaxLevels);
     L.Z64.resize(kMaxLevels);
     L.Z32.resize(kMaxLevels);
+    L.ZR64.resize(kMaxLevels);
+    L.ZR32.resize(kMaxLevels);
+    L.BcS.resize(kMaxLevels);
     // level extents per instance (-1: no such level) for the strip planner
     std::vector<std::vector<int>> lnx(kMaxLevels, std::vector<int>(n_inst, -1));
     std::vector<std::vector<int>> lny(kMaxLevels, std::vector<int>(n_inst, -1));
@@ -527,7 +540,10 @@ bool plan(const chhs_problem* p, int n_inst, const chhs_opts* o, char* base, Lay
         in.n0 = cells[0];
         const bool first = o->order == 1;
         in.order = first ? 1 : 2;
-        in.fused = (!mixed && !first && dim == 2 && o->nu2 > 0 && tail > 0) ? 1 : 0;
+        // the finest level's norm partials: from the fused 2D post launch, or
+        // (3D) from the z-marching residual kernel over the fused-step tasks
+        in.fused = (!mixed && !first && tail > 0 &&
+                    ((dim == 2 && o->nu2 > 0) || (dim == 3 && step3d_opts(dim, o)))) ? 1 : 0;
         in.h = p[i].h;
         in.eps = p[i].eps;
         in.gamma = p[i].gamma;
@@ -654,6 +670,21 @@ bool plan(const chhs_problem* p, int n_inst, const chhs_opts* o, char* base, Lay
             const int zs = mixed ? L.zseg32[l] : L.zseg64[l];
             L.z3[l] = o->smoother == 4 || zs >= kStep3MinSeg;
         }
+    // 3D restriction per instance (never by what else the batch holds): the
+    // z-marching residual kernel on levels of at least kRes3MinCells cells, the
+    // per-cell kernel on smaller ones (where its short launches win)
+    for (int l = 0; l < kMaxLevels; ++l) {
+        auto big = [&](int i) {
+            return step3d_opts(dim, o) && lnx_t[l][i] >= 0 &&
+                   long(lnx[l][i]) * lny[l][i] * lnz[l][i] >= kRes3MinCells;
+        };
+        for (const Step3Task& t : L.Z64[l])
+            if (big(t.inst)) L.ZR64[l].push_back(t);
+        for (const Step3Task& t : L.Z32[l])
+            if (big(t.inst)) L.ZR32[l].push_back(t);
+        for (const CellTask& t : L.Bc[l])
+            if (!big(t.inst)) L.BcS[l].push_back(t);
+    }
     // 2D mixed precision: tasks of the row-marching refinement step over every
     // instance's finest level (instance, then row segment, then column window)
     if (dim == 2 && mixed) {
@@ -682,7 +713,8 @@ bool plan(const chhs_problem* p, int n_inst, const chhs_opts* o, char* base, Lay
     fold_of(L.rngA0n, L.FA0n, L.rngA0nf);
     fused_ranges(L, n_inst);
     L.partial_cap = int(std::max(L.A[0].size(), L.M0.size()));
-    L.partial_t_cap = int(std::max<size_t>(1, std::max(L.T[0].size(), L.S[0].size())));
+    L.partial_t_cap =
+        int(std::max<size_t>(1, std::max({L.T[0].size(), L.S[0].size(), L.Z64[0].size()})));
     L.off_desc = take(L.desc.size() * sizeof(LevelDesc<double>));
     L.off_desc32 = take(std::max<size_t>(1, L.desc32.size()) * sizeof(LevelDesc<float>));
     L.off_info = take(L.info.size() * sizeof(InstInfo));
@@ -713,6 +745,9 @@ bool plan(const chhs_problem* p, int n_inst, const chhs_opts* o, char* base, Lay
         L.off_Sall.push_back(take(L.Sall[l].size() * sizeof(StripTask)));
         L.off_Z64.push_back(take(L.Z64[l].size() * sizeof(Step3Task)));
         L.off_Z32.push_back(take(L.Z32[l].size() * sizeof(Step3Task)));
+        L.off_ZR64.push_back(take(L.ZR64[l].size() * sizeof(Step3Task)));
+        L.off_ZR32.push_back(take(L.ZR32[l].size() * sizeof(Step3Task)));
+        L.off_BcS.push_back(take(L.BcS[l].size() * sizeof(CellTask)));
     }
     L.off_partial = take(size_t(L.partial_cap) * chhs::kPartialStride * sizeof(double));
     L.off_partial_t = take(size_t(L.partial_t_cap) * chhs::kPartialStride * sizeof(double));
@@ -981,8 +1016,14 @@ void enqueue_vcycle(chhs_ctx* c, const Hier<T>& H, bool zero_corr = true) {
                                                   c->Bh[d].dev, c->Bh[d].n, color, c->stream);
                     }
             TimedScope t(c, xfer_cls);
-            chhs::launch_restrict_residual(dim, make_batch(H.dev, H.cur, d, act), c->Bc[d].dev,
-                                           c->Bc[d].n, c->stream);
+            // z marching for the instances whose level is large, per cell for
+            // the others (a batched instance restricts as it does alone)
+            const Table<Step3Task>& zt = kPlain ? c->ZR64[d] : c->ZR32[d];
+            if (zt.n > 0)
+                chhs::launch_restrict3d(make_batch(H.dev, H.cur, d, act), zt.dev, zt.n, c->stream);
+            if (c->BcS[d].n > 0)
+                chhs::launch_restrict_residual(dim, make_batch(H.dev, H.cur, d, act), c->BcS[d].dev,
+                                               c->BcS[d].n, c->stream);
         }
         // level d + 1's right-hand side f = fr + N(u), unless its first tiled
         // launch forms it (tail levels: the tail does)
@@ -1289,6 +1330,10 @@ void enqueue_plain_cycle(chhs_ctx* c, bool count) {
     chhs::launch_copy_int(c->act_cycle, c->act_next, c->n_inst, c->stream);
     enqueue_vcycle(c, hier64(c));
     TimedScope t(c, CHHS_K_NORM);
+    // 3D: the z-marching residual over the finest level's fused-step tasks
+    if (c->dim == 3 && c->Z64[0].n > 0)
+        chhs::launch_residual3d_partials(batch(c, 0, act), c->Z64[0].dev, c->Z64[0].n,
+                                         c->partial_t, c->stream);
     // instances without a fused finest-level norm: per-cell residual partials
     chhs::launch_residual_partials(c->dim, batch(c, 0, act), c->A0n.dev, c->A0n.n, c->partial,
                                    c->stream);
@@ -1888,6 +1933,9 @@ int chhs_init(const chhs_problem* p, int32_t n_inst, const chhs_opts* o, void* w
         rc |= upload(c->Sall[l], b, L.off_Sall[l], L.Sall[l], st);
         rc |= upload(c->Z64[l], b, L.off_Z64[l], L.Z64[l], st);
         rc |= upload(c->Z32[l], b, L.off_Z32[l], L.Z32[l], st);
+        rc |= upload(c->ZR64[l], b, L.off_ZR64[l], L.ZR64[l], st);
+        rc |= upload(c->ZR32[l], b, L.off_ZR32[l], L.ZR32[l], st);
+        rc |= upload(c->BcS[l], b, L.off_BcS[l], L.BcS[l], st);
     }
     rc |= upload(c->A0n, b, L.off_A0n, L.A0n, st);
     rc |= upload(c->A0t, b, L.off_A0t, L.A0t, st);

@@ -299,6 +299,14 @@ void launch_stream2d(const Batch<T>& b, const StripTask* t, int nt, bool level0,
 // 16 x 16 in FP64, 32 x 8 in FP32 (correction form).
 constexpr int kStep3TX64 = 16, kStep3TY64 = 16;
 constexpr int kStep3TX32 = 32, kStep3TY32 = 8;
+// Residual of a 3D level by z marching over the level's fused-step tasks:
+// norm partials of the finest FP64 level (one per task, as the per-cell
+// residual partials) or residual + restriction into level b.level + 1 (copy
+// b.cur_c): u_c, ub_c, fr_c (and b_c in the correction form).
+void launch_residual3d_partials(const Batch<double>& b, const Step3Task* t, int nt, double* partial,
+                                hipStream_t st);
+void launch_restrict3d(const Batch<double>& b, const Step3Task* t, int nt, hipStream_t st);
+void launch_restrict3d(const Batch<float>& b, const Step3Task* t, int nt, hipStream_t st);
 // pro: 0 no prolongation, 1 piecewise-constant, 2 trilinear coarse correction
 // added to u (from level + 1, copy cur_c) as the launch loads it
 void launch_step3d(const Batch<double>& b, const Step3Task* t, int nt, int pro, hipStream_t st);

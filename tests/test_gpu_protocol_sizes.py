@@ -230,19 +230,25 @@ def test_batched_draw_with_1024_instances_matches_fp64_and_oracle(chhs):
             assert np.max(np.abs(host(b) - r.phi)) <= 1e-10, i
 
 
-def test_3d_batch_across_the_restriction_kernels_equals_single_runs(chhs):
-    """Three 64^3 instances: the restriction into 32^3 covers 384 coarse tasks
-    over the batch (the one-thread-per-coarse-cell kernel) and 128 for one
-    instance alone (the lane-exchange kernel); results are bitwise equal."""
+@pytest.mark.parametrize("smoother", [3, 0], ids=["per-cell", "default"])
+def test_3d_batch_across_the_restriction_kernels_equals_single_runs(chhs, smoother):
+    """Per-cell kernels, three 64^3 instances: the restriction into 32^3 covers
+    384 coarse tasks over the batch (the one-thread-per-coarse-cell kernel) and
+    128 for one instance alone (the lane-exchange kernel).  Default kernels, a
+    64 x 128 x 128 instance with two 64^3 ones: the large one restricts its
+    finest level by z marching, the small ones per cell, in the batch as
+    alone.  Results are bitwise equal."""
     spec = [((64, 64, 64), 0.02, 2.0, 5e-4, 0.1), ((64, 64, 64), 0.03, 1.0, 1e-3, -0.1),
             ((64, 64, 64), 0.04, 3.0, 5e-4, 0.0)]
+    if smoother == 0:
+        spec[0] = ((64, 128, 128), 0.02, 2.0, 5e-4, 0.1)
     shapes = [s[0] for s in spec]
     phi0s = [uniform_field(sh, 5300 + i, mean=sp[4], amp=0.05) for i, (sh, sp) in
              enumerate(zip(shapes, spec))]
 
     def run(sp_list, arrays):
         probs = [chhs.make_problem(sh, 1.0 / sh[-1], e, g, s) for sh, e, g, s, _ in sp_list]
-        sv = chhs.Solver(probs, chhs.chhs_default_opts())
+        sv = chhs.Solver(probs, chhs.chhs_default_opts(smoother=smoother))
         flat = _pack(arrays)
         tp, tc = dev(flat), dev(flat)
         z = np.zeros(flat.size)
