@@ -85,6 +85,8 @@ struct Layout {
     std::vector<int> tail_insts;
     std::vector<CellTask> A0n;              // finest-level cells of instances without a fused norm
     std::vector<CellTask> A0t;              // finest-level cells of instances held by the tail
+    std::vector<CellTask> A0x;              // 3D mixed: finest cells refined per cell
+    std::vector<Range> rngA0x;
     std::vector<StripTask> M0;              // 2D mixed: row-marching refinement tasks
     std::vector<Range> rngM0, rngM0f;
     std::vector<FoldTask> FM0;
@@ -104,7 +106,7 @@ struct Layout {
     // offsets into the workspace
     size_t off_desc = 0, off_desc32 = 0, off_info = 0, off_tail = 0, off_rngA0 = 0, off_rngT0 = 0,
            off_rngA0n = 0;
-    size_t off_A0n = 0, off_A0t = 0, off_partial_t = 0;
+    size_t off_A0n = 0, off_A0t = 0, off_partial_t = 0, off_A0x = 0, off_rngA0x = 0;
     size_t off_M0 = 0, off_rngM0 = 0, off_rngM0f = 0, off_FM0 = 0;
     size_t off_FA0 = 0, off_FA0n = 0, off_rngA0f = 0, off_rngA0nf = 0, off_partial_f = 0;
     size_t off_partial = 0, off_res = 0, off_eres = 0, off_act_cycle = 0, off_act_next = 0,
@@ -136,7 +138,8 @@ struct chhs_ctx {
     Table<StripTask> S[kMaxLevels], Sall[kMaxLevels];
     Table<Step3Task> Z64[kMaxLevels], Z32[kMaxLevels], ZR64[kMaxLevels], ZR32[kMaxLevels];
     Table<CellTask> BcS[kMaxLevels];
-    Table<CellTask> A0n, A0t;
+    Table<CellTask> A0n, A0t, A0x;
+    Range* rngA0x = nullptr;
     Table<StripTask> M0;
     Table<FoldTask> FM0;
     Range* rngM0 = nullptr;
@@ -542,8 +545,10 @@ bool plan(const chhs_problem* p, int n_inst, const chhs_opts* o, char* base, Lay
         in.order = first ? 1 : 2;
         // the finest level's norm partials: from the fused 2D post launch, or
         // (3D) from the z-marching residual kernel over the fused-step tasks
-        in.fused = (!mixed && !first && tail > 0 &&
-                    ((dim == 2 && o->nu2 > 0) || (dim == 3 && step3d_opts(dim, o)))) ? 1 : 0;
+        // (the mixed 3D path: from the z-marching refinement step)
+        in.fused = (!first && tail > 0 &&
+                    ((dim == 2 && !mixed && o->nu2 > 0) || (dim == 3 && step3d_opts(dim, o))))
+                       ? 1 : 0;
         in.h = p[i].h;
         in.eps = p[i].eps;
         in.gamma = p[i].gamma;
@@ -626,6 +631,7 @@ bool plan(const chhs_problem* p, int n_inst, const chhs_opts* o, char* base, Lay
         // coarse levels above the tail (the tail forms its top level's f itself)
         for (int l = 0; l + 1 < tail; ++l) cell_tasks(L.Bcs[l], i, cells[l + 1]);
         if (!in.fused) cell_tasks(L.A0n, i, cells[0]);
+        if (!in.fused && mixed && dim == 3 && step3d_opts(dim, o)) cell_tasks(L.A0x, i, cells[0]);
         if (tail == 0) cell_tasks(L.A0t, i, cells[0]);
         L.tail_insts.push_back(i);
     }
@@ -709,6 +715,7 @@ bool plan(const chhs_problem* p, int n_inst, const chhs_opts* o, char* base, Lay
     task_ranges(L.rngM0, n_inst, L.M0);
     fold_of(L.rngM0, L.FM0, L.rngM0f);
     ranges_of(L.rngA0n, n_inst, L.A0n);
+    ranges_of(L.rngA0x, n_inst, L.A0x);
     fold_of(L.rngA0, L.FA0, L.rngA0f);
     fold_of(L.rngA0n, L.FA0n, L.rngA0nf);
     fused_ranges(L, n_inst);
@@ -724,6 +731,8 @@ bool plan(const chhs_problem* p, int n_inst, const chhs_opts* o, char* base, Lay
     L.off_rngA0n = take(n_inst * sizeof(Range));
     L.off_A0n = take(L.A0n.size() * sizeof(CellTask));
     L.off_A0t = take(L.A0t.size() * sizeof(CellTask));
+    L.off_A0x = take(L.A0x.size() * sizeof(CellTask));
+    L.off_rngA0x = take(n_inst * sizeof(Range));
     L.off_M0 = take(L.M0.size() * sizeof(StripTask));
     L.off_rngM0 = take(n_inst * sizeof(Range));
     L.off_rngM0f = take(n_inst * sizeof(Range));
@@ -1379,28 +1388,45 @@ void enqueue_refinement(chhs_ctx* c, bool count, bool add) {
         for (int k = 1; k < o.inner_cycles; ++k) enqueue_vcycle(c, hier32(c), false);
     }
     const bool rows = c->M0.n > 0;       // 2D: the row-marching kernel
+    // 3D: z marching over the finest level's fused-step tasks (partials into
+    // the fused buffer), per cell for instances whose finest level is the tail
+    const bool zm = c->dim == 3 && c->Z64[0].n > 0;
     {
         TimedScope t(c, CHHS_K_REFINE);
-        if (rows)
+        if (rows) {
             chhs::launch_mixed_residual_rows(batch(c, 0, add ? act : nullptr), batch32(c, 0, act),
                                              c->M0.dev, c->M0.n, add ? 1 : 0,
                                              add ? c->act_last : nullptr, c->partial, c->stream);
-        else
+        } else if (zm) {
+            chhs::launch_refine3d(batch(c, 0, add ? act : nullptr), batch32(c, 0, act), c->Z64[0].dev,
+                                  c->Z64[0].n, add ? 1 : 0, add ? c->act_last : nullptr,
+                                  c->partial_t, c->stream);
+            if (c->A0x.n > 0)
+                chhs::launch_mixed_residual(c->dim, batch(c, 0, add ? act : nullptr),
+                                            batch32(c, 0, act), c->A0x.dev, c->A0x.n, add ? 1 : 0,
+                                            add ? c->act_last : nullptr, c->partial, c->stream);
+        } else {
             chhs::launch_mixed_residual(c->dim, batch(c, 0, add ? act : nullptr),
                                         batch32(c, 0, act), c->A[0].dev, c->A[0].n, add ? 1 : 0,
                                         add ? c->act_last : nullptr, c->partial, c->stream);
+        }
     }
     TimedScope t(c, CHHS_K_NORM);
     c->cur[0] ^= 1;
     const double* src;
     const Range* rng;
-    if (rows)
+    if (rows) {
         fold_table(c, c->FM0, c->rngM0, c->rngM0f, add ? act : nullptr, &src, &rng);
-    else
+    } else if (zm) {
+        src = c->partial;
+        rng = c->rngA0x;
+    } else {
         fold_cells(c, false, add ? act : nullptr, &src, &rng);
-    chhs::launch_inst_reduce(src, rng, nullptr, nullptr, 0, c->dinfo,
-                             add ? act : nullptr, c->act_next, c->cycles, c->res, c->n_inst,
-                             o.tol, count ? o.max_vcycles : 1 << 30, count ? 1 : 0, c->stream);
+    }
+    chhs::launch_inst_reduce(src, rng, zm ? c->partial_t : nullptr, zm ? c->rngT0 : nullptr,
+                             zm ? 1 : 0, c->dinfo, add ? act : nullptr, c->act_next, c->cycles,
+                             c->res, c->n_inst, o.tol, count ? o.max_vcycles : 1 << 30,
+                             count ? 1 : 0, c->stream);
 }
 
 void enqueue_cycle(chhs_ctx* c, bool count) {
@@ -1892,6 +1918,7 @@ int chhs_init(const chhs_problem* p, int32_t n_inst, const chhs_opts* o, void* w
     c->rngA0 = reinterpret_cast<Range*>(b + L.off_rngA0);
     c->rngT0 = reinterpret_cast<Range*>(b + L.off_rngT0);
     c->rngA0n = reinterpret_cast<Range*>(b + L.off_rngA0n);
+    c->rngA0x = reinterpret_cast<Range*>(b + L.off_rngA0x);
     c->partial_t = reinterpret_cast<double*>(b + L.off_partial_t);
     c->partial = reinterpret_cast<double*>(b + L.off_partial);
     c->partial_f = reinterpret_cast<double*>(b + L.off_partial_f);
@@ -1919,6 +1946,8 @@ int chhs_init(const chhs_problem* p, int32_t n_inst, const chhs_opts* o, void* w
         hipMemcpyAsync(c->rngT0, L.rngT0.data(), n_inst * sizeof(Range), hipMemcpyHostToDevice,
                        st) != hipSuccess ||
         hipMemcpyAsync(c->rngA0n, L.rngA0n.data(), n_inst * sizeof(Range), hipMemcpyHostToDevice,
+                       st) != hipSuccess ||
+        hipMemcpyAsync(c->rngA0x, L.rngA0x.data(), n_inst * sizeof(Range), hipMemcpyHostToDevice,
                        st) != hipSuccess)
         return fail(CHHS_E_HIP);
     for (int l = 0; l < kMaxLevels; ++l) {
@@ -1939,6 +1968,7 @@ int chhs_init(const chhs_problem* p, int32_t n_inst, const chhs_opts* o, void* w
     }
     rc |= upload(c->A0n, b, L.off_A0n, L.A0n, st);
     rc |= upload(c->A0t, b, L.off_A0t, L.A0t, st);
+    rc |= upload(c->A0x, b, L.off_A0x, L.A0x, st);
     rc |= upload(c->M0, b, L.off_M0, L.M0, st);
     rc |= upload(c->FM0, b, L.off_FM0, L.FM0, st);
     c->rngM0 = reinterpret_cast<Range*>(b + L.off_rngM0);

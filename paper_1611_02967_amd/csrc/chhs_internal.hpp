@@ -307,6 +307,10 @@ void launch_residual3d_partials(const Batch<double>& b, const Step3Task* t, int 
                                 hipStream_t st);
 void launch_restrict3d(const Batch<double>& b, const Step3Task* t, int nt, hipStream_t st);
 void launch_restrict3d(const Batch<float>& b, const Step3Task* t, int nt, hipStream_t st);
+// The FP64 refinement step of the mixed path on the finest 3D level over its
+// fused-step tasks (as launch_mixed_residual; partials one per task).
+void launch_refine3d(const Batch<double>& b64, const Batch<float>& b32, const Step3Task* t, int nt,
+                     int add, const int* was_active, double* partial, hipStream_t st);
 // pro: 0 no prolongation, 1 piecewise-constant, 2 trilinear coarse correction
 // added to u (from level + 1, copy cur_c) as the launch loads it
 void launch_step3d(const Batch<double>& b, const Step3Task* t, int nt, int pro, hipStream_t st);
