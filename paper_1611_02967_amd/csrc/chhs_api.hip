@@ -925,12 +925,14 @@ void tiled(chhs_ctx* c, const Hier<T>& H, bool all, int l, int ns, int epi, bool
 // One fused 3D smoothing step on level l of a hierarchy (the instances above
 // their tail); flips the level's current copy.
 template <typename T>
-void step3(chhs_ctx* c, const Hier<T>& H, int l, const int* active, int cls, int pro = 0) {
+void step3(chhs_ctx* c, const Hier<T>& H, int l, const int* active, int cls, int pro = 0,
+           bool zero = false, const double* psh = nullptr) {
     Batch<T> b = make_batch(H.dev, H.cur, l, active);
+    b.pshift = psh;
     const Table<Step3Task>& z = std::is_same<T, double>::value ? c->Z64[l] : c->Z32[l];
     {
         TimedScope t(c, cls);
-        chhs::launch_step3d(b, z.dev, z.n, pro, c->stream);
+        chhs::launch_step3d(b, z.dev, z.n, pro, zero ? 1 : 0, c->stream);
     }
     H.cur[l] ^= 1;
 }
@@ -985,6 +987,8 @@ void smooth_steps(chhs_ctx* c, int l, int nsweeps, const int* active, int cls) {
 // launch also yields the fused norm partials; FP32: the correction form,
 // starting from a zero correction (zero_corr; the tiled finest level's first
 // launch then takes it as implied) or from the previous cycle's.
+bool zero_start(const chhs_ctx* c);
+
 template <typename T>
 void enqueue_vcycle(chhs_ctx* c, const Hier<T>& H, bool zero_corr = true) {
     constexpr bool kPlain = std::is_same<T, double>::value;
@@ -1015,8 +1019,14 @@ void enqueue_vcycle(chhs_ctx* c, const Hier<T>& H, bool zero_corr = true) {
             tiled(c, H, false, d, rem, 1, false, act, pre_cls, rhs && first, first ? psh : nullptr,
                   zero && first);
         } else {
-            if (z3_at(c, d))
-                for (int s = 0; s < nu1; ++s) step3(c, H, d, act, pre_cls);
+            if (z3_at(c, d)) {
+                // on the finest level the first step takes the zero correction
+                // as implied (correction cycles) or subtracts a deferred p shift
+                const bool zero = !kPlain && d == 0 && zero_corr && zero_start(c);
+                const double* psh = kPlain && d == 0 && c->defer_shift ? c->res : nullptr;
+                for (int s = 0; s < nu1; ++s)
+                    step3(c, H, d, act, pre_cls, 0, zero && s == 0, s == 0 ? psh : nullptr);
+            }
             else if (!tiled2d(c))
                 for (int s = 0; s < nu1; ++s)
                     for (int color = 0; color < 2; ++color) {
@@ -1362,14 +1372,17 @@ void apply_pshift(chhs_ctx* c) {
     chhs::launch_clear_pshift(c->res, c->n_inst, c->stream);
 }
 
-// Mixed precision, one refinement step: zero FP32 correction, one FP32
-// correction-form V-cycle, then in FP64 u += e, the residual of the full
+// Mixed precision, one refinement step: zero FP32 correction, inner_cycles FP32
+// correction-form V-cycles, then in FP64 u += e, the residual of the full
 // system (into the FP32 right-hand side) and its norms.
 // The first FP32 launch of a correction cycle on the finest level is a tiled
-// pre-smoothing launch that takes the zero starting correction as implied
-// (2D with nu1 > 0); otherwise the correction is cleared by a pass of its own,
-// as it is for instances whose finest level the one-workgroup tail holds.
-bool zero_start(const chhs_ctx* c) { return tiled2d(c) && c->opts.nu1 > 0; }
+// (2D) or fused 3D pre-smoothing launch that takes the zero starting
+// correction as implied (nu1 > 0); otherwise the correction is cleared by a
+// pass of its own, as it is for instances whose finest level the
+// one-workgroup tail holds.
+bool zero_start(const chhs_ctx* c) {
+    return c->opts.nu1 > 0 && (tiled2d(c) || z3_at(c, 0));
+}
 
 // p's mean is not subtracted here: N(u) depends on p through differences only,
 // so the residual and the cycle do not change; res slot 4 holds the mean of the
@@ -1714,7 +1727,16 @@ int enqueue_energies(chhs_ctx* c, int ws, const double* phi, const double* q, do
         b.pshift = c->defer_shift ? c->res : nullptr;
         chhs::launch_energy_partials(c->dim, b, c->A[0].dev, c->A[0].n, c->dinfo, ws, phi, q,
                                      c->partial, c->stream, copy);
-        chhs::launch_energy_reduce(c->partial, c->rngA0, c->dinfo, c->eres, c->n_inst, c->stream);
+        // instances with more than kFold partials: folded in runs first, so
+        // that one workgroup per instance reads a few partials
+        if (c->FA0.n > 0) {
+            chhs::launch_fold_energy(c->partial, c->FA0.dev, c->FA0.n, c->partial_f, c->stream);
+            chhs::launch_energy_reduce(c->partial_f, c->rngA0f, c->dinfo, c->eres, c->n_inst,
+                                       c->stream);
+        } else {
+            chhs::launch_energy_reduce(c->partial, c->rngA0, c->dinfo, c->eres, c->n_inst,
+                                       c->stream);
+        }
     }
     int rc = check_launch();
     if (rc) return rc;
@@ -2013,6 +2035,9 @@ int chhs_init(const chhs_problem* p, int32_t n_inst, const chhs_opts* o, void* w
         const int arc = autotune3(c);
         if (arc) return fail(arc);
     }
+    // 3D plain FP64 with the fused step on the finest level: its first
+    // pre-smoothing launch subtracts p's pending mean as it loads p
+    if (!c->mixed && z3_at(c, 0) && o->nu1 > 0) c->defer_shift = true;
     {
         // the per-step log of chhs_step_log, reserved up front
         const size_t per_step = size_t(n_inst) * chhs::kResStride * sizeof(double);

@@ -219,6 +219,8 @@ void launch_residual_partials(int dim, const Batch<double>& b, const CellTask* t
 // tasks of active instances.
 void launch_fold_partials(const double* src, const FoldTask* t, int nt, const int* active,
                           double* dst, hipStream_t st);
+// The same for the energy partials (eight sums and a maximum each).
+void launch_fold_energy(const double* src, const FoldTask* t, int nt, double* dst, hipStream_t st);
 void launch_inst_reduce(const double* partial, const Range* ranges, const double* partial_t,
                         const Range* ranges_t, int use_fused, const InstInfo* info,
                         const int* active, int* act_next, int* cycles, double* res, int n_inst,
@@ -312,9 +314,13 @@ void launch_restrict3d(const Batch<float>& b, const Step3Task* t, int nt, hipStr
 void launch_refine3d(const Batch<double>& b64, const Batch<float>& b32, const Step3Task* t, int nt,
                      int add, const int* was_active, double* partial, hipStream_t st);
 // pro: 0 no prolongation, 1 piecewise-constant, 2 trilinear coarse correction
-// added to u (from level + 1, copy cur_c) as the launch loads it
-void launch_step3d(const Batch<double>& b, const Step3Task* t, int nt, int pro, hipStream_t st);
-void launch_step3d(const Batch<float>& b, const Step3Task* t, int nt, int pro, hipStream_t st);
+// added to u (from level + 1, copy cur_c) as the launch loads it; zero: u is
+// the zero correction (not read); b.pshift: the pending mean of p subtracted
+// as p is loaded
+void launch_step3d(const Batch<double>& b, const Step3Task* t, int nt, int pro, int zero,
+                   hipStream_t st);
+void launch_step3d(const Batch<float>& b, const Step3Task* t, int nt, int pro, int zero,
+                   hipStream_t st);
 
 // ---- single-workgroup coarse tail (chhs_tail.hip) ----------------------------------
 // The cycle's shape: smoothing steps before / after the coarse correction on

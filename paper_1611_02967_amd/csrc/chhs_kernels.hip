@@ -627,6 +627,26 @@ __global__ __launch_bounds__(kBlock) void k_fold_partials(const double* __restri
         for (int c = 0; c < 4; ++c) dst[blockIdx.x * kPartialStride + c] = s[c];
 }
 
+// The same for the energy partials: eight sums and a maximum per partial.
+__global__ __launch_bounds__(kBlock) void k_fold_energy(const double* __restrict__ src,
+                                                        const FoldTask* __restrict__ t, double* dst) {
+    const FoldTask ft = t[blockIdx.x];
+    double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double vmax = 0.0;
+#pragma unroll 4
+    for (int q = ft.begin + threadIdx.x; q < ft.end; q += kBlock) {
+        for (int c = 0; c < 8; ++c) v[c] += src[q * kPartialStride + c];
+        vmax = fmax(vmax, src[q * kPartialStride + 8]);
+    }
+    double s[8];
+    block_sum<8>(v, s);
+    const double m = block_max(vmax);
+    if (threadIdx.x == 0) {
+        for (int c = 0; c < 8; ++c) dst[blockIdx.x * kPartialStride + c] = s[c];
+        dst[blockIdx.x * kPartialStride + 8] = m;
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_inst_reduce(const double* __restrict__ partial,
                                                         const Range* __restrict__ ranges,
                                                         const double* __restrict__ partial_t,
@@ -989,6 +1009,10 @@ void launch_fold_partials(const double* src, const FoldTask* t, int nt, const in
                           double* dst, hipStream_t st) {
     if (nt <= 0) return;
     hipLaunchKernelGGL(k_fold_partials, dim3(nt), dim3(kBlock), 0, st, src, t, active, dst);
+}
+
+void launch_fold_energy(const double* src, const FoldTask* t, int nt, double* dst, hipStream_t st) {
+    if (nt > 0) hipLaunchKernelGGL(k_fold_energy, dim3(nt), dim3(kBlock), 0, st, src, t, dst);
 }
 
 void launch_inst_reduce(const double* partial, const Range* ranges, const double* partial_t,

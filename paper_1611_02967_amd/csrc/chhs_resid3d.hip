@@ -20,7 +20,9 @@
 // residual of its cells of plane t from planes t - 1 .. t + 1.  Plane t + 3
 // and the own data of plane t + 2 (f, phi^m, b) are loaded into one of two
 // register sets at the end of iteration t, so a load's latency overlaps a
-// whole iteration.  In MODE 1 the 2 x 2 in-plane sums are lane exchanges (the
+// whole iteration (region cells outside the grid load cell 0 of the level:
+// finite values that no face reads; no operation follows a load before its
+// value is stored to LDS).  In MODE 1 the 2 x 2 in-plane sums are lane exchanges (the
 // x neighbour is lane ^ 1, the y neighbour lane ^ TX) and the z pair is summed
 // in registers over two iterations.
 #include "chhs_cell.hpp"
@@ -74,7 +76,6 @@ __global__ __launch_bounds__(kThreads) void k_resid3d(Batch<T> bt, const Step3Ta
             rv[k][MU] = gload(L.mu, g);
             rv[k][P] = gload(L.p, g);
             rv[k][PS] = gload(L.pstar, g);
-            if (!ok) rv[k][PHI] = rv[k][MU] = rv[k][P] = rv[k][PS] = T(0);
         }
     };
     auto store_plane = [&](int z, const Regs& rv) {

@@ -21,8 +21,14 @@
 // iterations before its update by the thread that makes it, so a load's
 // latency overlaps a whole iteration of work.
 //
-// With pro != 0 the launch first prolongs the coarse correction: every
-// region cell's iterate is loaded as u + P(u_c - ub_c) (pro = 1 piecewise-
+// With ZERO (the first pre-smoothing launch of a correction cycle on the
+// finest level) the iterate is taken as the zero correction and not read.
+// With b.pshift set (the first pre-smoothing launch on the finest FP64 level)
+// the pending mean of p (res slot 4 of the instance) is subtracted from p as
+// it is loaded, so that p's normalisation after a cycle costs no pass.
+//
+// With PRO != 0 the launch first prolongs the coarse correction: every
+// region cell's iterate is loaded as u + P(u_c - ub_c) (PRO = 1 piecewise-
 // constant injection, 2 cell-centred trilinear interpolation), the update the
 // prolongation kernel makes, so the first post-smoothing step needs no pass of
 // its own over the fine level.  Halo cells get the same corrected values as in
@@ -62,9 +68,12 @@ struct Own {
     T psi, f0, f1, f2, b;
 };
 
-template <typename T, bool CORR, int TX, int TY>
+// PRO and ZERO are template arguments: a branch around the region loads
+// would make the compiler wait for every load in flight where the branches
+// join, and the loads would no longer overlap an iteration.
+template <typename T, bool CORR, int TX, int TY, int PRO, bool ZERO>
 __global__ __launch_bounds__(kThreads) void k_step3d(Batch<T> bt, const Step3Task* __restrict__ tasks,
-                                                     int ntasks, int pro) {
+                                                     int ntasks) {
     using G = Geo<TX, TY>;
     constexpr int RX = G::RX, RY = G::RY, NR = G::NR;
     __shared__ T s[kRing][NRF][NR];
@@ -75,8 +84,8 @@ __global__ __launch_bounds__(kThreads) void k_step3d(Batch<T> bt, const Step3Tas
     const Step3Task tk = tasks[xcd * q8 + (xcd < rem ? xcd : rem) + jj];
     if (bt.active != nullptr && bt.active[tk.inst] == 0) return;
     const Level<T> L = make_view(bt.desc[tk.inst * kMaxLevels + bt.level], bt.cur);
-    // the coarse level of the prolongation (pro != 0 only)
-    const Level<T> C = make_view(bt.desc[tk.inst * kMaxLevels + bt.level + (pro != 0 ? 1 : 0)],
+    // the coarse level of the prolongation (PRO != 0 only)
+    const Level<T> C = make_view(bt.desc[tk.inst * kMaxLevels + bt.level + (PRO != 0 ? 1 : 0)],
                                  bt.cur_c);
     const int nx = L.nx, ny = L.ny, nz = L.nz;
     const int sxy = nx * ny;
@@ -89,9 +98,16 @@ __global__ __launch_bounds__(kThreads) void k_step3d(Batch<T> bt, const Step3Tas
     const int tid = threadIdx.x;
     const T lam = L.lam, kap = L.kap, gam = L.gamma;
     const T inv_lam = T(1) / lam;
+    const T psh = bt.pshift != nullptr ? T(bt.pshift[tk.inst * kResStride + 4]) : T(0);
 
     // ---- region loads: thread takes region cells tid + k kThreads ----------------------
-    using Regs = T[G::KR][NRF];
+    // Loaded values are only stored to LDS two iterations later, and every
+    // operation on them (the pending p shift, the coarse correction) is done
+    // there: an operation right after a load would wait for it (and for every
+    // load issued before it).  Region cells outside the grid load cell 0 of the
+    // level (finite values that no face reads: boundary faces are dropped).
+    // (PRO 1: u_c and ub_c of the coarse parent in six more slots, unused otherwise)
+    using Regs = T[G::KR][NRF + 6];
     auto load_plane = [&](int z, Regs& rv) {
 #pragma unroll
         for (int k = 0; k < G::KR; ++k) {
@@ -100,21 +116,27 @@ __global__ __launch_bounds__(kThreads) void k_step3d(Batch<T> bt, const Step3Tas
             const int gx = x0 + rx, gy = y0 + ry;
             const bool ok = q < NR && gx >= 0 && gx < nx && gy >= 0 && gy < ny && z >= 0 && z < nz;
             const int g = ok ? z * sxy + gy * nx + gx : 0;
-            rv[k][PHI] = gload(L.phi, g);
-            rv[k][MU] = gload(L.mu, g);
-            rv[k][P] = gload(L.p, g);
+            if (ZERO) {
+                rv[k][PHI] = rv[k][MU] = rv[k][P] = T(0);
+            } else {
+                rv[k][PHI] = gload(L.phi, g);
+                rv[k][MU] = gload(L.mu, g);
+                rv[k][P] = gload(L.p, g);
+            }
             rv[k][PS] = gload(L.pstar, g);
-            if (pro == 1 && ok) {
-                const int c = ((z >> 1) * C.ny + (gy >> 1)) * C.nx + (gx >> 1);
-                rv[k][PHI] += gload(C.phi, c) - gload(C.ub0, c);
-                rv[k][MU] += gload(C.mu, c) - gload(C.ub1, c);
-                rv[k][P] += gload(C.p, c) - gload(C.ub2, c);
-            } else if (pro == 2 && ok) {
+            if (PRO == 1) {
+                const int c = ok ? ((z >> 1) * C.ny + (gy >> 1)) * C.nx + (gx >> 1) : 0;
+                rv[k][NRF + 0] = gload(C.phi, c);
+                rv[k][NRF + 1] = gload(C.mu, c);
+                rv[k][NRF + 2] = gload(C.p, c);
+                rv[k][NRF + 3] = gload(C.ub0, c);
+                rv[k][NRF + 4] = gload(C.ub1, c);
+                rv[k][NRF + 5] = gload(C.ub2, c);
+            } else if (PRO == 2 && ok) {
                 rv[k][PHI] += bilinear_corr<3>(C.phi, C.ub0, C.nx, C.ny, C.nz, gx, gy, z);
                 rv[k][MU] += bilinear_corr<3>(C.mu, C.ub1, C.nx, C.ny, C.nz, gx, gy, z);
                 rv[k][P] += bilinear_corr<3>(C.p, C.ub2, C.nx, C.ny, C.nz, gx, gy, z);
             }
-            if (!ok) rv[k][PHI] = rv[k][MU] = rv[k][P] = rv[k][PS] = T(0);
         }
     };
     auto store_plane = [&](int z, const Regs& rv) {
@@ -122,9 +144,17 @@ __global__ __launch_bounds__(kThreads) void k_step3d(Batch<T> bt, const Step3Tas
 #pragma unroll
         for (int k = 0; k < G::KR; ++k) {
             const int q = tid + k * kThreads;
-            if (q < NR)
-#pragma unroll
-                for (int f = 0; f < NRF; ++f) s[sl][f][q] = rv[k][f];
+            if (q >= NR) continue;
+            T ph = rv[k][PHI], mu = rv[k][MU], p = rv[k][P] - psh;
+            if (PRO == 1) {
+                ph += rv[k][NRF + 0] - rv[k][NRF + 3];
+                mu += rv[k][NRF + 1] - rv[k][NRF + 4];
+                p += rv[k][NRF + 2] - rv[k][NRF + 5];
+            }
+            s[sl][PHI][q] = ph;
+            s[sl][MU][q] = mu;
+            s[sl][P][q] = p;
+            s[sl][PS][q] = rv[k][PS];
         }
     };
 
@@ -300,18 +330,31 @@ __global__ __launch_bounds__(kThreads) void k_step3d(Batch<T> bt, const Step3Tas
 }
 
 template <typename T, bool CORR, int TX, int TY>
-void launch_tiles(const Batch<T>& b, const Step3Task* t, int nt, int pro, hipStream_t st) {
-    hipLaunchKernelGGL((k_step3d<T, CORR, TX, TY>), dim3(nt), dim3(kThreads), 0, st, b, t, nt, pro);
+void launch_tiles(const Batch<T>& b, const Step3Task* t, int nt, int pro, int zero, hipStream_t st) {
+    if (pro == 1)
+        hipLaunchKernelGGL((k_step3d<T, CORR, TX, TY, 1, false>), dim3(nt), dim3(kThreads), 0, st,
+                           b, t, nt);
+    else if (pro == 2)
+        hipLaunchKernelGGL((k_step3d<T, CORR, TX, TY, 2, false>), dim3(nt), dim3(kThreads), 0, st,
+                           b, t, nt);
+    else if (zero && CORR)
+        hipLaunchKernelGGL((k_step3d<T, CORR, TX, TY, 0, CORR>), dim3(nt), dim3(kThreads), 0, st,
+                           b, t, nt);
+    else
+        hipLaunchKernelGGL((k_step3d<T, CORR, TX, TY, 0, false>), dim3(nt), dim3(kThreads), 0, st,
+                           b, t, nt);
 }
 
 }  // namespace
 
-void launch_step3d(const Batch<double>& b, const Step3Task* t, int nt, int pro, hipStream_t st) {
-    if (nt > 0) launch_tiles<double, false, kStep3TX64, kStep3TY64>(b, t, nt, pro, st);
+void launch_step3d(const Batch<double>& b, const Step3Task* t, int nt, int pro, int zero,
+                   hipStream_t st) {
+    if (nt > 0) launch_tiles<double, false, kStep3TX64, kStep3TY64>(b, t, nt, pro, zero, st);
 }
 
-void launch_step3d(const Batch<float>& b, const Step3Task* t, int nt, int pro, hipStream_t st) {
-    if (nt > 0) launch_tiles<float, true, kStep3TX32, kStep3TY32>(b, t, nt, pro, st);
+void launch_step3d(const Batch<float>& b, const Step3Task* t, int nt, int pro, int zero,
+                   hipStream_t st) {
+    if (nt > 0) launch_tiles<float, true, kStep3TX32, kStep3TY32>(b, t, nt, pro, zero, st);
 }
 
 }  // namespace chhs
