@@ -249,31 +249,47 @@ __global__ __launch_bounds__(NT) void k_tile2d(Batch<T> bt, const TileTask* __re
         __syncthreads();
     }
 
+    // Per pair and color, once for all phases: the LDS word of the member with
+    // that color, the word of its x - 1 neighbour (the x + 1 neighbour is the
+    // next word: an even member's x neighbours are odd columns, stored after
+    // the row's even ones, and the other way round), its ring distance from the
+    // block (more than any ring outside the grid) and which of its faces are
+    // interior (bits x - 1, x + 1, y - 1, y + 1).  A phase then needs no
+    // geometry of its own.
+    int wcol[2][KP], wlcol[2][KP], dcol[2][KP], fcol[2][KP];
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+        const int q = tid + k * kThreads;
+        const int r = q / PW, xp = 2 * (q % PW);
+        const int gy = y0 + r;
+#pragma unroll
+        for (int color = 0; color < 2; ++color) {
+            const int e = (gy & 1) ^ color;         // the pair member with this color
+            const int x = xp + e;
+            const int gx = x0 + x;
+            const bool in = q < NP && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+            const int dx = x < HX ? HX - x : (x >= HX + kTX ? x - (HX + kTX - 1) : 0);
+            const int dy = r < H ? H - r : (r >= H + kTY ? r - (H + kTY - 1) : 0);
+            dcol[color][k] = in ? (dx > dy ? dx : dy) : H + 1;
+            wcol[color][k] = lds<PW>(r, x);
+            wlcol[color][k] = wcol[color][k] + (e ? -PW : PW - 1);
+            fcol[color][k] = (gx > 0 ? 1 : 0) | (gx < nx - 1 ? 2 : 0) | (gy > 0 ? 4 : 0) |
+                             (gy < ny - 1 ? 8 : 0);
+        }
+    }
+
 #pragma unroll
     for (int ph = 0; ph < 2 * NS; ++ph) {
         const int color = ph & 1;
         const int ring = G::X + 2 * NS - 1 - ph;
 #pragma unroll
         for (int k = 0; k < KP; ++k) {
-            const int q = tid + k * kThreads;
-            if (q >= NP) continue;
-            const int r = q / PW, xp = 2 * (q % PW);
-            const int gy = y0 + r;
-            // the pair member with this color (x0 + xp is even): same for a whole row
-            const int e = (gy & 1) ^ color;
-            const int x = xp + e;
-            const int gx = x0 + x;
-            if (gx < 0 || gx >= nx || gy < 0 || gy >= ny) continue;
-            const int dx = x < HX ? HX - x : (x >= HX + kTX ? x - (HX + kTX - 1) : 0);
-            const int dy = r < H ? H - r : (r >= H + kTY ? r - (H + kTY - 1) : 0);
-            if ((dx > dy ? dx : dy) > ring) continue;
-
-            const int wc = lds<PW>(r, x);
+            if (dcol[color][k] > ring) continue;
+            const int wc = wcol[color][k], wl = wlcol[color][k], fl = fcol[color][k];
             const T psc = s_ps[wc];
             int nf = 0;
             T sa = 0, sa2 = 0, smmu = 0, sphi = 0, sp = 0, sap = 0, samu = 0;
-            auto nb_acc = [&](int rr, int xx) {
-                const int w = lds<PW>(rr, xx);
+            auto nb_acc = [&](int w) {
                 const T a = T(0.5) * (psc + s_ps[w]);
                 const T m = T(1) + gam * a * a;
                 const T munb = s_mu[w];
@@ -287,10 +303,11 @@ __global__ __launch_bounds__(NT) void k_tile2d(Batch<T> bt, const TileTask* __re
                 sap += a * pnb;
                 samu += a * munb;
             };
-            if (gx > 0) nb_acc(r, x - 1);
-            if (gx < nx - 1) nb_acc(r, x + 1);
-            if (gy > 0) nb_acc(r - 1, x);
-            if (gy < ny - 1) nb_acc(r + 1, x);
+            // faces in the order x - 1, x + 1, y - 1, y + 1
+            if (fl & 1) nb_acc(wl);
+            if (fl & 2) nb_acc(wl + 1);
+            if (fl & 4) nb_acc(wc - 2 * PW);
+            if (fl & 8) nb_acc(wc + 2 * PW);
             const T fnf = T(nf);
             const T inv_nf = nf == 4 ? T(0.25) : (nf == 3 ? T(1) / T(3) : (nf == 2 ? T(0.5) : T(1)));
             const T phit = s_phi[wc];
