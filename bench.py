@@ -738,10 +738,19 @@ TRAFFIC_KERNELS = [
      ["chhs_stream2d.hip", "chhs_cell.hpp", "chhs_internal.hpp"]),
     ("post0", r"k_stream2d<double, true, 2, 2,", 84.0,
      ["chhs_stream2d.hip", "chhs_cell.hpp", "chhs_internal.hpp"]),
-    ("pre0", r"k_step3d<double", 88.0, ["chhs_step3d.hip", "chhs_cell.hpp", "chhs_internal.hpp"]),
-    ("post0", r"k_step3d<double", 88.0, ["chhs_step3d.hip", "chhs_cell.hpp", "chhs_internal.hpp"]),
-    ("pre0", r"k_step3d<float", 48.0, ["chhs_step3d.hip", "chhs_cell.hpp", "chhs_internal.hpp"]),
-    ("post0", r"k_step3d<float", 48.0, ["chhs_step3d.hip", "chhs_cell.hpp", "chhs_internal.hpp"]),
+    # fused 3D step (template arguments T, CORR, TX, TY, PRO, ZERO): pre launches
+    # without prolongation; the post class by its first launch, which also
+    # reads u_c and ub_c of the coarse parent (6 values per 8 cells)
+    ("pre0", r"k_step3d<double, false, \d+, \d+, 0, false>", 88.0,
+     ["chhs_step3d.hip", "chhs_cell.hpp", "chhs_internal.hpp"]),
+    ("post0", r"k_step3d<double, false, \d+, \d+, 1, false>", 94.0,
+     ["chhs_step3d.hip", "chhs_cell.hpp", "chhs_internal.hpp"]),
+    ("pre0", r"k_step3d<float, true, \d+, \d+, 0, true>", 36.0,
+     ["chhs_step3d.hip", "chhs_cell.hpp", "chhs_internal.hpp"]),
+    ("pre0", r"k_step3d<float, true, \d+, \d+, 0, false>", 48.0,
+     ["chhs_step3d.hip", "chhs_cell.hpp", "chhs_internal.hpp"]),
+    ("post0", r"k_step3d<float, true, \d+, \d+, 1, false>", 51.0,
+     ["chhs_step3d.hip", "chhs_cell.hpp", "chhs_internal.hpp"]),
 ]
 
 
