@@ -94,12 +94,15 @@ typedef struct chhs_problem {
  * tile_rows = 0 (default) cuts coarse tiled levels into 64 x 8 tiles when they
  * have at most 128 tiles of 64 x 16 (over the batch) and into 64 x 16 tiles
  * otherwise; 16, 8 or 4 fixes the tile height of every coarse tiled level
- * (the finest level always has 64 x 16 tiles).
+ * (the finest level has 64 x 16 tiles); 32 (precision = 1 only) gives the
+ * finest level of the FP32 hierarchy 64 x 32 tiles (fewer halo cells
+ * recomputed per cell) and leaves the coarse levels at their default.
  * autotune = 1 (smoother = 0, second-order scheme): chhs_init times, on the
  * problem at hand, each level's smoothing launches and keeps the fastest per
  * level (the choice then depends on the device; results agree to rounding).
  * 2D (nu1, nu2 >= 1): tiles of 256, 512 and 1024 threads (on coarse levels
- * each with 16, 8 and 4 rows) and strips of 1/4, 1/2, 1, 2 and 4 times the
+ * each with 16, 8 and 4 rows; on the FP32 finest level also 64 x 32 tiles of
+ * 512 and 1024 threads) and strips of 1/4, 1/2, 1, 2 and 4 times the
  * default segment height.  3D: the fused step or the per-cell kernels.
  * order = 2 (default; 0 means the same) solves the second-order scheme
  * (2.4)-(2.7).  order = 1 solves instead the first-order convex-splitting step

@@ -238,7 +238,10 @@ bool valid_opts(const chhs_opts* o) {
         o->tile_threads != 1024)
         return false;
     if (o->tile_rows != 0 && o->tile_rows != chhs::kTileY && o->tile_rows != chhs::kTileYSmall &&
-        o->tile_rows != chhs::kTileYTiny)
+        o->tile_rows != chhs::kTileYTiny && o->tile_rows != chhs::kTileYTall)
+        return false;
+    // 32 rows: the finest level of the FP32 hierarchy (mixed precision) only
+    if (o->tile_rows == chhs::kTileYTall && o->precision != 1)
         return false;
     if (o->nu1_coarse < 0 || o->nu2_coarse < 0) return false;
     if (o->prolong != 0 && o->prolong != 1) return false;
@@ -519,9 +522,12 @@ bool plan(const chhs_problem* p, int n_inst, const chhs_opts* o, char* base, Lay
                 tiles16[l] += long((ext[3 * l] + chhs::kTileX - 1) / chhs::kTileX) *
                               ((ext[3 * l + 1] + chhs::kTileY - 1) / chhs::kTileY);
         }
+        const bool tall = o->tile_rows == chhs::kTileYTall;    // finest level only
+        if (tall) L.tile_y[0] = chhs::kTileYTall;
         for (int l = 1; l < kMaxLevels; ++l)
-            L.tile_y[l] = o->tile_rows != 0 ? o->tile_rows
-                        : (tiles16[l] <= kSmallTileLevel ? chhs::kTileYSmall : chhs::kTileY);
+            L.tile_y[l] = o->tile_rows != 0 && !tall
+                              ? o->tile_rows
+                              : (tiles16[l] <= kSmallTileLevel ? chhs::kTileYSmall : chhs::kTileY);
     }
     int packed = 0;
     for (int i = 0; i < n_inst; ++i) {
@@ -1243,6 +1249,9 @@ int autotune(chhs_ctx* c) {
             if (l == 0 && ty != chhs::kTileY) continue;     // the finest level has 64 x 16 tiles
             for (int nt : {256, 512, 1024}) cands.push_back({false, nt, 0, ty});
         }
+        // ... or, in FP32 (mixed precision), 64 x 32
+        if (l == 0 && c->mixed)
+            for (int nt : {512, 1024}) cands.push_back({false, nt, 0, chhs::kTileYTall});
         bool even = true;
         int maxny = 0;
         for (int i = 0; i < c->n_inst; ++i)

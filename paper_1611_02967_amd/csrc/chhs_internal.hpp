@@ -263,11 +263,13 @@ void launch_roll_flags(int* last, int* cur, const int* next, int n, hipStream_t 
 // ---- tiled 2D smoothing (chhs_tile2d.hip) ------------------------------------------
 // Tiles are 64 x 16 cells, or on coarse levels 64 x 8 or 64 x 4 (more,
 // smaller blocks: on levels with few tiles the time of one block is the time
-// of the launch).
+// of the launch), or on the FP32 finest level 64 x 32 (fewer cells of the
+// halo recomputed per cell of the tile).
 constexpr int kTileX = 64;
 constexpr int kTileY = 16;
 constexpr int kTileYSmall = 8;
 constexpr int kTileYTiny = 4;
+constexpr int kTileYTall = 32;
 // ns fused smoothing steps on level b.level of every tasked instance, read from
 // copy b.cur and written to the other copy; epi 0 none, 1 residual + restriction
 // into level + 1 (copy b.cur_c), 2 residual-norm partials (4 per block, in task
@@ -276,9 +278,10 @@ constexpr int kTileYTiny = 4;
 // or one pair of cells per thread);
 // rhs: first pre-smoothing launch on a coarse level, which first forms the FAS
 // right-hand side f += N(u) (not with level0, pro or epi 2); ty: tile height,
-// kTileY or (not with level0) kTileYSmall or kTileYTiny, as the tasks were cut;
+// kTileY or (not with level0) kTileYSmall or kTileYTiny, as the tasks were cut,
+// or (FP32, not with rhs) kTileYTall;
 // zero (FP32 only, the finest level's first launch of a correction cycle, 64 x
-// 16 tiles, not with pro, rhs or epi 2): u is taken as zero instead of read.
+// 16 or 64 x 32 tiles, not with pro, rhs or epi 2): u is taken as zero instead of read.
 template <typename T>
 void launch_tile2d(const Batch<T>& b, const TileTask* t, int nt, bool level0, int ns, int epi,
                    bool pro, int threads, bool rhs, int ty, bool zero, double* partial,

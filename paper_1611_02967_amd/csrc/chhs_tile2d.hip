@@ -477,6 +477,13 @@ template <typename T, bool LEVEL0, int NS, int EPI, bool PRO, bool CORR, bool RH
           bool ZERO = false>
 void launch_one(const Batch<T>& b, const TileTask* t, int nt, int threads, int ty, double* partial,
                 hipStream_t st) {
+    if constexpr (CORR && !RHS) {
+        if (ty == kTileYTall) {
+            launch_ty<T, LEVEL0, NS, EPI, PRO, CORR, RHS, kTileYTall, ZERO>(b, t, nt, threads,
+                                                                           partial, st);
+            return;
+        }
+    }
     if constexpr (!LEVEL0 && !ZERO) {
         if (ty == kTileYSmall) {
             launch_ty<T, LEVEL0, NS, EPI, PRO, CORR, RHS, kTileYSmall, false>(b, t, nt, threads,
@@ -540,8 +547,9 @@ void launch_tile2d<float>(const Batch<float>& b, const TileTask* t, int nt, bool
     (void)level0;
     if (nt <= 0) return;
     if (zero) {
-        // first launch of a correction cycle on the finest level (64 x 16 tiles)
-        if (pro || rhs || epi == 2 || ty != kTileY) return;
+        // first launch of a correction cycle on the finest level (64 x 16 or
+        // 64 x 32 tiles)
+        if (pro || rhs || epi == 2 || (ty != kTileY && ty != kTileYTall)) return;
 #define CHHS_TILE_ZERO(NS, EPI)                                                   \
     if (ns == NS && epi == EPI) {                                                 \
         launch_one<float, false, NS, EPI, false, true, false, true>(b, t, nt, threads, ty, partial, st); \

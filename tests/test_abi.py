@@ -118,6 +118,9 @@ def test_workspace_bytes_rejects_invalid_problems(binding):
         assert binding.chhs_workspace_bytes([good], binding.chhs_default_opts(tile_rows=rows)) > 0
     for rows in (2, 32, -4):
         assert binding.chhs_workspace_bytes([good], binding.chhs_default_opts(tile_rows=rows)) == 0
+    # 32 rows: the FP32 finest level of the mixed path only
+    assert binding.chhs_workspace_bytes([good], binding.chhs_default_opts(tile_rows=32,
+                                                                          precision=1)) > 0
     # smoother 4 (fused 3D step on every level): the 3D second-order scheme only
     cube = binding.make_problem((32, 32, 32), 1 / 32, 0.05, 1.0, 1e-3)
     assert binding.chhs_workspace_bytes([cube], binding.chhs_default_opts(smoother=4)) > 0

@@ -167,3 +167,27 @@ def test_inner_cycles_solve_the_same_steps(chhs, name, inner):
     for hg, hs in zip(got, single):
         for k in ("phi", "mu", "p"):
             assert np.array_equal(_unpack(hg[k], shapes)[0], hs[k].reshape(shapes[0])), k
+
+
+@pytest.mark.parametrize("name", ["2d-64", "2d-ragged"])
+def test_tall_finest_tiles_solve_the_same_steps(chhs, name):
+    """64 x 32 tiles on the FP32 finest level (tile_rows = 32): the same FP64
+    solution (<= 1e-8 against the FP64 path, residual at tol), the same
+    refinement counts as 64 x 16 tiles (to one), and batch = single runs bitwise."""
+    spec = SPECS[name]
+    shapes = [s[0] for s in spec]
+    phi0s = [uniform_field(sh, 4600 + i, mean=0.1, amp=0.05) for i, sh in enumerate(shapes)]
+    ref = _steps(chhs, spec, phi0s, 3, precision=0)
+    base = _steps(chhs, spec, phi0s, 3, precision=1)
+    tall = _steps(chhs, spec, phi0s, 3, precision=1, tile_rows=32)
+    for hr, hb, ht in zip(ref, base, tall):
+        assert np.max(np.abs(ht["phi"] - hr["phi"])) <= 1e-8
+        assert np.max(np.abs(ht["phi"] - hb["phi"])) <= 1e-8
+        for st, sb in zip(ht["stats"], hb["stats"]):
+            assert st["res_norm"] <= 1e-10
+            assert abs(st["vcycles"] - sb["vcycles"]) <= 1
+    if len(spec) > 1:
+        single = _steps(chhs, [spec[0]], [phi0s[0]], 3, precision=1, tile_rows=32)
+        for ht, hs in zip(tall, single):
+            for k in ("phi", "mu", "p"):
+                assert np.array_equal(_unpack(ht[k], shapes)[0], hs[k].reshape(shapes[0])), k
