@@ -39,6 +39,8 @@
 // touch consecutive LDS words.
 #include "chhs_cell.hpp"
 
+#include <type_traits>
+
 namespace chhs {
 namespace {
 
@@ -96,352 +98,372 @@ __global__ __launch_bounds__(NT) void k_tile2d(Batch<T> bt, const TileTask* __re
     // a deferred shift of p (Batch::pshift), subtracted as p loads
     const T psh = bt.pshift != nullptr ? T(bt.pshift[tk.inst * kResStride + 4]) : T(0);
 
-    // own-cell data of the thread's pairs, stored by color (index 0 = the red
-    // member, 1 = the black member) so that every phase reads them with
-    // compile-time indices: psi, f0, f1, f2
-    T o_psi[2][KP], o_f0[2][KP], o_f1[2][KP], o_f2[2][KP], o_b[2][KP];
-    // staged values of the pairs before they go to LDS
-    T v_phi[KP][2], v_mu[KP][2], v_p[KP][2], v_ps[KP][2];
+    // A block whose whole region lies inside the grid (most blocks of a large
+    // level) takes every position test as passed: no bounds tests on loads and
+    // stores, no tests per face (nf = 4).  The arithmetic is the same in both
+    // forms of the body.
+    const bool inner = x0 >= 0 && y0 >= 0 && x0 + W <= nx && y0 + R <= ny;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};      // EPI 2 partial sums of the thread
+    auto body = [&](auto kind) {
+        constexpr bool kInner = decltype(kind)::value;
+        // own-cell data of the thread's pairs, stored by color (index 0 = the red
+        // member, 1 = the black member) so that every phase reads them with
+        // compile-time indices: psi, f0, f1, f2
+        T o_psi[2][KP], o_f0[2][KP], o_f1[2][KP], o_f2[2][KP], o_b[2][KP];
+        // staged values of the pairs before they go to LDS
+        T v_phi[KP][2], v_mu[KP][2], v_p[KP][2], v_ps[KP][2];
 
-    // 1) issue every global load of the region first ...
+        // 1) issue every global load of the region first ...
 #pragma unroll
-    for (int k = 0; k < KP; ++k) {
-        const int q = tid + k * kThreads;
-        const int r = q / PW, x = 2 * (q % PW);
-        const int gy = y0 + r;
+        for (int k = 0; k < KP; ++k) {
+            const int q = tid + k * kThreads;
+            const int r = q / PW, x = 2 * (q % PW);
+            const int gy = y0 + r;
 #pragma unroll
-        for (int e = 0; e < 2; ++e) {
-            const int gx = x0 + x + e;
-            T phi = 0, mu = 0, p = 0, ps = 0, psi = 0, f0 = 0, f1 = 0, f2 = 0, bs = 0;
-            if (q < NP && gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
-                const int g = gy * nx + gx;
-                phi = ZERO ? T(0) : gload(L.phi, g);
-                mu = ZERO ? T(0) : gload(L.mu, g);
-                p = ZERO ? T(0) : gload(L.p, g) - psh;
-                ps = gload(L.pstar, g);
-                psi = gload(L.psi, g);
-                // the first launch on a coarse level forms f from the restricted residual
-                f1 = gload(RHS ? L.fr1 : L.f1, g);
-                if (LEVEL0) {
-                    f0 = psi;
+            for (int e = 0; e < 2; ++e) {
+                const int gx = x0 + x + e;
+                T phi = 0, mu = 0, p = 0, ps = 0, psi = 0, f0 = 0, f1 = 0, f2 = 0, bs = 0;
+                if (q < NP && (kInner || (gx >= 0 && gx < nx && gy >= 0 && gy < ny))) {
+                    const int g = gy * nx + gx;
+                    phi = ZERO ? T(0) : gload(L.phi, g);
+                    mu = ZERO ? T(0) : gload(L.mu, g);
+                    p = ZERO ? T(0) : gload(L.p, g) - psh;
+                    ps = gload(L.pstar, g);
+                    psi = gload(L.psi, g);
+                    // the first launch on a coarse level forms f from the restricted residual
+                    f1 = gload(RHS ? L.fr1 : L.f1, g);
+                    if (LEVEL0) {
+                        f0 = psi;
+                    } else {
+                        f0 = gload(RHS ? L.fr0 : L.f0, g);
+                        f2 = gload(RHS ? L.fr2 : L.f2, g);
+                    }
+                    if (CORR) bs = gload(L.b, g);
+                    if (PRO) {
+                        const int c = (gy >> 1) * C.nx + (gx >> 1);
+                        phi += gload(C.phi, c) - gload(C.ub0, c);
+                        mu += gload(C.mu, c) - gload(C.ub1, c);
+                        p += gload(C.p, c) - gload(C.ub2, c);
+                    }
+                }
+                v_phi[k][e] = phi;
+                v_mu[k][e] = mu;
+                v_p[k][e] = p;
+                v_ps[k][e] = ps;
+                // member e has color (e + gy) & 1 because x0 + x is even
+                const bool red = ((e + gy) & 1) == 0;
+                if (e == 0) {
+                    o_psi[0][k] = o_psi[1][k] = psi;
+                    o_f0[0][k] = o_f0[1][k] = f0;
+                    o_f1[0][k] = o_f1[1][k] = f1;
+                    o_f2[0][k] = o_f2[1][k] = f2;
+                    o_b[0][k] = o_b[1][k] = bs;
                 } else {
-                    f0 = gload(RHS ? L.fr0 : L.f0, g);
-                    f2 = gload(RHS ? L.fr2 : L.f2, g);
-                }
-                if (CORR) bs = gload(L.b, g);
-                if (PRO) {
-                    const int c = (gy >> 1) * C.nx + (gx >> 1);
-                    phi += gload(C.phi, c) - gload(C.ub0, c);
-                    mu += gload(C.mu, c) - gload(C.ub1, c);
-                    p += gload(C.p, c) - gload(C.ub2, c);
+                    o_b[0][k] = red ? bs : o_b[0][k];
+                    o_b[1][k] = red ? o_b[1][k] : bs;
+                    o_psi[0][k] = red ? psi : o_psi[0][k];
+                    o_f0[0][k] = red ? f0 : o_f0[0][k];
+                    o_f1[0][k] = red ? f1 : o_f1[0][k];
+                    o_f2[0][k] = red ? f2 : o_f2[0][k];
+                    o_psi[1][k] = red ? o_psi[1][k] : psi;
+                    o_f0[1][k] = red ? o_f0[1][k] : f0;
+                    o_f1[1][k] = red ? o_f1[1][k] : f1;
+                    o_f2[1][k] = red ? o_f2[1][k] : f2;
                 }
             }
-            v_phi[k][e] = phi;
-            v_mu[k][e] = mu;
-            v_p[k][e] = p;
-            v_ps[k][e] = ps;
-            // member e has color (e + gy) & 1 because x0 + x is even
-            const bool red = ((e + gy) & 1) == 0;
-            if (e == 0) {
-                o_psi[0][k] = o_psi[1][k] = psi;
-                o_f0[0][k] = o_f0[1][k] = f0;
-                o_f1[0][k] = o_f1[1][k] = f1;
-                o_f2[0][k] = o_f2[1][k] = f2;
-                o_b[0][k] = o_b[1][k] = bs;
-            } else {
-                o_b[0][k] = red ? bs : o_b[0][k];
-                o_b[1][k] = red ? o_b[1][k] : bs;
-                o_psi[0][k] = red ? psi : o_psi[0][k];
-                o_f0[0][k] = red ? f0 : o_f0[0][k];
-                o_f1[0][k] = red ? f1 : o_f1[0][k];
-                o_f2[0][k] = red ? f2 : o_f2[0][k];
-                o_psi[1][k] = red ? o_psi[1][k] : psi;
-                o_f0[1][k] = red ? o_f0[1][k] : f0;
-                o_f1[1][k] = red ? o_f1[1][k] : f1;
-                o_f2[1][k] = red ? o_f2[1][k] : f2;
+        }
+        // 2) ... then stage them in LDS
+#pragma unroll
+        for (int k = 0; k < KP; ++k) {
+            const int q = tid + k * kThreads;
+            if (q >= NP) continue;
+            const int r = q / PW, x = 2 * (q % PW);
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const int w = lds<PW>(r, x + e);
+                s_phi[w] = v_phi[k][e];
+                s_mu[w] = v_mu[k][e];
+                s_p[w] = v_p[k][e];
+                s_ps[w] = v_ps[k][e];
             }
         }
-    }
-    // 2) ... then stage them in LDS
+        __syncthreads();
+
+        const T lam = L.lam, kap = L.kap, gam = L.gamma;
+        const T inv_lam = T(1) / lam;
+
+        if (RHS) {
+            // f += N(u) on every cell within ring H - 1 of the block (the cells
+            // the phases update; their neighbours are in the region)
 #pragma unroll
-    for (int k = 0; k < KP; ++k) {
-        const int q = tid + k * kThreads;
-        if (q >= NP) continue;
-        const int r = q / PW, x = 2 * (q % PW);
+            for (int k = 0; k < KP; ++k) {
+                const int q = tid + k * kThreads;
+                if (q >= NP) continue;
+                const int r = q / PW, xp = 2 * (q % PW);
+                const int gy = y0 + r;
 #pragma unroll
-        for (int e = 0; e < 2; ++e) {
-            const int w = lds<PW>(r, x + e);
-            s_phi[w] = v_phi[k][e];
-            s_mu[w] = v_mu[k][e];
-            s_p[w] = v_p[k][e];
-            s_ps[w] = v_ps[k][e];
+                for (int e = 0; e < 2; ++e) {
+                    const int x = xp + e;
+                    const int gx = x0 + x;
+                    if (!kInner && (gx < 0 || gx >= nx || gy < 0 || gy >= ny)) continue;
+                    const int dx = x < HX ? HX - x : (x >= HX + kTX ? x - (HX + kTX - 1) : 0);
+                    const int dy = r < H ? H - r : (r >= H + kTY ? r - (H + kTY - 1) : 0);
+                    if ((dx > dy ? dx : dy) > H - 1) continue;
+                    const bool red = ((e + gy) & 1) == 0;
+                    const int wc = lds<PW>(r, x);
+                    const T phic = s_phi[wc], muc = s_mu[wc], pc = s_p[wc], psc = s_ps[wc];
+                    T smm = 0, sap = 0, sphi = 0, sp = 0, samu = 0;
+                    auto nb_n = [&](int rr, int xx) {
+                        const int w = lds<PW>(rr, xx);
+                        const T a = T(0.5) * (psc + s_ps[w]);
+                        const T m = T(1) + gam * a * a;
+                        const T dmu = s_mu[w] - muc;
+                        const T dp = s_p[w] - pc;
+                        smm += m * dmu;
+                        sap += a * dp;
+                        sphi += s_phi[w] - phic;
+                        sp += dp;
+                        samu += a * dmu;
+                    };
+                    if (kInner || gx > 0) nb_n(r, x - 1);
+                    if (kInner || gx < nx - 1) nb_n(r, x + 1);
+                    if (kInner || gy > 0) nb_n(r - 1, x);
+                    if (kInner || gy < ny - 1) nb_n(r + 1, x);
+                    // select values, not addresses, so that the arrays stay in registers
+                    const T psi0 = o_psi[0][k], psi1 = o_psi[1][k], b0 = o_b[0][k], b1 = o_b[1][k];
+                    const T fa0 = o_f0[0][k], fb0 = o_f0[1][k], fa1 = o_f1[0][k], fb1 = o_f1[1][k];
+                    const T fa2 = o_f2[0][k], fb2 = o_f2[1][k];
+                    const T psi = red ? psi0 : psi1;
+                    const T bg = red ? b0 : b1;
+                    const T n0 = phic - lam * smm - lam * sap;
+                    const T n1 = muc - nonlin<T, CORR>(phic, psi, bg) + kap * sphi;
+                    const T n2 = lam * sp + lam * gam * samu;
+                    const T f0 = (red ? fa0 : fb0) + n0;
+                    const T f1 = (red ? fa1 : fb1) + n1;
+                    const T f2 = (red ? fa2 : fb2) + n2;
+                    o_f0[0][k] = red ? f0 : fa0;
+                    o_f0[1][k] = red ? fb0 : f0;
+                    o_f1[0][k] = red ? f1 : fa1;
+                    o_f1[1][k] = red ? fb1 : f1;
+                    o_f2[0][k] = red ? f2 : fa2;
+                    o_f2[1][k] = red ? fb2 : f2;
+                    if (r >= H && r < H + kTY && x >= HX && x < HX + kTX) {
+                        const int g = gy * nx + gx;
+                        gstore(L.f0, g, f0);
+                        gstore(L.f1, g, f1);
+                        gstore(L.f2, g, f2);
+                    }
+                }
+            }
+            // the first phase overwrites cells whose values other waves still read here
+            __syncthreads();
         }
-    }
-    __syncthreads();
 
-    const T lam = L.lam, kap = L.kap, gam = L.gamma;
-    const T inv_lam = T(1) / lam;
+        // Per pair and color, once for all phases: the LDS word of the member with
+        // that color, the word of its x - 1 neighbour (the x + 1 neighbour is the
+        // next word: an even member's x neighbours are odd columns, stored after
+        // the row's even ones, and the other way round), its ring distance from the
+        // block (more than any ring outside the grid) and which of its faces are
+        // interior (bits x - 1, x + 1, y - 1, y + 1).  A phase then needs no
+        // geometry of its own.
+        int wcol[2][KP], wlcol[2][KP], dcol[2][KP], fcol[2][KP];
+#pragma unroll
+        for (int k = 0; k < KP; ++k) {
+            const int q = tid + k * kThreads;
+            const int r = q / PW, xp = 2 * (q % PW);
+            const int gy = y0 + r;
+#pragma unroll
+            for (int color = 0; color < 2; ++color) {
+                const int e = (gy & 1) ^ color;         // the pair member with this color
+                const int x = xp + e;
+                const int gx = x0 + x;
+                const bool in = q < NP && (kInner || (gx >= 0 && gx < nx && gy >= 0 && gy < ny));
+                const int dx = x < HX ? HX - x : (x >= HX + kTX ? x - (HX + kTX - 1) : 0);
+                const int dy = r < H ? H - r : (r >= H + kTY ? r - (H + kTY - 1) : 0);
+                dcol[color][k] = in ? (dx > dy ? dx : dy) : H + 1;
+                wcol[color][k] = lds<PW>(r, x);
+                wlcol[color][k] = wcol[color][k] + (e ? -PW : PW - 1);
+                fcol[color][k] = (gx > 0 ? 1 : 0) | (gx < nx - 1 ? 2 : 0) | (gy > 0 ? 4 : 0) |
+                                 (gy < ny - 1 ? 8 : 0);
+            }
+        }
 
-    if (RHS) {
-        // f += N(u) on every cell within ring H - 1 of the block (the cells
-        // the phases update; their neighbours are in the region)
+#pragma unroll
+        for (int ph = 0; ph < 2 * NS; ++ph) {
+            const int color = ph & 1;
+            const int ring = G::X + 2 * NS - 1 - ph;
+#pragma unroll
+            for (int k = 0; k < KP; ++k) {
+                if (dcol[color][k] > ring) continue;
+                const int wc = wcol[color][k], wl = wlcol[color][k], fl = fcol[color][k];
+                const T psc = s_ps[wc];
+                int nf = 0;
+                T sa = 0, sa2 = 0, smmu = 0, sphi = 0, sp = 0, sap = 0, samu = 0;
+                auto nb_acc = [&](int w) {
+                    const T a = T(0.5) * (psc + s_ps[w]);
+                    const T m = T(1) + gam * a * a;
+                    const T munb = s_mu[w];
+                    const T pnb = s_p[w];
+                    nf += 1;
+                    sa += a;
+                    sa2 += a * a;
+                    smmu += m * munb;
+                    sphi += s_phi[w];
+                    sp += pnb;
+                    sap += a * pnb;
+                    samu += a * munb;
+                };
+                // faces in the order x - 1, x + 1, y - 1, y + 1
+                if (kInner) {
+                    nb_acc(wl);
+                    nb_acc(wl + 1);
+                    nb_acc(wc - 2 * PW);
+                    nb_acc(wc + 2 * PW);
+                } else {
+                    if (fl & 1) nb_acc(wl);
+                    if (fl & 2) nb_acc(wl + 1);
+                    if (fl & 4) nb_acc(wc - 2 * PW);
+                    if (fl & 8) nb_acc(wc + 2 * PW);
+                }
+                const T fnf = T(nf);
+                const T inv_nf = nf == 4 ? T(0.25) : (nf == 3 ? T(1) / T(3) : (nf == 2 ? T(0.5) : T(1)));
+                const T phit = s_phi[wc];
+                const T psi = o_psi[color][k];
+                const T f0 = o_f0[color][k];
+                const T f1 = o_f1[color][k];
+                const T f2 = o_f2[color][k];
+                const T base = o_b[color][k];
+                const T dchi = dnonlin<T, CORR>(phit, psi, base);
+                const T chi = nonlin<T, CORR>(phit, psi, base);
+                const T b1 = f0 + lam * smmu + lam * sap;
+                const T b2 = f1 + chi - dchi * phit - kap * sphi;
+                const T b3 = f2 - lam * sp - lam * gam * samu;
+                const T ared = lam * (fnf + gam * (sa2 - sa * sa * inv_nf));
+                const T b1r = b1 + (sa * inv_nf) * b3;
+                const T bb = dchi + kap * fnf;
+                const T inv_det = recip_ge1(T(1) + ared * bb);
+                const T mun = (b2 + bb * b1r) * inv_det;
+                s_phi[wc] = (b1r - ared * b2) * inv_det;
+                s_mu[wc] = mun;
+                s_p[wc] = -(b3 * inv_lam + gam * sa * mun) * inv_nf;
+            }
+            __syncthreads();
+        }
+
+        // write the block into the other copy of u
 #pragma unroll
         for (int k = 0; k < KP; ++k) {
             const int q = tid + k * kThreads;
             if (q >= NP) continue;
             const int r = q / PW, xp = 2 * (q % PW);
+            if (r < H || r >= H + kTY || xp < HX || xp >= HX + kTX) continue;
             const int gy = y0 + r;
 #pragma unroll
             for (int e = 0; e < 2; ++e) {
-                const int x = xp + e;
-                const int gx = x0 + x;
-                if (gx < 0 || gx >= nx || gy < 0 || gy >= ny) continue;
-                const int dx = x < HX ? HX - x : (x >= HX + kTX ? x - (HX + kTX - 1) : 0);
-                const int dy = r < H ? H - r : (r >= H + kTY ? r - (H + kTY - 1) : 0);
-                if ((dx > dy ? dx : dy) > H - 1) continue;
-                const bool red = ((e + gy) & 1) == 0;
-                const int wc = lds<PW>(r, x);
-                const T phic = s_phi[wc], muc = s_mu[wc], pc = s_p[wc], psc = s_ps[wc];
-                T smm = 0, sap = 0, sphi = 0, sp = 0, samu = 0;
-                auto nb_n = [&](int rr, int xx) {
-                    const int w = lds<PW>(rr, xx);
-                    const T a = T(0.5) * (psc + s_ps[w]);
-                    const T m = T(1) + gam * a * a;
-                    const T dmu = s_mu[w] - muc;
-                    const T dp = s_p[w] - pc;
-                    smm += m * dmu;
-                    sap += a * dp;
-                    sphi += s_phi[w] - phic;
-                    sp += dp;
-                    samu += a * dmu;
-                };
-                if (gx > 0) nb_n(r, x - 1);
-                if (gx < nx - 1) nb_n(r, x + 1);
-                if (gy > 0) nb_n(r - 1, x);
-                if (gy < ny - 1) nb_n(r + 1, x);
-                // select values, not addresses, so that the arrays stay in registers
-                const T psi0 = o_psi[0][k], psi1 = o_psi[1][k], b0 = o_b[0][k], b1 = o_b[1][k];
-                const T fa0 = o_f0[0][k], fb0 = o_f0[1][k], fa1 = o_f1[0][k], fb1 = o_f1[1][k];
-                const T fa2 = o_f2[0][k], fb2 = o_f2[1][k];
-                const T psi = red ? psi0 : psi1;
-                const T bg = red ? b0 : b1;
-                const T n0 = phic - lam * smm - lam * sap;
-                const T n1 = muc - nonlin<T, CORR>(phic, psi, bg) + kap * sphi;
-                const T n2 = lam * sp + lam * gam * samu;
-                const T f0 = (red ? fa0 : fb0) + n0;
-                const T f1 = (red ? fa1 : fb1) + n1;
-                const T f2 = (red ? fa2 : fb2) + n2;
-                o_f0[0][k] = red ? f0 : fa0;
-                o_f0[1][k] = red ? fb0 : f0;
-                o_f1[0][k] = red ? f1 : fa1;
-                o_f1[1][k] = red ? fb1 : f1;
-                o_f2[0][k] = red ? f2 : fa2;
-                o_f2[1][k] = red ? fb2 : f2;
-                if (r >= H && r < H + kTY && x >= HX && x < HX + kTX) {
-                    const int g = gy * nx + gx;
-                    gstore(L.f0, g, f0);
-                    gstore(L.f1, g, f1);
-                    gstore(L.f2, g, f2);
-                }
-            }
-        }
-        // the first phase overwrites cells whose values other waves still read here
-        __syncthreads();
-    }
-
-    // Per pair and color, once for all phases: the LDS word of the member with
-    // that color, the word of its x - 1 neighbour (the x + 1 neighbour is the
-    // next word: an even member's x neighbours are odd columns, stored after
-    // the row's even ones, and the other way round), its ring distance from the
-    // block (more than any ring outside the grid) and which of its faces are
-    // interior (bits x - 1, x + 1, y - 1, y + 1).  A phase then needs no
-    // geometry of its own.
-    int wcol[2][KP], wlcol[2][KP], dcol[2][KP], fcol[2][KP];
-#pragma unroll
-    for (int k = 0; k < KP; ++k) {
-        const int q = tid + k * kThreads;
-        const int r = q / PW, xp = 2 * (q % PW);
-        const int gy = y0 + r;
-#pragma unroll
-        for (int color = 0; color < 2; ++color) {
-            const int e = (gy & 1) ^ color;         // the pair member with this color
-            const int x = xp + e;
-            const int gx = x0 + x;
-            const bool in = q < NP && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
-            const int dx = x < HX ? HX - x : (x >= HX + kTX ? x - (HX + kTX - 1) : 0);
-            const int dy = r < H ? H - r : (r >= H + kTY ? r - (H + kTY - 1) : 0);
-            dcol[color][k] = in ? (dx > dy ? dx : dy) : H + 1;
-            wcol[color][k] = lds<PW>(r, x);
-            wlcol[color][k] = wcol[color][k] + (e ? -PW : PW - 1);
-            fcol[color][k] = (gx > 0 ? 1 : 0) | (gx < nx - 1 ? 2 : 0) | (gy > 0 ? 4 : 0) |
-                             (gy < ny - 1 ? 8 : 0);
-        }
-    }
-
-#pragma unroll
-    for (int ph = 0; ph < 2 * NS; ++ph) {
-        const int color = ph & 1;
-        const int ring = G::X + 2 * NS - 1 - ph;
-#pragma unroll
-        for (int k = 0; k < KP; ++k) {
-            if (dcol[color][k] > ring) continue;
-            const int wc = wcol[color][k], wl = wlcol[color][k], fl = fcol[color][k];
-            const T psc = s_ps[wc];
-            int nf = 0;
-            T sa = 0, sa2 = 0, smmu = 0, sphi = 0, sp = 0, sap = 0, samu = 0;
-            auto nb_acc = [&](int w) {
-                const T a = T(0.5) * (psc + s_ps[w]);
-                const T m = T(1) + gam * a * a;
-                const T munb = s_mu[w];
-                const T pnb = s_p[w];
-                nf += 1;
-                sa += a;
-                sa2 += a * a;
-                smmu += m * munb;
-                sphi += s_phi[w];
-                sp += pnb;
-                sap += a * pnb;
-                samu += a * munb;
-            };
-            // faces in the order x - 1, x + 1, y - 1, y + 1
-            if (fl & 1) nb_acc(wl);
-            if (fl & 2) nb_acc(wl + 1);
-            if (fl & 4) nb_acc(wc - 2 * PW);
-            if (fl & 8) nb_acc(wc + 2 * PW);
-            const T fnf = T(nf);
-            const T inv_nf = nf == 4 ? T(0.25) : (nf == 3 ? T(1) / T(3) : (nf == 2 ? T(0.5) : T(1)));
-            const T phit = s_phi[wc];
-            const T psi = o_psi[color][k];
-            const T f0 = o_f0[color][k];
-            const T f1 = o_f1[color][k];
-            const T f2 = o_f2[color][k];
-            const T base = o_b[color][k];
-            const T dchi = dnonlin<T, CORR>(phit, psi, base);
-            const T chi = nonlin<T, CORR>(phit, psi, base);
-            const T b1 = f0 + lam * smmu + lam * sap;
-            const T b2 = f1 + chi - dchi * phit - kap * sphi;
-            const T b3 = f2 - lam * sp - lam * gam * samu;
-            const T ared = lam * (fnf + gam * (sa2 - sa * sa * inv_nf));
-            const T b1r = b1 + (sa * inv_nf) * b3;
-            const T bb = dchi + kap * fnf;
-            const T inv_det = recip_ge1(T(1) + ared * bb);
-            const T mun = (b2 + bb * b1r) * inv_det;
-            s_phi[wc] = (b1r - ared * b2) * inv_det;
-            s_mu[wc] = mun;
-            s_p[wc] = -(b3 * inv_lam + gam * sa * mun) * inv_nf;
-        }
-        __syncthreads();
-    }
-
-    // write the block into the other copy of u
-#pragma unroll
-    for (int k = 0; k < KP; ++k) {
-        const int q = tid + k * kThreads;
-        if (q >= NP) continue;
-        const int r = q / PW, xp = 2 * (q % PW);
-        if (r < H || r >= H + kTY || xp < HX || xp >= HX + kTX) continue;
-        const int gy = y0 + r;
-#pragma unroll
-        for (int e = 0; e < 2; ++e) {
-            const int gx = x0 + xp + e;
-            if (gx >= nx || gy >= ny) continue;
-            const int g = gy * nx + gx;
-            const int w = lds<PW>(r, xp + e);
-            gstore(L.phi_alt, g, s_phi[w]);
-            gstore(L.mu_alt, g, s_mu[w]);
-            gstore(L.p_alt, g, s_p[w]);
-        }
-    }
-
-    if (EPI == 0) return;
-
-    // residual on the block.  Slot s (512 per block) is the pair of
-    // horizontally adjacent fine cells in row cy of coarse cell (cxl, cyl);
-    // slots s and s ^ 32 -- lanes l and l ^ 32 of one wave -- are the two rows
-    // of the same coarse cell.
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int j = 0; j < (kSlots + kThreads - 1) / kThreads; ++j) {
-        const int slot = tid + j * kThreads;
-        if (slot >= kSlots) break;      // whole waves
-        const int cxl = slot & 31, cy = (slot >> 5) & 1, cyl = slot >> 6;   // 32 x 8 coarse cells
-        T su[3] = {0, 0, 0}, sr[3] = {0, 0, 0}, sb = 0;
-        const int gcx = (x0 + HX) / 2 + cxl, gcy = (y0 + H) / 2 + cyl;
-        const bool live = 2 * gcx < nx && 2 * gcy < ny;
-        if (live) {
-            for (int cx = 0; cx < 2; ++cx) {
-                const int r = H + 2 * cyl + cy, x = HX + 2 * cxl + cx;
-                const int gx = x0 + x, gy = y0 + r;
+                const int gx = x0 + xp + e;
+                if (!kInner && (gx >= nx || gy >= ny)) continue;
                 const int g = gy * nx + gx;
-                const int wc = lds<PW>(r, x);
-                const T phic = s_phi[wc], muc = s_mu[wc], pc = s_p[wc], psc = s_ps[wc];
-                T smm = 0, sap = 0, sphi = 0, sp = 0, samu = 0;
-                auto nb_res = [&](int rr, int xx) {
-                    const int w = lds<PW>(rr, xx);
-                    const T a = T(0.5) * (psc + s_ps[w]);
-                    const T m = T(1) + gam * a * a;
-                    const T dmu = s_mu[w] - muc;
-                    const T dp = s_p[w] - pc;
-                    smm += m * dmu;
-                    sap += a * dp;
-                    sphi += s_phi[w] - phic;
-                    sp += dp;
-                    samu += a * dmu;
-                };
-                if (gx > 0) nb_res(r, x - 1);
-                if (gx < nx - 1) nb_res(r, x + 1);
-                if (gy > 0) nb_res(r - 1, x);
-                if (gy < ny - 1) nb_res(r + 1, x);
-                const T psi = gload(L.psi, g);
-                const T f0 = LEVEL0 ? psi : gload(L.f0, g);
-                const T f1 = gload(L.f1, g);
-                const T f2 = LEVEL0 ? T(0) : gload(L.f2, g);
-                const T bg = CORR ? gload(L.b, g) : T(0);
-                const T r0 = f0 - (phic - lam * smm - lam * sap);
-                const T r1 = f1 - (muc - nonlin<T, CORR>(phic, psi, bg) + kap * sphi);
-                const T r2 = f2 - (lam * sp + lam * gam * samu);
-                if (EPI == 1) {
-                    sr[0] += r0;
-                    sr[1] += r1;
-                    sr[2] += r2;
-                    su[0] += phic;
-                    su[1] += muc;
-                    su[2] += pc;
-                    sb += bg;
-                } else {
-                    acc[0] += double(r0) * double(r0);
-                    acc[1] += double(r1) * double(r1);
-                    acc[2] += double(r2) * double(r2);
-                    acc[3] += double(pc);
+                const int w = lds<PW>(r, xp + e);
+                gstore(L.phi_alt, g, s_phi[w]);
+                gstore(L.mu_alt, g, s_mu[w]);
+                gstore(L.p_alt, g, s_p[w]);
+            }
+        }
+
+        if (EPI == 0) return;
+
+        // residual on the block.  Slot s (512 per block) is the pair of
+        // horizontally adjacent fine cells in row cy of coarse cell (cxl, cyl);
+        // slots s and s ^ 32 -- lanes l and l ^ 32 of one wave -- are the two rows
+        // of the same coarse cell.
+#pragma unroll
+        for (int j = 0; j < (kSlots + kThreads - 1) / kThreads; ++j) {
+            const int slot = tid + j * kThreads;
+            if (slot >= kSlots) break;      // whole waves
+            const int cxl = slot & 31, cy = (slot >> 5) & 1, cyl = slot >> 6;   // 32 x 8 coarse cells
+            T su[3] = {0, 0, 0}, sr[3] = {0, 0, 0}, sb = 0;
+            const int gcx = (x0 + HX) / 2 + cxl, gcy = (y0 + H) / 2 + cyl;
+            const bool live = kInner || (2 * gcx < nx && 2 * gcy < ny);
+            if (live) {
+                for (int cx = 0; cx < 2; ++cx) {
+                    const int r = H + 2 * cyl + cy, x = HX + 2 * cxl + cx;
+                    const int gx = x0 + x, gy = y0 + r;
+                    const int g = gy * nx + gx;
+                    const int wc = lds<PW>(r, x);
+                    const T phic = s_phi[wc], muc = s_mu[wc], pc = s_p[wc], psc = s_ps[wc];
+                    T smm = 0, sap = 0, sphi = 0, sp = 0, samu = 0;
+                    auto nb_res = [&](int rr, int xx) {
+                        const int w = lds<PW>(rr, xx);
+                        const T a = T(0.5) * (psc + s_ps[w]);
+                        const T m = T(1) + gam * a * a;
+                        const T dmu = s_mu[w] - muc;
+                        const T dp = s_p[w] - pc;
+                        smm += m * dmu;
+                        sap += a * dp;
+                        sphi += s_phi[w] - phic;
+                        sp += dp;
+                        samu += a * dmu;
+                    };
+                    if (kInner || gx > 0) nb_res(r, x - 1);
+                    if (kInner || gx < nx - 1) nb_res(r, x + 1);
+                    if (kInner || gy > 0) nb_res(r - 1, x);
+                    if (kInner || gy < ny - 1) nb_res(r + 1, x);
+                    const T psi = gload(L.psi, g);
+                    const T f0 = LEVEL0 ? psi : gload(L.f0, g);
+                    const T f1 = gload(L.f1, g);
+                    const T f2 = LEVEL0 ? T(0) : gload(L.f2, g);
+                    const T bg = CORR ? gload(L.b, g) : T(0);
+                    const T r0 = f0 - (phic - lam * smm - lam * sap);
+                    const T r1 = f1 - (muc - nonlin<T, CORR>(phic, psi, bg) + kap * sphi);
+                    const T r2 = f2 - (lam * sp + lam * gam * samu);
+                    if (EPI == 1) {
+                        sr[0] += r0;
+                        sr[1] += r1;
+                        sr[2] += r2;
+                        su[0] += phic;
+                        su[1] += muc;
+                        su[2] += pc;
+                        sb += bg;
+                    } else {
+                        acc[0] += double(r0) * double(r0);
+                        acc[1] += double(r1) * double(r1);
+                        acc[2] += double(r2) * double(r2);
+                        acc[3] += double(pc);
+                    }
+                }
+            }
+            if (EPI == 1) {
+                // combine the two rows (lane ^ 32), two fields per exchange: lanes
+                // 0-31 then hold r0, r2, mu and lanes 32-63 r1, phi, p of the coarse cell
+                const T w = T(0.25);
+                const T q0 = swap_sum(sr[0], sr[1], true) * w;
+                const T q1 = swap_sum(sr[2], su[0], true) * w;
+                const T q2 = swap_sum(su[1], su[2], true) * w;
+                const T qb = CORR ? rows_sum(sb, true) * w : T(0);
+                if (live) {
+                    const int c = gcy * C.nx + gcx;
+                    // separate conditions, so that no two stores merge into one
+                    // through a selected address
+                    if (cy == 0) gstore(C.fr0, c, q0);
+                    if (cy == 1) gstore(C.fr1, c, q0);
+                    if (cy == 0) gstore(C.fr2, c, q1);
+                    if (cy == 1) gstore(C.phi, c, q1);
+                    if (cy == 1) gstore(C.ub0, c, q1);
+                    if (cy == 0) gstore(C.mu, c, q2);
+                    if (cy == 0) gstore(C.ub1, c, q2);
+                    if (cy == 1) gstore(C.p, c, q2);
+                    if (cy == 1) gstore(C.ub2, c, q2);
+                    if (CORR && cy == 0) gstore(C.b, c, qb);
                 }
             }
         }
-        if (EPI == 1) {
-            // combine the two rows (lane ^ 32), two fields per exchange: lanes
-            // 0-31 then hold r0, r2, mu and lanes 32-63 r1, phi, p of the coarse cell
-            const T w = T(0.25);
-            const T q0 = swap_sum(sr[0], sr[1], true) * w;
-            const T q1 = swap_sum(sr[2], su[0], true) * w;
-            const T q2 = swap_sum(su[1], su[2], true) * w;
-            const T qb = CORR ? rows_sum(sb, true) * w : T(0);
-            if (live) {
-                const int c = gcy * C.nx + gcx;
-                // separate conditions, so that no two stores merge into one
-                // through a selected address
-                if (cy == 0) gstore(C.fr0, c, q0);
-                if (cy == 1) gstore(C.fr1, c, q0);
-                if (cy == 0) gstore(C.fr2, c, q1);
-                if (cy == 1) gstore(C.phi, c, q1);
-                if (cy == 1) gstore(C.ub0, c, q1);
-                if (cy == 0) gstore(C.mu, c, q2);
-                if (cy == 0) gstore(C.ub1, c, q2);
-                if (cy == 1) gstore(C.p, c, q2);
-                if (cy == 1) gstore(C.ub2, c, q2);
-                if (CORR && cy == 0) gstore(C.b, c, qb);
-            }
-        }
-    }
-    if (EPI == 1) return;
+        if (EPI == 1) return;
+    };
+    if (inner)
+        body(std::true_type{});
+    else
+        body(std::false_type{});
+    if (EPI != 2) return;
     // EPI == 2: block partial sums in a fixed order
     for (int off = 32; off > 0; off >>= 1)
         for (int c = 0; c < 4; ++c) acc[c] += __shfl_xor(acc[c], off, 64);
