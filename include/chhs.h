@@ -289,7 +289,9 @@ int chhs_graph_count(chhs_ctx* c, int32_t* graphs);
 
 /* One smoothing step (red then black collective cell update) on one level,
  * and the restriction + FAS coarse right-hand side from level to level+1.
- * Single-instance contexts only; for kernel-level tests. */
+ * Single-instance contexts only; for kernel-level tests.  chhs_smooth runs
+ * the FP64 kernels: CHHS_E_INVAL on a 2D level cut into 64 x 32 tiles (a
+ * mixed-precision context with tile_rows = 32 or an autotuned one). */
 int chhs_smooth(chhs_ctx* c, int32_t level, int32_t nsweeps);
 int chhs_restrict(chhs_ctx* c, int32_t level);
 

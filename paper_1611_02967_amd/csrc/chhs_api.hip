@@ -1225,7 +1225,9 @@ int autotune3(chhs_ctx* c) {
 }
 
 // Picks, per 2D level above the tail, the fastest of: tiles with 256, 512 or
-// 1024 threads (on coarse levels each also 16, 8 and 4 rows high), strips with 1, 2 or 4 times the default segment height.  Runs the
+// 1024 threads (on coarse levels each also 16, 8 and 4 rows high; on the FP32
+// finest level also 64 x 32), strips with 1/4, 1/2, 1, 2 or 4
+// times the default segment height.  Runs the
 // candidates on the workspace as it is (its contents do not matter for the
 // timing and are rewritten by the next setup).
 int autotune(chhs_ctx* c) {
@@ -1249,7 +1251,8 @@ int autotune(chhs_ctx* c) {
             if (l == 0 && ty != chhs::kTileY) continue;     // the finest level has 64 x 16 tiles
             for (int nt : {256, 512, 1024}) cands.push_back({false, nt, 0, ty});
         }
-        // ... or, in FP32 (mixed precision), 64 x 32
+        // ... or, on the FP32 finest level (mixed precision), 64 x 32 (on
+        // coarse FP32 levels they were never faster)
         if (l == 0 && c->mixed)
             for (int nt : {512, 1024}) cands.push_back({false, nt, 0, chhs::kTileYTall});
         bool even = true;
@@ -2217,6 +2220,9 @@ int chhs_smooth(chhs_ctx* c, int32_t level, int32_t nsweeps) {
     if (c == nullptr || c->n_inst != 1 || level < 0 || level >= c->lay.info[0].nlev ||
         nsweeps < 0)
         return CHHS_E_INVAL;
+    // the FP64 tile kernels have no 64 x 32 form (a mixed-precision level cut
+    // for the FP32 ones)
+    if (tiled2d(c) && c->lay.tile_y[level] == chhs::kTileYTall) return CHHS_E_INVAL;
     smooth_steps(c, level, nsweeps, nullptr, level == 0 ? CHHS_K_PRE0 : CHHS_K_COARSE);
     if (c->cur[level] != 0) {
         // the single instance's level: make the result copy 0 again

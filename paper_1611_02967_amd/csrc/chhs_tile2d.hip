@@ -494,7 +494,8 @@ void launch_ty(const Batch<T>& b, const TileTask* t, int nt, int threads, double
                            dim3(256), 0, st, b, t, nt, partial);
 }
 
-// Finest-level variants (LEVEL0, ZERO) exist for 64 x 16 tiles only.
+// 64 x 32 tiles exist for the FP32 (CORR) finest level only (no RHS form);
+// the finest-level variants (LEVEL0, ZERO) for 64 x 16 and 64 x 32 tiles only.
 template <typename T, bool LEVEL0, int NS, int EPI, bool PRO, bool CORR, bool RHS = false,
           bool ZERO = false>
 void launch_one(const Batch<T>& b, const TileTask* t, int nt, int threads, int ty, double* partial,

@@ -191,3 +191,16 @@ def test_tall_finest_tiles_solve_the_same_steps(chhs, name):
         for ht, hs in zip(tall, single):
             for k in ("phi", "mu", "p"):
                 assert np.array_equal(_unpack(ht[k], shapes)[0], hs[k].reshape(shapes[0])), k
+
+
+def test_fp64_smoothing_refuses_tall_tiles(chhs):
+    """A mixed-precision context whose finest level is cut into 64 x 32 tiles
+    (FP32 kernels only) refuses chhs_smooth there (the FP64 tile kernels have
+    no such form) and still smooths the coarse levels."""
+    prob = chhs.make_problem((128, 128), 1.0 / 128, 0.05, 1.0, 1e-3)
+    sv = chhs.Solver(prob, chhs.chhs_default_opts(precision=1, tile_rows=32))
+    phi = uniform_field((128, 128), 4700, amp=0.1).ravel()
+    sv.setup_step(dev(phi), dev(phi), dev(np.zeros(phi.size)), dev(np.zeros(phi.size)))
+    with pytest.raises(chhs.ChhsError):
+        sv.smooth(0, 1)
+    sv.smooth(1, 1)
