@@ -102,8 +102,10 @@ typedef struct chhs_problem {
  * level (the choice then depends on the device; results agree to rounding).
  * 2D (nu1, nu2 >= 1): tiles of 256, 512 and 1024 threads (on coarse levels
  * each with 16, 8 and 4 rows; on the FP32 finest level also 64 x 32 tiles of
- * 512 and 1024 threads) and strips of 1/4, 1/2, 1, 2 and 4 times the
- * default segment height.  3D: the fused step or the per-cell kernels.
+ * 512 and 1024 threads; the pre- and post-smoothing launches of a tile
+ * height each take their fastest block size) and strips of 1/4, 1/2, 1, 2
+ * and 4 times the default segment height.  3D: the fused step or the
+ * per-cell kernels.
  * order = 2 (default; 0 means the same) solves the second-order scheme
  * (2.4)-(2.7).  order = 1 solves instead the first-order convex-splitting step
  * that Remark 2.2 names as a way to obtain phi^1 from phi^0 (its form is cited,
@@ -271,8 +273,9 @@ int chhs_level_count(chhs_ctx* c, int32_t* levels);
 int chhs_level_shape(chhs_ctx* c, int32_t level, int32_t* nxyz3);
 
 /* The smoothing kernel the V-cycle uses on level `level` (counted from the
- * finest) of the batch: out3[0] = 0 square tiles (out3[1] = threads per block),
- * 1 row-streaming strips (out3[1] = rows per segment), 2 per-cell kernels (one
+ * finest) of the batch: out3[0] = 0 square tiles (out3[1] = threads per block
+ * of the pre-smoothing launches; the autotuner may give the post-smoothing
+ * launches another block size), 1 row-streaming strips (out3[1] = rows per segment), 2 per-cell kernels (one
  * launch per color), 3 inside the one-workgroup coarse tail for every instance
  * (out3[1] = 0), 4 fused 3D steps by z marching (out3[1] = planes per segment);
  * out3[2] = blocks per launch (0 for the tail).  Reflects the autotuner's

@@ -75,6 +75,7 @@ struct Layout {
     bool z3[kMaxLevels] = {};
     bool strip[kMaxLevels] = {};            // level smoothed by the row-streaming kernel
     int tile_threads[kMaxLevels] = {};      // tiles: threads per block, 0 = by the tile count
+    int tile_threads_post[kMaxLevels] = {}; // ... of the post-smoothing launches (0 = the same)
     int tile_y[kMaxLevels] = {};            // tile height of the level's tasks (T)
     int tile_y_all[kMaxLevels] = {};        // tile height of the tasks over every instance (Tall)
     size_t cap_T[kMaxLevels] = {};          // capacity of T: tasks of the smallest tile height
@@ -907,7 +908,7 @@ Hier<float> hier32(chhs_ctx* c) { return {c->ddesc32, &c->lay.desc32, c->cur32, 
 template <typename T>
 void tiled(chhs_ctx* c, const Hier<T>& H, bool all, int l, int ns, int epi, bool pro,
            const int* active, int cls, bool rhs = false, const double* pshift = nullptr,
-           bool zero = false) {
+           bool zero = false, bool post = false) {
     Batch<T> b = make_batch(H.dev, H.cur, l, active);
     b.pshift = pshift;
     const bool level0 = std::is_same<T, double>::value && l == 0;
@@ -919,8 +920,10 @@ void tiled(chhs_ctx* c, const Hier<T>& H, bool all, int l, int ns, int epi, bool
             chhs::launch_stream2d<T>(b, st.dev, st.n, level0, ns, epi, pro, zero, part, c->stream);
         } else {
             const Table<TileTask>& tt = all ? c->Tall[l] : c->T[l];
+            const int* thr = post && c->lay.tile_threads_post[l] > 0 ? c->lay.tile_threads_post
+                                                                     : c->lay.tile_threads;
             chhs::launch_tile2d<T>(b, tt.dev, tt.n, level0, ns, epi, pro,
-                                   tile_block(all ? 0 : c->lay.tile_threads[l], tt.n), rhs,
+                                   tile_block(all ? 0 : thr[l], tt.n), rhs,
                                    all ? c->lay.tile_y_all[l] : c->lay.tile_y[l], zero, part,
                                    c->stream);
         }
@@ -1088,7 +1091,8 @@ void enqueue_vcycle(chhs_ctx* c, const Hier<T>& H, bool zero_corr = true) {
                 const int k = rem >= 2 ? 2 : 1;
                 rem -= k;
                 const bool norm = kPlain && d == 0 && rem == 0 && c->fused_norm;
-                tiled(c, H, false, d, k, norm ? 2 : 0, first, act, post_cls);
+                tiled(c, H, false, d, k, norm ? 2 : 0, first, act, post_cls, false, nullptr, false,
+                      true);
                 first = false;
             }
         } else {
@@ -1116,12 +1120,15 @@ void enqueue_vcycle(chhs_ctx* c, const Hier<T>& H, bool zero_corr = true) {
 // ---- autotuning of the 2D smoothing kernels ----------------------------------------------
 
 // Device time (ms) of one level's pre- and post-smoothing launches as a V-cycle
-// issues them, the best of `reps` repetitions.
+// issues them, the best of `reps` repetitions; *pre and *post get the best
+// time of each part.
 template <typename T>
-float time_level(chhs_ctx* c, const Hier<T>& H, int l, int reps, hipEvent_t ea, hipEvent_t eb) {
+float time_level(chhs_ctx* c, const Hier<T>& H, int l, int reps, hipEvent_t ea, hipEvent_t em,
+                 hipEvent_t eb, float* pre, float* post) {
     const chhs_opts& o = c->opts;
     const bool norm = std::is_same<T, double>::value && l == 0 && c->fused_norm;
     float best = 1e30f;
+    *pre = *post = 1e30f;
     for (int r = 0; r < reps; ++r) {
         if (hipEventRecord(ea, c->stream) != hipSuccess) return -1.0f;
         // the level's right-hand side: formed by its first tiled launch, or
@@ -1142,19 +1149,26 @@ float time_level(chhs_ctx* c, const Hier<T>& H, int l, int reps, hipEvent_t ea, 
         }
         tiled(c, H, false, l, rem, 1, false, nullptr, CHHS_K_PRE0, rhs && first, nullptr,
               zero && first);
+        if (hipEventRecord(em, c->stream) != hipSuccess) return -1.0f;
         rem = nu_post(o, l);
         bool pro = o.prolong != 1;
         while (rem > 0) {
             const int k = rem >= 2 ? 2 : 1;
             rem -= k;
-            tiled(c, H, false, l, k, norm && rem == 0 ? 2 : 0, pro, nullptr, CHHS_K_POST0);
+            tiled(c, H, false, l, k, norm && rem == 0 ? 2 : 0, pro, nullptr, CHHS_K_POST0, false,
+                  nullptr, false, true);
             pro = false;
         }
         if (hipEventRecord(eb, c->stream) != hipSuccess || hipEventSynchronize(eb) != hipSuccess)
             return -1.0f;
-        float ms = 0.0f;
-        if (hipEventElapsedTime(&ms, ea, eb) != hipSuccess) return -1.0f;
+        float ms = 0.0f, m1 = 0.0f, m2 = 0.0f;
+        if (hipEventElapsedTime(&ms, ea, eb) != hipSuccess ||
+            hipEventElapsedTime(&m1, ea, em) != hipSuccess ||
+            hipEventElapsedTime(&m2, em, eb) != hipSuccess)
+            return -1.0f;
         best = std::min(best, ms);
+        *pre = std::min(*pre, m1);
+        *post = std::min(*post, m2);
     }
     if (H.cur[l] != 0) restore_copy0(c, H, l);
     return best;
@@ -1226,15 +1240,18 @@ int autotune3(chhs_ctx* c) {
 
 // Picks, per 2D level above the tail, the fastest of: tiles with 256, 512 or
 // 1024 threads (on coarse levels each also 16, 8 and 4 rows high; on the FP32
-// finest level also 64 x 32), strips with 1/4, 1/2, 1, 2 or 4
+// finest level also 64 x 32), the pre- and the post-smoothing launches each
+// with the block size that is fastest for it, or strips with 1/4, 1/2, 1, 2 or 4
 // times the default segment height.  Runs the
 // candidates on the workspace as it is (its contents do not matter for the
 // timing and are rewritten by the next setup).
 int autotune(chhs_ctx* c) {
     Layout& L = c->lay;
-    hipEvent_t ea = nullptr, eb = nullptr;
-    if (hipEventCreate(&ea) != hipSuccess || hipEventCreate(&eb) != hipSuccess) {
+    hipEvent_t ea = nullptr, em = nullptr, eb = nullptr;
+    if (hipEventCreate(&ea) != hipSuccess || hipEventCreate(&em) != hipSuccess ||
+        hipEventCreate(&eb) != hipSuccess) {
         if (ea) (void)hipEventDestroy(ea);
+        if (em) (void)hipEventDestroy(em);
         return CHHS_E_HIP;
     }
     const chhs_opts saved = c->opts;
@@ -1281,6 +1298,7 @@ int autotune(chhs_ctx* c) {
         auto apply = [&](const Cand& k) -> int {
             L.strip[l] = k.strip;
             L.tile_threads[l] = k.threads;
+            L.tile_threads_post[l] = 0;
             if (!k.strip) {
                 if (k.ty == L.tile_y[l]) return CHHS_OK;
                 // re-cut the level's tiles (same instance order as the plan)
@@ -1303,22 +1321,44 @@ int autotune(chhs_ctx* c) {
                                    hipMemcpyHostToDevice, c->stream));
             return CHHS_OK;
         };
-        float best = 1e30f;
-        int pick = 0;
+        std::vector<float> t_pre(cands.size()), t_post(cands.size());
         for (int k = 0; k < int(cands.size()) && rc == CHHS_OK; ++k) {
             rc = apply(cands[k]);
             if (rc) break;
-            const float ms = c->mixed ? time_level(c, hier32(c), l, 3, ea, eb)
-                                      : time_level(c, hier64(c), l, 3, ea, eb);
+            const float ms = c->mixed
+                                 ? time_level(c, hier32(c), l, 3, ea, em, eb, &t_pre[k], &t_post[k])
+                                 : time_level(c, hier64(c), l, 3, ea, em, eb, &t_pre[k], &t_post[k]);
             if (ms < 0.0f) rc = CHHS_E_HIP;
-            if (ms >= 0.0f && ms < best) {
-                best = ms;
+        }
+        if (rc) break;
+        // strips by their pre + post time; tiles per height by the fastest
+        // pre-smoothing block size plus the fastest post-smoothing one (the
+        // same tasks, so the two launches may take different block sizes)
+        float best = 1e30f;
+        int pick = 0, pick_post = -1;
+        for (int k = 0; k < int(cands.size()); ++k) {
+            if (cands[k].strip) {
+                if (t_pre[k] + t_post[k] < best) {
+                    best = t_pre[k] + t_post[k];
+                    pick = k;
+                    pick_post = -1;
+                }
+                continue;
+            }
+            int kq = k;
+            for (int j = 0; j < int(cands.size()); ++j)
+                if (!cands[j].strip && cands[j].ty == cands[k].ty && t_post[j] < t_post[kq]) kq = j;
+            if (t_pre[k] + t_post[kq] < best) {
+                best = t_pre[k] + t_post[kq];
                 pick = k;
+                pick_post = kq;
             }
         }
-        if (rc == CHHS_OK) rc = apply(cands[pick]);
+        rc = apply(cands[pick]);
+        if (rc == CHHS_OK && pick_post >= 0) L.tile_threads_post[l] = cands[pick_post].threads;
     }
     (void)hipEventDestroy(ea);
+    (void)hipEventDestroy(em);
     (void)hipEventDestroy(eb);
     c->opts = saved;
     if (rc) return rc;
