@@ -244,12 +244,23 @@ def make_pool(workers):
     return mp.get_context("fork").Pool(workers)
 
 
-def oracle_sample(phi_prev, phi_cur, mu, p, w, cycles_per_step):
-    """Time the oracle on a bounded sample of one 2D step: setup, one V-cycle
-    and one residual evaluation; return (cell-updates/s estimate, description)."""
+def oracle_sample(phi_prev, phi_cur, mu, p, w, cycles_per_step, max_cells=1 << 22):
+    """Time the oracle on a bounded sample of one step: setup, three V-cycles
+    and one residual evaluation; return (cell-updates/s estimate, description,
+    wall seconds).  Grids above max_cells are sampled on their leading box of
+    halved extents (same spacing h) so that the sample stays within tens of
+    seconds of CPU work; the oracle's cost per cell does not depend on the
+    grid's size."""
     import numpy as np
     from oracle import fas, scheme
-    n = phi_cur.shape[-1]
+    grid = phi_cur.shape
+    n = grid[-1]
+    k = 0
+    while int(np.prod([e >> k for e in grid])) > max_cells:
+        k += 1
+    if k:
+        box = tuple(slice(0, e >> k) for e in grid)
+        phi_prev, phi_cur, mu, p = (np.ascontiguousarray(a[box]) for a in (phi_prev, phi_cur, mu, p))
     prm = scheme.Params(eps=w["eps"], gamma=w["gamma"], s=w["s"], h=1.0 / n)
     t0 = time.perf_counter()
     phi_star, f = scheme.step_rhs(phi_prev, phi_cur, prm)
@@ -266,7 +277,9 @@ def oracle_sample(phi_prev, phi_cur, mu, p, w, cycles_per_step):
     t3 = time.perf_counter()
     t_cycle = (t3 - t2) / ncyc
     t_step = (t1 - t0) + (t2 - t1) * (cycles_per_step + 1) + t_cycle * cycles_per_step
-    desc = (f"oracle on the first timed step's input at {n}^2: setup {t1 - t0:.2f}s, one "
+    where = ("x".join(str(e) for e in phi_cur.shape) + " leading box of " if k else "") + \
+        "x".join(str(e) for e in grid)
+    desc = (f"oracle on the first timed step's input at {where}: setup {t1 - t0:.2f}s, one "
             f"residual {t2 - t1:.2f}s, {ncyc} V(2,2) cycles {t3 - t2:.2f}s; step time = setup + "
             f"{cycles_per_step:.2f} x (cycle + residual) + residual, with the GPU's mean "
             f"V-cycles per step")

@@ -1119,6 +1119,30 @@ void enqueue_vcycle(chhs_ctx* c, const Hier<T>& H, bool zero_corr = true) {
 
 // ---- autotuning of the 2D smoothing kernels ----------------------------------------------
 
+// Keeps the device busy for about `ticks` periods of the constant-rate wall
+// clock (bounded wait, one wave).  Launched before a timed sequence, it lets the
+// host enqueue the whole sequence before the device reaches it, so the events
+// time the kernels back to back (as a captured graph replays them) rather than
+// the host's launch rate.
+__global__ __launch_bounds__(64) void k_spin(long long ticks) {
+    const long long t0 = wall_clock64();
+    while (wall_clock64() - t0 < ticks) __builtin_amdgcn_s_sleep(8);
+}
+
+// Enqueues ~200 us of k_spin on the context's stream.
+int spin_ahead(chhs_ctx* c) {
+    static thread_local int rate_khz = 0;
+    if (rate_khz <= 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess ||
+            rate_khz <= 0)
+            rate_khz = 100000;      // the 100 MHz clock of gfx9
+    }
+    hipLaunchKernelGGL(k_spin, dim3(1), dim3(64), 0, c->stream, (long long)rate_khz / 5);
+    return check_launch();
+}
+
 // Device time (ms) of one level's pre- and post-smoothing launches as a V-cycle
 // issues them, the best of `reps` repetitions; *pre and *post get the best
 // time of each part.
@@ -1130,7 +1154,7 @@ float time_level(chhs_ctx* c, const Hier<T>& H, int l, int reps, hipEvent_t ea, 
     float best = 1e30f;
     *pre = *post = 1e30f;
     for (int r = 0; r < reps; ++r) {
-        if (hipEventRecord(ea, c->stream) != hipSuccess) return -1.0f;
+        if (spin_ahead(c) != CHHS_OK || hipEventRecord(ea, c->stream) != hipSuccess) return -1.0f;
         // the level's right-hand side: formed by its first tiled launch, or
         // by a separate launch before strips
         const bool rhs = l > 0 && !c->lay.strip[l];
@@ -1182,7 +1206,7 @@ float time_level3(chhs_ctx* c, const Hier<T>& H, int l, int reps, hipEvent_t ea,
     const bool bil = c->opts.prolong == 1;
     float best = 1e30f;
     for (int r = 0; r < reps; ++r) {
-        if (hipEventRecord(ea, c->stream) != hipSuccess) return -1.0f;
+        if (spin_ahead(c) != CHHS_OK || hipEventRecord(ea, c->stream) != hipSuccess) return -1.0f;
         // nu1 steps, the prolongation (a launch of its own unless the first
         // fused post step takes it), nu2 steps
         for (int s = 0; s < n1 + n2; ++s) {
