@@ -1747,11 +1747,12 @@ int setup(chhs_ctx* c, const double* phi_prev, const double* phi_cur, const doub
         chhs::launch_fill_int(c->cycles, c->n_inst, 0, c->stream);
         chhs::launch_copy_int(c->act_cycle, c->act_next, c->n_inst, c->stream);
         // the plain path forms the initial residual's norm partials in the same pass
+        // (mixed precision: the FP32 frozen fields of the finest level too)
+        const Batch<float> f32 = c->mixed ? batch32(c, 0, nullptr) : Batch<float>{};
         chhs::launch_setup(dim, batch(c, 0, nullptr), c->A[0].dev, c->A[0].n, c->dinfo, phi_prev,
-                           phi_cur, mu, p, c->mixed ? nullptr : c->partial, c->stream);
+                           phi_cur, mu, p, c->mixed ? nullptr : c->partial,
+                           c->mixed ? &f32 : nullptr, c->stream);
         if (c->mixed) {
-            chhs::launch_mixed_frozen(batch(c, 0, nullptr), batch32(c, 0, nullptr), c->A[0].dev,
-                                      c->A[0].n, c->stream);
             for (int l = 0; l < c->lay.chain_from; ++l)
                 chhs::launch_restrict_frozen(dim, batch32(c, l, nullptr), c->A[l + 1].dev,
                                              c->A[l + 1].n, c->stream);

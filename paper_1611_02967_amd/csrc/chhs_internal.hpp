@@ -148,10 +148,12 @@ struct Batch {
 
 // ---- per-cell kernels (chhs_kernels.hip); dim is 2 or 3 ----------------------------
 // With partial: also the norm partials of the initial guess's residual, as
-// launch_residual_partials gives them (one per task).
+// launch_residual_partials gives them (one per task).  With frozen32 (mixed
+// precision): also phi_* and phi^m rounded to FP32 on the finest level of that
+// hierarchy (its copy 0).
 void launch_setup(int dim, const Batch<double>& b, const CellTask* t, int nt, const InstInfo* info,
                   const double* phi_prev, const double* phi_cur, const double* mu,
-                  const double* p, double* partial, hipStream_t st);
+                  const double* p, double* partial, const Batch<float>* frozen32, hipStream_t st);
 // FP64 overloads act on the plain form, FP32 overloads on the correction form
 // of the mixed-precision inner solve (restriction then also averages b).
 void launch_restrict_frozen(int dim, const Batch<double>& b, const CellTask* t, int nt,
@@ -186,14 +188,12 @@ void launch_prolong(int dim, const Batch<double>& b, const CellTask* t, int nt, 
                     hipStream_t st);
 void launch_prolong(int dim, const Batch<float>& b, const CellTask* t, int nt, bool bilinear,
                     hipStream_t st);
-// Mixed precision (finest level): FP32 copies of phi_*, phi^m; a zero FP32
-// correction; the FP64 outer step u' = u (+ e), R = f - N(u') written as u'
-// (other FP64 copy), R and b = phi' in FP32, and norm partials (as
-// launch_residual_partials); an instance inactive now but flagged in
-// was_active (its flags of the previous refinement; nullptr: every inactive
-// instance) copies its iterate into the other copy.
-void launch_mixed_frozen(const Batch<double>& b64, const Batch<float>& b32, const CellTask* t,
-                         int nt, hipStream_t st);
+// Mixed precision (finest level): a zero FP32 correction; the FP64 outer step
+// u' = u (+ e), R = f - N(u') written as u' (other FP64 copy), R and b = phi'
+// in FP32, and norm partials (as launch_residual_partials); an instance
+// inactive now but flagged in was_active (its flags of the previous
+// refinement; nullptr: every inactive instance) copies its iterate into the
+// other copy.
 void launch_zero_correction(const Batch<float>& b32, const CellTask* t, int nt, hipStream_t st);
 // The same outer step on 2D finest levels, by row marching: task = window of
 // kMarchCols columns (StripTask::sx) x rows [y0, y1); partial[task] gets the

@@ -44,7 +44,8 @@ __global__ __launch_bounds__(kBlock) void k_setup(Batch<double> b, const CellTas
                                                   const double* __restrict__ phi_prev,
                                                   const double* __restrict__ phi_cur,
                                                   const double* __restrict__ mu,
-                                                  const double* __restrict__ p, double* partial) {
+                                                  const double* __restrict__ p, double* partial,
+                                                  Batch<float> e32) {
     const int task = xcd_task();
     const CellTask tk = t[task];
     const Level<double> L = view_at(b, tk.inst, 0, b.cur);
@@ -86,6 +87,12 @@ __global__ __launch_bounds__(kBlock) void k_setup(Batch<double> b, const CellTas
         const double f1 = first ? -pc : -ps - q * lap;
         L.pstar[idx] = ps;
         L.psi[idx] = pc;
+        if (e32.desc != nullptr) {
+            // the FP32 hierarchy's frozen fields (mixed precision)
+            const Level<float> E = view_at(e32, tk.inst, 0, 0);
+            E.pstar[idx] = float(ps);
+            E.psi[idx] = float(pc);
+        }
         L.f0[idx] = pc;                                   // (2.5): phi^m
         L.f1[idx] = f1;                                   // (2.6): -phi_* - eps^2/4 Lap phi^{m-1}
         L.f2[idx] = 0.0;                                  // (2.7)
@@ -371,19 +378,6 @@ __global__ __launch_bounds__(kBlock) void k_prolong(Batch<T> b, const CellTask* 
 }
 
 // ---- mixed precision: FP64 outer work around the FP32 correction solve ---------------
-
-// FP32 copies of the finest level's frozen data (phi_*, phi^m).
-__global__ __launch_bounds__(kBlock) void k_mixed_frozen(Batch<double> b64, Batch<float> b32,
-                                                         const CellTask* __restrict__ t) {
-    const int task = xcd_task();
-    const CellTask tk = t[task];
-    const Level<double> L = view_at(b64, tk.inst, 0, 0);
-    const Level<float> E = view_at(b32, tk.inst, 0, 0);
-    const int idx = tk.cell0 + threadIdx.x;
-    if (idx >= L.n) return;
-    E.pstar[idx] = float(L.pstar[idx]);
-    E.psi[idx] = float(L.psi[idx]);
-}
 
 // Zero correction on the FP32 finest level (current copy).
 __global__ __launch_bounds__(kBlock) void k_zero_correction(Batch<float> b32,
@@ -863,8 +857,11 @@ inline int blocks_for(int n) { return (n + kBlock - 1) / kBlock; }
 
 void launch_setup(int dim, const Batch<double>& b, const CellTask* t, int nt, const InstInfo* info,
                   const double* phi_prev, const double* phi_cur, const double* mu,
-                  const double* p, double* partial, hipStream_t st) {
-    CHHS_DISPATCH(dim, k_setup, nt, b, t, info, phi_prev, phi_cur, mu, p, partial);
+                  const double* p, double* partial, const Batch<float>* frozen32,
+                  hipStream_t st) {
+    Batch<float> e32{};
+    if (frozen32 != nullptr) e32 = *frozen32;
+    CHHS_DISPATCH(dim, k_setup, nt, b, t, info, phi_prev, phi_cur, mu, p, partial, e32);
 }
 
 #define CHHS_DISPATCH_T(dim, KERNEL, GRID, ...)                                           \
@@ -979,10 +976,6 @@ void launch_coarse_rhs(int dim, const Batch<float>& b, const CellTask* t, int nt
 }
 #undef CHHS_TARGS
 
-void launch_mixed_frozen(const Batch<double>& b64, const Batch<float>& b32, const CellTask* t,
-                         int nt, hipStream_t st) {
-    if (nt > 0) hipLaunchKernelGGL(k_mixed_frozen, dim3(nt), dim3(kBlock), 0, st, b64, b32, t);
-}
 
 void launch_zero_correction(const Batch<float>& b32, const CellTask* t, int nt, hipStream_t st) {
     if (nt > 0) hipLaunchKernelGGL(k_zero_correction, dim3(nt), dim3(kBlock), 0, st, b32, t);

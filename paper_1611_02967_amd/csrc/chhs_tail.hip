@@ -205,7 +205,62 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(const LevelDesc<T>* __res
         // holds the finest level, then cleared (the finest level's first
         // smoothing launch has already subtracted it otherwise)
         const T psh = pend != nullptr && top == 0 ? T(pend[inst * kResStride + 4]) : T(0);
-        for (int idx = threadIdx.x; idx < G.n; idx += blockDim.x) {
+        // Every global load of the first rounds is issued before any LDS
+        // store, so the staging waits for memory once: two cells of the top
+        // level per thread (the LDS budget keeps the top below 2 kTailThreads
+        // cells) and one of each lower level (a quarter or an eighth of the
+        // level above); any further cells by the loops after.
+        const int t0 = threadIdx.x;
+        T tv[2][9];
+        T lv[kMaxTailLevels][2];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int idx = t0 + k * kTailThreads;
+            if (idx < G.n) {
+                tv[k][0] = gload(G.phi, idx);
+                tv[k][1] = gload(G.mu, idx);
+                tv[k][2] = gload(G.p, idx);
+                tv[k][3] = gload(g0, idx);
+                tv[k][4] = gload(g1, idx);
+                tv[k][5] = gload(g2, idx);
+                tv[k][6] = CORR ? gload(G.b, idx) : T(0);
+                tv[k][7] = gload(G.pstar, idx);
+                tv[k][8] = gload(G.psi, idx);
+            }
+        }
+#pragma unroll
+        for (int m = 1; m < kMaxTailLevels; ++m) {
+            const int l = top + m;
+            if (l < nlev && t0 < d[l].n) {
+                lv[m][0] = gload(d[l].pstar, t0);
+                lv[m][1] = gload(d[l].psi, t0);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int idx = t0 + k * kTailThreads;
+            if (idx < G.n) {
+                S.phi[idx] = tv[k][0];
+                S.mu[idx] = tv[k][1];
+                S.p[idx] = tv[k][2] - psh;
+                S.f0[idx] = tv[k][3];
+                S.f1[idx] = tv[k][4];
+                S.f2[idx] = tv[k][5];
+                if (CORR) S.b[idx] = tv[k][6];
+                S.pstar[idx] = tv[k][7];
+                S.psi[idx] = tv[k][8];
+            }
+        }
+#pragma unroll
+        for (int m = 1; m < kMaxTailLevels; ++m) {
+            const int l = top + m;
+            if (l < nlev && t0 < d[l].n) {
+                const Level<T> V = lds_view<T, CORR>(d, top, l, base);
+                V.pstar[t0] = lv[m][0];
+                V.psi[t0] = lv[m][1];
+            }
+        }
+        for (int idx = t0 + 2 * kTailThreads; idx < G.n; idx += blockDim.x) {
             S.phi[idx] = G.phi[idx];
             S.mu[idx] = G.mu[idx];
             S.p[idx] = G.p[idx] - psh;
@@ -213,11 +268,13 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(const LevelDesc<T>* __res
             S.f1[idx] = g1[idx];
             S.f2[idx] = g2[idx];
             if (CORR) S.b[idx] = G.b[idx];
+            S.pstar[idx] = G.pstar[idx];
+            S.psi[idx] = G.psi[idx];
         }
-        for (int l = top; l < nlev; ++l) {
+        for (int l = top + 1; l < nlev; ++l) {
             const Level<T> V = lds_view<T, CORR>(d, top, l, base);
             const LevelDesc<T>& D = d[l];
-            for (int idx = threadIdx.x; idx < V.n; idx += blockDim.x) {
+            for (int idx = t0 + kTailThreads; idx < V.n; idx += blockDim.x) {
                 V.pstar[idx] = D.pstar[idx];
                 V.psi[idx] = D.psi[idx];
             }
@@ -260,9 +317,9 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(const LevelDesc<T>* __res
 
     const Level<T> S = lds_view<T, CORR>(d, top, top, base);
     for (int idx = threadIdx.x; idx < G.n; idx += blockDim.x) {
-        G.phi[idx] = S.phi[idx];
-        G.mu[idx] = S.mu[idx];
-        G.p[idx] = S.p[idx];
+        gstore(G.phi, idx, S.phi[idx]);
+        gstore(G.mu, idx, S.mu[idx]);
+        gstore(G.p, idx, S.p[idx]);
     }
 }
 
