@@ -713,23 +713,30 @@ __global__ __launch_bounds__(kBlock) void k_energy_partials(Batch<double> b,
     if (idx < L.n) {
         int i, j, k;
         decode<DIM>(idx, L.nx, L.ny, i, j, k);
-        const double f = phi[idx];
-        const double d = f - q[idx];
+        // (global-address-space loads: the block reductions below wait on
+        // LDS without also waiting for outstanding global accesses)
+        const double f = gload(phi, idx);
+        const double qc = gload(q, idx);
+        const double d = f - qc;
         v[0] = f;
         v[1] = f * f;
         v[2] = f * f * f * f;
         v[4] = d * d;
         vmax = fabs(f);
+        const double muc = ws ? gload(L.mu, idx) : 0.0;
+        const double pc = ws ? gload(L.p, idx) : 0.0;
+        const double psc = ws ? gload(L.pstar, idx) : 0.0;
         // forward faces only: every interior face counted once
         auto face = [&](int nb) {
-            const double df = phi[nb] - f;
-            const double dd = (phi[nb] - q[nb]) - d;
+            const double fn = gload(phi, nb);
+            const double df = fn - f;
+            const double dd = (fn - gload(q, nb)) - d;
             v[3] += df * df;
             v[5] += dd * dd;
             if (ws) {
-                const double dm = L.mu[nb] - L.mu[idx];
-                const double a = 0.5 * (L.pstar[idx] + L.pstar[nb]);
-                const double u = -(L.p[nb] - L.p[idx]) - gamma * a * dm;
+                const double dm = gload(L.mu, nb) - muc;
+                const double a = 0.5 * (psc + gload(L.pstar, nb));
+                const double u = -(gload(L.p, nb) - pc) - gamma * a * dm;
                 v[6] += dm * dm;
                 v[7] += u * u;
             }
@@ -741,10 +748,10 @@ __global__ __launch_bounds__(kBlock) void k_energy_partials(Batch<double> b,
             // the copy-out of the step (phi^m is the workspace's psi)
             const int g = off + idx;
             const double psh = b.pshift != nullptr ? b.pshift[tk.inst * kResStride + 4] : 0.0;
-            co.phi_prev[g] = q[idx];
-            co.phi_cur[g] = f;
-            co.mu[g] = L.mu[idx];
-            co.p[g] = L.p[idx] - psh;
+            gstore(co.phi_prev, g, qc);
+            gstore(co.phi_cur, g, f);
+            gstore(co.mu, g, muc);
+            gstore(co.p, g, pc - psh);
         }
     }
     double out[8];
