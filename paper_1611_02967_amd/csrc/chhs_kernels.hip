@@ -745,13 +745,13 @@ __global__ __launch_bounds__(kBlock) void k_energy_partials(Batch<double> b,
         if (j < L.ny - 1) face(idx + L.nx);
         if (DIM == 3 && k < L.nz - 1) face(idx + L.nx * L.ny);
         if (ws && co.phi_cur != nullptr) {
-            // the copy-out of the step (phi^m is the workspace's psi)
-            const int g = off + idx;
+            // the copy-out of the step (phi^m is the workspace's psi); the
+            // instance's own base pointers keep the 32-bit offsets in range
             const double psh = b.pshift != nullptr ? b.pshift[tk.inst * kResStride + 4] : 0.0;
-            gstore(co.phi_prev, g, qc);
-            gstore(co.phi_cur, g, f);
-            gstore(co.mu, g, muc);
-            gstore(co.p, g, pc - psh);
+            gstore(co.phi_prev + off, idx, qc);
+            gstore(co.phi_cur + off, idx, f);
+            gstore(co.mu + off, idx, muc);
+            gstore(co.p + off, idx, pc - psh);
         }
     }
     double out[8];
