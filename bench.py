@@ -59,7 +59,8 @@ def launch_bytes_per_cell(dim, cls, mixed=False, kind=None):
                  phi^m, f_phi, f_mu, f_p (6 per 2 cells) and its new phi, mu,
                  p (3 per 2 cells)                                          = 52 B
       3D fused (kind "zmarch"): one launch = one whole step: u, phi_*, phi^m
-                 and f read, u written: (8 + 3) values                      = 88 B
+                 and f_mu read (f_phi = phi^m, f_p = 0 are not), u written:
+                 (6 + 3) values                                             = 72 B
     Mixed precision, FP32 correction form (4 B per value; general right-hand
     sides and the base state b on every level):
       2D pre0  : 9 reads + 3 writes, plus u_c, ub_c, R(r), b_c (10 per 4)   = 58 B
@@ -80,7 +81,7 @@ def launch_bytes_per_cell(dim, cls, mixed=False, kind=None):
         return (9 + 3) * 4 if kind == "zmarch" else (4 + 7 + 3) / 2 * 4
     if dim == 2:
         return {"pre0": (9 + 9 / 4) * 8, "post0": (9 + 6 / 4) * 8}[cls]
-    return (8 + 3) * 8 if kind == "zmarch" else (4 + 6 + 3) / 2 * 8
+    return (6 + 3) * 8 if kind == "zmarch" else (4 + 6 + 3) / 2 * 8
 
 
 SWEEP_KEYS = ("nu1", "nu2", "nu1_coarse", "nu2_coarse", "prolong", "inner_cycles")
@@ -113,8 +114,12 @@ def vcycle_bytes(dim, shape, level_kernels, sweeps=None):
                                     right-hand side of level l + 1 unless the
                                     tail forms it, 11/r; the prolongation
                                     (6 + 6/r)
-      fused 3D steps ("zmarch")   : nu1 + nu2 launches of 88 B, the transfers
-                                    as for per-cell kernels
+      fused 3D steps ("zmarch")   : nu1 + nu2 launches of 88 B (72 B on the
+                                    finest level, which reads no f_phi, f_p),
+                                    the transfers as for per-cell kernels (on
+                                    the finest level of an instance of at
+                                    least 2^20 cells the residual + restriction
+                                    by z marching, which reads 6 values, not 8)
       tail (one launch)           : u and fr of its top level read, u written,
                                     phi_* and phi^m of every tail level read
     The norm reduction and the per-cycle readback (a few KB) are left out.
@@ -137,8 +142,9 @@ def vcycle_bytes(dim, shape, level_kernels, sweeps=None):
             break
         if kind in ("per-cell", "zmarch"):
             next_tail = l + 1 < len(kinds) and kinds[l + 1] == "tail"
-            smooth = (a + b) * 2 * 52 / 8 if kind == "per-cell" else (a + b) * 11
-            v = smooth + (8 + 9 / r) + (6 + 6 / r)
+            smooth = (a + b) * 2 * 52 / 8 if kind == "per-cell" else (a + b) * (9 if l == 0 else 11)
+            zres = kind == "zmarch" and l == 0 and n0 >= 2 ** 20
+            v = smooth + ((6 if zres else 8) + 9 / r) + (6 + 6 / r)
             v += 0 if next_tail else 11 / r
         else:
             read = 6 if l == 0 else 8
@@ -751,18 +757,19 @@ TRAFFIC_KERNELS = [
      ["chhs_stream2d.hip", "chhs_cell.hpp", "chhs_internal.hpp"]),
     ("post0", r"k_stream2d<double, true, 2, 2,", 84.0,
      ["chhs_stream2d.hip", "chhs_cell.hpp", "chhs_internal.hpp"]),
-    # fused 3D step (template arguments T, CORR, TX, TY, PRO, ZERO): pre launches
-    # without prolongation; the post class by its first launch, which also
-    # reads u_c and ub_c of the coarse parent (6 values per 8 cells)
-    ("pre0", r"k_step3d<double, false, \d+, \d+, 0, false>", 88.0,
+    # fused 3D step (template arguments T, CORR, TX, TY, PRO, ZERO, L0): pre
+    # launches without prolongation; the post class by its first launch, which
+    # also reads u_c and ub_c of the coarse parent (6 values per 8 cells); the
+    # finest FP64 level (L0) reads no f_phi, f_p
+    ("pre0", r"k_step3d<double, false, \d+, \d+, 0, false, true>", 72.0,
      ["chhs_step3d.hip", "chhs_cell.hpp", "chhs_internal.hpp"]),
-    ("post0", r"k_step3d<double, false, \d+, \d+, 1, false>", 94.0,
+    ("post0", r"k_step3d<double, false, \d+, \d+, 1, false, true>", 78.0,
      ["chhs_step3d.hip", "chhs_cell.hpp", "chhs_internal.hpp"]),
-    ("pre0", r"k_step3d<float, true, \d+, \d+, 0, true>", 36.0,
+    ("pre0", r"k_step3d<float, true, \d+, \d+, 0, true, false>", 36.0,
      ["chhs_step3d.hip", "chhs_cell.hpp", "chhs_internal.hpp"]),
-    ("pre0", r"k_step3d<float, true, \d+, \d+, 0, false>", 48.0,
+    ("pre0", r"k_step3d<float, true, \d+, \d+, 0, false, false>", 48.0,
      ["chhs_step3d.hip", "chhs_cell.hpp", "chhs_internal.hpp"]),
-    ("post0", r"k_step3d<float, true, \d+, \d+, 1, false>", 51.0,
+    ("post0", r"k_step3d<float, true, \d+, \d+, 1, false, false>", 51.0,
      ["chhs_step3d.hip", "chhs_cell.hpp", "chhs_internal.hpp"]),
 ]
 

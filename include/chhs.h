@@ -268,7 +268,9 @@ int chhs_energy_mass_noalloc(const chhs_problem* p, int32_t n_inst, const double
 
 /* Level-by-level access for kernel-level tests.  field: 0 phi, 1 mu, 2 p,
  * 3 f_phi, 4 f_mu, 5 f_p, 6 phi_*, 7 phi^m (psi).  dir 0: level -> dev,
- * dir 1: dev -> level.  Single-instance contexts only. */
+ * dir 1: dev -> level.  Single-instance contexts only.  On the finest level
+ * the kernels take f_phi = phi^m and f_p = 0, as the step's setup writes them
+ * (the fields themselves are not read there). */
 int chhs_level_count(chhs_ctx* c, int32_t* levels);
 int chhs_level_shape(chhs_ctx* c, int32_t level, int32_t* nxyz3);
 

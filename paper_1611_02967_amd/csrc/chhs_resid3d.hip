@@ -34,7 +34,9 @@ constexpr int kThreads = 256;
 constexpr int kRing = 4;          // planes t - 1 .. t + 2 are live in iteration t
 constexpr int PHI = 0, MU = 1, P = 2, PS = 3, NRF = 4;
 
-template <typename T, bool CORR, int MODE, int TX, int TY>
+// L0: the finest level of the plain form, whose right-hand side is f_phi =
+// phi^m (psi) and f_p = 0 ((2.5), (2.7)): neither is loaded.
+template <typename T, bool CORR, int MODE, int TX, int TY, bool L0>
 __global__ __launch_bounds__(kThreads) void k_resid3d(Batch<T> bt, const Step3Task* __restrict__ tasks,
                                                       int ntasks, double* __restrict__ partial) {
     static_assert(TX * TY == kThreads, "one cell per thread and plane");
@@ -94,10 +96,10 @@ __global__ __launch_bounds__(kThreads) void k_resid3d(Batch<T> bt, const Step3Ta
     auto load_own = [&](int z, Own& o) {
         const bool ok = own_ok && z >= 0 && z < nz;
         const int g = ok ? z * sxy + gy * nx + gx : 0;
-        o.f0 = gload(L.f0, g);
-        o.f1 = gload(L.f1, g);
-        o.f2 = gload(L.f2, g);
         o.psi = gload(L.psi, g);
+        o.f0 = L0 ? o.psi : gload(L.f0, g);
+        o.f1 = gload(L.f1, g);
+        o.f2 = L0 ? T(0) : gload(L.f2, g);
         o.b = CORR ? gload(L.b, g) : T(0);
     };
 
@@ -418,20 +420,28 @@ void launch_refine3d(const Batch<double>& b64, const Batch<float>& b32, const St
 
 void launch_residual3d_partials(const Batch<double>& b, const Step3Task* t, int nt, double* partial,
                                 hipStream_t st) {
-    if (nt > 0)
-        hipLaunchKernelGGL((k_resid3d<double, false, 0, kStep3TX64, kStep3TY64>), dim3(nt),
+    if (nt <= 0) return;
+    if (b.level == 0)
+        hipLaunchKernelGGL((k_resid3d<double, false, 0, kStep3TX64, kStep3TY64, true>), dim3(nt),
+                           dim3(kThreads), 0, st, b, t, nt, partial);
+    else
+        hipLaunchKernelGGL((k_resid3d<double, false, 0, kStep3TX64, kStep3TY64, false>), dim3(nt),
                            dim3(kThreads), 0, st, b, t, nt, partial);
 }
 
 void launch_restrict3d(const Batch<double>& b, const Step3Task* t, int nt, hipStream_t st) {
-    if (nt > 0)
-        hipLaunchKernelGGL((k_resid3d<double, false, 1, kStep3TX64, kStep3TY64>), dim3(nt),
+    if (nt <= 0) return;
+    if (b.level == 0)
+        hipLaunchKernelGGL((k_resid3d<double, false, 1, kStep3TX64, kStep3TY64, true>), dim3(nt),
+                           dim3(kThreads), 0, st, b, t, nt, nullptr);
+    else
+        hipLaunchKernelGGL((k_resid3d<double, false, 1, kStep3TX64, kStep3TY64, false>), dim3(nt),
                            dim3(kThreads), 0, st, b, t, nt, nullptr);
 }
 
 void launch_restrict3d(const Batch<float>& b, const Step3Task* t, int nt, hipStream_t st) {
     if (nt > 0)
-        hipLaunchKernelGGL((k_resid3d<float, true, 1, kStep3TX32, kStep3TY32>), dim3(nt),
+        hipLaunchKernelGGL((k_resid3d<float, true, 1, kStep3TX32, kStep3TY32, false>), dim3(nt),
                            dim3(kThreads), 0, st, b, t, nt, nullptr);
 }
 

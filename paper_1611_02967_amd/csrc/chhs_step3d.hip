@@ -70,8 +70,10 @@ struct Own {
 
 // PRO and ZERO are template arguments: a branch around the region loads
 // would make the compiler wait for every load in flight where the branches
-// join, and the loads would no longer overlap an iteration.
-template <typename T, bool CORR, int TX, int TY, int PRO, bool ZERO>
+// join, and the loads would no longer overlap an iteration.  L0: the finest
+// level of the plain form, whose right-hand side is f_phi = phi^m (psi) and
+// f_p = 0 ((2.5), (2.7)): neither is loaded.
+template <typename T, bool CORR, int TX, int TY, int PRO, bool ZERO, bool L0>
 __global__ __launch_bounds__(kThreads) void k_step3d(Batch<T> bt, const Step3Task* __restrict__ tasks,
                                                      int ntasks) {
     using G = Geo<TX, TY>;
@@ -176,9 +178,9 @@ __global__ __launch_bounds__(kThreads) void k_step3d(Batch<T> bt, const Step3Tas
         const bool ok = gx >= 0 && gx < nx && gy >= 0 && gy < ny && z >= 0 && z < nz;
         const int g = ok ? z * sxy + gy * nx + gx : 0;
         o.psi = gload(L.psi, g);
-        o.f0 = gload(L.f0, g);
+        o.f0 = L0 ? o.psi : gload(L.f0, g);
         o.f1 = gload(L.f1, g);
-        o.f2 = gload(L.f2, g);
+        o.f2 = L0 ? T(0) : gload(L.f2, g);
         o.b = CORR ? gload(L.b, g) : T(0);
     };
 
@@ -329,32 +331,36 @@ __global__ __launch_bounds__(kThreads) void k_step3d(Batch<T> bt, const Step3Tas
     }
 }
 
-template <typename T, bool CORR, int TX, int TY>
+template <typename T, bool CORR, int TX, int TY, bool L0>
 void launch_tiles(const Batch<T>& b, const Step3Task* t, int nt, int pro, int zero, hipStream_t st) {
     if (pro == 1)
-        hipLaunchKernelGGL((k_step3d<T, CORR, TX, TY, 1, false>), dim3(nt), dim3(kThreads), 0, st,
-                           b, t, nt);
+        hipLaunchKernelGGL((k_step3d<T, CORR, TX, TY, 1, false, L0>), dim3(nt), dim3(kThreads), 0,
+                           st, b, t, nt);
     else if (pro == 2)
-        hipLaunchKernelGGL((k_step3d<T, CORR, TX, TY, 2, false>), dim3(nt), dim3(kThreads), 0, st,
-                           b, t, nt);
+        hipLaunchKernelGGL((k_step3d<T, CORR, TX, TY, 2, false, L0>), dim3(nt), dim3(kThreads), 0,
+                           st, b, t, nt);
     else if (zero && CORR)
-        hipLaunchKernelGGL((k_step3d<T, CORR, TX, TY, 0, CORR>), dim3(nt), dim3(kThreads), 0, st,
-                           b, t, nt);
+        hipLaunchKernelGGL((k_step3d<T, CORR, TX, TY, 0, CORR, L0>), dim3(nt), dim3(kThreads), 0,
+                           st, b, t, nt);
     else
-        hipLaunchKernelGGL((k_step3d<T, CORR, TX, TY, 0, false>), dim3(nt), dim3(kThreads), 0, st,
-                           b, t, nt);
+        hipLaunchKernelGGL((k_step3d<T, CORR, TX, TY, 0, false, L0>), dim3(nt), dim3(kThreads), 0,
+                           st, b, t, nt);
 }
 
 }  // namespace
 
 void launch_step3d(const Batch<double>& b, const Step3Task* t, int nt, int pro, int zero,
                    hipStream_t st) {
-    if (nt > 0) launch_tiles<double, false, kStep3TX64, kStep3TY64>(b, t, nt, pro, zero, st);
+    if (nt <= 0) return;
+    if (b.level == 0)
+        launch_tiles<double, false, kStep3TX64, kStep3TY64, true>(b, t, nt, pro, zero, st);
+    else
+        launch_tiles<double, false, kStep3TX64, kStep3TY64, false>(b, t, nt, pro, zero, st);
 }
 
 void launch_step3d(const Batch<float>& b, const Step3Task* t, int nt, int pro, int zero,
                    hipStream_t st) {
-    if (nt > 0) launch_tiles<float, true, kStep3TX32, kStep3TY32>(b, t, nt, pro, zero, st);
+    if (nt > 0) launch_tiles<float, true, kStep3TX32, kStep3TY32, false>(b, t, nt, pro, zero, st);
 }
 
 }  // namespace chhs
