@@ -2287,7 +2287,8 @@ int chhs_smooth(chhs_ctx* c, int32_t level, int32_t nsweeps) {
         return CHHS_E_INVAL;
     // the FP64 tile kernels have no 64 x 32 form (a mixed-precision level cut
     // for the FP32 ones)
-    if (tiled2d(c) && c->lay.tile_y[level] == chhs::kTileYTall) return CHHS_E_INVAL;
+    if (tiled2d(c) && !c->lay.strip[level] && c->lay.tile_y[level] == chhs::kTileYTall)
+        return CHHS_E_INVAL;
     smooth_steps(c, level, nsweeps, nullptr, level == 0 ? CHHS_K_PRE0 : CHHS_K_COARSE);
     if (c->cur[level] != 0) {
         // the single instance's level: make the result copy 0 again

@@ -169,25 +169,35 @@ def test_inner_cycles_solve_the_same_steps(chhs, name, inner):
             assert np.array_equal(_unpack(hg[k], shapes)[0], hs[k].reshape(shapes[0])), k
 
 
-@pytest.mark.parametrize("name", ["2d-64", "2d-ragged"])
+# 256 x 256 and 96 x 160: blocks whose whole region lies inside the grid
+# (the interior form of the tile body) next to blocks at the grid's edges
+TILE_SPECS = {"2d-64": SPECS["2d-64"], "2d-ragged": SPECS["2d-ragged"],
+              "2d-interior": [((256, 256), 0.02, 1.0, 1e-4), ((96, 160), 0.03, 2.0, 5e-4)]}
+
+
+@pytest.mark.parametrize("name", list(TILE_SPECS))
 def test_tall_finest_tiles_solve_the_same_steps(chhs, name):
-    """64 x 32 tiles on the FP32 finest level (tile_rows = 32): the same FP64
-    solution (<= 1e-8 against the FP64 path, residual at tol), the same
-    refinement counts as 64 x 16 tiles (to one), and batch = single runs bitwise."""
-    spec = SPECS[name]
+    """Tiles on every level (smoother = 1), the FP32 finest level in 64 x 16
+    or 64 x 32 tiles (tile_rows = 32), against row-streaming strips on the
+    FP32 finest level (smoother = 2) and the FP64 path: the same FP64 solution
+    (<= 1e-8, residual at tol), refinement counts within one, and batch =
+    single runs bitwise."""
+    spec = TILE_SPECS[name]
     shapes = [s[0] for s in spec]
     phi0s = [uniform_field(sh, 4600 + i, mean=0.1, amp=0.05) for i, sh in enumerate(shapes)]
     ref = _steps(chhs, spec, phi0s, 3, precision=0)
-    base = _steps(chhs, spec, phi0s, 3, precision=1)
-    tall = _steps(chhs, spec, phi0s, 3, precision=1, tile_rows=32)
-    for hr, hb, ht in zip(ref, base, tall):
-        assert np.max(np.abs(ht["phi"] - hr["phi"])) <= 1e-8
-        assert np.max(np.abs(ht["phi"] - hb["phi"])) <= 1e-8
-        for st, sb in zip(ht["stats"], hb["stats"]):
-            assert st["res_norm"] <= 1e-10
-            assert abs(st["vcycles"] - sb["vcycles"]) <= 1
+    strips = _steps(chhs, spec, phi0s, 3, precision=1, smoother=2)
+    base = _steps(chhs, spec, phi0s, 3, precision=1, smoother=1)
+    tall = _steps(chhs, spec, phi0s, 3, precision=1, smoother=1, tile_rows=32)
+    for hr, hs, hb, ht in zip(ref, strips, base, tall):
+        for h in (hb, ht):
+            assert np.max(np.abs(h["phi"] - hr["phi"])) <= 1e-8
+            assert np.max(np.abs(h["phi"] - hs["phi"])) <= 1e-8
+            for st, ss in zip(h["stats"], hs["stats"]):
+                assert st["res_norm"] <= 1e-10
+                assert abs(st["vcycles"] - ss["vcycles"]) <= 1
     if len(spec) > 1:
-        single = _steps(chhs, [spec[0]], [phi0s[0]], 3, precision=1, tile_rows=32)
+        single = _steps(chhs, [spec[0]], [phi0s[0]], 3, precision=1, smoother=1, tile_rows=32)
         for ht, hs in zip(tall, single):
             for k in ("phi", "mu", "p"):
                 assert np.array_equal(_unpack(ht[k], shapes)[0], hs[k].reshape(shapes[0])), k
@@ -198,7 +208,7 @@ def test_fp64_smoothing_refuses_tall_tiles(chhs):
     (FP32 kernels only) refuses chhs_smooth there (the FP64 tile kernels have
     no such form) and still smooths the coarse levels."""
     prob = chhs.make_problem((128, 128), 1.0 / 128, 0.05, 1.0, 1e-3)
-    sv = chhs.Solver(prob, chhs.chhs_default_opts(precision=1, tile_rows=32))
+    sv = chhs.Solver(prob, chhs.chhs_default_opts(precision=1, smoother=1, tile_rows=32))
     phi = uniform_field((128, 128), 4700, amp=0.1).ravel()
     sv.setup_step(dev(phi), dev(phi), dev(np.zeros(phi.size)), dev(np.zeros(phi.size)))
     with pytest.raises(chhs.ChhsError):
