@@ -56,8 +56,8 @@ def launch_bytes_per_cell(dim, cls, mixed=False, kind=None):
                  6 reads + 3 writes, plus u_c, ub_c read (6 per 4 cells)    = 84 B
       3D       : one launch = one color of one step: the other color's phi,
                  mu, p, phi_* (4 values per 2 cells), the color's phi, phi_*,
-                 phi^m, f_phi, f_mu, f_p (6 per 2 cells) and its new phi, mu,
-                 p (3 per 2 cells)                                          = 52 B
+                 phi^m, f_mu (4 per 2 cells; f_phi = phi^m and f_p = 0 are not
+                 read) and its new phi, mu, p (3 per 2 cells)               = 44 B
       3D fused (kind "zmarch"): one launch = one whole step: u, phi_*, phi^m
                  and f_mu read (f_phi = phi^m, f_p = 0 are not), u written:
                  (6 + 3) values                                             = 72 B
@@ -81,7 +81,7 @@ def launch_bytes_per_cell(dim, cls, mixed=False, kind=None):
         return (9 + 3) * 4 if kind == "zmarch" else (4 + 7 + 3) / 2 * 4
     if dim == 2:
         return {"pre0": (9 + 9 / 4) * 8, "post0": (9 + 6 / 4) * 8}[cls]
-    return (6 + 3) * 8 if kind == "zmarch" else (4 + 6 + 3) / 2 * 8
+    return (6 + 3) * 8 if kind == "zmarch" else (4 + 4 + 3) / 2 * 8
 
 
 SWEEP_KEYS = ("nu1", "nu2", "nu1_coarse", "nu2_coarse", "prolong", "inner_cycles")
@@ -109,17 +109,18 @@ def vcycle_bytes(dim, shape, level_kernels, sweeps=None):
       strips on a coarse level    : a separate launch forms f (u, fr, phi_*,
                                     phi^m read, f written: 11), the first launch
                                     then reads f (no + 3)
-      per-cell kernels            : 2 (nu1 + nu2) color launches of 52 B; the
+      per-cell kernels            : 2 (nu1 + nu2) color launches of 52 B (44 B
+                                    on the finest level); the
                                     residual + restriction (8 + 9/r); the
                                     right-hand side of level l + 1 unless the
                                     tail forms it, 11/r; the prolongation
                                     (6 + 6/r)
       fused 3D steps ("zmarch")   : nu1 + nu2 launches of 88 B (72 B on the
                                     finest level, which reads no f_phi, f_p),
-                                    the transfers as for per-cell kernels (on
-                                    the finest level of an instance of at
-                                    least 2^20 cells the residual + restriction
-                                    by z marching, which reads 6 values, not 8)
+                                    the transfers as for per-cell kernels
+      (3D, either kind: on the finest level of an instance of at least 2^20
+      cells the residual + restriction runs by z marching and reads 6 values,
+      not 8)
       tail (one launch)           : u and fr of its top level read, u written,
                                     phi_* and phi^m of every tail level read
     The norm reduction and the per-cycle readback (a few KB) are left out.
@@ -142,8 +143,11 @@ def vcycle_bytes(dim, shape, level_kernels, sweeps=None):
             break
         if kind in ("per-cell", "zmarch"):
             next_tail = l + 1 < len(kinds) and kinds[l + 1] == "tail"
-            smooth = (a + b) * 2 * 52 / 8 if kind == "per-cell" else (a + b) * (9 if l == 0 else 11)
-            zres = kind == "zmarch" and l == 0 and n0 >= 2 ** 20
+            smooth = ((a + b) * 2 * (44 if l == 0 else 52) / 8 if kind == "per-cell"
+                      else (a + b) * (9 if l == 0 else 11))
+            # the residual + restriction from the finest level of an instance
+            # of at least 2^20 cells runs by z marching and reads no f_phi, f_p
+            zres = dim == 3 and l == 0 and n0 >= 2 ** 20
             v = smooth + ((6 if zres else 8) + 9 / r) + (6 + 6 / r)
             v += 0 if next_tail else 11 / r
         else:

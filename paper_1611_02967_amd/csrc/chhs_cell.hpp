@@ -230,7 +230,9 @@ __device__ __forceinline__ void cell_operator(const Level<T>& L, int idx, int i,
 // every path performs the same update; kernels differ at most in which
 // products the compiler fuses into multiply-adds, i.e. they agree to
 // rounding.  inv_lam = 1 / lam.
-template <int DIM, typename T, bool CORR = false>
+// L0: the finest level of the plain form, whose right-hand side is f_phi =
+// phi^m (psi) and f_p = 0 ((2.5), (2.7)): neither is loaded.
+template <int DIM, typename T, bool CORR = false, bool L0 = false>
 __device__ __forceinline__ void cell_solve(const Level<T>& L, int idx, int i, int j, int k,
                                            T inv_lam, T& phi_o, T& mu_o, T& p_o) {
     const T psc = L.pstar[idx];
@@ -263,9 +265,9 @@ __device__ __forceinline__ void cell_solve(const Level<T>& L, int idx, int i, in
     const bool cubic = !CORR && L.order == 1;
     const T dchi = cubic ? T(3) * phit * phit : dnonlin<T, CORR>(phit, psi, base);
     const T chi = cubic ? phit * phit * phit : nonlin<T, CORR>(phit, psi, base);
-    const T b1 = L.f0[idx] + lam * smmu + lam * sap;
+    const T b1 = (L0 ? psi : L.f0[idx]) + lam * smmu + lam * sap;
     const T b2 = L.f1[idx] + chi - dchi * phit - kap * sphi;
-    const T b3 = L.f2[idx] - lam * sp - lam * gam * samu;
+    const T b3 = (L0 ? T(0) : L.f2[idx]) - lam * sp - lam * gam * samu;
     const T ared = lam * (fnf + gam * (sa2 - sa * sa * inv_nf));
     const T b1r = b1 + (sa * inv_nf) * b3;
     const T bb = dchi + kap * fnf;

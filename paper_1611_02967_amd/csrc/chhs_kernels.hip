@@ -172,7 +172,8 @@ __global__ __launch_bounds__(kChainThreads) void k_restrict_frozen_chain(
     }
 }
 
-template <int DIM, typename T, bool CORR>
+// L0 (FP64 finest level): f_phi = phi^m and f_p = 0 are not loaded.
+template <int DIM, typename T, bool CORR, bool L0 = false>
 __global__ __launch_bounds__(kBlock) void k_smooth(Batch<T> b, const CellTask* __restrict__ t,
                                                    int color) {
     const int task = xcd_task();
@@ -185,7 +186,7 @@ __global__ __launch_bounds__(kBlock) void k_smooth(Batch<T> b, const CellTask* _
     decode<DIM>(idx, L.nx, L.ny, i, j, k);
     if (((i + j + k) & 1) != color) return;
     T phi, mu, p;
-    cell_solve<DIM, T, CORR>(L, idx, i, j, k, T(1) / L.lam, phi, mu, p);
+    cell_solve<DIM, T, CORR, L0>(L, idx, i, j, k, T(1) / L.lam, phi, mu, p);
     L.phi[idx] = phi;
     L.mu[idx] = mu;
     L.p[idx] = p;
@@ -195,7 +196,7 @@ __global__ __launch_bounds__(kBlock) void k_smooth(Batch<T> b, const CellTask* _
 // with an even x extent: every row holds nx / 2 cells of each color), so that
 // no lane of a launch idles on the other color.  Task cell0 counts cells of
 // the color.
-template <int DIM, typename T, bool CORR>
+template <int DIM, typename T, bool CORR, bool L0 = false>
 __global__ __launch_bounds__(kBlock) void k_smooth_color(Batch<T> b, const CellTask* __restrict__ t,
                                                          int color) {
     const int task = xcd_task();
@@ -212,7 +213,7 @@ __global__ __launch_bounds__(kBlock) void k_smooth_color(Batch<T> b, const CellT
     const int i = 2 * m + ((j + k + color) & 1);
     const int idx = row * L.nx + i;
     T phi, mu, p;
-    cell_solve<DIM, T, CORR>(L, idx, i, j, k, T(1) / L.lam, phi, mu, p);
+    cell_solve<DIM, T, CORR, L0>(L, idx, i, j, k, T(1) / L.lam, phi, mu, p);
     L.phi[idx] = phi;
     L.mu[idx] = mu;
     L.p[idx] = p;
@@ -590,7 +591,8 @@ __global__ __launch_bounds__(kBlock) void k_residual_partials(Batch<double> b,
             decode<DIM>(idx, L.nx, L.ny, i, j, k);
             double n0, n1, n2;
             cell_operator<DIM>(L, idx, i, j, k, n0, n1, n2);
-            const double r0 = L.f0[idx] - n0, r1 = L.f1[idx] - n1, r2 = L.f2[idx] - n2;
+            // the finest level: f_phi = phi^m, f_p = 0 ((2.5), (2.7))
+            const double r0 = L.psi[idx] - n0, r1 = L.f1[idx] - n1, r2 = -n2;
             v[0] = r0 * r0;
             v[1] = r1 * r1;
             v[2] = r2 * r2;
@@ -943,14 +945,33 @@ void launch_prolong(int dim, const Batch<float>& b, const CellTask* t, int nt, b
 }
 #undef CHHS_TARGS
 #define CHHS_TARGS double, false
+// (the finest level takes the form that does not load f_phi, f_p)
+#define CHHS_SMOOTH_LAUNCH(KERNEL)                                                             \
+    do {                                                                                       \
+        if (nt <= 0) break;                                                                    \
+        const bool l0 = b.level == 0;                                                          \
+        if (dim == 2 && l0)                                                                    \
+            hipLaunchKernelGGL((KERNEL<2, double, false, true>), dim3(nt), dim3(kBlock), 0, st, \
+                               b, t, color);                                                   \
+        else if (dim == 2)                                                                     \
+            hipLaunchKernelGGL((KERNEL<2, double, false, false>), dim3(nt), dim3(kBlock), 0, st, \
+                               b, t, color);                                                   \
+        else if (l0)                                                                           \
+            hipLaunchKernelGGL((KERNEL<3, double, false, true>), dim3(nt), dim3(kBlock), 0, st, \
+                               b, t, color);                                                   \
+        else                                                                                   \
+            hipLaunchKernelGGL((KERNEL<3, double, false, false>), dim3(nt), dim3(kBlock), 0, st, \
+                               b, t, color);                                                   \
+    } while (0)
 void launch_smooth(int dim, const Batch<double>& b, const CellTask* t, int nt, int color,
                    hipStream_t st) {
-    CHHS_DISPATCH_T(dim, k_smooth, nt, b, t, color);
+    CHHS_SMOOTH_LAUNCH(k_smooth);
 }
 void launch_smooth_color(int dim, const Batch<double>& b, const CellTask* t, int nt, int color,
                          hipStream_t st) {
-    CHHS_DISPATCH_T(dim, k_smooth_color, nt, b, t, color);
+    CHHS_SMOOTH_LAUNCH(k_smooth_color);
 }
+#undef CHHS_SMOOTH_LAUNCH
 void launch_restrict_residual(int dim, const Batch<double>& b, const CellTask* t, int nt,
                               hipStream_t st) {
     if (nt <= kLaneRestrictTasks)

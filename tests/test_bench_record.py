@@ -69,7 +69,10 @@ def test_vcycle_bytes_counts_every_launch_of_the_cycle():
     m = [128 ** 3 // 8 ** l for l in range(7)]
     want3 = 0.0
     for l in range(4):
-        launches = [52] * 8 + [8 * (8 + 9 / 8), 8 * (6 + 6 / 8)]
+        # the finest level reads no f_phi, f_p: 44 B per color launch, and its
+        # residual + restriction (z marching, 128^3 >= 2^20 cells) 6 values
+        launches = ([44] * 8 + [8 * (6 + 9 / 8), 8 * (6 + 6 / 8)] if l == 0
+                    else [52] * 8 + [8 * (8 + 9 / 8), 8 * (6 + 6 / 8)])
         if l < 3:
             launches.append(8 * 11 / 8)          # right-hand side of the next level
         want3 += sum(launches) * m[l]
