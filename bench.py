@@ -71,7 +71,7 @@ def launch_bytes_per_cell(dim, cls, mixed=False, kind=None):
                  phi^m, f_mu (FP64) read; u + e (FP64), the three FP32
                  right-hand sides and b written:
                  24 + 12 + 24 + 24 + 12 + 4                                 = 100 B
-                 (88 B in the launch of the step's setup, which reads no e)
+                 (the step's setup forms the first right-hand side itself)
     """
     if cls == "refine":
         return 100.0
@@ -392,7 +392,7 @@ def run_batched(args, pool):
     # algorithmic bytes of the timed class's launches in the timed region: each
     # launch covers the instances still active in that refinement step
     if cls == "refine":
-        per_launch_cells = cells * args.steps * 88 + sum(
+        per_launch_cells = sum(
             sizes[i] * refine[m][i] for m in range(args.steps) for i in range(len(insts))) * 100
         bytes_launch = per_launch_cells / max(1, tim[cls][1])
         name = ("finest-level FP64 refinement launch over the batch (u += e, residual of "
@@ -630,7 +630,7 @@ def run_single(args, name, cpu_baseline=True, parity=True, breakdown=True, copy_
     level_kernels = sv.level_kernels()
     kind0 = level_kernels[0][0]
     if cls == "refine":
-        bytes_launch = (cells * 88 * args.steps + cells * 100 * vcyc) / max(1, tim[cls][1])
+        bytes_launch = cells * 100 * vcyc / max(1, tim[cls][1])
     else:
         bytes_launch = launch_bytes_per_cell(dim, cls, mixed, kind0) * cells
     traffic = measured_traffic(name, cls, level_kernels[0])

@@ -1746,12 +1746,12 @@ int setup(chhs_ctx* c, const double* phi_prev, const double* phi_cur, const doub
         chhs::launch_fill_int(c->act_next, c->n_inst, 1, c->stream);
         chhs::launch_fill_int(c->cycles, c->n_inst, 0, c->stream);
         chhs::launch_copy_int(c->act_cycle, c->act_next, c->n_inst, c->stream);
-        // the plain path forms the initial residual's norm partials in the same pass
-        // (mixed precision: the FP32 frozen fields of the finest level too)
+        // the initial residual's norm partials in the same pass (mixed
+        // precision: also the FP32 frozen fields of the finest level and the
+        // residual as the first correction cycle's right-hand side)
         const Batch<float> f32 = c->mixed ? batch32(c, 0, nullptr) : Batch<float>{};
         chhs::launch_setup(dim, batch(c, 0, nullptr), c->A[0].dev, c->A[0].n, c->dinfo, phi_prev,
-                           phi_cur, mu, p, c->mixed ? nullptr : c->partial,
-                           c->mixed ? &f32 : nullptr, c->stream);
+                           phi_cur, mu, p, c->partial, c->mixed ? &f32 : nullptr, c->stream);
         if (c->mixed) {
             for (int l = 0; l < c->lay.chain_from; ++l)
                 chhs::launch_restrict_frozen(dim, batch32(c, l, nullptr), c->A[l + 1].dev,
@@ -1767,7 +1767,16 @@ int setup(chhs_ctx* c, const double* phi_prev, const double* phi_cur, const doub
         }
     }
     if (c->mixed) {
-        enqueue_refinement(c, false, false);
+        // the residual of the initial guess came with the setup pass: its
+        // norms and the flags, as a refinement step without a correction
+        // would leave them (u stays in the current FP64 copy)
+        TimedScope t(c, CHHS_K_NORM);
+        chhs::launch_roll_flags(c->act_last, c->act_cycle, c->act_next, c->n_inst, c->stream);
+        const double* src;
+        const Range* rng;
+        fold_cells(c, false, nullptr, &src, &rng);
+        chhs::launch_inst_reduce(src, rng, nullptr, nullptr, 0, c->dinfo, nullptr, c->act_next,
+                                 c->cycles, c->res, c->n_inst, c->opts.tol, 1 << 30, 0, c->stream);
     } else {
         TimedScope t(c, CHHS_K_NORM);
         const double* src;

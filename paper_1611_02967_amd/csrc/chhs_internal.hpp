@@ -150,7 +150,8 @@ struct Batch {
 // With partial: also the norm partials of the initial guess's residual, as
 // launch_residual_partials gives them (one per task).  With frozen32 (mixed
 // precision): also phi_* and phi^m rounded to FP32 on the finest level of that
-// hierarchy (its copy 0).
+// hierarchy, and with partial the residual rounded to FP32 as that level's
+// right-hand side and b = phi^m.
 void launch_setup(int dim, const Batch<double>& b, const CellTask* t, int nt, const InstInfo* info,
                   const double* phi_prev, const double* phi_cur, const double* mu,
                   const double* p, double* partial, const Batch<float>* frozen32, hipStream_t st);

@@ -37,7 +37,10 @@ __device__ __forceinline__ void block_sum(double (&v)[NC], double* out);
 // initial guess u = (phi^m, mu, p) in the same pass: its norm partials (R_phi^2,
 // R_mu^2, R_p^2, p) per block, as k_residual_partials gives them, formed from
 // the caller's arrays (the values the level receives here), with N(u) written
-// as cell_operator writes it.
+// as cell_operator writes it.  With e32 (mixed precision): the FP32 copies of
+// phi_* and phi^m, and with `partial` also the residual rounded to FP32 as the
+// first correction cycle's right-hand side and b = phi (what a refinement step
+// without a correction writes).
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_setup(Batch<double> b, const CellTask* __restrict__ t,
                                                   const InstInfo* __restrict__ info,
@@ -109,6 +112,15 @@ __global__ __launch_bounds__(kBlock) void k_setup(Batch<double> b, const CellTas
             v[1] = r1 * r1;
             v[2] = r2 * r2;
             v[3] = pp;
+            if (e32.desc != nullptr) {
+                // mixed precision: the right-hand side of the first FP32
+                // correction cycle (this residual) and its base state b = phi
+                const Level<float> E = view_at(e32, tk.inst, 0, 0);
+                E.f0[idx] = float(r0);
+                E.f1[idx] = float(r1);
+                E.f2[idx] = float(r2);
+                E.b[idx] = float(pc);
+            }
         }
     }
     if (partial == nullptr) return;
