@@ -577,13 +577,14 @@ __device__ __forceinline__ void block_sum(double (&v)[NC], double* out) {
     __syncthreads();
 }
 
+template <int NT = kBlock>
 __device__ __forceinline__ double block_max(double v) {
     for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
-    __shared__ double shm[kBlock / 64];
+    __shared__ double shm[NT / 64];
     if ((threadIdx.x & 63) == 0) shm[threadIdx.x >> 6] = v;
     __syncthreads();
     double m = 0.0;
-    for (int w = 0; w < kBlock / 64; ++w) m = fmax(m, shm[w]);
+    for (int w = 0; w < NT / 64; ++w) m = fmax(m, shm[w]);
     __syncthreads();
     return m;
 }
@@ -707,8 +708,13 @@ __global__ __launch_bounds__(kBlock) void k_shift_p(Batch<double> b, const CellT
     L.p[idx] -= res[tk.inst * kResStride + 4];
 }
 
+// Half a task's width of threads, each taking two cells of the task (kBlock
+// apart): half the workgroups and half the block reductions for the same
+// loads in flight.
+constexpr int kEnergyThreads = kBlock / 2;
+
 template <int DIM>
-__global__ __launch_bounds__(kBlock) void k_energy_partials(Batch<double> b,
+__global__ __launch_bounds__(kEnergyThreads) void k_energy_partials(Batch<double> b,
                                                             const CellTask* __restrict__ t,
                                                             const InstInfo* __restrict__ info,
                                                             int ws, const double* __restrict__ phi_c,
@@ -723,8 +729,10 @@ __global__ __launch_bounds__(kBlock) void k_energy_partials(Batch<double> b,
     const double* q = ws ? L.psi : q_c + off;
     double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     double vmax = 0.0;
-    const int idx = tk.cell0 + threadIdx.x;
-    if (idx < L.n) {
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+        const int idx = tk.cell0 + threadIdx.x + half * kEnergyThreads;
+        if (idx >= L.n) continue;
         int i, j, k;
         decode<DIM>(idx, L.nx, L.ny, i, j, k);
         // (global-address-space loads: the block reductions below wait on
@@ -732,11 +740,11 @@ __global__ __launch_bounds__(kBlock) void k_energy_partials(Batch<double> b,
         const double f = gload(phi, idx);
         const double qc = gload(q, idx);
         const double d = f - qc;
-        v[0] = f;
-        v[1] = f * f;
-        v[2] = f * f * f * f;
-        v[4] = d * d;
-        vmax = fabs(f);
+        v[0] += f;
+        v[1] += f * f;
+        v[2] += f * f * f * f;
+        v[4] += d * d;
+        vmax = fmax(vmax, fabs(f));
         const double muc = ws ? gload(L.mu, idx) : 0.0;
         const double pc = ws ? gload(L.p, idx) : 0.0;
         const double psc = ws ? gload(L.pstar, idx) : 0.0;
@@ -769,8 +777,8 @@ __global__ __launch_bounds__(kBlock) void k_energy_partials(Batch<double> b,
         }
     }
     double out[8];
-    block_sum<8>(v, out);
-    const double m = block_max(vmax);
+    block_sum<8, kEnergyThreads>(v, out);
+    const double m = block_max<kEnergyThreads>(vmax);
     if (threadIdx.x == 0) {
         double* pp = partial + task * kPartialStride;
         for (int c = 0; c < 8; ++c) pp[c] = out[c];
@@ -1070,7 +1078,13 @@ void launch_energy_partials(int dim, const Batch<double>& b, const CellTask* t, 
                             const InstInfo* info, int ws, const double* phi, const double* q,
                             double* partial, hipStream_t st, const CopyOut* copy) {
     const CopyOut co = copy != nullptr ? *copy : CopyOut{nullptr, nullptr, nullptr, nullptr};
-    CHHS_DISPATCH(dim, k_energy_partials, nt, b, t, info, ws, phi, q, partial, co);
+    if (nt <= 0) return;
+    if (dim == 2)
+        hipLaunchKernelGGL(k_energy_partials<2>, dim3(nt), dim3(kEnergyThreads), 0, st, b, t, info,
+                           ws, phi, q, partial, co);
+    else
+        hipLaunchKernelGGL(k_energy_partials<3>, dim3(nt), dim3(kEnergyThreads), 0, st, b, t, info,
+                           ws, phi, q, partial, co);
 }
 
 void launch_energy_reduce(const double* partial, const Range* ranges, const InstInfo* info,
