@@ -41,91 +41,199 @@ __device__ __forceinline__ void block_sum(double (&v)[NC], double* out);
 // phi_* and phi^m, and with `partial` also the residual rounded to FP32 as the
 // first correction cycle's right-hand side and b = phi (what a refinement step
 // without a correction writes).
+//
+// kPairThreads threads per 256-cell task.  Where the instance's x extent is
+// even and its arrays allow 2-element accesses (FP64 ones 16-byte aligned,
+// FP32 ones 8-byte), a thread takes a pair of x-adjacent cells (2-element loads and stores, the pair's inner faces read
+// from registers); otherwise cells q and q + kPairThreads of the task.  Both
+// forms sum each cell's faces in the order of for_each_face.
+constexpr int kPairThreads = kBlock / 2;
+
 template <int DIM>
-__global__ __launch_bounds__(kBlock) void k_setup(Batch<double> b, const CellTask* __restrict__ t,
-                                                  const InstInfo* __restrict__ info,
-                                                  const double* __restrict__ phi_prev,
-                                                  const double* __restrict__ phi_cur,
-                                                  const double* __restrict__ mu,
-                                                  const double* __restrict__ p, double* partial,
-                                                  Batch<float> e32) {
+__global__ __launch_bounds__(kPairThreads) void k_setup(Batch<double> b,
+                                                        const CellTask* __restrict__ t,
+                                                        const InstInfo* __restrict__ info,
+                                                        const double* __restrict__ phi_prev,
+                                                        const double* __restrict__ phi_cur,
+                                                        const double* __restrict__ mu,
+                                                        const double* __restrict__ p,
+                                                        double* partial, Batch<float> e32) {
+    typedef double D2 __attribute__((ext_vector_type(2)));
+    typedef float F2 __attribute__((ext_vector_type(2)));
     const int task = xcd_task();
     const CellTask tk = t[task];
     const Level<double> L = view_at(b, tk.inst, 0, b.cur);
-    const int idx = tk.cell0 + threadIdx.x;
+    const InstInfo in = info[tk.inst];
+    const bool res = partial != nullptr;
+    const bool mixed = e32.desc != nullptr;
+    const Level<float> E = mixed ? view_at(e32, tk.inst, 0, 0) : Level<float>{};
+    // the first-order step (order 1): phi_* := phi^m and f_mu = -phi^m
+    const bool first = in.order == 1;
+    const double q = 0.25 * in.eps * in.eps / (in.h * in.h);
     double v[4] = {0.0, 0.0, 0.0, 0.0};
-    if (idx < L.n) {
-        const InstInfo in = info[tk.inst];
-        const int g = in.off + idx;
-        int i, j, k;
-        decode<DIM>(idx, L.nx, L.ny, i, j, k);
-        const double pm = phi_prev[g];
-        const double pc = phi_cur[g];
-        const double muc = mu[g], pp = p[g];
-        // the first-order step (order 1): phi_* := phi^m and f_mu = -phi^m
-        const bool first = in.order == 1;
-        const double ps = first ? pc : 1.5 * pc - 0.5 * pm;   // phi_*, (2.4)
-        double lap = 0.0;
-        double smm = 0, sap = 0, sphi = 0, sp = 0, samu = 0;
-        for_each_face<DIM>(i, j, k, L.nx, L.ny, L.nz, idx, [&](bool h, int nb) {
-            const int gn = in.off + nb;
-            const double pmn = phi_prev[gn];
-            const double d = pmn - pm;
-            lap = h ? lap + d : lap;
-            if (partial != nullptr) {
-                const double pcn = phi_cur[gn];
-                const double a = 0.5 * (ps + (first ? pcn : 1.5 * pcn - 0.5 * pmn));
-                const double m = 1.0 + L.gamma * a * a;
-                const double dmu = mu[gn] - muc;
-                const double dp = p[gn] - pp;
-                const double dphi = pcn - pc;
-                smm = h ? smm + m * dmu : smm;
-                sap = h ? sap + a * dp : sap;
-                sphi = h ? sphi + dphi : sphi;
-                sp = h ? sp + dp : sp;
-                samu = h ? samu + a * dmu : samu;
-            }
-        });
-        const double q = 0.25 * in.eps * in.eps / (in.h * in.h);
-        const double f1 = first ? -pc : -ps - q * lap;
-        L.pstar[idx] = ps;
-        L.psi[idx] = pc;
-        if (e32.desc != nullptr) {
-            // the FP32 hierarchy's frozen fields (mixed precision)
-            const Level<float> E = view_at(e32, tk.inst, 0, 0);
-            E.pstar[idx] = float(ps);
-            E.psi[idx] = float(pc);
+
+    // One face of a cell (values pm, pc, ps, muc, pp) with the neighbour
+    // (pmn, pcn, mun, pn): the Laplacian of phi^{m-1} and N(u)'s face sums.
+    struct Acc {
+        double lap = 0, smm = 0, sap = 0, sphi = 0, sp = 0, samu = 0;
+    };
+    auto face = [&](Acc& s, bool h, double pm, double pc, double ps, double muc, double pp,
+                    double pmn, double pcn, double mun, double pn) {
+        const double d = pmn - pm;
+        s.lap = h ? s.lap + d : s.lap;
+        if (res) {
+            const double a = 0.5 * (ps + (first ? pcn : 1.5 * pcn - 0.5 * pmn));
+            const double m = 1.0 + L.gamma * a * a;
+            const double dmu = mun - muc;
+            const double dp = pn - pp;
+            const double dphi = pcn - pc;
+            s.smm = h ? s.smm + m * dmu : s.smm;
+            s.sap = h ? s.sap + a * dp : s.sap;
+            s.sphi = h ? s.sphi + dphi : s.sphi;
+            s.sp = h ? s.sp + dp : s.sp;
+            s.samu = h ? s.samu + a * dmu : s.samu;
         }
-        L.f0[idx] = pc;                                   // (2.5): phi^m
-        L.f1[idx] = f1;                                   // (2.6): -phi_* - eps^2/4 Lap phi^{m-1}
-        L.f2[idx] = 0.0;                                  // (2.7)
-        L.phi[idx] = pc;                                  // initial guess phi^m
-        L.mu[idx] = muc;
-        L.p[idx] = pp;
-        if (partial != nullptr) {
+    };
+    // phi_* (2.4), f_mu (2.6), and the residual of the initial guess
+    auto finish = [&](const Acc& s, double pc, double ps, double muc, double pp, double& f1,
+                      double& r0, double& r1, double& r2) {
+        f1 = first ? -pc : -ps - q * s.lap;
+        if (res) {
             const double chi = first ? pc * pc * pc : nonlin<double, false>(pc, pc, 0.0);
-            const double n0 = pc - L.lam * smm - L.lam * sap;
-            const double n1 = muc - chi + L.kap * sphi;
-            const double n2 = L.lam * sp + L.lam * L.gamma * samu;
-            const double r0 = pc - n0, r1 = f1 - n1, r2 = -n2;
-            v[0] = r0 * r0;
-            v[1] = r1 * r1;
-            v[2] = r2 * r2;
-            v[3] = pp;
-            if (e32.desc != nullptr) {
-                // mixed precision: the right-hand side of the first FP32
-                // correction cycle (this residual) and its base state b = phi
-                const Level<float> E = view_at(e32, tk.inst, 0, 0);
-                E.f0[idx] = float(r0);
-                E.f1[idx] = float(r1);
-                E.f2[idx] = float(r2);
-                E.b[idx] = float(pc);
+            const double n0 = pc - L.lam * s.smm - L.lam * s.sap;
+            const double n1 = muc - chi + L.kap * s.sphi;
+            const double n2 = L.lam * s.sp + L.lam * L.gamma * s.samu;
+            r0 = pc - n0;
+            r1 = f1 - n1;
+            r2 = -n2;
+            v[0] += r0 * r0;
+            v[1] += r1 * r1;
+            v[2] += r2 * r2;
+            v[3] += pp;
+        }
+    };
+    auto phistar = [&](double pm, double pc) { return first ? pc : 1.5 * pc - 0.5 * pm; };
+
+    const uintptr_t bits64 =
+        uintptr_t(phi_prev) | uintptr_t(phi_cur) | uintptr_t(mu) | uintptr_t(p) |
+        uintptr_t(L.pstar) | uintptr_t(L.psi) | uintptr_t(L.f0) | uintptr_t(L.f1) |
+        uintptr_t(L.f2) | uintptr_t(L.phi) | uintptr_t(L.mu) | uintptr_t(L.p);
+    const uintptr_t bits32 =
+        mixed ? uintptr_t(E.pstar) | uintptr_t(E.psi) | uintptr_t(E.f0) | uintptr_t(E.f1) |
+                    uintptr_t(E.f2) | uintptr_t(E.b)
+              : uintptr_t(0);
+    // (FP64 pairs take 16-byte alignment, FP32 pairs 8-byte)
+    const bool pairs =
+        (L.nx & 1) == 0 && (in.off & 1) == 0 && (bits64 & 15) == 0 && (bits32 & 7) == 0;
+
+    if (pairs) {
+        const int idx = tk.cell0 + 2 * int(threadIdx.x);   // first cell of the pair
+        if (idx < L.n) {
+            int i, j, k;
+            decode<DIM>(idx, L.nx, L.ny, i, j, k);
+            const int g = in.off + idx;
+            auto ld2 = [&](const double* a, int c) {
+                return gload(reinterpret_cast<const D2*>(a), c >> 1);
+            };
+            const D2 pm = ld2(phi_prev, g), pc = ld2(phi_cur, g);
+            const D2 muc = ld2(mu, g), pp = ld2(p, g);
+            const D2 ps = {phistar(pm.x, pc.x), phistar(pm.y, pc.y)};
+            // outer x neighbours (the cell itself across a boundary face)
+            const bool hl = i > 0, hr = i + 2 < L.nx;
+            const int ql = hl ? g - 1 : g, qr = hr ? g + 2 : g + 1;
+            const double pml = gload(phi_prev, ql), pmr = gload(phi_prev, qr);
+            const double pcl = res ? gload(phi_cur, ql) : 0.0, pcr = res ? gload(phi_cur, qr) : 0.0;
+            const double mul = res ? gload(mu, ql) : 0.0, mur = res ? gload(mu, qr) : 0.0;
+            const double pl = res ? gload(p, ql) : 0.0, pr = res ? gload(p, qr) : 0.0;
+            Acc sa, sb;
+            face(sa, hl, pm.x, pc.x, ps.x, muc.x, pp.x, pml, pcl, mul, pl);
+            face(sa, true, pm.x, pc.x, ps.x, muc.x, pp.x, pm.y, pc.y, muc.y, pp.y);
+            face(sb, true, pm.y, pc.y, ps.y, muc.y, pp.y, pm.x, pc.x, muc.x, pp.x);
+            face(sb, hr, pm.y, pc.y, ps.y, muc.y, pp.y, pmr, pcr, mur, pr);
+            // y (and z) neighbour pairs: -y, +y (, -z, +z)
+            const int sz = L.nx * L.ny;
+            const int off[4] = {-L.nx, L.nx, -sz, sz};
+            const bool has[4] = {j > 0, j < L.ny - 1, k > 0, k < L.nz - 1};
+#pragma unroll
+            for (int f = 0; f < 2 * (DIM - 1); ++f) {
+                const int qn = has[f] ? g + off[f] : g;
+                const D2 pmn = ld2(phi_prev, qn);
+                const D2 pcn = res ? ld2(phi_cur, qn) : D2{0.0, 0.0};
+                const D2 mun = res ? ld2(mu, qn) : D2{0.0, 0.0};
+                const D2 pn = res ? ld2(p, qn) : D2{0.0, 0.0};
+                face(sa, has[f], pm.x, pc.x, ps.x, muc.x, pp.x, pmn.x, pcn.x, mun.x, pn.x);
+                face(sb, has[f], pm.y, pc.y, ps.y, muc.y, pp.y, pmn.y, pcn.y, mun.y, pn.y);
+            }
+            double fa, fb, ra0 = 0, ra1 = 0, ra2 = 0, rb0 = 0, rb1 = 0, rb2 = 0;
+            finish(sa, pc.x, ps.x, muc.x, pp.x, fa, ra0, ra1, ra2);
+            finish(sb, pc.y, ps.y, muc.y, pp.y, fb, rb0, rb1, rb2);
+            const int hw = idx >> 1;
+            auto st2 = [&](double* a, D2 x) { gstore(reinterpret_cast<D2*>(a), hw, x); };
+            auto st2f = [&](float* a, double x, double y) {
+                gstore(reinterpret_cast<F2*>(a), hw, F2{float(x), float(y)});
+            };
+            st2(L.pstar, ps);
+            st2(L.psi, pc);
+            st2(L.f0, pc);                                 // (2.5): phi^m
+            st2(L.f1, D2{fa, fb});                         // (2.6)
+            st2(L.f2, D2{0.0, 0.0});                       // (2.7)
+            st2(L.phi, pc);                                // initial guess phi^m
+            st2(L.mu, muc);
+            st2(L.p, pp);
+            if (mixed) {
+                st2f(E.pstar, ps.x, ps.y);
+                st2f(E.psi, pc.x, pc.y);
+                if (res) {
+                    st2f(E.f0, ra0, rb0);
+                    st2f(E.f1, ra1, rb1);
+                    st2f(E.f2, ra2, rb2);
+                    st2f(E.b, pc.x, pc.y);
+                }
+            }
+        }
+    } else {
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+            const int idx = tk.cell0 + int(threadIdx.x) + half * kPairThreads;
+            if (idx >= L.n) continue;
+            const int g = in.off + idx;
+            int i, j, k;
+            decode<DIM>(idx, L.nx, L.ny, i, j, k);
+            const double pm = gload(phi_prev, g), pc = gload(phi_cur, g);
+            const double muc = gload(mu, g), pp = gload(p, g);
+            const double ps = phistar(pm, pc);
+            Acc s;
+            for_each_face<DIM>(i, j, k, L.nx, L.ny, L.nz, idx, [&](bool h, int nb) {
+                const int gn = in.off + nb;
+                face(s, h, pm, pc, ps, muc, pp, gload(phi_prev, gn),
+                     res ? gload(phi_cur, gn) : 0.0, res ? gload(mu, gn) : 0.0,
+                     res ? gload(p, gn) : 0.0);
+            });
+            double f1, r0 = 0, r1 = 0, r2 = 0;
+            finish(s, pc, ps, muc, pp, f1, r0, r1, r2);
+            gstore(L.pstar, idx, ps);
+            gstore(L.psi, idx, pc);
+            gstore(L.f0, idx, pc);
+            gstore(L.f1, idx, f1);
+            gstore(L.f2, idx, 0.0);
+            gstore(L.phi, idx, pc);
+            gstore(L.mu, idx, muc);
+            gstore(L.p, idx, pp);
+            if (mixed) {
+                gstore(E.pstar, idx, float(ps));
+                gstore(E.psi, idx, float(pc));
+                if (res) {
+                    gstore(E.f0, idx, float(r0));
+                    gstore(E.f1, idx, float(r1));
+                    gstore(E.f2, idx, float(r2));
+                    gstore(E.b, idx, float(pc));
+                }
             }
         }
     }
-    if (partial == nullptr) return;
+    if (!res) return;
     double out[4];
-    block_sum<4>(v, out);
+    block_sum<4, kPairThreads>(v, out);
     if (threadIdx.x == 0)
         for (int c = 0; c < 4; ++c) partial[task * kPartialStride + c] = out[c];
 }
@@ -420,7 +528,6 @@ __global__ __launch_bounds__(kBlock) void k_zero_correction(Batch<float> b32,
 // whole pairs of one row each.  The pair's own values and its y (and z)
 // neighbours load as 2-element vectors, the pair's outer x neighbours as
 // single values; each cell sums its faces in the order of for_each_face.
-constexpr int kPairThreads = kBlock / 2;
 
 template <int DIM>
 __global__ __launch_bounds__(kPairThreads) void k_mixed_residual(Batch<double> b64,
@@ -890,7 +997,13 @@ void launch_setup(int dim, const Batch<double>& b, const CellTask* t, int nt, co
                   hipStream_t st) {
     Batch<float> e32{};
     if (frozen32 != nullptr) e32 = *frozen32;
-    CHHS_DISPATCH(dim, k_setup, nt, b, t, info, phi_prev, phi_cur, mu, p, partial, e32);
+    if (nt <= 0) return;
+    if (dim == 2)
+        hipLaunchKernelGGL(k_setup<2>, dim3(nt), dim3(kPairThreads), 0, st, b, t, info, phi_prev,
+                           phi_cur, mu, p, partial, e32);
+    else
+        hipLaunchKernelGGL(k_setup<3>, dim3(nt), dim3(kPairThreads), 0, st, b, t, info, phi_prev,
+                           phi_cur, mu, p, partial, e32);
 }
 
 #define CHHS_DISPATCH_T(dim, KERNEL, GRID, ...)                                           \

@@ -116,6 +116,43 @@ def test_batch_matches_oracle_per_instance(chhs, spec):
             assert abs(ps[i].mean()) <= 1e-13
 
 
+def _shifted(a):
+    """A device copy of `a` that starts 8 bytes past a 16-byte boundary."""
+    import torch
+    buf = torch.empty(a.size + 1, dtype=torch.float64, device="cuda")
+    t = buf[1:]
+    t.copy_(torch.from_numpy(np.ascontiguousarray(a)))
+    assert t.data_ptr() % 16 == 8
+    return t
+
+
+@pytest.mark.parametrize("spec", [RAGGED_2D, RAGGED_3D], ids=["2d", "3d"])
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_caller_arrays_off_16_byte_alignment(chhs, spec, precision):
+    """Caller arrays 8 bytes off a 16-byte boundary: the setup pass takes its
+    one-cell-per-access form instead of x-adjacent pairs; both form every
+    cell's values with the same operations, so the steps agree."""
+    shapes = [s[0] for s in spec]
+    phi0s = [uniform_field(sh, 3300 + i, mean=sp[4], amp=0.05) for i, (sh, sp) in
+             enumerate(zip(shapes, spec))]
+    flat = _pack(phi0s)
+    out = []
+    for make in (dev, _shifted):
+        probs = [chhs.make_problem(sh, 1.0 / sh[-1], e, g, s) for sh, e, g, s, _ in spec]
+        sv = chhs.Solver(probs, chhs.chhs_default_opts(precision=precision))
+        tp, tc = make(flat), make(flat)
+        tm, tpp = make(np.zeros(flat.size)), make(np.zeros(flat.size))
+        steps = []
+        for _ in range(2):
+            _, st = sv.step(tp, tc, tm, tpp, 1)
+            steps.append(([host(x).copy() for x in (tc, tm, tpp)], [x["vcycles"] for x in st]))
+        out.append(steps)
+    for (fa, ca), (fb, cb) in zip(*out):
+        assert ca == cb
+        for a, b in zip(fa, fb):
+            assert np.max(np.abs(a - b)) <= 1e-12
+
+
 def test_graph_replay_equals_eager_launches(chhs):
     spec = RAGGED_2D
     shapes = [s[0] for s in spec]
