@@ -815,9 +815,10 @@ __global__ __launch_bounds__(kBlock) void k_shift_p(Batch<double> b, const CellT
     L.p[idx] -= res[tk.inst * kResStride + 4];
 }
 
-// Half a task's width of threads, each taking two cells of the task (kBlock
-// apart): half the workgroups and half the block reductions for the same
-// loads in flight.
+// Half a task's width of threads, each taking two cells of the task: a pair of
+// x-adjacent cells (2-element loads and stores, the pair's inner face from
+// registers) where the instance's x extent is even and its arrays are 16-byte
+// aligned, otherwise cells q and q + kEnergyThreads.
 constexpr int kEnergyThreads = kBlock / 2;
 
 template <int DIM>
@@ -827,6 +828,7 @@ __global__ __launch_bounds__(kEnergyThreads) void k_energy_partials(Batch<double
                                                             int ws, const double* __restrict__ phi_c,
                                                             const double* __restrict__ q_c,
                                                             double* partial, CopyOut co) {
+    typedef double D2 __attribute__((ext_vector_type(2)));
     const int task = xcd_task();
     const CellTask tk = t[task];
     const Level<double> L = view_at(b, tk.inst, 0, b.cur);
@@ -834,53 +836,115 @@ __global__ __launch_bounds__(kEnergyThreads) void k_energy_partials(Batch<double
     const double gamma = L.gamma;
     const double* phi = ws ? L.phi : phi_c + off;
     const double* q = ws ? L.psi : q_c + off;
+    const bool copy = ws && co.phi_cur != nullptr;
+    // the copy-out of the step (phi^m is the workspace's psi); the instance's
+    // own base pointers keep the 32-bit offsets in range
+    double* const cp_prev = copy ? co.phi_prev + off : nullptr;
+    double* const cp_cur = copy ? co.phi_cur + off : nullptr;
+    double* const cp_mu = copy ? co.mu + off : nullptr;
+    double* const cp_p = copy ? co.p + off : nullptr;
+    const double psh = copy && b.pshift != nullptr ? b.pshift[tk.inst * kResStride + 4] : 0.0;
     double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     double vmax = 0.0;
-#pragma unroll
-    for (int half = 0; half < 2; ++half) {
-        const int idx = tk.cell0 + threadIdx.x + half * kEnergyThreads;
-        if (idx >= L.n) continue;
-        int i, j, k;
-        decode<DIM>(idx, L.nx, L.ny, i, j, k);
-        // (global-address-space loads: the block reductions below wait on
-        // LDS without also waiting for outstanding global accesses)
-        const double f = gload(phi, idx);
-        const double qc = gload(q, idx);
+    // a cell's own terms (phi, phi^m): mass, the two potentials, |phi - phi^m|^2
+    auto own = [&](double f, double qc) {
         const double d = f - qc;
         v[0] += f;
         v[1] += f * f;
         v[2] += f * f * f * f;
         v[4] += d * d;
         vmax = fmax(vmax, fabs(f));
-        const double muc = ws ? gload(L.mu, idx) : 0.0;
-        const double pc = ws ? gload(L.p, idx) : 0.0;
-        const double psc = ws ? gload(L.pstar, idx) : 0.0;
-        // forward faces only: every interior face counted once
-        auto face = [&](int nb) {
-            const double fn = gload(phi, nb);
-            const double df = fn - f;
-            const double dd = (fn - gload(q, nb)) - d;
-            v[3] += df * df;
-            v[5] += dd * dd;
-            if (ws) {
-                const double dm = gload(L.mu, nb) - muc;
-                const double a = 0.5 * (psc + gload(L.pstar, nb));
-                const double u = -(gload(L.p, nb) - pc) - gamma * a * dm;
-                v[6] += dm * dm;
-                v[7] += u * u;
+    };
+    // a forward face (every interior face counted once): the cell (f, phi^m
+    // difference d, mu, p, phi_*) and its neighbour (fn, qn, mun, pn, psn)
+    auto face = [&](double f, double d, double muc, double pc, double psc, double fn,
+                    double qn, double mun, double pn, double psn) {
+        const double df = fn - f;
+        const double dd = (fn - qn) - d;
+        v[3] += df * df;
+        v[5] += dd * dd;
+        if (ws) {
+            const double dm = mun - muc;
+            const double a = 0.5 * (psc + psn);
+            const double u = -(pn - pc) - gamma * a * dm;
+            v[6] += dm * dm;
+            v[7] += u * u;
+        }
+    };
+    const uintptr_t bits = uintptr_t(phi) | uintptr_t(q) |
+                           (ws ? uintptr_t(L.mu) | uintptr_t(L.p) | uintptr_t(L.pstar) : 0) |
+                           (copy ? uintptr_t(cp_prev) | uintptr_t(cp_cur) | uintptr_t(cp_mu) |
+                                       uintptr_t(cp_p)
+                                 : 0);
+    // (global-address-space loads: the block reductions below wait on LDS
+    // without also waiting for outstanding global accesses)
+    if ((L.nx & 1) == 0 && (bits & 15) == 0) {
+        const int idx = tk.cell0 + 2 * int(threadIdx.x);   // first cell of the pair
+        if (idx < L.n) {
+            int i, j, k;
+            decode<DIM>(idx, L.nx, L.ny, i, j, k);
+            auto ld2 = [&](const double* a, int c) {
+                return gload(reinterpret_cast<const D2*>(a), c >> 1);
+            };
+            const D2 z2 = {0.0, 0.0};
+            const D2 f = ld2(phi, idx), qc = ld2(q, idx);
+            const D2 muc = ws ? ld2(L.mu, idx) : z2, pc = ws ? ld2(L.p, idx) : z2;
+            const D2 psc = ws ? ld2(L.pstar, idx) : z2;
+            const D2 d = f - qc;
+            own(f.x, qc.x);
+            own(f.y, qc.y);
+            face(f.x, d.x, muc.x, pc.x, psc.x, f.y, qc.y, muc.y, pc.y, psc.y);
+            if (i + 2 < L.nx) {
+                const int r = idx + 2;
+                face(f.y, d.y, muc.y, pc.y, psc.y, gload(phi, r), gload(q, r),
+                     ws ? gload(L.mu, r) : 0.0, ws ? gload(L.p, r) : 0.0,
+                     ws ? gload(L.pstar, r) : 0.0);
             }
-        };
-        if (i < L.nx - 1) face(idx + 1);
-        if (j < L.ny - 1) face(idx + L.nx);
-        if (DIM == 3 && k < L.nz - 1) face(idx + L.nx * L.ny);
-        if (ws && co.phi_cur != nullptr) {
-            // the copy-out of the step (phi^m is the workspace's psi); the
-            // instance's own base pointers keep the 32-bit offsets in range
-            const double psh = b.pshift != nullptr ? b.pshift[tk.inst * kResStride + 4] : 0.0;
-            gstore(co.phi_prev + off, idx, qc);
-            gstore(co.phi_cur + off, idx, f);
-            gstore(co.mu + off, idx, muc);
-            gstore(co.p + off, idx, pc - psh);
+            auto face2 = [&](int nb) {
+                const D2 fn = ld2(phi, nb), qn = ld2(q, nb);
+                const D2 mun = ws ? ld2(L.mu, nb) : z2, pn = ws ? ld2(L.p, nb) : z2;
+                const D2 psn = ws ? ld2(L.pstar, nb) : z2;
+                face(f.x, d.x, muc.x, pc.x, psc.x, fn.x, qn.x, mun.x, pn.x, psn.x);
+                face(f.y, d.y, muc.y, pc.y, psc.y, fn.y, qn.y, mun.y, pn.y, psn.y);
+            };
+            if (j < L.ny - 1) face2(idx + L.nx);
+            if (DIM == 3 && k < L.nz - 1) face2(idx + L.nx * L.ny);
+            if (copy) {
+                const int h = idx >> 1;
+                gstore(reinterpret_cast<D2*>(cp_prev), h, qc);
+                gstore(reinterpret_cast<D2*>(cp_cur), h, f);
+                gstore(reinterpret_cast<D2*>(cp_mu), h, muc);
+                gstore(reinterpret_cast<D2*>(cp_p), h, D2{pc.x - psh, pc.y - psh});
+            }
+        }
+    } else {
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+            const int idx = tk.cell0 + int(threadIdx.x) + half * kEnergyThreads;
+            if (idx >= L.n) continue;
+            int i, j, k;
+            decode<DIM>(idx, L.nx, L.ny, i, j, k);
+            const double f = gload(phi, idx);
+            const double qc = gload(q, idx);
+            const double d = f - qc;
+            own(f, qc);
+            const double muc = ws ? gload(L.mu, idx) : 0.0;
+            const double pc = ws ? gload(L.p, idx) : 0.0;
+            const double psc = ws ? gload(L.pstar, idx) : 0.0;
+            auto face1 = [&](int nb) {
+                face(f, d, muc, pc, psc, gload(phi, nb), gload(q, nb),
+                     ws ? gload(L.mu, nb) : 0.0, ws ? gload(L.p, nb) : 0.0,
+                     ws ? gload(L.pstar, nb) : 0.0);
+            };
+            if (i < L.nx - 1) face1(idx + 1);
+            if (j < L.ny - 1) face1(idx + L.nx);
+            if (DIM == 3 && k < L.nz - 1) face1(idx + L.nx * L.ny);
+            if (copy) {
+                gstore(cp_prev, idx, qc);
+                gstore(cp_cur, idx, f);
+                gstore(cp_mu, idx, muc);
+                gstore(cp_p, idx, pc - psh);
+            }
         }
     }
     double out[8];
