@@ -1562,10 +1562,6 @@ void drop_graphs(chhs_ctx* c) {
     }
 }
 
-// One counted cycle (plain V-cycle or mixed refinement step) with norms and
-// readback, replayed from a captured graph when enabled; returns after the
-// results are on the host.  The graph slot is the FP64 finest level's current
-// copy, which a mixed refinement step flips.
 // Captures the counted cycle into graph slot `slot` (reading back into mirror
 // `buf`) unless already captured; on failure graphs are disabled for the
 // context and the eager path is used.  Timed contexts are not captured (event
@@ -1596,21 +1592,15 @@ void ensure_graph(chhs_ctx* c, int slot, int buf) {
     }
 }
 
+// One cycle (plain V-cycle or mixed refinement step) with norms and readback
+// into mirror 0, launched directly; returns after the results are on the host.
 int run_cycle(chhs_ctx* c, bool count) {
-    const int slot = c->mixed ? c->cur[0] : 0;
     view_results(c, 0);
-    if (count) ensure_graph(c, slot, 0);
-    if (count && c->gexec[slot] != nullptr) {
-        HIP_TRY(hipGraphLaunch(c->gexec[slot], c->stream));
-        c->last_slot = slot;
-        if (c->mixed) c->cur[0] ^= 1;
-    } else {
-        enqueue_cycle(c, count);
-        int rc = check_launch();
-        if (rc) return rc;
-        rc = enqueue_readback(c);
-        if (rc) return rc;
-    }
+    enqueue_cycle(c, count);
+    int rc = check_launch();
+    if (rc) return rc;
+    rc = enqueue_readback(c);
+    if (rc) return rc;
     return sync_results(c);
 }
 
@@ -1632,8 +1622,8 @@ bool expect_more(const chhs_ctx* c, const std::vector<double>& rho) {
     return false;
 }
 
-// The counted cycles of one step until no instance is active.  Plain FP64:
-// while the cycle in flight is not expected to converge, the next one is
+// The counted cycles of one step until no instance is active: while the cycle
+// in flight is not expected to converge, the next one is
 // enqueued before the host reads its results (two pinned mirrors, cycles
 // alternating between them), so the device does not wait for the host's
 // stopping test; near convergence the host reads each cycle first, so that
@@ -1641,25 +1631,25 @@ bool expect_more(const chhs_ctx* c, const std::vector<double>& rho) {
 // one finds every instance inactive on the device and does nothing; its timing
 // events are dropped.  Cycles replay captured graphs (one per mirror) when
 // the stream can be captured and no class is timed, else launch directly.
-// Mixed precision: one refinement step at a time.
+// Mixed precision: a refinement step flips the FP64 finest level's two copies,
+// so slot s is the step that starts from copy s, captured with that copy
+// current and reading back into mirror s; successive steps alternate slots
+// and mirrors as plain cycles do.
 // setup_pending: the step's setup was enqueued without waiting, its norms
-// arriving in the third mirror (plain FP64 only); the first cycle is then
-// enqueued at once (it does nothing for an instance that is converged already).
+// arriving in the third mirror; the first cycle is then enqueued at once (it
+// does nothing for an instance that is converged already).
 int run_cycles(chhs_ctx* c, bool setup_pending = false) {
-    if (c->mixed) {
-        while (any_active(c)) {
-            const int rc = run_cycle(c, true);
-            if (rc) return rc;
-        }
-        return CHHS_OK;
-    }
     if (!setup_pending && !any_active(c)) return CHHS_OK;
     for (int s = 0; s < 2; ++s)
         if (c->cycle_done[s] == nullptr && hipEventCreateWithFlags(&c->cycle_done[s],
                                                                     hipEventDisableTiming) != hipSuccess)
             return CHHS_E_HIP;
-    ensure_graph(c, 0, 0);
-    ensure_graph(c, 1, 1);
+    const int cur0 = c->cur[0];
+    for (int s = 0; s < 2; ++s) {
+        if (c->mixed) c->cur[0] = s;
+        ensure_graph(c, s, s);
+    }
+    c->cur[0] = cur0;
     const bool graphs = c->gexec[0] != nullptr && c->gexec[1] != nullptr;
     // last residual read and the contraction of the last cycle per instance
     // (a typical V-cycle contraction until one has been measured)
@@ -1667,12 +1657,13 @@ int run_cycles(chhs_ctx* c, bool setup_pending = false) {
     if (!setup_pending)
         for (int i = 0; i < c->n_inst; ++i) prev[i] = c->hres[size_t(i) * chhs::kResStride + 3];
     size_t mark[2] = {0, 0};       // pending timing pairs before each mirror's latest cycle
-    int queue[2], nq = 0, next = 0;
+    int queue[2], nq = 0, next = c->mixed ? c->cur[0] : 0;
     auto launch = [&]() -> int {
         const int s = next;
         mark[s] = c->pending.size();
         if (graphs) {
             HIP_TRY(hipGraphLaunch(c->gexec[s], c->stream));
+            if (c->mixed) c->cur[0] ^= 1;    // as the captured step does
         } else {
             enqueue_cycle(c, true);
             int rc = check_launch();
@@ -1736,7 +1727,7 @@ int run_cycles(chhs_ctx* c, bool setup_pending = false) {
 // norms of the initial guess on the host.
 // defer: leave the mean of the initial p pending (the step loop) rather than
 // subtract it at once (callers that read the level's fields).  wait = false
-// (the plain step loop): the norms go to the third mirror and nothing is
+// (the step loop, the cycle tuner): the norms go to the third mirror and nothing is
 // synchronised; the cycle loop reads them with its first cycle.
 int setup(chhs_ctx* c, const double* phi_prev, const double* phi_cur, const double* mu,
           const double* p, bool defer = false, bool wait = true) {
@@ -1883,16 +1874,12 @@ int step_loop(chhs_ctx* c, double* phi_prev, double* phi_cur, double* mu, double
     int rc = log != nullptr ? reserve_log(c, nsteps) : CHHS_OK;
     int done = 0;
     for (int m = 0; m < nsteps && rc == CHHS_OK; ++m) {
-        // plain FP64: the setup is not waited for; its norms come with the first cycle
-        const bool early = !c->mixed;
-        rc = setup(c, phi_prev, phi_cur, mu, p, true, !early);
+        // the setup is not waited for; its norms come with the first cycle
+        rc = setup(c, phi_prev, phi_cur, mu, p, true, false);
         if (rc) break;
-        if (!early)
-            for (int i = 0; i < n; ++i) st[i].res0 = hres_of(c, i)[3];
-        rc = run_cycles(c, early);
+        rc = run_cycles(c, true);
         if (rc) break;
-        if (early)
-            for (int i = 0; i < n; ++i) st[i].res0 = c->hbuf[2][size_t(i) * chhs::kResStride + 3];
+        for (int i = 0; i < n; ++i) st[i].res0 = c->hbuf[2][size_t(i) * chhs::kResStride + 3];
         for (int i = 0; i < n; ++i) {
             const double* r = hres_of(c, i);
             st[i].vcycles = c->hcyc[i];
@@ -2370,7 +2357,6 @@ int chhs_tune_sweeps(chhs_ctx* c, const double* phi_prev, const double* phi_cur,
     const int own_inner = saved.inner_cycles;
     HIP_TRY(hipStreamSynchronize(c->stream));
     resolve_timing(c);
-    const bool early = !c->mixed;
     constexpr int kTuneReps = 3;
     // time to tolerance of one candidate (1e300: it did not converge)
     auto time_of = [&](const Cand& q, double& t) -> int {
@@ -2388,8 +2374,8 @@ int chhs_tune_sweeps(chhs_ctx* c, const double* phi_prev, const double* phi_cur,
         bool ok = true;
         for (int r = 0; r <= kTuneReps && ok; ++r) {
             const auto t0 = std::chrono::steady_clock::now();
-            int rc = setup(c, phi_prev, phi_cur, mu, p, true, !early);
-            if (rc == CHHS_OK) rc = run_cycles(c, early);
+            int rc = setup(c, phi_prev, phi_cur, mu, p, true, false);
+            if (rc == CHHS_OK) rc = run_cycles(c, true);
             const auto t1 = std::chrono::steady_clock::now();
             if (rc != CHHS_OK) return rc;
             for (int i = 0; i < c->n_inst; ++i) {
