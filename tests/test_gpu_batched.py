@@ -153,16 +153,21 @@ def test_caller_arrays_off_16_byte_alignment(chhs, spec, precision):
             assert np.max(np.abs(a - b)) <= 1e-12
 
 
-def test_graph_replay_equals_eager_launches(chhs):
-    spec = RAGGED_2D
+@pytest.mark.parametrize("spec", [RAGGED_2D, RAGGED_3D], ids=["2d", "3d"])
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_graph_replay_equals_eager_launches(chhs, spec, precision):
+    """Cycles replayed from the two captured graphs (mixed precision: one per
+    copy of the FP64 finest level, each reading back into its own mirror)
+    equal direct launches bit for bit, with the same cycle counts."""
     shapes = [s[0] for s in spec]
     phi0s = [uniform_field(sh, 3200 + i, mean=sp[4], amp=0.05) for i, (sh, sp) in
              enumerate(zip(shapes, spec))]
-    a = _run_batch(chhs, spec, phi0s, 3, use_graph=1)
-    b = _run_batch(chhs, spec, phi0s, 3, use_graph=0)
+    a = _run_batch(chhs, spec, phi0s, 3, use_graph=1, precision=precision)
+    b = _run_batch(chhs, spec, phi0s, 3, use_graph=0, precision=precision)
     for m in range(3):
         for k in (2, 3, 4):
             assert np.array_equal(a[m][k], b[m][k]), (m, k)
+        assert a[m][5] == b[m][5]
 
 
 def test_batched_workload_instances_step(chhs):
